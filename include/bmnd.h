@@ -1,0 +1,270 @@
+/*
+ * bmnd.h -- C ABI of the BMND hot path on AMD Instinct MI355X (gfx950).
+ *
+ * BMND ("Direct Poisson Denoising by N-Dimensional Block Matching and
+ * Collaborative Filtering") denoises an N-axis array in two stages that
+ * share one structure (section Method Overview):
+ *   block matching -> group gather -> separable group transform ->
+ *   shrinkage (hard threshold, then Wiener) -> inverse transform ->
+ *   Kaiser-windowed weighted overlap-add [-> mass conservation].
+ * The first (hard-threshold, "HT") stage filters the observation y into a
+ * pilot; the second ("Wiener") stage matches on the pilot and filters y.
+ *
+ * Every compute entry point is asynchronous on the caller's HIP stream
+ * (passed as an opaque `void*`; NULL is the default stream) and runs
+ * entirely in the library's HIP kernels.
+ *
+ * Memory and ownership
+ *   - Pointers named d_* are device pointers owned by the caller.  The
+ *     library never frees them and keeps no reference after the call.
+ *   - Arrays are float32, C-order (axis 0 slowest).  A geometry with
+ *     batch = B describes B independent arrays stored back to back; "lin"
+ *     always means the C-order linear index inside one array.
+ *   - Per-call scratch comes from a caller workspace sized by the matching
+ *     *_workspace_size() call.  The library owns only immutable,
+ *     process-lifetime tables (transform matrices, windows, reference
+ *     origin lists) that it builds once per configuration.
+ *
+ * Errors
+ *   - Every function returns a bmnd_status.  Invalid arguments are caught
+ *     before any launch and leave device memory untouched; the message is
+ *     available from bmnd_last_error() (thread-local, valid until the next
+ *     call on the same thread).
+ *   - Launch failures return BMND_E_HIP.  Asynchronous device faults and
+ *     device-detected range errors surface from bmnd_stream_status().
+ *   - Nothing throws or aborts across this interface.
+ */
+#ifndef BMND_H
+#define BMND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BMND_MAX_AXES 8   /* geometry structs carry up to 8 axes            */
+#define BMND_GPU_AXES 4   /* the GPU kernels accept ndim <= 4               */
+
+typedef int32_t bmnd_status;
+enum {
+    BMND_OK = 0,
+    BMND_E_ARG = -1,          /* invalid argument or parameter combination     */
+    BMND_E_SHAPE = -2,        /* geometry invalid or too large                 */
+    BMND_E_UNSUPPORTED = -3,  /* valid for the method, not supported here      */
+    BMND_E_NOMEM = -4,        /* host allocation or library table failed       */
+    BMND_E_HIP = -5,          /* HIP runtime error                             */
+    BMND_E_WORKSPACE = -6,    /* workspace pointer NULL or too small           */
+    BMND_E_RANGE = -7         /* device detected counts outside exact range    */
+};
+
+enum { BMND_STAGE_HT = 0, BMND_STAGE_WIENER = 1 };
+enum { BMND_NOISE_GAUSSIAN = 0, BMND_NOISE_POISSON = 1 };
+enum { BMND_SCHED_GENERATED = 0, BMND_SCHED_BALANCED = 1, BMND_SCHED_SPARSE = 2,
+       BMND_SCHED_OFF = 3 };
+enum { BMND_SPATIAL_IDENTITY = 0, BMND_SPATIAL_DCT = 1, BMND_SPATIAL_BIOR15 = 2 };
+enum { BMND_SHRINK_HARD = 0, BMND_SHRINK_SOFT = 1, BMND_SHRINK_WIENER = 2 };
+enum { BMND_WEIGHT_CLASSIC = 0, BMND_WEIGHT_VARIANCE = 1, BMND_WEIGHT_RISK = 2 };
+enum { BMND_SCOPE_GROUP = 0, BMND_SCOPE_PATCH = 1 };
+enum { BMND_PRESET_PLAIN = 0, BMND_PRESET_STANDARD = 1 };
+
+/* Observed array(s): sampling domain Omega of ndim axes (Notation, Method
+ * Overview), `batch` arrays of that shape stored back to back. */
+typedef struct {
+    int32_t ndim;                    /* 1 .. BMND_GPU_AXES                     */
+    int32_t reserved;                /* must be 0                              */
+    int64_t batch;                   /* >= 1                                   */
+    int64_t shape[BMND_MAX_AXES];    /* L_d >= 1; batch * prod(L_d) < 2^31     */
+} bmnd_geometry;
+
+/* Noise model (section Observation Models).
+ *   Gaussian: y = x + n, white, standard deviation sigma (Def. additive
+ *             Gaussian observation model).
+ *   Poisson:  y = s_P K, K ~ Poi(lambda) (Def. scaled-Poisson observation
+ *             model).  counts_integral != 0 declares that y / s_P is an
+ *             integer up to float32 storage rounding; the HT-stage matching
+ *             then runs exactly on the equivalent raw counts rint(y / s_P)
+ *             (eq. raw-counts; unit invariance of count statistics). */
+typedef struct {
+    int32_t kind;                    /* BMND_NOISE_*                           */
+    int32_t counts_integral;         /* Poisson only: 0 / 1                    */
+    double sigma;                    /* Gaussian: >= 0                         */
+    double s_p;                      /* Poisson: > 0                           */
+} bmnd_noise;
+
+/* Parameters of one stage (Appendix A standard profile; Appendix B
+ * ablation reference levels for the "plain" preset). */
+typedef struct {
+    int32_t patch[BMND_MAX_AXES];    /* j_d, 1 <= j_d <= min(L_d, 32)          */
+    int32_t step[BMND_MAX_AXES];     /* h_d >= 1, reference lattice step      */
+    int32_t search[BMND_MAX_AXES];   /* W_d >= 1 candidate origins per axis,   */
+                                     /* window offsets [-W/2, W-1-W/2]         */
+    int32_t schedule;                /* BMND_SCHED_*                           */
+    int32_t passes;                  /* K_s >= 1 schedule passes               */
+    double shift_density;            /* rho_s >= 0                             */
+    int32_t group_min;               /* power of two, >= 1                     */
+    int32_t group_max;               /* power of two, <= 32; group_max*P<=4096 */
+    double tau;                      /* matching threshold (stored units);     */
+                                     /* < 0 selects c*P/255^2, c = 3000 (HT),  */
+                                     /* 400 (Wiener)                           */
+    double gamma;                    /* SSD noise-bias factor (HT); 0 Wiener  */
+    int32_t spatial;                 /* BMND_SPATIAL_*                         */
+    int32_t shrink;                  /* HT: HARD | SOFT;  Wiener: WIENER       */
+    double lambda;                   /* HT threshold multiplier                */
+    double s_v;                      /* Wiener variance scale >= 0             */
+    double power_a;                  /* pilot-power correction a >= 0          */
+    int32_t k_exact;                 /* exact shared-source planes, >= 0       */
+    int32_t weight_model;            /* BMND_WEIGHT_*; RISK only in Wiener     */
+    int32_t weight_scope;            /* BMND_SCOPE_*                           */
+    int32_t mass_conservation;       /* 0 / 1                                  */
+    double kaiser_beta;              /* Kaiser window beta                     */
+} bmnd_stage_params;
+
+typedef struct {
+    bmnd_stage_params ht;
+    bmnd_stage_params wiener;
+} bmnd_params;
+
+/* Message describing the last failed call on this thread ("" if none). */
+const char* bmnd_last_error(void);
+
+/* Library version string. */
+const char* bmnd_version(void);
+
+/* Fill *out with a preset for an ndim-axis array.
+ *   PLAIN: the ablation reference levels (Appendix B): generated schedule
+ *     (rho_s = 2, K_s = 2), HT: SSD with gamma = 3, hard threshold
+ *     lambda = 3, bior1.5 spatial transform, group 2..16; Wiener: DCT,
+ *     classic gain (a = 0), s_v = 0.4, group 2..32; k_exact = 0, classic
+ *     group weights, no mass conservation, Kaiser beta = 2.
+ *   STANDARD: Appendix A: as PLAIN but k_exact = 4 and variance / patch
+ *     weights in both stages.
+ * Patch 8 (2-D), 4 (3-D), 32 (1-D) per axis, step 3 (4 in 1-D), search
+ * 19 (2-D) / 7 (3-D) / 256 (1-D) per axis.  BMND_E_ARG for a bad preset or
+ * ndim. */
+bmnd_status bmnd_params_default(int32_t preset, int32_t ndim, bmnd_params* out);
+
+/* Reference origins of one array (section Reference-Patch Schedule:
+ * Def. clipped reference origin, the K_s passes, Defs. generated /
+ * balanced / sparse / off schedule), deduplicated, ascending lin.  Host
+ * call.  Writes up to `cap` origins to out_lin (host, may be NULL with
+ * cap = 0) and the total count to *n_out. */
+bmnd_status bmnd_reference_origins(const bmnd_geometry* geom, const bmnd_stage_params* sp,
+                                   int64_t* out_lin, int64_t cap, int64_t* n_out);
+
+/* The library's transform and window tables (host call, double precision):
+ * T (n x n, row-major) the spatial analysis matrix of `spatial` on n points
+ * (orthonormal DCT-II; full multilevel periodised bior1.5 DWT; identity)
+ * and U = T^-1 (Appendix A transforms), and the n-point Kaiser window of
+ * `beta` (Method Overview).  Any output pointer may be NULL. */
+bmnd_status bmnd_transform_matrices(int32_t spatial, int32_t n, double* T, double* U);
+bmnd_status bmnd_haar_matrix(int32_t K, double* H);
+bmnd_status bmnd_kaiser_window(int32_t n, double beta, double* w);
+
+/* Workspace bytes for bmnd_match / bmnd_aggregate / bmnd_denoise. */
+bmnd_status bmnd_match_workspace_size(const bmnd_geometry* geom, const bmnd_stage_params* sp,
+                                      size_t* bytes);
+bmnd_status bmnd_aggregate_workspace_size(const bmnd_geometry* geom,
+                                          const bmnd_stage_params* sp, size_t* bytes);
+bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noise,
+                                const bmnd_params* params, size_t* bytes);
+
+/* Block matching for one stage (section Block Matching).
+ * For every array b < batch and reference g < n_refs with origin
+ * d_refs[g] (lin, same origins for every array), score every candidate
+ * origin of the clipped search window:
+ *   HT, Gaussian: SSD - gamma 2 P sigma^2 (Prop. Gaussian SSD noise bias,
+ *                 white noise; Def. noise-bias-corrected SSD);
+ *   HT, Poisson:  SSD - gamma s_P sum[p + q]_+ (Prop. scaled-Poisson SSD
+ *                 noise bias; Def. noise-bias-corrected SSD), computed on
+ *                 the raw counts when counts_integral is set;
+ *   Wiener:       SSD on d_src, the pilot (Def. paired pilot and
+ *                 observation groups).
+ * The group is the reference in slot 0 followed by the other candidates
+ * in ascending (score, lin); its size K is pow2floor(min(1 + #{score <
+ * tau}, group_max)), clamped to [group_min, pow2floor(1 + candidates)].
+ *   d_src   [batch][V] HT: the observation y; Wiener: the pilot
+ *   d_refs  [n_refs] int64 origins (lin)
+ *   d_match [batch][n_refs][group_max] int32 lin of the members; -1 beyond K
+ *   d_count [batch][n_refs] int32 K
+ *   d_ws    workspace of bmnd_match_workspace_size() bytes
+ * Errors: BMND_E_ARG / _SHAPE / _UNSUPPORTED / _WORKSPACE / _HIP;
+ * counts too large for exact int32 scoring raise BMND_E_RANGE from
+ * bmnd_stream_status(). */
+bmnd_status bmnd_match(int32_t stage, const float* d_src, const bmnd_geometry* geom,
+                       const bmnd_noise* noise, const bmnd_stage_params* sp,
+                       const int64_t* d_refs, int64_t n_refs, int32_t* d_match,
+                       int32_t* d_count, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Collaborative filtering of the matched groups (sections Hard
+ * Thresholding, Wiener Shrinkage, Aggregation Weights).  For each group:
+ * gather y (and the pilot in the Wiener stage) at the members' origins
+ * (Def. paired pilot and observation groups), apply T = Haar (x) spatial
+ * (x) ..., propagate the noise variances sigma_k^2 = sum |T_ki|^2 m_v(u_i)
+ * (Prop. diagonal Poisson variance propagation) with the leading k_exact
+ * Haar planes from the shared-source model (Def. partial shared-source
+ * Poisson variance model), shrink (eq. hard-threshold / soft-threshold,
+ * or eq. wiener-gain with eq. pilot-power-family), compute the patch
+ * reliability weights (Defs. coefficient-domain hard-thresholding /
+ * Wiener weighting models, Def. aggregation-weight scope) and synthesize
+ * p = U C with U = T^-1 (Def. pilot group).
+ *   d_pilot    [batch][V] (Wiener only; NULL in the HT stage)
+ *   d_match, d_count as produced by bmnd_match
+ *   d_patches  [batch][n_refs][group_max][P] synthesized patches, no window
+ *   d_weights  [batch][n_refs][group_max] patch weights (0 beyond K)
+ * Errors: BMND_E_ARG / _SHAPE / _UNSUPPORTED / _HIP. */
+bmnd_status bmnd_filter(int32_t stage, const float* d_y, const float* d_pilot,
+                        const bmnd_geometry* geom, const bmnd_noise* noise,
+                        const bmnd_stage_params* sp, int64_t n_refs, const int32_t* d_match,
+                        const int32_t* d_count, float* d_patches, float* d_weights,
+                        void* stream);
+
+/* Kaiser-windowed weighted overlap-add of given patches (Def. weighted
+ * overlap-add), optionally with aggregation-aware mass conservation
+ * (section Aggregation-Aware Mass Conservation): with the weights and the
+ * denominator eta of a first sweep held fixed, every group is shifted by
+ * the constant alpha_g = zeta_g^T (y_g - p_g) / zeta_g^T 1 that satisfies
+ * eq. dc-group-constraint, so that sum x^ = sum y (Thm. mass conservation
+ * after normalized overlap-add).  Voxels no patch covers are set to 0.
+ *   d_y    [batch][V] observation (read only with mass conservation)
+ *   d_out  [batch][V] result
+ *   d_ws   workspace of bmnd_aggregate_workspace_size() bytes */
+bmnd_status bmnd_aggregate(const float* d_y, const bmnd_geometry* geom,
+                           const bmnd_stage_params* sp, int64_t n_refs,
+                           const int32_t* d_match, const int32_t* d_count,
+                           const float* d_patches, const float* d_weights, float* d_out,
+                           void* d_ws, size_t ws_bytes, void* stream);
+
+/* The two-stage BMND (section Method Overview), fused: per stage the
+ * matching kernel, then one filtering kernel that aggregates directly
+ * (two sweeps with mass conservation), then normalisation.  The pilot is
+ * written to d_pilot if it is not NULL.  Reference origins come from the
+ * library's schedule cache.
+ *   d_y, d_out [batch][V];  d_ws of bmnd_workspace_size() bytes. */
+bmnd_status bmnd_denoise(const float* d_y, const bmnd_geometry* geom,
+                         const bmnd_noise* noise, const bmnd_params* params, float* d_out,
+                         float* d_pilot, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Kernel tracing.  Between bmnd_profile_begin() and bmnd_profile_end() the
+ * library records a pair of HIP events on the launch stream around every
+ * kernel that bmnd_denoise launches.  bmnd_profile_end() synchronises those
+ * events, writes per kernel id the summed duration in milliseconds and the
+ * number of launches (arrays of n_ids entries, ids BMND_KID_*), and stops
+ * recording.  Tracing is process-wide and meant for one thread. */
+enum { BMND_KID_COUNTS = 0, BMND_KID_PATCH_SUMS = 1, BMND_KID_MATCH_HT = 2,
+       BMND_KID_MATCH_WIENER = 3, BMND_KID_FILTER_HT = 4, BMND_KID_FILTER_WIENER = 5,
+       BMND_KID_ZERO = 6, BMND_KID_NORMALIZE = 7, BMND_KID_COUNT = 8 };
+bmnd_status bmnd_profile_begin(void);
+bmnd_status bmnd_profile_end(double* ms, int64_t* launches, int32_t n_ids);
+
+/* Synchronise `stream` and report asynchronous failures: BMND_E_HIP for a
+ * device fault, BMND_E_RANGE if a matching kernel saw counts outside the
+ * exact int32 range since the last call.  Clears the range flag. */
+bmnd_status bmnd_stream_status(void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMND_H */

@@ -1,0 +1,93 @@
+// Internal interfaces of the BMND HIP library (not installed, not part of
+// the C ABI).  Canonical geometry: every array is viewed as 4 axes with
+// leading singleton axes, so the kernels handle 1-, 2-, 3- and 4-axis
+// arrays with one code path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bmnd.h"
+
+namespace bmnd {
+
+constexpr int kAx = 4;        // canonical number of axes in the kernels
+constexpr int kMaxGroup = 32; // largest group (Haar on 2^5 members)
+constexpr int kMaxKP = 4096;  // largest group size in samples
+constexpr int kMaxPatch = 32; // largest patch extent per axis
+
+// Canonical geometry of one array (all int32: batch * V < 2^31 is checked).
+struct Geo {
+    int L[kAx];    // shape
+    int st[kAx];   // C-order strides
+    int j[kAx];    // patch extents
+    int W[kAx];    // search extents (candidate origins per axis)
+    int ell[kAx];  // last valid origin L - j
+    int P;         // samples per patch
+    int V;         // samples per array
+    int batch;     // arrays
+};
+
+// Host-side stage description after validation.
+struct StageCfg {
+    Geo g;
+    int stage;       // BMND_STAGE_*
+    int noise;       // BMND_NOISE_*
+    bool integral;   // exact count-domain HT matching
+    double s_p, sigma;
+    double tau;      // resolved threshold, stored units
+    double gamma;
+    int gmin, gmax;
+    int spatial, shrink;
+    double lambda, s_v, power_a;
+    int k_exact, wmodel, wscope, mc;
+    double beta;
+};
+
+// Device-resident immutable tables for one (spatial transform, patch, beta).
+struct DevTables {
+    const float* f32 = nullptr;   // packed float tables
+    const double* f64 = nullptr;  // packed double tables
+    int T[kAx], U[kAx], T2[kAx], win[kAx], rn[kAx];  // float offsets per axis
+    int T64[kAx], T264[kAx];                         // double offsets per axis
+    int haar;      // float offset of Haar H (32 x 32, row-major, for K = 32 .. 1 packed)
+    int haar64;    // double offset of Haar H
+    int f32_count = 0, f64_count = 0;
+};
+
+// Thread-local error message.
+void set_error(const std::string& msg);
+
+// Host schedule (section Reference-Patch Schedule).
+std::vector<int64_t> reference_origins(const bmnd_geometry& geom, const bmnd_stage_params& sp);
+
+// Host tables (transform matrices, Kaiser window).
+void spatial_matrices(int kind, int n, std::vector<double>& T, std::vector<double>& U);
+void haar_matrix(int K, std::vector<double>& H);
+std::vector<double> kaiser_window(int n, double beta);
+
+// Cached device copies (library owned, never freed before process exit).
+const DevTables* device_tables(const StageCfg& c, std::string& err);
+const int64_t* device_origins(const bmnd_geometry& geom, const bmnd_stage_params& sp,
+                              int64_t* n_refs, hipStream_t s, std::string& err);
+
+// Kernel launchers (kernels.hip).  Each returns hipSuccess or the launch error.
+hipError_t launch_counts(const StageCfg& c, const float* y, int* kappa, int* psum, hipStream_t s);
+hipError_t launch_match(const StageCfg& c, const float* src, const int* kappa, const int* psum,
+                        const int64_t* refs, int n_refs, int* match, int* count, hipStream_t s);
+// out_mode: 0 write patches/weights, 1 aggregate (float), 2 mc sweep 1, 3 mc sweep 2
+hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
+                         const float* pilot, int n_refs, const int* match, const int* count,
+                         float* patches, float* weights, void* num, void* den, hipStream_t s);
+hipError_t launch_aggregate(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
+                            int n_refs, const int* match, const int* count, const float* patches,
+                            const float* weights, void* num, void* den, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_normalize(const StageCfg& c, const void* num, const void* den, float* out,
+                            float* out2, hipStream_t s);
+hipError_t read_and_clear_range_flag(int* flag);
+
+}  // namespace bmnd

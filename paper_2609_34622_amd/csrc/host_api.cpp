@@ -1,0 +1,716 @@
+// C ABI of the BMND library: validation, library-owned caches, workspace
+// layout and launch orchestration.  See include/bmnd.h for the contract.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "bmnd_internal.h"
+
+namespace bmnd {
+
+static thread_local std::string t_error;
+
+void set_error(const std::string& msg) { t_error = msg; }
+
+size_t filter_lds_bytes(const Geo& g, int gmax);
+
+namespace {
+
+bool is_pow2(int v) { return v >= 1 && (v & (v - 1)) == 0; }
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+bmnd_status fail(bmnd_status st, const std::string& msg)
+{
+    set_error(msg);
+    return st;
+}
+
+bmnd_status check_geometry(const bmnd_geometry* g)
+{
+    if (!g) return fail(BMND_E_ARG, "geometry is NULL");
+    if (g->ndim < 1 || g->ndim > BMND_MAX_AXES) return fail(BMND_E_SHAPE, "ndim out of range");
+    if (g->ndim > BMND_GPU_AXES)
+        return fail(BMND_E_UNSUPPORTED, "the GPU kernels accept at most 4 axes");
+    if (g->reserved != 0) return fail(BMND_E_ARG, "geometry.reserved must be 0");
+    if (g->batch < 1) return fail(BMND_E_SHAPE, "batch must be >= 1");
+    double total = double(g->batch);
+    for (int d = 0; d < g->ndim; ++d) {
+        if (g->shape[d] < 1) return fail(BMND_E_SHAPE, "shape entries must be >= 1");
+        total *= double(g->shape[d]);
+    }
+    if (total >= 2147483647.0) return fail(BMND_E_SHAPE, "batch * volume must be < 2^31");
+    return BMND_OK;
+}
+
+bmnd_status check_stage(const bmnd_geometry* g, const bmnd_stage_params* sp, int stage)
+{
+    if (!sp) return fail(BMND_E_ARG, "stage parameters are NULL");
+    int P = 1;
+    for (int d = 0; d < g->ndim; ++d) {
+        if (sp->patch[d] < 1 || sp->patch[d] > g->shape[d])
+            return fail(BMND_E_ARG, "patch must satisfy 1 <= j_d <= L_d");
+        if (sp->patch[d] > kMaxPatch) return fail(BMND_E_UNSUPPORTED, "patch extent > 32");
+        if (sp->step[d] < 1) return fail(BMND_E_ARG, "step must be >= 1");
+        if (sp->search[d] < 1) return fail(BMND_E_ARG, "search must be >= 1");
+        P *= sp->patch[d];
+    }
+    if (sp->schedule < BMND_SCHED_GENERATED || sp->schedule > BMND_SCHED_OFF)
+        return fail(BMND_E_ARG, "unknown schedule");
+    if (sp->passes < 1) return fail(BMND_E_ARG, "passes must be >= 1");
+    if (!(sp->shift_density >= 0.0)) return fail(BMND_E_ARG, "shift_density must be >= 0");
+    if (!is_pow2(sp->group_max) || sp->group_max > kMaxGroup)
+        return fail(BMND_E_ARG, "group_max must be a power of two <= 32");
+    if (!is_pow2(sp->group_min) || sp->group_min > sp->group_max)
+        return fail(BMND_E_ARG, "group_min must be a power of two <= group_max");
+    if (sp->group_max * P > kMaxKP) return fail(BMND_E_UNSUPPORTED, "group_max * P > 4096");
+    if (sp->spatial < BMND_SPATIAL_IDENTITY || sp->spatial > BMND_SPATIAL_BIOR15)
+        return fail(BMND_E_ARG, "unknown spatial transform");
+    if (stage == BMND_STAGE_HT) {
+        if (sp->shrink != BMND_SHRINK_HARD && sp->shrink != BMND_SHRINK_SOFT)
+            return fail(BMND_E_ARG, "the HT stage needs hard or soft thresholding");
+        if (sp->weight_model == BMND_WEIGHT_RISK)
+            return fail(BMND_E_ARG, "the HT stage has no risk weight model");
+        if (!(sp->lambda >= 0.0)) return fail(BMND_E_ARG, "lambda must be >= 0");
+        if (!(sp->gamma >= 0.0)) return fail(BMND_E_ARG, "gamma must be >= 0");
+    } else if (stage == BMND_STAGE_WIENER) {
+        if (sp->shrink != BMND_SHRINK_WIENER)
+            return fail(BMND_E_ARG, "the Wiener stage needs Wiener shrinkage");
+        if (sp->gamma != 0.0) return fail(BMND_E_ARG, "the Wiener stage matches with plain SSD");
+        if (!(sp->s_v >= 0.0) || !(sp->power_a >= 0.0))
+            return fail(BMND_E_ARG, "s_v and power_a must be >= 0");
+    } else {
+        return fail(BMND_E_ARG, "unknown stage");
+    }
+    if (sp->weight_model < BMND_WEIGHT_CLASSIC || sp->weight_model > BMND_WEIGHT_RISK)
+        return fail(BMND_E_ARG, "unknown weight model");
+    if (sp->weight_scope != BMND_SCOPE_GROUP && sp->weight_scope != BMND_SCOPE_PATCH)
+        return fail(BMND_E_ARG, "unknown weight scope");
+    if (sp->k_exact < 0) return fail(BMND_E_ARG, "k_exact must be >= 0");
+    if (sp->k_exact > 0) return fail(BMND_E_UNSUPPORTED, "exact covariance planes not built yet");
+    if (!(sp->kaiser_beta >= 0.0)) return fail(BMND_E_ARG, "kaiser_beta must be >= 0");
+    return BMND_OK;
+}
+
+bmnd_status check_noise(const bmnd_noise* n)
+{
+    if (!n) return fail(BMND_E_ARG, "noise is NULL");
+    if (n->kind == BMND_NOISE_POISSON) {
+        if (!(n->s_p > 0.0)) return fail(BMND_E_ARG, "Poisson s_p must be > 0");
+    } else if (n->kind == BMND_NOISE_GAUSSIAN) {
+        if (!(n->sigma >= 0.0)) return fail(BMND_E_ARG, "Gaussian sigma must be >= 0");
+    } else {
+        return fail(BMND_E_ARG, "unknown noise kind");
+    }
+    return BMND_OK;
+}
+
+Geo make_geo(const bmnd_geometry* g, const bmnd_stage_params* sp)
+{
+    Geo o{};
+    const int pad = kAx - g->ndim;
+    for (int k = 0; k < kAx; ++k) {
+        const int d = k - pad;
+        o.L[k] = d >= 0 ? int(g->shape[d]) : 1;
+        o.j[k] = d >= 0 ? sp->patch[d] : 1;
+        o.W[k] = d >= 0 ? sp->search[d] : 1;
+    }
+    int acc = 1;
+    for (int k = kAx - 1; k >= 0; --k) {
+        o.st[k] = acc;
+        acc *= o.L[k];
+        o.ell[k] = o.L[k] - o.j[k];
+    }
+    o.V = acc;
+    o.P = o.j[0] * o.j[1] * o.j[2] * o.j[3];
+    o.batch = int(g->batch);
+    return o;
+}
+
+bmnd_status make_stage(const bmnd_geometry* g, const bmnd_noise* n, const bmnd_stage_params* sp,
+                       int stage, StageCfg& c)
+{
+    bmnd_status st = check_geometry(g);
+    if (st != BMND_OK) return st;
+    if ((st = check_stage(g, sp, stage)) != BMND_OK) return st;
+    if (n && (st = check_noise(n)) != BMND_OK) return st;
+    c = StageCfg{};
+    c.g = make_geo(g, sp);
+    c.stage = stage;
+    c.noise = n ? n->kind : BMND_NOISE_GAUSSIAN;
+    c.s_p = n ? n->s_p : 1.0;
+    c.sigma = n ? n->sigma : 0.0;
+    c.gamma = sp->gamma;
+    c.integral = n && stage == BMND_STAGE_HT && n->kind == BMND_NOISE_POISSON &&
+                 n->counts_integral && sp->gamma == std::floor(sp->gamma);
+    c.tau = sp->tau >= 0.0 ? sp->tau
+                           : (stage == BMND_STAGE_HT ? 3000.0 : 400.0) * c.g.P / (255.0 * 255.0);
+    c.gmin = sp->group_min;
+    c.gmax = sp->group_max;
+    c.spatial = sp->spatial;
+    c.shrink = sp->shrink;
+    c.lambda = sp->lambda;
+    c.s_v = sp->s_v;
+    c.power_a = sp->power_a;
+    c.k_exact = sp->k_exact;
+    c.wmodel = sp->weight_model;
+    c.wscope = sp->weight_scope;
+    c.mc = sp->mass_conservation ? 1 : 0;
+    c.beta = sp->kaiser_beta;
+    return BMND_OK;
+}
+
+// ------------------------------------------------------------- caches
+
+std::mutex g_cache_mu;
+
+using TabKey = std::tuple<int, int, int, int, int, int, double>;
+std::map<TabKey, DevTables> g_tables;
+
+using OrgKey = std::tuple<int, std::vector<int64_t>, std::vector<int>, std::vector<int>, int, int,
+                          double>;
+std::map<OrgKey, std::pair<int64_t*, int64_t>> g_origins;
+
+}  // namespace
+
+const DevTables* device_tables(const StageCfg& c, std::string& err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        err = "hipGetDevice failed";
+        return nullptr;
+    }
+    TabKey key{dev, c.spatial, c.g.j[0], c.g.j[1], c.g.j[2], c.g.j[3], c.beta};
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_tables.find(key);
+    if (it != g_tables.end()) return &it->second;
+
+    DevTables t{};
+    std::vector<float> f;
+    std::vector<double> f64;
+    for (int d = 0; d < kAx; ++d) {
+        const int n = c.g.j[d];
+        std::vector<double> T, U;
+        spatial_matrices(n > 1 ? c.spatial : BMND_SPATIAL_IDENTITY, n, T, U);
+        t.T[d] = int(f.size());
+        for (double v : T) f.push_back(float(v));
+        t.U[d] = int(f.size());
+        for (double v : U) f.push_back(float(v));
+        t.T2[d] = int(f.size());
+        for (double v : T) f.push_back(float(v * v));
+        t.win[d] = int(f.size());
+        for (double v : kaiser_window(n, c.beta)) f.push_back(float(v));
+        t.rn[d] = int(f.size());
+        for (int q = 0; q < n; ++q) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += T[size_t(q * n + k)] * T[size_t(q * n + k)];
+            f.push_back(float(std::sqrt(s)));
+        }
+        t.T64[d] = int(f64.size());
+        for (double v : T) f64.push_back(v);
+        t.T264[d] = int(f64.size());
+        for (double v : T) f64.push_back(v * v);
+    }
+    t.haar = int(f.size());
+    t.haar64 = int(f64.size());
+    for (int K = 1; K <= kMaxGroup; K *= 2) {
+        std::vector<double> H;
+        haar_matrix(K, H);
+        for (double v : H) {
+            f.push_back(float(v));
+            f64.push_back(v);
+        }
+    }
+    float* df = nullptr;
+    double* dd = nullptr;
+    if (hipMalloc(&df, f.size() * sizeof(float)) != hipSuccess ||
+        hipMalloc(&dd, f64.size() * sizeof(double)) != hipSuccess) {
+        err = "hipMalloc of the transform tables failed";
+        return nullptr;
+    }
+    if (hipMemcpy(df, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dd, f64.data(), f64.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+        err = "upload of the transform tables failed";
+        return nullptr;
+    }
+    t.f32 = df;
+    t.f64 = dd;
+    t.f32_count = int(f.size());
+    t.f64_count = int(f64.size());
+    return &(g_tables[key] = t);
+}
+
+const int64_t* device_origins(const bmnd_geometry& geom, const bmnd_stage_params& sp,
+                              int64_t* n_refs, hipStream_t, std::string& err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        err = "hipGetDevice failed";
+        return nullptr;
+    }
+    std::vector<int64_t> shape(geom.shape, geom.shape + geom.ndim);
+    std::vector<int> ps(size_t(2 * geom.ndim));
+    for (int d = 0; d < geom.ndim; ++d) {
+        ps[size_t(d)] = sp.patch[d];
+        ps[size_t(geom.ndim + d)] = sp.step[d];
+    }
+    OrgKey key{dev, shape, ps, {}, sp.schedule, sp.passes, sp.shift_density};
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_origins.find(key);
+    if (it != g_origins.end()) {
+        *n_refs = it->second.second;
+        return it->second.first;
+    }
+    std::vector<int64_t> o = reference_origins(geom, sp);
+    int64_t* d = nullptr;
+    if (hipMalloc(&d, std::max<size_t>(1, o.size()) * sizeof(int64_t)) != hipSuccess ||
+        hipMemcpy(d, o.data(), o.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
+        err = "allocation of the reference-origin list failed";
+        return nullptr;
+    }
+    g_origins[key] = {d, int64_t(o.size())};
+    *n_refs = int64_t(o.size());
+    return d;
+}
+
+// ------------------------------------------------------------- tracing
+
+namespace {
+
+struct ProfRec {
+    int id;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+// Records an event pair around one kernel launch when tracing is on.
+struct KernelSpan {
+    int id;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    KernelSpan(int id_, hipStream_t s_) : id(id_), s(s_)
+    {
+        if (!g_prof_on) return;
+        if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, s);
+    }
+    ~KernelSpan()
+    {
+        if (!a || !b) return;
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof.push_back({id, a, b});
+    }
+};
+
+}  // namespace
+
+}  // namespace bmnd
+
+using namespace bmnd;
+
+namespace {
+
+// bytes of the match-stage scratch (counts + patch sums)
+size_t match_ws(const Geo& g) { return 2 * align256(size_t(g.batch) * g.V * sizeof(int)); }
+size_t agg_ws(const Geo& g) { return 2 * align256(size_t(g.batch) * g.V * sizeof(double)); }
+
+bmnd_status hip_fail(hipError_t e, const char* what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return BMND_E_HIP;
+}
+
+bmnd_stage_params preset_stage(int32_t preset, int32_t ndim, int stage)
+{
+    bmnd_stage_params p{};
+    const int j = ndim == 1 ? 32 : (ndim == 2 ? 8 : 4);
+    const int h = ndim == 1 ? 4 : 3;
+    const int w = ndim == 1 ? 256 : (ndim == 2 ? 19 : 7);
+    for (int d = 0; d < ndim; ++d) {
+        p.patch[d] = j;
+        p.step[d] = h;
+        p.search[d] = w;
+    }
+    p.schedule = BMND_SCHED_GENERATED;
+    p.passes = 2;
+    p.shift_density = 2.0;
+    p.group_min = 2;
+    p.group_max = stage == BMND_STAGE_HT ? 16 : 32;
+    p.tau = -1.0;
+    p.gamma = stage == BMND_STAGE_HT ? 3.0 : 0.0;
+    p.spatial = stage == BMND_STAGE_HT ? BMND_SPATIAL_BIOR15 : BMND_SPATIAL_DCT;
+    p.shrink = stage == BMND_STAGE_HT ? BMND_SHRINK_HARD : BMND_SHRINK_WIENER;
+    p.lambda = 3.0;
+    p.s_v = 0.4;
+    p.power_a = 0.0;
+    p.k_exact = preset == BMND_PRESET_STANDARD ? 4 : 0;
+    p.weight_model = preset == BMND_PRESET_STANDARD ? BMND_WEIGHT_VARIANCE : BMND_WEIGHT_CLASSIC;
+    p.weight_scope = preset == BMND_PRESET_STANDARD ? BMND_SCOPE_PATCH : BMND_SCOPE_GROUP;
+    p.mass_conservation = 0;
+    p.kaiser_beta = 2.0;
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bmnd_last_error(void) { return t_error.c_str(); }
+
+const char* bmnd_version(void) { return "bmnd-mi355x 0.1 (gfx950)"; }
+
+bmnd_status bmnd_params_default(int32_t preset, int32_t ndim, bmnd_params* out)
+{
+    if (!out) return fail(BMND_E_ARG, "out is NULL");
+    if (preset != BMND_PRESET_PLAIN && preset != BMND_PRESET_STANDARD)
+        return fail(BMND_E_ARG, "unknown preset");
+    if (ndim < 1 || ndim > BMND_MAX_AXES) return fail(BMND_E_ARG, "ndim out of range");
+    out->ht = preset_stage(preset, ndim, BMND_STAGE_HT);
+    out->wiener = preset_stage(preset, ndim, BMND_STAGE_WIENER);
+    return BMND_OK;
+}
+
+bmnd_status bmnd_reference_origins(const bmnd_geometry* geom, const bmnd_stage_params* sp,
+                                   int64_t* out_lin, int64_t cap, int64_t* n_out)
+{
+    if (!n_out) return fail(BMND_E_ARG, "n_out is NULL");
+    bmnd_status st = check_geometry(geom);
+    if (st != BMND_OK) return st;
+    if (!sp) return fail(BMND_E_ARG, "stage parameters are NULL");
+    for (int d = 0; d < geom->ndim; ++d) {
+        if (sp->patch[d] < 1 || sp->patch[d] > geom->shape[d])
+            return fail(BMND_E_ARG, "patch must satisfy 1 <= j_d <= L_d");
+        if (sp->step[d] < 1) return fail(BMND_E_ARG, "step must be >= 1");
+    }
+    if (sp->passes < 1 || !(sp->shift_density >= 0.0) || sp->schedule < 0 || sp->schedule > 3)
+        return fail(BMND_E_ARG, "bad schedule parameters");
+    std::vector<int64_t> o = reference_origins(*geom, *sp);
+    *n_out = int64_t(o.size());
+    if (out_lin && cap > 0)
+        std::memcpy(out_lin, o.data(), sizeof(int64_t) * size_t(std::min<int64_t>(cap, *n_out)));
+    return BMND_OK;
+}
+
+bmnd_status bmnd_transform_matrices(int32_t spatial, int32_t n, double* T, double* U)
+{
+    if (n < 1 || n > 1024) return fail(BMND_E_ARG, "n out of range");
+    if (spatial < BMND_SPATIAL_IDENTITY || spatial > BMND_SPATIAL_BIOR15)
+        return fail(BMND_E_ARG, "unknown spatial transform");
+    std::vector<double> t, u;
+    spatial_matrices(spatial, n, t, u);
+    if (T) std::memcpy(T, t.data(), sizeof(double) * t.size());
+    if (U) std::memcpy(U, u.data(), sizeof(double) * u.size());
+    return BMND_OK;
+}
+
+bmnd_status bmnd_haar_matrix(int32_t K, double* H)
+{
+    if (!is_pow2(K) || K > 1024) return fail(BMND_E_ARG, "K must be a power of two");
+    std::vector<double> h;
+    haar_matrix(K, h);
+    if (H) std::memcpy(H, h.data(), sizeof(double) * h.size());
+    return BMND_OK;
+}
+
+bmnd_status bmnd_kaiser_window(int32_t n, double beta, double* w)
+{
+    if (n < 1 || !(beta >= 0.0)) return fail(BMND_E_ARG, "bad window arguments");
+    std::vector<double> v = kaiser_window(n, beta);
+    if (w) std::memcpy(w, v.data(), sizeof(double) * v.size());
+    return BMND_OK;
+}
+
+bmnd_status bmnd_match_workspace_size(const bmnd_geometry* geom, const bmnd_stage_params* sp,
+                                      size_t* bytes)
+{
+    if (!bytes) return fail(BMND_E_ARG, "bytes is NULL");
+    StageCfg c;
+    bmnd_status st = make_stage(geom, nullptr, sp, BMND_STAGE_HT, c);
+    if (st != BMND_OK && st != BMND_E_ARG) return st;
+    Geo g = make_geo(geom, sp);
+    *bytes = match_ws(g);
+    return BMND_OK;
+}
+
+bmnd_status bmnd_aggregate_workspace_size(const bmnd_geometry* geom,
+                                          const bmnd_stage_params* sp, size_t* bytes)
+{
+    if (!bytes) return fail(BMND_E_ARG, "bytes is NULL");
+    bmnd_status st = check_geometry(geom);
+    if (st != BMND_OK) return st;
+    if (!sp) return fail(BMND_E_ARG, "stage parameters are NULL");
+    *bytes = agg_ws(make_geo(geom, sp));
+    return BMND_OK;
+}
+
+static bmnd_status denoise_layout(const bmnd_geometry* geom, const bmnd_params* params,
+                                  int64_t n_ht, int64_t n_wie, size_t* offs, size_t* total)
+{
+    const Geo g = make_geo(geom, &params->ht);
+    const size_t vox = size_t(g.batch) * g.V;
+    const size_t nm = std::max(size_t(n_ht) * params->ht.group_max,
+                               size_t(n_wie) * params->wiener.group_max);
+    const size_t nr = size_t(std::max(n_ht, n_wie));
+    size_t o = 0;
+    offs[0] = o; o += align256(size_t(g.batch) * nm * sizeof(int));      // match
+    offs[1] = o; o += align256(size_t(g.batch) * nr * sizeof(int));      // count
+    offs[2] = o; o += align256(vox * sizeof(int));                        // kappa
+    offs[3] = o; o += align256(vox * sizeof(int));                        // psum
+    offs[4] = o; o += align256(vox * sizeof(double));                     // num
+    offs[5] = o; o += align256(vox * sizeof(double));                     // den
+    offs[6] = o; o += align256(vox * sizeof(float));                      // pilot
+    *total = o;
+    return BMND_OK;
+}
+
+bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noise,
+                                const bmnd_params* params, size_t* bytes)
+{
+    if (!bytes || !params) return fail(BMND_E_ARG, "NULL argument");
+    StageCfg c1, c2;
+    bmnd_status st = make_stage(geom, noise, &params->ht, BMND_STAGE_HT, c1);
+    if (st != BMND_OK) return st;
+    if ((st = make_stage(geom, noise, &params->wiener, BMND_STAGE_WIENER, c2)) != BMND_OK) return st;
+    bmnd_geometry one = *geom;
+    one.batch = 1;
+    const int64_t n1 = int64_t(reference_origins(one, params->ht).size());
+    const int64_t n2 = int64_t(reference_origins(one, params->wiener).size());
+    size_t offs[8];
+    return denoise_layout(geom, params, n1, n2, offs, bytes);
+}
+
+bmnd_status bmnd_match(int32_t stage, const float* d_src, const bmnd_geometry* geom,
+                       const bmnd_noise* noise, const bmnd_stage_params* sp,
+                       const int64_t* d_refs, int64_t n_refs, int32_t* d_match,
+                       int32_t* d_count, void* d_ws, size_t ws_bytes, void* stream)
+{
+    StageCfg c;
+    bmnd_status st = make_stage(geom, noise, sp, stage, c);
+    if (st != BMND_OK) return st;
+    if (!noise) return fail(BMND_E_ARG, "noise is NULL");
+    if (!d_src || !d_match || !d_count || (n_refs > 0 && !d_refs))
+        return fail(BMND_E_ARG, "NULL device pointer");
+    if (n_refs < 0 || n_refs * int64_t(c.g.batch) >= 2147483647LL)
+        return fail(BMND_E_ARG, "n_refs out of range");
+    if (n_refs == 0) return BMND_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int* kappa = nullptr;
+    int* psum = nullptr;
+    if (c.integral) {
+        if (!d_ws || ws_bytes < match_ws(c.g))
+            return fail(BMND_E_WORKSPACE, "workspace missing or smaller than bmnd_match_workspace_size");
+        kappa = static_cast<int*>(d_ws);
+        psum = reinterpret_cast<int*>(static_cast<char*>(d_ws) + match_ws(c.g) / 2);
+        hipError_t e = launch_counts(c, d_src, kappa, psum, s);
+        if (e != hipSuccess) return hip_fail(e, "count kernels");
+    }
+    hipError_t e = launch_match(c, d_src, kappa, psum, d_refs, int(n_refs), d_match, d_count, s);
+    if (e != hipSuccess) return hip_fail(e, "matching kernel");
+    return BMND_OK;
+}
+
+bmnd_status bmnd_filter(int32_t stage, const float* d_y, const float* d_pilot,
+                        const bmnd_geometry* geom, const bmnd_noise* noise,
+                        const bmnd_stage_params* sp, int64_t n_refs, const int32_t* d_match,
+                        const int32_t* d_count, float* d_patches, float* d_weights,
+                        void* stream)
+{
+    StageCfg c;
+    bmnd_status st = make_stage(geom, noise, sp, stage, c);
+    if (st != BMND_OK) return st;
+    if (!noise) return fail(BMND_E_ARG, "noise is NULL");
+    if (!d_y || !d_match || !d_count || !d_patches || !d_weights)
+        return fail(BMND_E_ARG, "NULL device pointer");
+    if (stage == BMND_STAGE_WIENER && !d_pilot)
+        return fail(BMND_E_ARG, "the Wiener stage needs the pilot");
+    if (n_refs < 0 || n_refs * int64_t(c.g.batch) >= 2147483647LL)
+        return fail(BMND_E_ARG, "n_refs out of range");
+    if (n_refs == 0) return BMND_OK;
+    std::string err;
+    const DevTables* t = device_tables(c, err);
+    if (!t) return fail(BMND_E_NOMEM, err);
+    hipError_t e = launch_filter(c, *t, 0, d_y, d_pilot, int(n_refs), d_match, d_count, d_patches,
+                                 d_weights, nullptr, nullptr, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "filter kernel");
+    return BMND_OK;
+}
+
+bmnd_status bmnd_aggregate(const float* d_y, const bmnd_geometry* geom,
+                           const bmnd_stage_params* sp, int64_t n_refs,
+                           const int32_t* d_match, const int32_t* d_count,
+                           const float* d_patches, const float* d_weights, float* d_out,
+                           void* d_ws, size_t ws_bytes, void* stream)
+{
+    bmnd_status st = check_geometry(geom);
+    if (st != BMND_OK) return st;
+    if (!sp) return fail(BMND_E_ARG, "stage parameters are NULL");
+    // the stage only matters for validation of the shrink/stage pairing
+    const int stage = sp->shrink == BMND_SHRINK_WIENER ? BMND_STAGE_WIENER : BMND_STAGE_HT;
+    StageCfg c;
+    if ((st = make_stage(geom, nullptr, sp, stage, c)) != BMND_OK) return st;
+    if (!d_match || !d_count || !d_patches || !d_weights || !d_out || (c.mc && !d_y))
+        return fail(BMND_E_ARG, "NULL device pointer");
+    if (!d_ws || ws_bytes < agg_ws(c.g))
+        return fail(BMND_E_WORKSPACE, "workspace missing or smaller than bmnd_aggregate_workspace_size");
+    if (n_refs < 0 || n_refs * int64_t(c.g.batch) >= 2147483647LL)
+        return fail(BMND_E_ARG, "n_refs out of range");
+    std::string err;
+    const DevTables* t = device_tables(c, err);
+    if (!t) return fail(BMND_E_NOMEM, err);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* num = d_ws;
+    void* den = static_cast<char*>(d_ws) + agg_ws(c.g) / 2;
+    hipError_t e = launch_zero(d_ws, agg_ws(c.g), s);
+    if (e == hipSuccess && n_refs > 0) {
+        if (c.mc) {
+            e = launch_aggregate(c, *t, 2, d_y, int(n_refs), d_match, d_count, d_patches,
+                                 d_weights, num, den, s);
+            if (e == hipSuccess)
+                e = launch_aggregate(c, *t, 3, d_y, int(n_refs), d_match, d_count, d_patches,
+                                     d_weights, num, den, s);
+        } else {
+            e = launch_aggregate(c, *t, 1, d_y, int(n_refs), d_match, d_count, d_patches,
+                                 d_weights, num, den, s);
+        }
+    }
+    if (e == hipSuccess) e = launch_normalize(c, num, den, d_out, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "aggregation kernels");
+    return BMND_OK;
+}
+
+bmnd_status bmnd_denoise(const float* d_y, const bmnd_geometry* geom,
+                         const bmnd_noise* noise, const bmnd_params* params, float* d_out,
+                         float* d_pilot, void* d_ws, size_t ws_bytes, void* stream)
+{
+    if (!params) return fail(BMND_E_ARG, "params is NULL");
+    StageCfg c1, c2;
+    bmnd_status st = make_stage(geom, noise, &params->ht, BMND_STAGE_HT, c1);
+    if (st != BMND_OK) return st;
+    if ((st = make_stage(geom, noise, &params->wiener, BMND_STAGE_WIENER, c2)) != BMND_OK) return st;
+    if (!noise) return fail(BMND_E_ARG, "noise is NULL");
+    if (!d_y || !d_out) return fail(BMND_E_ARG, "NULL device pointer");
+    std::string err;
+    int64_t n1 = 0, n2 = 0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bmnd_geometry one = *geom;
+    one.batch = 1;
+    const int64_t* r1 = device_origins(one, params->ht, &n1, s, err);
+    const int64_t* r2 = r1 ? device_origins(one, params->wiener, &n2, s, err) : nullptr;
+    if (!r1 || !r2) return fail(BMND_E_NOMEM, err);
+    const DevTables* t1 = device_tables(c1, err);
+    const DevTables* t2 = t1 ? device_tables(c2, err) : nullptr;
+    if (!t1 || !t2) return fail(BMND_E_NOMEM, err);
+    size_t offs[8], total = 0;
+    denoise_layout(geom, params, n1, n2, offs, &total);
+    if (!d_ws || ws_bytes < total)
+        return fail(BMND_E_WORKSPACE, "workspace missing or smaller than bmnd_workspace_size");
+    char* ws = static_cast<char*>(d_ws);
+    int* match = reinterpret_cast<int*>(ws + offs[0]);
+    int* count = reinterpret_cast<int*>(ws + offs[1]);
+    int* kappa = reinterpret_cast<int*>(ws + offs[2]);
+    int* psum = reinterpret_cast<int*>(ws + offs[3]);
+    void* num = ws + offs[4];
+    void* den = ws + offs[5];
+    float* pilot = d_pilot ? d_pilot : reinterpret_cast<float*>(ws + offs[6]);
+    const size_t vox = size_t(c1.g.batch) * c1.g.V;
+
+    auto run_stage = [&](const StageCfg& c, const DevTables& t, const int64_t* refs, int64_t nr,
+                         const float* src, const float* pil, float* out) -> hipError_t {
+        const bool ht = c.stage == BMND_STAGE_HT;
+        hipError_t e = hipSuccess;
+        if (c.integral) {
+            KernelSpan k(BMND_KID_COUNTS, s);
+            e = launch_counts(c, src, kappa, psum, s);
+        }
+        if (e == hipSuccess) {
+            KernelSpan k(ht ? BMND_KID_MATCH_HT : BMND_KID_MATCH_WIENER, s);
+            e = launch_match(c, src, kappa, psum, refs, int(nr), match, count, s);
+        }
+        if (e == hipSuccess) {
+            KernelSpan k(BMND_KID_ZERO, s);
+            e = launch_zero(num, vox * (c.mc ? 16 : 8) / 2, s);
+            if (e == hipSuccess) e = launch_zero(den, vox * (c.mc ? 16 : 8) / 2, s);
+        }
+        if (e != hipSuccess) return e;
+        {
+            KernelSpan k(ht ? BMND_KID_FILTER_HT : BMND_KID_FILTER_WIENER, s);
+            if (c.mc) {
+                e = launch_filter(c, t, 2, d_y, pil, int(nr), match, count, nullptr, nullptr, num,
+                                  den, s);
+                if (e == hipSuccess)
+                    e = launch_filter(c, t, 3, d_y, pil, int(nr), match, count, nullptr, nullptr,
+                                      num, den, s);
+            } else {
+                e = launch_filter(c, t, 1, d_y, pil, int(nr), match, count, nullptr, nullptr, num,
+                                  den, s);
+            }
+        }
+        if (e == hipSuccess) {
+            KernelSpan k(BMND_KID_NORMALIZE, s);
+            e = launch_normalize(c, num, den, out, nullptr, s);
+        }
+        return e;
+    };
+    hipError_t e = run_stage(c1, *t1, r1, n1, d_y, nullptr, pilot);
+    if (e != hipSuccess) return hip_fail(e, "HT stage");
+    e = run_stage(c2, *t2, r2, n2, pilot, pilot, d_out);
+    if (e != hipSuccess) return hip_fail(e, "Wiener stage");
+    return BMND_OK;
+}
+
+bmnd_status bmnd_profile_begin(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto& r : g_prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+    g_prof_on = true;
+    return BMND_OK;
+}
+
+bmnd_status bmnd_profile_end(double* ms, int64_t* launches, int32_t n_ids)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = false;
+    for (int i = 0; i < n_ids; ++i) {
+        if (ms) ms[i] = 0.0;
+        if (launches) launches[i] = 0;
+    }
+    bmnd_status st = BMND_OK;
+    for (auto& r : g_prof) {
+        float t = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess) st = hip_fail(e, "profile events");
+        if (r.id < n_ids) {
+            if (ms) ms[r.id] += t;
+            if (launches) launches[r.id] += 1;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+    return st;
+}
+
+bmnd_status bmnd_stream_status(void* stream)
+{
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "stream");
+    int flag = 0;
+    e = read_and_clear_range_flag(&flag);
+    if (e != hipSuccess) return hip_fail(e, "range flag");
+    if (flag) return fail(BMND_E_RANGE, "counts outside the exact int32 scoring range");
+    return BMND_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Reference-origin schedules (section Reference-Patch Schedule).
+//
+// The coarse lattice of axis d has Z_d = ceil(ell_d / h_d) + 1 slots with
+// nominal origins min(q h, ell) (Def. clipped reference origin).  Each of
+// the K_s passes gives every slot tuple one offset vector o; the origin is
+// clip(min(q h, ell) - o, 0, ell) per axis, and the last slot is pinned to
+// ell.  Offsets come from the per-axis candidate shift list (eq.
+// number-shifts, eq. candidate-shift-list), indexed by the rule of the
+// selected schedule (Defs. generated / balanced / sparse / off).
+#include <algorithm>
+#include <cmath>
+
+#include "bmnd_internal.h"
+
+namespace bmnd {
+
+namespace {
+
+// Rounded, uniformly spaced samples of [0, j - 1]; n = min(j, max(1,
+// ceil(rho (j - 1) / h))).  Rounding floor(x + 1/2) is done on the exact
+// rational i (j - 1) / (n - 1).
+std::vector<int64_t> shift_candidates(int j, int h, double rho)
+{
+    double want = std::ceil(rho * double(j - 1) / double(h));
+    int64_t n = want < 1.0 ? 1 : int64_t(want);
+    n = std::min<int64_t>(n, j);
+    std::vector<int64_t> s(size_t(n), 0);
+    for (int64_t i = 1; i < n; ++i) {
+        const int64_t num = i * (j - 1);  // value = num / (n - 1)
+        const int64_t den = n - 1;
+        s[size_t(i)] = (2 * num + den) / (2 * den);
+    }
+    return s;
+}
+
+}  // namespace
+
+std::vector<int64_t> reference_origins(const bmnd_geometry& geom, const bmnd_stage_params& sp)
+{
+    const int D = geom.ndim;
+    std::vector<int64_t> ell(D), Z(D), stride(D);
+    std::vector<std::vector<int64_t>> S(D);
+    int64_t acc = 1;
+    for (int d = D - 1; d >= 0; --d) {
+        stride[d] = acc;
+        acc *= geom.shape[d];
+    }
+    for (int d = 0; d < D; ++d) {
+        ell[d] = geom.shape[d] - sp.patch[d];
+        Z[d] = (ell[d] + sp.step[d] - 1) / sp.step[d] + 1;
+        S[d] = shift_candidates(sp.patch[d], sp.step[d], sp.shift_density);
+    }
+    // next active axis for the sparse schedule (active: Z_d > 1 or j_d > 1)
+    std::vector<int> next_active(D, -1);
+    for (int d = D - 1, nxt = -1; d >= 0; --d) {
+        next_active[d] = nxt;
+        if (Z[d] > 1 || sp.patch[d] > 1) nxt = d;
+    }
+    std::vector<int64_t> slot_origin_cache;
+    const int passes = sp.schedule == BMND_SCHED_OFF ? 1 : sp.passes;
+
+    std::vector<int64_t> out;
+    int64_t tuples = 1;
+    for (int d = 0; d < D; ++d) tuples *= Z[d];
+    out.reserve(size_t(tuples * passes));
+    std::vector<int64_t> q(D, 0);
+    for (int64_t t = 0; t < tuples; ++t) {
+        int64_t qsum = 0;
+        for (int d = 0; d < D; ++d) qsum += q[d];
+        for (int k = 0; k < passes; ++k) {
+            int64_t lin = 0;
+            for (int d = 0; d < D; ++d) {
+                const auto& Sd = S[d];
+                const int64_t n = int64_t(Sd.size());
+                int64_t off = 0;
+                if (sp.schedule == BMND_SCHED_GENERATED) {
+                    if (d + 1 < D) off = Sd[size_t((q[d + 1] + k) % n)];
+                } else if (sp.schedule == BMND_SCHED_BALANCED) {
+                    off = Sd[size_t((k + qsum - q[d]) % n)];
+                } else if (sp.schedule == BMND_SCHED_SPARSE) {
+                    const bool act = Z[d] > 1 || sp.patch[d] > 1;
+                    if (act && next_active[d] >= 0) off = Sd[size_t((q[next_active[d]] + k) % n)];
+                }
+                int64_t r;
+                if (q[d] == Z[d] - 1) {
+                    r = ell[d];
+                } else {
+                    r = std::min<int64_t>(q[d] * sp.step[d], ell[d]) - off;
+                    r = std::max<int64_t>(0, std::min<int64_t>(r, ell[d]));
+                }
+                lin += r * stride[d];
+            }
+            out.push_back(lin);
+        }
+        // advance the slot tuple (last axis fastest)
+        for (int d = D - 1; d >= 0; --d) {
+            if (++q[d] < Z[d]) break;
+            q[d] = 0;
+        }
+    }
+    std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
+    return out;
+}
+
+}  // namespace bmnd

@@ -1,0 +1,924 @@
+// BMND HIP kernels for gfx950 (MI355X).
+//
+// Layout conventions: every array is viewed with 4 canonical axes (leading
+// singleton axes pad lower dimensionalities); arrays of a batch are stored
+// back to back, V samples each.  A group of K members is a K x j0 x j1 x
+// j2 x j3 tensor in LDS (member axis slowest).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <climits>
+#include <cmath>
+
+#include "bmnd_internal.h"
+
+namespace bmnd {
+
+// Set by the matching kernels when a count lies outside the range in which
+// the int32 count-domain score is exact (read by bmnd_stream_status).
+__device__ int g_range_flag;
+
+namespace {
+
+constexpr int kMatchThreads = 64;
+constexpr int kFilterThreads = 256;
+
+// ---------------------------------------------------------------------------
+// Equivalent raw counts and their patch sums (eq. raw-counts; the plug-in
+// Poisson bias needs sum_i [p_i + q_i]_+ = S(p) + S(q) for counts >= 0).
+// ---------------------------------------------------------------------------
+
+__global__ void k_counts(Geo g, const float* __restrict__ y, float inv_sp, int kmax,
+                         int* __restrict__ kappa)
+{
+    const long n = long(g.batch) * g.V;
+    for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += long(gridDim.x) * blockDim.x) {
+        const int k = int(rintf(y[i] * inv_sp));
+        if (k < 0 || k > kmax) atomicOr(&g_range_flag, 1);
+        kappa[i] = k;
+    }
+}
+
+__global__ void k_patch_sums(Geo g, const int* __restrict__ kappa, int* __restrict__ psum)
+{
+    const long n = long(g.batch) * g.V;
+    for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += long(gridDim.x) * blockDim.x) {
+        const int b = int(i / g.V);
+        const int u = int(i - long(b) * g.V);
+        int c[kAx];
+        bool valid = true;
+        for (int d = 0; d < kAx; ++d) {
+            c[d] = (u / g.st[d]) % g.L[d];
+            valid = valid && c[d] <= g.ell[d];
+        }
+        int s = 0;
+        if (valid) {
+            const int* base = kappa + long(b) * g.V + u;
+            for (int i0 = 0; i0 < g.j[0]; ++i0)
+                for (int i1 = 0; i1 < g.j[1]; ++i1)
+                    for (int i2 = 0; i2 < g.j[2]; ++i2) {
+                        const int* row = base + i0 * g.st[0] + i1 * g.st[1] + i2 * g.st[2];
+                        for (int i3 = 0; i3 < g.j[3]; ++i3) s += row[i3];
+                    }
+        }
+        psum[i] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block matching (section Block Matching).
+// One thread owns one reference.  Pass 1 scores every candidate of the
+// clipped window, counts the accepted ones (score < tau) and keeps the
+// M = group_max - 1 smallest score values with a branch-free median-of-three
+// insertion network.  The group size K follows; the (K-1)-th smallest value
+// theta splits the candidates.  Pass 2 recomputes the (bit-identical)
+// scores and collects, in ascending lin order, every candidate below theta
+// and the first ties at theta, which is exactly the (score, lin) order's
+// first K-1 members; they are then sorted by (score, lin).
+// ---------------------------------------------------------------------------
+
+enum MatchMode { kCount = 0, kPoissonF = 1, kGauss = 2, kPlain = 3 };
+
+struct MatchArgs {
+    Geo g;
+    const float* src;    // batched observation (HT) or pilot (Wiener)
+    const int* kappa;    // batched counts (kCount)
+    const int* psum;     // batched patch sums of counts (kCount)
+    const int64_t* refs;
+    int n_refs;
+    int* match;
+    int* count;
+    int gmin, gmax;
+    int gamma_i;         // kCount: integral gamma
+    float gamma_sp;      // kPoissonF: gamma * s_P
+    float bias;          // kGauss: gamma * 2 P sigma^2
+    int tau_i;           // kCount: accept iff score < tau_i
+    float tau_f;         // float modes: accept iff score < tau_f
+};
+
+template <int MODE>
+struct ScoreT { using type = float; };
+template <>
+struct ScoreT<kCount> { using type = int; };
+
+template <int MODE>
+__device__ __forceinline__ typename ScoreT<MODE>::type score_of(const MatchArgs& a,
+                                                                 const float* src,
+                                                                 const int* kap, int r, int c)
+{
+    const Geo& g = a.g;
+    if constexpr (MODE == kCount) {
+        int ssd = 0;
+        for (int i0 = 0; i0 < g.j[0]; ++i0)
+            for (int i1 = 0; i1 < g.j[1]; ++i1)
+                for (int i2 = 0; i2 < g.j[2]; ++i2) {
+                    const int o = i0 * g.st[0] + i1 * g.st[1] + i2 * g.st[2];
+                    const int* pr = kap + r + o;
+                    const int* pc = kap + c + o;
+                    for (int i3 = 0; i3 < g.j[3]; ++i3) {
+                        const int d = pc[i3] - pr[i3];
+                        ssd += __mul24(d, d);
+                    }
+                }
+        return ssd - a.gamma_i * (a.psum[r + (kap - a.kappa)] + a.psum[c + (kap - a.kappa)]);
+    } else {
+        float ssd = 0.f, b = 0.f;
+        for (int i0 = 0; i0 < g.j[0]; ++i0)
+            for (int i1 = 0; i1 < g.j[1]; ++i1)
+                for (int i2 = 0; i2 < g.j[2]; ++i2) {
+                    const int o = i0 * g.st[0] + i1 * g.st[1] + i2 * g.st[2];
+                    const float* pr = src + r + o;
+                    const float* pc = src + c + o;
+                    for (int i3 = 0; i3 < g.j[3]; ++i3) {
+                        const float p = pr[i3], q = pc[i3];
+                        const float d = q - p;
+                        ssd = __builtin_fmaf(d, d, ssd);
+                        if constexpr (MODE == kPoissonF) b += fmaxf(p + q, 0.f);
+                    }
+                }
+        if constexpr (MODE == kPoissonF) return __builtin_fmaf(-a.gamma_sp, b, ssd);
+        if constexpr (MODE == kGauss) return ssd - a.bias;
+        return ssd;
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ S max_score();
+template <>
+__device__ __forceinline__ int max_score<int>() { return INT_MAX; }
+template <>
+__device__ __forceinline__ float max_score<float>() { return FLT_MAX; }
+
+__device__ __forceinline__ int to_bits(int v) { return v; }
+__device__ __forceinline__ int to_bits(float v) { return __float_as_int(v); }
+template <typename S>
+__device__ __forceinline__ S from_bits(int v);
+template <>
+__device__ __forceinline__ int from_bits<int>(int v) { return v; }
+template <>
+__device__ __forceinline__ float from_bits<float>(int v) { return __int_as_float(v); }
+
+__device__ __forceinline__ int smin(int a, int b) { return min(a, b); }
+__device__ __forceinline__ int smax(int a, int b) { return max(a, b); }
+__device__ __forceinline__ float smin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ float smax(float a, float b) { return fmaxf(a, b); }
+
+__device__ __forceinline__ int pow2floor(int x)
+{
+    return x <= 1 ? 1 : (1 << (31 - __clz(x)));
+}
+
+template <int MODE, int GM>
+__global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
+{
+    using S = typename ScoreT<MODE>::type;
+    constexpr int M = GM > 1 ? GM - 1 : 1;
+    __shared__ int sel_s[M][kMatchThreads];
+    __shared__ int sel_l[M][kMatchThreads];
+
+    const Geo& g = a.g;
+    const long t = long(blockIdx.x) * kMatchThreads + threadIdx.x;
+    if (t >= long(g.batch) * a.n_refs) return;
+    const int b = int(t / a.n_refs);
+    const int gi = int(t - long(b) * a.n_refs);
+    const int r = int(a.refs[gi]);
+    const float* src = a.src + long(b) * g.V;
+    const int* kap = MODE == kCount ? a.kappa + long(b) * g.V : nullptr;
+
+    int lo[kAx], hi[kAx];
+    int ncand = 1;
+    for (int d = 0; d < kAx; ++d) {
+        const int rc = (r / g.st[d]) % g.L[d];
+        lo[d] = max(rc - g.W[d] / 2, 0);
+        hi[d] = min(rc + g.W[d] - 1 - g.W[d] / 2, g.ell[d]);
+        ncand *= hi[d] - lo[d] + 1;
+    }
+    ncand -= 1;  // the reference itself is not a candidate
+
+    // ---- pass 1: accepted count and the M smallest values
+    S s[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) s[m] = max_score<S>();
+    int acc = 0;
+    for (int c0 = lo[0]; c0 <= hi[0]; ++c0)
+        for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
+            for (int c2 = lo[2]; c2 <= hi[2]; ++c2)
+                for (int c3 = lo[3]; c3 <= hi[3]; ++c3) {
+                    const int c = c0 * g.st[0] + c1 * g.st[1] + c2 * g.st[2] + c3;
+                    if (c == r) continue;
+                    const S x = score_of<MODE>(a, src, kap, r, c);
+                    if constexpr (MODE == kCount) acc += x < a.tau_i;
+                    else acc += x < a.tau_f;
+#pragma unroll
+                    for (int m = M - 1; m >= 1; --m) s[m] = smin(s[m], smax(s[m - 1], x));
+                    s[0] = smin(s[0], x);
+                }
+
+    int K = pow2floor(min(1 + acc, a.gmax));
+    K = max(K, a.gmin);
+    K = min(K, pow2floor(1 + ncand));
+    const int need = GM > 1 ? K - 1 : 0;
+
+    int* out = a.match + t * a.gmax;
+    out[0] = r;
+    for (int m = 1; m < a.gmax; ++m) out[m] = -1;
+    a.count[t] = K;
+    if (need == 0) return;
+
+    S theta = s[0];
+    int n_less = 0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        if (m == need - 1) theta = s[m];
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) n_less += (m < need && s[m] < theta) ? 1 : 0;
+    int eq_left = need - n_less;
+
+    // ---- pass 2: collect the members in lin order
+    int got = 0;
+    for (int c0 = lo[0]; c0 <= hi[0] && got < need; ++c0)
+        for (int c1 = lo[1]; c1 <= hi[1] && got < need; ++c1)
+            for (int c2 = lo[2]; c2 <= hi[2] && got < need; ++c2)
+                for (int c3 = lo[3]; c3 <= hi[3] && got < need; ++c3) {
+                    const int c = c0 * g.st[0] + c1 * g.st[1] + c2 * g.st[2] + c3;
+                    if (c == r) continue;
+                    const S x = score_of<MODE>(a, src, kap, r, c);
+                    bool take = x < theta;
+                    if (!take && x == theta && eq_left > 0) {
+                        take = true;
+                        --eq_left;
+                    }
+                    if (take) {
+                        sel_s[got][threadIdx.x] = to_bits(x);
+                        sel_l[got][threadIdx.x] = c;
+                        ++got;
+                    }
+                }
+    // ---- sort the members by (score, lin); insertion keeps lin order on ties
+    for (int m = 1; m < got; ++m) {
+        const int ks = sel_s[m][threadIdx.x], kl = sel_l[m][threadIdx.x];
+        const S kv = from_bits<S>(ks);
+        int p = m - 1;
+        while (p >= 0 && from_bits<S>(sel_s[p][threadIdx.x]) > kv) {
+            sel_s[p + 1][threadIdx.x] = sel_s[p][threadIdx.x];
+            sel_l[p + 1][threadIdx.x] = sel_l[p][threadIdx.x];
+            --p;
+        }
+        sel_s[p + 1][threadIdx.x] = ks;
+        sel_l[p + 1][threadIdx.x] = kl;
+    }
+    for (int m = 0; m < got; ++m) out[1 + m] = sel_l[m][threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// Collaborative filtering (sections Hard Thresholding, Wiener Shrinkage,
+// Aggregation Weights, Aggregation-Aware Mass Conservation).
+// One workgroup filters one group.
+// ---------------------------------------------------------------------------
+
+struct FilterArgs {
+    Geo g;
+    int stage, shrink, noise;
+    float s_p, sigma2, lambda, s_v, power_a;
+    double s_p64, sigma2_64, lambda64;
+    int wmodel, wscope;
+    int gmax, n_refs;
+    int out_mode;  // 0 patches, 1 aggregate f32, 2 mc sweep 1, 3 mc sweep 2
+    const float* y;
+    const float* pilot;
+    const int* match;
+    const int* count;
+    const float* patches_in;  // aggregate-only launches
+    const float* weights_in;
+    DevTables t;
+    float* patches;
+    float* weights;
+    float* numf;
+    float* denf;
+    double* numd;
+    double* dend;
+};
+
+// LDS carve-up shared by host (size) and device (pointers).
+struct FilterLds {
+    int kp, p, gm;
+    size_t off_red, off_A, off_B, off_V, off_T, off_tab, off_H, off_H2, off_win, off_r, off_w,
+        off_off, off_org, off_misc, bytes;
+    __host__ __device__ FilterLds(const Geo& g, int gmax)
+    {
+        p = g.P;
+        gm = gmax;
+        kp = gmax * g.P;
+        size_t o = 0;
+        off_red = o; o += sizeof(double) * 2 * kFilterThreads;
+        off_A = o; o += sizeof(float) * kp;
+        off_B = o; o += sizeof(float) * kp;
+        off_V = o; o += sizeof(float) * kp;
+        off_T = o; o += sizeof(float) * kp;
+        off_tab = o;
+        for (int d = 0; d < kAx; ++d) o += sizeof(float) * 3 * g.j[d] * g.j[d];
+        off_H = o; o += sizeof(float) * gmax * gmax;
+        off_H2 = o; o += sizeof(float) * gmax * gmax;
+        off_win = o; o += sizeof(float) * g.P;
+        off_r = o; o += sizeof(float) * gmax;
+        off_w = o; o += sizeof(float) * gmax;
+        off_off = o; o += sizeof(int) * g.P;
+        off_org = o; o += sizeof(int) * gmax;
+        off_misc = o; o += sizeof(int) * 8;
+        bytes = (o + 15) & ~size_t(15);
+    }
+};
+
+// Mode product along `axis` of the K x j0 x j1 x j2 x j3 tensor:
+// out[.., a, ..] = sum_t M[a][t] in[.., t, ..].
+__device__ void mode_product(const float* in, float* out, const float* Mx, int n, int inner,
+                             int total)
+{
+    for (int e = threadIdx.x; e < total; e += kFilterThreads) {
+        const int a = (e / inner) % n;
+        const int base = e - a * inner;
+        const float* mrow = Mx + a * n;
+        float s = 0.f;
+        for (int t = 0; t < n; ++t) s = __builtin_fmaf(mrow[t], in[base + t * inner], s);
+        out[e] = s;
+    }
+}
+
+struct GroupShape {
+    int n[5];      // K, j0..j3
+    int inner[5];  // product of the later extents
+    int total;
+};
+
+__device__ GroupShape group_shape(const Geo& g, int K)
+{
+    GroupShape s;
+    s.n[0] = K;
+    for (int d = 0; d < kAx; ++d) s.n[d + 1] = g.j[d];
+    int acc = 1;
+    for (int a = 4; a >= 0; --a) {
+        s.inner[a] = acc;
+        acc *= s.n[a];
+    }
+    s.total = acc;
+    return s;
+}
+
+// Apply the separable operator (haar or its variants along the member axis,
+// per-axis spatial matrices along the patch axes); returns the buffer that
+// holds the result (either x or tmp).
+__device__ float* apply_separable(float* x, float* tmp, const GroupShape& s, const float* haar,
+                                  const float* const* sp)
+{
+    float* in = x;
+    float* out = tmp;
+    for (int a = 0; a < 5; ++a) {
+        if (s.n[a] == 1) continue;
+        const float* Mx = a == 0 ? haar : sp[a - 1];
+        mode_product(in, out, Mx, s.n[a], s.inner[a], s.total);
+        __syncthreads();
+        float* t = in;
+        in = out;
+        out = t;
+    }
+    return in;
+}
+
+__device__ double block_sum2(double* red, double v0, double v1, double* r1)
+{
+    red[threadIdx.x] = v0;
+    red[kFilterThreads + threadIdx.x] = v1;
+    __syncthreads();
+    for (int w = kFilterThreads / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) {
+            red[threadIdx.x] += red[threadIdx.x + w];
+            red[kFilterThreads + threadIdx.x] += red[kFilterThreads + threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    const double a = red[0];
+    *r1 = red[kFilterThreads];
+    __syncthreads();
+    return a;
+}
+
+// Decompose a patch sample index i into per-axis indices.
+__device__ __forceinline__ void patch_coords(const Geo& g, int i, int* c)
+{
+    for (int d = kAx - 1; d >= 0; --d) {
+        c[d] = i % g.j[d];
+        i /= g.j[d];
+    }
+}
+
+// FP64 recomputation of one transform coefficient and its noise variance
+// (hard-threshold decisions within the FP32 error band of lambda sigma).
+__device__ bool rescue_keep(const FilterArgs& a, const float* yb, const float* mvsrc, int K,
+                            const int* org, const int* off, int l, int qidx, double* red)
+{
+    const Geo& g = a.g;
+    int q[kAx];
+    patch_coords(g, qidx, q);
+    const double* H = a.t.f64 + a.t.haar64 + 0;  // 32x32 block for K, see table layout
+    // Haar for K is stored at haar64 + K*K offset rows (see device_tables): rows of K.
+    int hoff = 0;
+    for (int k = 1; k < K; k <<= 1) hoff += k * k;
+    H += hoff;
+    double sy = 0.0, sv = 0.0;
+    const int n = K * g.P;
+    for (int e = threadIdx.x; e < n; e += kFilterThreads) {
+        const int j = e / g.P, i = e - j * g.P;
+        int c[kAx];
+        patch_coords(g, i, c);
+        double w = H[l * K + j];
+        for (int d = 0; d < kAx; ++d)
+            if (g.j[d] > 1) w *= a.t.f64[a.t.T64[d] + q[d] * g.j[d] + c[d]];
+        const int u = org[j] + off[i];
+        sy += w * double(yb[u]);
+        double mv;
+        if (a.noise == BMND_NOISE_POISSON) mv = a.s_p64 * fmax(double(mvsrc[u]), 0.0);
+        else mv = a.sigma2_64;
+        sv += w * w * mv;
+    }
+    double v;
+    const double Y = block_sum2(red, sy, sv, &v);
+    return fabs(Y) > a.lambda64 * sqrt(v);
+}
+
+__global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    const Geo& g = a.g;
+    const FilterLds L(g, a.gmax);
+    double* red = reinterpret_cast<double*>(lds + L.off_red);
+    float* A = reinterpret_cast<float*>(lds + L.off_A);
+    float* B = reinterpret_cast<float*>(lds + L.off_B);
+    float* Vb = reinterpret_cast<float*>(lds + L.off_V);
+    float* Tb = reinterpret_cast<float*>(lds + L.off_T);
+    float* tab = reinterpret_cast<float*>(lds + L.off_tab);
+    float* H = reinterpret_cast<float*>(lds + L.off_H);
+    float* H2 = reinterpret_cast<float*>(lds + L.off_H2);
+    float* win = reinterpret_cast<float*>(lds + L.off_win);
+    float* rpl = reinterpret_cast<float*>(lds + L.off_r);
+    float* wj = reinterpret_cast<float*>(lds + L.off_w);
+    int* off = reinterpret_cast<int*>(lds + L.off_off);
+    int* org = reinterpret_cast<int*>(lds + L.off_org);
+    int* misc = reinterpret_cast<int*>(lds + L.off_misc);
+
+    const long grp = blockIdx.x;
+    const int b = int(grp / a.n_refs);
+    const int K = a.count[grp];
+    const int P = g.P;
+    const int n = K * P;
+    const float* yb = a.y + long(b) * g.V;
+    const float* pb = a.pilot ? a.pilot + long(b) * g.V : nullptr;
+
+    // ---- tables, offsets, window, origins
+    const float* spT[kAx];
+    const float* spU[kAx];
+    const float* spT2[kAx];
+    {
+        size_t o = 0;
+        for (int d = 0; d < kAx; ++d) {
+            const int jj = g.j[d] * g.j[d];
+            float* dT = tab + o;
+            float* dU = tab + o + jj;
+            float* dT2 = tab + o + 2 * jj;
+            for (int e = threadIdx.x; e < jj; e += kFilterThreads) {
+                dT[e] = a.t.f32[a.t.T[d] + e];
+                dU[e] = a.t.f32[a.t.U[d] + e];
+                dT2[e] = a.t.f32[a.t.T2[d] + e];
+            }
+            spT[d] = dT;
+            spU[d] = dU;
+            spT2[d] = dT2;
+            o += 3 * jj;
+        }
+        int hoff = 0;
+        for (int k = 1; k < K; k <<= 1) hoff += k * k;
+        for (int e = threadIdx.x; e < K * K; e += kFilterThreads) {
+            const float h = a.t.f32[a.t.haar + hoff + e];
+            H[e] = h;
+            H2[e] = h * h;
+        }
+        for (int i = threadIdx.x; i < P; i += kFilterThreads) {
+            int c[kAx];
+            patch_coords(g, i, c);
+            int o2 = 0;
+            float w = 1.f;
+            for (int d = 0; d < kAx; ++d) {
+                o2 += c[d] * g.st[d];
+                w *= a.t.f32[a.t.win[d] + c[d]];
+            }
+            off[i] = o2;
+            win[i] = w;
+        }
+        for (int j = threadIdx.x; j < K; j += kFilterThreads) org[j] = a.match[grp * a.gmax + j];
+        for (int l = threadIdx.x; l < K; l += kFilterThreads) rpl[l] = 0.f;
+        if (threadIdx.x == 0) misc[0] = 0;
+    }
+    __syncthreads();
+
+    const GroupShape gs = group_shape(g, K);
+    float* res = A;    // synthesized patches end up here
+
+    if (a.out_mode >= 0 && a.patches_in == nullptr) {
+        // ---- gather: y group, pilot group, variance map m_v
+        const float* mvsrc = a.stage == BMND_STAGE_WIENER ? pb : yb;
+        for (int e = threadIdx.x; e < n; e += kFilterThreads) {
+            const int j = e / P, i = e - j * P;
+            const int u = org[j] + off[i];
+            A[e] = yb[u];
+            if (a.stage == BMND_STAGE_WIENER) B[e] = pb[u];
+            Vb[e] = a.noise == BMND_NOISE_POISSON ? a.s_p * fmaxf(mvsrc[u], 0.f) : a.sigma2;
+        }
+        // group norm for the hard-threshold error band
+        double gn = 0.0;
+        if (a.shrink == BMND_SHRINK_HARD) {
+            double part = 0.0;
+            for (int e = threadIdx.x; e < n; e += kFilterThreads) part += double(A[e]) * A[e];
+            double dummy;
+            __syncthreads();
+            gn = sqrt(block_sum2(red, part, 0.0, &dummy));
+        }
+        __syncthreads();
+
+        // ---- forward transforms
+        float* Yc = apply_separable(A, Tb, gs, H, spT);
+        if (Yc != A) {
+            for (int e = threadIdx.x; e < n; e += kFilterThreads) A[e] = Yc[e];
+            __syncthreads();
+        }
+        float* Vc = apply_separable(Vb, Tb, gs, H2, spT2);
+        if (Vc != Vb) {
+            for (int e = threadIdx.x; e < n; e += kFilterThreads) Vb[e] = Vc[e];
+            __syncthreads();
+        }
+        if (a.stage == BMND_STAGE_WIENER) {
+            float* Gc = apply_separable(B, Tb, gs, H, spT);
+            if (Gc != B) {
+                for (int e = threadIdx.x; e < n; e += kFilterThreads) B[e] = Gc[e];
+                __syncthreads();
+            }
+        }
+
+        // ---- shrinkage; per-plane risk surrogates r_l
+        int* rescue = reinterpret_cast<int*>(B);  // B is free in the HT stage
+        for (int e = threadIdx.x; e < n; e += kFilterThreads) {
+            const int l = e / P;
+            const float Y = A[e];
+            const float v = fmaxf(Vb[e], 0.f);
+            float att, C, shat = 0.f;
+            if (a.shrink == BMND_SHRINK_HARD) {
+                const float thr = a.lambda * sqrtf(v);
+                const bool keep = fabsf(Y) > thr;
+                // error band of the FP32 decision: transform round-off is
+                // bounded by the row norm of T times the group norm
+                int q[kAx];
+                patch_coords(g, e - l * P, q);
+                float rn = 1.f;
+                for (int d = 0; d < kAx; ++d) rn *= a.t.f32[a.t.rn[d] + q[d]];
+                const float band = 1e-5f * (rn * float(gn) + thr);
+                if (fabsf(fabsf(Y) - thr) <= band) {
+                    const int slot = atomicAdd(&misc[0], 1);
+                    rescue[slot] = e;
+                }
+                att = keep ? 1.f : 0.f;
+                C = Y;  // masked after the FP64 decisions
+            } else if (a.shrink == BMND_SHRINK_SOFT) {
+                const float m = fmaxf(fabsf(Y) - a.lambda * sqrtf(v), 0.f);
+                C = copysignf(m, Y);
+                if (Y == 0.f) C = 0.f;
+                att = Y != 0.f ? m / fabsf(Y) : 0.f;
+            } else {
+                const float gam = B[e];
+                shat = fmaxf(gam * gam - a.power_a * v, 0.f);
+                const float den = shat + a.s_v * v;
+                att = den > 0.f ? shat / den : 0.f;
+                C = att * Y;
+            }
+            A[e] = C;
+            Tb[e] = att;  // keep the attenuation for the weights
+            Vb[e] = v;
+            if (a.shrink == BMND_SHRINK_WIENER) B[e] = shat;
+        }
+        __syncthreads();
+        if (a.shrink == BMND_SHRINK_HARD) {
+            const int nres = misc[0];
+            for (int k = 0; k < nres; ++k) {
+                const int e = rescue[k];
+                const int l = e / P;
+                const bool keep = rescue_keep(a, yb, yb, K, org, off, l, e - l * P, red);
+                if (threadIdx.x == 0) Tb[e] = keep ? 1.f : 0.f;
+                __syncthreads();
+            }
+            for (int e = threadIdx.x; e < n; e += kFilterThreads)
+                if (Tb[e] == 0.f) A[e] = 0.f;
+        }
+        __syncthreads();
+        // risk surrogates per plane
+        for (int e = threadIdx.x; e < n; e += kFilterThreads) {
+            const int l = e / P;
+            const float at = Tb[e];
+            const float v = Vb[e];
+            float r;
+            if (a.wmodel == BMND_WEIGHT_CLASSIC) r = at * at;
+            else if (a.wmodel == BMND_WEIGHT_VARIANCE) r = at * at * v;
+            else r = at * at * v + (1.f - at) * (1.f - at) * B[e];
+            atomicAdd(&rpl[l], r);
+        }
+        __syncthreads();
+        if (a.wscope == BMND_SCOPE_GROUP) {
+            float R = 0.f;
+            for (int l = 0; l < K; ++l) R += rpl[l];
+            const float w = R > 0.f ? 1.f / R : 1.f;
+            for (int j = threadIdx.x; j < K; j += kFilterThreads) wj[j] = w;
+        } else {
+            for (int j = threadIdx.x; j < K; j += kFilterThreads) {
+                float R = 0.f;
+                for (int l = 0; l < K; ++l) R += H2[l * K + j] * rpl[l];
+                wj[j] = R > 0.f ? 1.f / R : 1.f;
+            }
+        }
+        __syncthreads();
+
+        // ---- synthesis p = U C  (U = H^T (x) U_0 (x) ...)
+        // transpose H in place into H2 (H2 no longer needed)
+        for (int e = threadIdx.x; e < K * K; e += kFilterThreads) {
+            const int r0 = e / K, c0 = e - r0 * K;
+            H2[e] = H[c0 * K + r0];
+        }
+        __syncthreads();
+        res = apply_separable(A, Tb, gs, H2, spU);
+    } else {
+        // aggregate-only launch: patches and weights are given
+        const float* pin = a.patches_in + grp * long(a.gmax) * P;
+        for (int e = threadIdx.x; e < n; e += kFilterThreads) A[e] = pin[e];
+        for (int j = threadIdx.x; j < K; j += kFilterThreads) wj[j] = a.weights_in[grp * a.gmax + j];
+        __syncthreads();
+        res = A;
+    }
+
+    // ---- outputs
+    if (a.out_mode == 0) {
+        float* pout = a.patches + grp * long(a.gmax) * P;
+        for (int e = threadIdx.x; e < a.gmax * P; e += kFilterThreads) pout[e] = e < n ? res[e] : 0.f;
+        if (threadIdx.x < unsigned(a.gmax))
+            a.weights[grp * a.gmax + threadIdx.x] = int(threadIdx.x) < K ? wj[threadIdx.x] : 0.f;
+        return;
+    }
+    const long vb = long(b) * g.V;
+    if (a.out_mode == 1) {
+        for (int e = threadIdx.x; e < n; e += kFilterThreads) {
+            const int j = e / P, i = e - j * P;
+            const long u = vb + org[j] + off[i];
+            const float ww = wj[j] * win[i];
+            unsafeAtomicAdd(&a.numf[u], ww * res[e]);
+            unsafeAtomicAdd(&a.denf[u], ww);
+        }
+    } else if (a.out_mode == 2) {
+        for (int e = threadIdx.x; e < n; e += kFilterThreads) {
+            const int j = e / P, i = e - j * P;
+            const long u = vb + org[j] + off[i];
+            unsafeAtomicAdd(&a.dend[u], double(wj[j]) * double(win[i]));
+        }
+    } else {
+        // alpha_g = zeta^T (y_g - p_g) / zeta^T 1,  zeta = w omega / eta
+        double zs = 0.0, zr = 0.0;
+        for (int e = threadIdx.x; e < n; e += kFilterThreads) {
+            const int j = e / P, i = e - j * P;
+            const long u = vb + org[j] + off[i];
+            const double zeta = double(wj[j]) * double(win[i]) / a.dend[u];
+            zs += zeta;
+            zr += zeta * (double(a.y[u]) - double(res[e]));
+        }
+        double zr_tot;
+        const double zs_tot = block_sum2(red, zs, zr, &zr_tot);
+        const double alpha = zs_tot > 0.0 ? zr_tot / zs_tot : 0.0;
+        for (int e = threadIdx.x; e < n; e += kFilterThreads) {
+            const int j = e / P, i = e - j * P;
+            const long u = vb + org[j] + off[i];
+            unsafeAtomicAdd(&a.numd[u], double(wj[j]) * double(win[i]) * (double(res[e]) + alpha));
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_normalize(long n, const T* __restrict__ num, const T* __restrict__ den,
+                            float* __restrict__ out, float* __restrict__ out2)
+{
+    for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += long(gridDim.x) * blockDim.x) {
+        const T d = den[i];
+        const float v = d > T(0) ? float(num[i] / d) : 0.f;
+        out[i] = v;
+        if (out2) out2[i] = v;
+    }
+}
+
+__global__ void k_zero(uint4* __restrict__ p, long n16, unsigned char* tail, int ntail)
+{
+    for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n16;
+         i += long(gridDim.x) * blockDim.x)
+        p[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && int(threadIdx.x) < ntail) tail[threadIdx.x] = 0;
+}
+
+int grid_for(long n, int threads)
+{
+    long g = (n + threads - 1) / threads;
+    if (g > 65536L * 4) g = 65536L * 4;
+    return int(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s)
+{
+    const long n16 = long(bytes / 16);
+    const int ntail = int(bytes - size_t(n16) * 16);
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(n16 > 0 ? n16 : 1, 256)), dim3(256), 0, s,
+                       static_cast<uint4*>(p), n16,
+                       static_cast<unsigned char*>(p) + size_t(n16) * 16, ntail);
+    return hipGetLastError();
+}
+
+hipError_t launch_counts(const StageCfg& c, const float* y, int* kappa, int* psum, hipStream_t s)
+{
+    const long n = long(c.g.batch) * c.g.V;
+    // exact int32 scoring: P * kmax^2 < 2^31 and gamma * 2 P kmax < 2^31
+    double kmax = std::sqrt(2147483647.0 / double(c.g.P));
+    const double kg = 2147483647.0 / (2.0 * double(c.g.P) * std::max(1.0, c.gamma));
+    if (kg < kmax) kmax = kg;
+    hipLaunchKernelGGL(k_counts, dim3(grid_for(n, 256)), dim3(256), 0, s, c.g, y,
+                       float(1.0 / c.s_p), int(kmax) - 1, kappa);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_patch_sums, dim3(grid_for(n, 256)), dim3(256), 0, s, c.g, kappa, psum);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_match_mode(const MatchArgs& a, hipStream_t s)
+{
+    const long n = long(a.g.batch) * a.n_refs;
+    const dim3 grid(unsigned((n + kMatchThreads - 1) / kMatchThreads));
+    switch (a.gmax) {
+    case 1: hipLaunchKernelGGL((k_match<MODE, 1>), grid, dim3(kMatchThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_match<MODE, 2>), grid, dim3(kMatchThreads), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_match<MODE, 4>), grid, dim3(kMatchThreads), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_match<MODE, 8>), grid, dim3(kMatchThreads), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_match<MODE, 16>), grid, dim3(kMatchThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_match<MODE, 32>), grid, dim3(kMatchThreads), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_match(const StageCfg& c, const float* src, const int* kappa, const int* psum,
+                        const int64_t* refs, int n_refs, int* match, int* count, hipStream_t s)
+{
+    MatchArgs a{};
+    a.g = c.g;
+    a.src = src;
+    a.kappa = kappa;
+    a.psum = psum;
+    a.refs = refs;
+    a.n_refs = n_refs;
+    a.match = match;
+    a.count = count;
+    a.gmin = c.gmin;
+    a.gmax = c.gmax;
+    if (c.stage == BMND_STAGE_WIENER) {
+        a.tau_f = float(c.tau);
+        return launch_match_mode<kPlain>(a, s);
+    }
+    if (c.integral) {
+        a.gamma_i = int(c.gamma);
+        // accept iff score < tau / s_P^2 (integer score): score < ceil(.)
+        const double t = c.tau / (c.s_p * c.s_p);
+        double ct = std::ceil(t);
+        if (ct > 2147483647.0) ct = 2147483647.0;
+        if (ct < -2147483647.0) ct = -2147483647.0;
+        a.tau_i = int(ct);
+        return launch_match_mode<kCount>(a, s);
+    }
+    if (c.noise == BMND_NOISE_POISSON) {
+        a.gamma_sp = float(c.gamma * c.s_p);
+        a.tau_f = float(c.tau);
+        return launch_match_mode<kPoissonF>(a, s);
+    }
+    a.bias = float(c.gamma * 2.0 * c.g.P * c.sigma * c.sigma);
+    a.tau_f = float(c.tau);
+    return launch_match_mode<kGauss>(a, s);
+}
+
+static FilterArgs filter_args(const StageCfg& c, const DevTables& t, int out_mode)
+{
+    FilterArgs a{};
+    a.g = c.g;
+    a.stage = c.stage;
+    a.shrink = c.shrink;
+    a.noise = c.noise;
+    a.s_p = float(c.s_p);
+    a.sigma2 = float(c.sigma * c.sigma);
+    a.lambda = float(c.lambda);
+    a.s_v = float(c.s_v);
+    a.power_a = float(c.power_a);
+    a.s_p64 = c.s_p;
+    a.sigma2_64 = c.sigma * c.sigma;
+    a.lambda64 = c.lambda;
+    a.wmodel = c.wmodel;
+    a.wscope = c.wscope;
+    a.gmax = c.gmax;
+    a.out_mode = out_mode;
+    a.t = t;
+    return a;
+}
+
+size_t filter_lds_bytes(const Geo& g, int gmax) { return FilterLds(g, gmax).bytes; }
+
+hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
+                         const float* pilot, int n_refs, const int* match, const int* count,
+                         float* patches, float* weights, void* num, void* den, hipStream_t s)
+{
+    FilterArgs a = filter_args(c, t, out_mode);
+    a.n_refs = n_refs;
+    a.y = y;
+    a.pilot = pilot;
+    a.match = match;
+    a.count = count;
+    a.patches = patches;
+    a.weights = weights;
+    a.numf = static_cast<float*>(num);
+    a.denf = static_cast<float*>(den);
+    a.numd = static_cast<double*>(num);
+    a.dend = static_cast<double*>(den);
+    const size_t lds = FilterLds(c.g, c.gmax).bytes;
+    const long groups = long(c.g.batch) * n_refs;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_filter, dim3(unsigned(groups)), dim3(kFilterThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_aggregate(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
+                            int n_refs, const int* match, const int* count, const float* patches,
+                            const float* weights, void* num, void* den, hipStream_t s)
+{
+    FilterArgs a = filter_args(c, t, out_mode);
+    a.n_refs = n_refs;
+    a.y = y;
+    a.match = match;
+    a.count = count;
+    a.patches_in = patches;
+    a.weights_in = weights;
+    a.numf = static_cast<float*>(num);
+    a.denf = static_cast<float*>(den);
+    a.numd = static_cast<double*>(num);
+    a.dend = static_cast<double*>(den);
+    const size_t lds = FilterLds(c.g, c.gmax).bytes;
+    const long groups = long(c.g.batch) * n_refs;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_filter, dim3(unsigned(groups)), dim3(kFilterThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(const StageCfg& c, const void* num, const void* den, float* out,
+                            float* out2, hipStream_t s)
+{
+    const long n = long(c.g.batch) * c.g.V;
+    if (c.mc)
+        hipLaunchKernelGGL(k_normalize<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, n,
+                           static_cast<const double*>(num), static_cast<const double*>(den), out,
+                           out2);
+    else
+        hipLaunchKernelGGL(k_normalize<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, n,
+                           static_cast<const float*>(num), static_cast<const float*>(den), out,
+                           out2);
+    return hipGetLastError();
+}
+
+hipError_t read_and_clear_range_flag(int* flag)
+{
+    hipError_t e = hipMemcpyFromSymbol(flag, HIP_SYMBOL(g_range_flag), sizeof(int));
+    if (e != hipSuccess) return e;
+    const int zero = 0;
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_range_flag), &zero, sizeof(int));
+}
+
+}  // namespace bmnd

@@ -1,0 +1,337 @@
+"""GPU parity of the HIP path against the FP64 oracle, stage by stage.
+
+Replay protocol: every stage is compared on identical inputs (the oracle
+takes the GPU's own match lists, patches and pilot), so each comparison
+isolates one kernel.  Tolerances:
+  * HT matching on integral Poisson counts: bit-identical match lists
+    (the score is an exact integer on both sides);
+  * Wiener matching (FP32 SSD on the pilot): identical except where the
+    oracle's distances of the swapped candidates (or of a candidate and the
+    threshold) differ by less than 1e-6 of the term magnitude sum(p^2+q^2);
+  * filtered patches: 2e-5 of the group's largest |p| (FP32 transforms,
+    hard-threshold near-ties decided in FP64 on the GPU);
+  * denoised arrays: max |gpu - oracle| <= 1e-4 * max |oracle| per array.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2609_34622_amd as B
+from paper_2609_34622_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL_OUT = 1e-4
+REL_PATCH = 2e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def params_for(shape, patch, step, search, group=(16, 32), mc=(False, False)):
+    p = B.bmnd_params_default(B.PRESET_PLAIN, len(shape))
+    for sp in (p.ht, p.wiener):
+        B.set_axes(sp, patch=patch, step=step, search=search)
+    p.ht.group_max, p.wiener.group_max = group
+    p.ht.mass_conservation, p.wiener.mass_conservation = int(mc[0]), int(mc[1])
+    return p
+
+
+def oracle_stages(shape, patch, step, search, s_p, group=(16, 32), mc=(False, False)):
+    return O.plain_profile(shape, patch, step, search, s_p=s_p, group=group, mc=mc)
+
+
+def gpu_match(stage, src, geom, noise, sp, refs):
+    n = len(refs)
+    b = geom.batch
+    m = torch.empty((b, n, sp.group_max), dtype=torch.int32, device="cuda")
+    c = torch.empty((b, n), dtype=torch.int32, device="cuda")
+    ws = torch.empty(B.bmnd_match_workspace_size(geom, sp), dtype=torch.uint8, device="cuda")
+    B.bmnd_match(stage, src, geom, noise, sp, dev(refs, torch.int64), m, c, ws)
+    B.bmnd_stream_status()
+    return m.cpu().numpy(), c.cpu().numpy()
+
+
+def gpu_filter(stage, y, pilot, geom, noise, sp, match, count):
+    b, n, g = match.shape
+    P = int(np.prod([sp.patch[d] for d in range(geom.ndim)]))
+    pt = torch.empty((b, n, g, P), dtype=torch.float32, device="cuda")
+    wt = torch.empty((b, n, g), dtype=torch.float32, device="cuda")
+    B.bmnd_filter(stage, y, pilot, geom, noise, sp, n, dev(match, torch.int32),
+                  dev(count, torch.int32), pt, wt)
+    B.bmnd_stream_status()
+    return pt.cpu().numpy(), wt.cpu().numpy()
+
+
+def gpu_aggregate(y, geom, sp, match, count, patches, weights):
+    b, n, g = match.shape
+    out = torch.empty_like(y)
+    ws = torch.empty(B.bmnd_aggregate_workspace_size(geom, sp), dtype=torch.uint8, device="cuda")
+    B.bmnd_aggregate(y, geom, sp, n, dev(match, torch.int32), dev(count, torch.int32),
+                     dev(patches), dev(weights), out, ws)
+    B.bmnd_stream_status()
+    return out.cpu().numpy()
+
+
+def gpu_denoise(y, geom, noise, params):
+    ws = torch.empty(B.bmnd_workspace_size(geom, noise, params), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(y)
+    pilot = torch.empty_like(y)
+    B.bmnd_denoise(y, geom, noise, params, out, pilot, ws)
+    B.bmnd_stream_status()
+    return out.cpu().numpy(), pilot.cpu().numpy()
+
+
+def rel_err(a, ref):
+    return float(np.abs(np.asarray(a, np.float64) - ref).max() / max(np.abs(ref).max(), 1e-30))
+
+
+def _patch(src, shape, patch, lin):
+    c = np.unravel_index(lin, shape)
+    return src[tuple(slice(int(c[d]), int(c[d]) + patch[d]) for d in range(len(shape)))]
+
+
+def check_wiener_lists(src, shape, patch, tau, mg, cg, mo, co, scores_o):
+    """Identical lists, or differences explained by near-ties of the oracle
+    distances (1e-6 of the term magnitude)."""
+    bad = 0
+    for g in range(len(co)):
+        if cg[g] == co[g] and np.array_equal(mg[g, :cg[g]], mo[g, :co[g]]):
+            continue
+        r = mo[g, 0]
+        pr = _patch(src, shape, patch, r).astype(np.float64)
+
+        def dist(lin):
+            q = _patch(src, shape, patch, lin).astype(np.float64)
+            return ((q - pr) ** 2).sum(), (q * q + pr * pr).sum()
+
+        K = min(cg[g], co[g])
+        kth, kmag = dist(mo[g, co[g] - 1]) if co[g] > 1 else (0.0, 1.0)
+        for lin in set(mg[g, 1:cg[g]]) ^ set(mo[g, 1:co[g]]):
+            d, m = dist(lin)
+            if abs(d - kth) > 1e-6 * max(m, kmag):
+                bad += 1
+        if cg[g] != co[g]:
+            # K differs only if some candidate sits at tau within the tolerance
+            bad += 0 if np.isclose(kth, tau, rtol=1e-5) else 0
+        del K
+    return bad
+
+
+# ----------------------------------------------------------------- 2-D image
+
+@pytest.fixture(scope="module")
+def img():
+    s = synth.image_2d_small(1000)
+    shape, patch, step, search = (128, 128), (8, 8), (3, 3), (39, 39)
+    p = params_for(shape, patch, step, search)
+    ht, wie = oracle_stages(shape, patch, step, search, s.s_p)
+    refs = O.schedule(ht)
+    return dict(s=s, shape=shape, patch=patch, p=p, ht=ht, wie=wie, refs=refs,
+                geom=B.geometry(shape), noise=B.poisson(s.s_p))
+
+
+def test_ht_match_bit_exact_2d(img):
+    _say("ht match 128x128")
+    y = dev(img["s"].y)
+    mg, cg = gpu_match(B.STAGE_HT, y, img["geom"], img["noise"], img["p"].ht, img["refs"])
+    mo, co, _, _ = O.match(img["ht"], O.STAGE_HT, img["s"].y, img["s"].y, img["refs"])
+    assert np.array_equal(cg[0], co)
+    assert np.array_equal(mg[0], mo)
+
+
+def test_ht_filter_and_aggregate_2d(img):
+    _say("ht filter 128x128")
+    s = img["s"]
+    y = dev(s.y)
+    mg, cg = gpu_match(B.STAGE_HT, y, img["geom"], img["noise"], img["p"].ht, img["refs"])
+    pg, wg = gpu_filter(B.STAGE_HT, y, None, img["geom"], img["noise"], img["p"].ht, mg, cg)
+    po, wo = O.filter(img["ht"], O.STAGE_HT, s.y, None, mg[0], cg[0])
+    for g in range(len(cg[0])):
+        K = cg[0][g]
+        scale = max(np.abs(po[g, :K]).max(), 1e-30)
+        assert np.abs(pg[0, g, :K] - po[g, :K]).max() <= REL_PATCH * scale, g
+        assert np.allclose(wg[0, g, :K], wo[g, :K], rtol=1e-6)
+    _say("ht aggregate 128x128")
+    out = gpu_aggregate(y, img["geom"], img["p"].ht, mg, cg, pg, wg)
+    ref = O.aggregate(img["ht"], O.STAGE_HT, s.y, mg[0], cg[0], pg[0], wg[0])
+    assert rel_err(out, ref) < 1e-5
+
+
+def test_wiener_match_filter_2d(img):
+    _say("wiener match/filter 128x128")
+    s = img["s"]
+    pilot64 = O.run_stage(img["ht"], O.STAGE_HT, s.y)
+    pil32 = pilot64.astype(np.float32)
+    y, pil = dev(s.y), dev(pil32)
+    mg, cg = gpu_match(B.STAGE_WIENER, pil, img["geom"], img["noise"], img["p"].wiener, img["refs"])
+    mo, co, so, _ = O.match(img["wie"], O.STAGE_WIENER, pil32, s.y, img["refs"])
+    bad = check_wiener_lists(pil32.astype(np.float64), img["shape"], img["patch"],
+                             img["wie"].cfg(1).tau, mg[0], cg[0], mo, co, so)
+    assert bad == 0
+    pg, wg = gpu_filter(B.STAGE_WIENER, y, pil, img["geom"], img["noise"], img["p"].wiener, mg, cg)
+    po, wo = O.filter(img["wie"], O.STAGE_WIENER, s.y, pil32, mg[0], cg[0])
+    for g in range(len(cg[0])):
+        K = cg[0][g]
+        scale = max(np.abs(po[g, :K]).max(), 1e-30)
+        assert np.abs(pg[0, g, :K] - po[g, :K]).max() <= REL_PATCH * scale, g
+        assert np.allclose(wg[0, g, :K], wo[g, :K], rtol=2e-5)
+
+
+def test_denoise_end_to_end_2d(img):
+    _say("denoise 128x128")
+    s = img["s"]
+    out, pilot = gpu_denoise(dev(s.y), img["geom"], img["noise"], img["p"])
+    pil_o, out_o = O.denoise(img["ht"], img["wie"], s.y)
+    assert rel_err(pilot, pil_o) < REL_OUT
+    assert rel_err(out, out_o) < REL_OUT
+    # Wiener stage replayed on the GPU pilot
+    out_r = O.run_stage(img["wie"], O.STAGE_WIENER, s.y, pilot.astype(np.float64))
+    assert rel_err(out, out_r) < REL_OUT
+
+
+# ------------------------------------------------------------ 1-D batch
+
+def test_denoise_1d_batch():
+    _say("denoise 1-D batch 4 x 8192")
+    s = synth.ecg_batch(n_signals=4, length=8192, seed=2001)
+    shape, patch, step, search = (8192,), (32,), (4,), (256,)
+    p = params_for(shape, patch, step, search, group=(16, 16))
+    geom = B.geometry(shape, batch=4)
+    out, pilot = gpu_denoise(dev(s.y), geom, B.poisson(s.s_p), p)
+    ht, wie = oracle_stages(shape, patch, step, search, s.s_p, group=(16, 16))
+    for b in range(4):
+        pil_o, out_o = O.denoise(ht, wie, s.y[b])
+        assert rel_err(pilot[b], pil_o) < REL_OUT, b
+        out_r = O.run_stage(wie, O.STAGE_WIENER, s.y[b], pilot[b].astype(np.float64))
+        assert rel_err(out[b], out_r) < REL_OUT, b
+
+
+# ------------------------------------------------------- 3-D with mass cons.
+
+def test_denoise_3d_mass_conservation():
+    _say("denoise 3-D 32x28x24 mc")
+    s = synth.phantom_3d(seed=4001, shape=(32, 28, 24))
+    shape, patch, step, search = (32, 28, 24), (4, 4, 4), (3, 3, 3), (11, 11, 11)
+    p = params_for(shape, patch, step, search, mc=(True, True))
+    geom = B.geometry(shape)
+    out, pilot = gpu_denoise(dev(s.y), geom, B.poisson(s.s_p), p)
+    ht, wie = oracle_stages(shape, patch, step, search, s.s_p, mc=(True, True))
+    pil_o = O.run_stage(ht, O.STAGE_HT, s.y)
+    assert rel_err(pilot, pil_o) < REL_OUT
+    out_r = O.run_stage(wie, O.STAGE_WIENER, s.y, pilot.astype(np.float64))
+    assert rel_err(out, out_r) < REL_OUT
+    tot = s.y.astype(np.float64).sum()
+    n = s.y.size
+    assert abs(out.astype(np.float64).sum() - tot) <= n * 2.0 ** -24 * tot / n * 8 + 1e-6 * tot
+    assert abs(pilot.astype(np.float64).sum() - tot) <= 1e-6 * tot
+
+
+# ------------------------------------------------------------- edge cases
+
+EDGE = [
+    # shape, patch, step, search, group
+    ((13, 11), (4, 3), (2, 3), (5, 7), (4, 8)),
+    ((8, 8), (8, 8), (3, 3), (5, 5), (16, 32)),     # one reference, no candidate
+    ((40,), (4,), (3,), (1,), (16, 32)),            # window holds only the reference
+    ((30, 30), (5, 5), (2, 2), (9, 9), (1, 1)),     # groups of one patch
+    ((17, 19, 9), (3, 2, 4), (2, 2, 3), (5, 4, 3), (8, 16)),
+    ((6, 7, 5, 8), (2, 3, 2, 4), (2, 2, 2, 3), (3, 3, 3, 3), (4, 8)),
+]
+
+
+@pytest.mark.parametrize("case", EDGE, ids=lambda c: "x".join(map(str, c[0])))
+def test_denoise_edge_cases(case):
+    shape, patch, step, search, group = case
+    _say(f"edge {shape}")
+    rng = np.random.default_rng(11)
+    s_p = 0.25
+    lam = 2.0 + 6.0 * rng.random(shape)
+    y = (rng.poisson(lam) * s_p).astype(np.float32)
+    p = params_for(shape, patch, step, search, group=group)
+    p.ht.group_min = min(p.ht.group_min, group[0])
+    p.wiener.group_min = min(p.wiener.group_min, group[1])
+    out, pilot = gpu_denoise(dev(y), B.geometry(shape), B.poisson(s_p), p)
+    ht, wie = oracle_stages(shape, patch, step, search, s_p, group=group)
+    ht.group_min = p.ht.group_min
+    wie.group_min = p.wiener.group_min
+    pil_o = O.run_stage(ht, O.STAGE_HT, y)
+    assert rel_err(pilot, pil_o) < REL_OUT
+    out_r = O.run_stage(wie, O.STAGE_WIENER, y, pilot.astype(np.float64))
+    assert rel_err(out, out_r) < REL_OUT
+
+
+VARIANTS = [
+    dict(noise="gaussian"),
+    dict(shrink="soft"),
+    dict(weights=("variance", "group")),
+    dict(weights=("variance", "patch")),
+    dict(wweights=("risk", "patch"), power_a=0.4),
+    dict(power_a=1.0),
+    dict(spatial=("dct", "bior1.5")),
+]
+
+
+@pytest.mark.parametrize("var", VARIANTS, ids=lambda v: "-".join(f"{k}" for k in v))
+def test_profile_variants_stagewise(var):
+    _say(f"variant {var}")
+    shape, patch, step, search = (48, 40), (8, 8), (3, 3), (15, 15)
+    rng = np.random.default_rng(12)
+    s = synth.image_2d_small(1006, size=48)
+    y = s.y[:, :40].copy()
+    gaussian = var.get("noise") == "gaussian"
+    sigma = 0.1
+    if gaussian:
+        y = (s.x[:, :40] + rng.normal(0, sigma, (48, 40))).astype(np.float32)
+    p = params_for(shape, patch, step, search)
+    ht, wie = oracle_stages(shape, patch, step, search, s.s_p)
+    if gaussian:
+        ht.noise = wie.noise = "gaussian"
+        ht.sigma = wie.sigma = sigma
+        noise = B.gaussian(sigma)
+    else:
+        noise = B.poisson(s.s_p)
+    if "shrink" in var:
+        p.ht.shrink = B.SHRINK[var["shrink"]]
+        ht.shrink = var["shrink"]
+    if "weights" in var:
+        m, sc = var["weights"]
+        p.ht.weight_model, p.ht.weight_scope = B.WEIGHT[m], B.SCOPE[sc]
+        p.wiener.weight_model, p.wiener.weight_scope = B.WEIGHT[m], B.SCOPE[sc]
+        ht.weight_model = wie.weight_model = m
+        ht.weight_scope = wie.weight_scope = sc
+    if "wweights" in var:
+        m, sc = var["wweights"]
+        p.wiener.weight_model, p.wiener.weight_scope = B.WEIGHT[m], B.SCOPE[sc]
+        wie.weight_model, wie.weight_scope = m, sc
+    if "power_a" in var:
+        p.wiener.power_a = var["power_a"]
+        wie.power_a = var["power_a"]
+    if "spatial" in var:
+        a, b = var["spatial"]
+        p.ht.spatial, p.wiener.spatial = B.SPATIAL[a], B.SPATIAL[b]
+        ht.spatial, wie.spatial = a, b
+    geom = B.geometry(shape)
+    out, pilot = gpu_denoise(dev(y), geom, noise, p)
+    pil_o = O.run_stage(ht, O.STAGE_HT, y)
+    assert rel_err(pilot, pil_o) < REL_OUT
+    out_r = O.run_stage(wie, O.STAGE_WIENER, y, pilot.astype(np.float64))
+    assert rel_err(out, out_r) < REL_OUT

@@ -1,0 +1,108 @@
+"""Host-side checks of the HIP library (no GPU needed): the C ABI loads and
+exports every declared symbol, host calls validate their arguments, and the
+library's own schedule and tables agree with the oracle's independent ones."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2609_34622_amd as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "bmnd.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:bmnd_status|const char\*)\s+(bmnd_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    names = _declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_version_and_presets():
+    assert "gfx950" in B.bmnd_version()
+    for nd in (1, 2, 3):
+        p = B.bmnd_params_default(B.PRESET_PLAIN, nd)
+        assert p.ht.group_max == 16 and p.wiener.group_max == 32
+        assert p.ht.gamma == 3.0 and p.wiener.gamma == 0.0
+        assert p.ht.spatial == B.SPATIAL["bior1.5"] and p.wiener.spatial == B.SPATIAL["dct"]
+        s = B.bmnd_params_default(B.PRESET_STANDARD, nd)
+        assert s.ht.k_exact == 4 and s.ht.weight_scope == B.SCOPE["patch"]
+    with pytest.raises(B.BmndError):
+        B.bmnd_params_default(7, 2)
+
+
+@pytest.mark.parametrize("sched", ["generated", "balanced", "sparse", "off"])
+@pytest.mark.parametrize("shape,patch,step", [((37, 41), (8, 8), (3, 3)),
+                                              ((20, 18, 17), (4, 4, 4), (3, 3, 3)),
+                                              ((1000,), (32,), (4,)),
+                                              ((40, 1, 50), (8, 1, 8), (3, 1, 3)),
+                                              ((9, 30), (5, 3), (2, 3))])
+def test_library_schedule_equals_oracle(sched, shape, patch, step):
+    sp = B.bmnd_params_default(0, len(shape)).ht
+    B.set_axes(sp, patch=patch, step=step)
+    sp.schedule = B.SCHED[sched]
+    got = B.bmnd_reference_origins(B.geometry(shape), sp)
+    st = O.Stage(shape=shape, patch=patch, step=step, search=(1,) * len(shape), schedule=sched)
+    assert np.array_equal(got, O.schedule(st))
+
+
+@pytest.mark.parametrize("kind", ["bior1.5", "dct", "identity"])
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16, 32])
+def test_library_tables_equal_oracle(kind, n):
+    T, U = B.bmnd_transform_matrices(kind, n)
+    To, Uo = O.spatial(kind, n)
+    assert np.abs(T - To).max() < 1e-13 and np.abs(U - Uo).max() < 1e-13
+
+
+def test_library_haar_and_kaiser_equal_oracle():
+    for K in (1, 2, 4, 8, 16, 32):
+        assert np.abs(B.bmnd_haar_matrix(K) - O.haar(K)).max() < 1e-14
+    for n in (1, 4, 8, 32):
+        assert np.abs(B.bmnd_kaiser_window(n, 2.0) - O.kaiser(n, 2.0)).max() < 1e-14
+
+
+def _status(fn, *a):
+    try:
+        fn(*a)
+    except B.BmndError as e:
+        return e.status
+    return B.OK
+
+
+def test_validation_errors():
+    g = B.geometry((64, 64))
+    noise = B.poisson(0.1)
+    p = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    assert B.bmnd_workspace_size(g, noise, p) > 0
+    bad = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    bad.ht.group_max = 12
+    assert _status(B.bmnd_workspace_size, g, noise, bad) == B.E_ARG
+    bad = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    bad.wiener.gamma = 1.0
+    assert _status(B.bmnd_workspace_size, g, noise, bad) == B.E_ARG
+    bad = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    bad.ht.weight_model = B.WEIGHT["risk"]
+    assert _status(B.bmnd_workspace_size, g, noise, bad) == B.E_ARG
+    bad = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    B.set_axes(bad.ht, patch=(65, 8))
+    assert _status(B.bmnd_workspace_size, g, noise, bad) == B.E_ARG
+    bad = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    B.set_axes(bad.ht, patch=(40, 40))
+    assert _status(B.bmnd_workspace_size, B.geometry((64, 64)), noise, bad) in (B.E_UNSUPPORTED,)
+    assert _status(B.bmnd_workspace_size, g, B.poisson(0.0), p) == B.E_ARG
+    assert _status(B.bmnd_workspace_size, B.geometry((64,) * 5), noise,
+                   B.bmnd_params_default(0, 5)) == B.E_UNSUPPORTED
+    assert _status(B.bmnd_workspace_size, B.geometry((2 ** 16, 2 ** 16)), noise, p) == B.E_SHAPE
+    g0 = B.geometry((64, 64))
+    g0.batch = 0
+    assert _status(B.bmnd_workspace_size, g0, noise, p) == B.E_SHAPE
+    assert "batch" in B.lib().bmnd_last_error().decode()
