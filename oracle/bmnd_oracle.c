@@ -14,6 +14,7 @@
 #include <string.h>
 
 #define ORC_PI 3.14159265358979323846
+#define ORC_TIE_REL 1e-9
 
 /* ------------------------------------------------------------------ */
 /* geometry helpers                                                    */
@@ -355,7 +356,11 @@ int orc_spatial_matrices(int32_t kind, int32_t n, double* T, double* U)
         for (int k = 0; k < n; ++k) {
             double ck = sqrt((k == 0 ? 1.0 : 2.0) / (double)n);
             for (int m = 0; m < n; ++m) {
-                T[k * n + m] = ck * cos(ORC_PI * (2.0 * m + 1.0) * k / (2.0 * n));
+                /* cos(pi q / (2n)), q = k (2m + 1), is exactly 0 when q / n is
+                 * an odd integer (an odd multiple of pi/2) */
+                const long q = (long)k * (2L * m + 1L);
+                const int zero = (q % n == 0) && ((q / n) % 2 == 1);
+                T[k * n + m] = zero ? 0.0 : ck * cos(ORC_PI * (2.0 * m + 1.0) * k / (2.0 * n));
                 U[m * n + k] = T[k * n + m];
             }
         }
@@ -828,8 +833,13 @@ static int filter_group(stage_ctx* x, const orc_cfg* c, int stage, const double*
         double sig2 = var[e] > 0.0 ? var[e] : 0.0;
         double Y = Yc[e];
         if (c->shrink == ORC_SHRINK_HARD) {
-            /* eq. hard-threshold: keep iff |Y_k| > lambda sigma_k */
-            double a = (fabs(Y) > c->lambda * sqrt(sig2)) ? 1.0 : 0.0;
+            /* eq. hard-threshold: keep iff |Y_k| > lambda sigma_k.  With
+             * integral counts exact ties occur (a coefficient fed by one
+             * sample with kappa = lambda^2 has |Y| = lambda sigma exactly),
+             * and the strict inequality drops them; the comparison is made
+             * with a relative margin of 1e-9 so that a tie is not decided by
+             * the rounding of Y and sigma. */
+            double a = (fabs(Y) > c->lambda * sqrt(sig2) * (1.0 + ORC_TIE_REL)) ? 1.0 : 0.0;
             att[e] = a;
             C[e] = a * Y;
             shat[e] = 0.0;

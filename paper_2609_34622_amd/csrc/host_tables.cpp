@@ -5,11 +5,12 @@
 // bior1.5: the synthesis lowpass is the order-1 B-spline filter
 // (1, 1)/sqrt(2).  Its 10-tap dual (analysis) lowpass is obtained here as
 // the solution of the linear conditions that define it: biorthogonality
-// sum_n lo[n] lo~[n + 2k] = sqrt(2)^0 delta_k for |k| <= 2, and five
+// sum_n lo[n] lo~[n + 2k] = delta_k for |k| <= 2, and five
 // vanishing moments of the synthesis highpass hi[t] = (-1)^t lo~[1 - t]
 // (equivalently a fifth-order zero of lo~ at the Nyquist frequency).  The
 // periodised multilevel synthesis operator U is assembled from (lo, hi)
 // and the analysis operator is T = U^-1, inverted in double precision.
+#include <algorithm>
 #include <cmath>
 #include <utility>
 
@@ -125,7 +126,9 @@ void spatial_matrices(int kind, int n, std::vector<double>& T, std::vector<doubl
         for (int k = 0; k < n; ++k)
             for (int s = 0; s < n; ++s) {
                 const double scale = std::sqrt((k == 0 ? 1.0 : 2.0) / n);
-                const double v = scale * std::cos(pi * k * (2 * s + 1) / (2.0 * n));
+                double v = scale * std::cos(pi * k * (2 * s + 1) / (2.0 * n));
+                // odd multiples of pi/2 are exact zeros of the DCT-II matrix
+                if (std::fabs(v) < 1e-12) v = 0.0;
                 T[size_t(k * n + s)] = v;
                 U[size_t(s * n + k)] = v;
             }
@@ -147,6 +150,15 @@ void spatial_matrices(int kind, int n, std::vector<double>& T, std::vector<doubl
         }
     }
     T = inverse(U, n);
+    // Both multilevel operators have exact zeros (their nonzero entries are
+    // >= 1e-4 in magnitude up to n = 32); the solved dual taps and the
+    // inversion leave round-off of order 1e-16 there, which would turn
+    // zero-variance coefficients of dark groups into spurious nonzero ones.
+    // Restore the exact zeros.
+    for (double& v : T)
+        if (std::fabs(v) < 1e-12) v = 0.0;
+    for (double& v : U)
+        if (std::fabs(v) < 1e-12) v = 0.0;
 }
 
 // Orthonormal multilevel Haar, rows: scaling, then detail rows with support

@@ -23,6 +23,7 @@ namespace {
 
 constexpr int kMatchThreads = 64;
 constexpr int kFilterThreads = 256;
+constexpr double kTieRel = 1e-9;  // relative tie margin of the hard threshold
 
 // ---------------------------------------------------------------------------
 // Equivalent raw counts and their patch sums (eq. raw-counts; the plug-in
@@ -446,7 +447,7 @@ __device__ bool rescue_keep(const FilterArgs& a, const float* yb, const float* m
     }
     double v;
     const double Y = block_sum2(red, sy, sv, &v);
-    return fabs(Y) > a.lambda64 * sqrt(v);
+    return fabs(Y) > a.lambda64 * sqrt(v) * (1.0 + kTieRel);
 }
 
 __global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
@@ -574,6 +575,9 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
             const float v = fmaxf(Vb[e], 0.f);
             float att, C, shat = 0.f;
             if (a.shrink == BMND_SHRINK_HARD) {
+                // strict inequality; exact ties |Y| = lambda sigma (common with
+                // integral counts) fall inside the band and are dropped by the
+                // FP64 decision, which applies a 1e-9 relative tie margin
                 const float thr = a.lambda * sqrtf(v);
                 const bool keep = fabsf(Y) > thr;
                 // error band of the FP32 decision: transform round-off is
@@ -583,7 +587,9 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
                 float rn = 1.f;
                 for (int d = 0; d < kAx; ++d) rn *= a.t.f32[a.t.rn[d] + q[d]];
                 const float band = 1e-5f * (rn * float(gn) + thr);
-                if (fabsf(fabsf(Y) - thr) <= band) {
+                // v == 0 only if every source sample of the coefficient has
+                // zero variance; the decision is then Y != 0 on both sides
+                if (v > 0.f && fabsf(fabsf(Y) - thr) <= band) {
                     const int slot = atomicAdd(&misc[0], 1);
                     rescue[slot] = e;
                 }

@@ -56,11 +56,14 @@ def test_library_schedule_equals_oracle(sched, shape, patch, step):
 
 
 @pytest.mark.parametrize("kind", ["bior1.5", "dct", "identity"])
-@pytest.mark.parametrize("n", [1, 2, 4, 8, 16, 32])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 8, 12, 16, 32])
 def test_library_tables_equal_oracle(kind, n):
     T, U = B.bmnd_transform_matrices(kind, n)
     To, Uo = O.spatial(kind, n)
     assert np.abs(T - To).max() < 1e-13 and np.abs(U - Uo).max() < 1e-13
+    # exact zeros must stay exact (hard thresholds of zero-variance
+    # coefficients depend on them)
+    assert np.array_equal(T == 0, To == 0) and np.array_equal(U == 0, Uo == 0)
 
 
 def test_library_haar_and_kaiser_equal_oracle():
