@@ -1,0 +1,36 @@
+// Arguments shared by the filtering kernels (generic and cube-patch paths).
+#pragma once
+
+#include "bmnd_internal.h"
+
+namespace bmnd {
+
+struct FilterArgs {
+    Geo g;
+    int stage, shrink, noise;
+    float s_p, sigma2, lambda, s_v, power_a;
+    double s_p64, sigma2_64, lambda64;
+    int wmodel, wscope;
+    int gmax, n_refs;
+    int out_mode;  // 0 patches, 1 aggregate f32, 2 mc sweep 1, 3 mc sweep 2
+    const float* y;
+    const float* pilot;
+    const int* match;
+    const int* count;
+    const float* patches_in;  // aggregate-only launches
+    const float* weights_in;
+    DevTables t;
+    float* patches;
+    float* weights;
+    float* numf;
+    float* denf;
+    double* numd;
+    double* dend;
+};
+
+constexpr int ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
+
+bool cube_filter_supported(const Geo& g, int gmax);
+hipError_t launch_filter_cube(const FilterArgs& a, long groups, hipStream_t s);
+
+}  // namespace bmnd

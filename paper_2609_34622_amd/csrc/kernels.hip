@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "bmnd_internal.h"
+#include "filter_common.h"
 
 namespace bmnd {
 
@@ -281,28 +282,7 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
 // One workgroup filters one group.
 // ---------------------------------------------------------------------------
 
-struct FilterArgs {
-    Geo g;
-    int stage, shrink, noise;
-    float s_p, sigma2, lambda, s_v, power_a;
-    double s_p64, sigma2_64, lambda64;
-    int wmodel, wscope;
-    int gmax, n_refs;
-    int out_mode;  // 0 patches, 1 aggregate f32, 2 mc sweep 1, 3 mc sweep 2
-    const float* y;
-    const float* pilot;
-    const int* match;
-    const int* count;
-    const float* patches_in;  // aggregate-only launches
-    const float* weights_in;
-    DevTables t;
-    float* patches;
-    float* weights;
-    float* numf;
-    float* denf;
-    double* numd;
-    double* dend;
-};
+
 
 // LDS carve-up shared by host (size) and device (pointers).
 struct FilterLds {
@@ -867,8 +847,9 @@ hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, co
     a.denf = static_cast<float*>(den);
     a.numd = static_cast<double*>(num);
     a.dend = static_cast<double*>(den);
-    const size_t lds = FilterLds(c.g, c.gmax).bytes;
     const long groups = long(c.g.batch) * n_refs;
+    if (cube_filter_supported(c.g, c.gmax)) return launch_filter_cube(a, groups, s);
+    const size_t lds = FilterLds(c.g, c.gmax).bytes;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -893,8 +874,9 @@ hipError_t launch_aggregate(const StageCfg& c, const DevTables& t, int out_mode,
     a.denf = static_cast<float*>(den);
     a.numd = static_cast<double*>(num);
     a.dend = static_cast<double*>(den);
-    const size_t lds = FilterLds(c.g, c.gmax).bytes;
     const long groups = long(c.g.batch) * n_refs;
+    if (cube_filter_supported(c.g, c.gmax)) return launch_filter_cube(a, groups, s);
+    const size_t lds = FilterLds(c.g, c.gmax).bytes;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));

@@ -1,0 +1,526 @@
+// Collaborative filtering for cube patches (extent J per axis, J | 64):
+// one wavefront filters one group, in a persistent loop over groups.
+//
+// A group of K members is a K x P tensor (P = J^D) in the wave's LDS.
+// Spatial transform (the same J x J matrix on every axis): each lane owns
+// one output row q of the matrix (held in registers) and sweeps the
+// fibres of the current innermost axis with 128-bit LDS reads; it writes
+// its result with the transformed axis moved to the front of the patch
+// axes, so after D passes the layout is back in order and every pass reads
+// its axis contiguously.  Haar along the member axis: one lane per patch
+// sample, butterflies in registers (orthonormal multilevel Haar, rows:
+// scaling, coarsest ... finest detail), block sums for the squared rows.
+#include <hip/hip_runtime.h>
+
+#include "bmnd_internal.h"
+#include "filter_common.h"
+
+namespace bmnd {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr float kRsqrt2 = 0.70710678118654752440f;
+
+template <int J>
+__device__ __forceinline__ void load_row(const float* __restrict__ M, int q, float* r)
+{
+#pragma unroll
+    for (int t = 0; t < J; ++t) r[t] = M[q * J + t];
+}
+
+// One transform pass along the innermost axis of the current layout
+// (k, rest, t) -> (k, q, rest).
+template <int J, int P>
+__device__ __forceinline__ void pass_axis(const float* __restrict__ in, float* __restrict__ out,
+                                          const float* row, int K)
+{
+    constexpr int FPI = kWave / J;   // fibres per sweep step
+    constexpr int R = P / J;         // fibres per member
+    const int lane = threadIdx.x;
+    const int q = lane % J;
+    const int fs = lane / J;
+    const int F = K * R;
+    for (int fb = 0; fb < F; fb += FPI) {
+        const int f = fb + fs;
+        if (f < F) {
+            const float* x = in + f * J;
+            float s = 0.f;
+            if constexpr (J >= 4) {
+#pragma unroll
+                for (int t = 0; t < J; t += 4) {
+                    const float4 v = *reinterpret_cast<const float4*>(x + t);
+                    s = __builtin_fmaf(row[t], v.x, s);
+                    s = __builtin_fmaf(row[t + 1], v.y, s);
+                    s = __builtin_fmaf(row[t + 2], v.z, s);
+                    s = __builtin_fmaf(row[t + 3], v.w, s);
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < J; ++t) s = __builtin_fmaf(row[t], x[t], s);
+            }
+            const int k = f / R;
+            const int rest = f - k * R;
+            out[k * P + q * R + rest] = s;
+        }
+    }
+}
+
+// D passes with the same matrix; returns the buffer holding the result.
+template <int D, int J, int P>
+__device__ __forceinline__ float* spatial(float* x, float* tmp, const float* __restrict__ M, int K)
+{
+    float row[J];
+    load_row<J>(M, threadIdx.x % J, row);
+    float* in = x;
+    float* out = tmp;
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+        pass_axis<J, P>(in, out, row, K);
+        __syncthreads();
+        float* t = in;
+        in = out;
+        out = t;
+    }
+    return in;
+}
+
+// ---- Haar butterflies on K values held in registers
+template <int KK>
+__device__ __forceinline__ void haar_fwd(float* r)
+{
+    float a[KK], o[KK];
+#pragma unroll
+    for (int i = 0; i < KK; ++i) a[i] = r[i];
+    int n = KK;
+#pragma unroll
+    for (int lev = 0; (1 << lev) < KK; ++lev) {
+        const int h = KK >> (lev + 1);
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            o[h + i] = (a[2 * i] - a[2 * i + 1]) * kRsqrt2;
+            a[i] = (a[2 * i] + a[2 * i + 1]) * kRsqrt2;
+        }
+        n = h;
+    }
+    o[0] = a[0];
+#pragma unroll
+    for (int i = 0; i < KK; ++i) r[i] = o[i];
+    (void)n;
+}
+
+template <int KK>
+__device__ __forceinline__ void haar_inv(float* r)
+{
+    float a[KK];
+    a[0] = r[0];
+#pragma unroll
+    for (int n = 1; n < KK; n *= 2) {
+        float b[KK];
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+            const float d = r[n + i];
+            b[2 * i] = (a[i] + d) * kRsqrt2;
+            b[2 * i + 1] = (a[i] - d) * kRsqrt2;
+        }
+#pragma unroll
+        for (int i = 0; i < 2 * n; ++i) a[i] = b[i];
+    }
+#pragma unroll
+    for (int i = 0; i < KK; ++i) r[i] = a[i];
+}
+
+// variance through the squared Haar rows: block sums over the row support
+template <int KK>
+__device__ __forceinline__ void haar_sq(float* r)
+{
+    float s[KK], o[KK];
+#pragma unroll
+    for (int i = 0; i < KK; ++i) s[i] = r[i];
+    int b = 1;  // members per block
+#pragma unroll
+    for (int lev = 0; (1 << lev) < KK; ++lev) {
+        const int h = KK >> (lev + 1);
+        const float inv = 1.f / float(2 * b);
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            const float t = s[2 * i] + s[2 * i + 1];
+            o[h + i] = t * inv;
+            s[i] = t;
+        }
+        b *= 2;
+    }
+    o[0] = s[0] / float(KK);
+#pragma unroll
+    for (int i = 0; i < KK; ++i) r[i] = o[i];
+}
+
+// mode 0: forward, 1: inverse, 2: squared
+template <int KK, int P>
+__device__ __forceinline__ void haar_column(float* X, int p, int mode)
+{
+    float r[KK];
+#pragma unroll
+    for (int k = 0; k < KK; ++k) r[k] = X[k * P + p];
+    if (mode == 0) haar_fwd<KK>(r);
+    else if (mode == 1) haar_inv<KK>(r);
+    else haar_sq<KK>(r);
+#pragma unroll
+    for (int k = 0; k < KK; ++k) X[k * P + p] = r[k];
+}
+
+// Apply the Haar operator along the member axis to up to three arrays
+// (x0 forward, x1 squared, x2 forward; or x0 inverse when `inverse`);
+// lanes take (array, sample) pairs.
+template <int GM, int P>
+__device__ void haar_arrays(float* x0, float* x1, float* x2, int narr, bool inverse, int K)
+{
+    for (int idx = threadIdx.x; idx < narr * P; idx += kWave) {
+        const int a = idx / P;
+        const int p = idx - a * P;
+        float* X = a == 0 ? x0 : (a == 1 ? x1 : x2);
+        const int mode = inverse ? 1 : (a == 1 ? 2 : 0);
+        switch (K) {
+        case 2: if constexpr (GM >= 2) haar_column<2, P>(X, p, mode); break;
+        case 4: if constexpr (GM >= 4) haar_column<4, P>(X, p, mode); break;
+        case 8: if constexpr (GM >= 8) haar_column<8, P>(X, p, mode); break;
+        case 16: if constexpr (GM >= 16) haar_column<16, P>(X, p, mode); break;
+        case 32: if constexpr (GM >= 32) haar_column<32, P>(X, p, mode); break;
+        default: break;  // K = 1: identity
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum64(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Haar entry H[l][j] for K members in double precision (same definition as
+// the table: scaling row, then detail rows with support K, K/2, ..., 2).
+__device__ __forceinline__ double haar64(int K, int l, int j)
+{
+    if (l == 0) return 1.0 / sqrt(double(K));
+    int t = 31 - __clz(l);
+    const int support = K >> t;
+    const int first = (l - (1 << t)) * support;
+    if (j < first || j >= first + support) return 0.0;
+    const double v = 1.0 / sqrt(double(support));
+    return (j - first) < support / 2 ? v : -v;
+}
+
+template <int D, int J, int GM>
+__global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
+{
+    constexpr int P = ipow_c(J, D);
+    constexpr int KP = GM * P;
+    __shared__ __align__(16) float A[KP];
+    __shared__ __align__(16) float Bb[KP];
+    __shared__ __align__(16) float Vb[KP];
+    __shared__ __align__(16) float Tb[KP];
+    __shared__ int off[P];
+    __shared__ float win[P];
+    __shared__ int org[GM];
+    __shared__ float rpl[GM];
+    __shared__ float wj[GM];
+    __shared__ int nres;
+
+    const Geo& g = a.g;
+    const int lane = threadIdx.x;
+    const int cax = kAx - D;  // first canonical axis of the patch
+    for (int p = lane; p < P; p += kWave) {
+        int rem = p, o = 0;
+        float w = 1.f;
+#pragma unroll
+        for (int d = D - 1; d >= 0; --d) {
+            const int c = rem % J;
+            rem /= J;
+            o += c * g.st[cax + d];
+            w *= a.t.f32[a.t.win[cax + d] + c];
+        }
+        off[p] = o;
+        win[p] = w;
+    }
+    const float* Tm = a.t.f32 + a.t.T[kAx - 1];
+    const float* T2m = a.t.f32 + a.t.T2[kAx - 1];
+    const float* Um = a.t.f32 + a.t.U[kAx - 1];
+    const float* rn1 = a.t.f32 + a.t.rn[kAx - 1];
+    const double* T64 = a.t.f64 + a.t.T64[kAx - 1];
+    __syncthreads();
+
+    // each workgroup takes a contiguous run of groups (neighbouring
+    // references share source samples in its XCD's L2)
+    const long ngroups = long(g.batch) * a.n_refs;
+    const long chunk = (ngroups + gridDim.x - 1) / gridDim.x;
+    const long g_end = min(ngroups, long(blockIdx.x + 1) * chunk);
+    for (long grp = long(blockIdx.x) * chunk; grp < g_end; ++grp) {
+        const int b = int(grp / a.n_refs);
+        const int K = a.count[grp];
+        const int n = K * P;
+        const float* yb = a.y + long(b) * g.V;
+        const float* pb = a.pilot ? a.pilot + long(b) * g.V : nullptr;
+        if (lane < K) {
+            org[lane] = a.match[grp * a.gmax + lane];
+            rpl[lane] = 0.f;
+        }
+        if (lane == 0) nres = 0;
+        __syncthreads();
+
+        float* res = A;
+        if (a.patches_in == nullptr) {
+            // ---- gather y, pilot, variance map; group norm
+            const bool wiener = a.stage == BMND_STAGE_WIENER;
+            const float* mvsrc = wiener ? pb : yb;
+            float gn2 = 0.f;
+            for (int e = lane; e < n; e += kWave) {
+                const int k = e / P;
+                const int u = org[k] + off[e - k * P];
+                const float yv = yb[u];
+                A[e] = yv;
+                gn2 = __builtin_fmaf(yv, yv, gn2);
+                if (wiener) Bb[e] = pb[u];
+                Vb[e] = a.noise == BMND_NOISE_POISSON ? a.s_p * fmaxf(mvsrc[u], 0.f) : a.sigma2;
+            }
+            const float gn = sqrtf(wave_sum(gn2));
+            __syncthreads();
+
+            // ---- forward transforms: spatial passes, then Haar
+            float* Y = spatial<D, J, P>(A, Tb, Tm, K);
+            if (Y != A) {
+                for (int e = lane; e < n; e += kWave) A[e] = Y[e];
+                __syncthreads();
+            }
+            float* Vr = spatial<D, J, P>(Vb, Tb, T2m, K);
+            if (Vr != Vb) {
+                for (int e = lane; e < n; e += kWave) Vb[e] = Vr[e];
+                __syncthreads();
+            }
+            if (wiener) {
+                float* Gr = spatial<D, J, P>(Bb, Tb, Tm, K);
+                if (Gr != Bb) {
+                    for (int e = lane; e < n; e += kWave) Bb[e] = Gr[e];
+                    __syncthreads();
+                }
+            }
+            haar_arrays<GM, P>(A, Vb, Bb, wiener ? 3 : 2, false, K);
+
+            // ---- shrinkage and per-plane risk surrogates
+            for (int e = lane; e < n; e += kWave) {
+                const int l = e / P;
+                const float Yv = A[e];
+                const float v = fmaxf(Vb[e], 0.f);
+                float att, C, shat = 0.f;
+                if (a.shrink == BMND_SHRINK_HARD) {
+                    const float thr = a.lambda * sqrtf(v);
+                    const bool keep = fabsf(Yv) > thr;
+                    int qq = e - l * P;
+                    float rn = 1.f;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        rn *= rn1[qq % J];
+                        qq /= J;
+                    }
+                    const float band = 1e-5f * (rn * gn + thr);
+                    if (v > 0.f && fabsf(fabsf(Yv) - thr) <= band) {
+                        const int slot = atomicAdd(&nres, 1);
+                        reinterpret_cast<int*>(Bb)[slot] = e;
+                    }
+                    att = keep ? 1.f : 0.f;
+                    C = Yv;
+                } else if (a.shrink == BMND_SHRINK_SOFT) {
+                    const float m = fmaxf(fabsf(Yv) - a.lambda * sqrtf(v), 0.f);
+                    C = Yv > 0.f ? m : (Yv < 0.f ? -m : 0.f);
+                    att = Yv != 0.f ? m / fabsf(Yv) : 0.f;
+                } else {
+                    const float gam = Bb[e];
+                    shat = fmaxf(gam * gam - a.power_a * v, 0.f);
+                    const float den = shat + a.s_v * v;
+                    att = den > 0.f ? shat / den : 0.f;
+                    C = att * Yv;
+                    Bb[e] = shat;
+                }
+                A[e] = C;
+                Tb[e] = att;
+                Vb[e] = v;
+            }
+            __syncthreads();
+            if (a.shrink == BMND_SHRINK_HARD) {
+                const int nr = nres;
+                for (int r = 0; r < nr; ++r) {
+                    const int e = reinterpret_cast<int*>(Bb)[r];
+                    const int l = e / P;
+                    int q[D];
+                    {
+                        int qq = e - l * P;
+#pragma unroll
+                        for (int d = D - 1; d >= 0; --d) {
+                            q[d] = qq % J;
+                            qq /= J;
+                        }
+                    }
+                    double sy = 0.0, sv = 0.0;
+                    for (int f = lane; f < n; f += kWave) {
+                        const int j = f / P;
+                        const int i = f - j * P;
+                        double w = haar64(K, l, j);
+                        int ii = i;
+#pragma unroll
+                        for (int d = D - 1; d >= 0; --d) {
+                            w *= T64[q[d] * J + ii % J];
+                            ii /= J;
+                        }
+                        const int u = org[j] + off[i];
+                        sy += w * double(yb[u]);
+                        const double mv = a.noise == BMND_NOISE_POISSON
+                                              ? a.s_p64 * fmax(double(yb[u]), 0.0)
+                                              : a.sigma2_64;
+                        sv += w * w * mv;
+                    }
+                    sy = wave_sum64(sy);
+                    sv = wave_sum64(sv);
+                    const bool keep = fabs(sy) > a.lambda64 * sqrt(sv) * (1.0 + 1e-9);
+                    if (lane == 0) Tb[e] = keep ? 1.f : 0.f;
+                    __syncthreads();
+                }
+                for (int e = lane; e < n; e += kWave)
+                    if (Tb[e] == 0.f) A[e] = 0.f;
+                __syncthreads();
+            }
+            for (int e = lane; e < n; e += kWave) {
+                const int l = e / P;
+                const float at = Tb[e];
+                const float v = Vb[e];
+                float r;
+                if (a.wmodel == BMND_WEIGHT_CLASSIC) r = at * at;
+                else if (a.wmodel == BMND_WEIGHT_VARIANCE) r = at * at * v;
+                else r = at * at * v + (1.f - at) * (1.f - at) * Bb[e];
+                atomicAdd(&rpl[l], r);
+            }
+            __syncthreads();
+            if (a.wscope == BMND_SCOPE_GROUP) {
+                float R = 0.f;
+                for (int l = 0; l < K; ++l) R += rpl[l];
+                if (lane < K) wj[lane] = R > 0.f ? 1.f / R : 1.f;
+            } else if (lane < K) {
+                // R_j = sum_l H[l][j]^2 r_l
+                float R = 0.f;
+                for (int l = 0; l < K; ++l) {
+                    const float h = float(haar64(K, l, lane));
+                    R += h * h * rpl[l];
+                }
+                wj[lane] = R > 0.f ? 1.f / R : 1.f;
+            }
+            __syncthreads();
+
+            // ---- synthesis: Haar^T, then U along every axis
+            haar_arrays<GM, P>(A, nullptr, nullptr, 1, true, K);
+            res = spatial<D, J, P>(A, Tb, Um, K);
+        } else {
+            const float* pin = a.patches_in + grp * long(a.gmax) * P;
+            for (int e = lane; e < n; e += kWave) A[e] = pin[e];
+            if (lane < K) wj[lane] = a.weights_in[grp * a.gmax + lane];
+            __syncthreads();
+        }
+
+        // ---- outputs
+        const long vb = long(b) * g.V;
+        if (a.out_mode == 0) {
+            float* pout = a.patches + grp * long(a.gmax) * P;
+            for (int e = lane; e < a.gmax * P; e += kWave) pout[e] = e < n ? res[e] : 0.f;
+            if (lane < a.gmax) a.weights[grp * a.gmax + lane] = lane < K ? wj[lane] : 0.f;
+        } else if (a.out_mode == 1) {
+            for (int e = lane; e < n; e += kWave) {
+                const int k = e / P;
+                const int p = e - k * P;
+                const long u = vb + org[k] + off[p];
+                const float ww = wj[k] * win[p];
+                unsafeAtomicAdd(&a.numf[u], ww * res[e]);
+                unsafeAtomicAdd(&a.denf[u], ww);
+            }
+        } else if (a.out_mode == 2) {
+            for (int e = lane; e < n; e += kWave) {
+                const int k = e / P;
+                const int p = e - k * P;
+                const long u = vb + org[k] + off[p];
+                unsafeAtomicAdd(&a.dend[u], double(wj[k]) * double(win[p]));
+            }
+        } else {
+            double zs = 0.0, zr = 0.0;
+            for (int e = lane; e < n; e += kWave) {
+                const int k = e / P;
+                const int p = e - k * P;
+                const long u = vb + org[k] + off[p];
+                const double zeta = double(wj[k]) * double(win[p]) / a.dend[u];
+                zs += zeta;
+                zr += zeta * (double(a.y[u]) - double(res[e]));
+            }
+            zs = wave_sum64(zs);
+            zr = wave_sum64(zr);
+            const double alpha = zs > 0.0 ? zr / zs : 0.0;
+            for (int e = lane; e < n; e += kWave) {
+                const int k = e / P;
+                const int p = e - k * P;
+                const long u = vb + org[k] + off[p];
+                unsafeAtomicAdd(&a.numd[u],
+                                double(wj[k]) * double(win[p]) * (double(res[e]) + alpha));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int D, int J>
+hipError_t launch_cube_gm(const FilterArgs& a, long groups, hipStream_t s)
+{
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu <= 0) ncu = 256;
+    const long cap = long(ncu) * 32;
+    const dim3 grid(unsigned(groups < cap ? groups : cap));
+    switch (a.gmax) {
+    case 1: hipLaunchKernelGGL((k_filter_cube<D, J, 1>), grid, dim3(kWave), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_filter_cube<D, J, 2>), grid, dim3(kWave), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_filter_cube<D, J, 4>), grid, dim3(kWave), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_filter_cube<D, J, 8>), grid, dim3(kWave), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_filter_cube<D, J, 16>), grid, dim3(kWave), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_filter_cube<D, J, 32>), grid, dim3(kWave), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool cube_filter_supported(const Geo& g, int gmax)
+{
+    int D = 0, J = 0;
+    for (int d = 0; d < kAx; ++d) {
+        if (g.j[d] == 1 && D == 0) continue;
+        if (J == 0) J = g.j[d];
+        if (g.j[d] != J) return false;
+        ++D;
+    }
+    if (D == 0) return false;
+    const bool shape_ok = (D == 1 && J == 32) || (D == 2 && J == 8) || (D == 3 && J == 4);
+    return shape_ok && gmax * g.P <= kMaxKP && g.P * gmax * 16 <= 65536;
+}
+
+hipError_t launch_filter_cube(const FilterArgs& a, long groups, hipStream_t s)
+{
+    const Geo& g = a.g;
+    if (g.P == 32) return launch_cube_gm<1, 32>(a, groups, s);
+    if (g.j[kAx - 1] == 8) return launch_cube_gm<2, 8>(a, groups, s);
+    return launch_cube_gm<3, 4>(a, groups, s);
+}
+
+}  // namespace bmnd
