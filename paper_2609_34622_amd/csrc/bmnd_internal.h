@@ -45,6 +45,7 @@ struct StageCfg {
     double lambda, s_v, power_a;
     int k_exact, wmodel, wscope, mc;
     double beta;
+    int step_last;   // reference step along the last axis
 };
 
 // Device-resident immutable tables for one (spatial transform, patch, beta).
@@ -76,7 +77,9 @@ const int64_t* device_origins(const bmnd_geometry& geom, const bmnd_stage_params
 
 // Kernel launchers (kernels.hip).  Each returns hipSuccess or the launch error.
 hipError_t launch_counts(const StageCfg& c, const float* y, int* kappa, int* psum, hipStream_t s);
-hipError_t launch_match(const StageCfg& c, const float* src, const int* kappa, const int* psum,
+// Matching; kappa/psum (workspace, one int per voxel each) are used by
+// the generic count-domain path and may be NULL otherwise.
+hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* psum,
                         const int64_t* refs, int n_refs, int* match, int* count, hipStream_t s);
 // out_mode: 0 write patches/weights, 1 aggregate (float), 2 mc sweep 1, 3 mc sweep 2
 hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, const float* y,

@@ -160,6 +160,7 @@ bmnd_status make_stage(const bmnd_geometry* g, const bmnd_noise* n, const bmnd_s
     c.wscope = sp->weight_scope;
     c.mc = sp->mass_conservation ? 1 : 0;
     c.beta = sp->kaiser_beta;
+    c.step_last = sp->step[g->ndim - 1];
     return BMND_OK;
 }
 
@@ -508,8 +509,6 @@ bmnd_status bmnd_match(int32_t stage, const float* d_src, const bmnd_geometry* g
             return fail(BMND_E_WORKSPACE, "workspace missing or smaller than bmnd_match_workspace_size");
         kappa = static_cast<int*>(d_ws);
         psum = reinterpret_cast<int*>(static_cast<char*>(d_ws) + match_ws(c.g) / 2);
-        hipError_t e = launch_counts(c, d_src, kappa, psum, s);
-        if (e != hipSuccess) return hip_fail(e, "count kernels");
     }
     hipError_t e = launch_match(c, d_src, kappa, psum, d_refs, int(n_refs), d_match, d_count, s);
     if (e != hipSuccess) return hip_fail(e, "matching kernel");
@@ -625,11 +624,7 @@ bmnd_status bmnd_denoise(const float* d_y, const bmnd_geometry* geom,
                          const float* src, const float* pil, float* out) -> hipError_t {
         const bool ht = c.stage == BMND_STAGE_HT;
         hipError_t e = hipSuccess;
-        if (c.integral) {
-            KernelSpan k(BMND_KID_COUNTS, s);
-            e = launch_counts(c, src, kappa, psum, s);
-        }
-        if (e == hipSuccess) {
+        {
             KernelSpan k(ht ? BMND_KID_MATCH_HT : BMND_KID_MATCH_WIENER, s);
             e = launch_match(c, src, kappa, psum, refs, int(nr), match, count, s);
         }

@@ -13,6 +13,7 @@
 
 #include "bmnd_internal.h"
 #include "filter_common.h"
+#include "match_common.h"
 
 namespace bmnd {
 
@@ -32,13 +33,13 @@ constexpr double kTieRel = 1e-9;  // relative tie margin of the hard threshold
 // ---------------------------------------------------------------------------
 
 __global__ void k_counts(Geo g, const float* __restrict__ y, float inv_sp, int kmax,
-                         int* __restrict__ kappa)
+                         int* __restrict__ kappa, int* __restrict__ flag)
 {
     const long n = long(g.batch) * g.V;
     for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += long(gridDim.x) * blockDim.x) {
         const int k = int(rintf(y[i] * inv_sp));
-        if (k < 0 || k > kmax) atomicOr(&g_range_flag, 1);
+        if (k < 0 || k > kmax) atomicOr(flag, 1);
         kappa[i] = k;
     }
 }
@@ -82,24 +83,7 @@ __global__ void k_patch_sums(Geo g, const int* __restrict__ kappa, int* __restri
 // first K-1 members; they are then sorted by (score, lin).
 // ---------------------------------------------------------------------------
 
-enum MatchMode { kCount = 0, kPoissonF = 1, kGauss = 2, kPlain = 3 };
 
-struct MatchArgs {
-    Geo g;
-    const float* src;    // batched observation (HT) or pilot (Wiener)
-    const int* kappa;    // batched counts (kCount)
-    const int* psum;     // batched patch sums of counts (kCount)
-    const int64_t* refs;
-    int n_refs;
-    int* match;
-    int* count;
-    int gmin, gmax;
-    int gamma_i;         // kCount: integral gamma
-    float gamma_sp;      // kPoissonF: gamma * s_P
-    float bias;          // kGauss: gamma * 2 P sigma^2
-    int tau_i;           // kCount: accept iff score < tau_i
-    float tau_f;         // float modes: accept iff score < tau_f
-};
 
 template <int MODE>
 struct ScoreT { using type = float; };
@@ -737,15 +721,28 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_counts(const StageCfg& c, const float* y, int* kappa, int* psum, hipStream_t s)
+static int* range_flag_ptr()
 {
-    const long n = long(c.g.batch) * c.g.V;
-    // exact int32 scoring: P * kmax^2 < 2^31 and gamma * 2 P kmax < 2^31
+    static int* p = nullptr;
+    if (!p) (void)hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(g_range_flag));
+    return p;
+}
+
+// counts up to which the int32 count-domain score is exact:
+// P kmax^2 < 2^31 and gamma 2 P kmax < 2^31
+static int count_limit(const StageCfg& c)
+{
     double kmax = std::sqrt(2147483647.0 / double(c.g.P));
     const double kg = 2147483647.0 / (2.0 * double(c.g.P) * std::max(1.0, c.gamma));
     if (kg < kmax) kmax = kg;
+    return int(kmax) - 1;
+}
+
+hipError_t launch_counts(const StageCfg& c, const float* y, int* kappa, int* psum, hipStream_t s)
+{
+    const long n = long(c.g.batch) * c.g.V;
     hipLaunchKernelGGL(k_counts, dim3(grid_for(n, 256)), dim3(256), 0, s, c.g, y,
-                       float(1.0 / c.s_p), int(kmax) - 1, kappa);
+                       float(1.0 / c.s_p), count_limit(c), kappa, range_flag_ptr());
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_patch_sums, dim3(grid_for(n, 256)), dim3(256), 0, s, c.g, kappa, psum);
@@ -768,7 +765,7 @@ static hipError_t launch_match_mode(const MatchArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_match(const StageCfg& c, const float* src, const int* kappa, const int* psum,
+hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* psum,
                         const int64_t* refs, int n_refs, int* match, int* count, hipStream_t s)
 {
     MatchArgs a{};
@@ -782,11 +779,14 @@ hipError_t launch_match(const StageCfg& c, const float* src, const int* kappa, c
     a.count = count;
     a.gmin = c.gmin;
     a.gmax = c.gmax;
+    a.inv_sp = float(1.0 / c.s_p);
+    a.range_flag = range_flag_ptr();
+    int mode;
     if (c.stage == BMND_STAGE_WIENER) {
+        mode = kPlain;
         a.tau_f = float(c.tau);
-        return launch_match_mode<kPlain>(a, s);
-    }
-    if (c.integral) {
+    } else if (c.integral) {
+        mode = kCount;
         a.gamma_i = int(c.gamma);
         // accept iff score < tau / s_P^2 (integer score): score < ceil(.)
         const double t = c.tau / (c.s_p * c.s_p);
@@ -794,16 +794,28 @@ hipError_t launch_match(const StageCfg& c, const float* src, const int* kappa, c
         if (ct > 2147483647.0) ct = 2147483647.0;
         if (ct < -2147483647.0) ct = -2147483647.0;
         a.tau_i = int(ct);
-        return launch_match_mode<kCount>(a, s);
-    }
-    if (c.noise == BMND_NOISE_POISSON) {
+    } else if (c.noise == BMND_NOISE_POISSON) {
+        mode = kPoissonF;
         a.gamma_sp = float(c.gamma * c.s_p);
         a.tau_f = float(c.tau);
-        return launch_match_mode<kPoissonF>(a, s);
+    } else {
+        mode = kGauss;
+        a.bias = float(c.gamma * 2.0 * c.g.P * c.sigma * c.sigma);
+        a.tau_f = float(c.tau);
     }
-    a.bias = float(c.gamma * 2.0 * c.g.P * c.sigma * c.sigma);
-    a.tau_f = float(c.tau);
-    return launch_match_mode<kGauss>(a, s);
+    if (match_1d_supported(c.g, mode))
+        return launch_match_1d(a, mode, c.step_last, count_limit(c), s);
+    if (mode == kCount) {
+        if (!kappa || !psum) return hipErrorInvalidValue;
+        hipError_t e = launch_counts(c, src, kappa, psum, s);
+        if (e != hipSuccess) return e;
+    }
+    switch (mode) {
+    case kPlain: return launch_match_mode<kPlain>(a, s);
+    case kCount: return launch_match_mode<kCount>(a, s);
+    case kPoissonF: return launch_match_mode<kPoissonF>(a, s);
+    default: return launch_match_mode<kGauss>(a, s);
+    }
 }
 
 static FilterArgs filter_args(const StageCfg& c, const DevTables& t, int out_mode)

@@ -1,0 +1,273 @@
+// Block matching for 1-D arrays with 32-sample patches (section Block
+// Matching): one wavefront scores the windows of 64 consecutive
+// references.  The samples covering their windows are staged once in LDS
+// (raw counts for exact count-domain HT scores, the pilot for the Wiener
+// stage); each lane keeps its reference patch in registers and walks the
+// window offsets 32 at a time over a 64-sample register block, so every
+// squared difference is computed from registers.  The Poisson bias uses a
+// sliding patch sum of the candidate.
+//
+// Selection is the two-pass scheme of the generic kernel: pass 1 counts the
+// accepted candidates and keeps the M smallest score values (median-of-three
+// insertion network); every candidate whose score does not exceed the
+// running M-th value is recorded (offset index, in lin order).  The group's
+// members are exactly the recorded candidates below the (K-1)-th value and
+// the first ties at it, so pass 2 rescans only the record.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <climits>
+
+#include "bmnd_internal.h"
+#include "match_common.h"
+
+namespace bmnd {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kJ = 32;      // patch length
+constexpr int kRec = 96;    // recorded offsets per lane before falling back
+
+template <int MODE>
+struct Sc { using T = float; };
+template <>
+struct Sc<kCount> { using T = int; };
+
+__device__ __forceinline__ int smin(int a, int b) { return min(a, b); }
+__device__ __forceinline__ int smax(int a, int b) { return max(a, b); }
+__device__ __forceinline__ float smin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ float smax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ int as_bits(int v) { return v; }
+__device__ __forceinline__ int as_bits(float v) { return __float_as_int(v); }
+template <typename S> __device__ __forceinline__ S from_bits(int v);
+template <> __device__ __forceinline__ int from_bits<int>(int v) { return v; }
+template <> __device__ __forceinline__ float from_bits<float>(int v) { return __int_as_float(v); }
+template <typename S> __device__ __forceinline__ S big();
+template <> __device__ __forceinline__ int big<int>() { return INT_MAX; }
+template <> __device__ __forceinline__ float big<float>() { return FLT_MAX; }
+
+__device__ __forceinline__ int p2floor(int x) { return x <= 1 ? 1 : (1 << (31 - __clz(x))); }
+
+// squared distance of the reference patch rp and the candidate starting
+// at c (LDS), always in the same order (pass 1 and pass 2 agree bitwise)
+template <int MODE>
+__device__ __forceinline__ typename Sc<MODE>::T ssd_lds(const typename Sc<MODE>::T* rp,
+                                                        const int* sx, int c)
+{
+    using S = typename Sc<MODE>::T;
+    S s = 0;
+#pragma unroll
+    for (int i = 0; i < kJ; ++i) {
+        const S q = from_bits<S>(sx[c + i]);
+        const S d = q - rp[i];
+        if constexpr (MODE == kCount) s += __mul24(d, d);
+        else s = __builtin_fmaf(d, d, s);
+    }
+    return s;
+}
+
+template <int MODE, int GM>
+__global__ __launch_bounds__(kWave) void k_match_1d(MatchArgs a, int cap_span, int kmax)
+{
+    using S = typename Sc<MODE>::T;
+    constexpr int M = GM > 1 ? GM - 1 : 1;
+    extern __shared__ __align__(16) int sx[];   // staged samples
+    __shared__ int sel_s[M][kWave];
+    __shared__ int sel_l[M][kWave];
+    __shared__ unsigned char rec[kRec][kWave];
+
+    const Geo& g = a.g;
+    const int L = g.L[kAx - 1];
+    const int W = g.W[kAx - 1];
+    const int ell = L - kJ;
+    const int wlo = -(W / 2), whi = W - 1 - W / 2;
+    const int nchunk = (a.n_refs + kWave - 1) / kWave;
+    const int b = blockIdx.x / nchunk;
+    const int chunk = blockIdx.x - b * nchunk;
+    const int lane = threadIdx.x;
+    const int gi = chunk * kWave + lane;
+    const bool have = gi < a.n_refs;
+    const int r = have ? int(a.refs[gi]) : 0;
+    const float* src = a.src + long(b) * g.V;
+    const long t = long(b) * a.n_refs + gi;
+    const float inv_sp = a.inv_sp;
+
+    bool pending = have;
+    while (__any(pending)) {
+        // ---- stage the window of the first pending reference onward
+        const int r0 = __shfl(r, __ffsll(__ballot(pending)) - 1);
+        const bool mine = pending && (r - r0) <= cap_span;
+        const int base = r0 + wlo;
+        const int len = cap_span + W + 2 * kJ;  // covers the last 64-sample block
+        for (int i = lane; i < len; i += kWave) {
+            const int pos = base + i;
+            int v = 0;
+            if (pos >= 0 && pos < L) {
+                const float x = src[pos];
+                if constexpr (MODE == kCount) {
+                    const int k = int(rintf(x * inv_sp));
+                    if (k < 0 || k > kmax) atomicOr(a.range_flag, 1);
+                    v = k;
+                } else {
+                    v = __float_as_int(x);
+                }
+            }
+            sx[i] = v;
+        }
+        __syncthreads();
+
+        if (mine) {
+            const int rl = r - base;  // reference start in the stage
+            S rp[kJ];
+            S sr = 0;
+#pragma unroll
+            for (int i = 0; i < kJ; ++i) {
+                rp[i] = from_bits<S>(sx[rl + i]);
+                sr += rp[i];
+            }
+            const int dlo = max(wlo, -r), dhi = min(whi, ell - r);
+            const int ncand = dhi - dlo;  // window size minus the reference
+            S s[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) s[m] = big<S>();
+            int acc = 0, nrec = 0;
+            for (int d0 = wlo; d0 <= whi; d0 += kJ) {
+                S buf[2 * kJ];
+#pragma unroll
+                for (int i = 0; i < 2 * kJ; ++i) buf[i] = from_bits<S>(sx[rl + d0 + i]);
+                S sc = 0;
+                if constexpr (MODE == kCount) {
+#pragma unroll
+                    for (int i = 0; i < kJ; ++i) sc += buf[i];
+                }
+#pragma unroll
+                for (int u = 0; u < kJ; ++u) {
+                    const int d = d0 + u;
+                    S x = 0;
+#pragma unroll
+                    for (int i = 0; i < kJ; ++i) {
+                        const S df = buf[u + i] - rp[i];
+                        if constexpr (MODE == kCount) x += __mul24(df, df);
+                        else x = __builtin_fmaf(df, df, x);
+                    }
+                    if constexpr (MODE == kCount) {
+                        x -= a.gamma_i * (sr + sc);
+                        sc += buf[u + kJ] - buf[u];
+                    } else if constexpr (MODE == kGauss) {
+                        x -= a.bias;
+                    }
+                    if (d >= dlo && d <= dhi && d != 0) {
+                        if constexpr (MODE == kCount) acc += x < a.tau_i;
+                        else acc += x < a.tau_f;
+                        if (x <= s[M - 1]) {
+                            if (nrec < kRec) rec[nrec][lane] = (unsigned char)(d - wlo);
+                            ++nrec;
+                        }
+#pragma unroll
+                        for (int m = M - 1; m >= 1; --m) s[m] = smin(s[m], smax(s[m - 1], x));
+                        s[0] = smin(s[0], x);
+                    }
+                }
+            }
+
+            int K = p2floor(min(1 + acc, a.gmax));
+            K = max(K, a.gmin);
+            K = min(K, p2floor(1 + ncand));
+            const int need = GM > 1 ? K - 1 : 0;
+            int* out = a.match + t * a.gmax;
+            out[0] = r;
+            for (int m = 1; m < a.gmax; ++m) out[m] = -1;
+            a.count[t] = K;
+            if (need > 0) {
+                S theta = s[0];
+#pragma unroll
+                for (int m = 0; m < M; ++m)
+                    if (m == need - 1) theta = s[m];
+                int n_less = 0;
+#pragma unroll
+                for (int m = 0; m < M; ++m) n_less += (m < need && s[m] < theta) ? 1 : 0;
+                int eq_left = need - n_less;
+                int got = 0;
+                auto consider = [&](int d) {
+                    S x = ssd_lds<MODE>(rp, sx, rl + d);
+                    if constexpr (MODE == kCount) {
+                        int sc2 = 0;
+                        for (int i = 0; i < kJ; ++i) sc2 += sx[rl + d + i];
+                        x -= a.gamma_i * (sr + sc2);
+                    } else if constexpr (MODE == kGauss) {
+                        x -= a.bias;
+                    }
+                    bool take = x < theta;
+                    if (!take && x == theta && eq_left > 0) {
+                        take = true;
+                        --eq_left;
+                    }
+                    if (take) {
+                        sel_s[got][lane] = as_bits(x);
+                        sel_l[got][lane] = r + d;
+                        ++got;
+                    }
+                };
+                if (nrec <= kRec) {
+                    for (int k = 0; k < nrec && got < need; ++k) consider(int(rec[k][lane]) + wlo);
+                } else {
+                    for (int d = dlo; d <= dhi && got < need; ++d)
+                        if (d != 0) consider(d);
+                }
+                for (int m = 1; m < got; ++m) {
+                    const int ks = sel_s[m][lane], kl = sel_l[m][lane];
+                    const S kv = from_bits<S>(ks);
+                    int p = m - 1;
+                    while (p >= 0 && from_bits<S>(sel_s[p][lane]) > kv) {
+                        sel_s[p + 1][lane] = sel_s[p][lane];
+                        sel_l[p + 1][lane] = sel_l[p][lane];
+                        --p;
+                    }
+                    sel_s[p + 1][lane] = ks;
+                    sel_l[p + 1][lane] = kl;
+                }
+                for (int m = 0; m < got; ++m) out[1 + m] = sel_l[m][lane];
+            }
+        }
+        pending = pending && !mine;
+        __syncthreads();
+    }
+}
+
+template <int MODE>
+hipError_t launch_1d_mode(const MatchArgs& a, int cap_span, int kmax, hipStream_t s)
+{
+    const int nchunk = (a.n_refs + kWave - 1) / kWave;
+    const dim3 grid(unsigned(long(nchunk) * a.g.batch));
+    const size_t lds = sizeof(int) * size_t(cap_span + a.g.W[kAx - 1] + 2 * kJ);
+    switch (a.gmax) {
+    case 1: hipLaunchKernelGGL((k_match_1d<MODE, 1>), grid, dim3(kWave), lds, s, a, cap_span, kmax); break;
+    case 2: hipLaunchKernelGGL((k_match_1d<MODE, 2>), grid, dim3(kWave), lds, s, a, cap_span, kmax); break;
+    case 4: hipLaunchKernelGGL((k_match_1d<MODE, 4>), grid, dim3(kWave), lds, s, a, cap_span, kmax); break;
+    case 8: hipLaunchKernelGGL((k_match_1d<MODE, 8>), grid, dim3(kWave), lds, s, a, cap_span, kmax); break;
+    case 16: hipLaunchKernelGGL((k_match_1d<MODE, 16>), grid, dim3(kWave), lds, s, a, cap_span, kmax); break;
+    default: hipLaunchKernelGGL((k_match_1d<MODE, 32>), grid, dim3(kWave), lds, s, a, cap_span, kmax); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool match_1d_supported(const Geo& g, int mode)
+{
+    for (int d = 0; d < kAx - 1; ++d)
+        if (g.L[d] != 1) return false;
+    return g.j[kAx - 1] == kJ && g.W[kAx - 1] <= 256 && g.W[kAx - 1] >= 1 &&
+           (mode == kCount || mode == kPlain || mode == kGauss);
+}
+
+hipError_t launch_match_1d(const MatchArgs& a, int mode, int step, int kmax, hipStream_t s)
+{
+    const int cap_span = kWave * max(step, 1);
+    if (mode == kCount) return launch_1d_mode<kCount>(a, cap_span, kmax, s);
+    if (mode == kGauss) return launch_1d_mode<kGauss>(a, cap_span, kmax, s);
+    return launch_1d_mode<kPlain>(a, cap_span, kmax, s);
+}
+
+}  // namespace bmnd

@@ -1,0 +1,32 @@
+// Arguments shared by the matching kernels (generic and 1-D paths).
+#pragma once
+
+#include "bmnd_internal.h"
+
+namespace bmnd {
+
+enum MatchMode { kCount = 0, kPoissonF = 1, kGauss = 2, kPlain = 3 };
+
+struct MatchArgs {
+    Geo g;
+    const float* src;    // batched observation (HT) or pilot (Wiener)
+    const int* kappa;    // batched counts (kCount, generic path)
+    const int* psum;     // batched patch sums of counts (kCount, generic path)
+    const int64_t* refs;
+    int n_refs;
+    int* match;
+    int* count;
+    int gmin, gmax;
+    int gamma_i;         // kCount: integral gamma
+    float gamma_sp;      // kPoissonF: gamma * s_P
+    float bias;          // kGauss: gamma * 2 P sigma^2
+    int tau_i;           // kCount: accept iff score < tau_i
+    float tau_f;         // float modes: accept iff score < tau_f
+    float inv_sp;        // 1 / s_P
+    int* range_flag;     // set when a count leaves the exact int32 range
+};
+
+bool match_1d_supported(const Geo& g, int mode);
+hipError_t launch_match_1d(const MatchArgs& a, int mode, int step, int kmax, hipStream_t s);
+
+}  // namespace bmnd

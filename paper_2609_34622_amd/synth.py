@@ -100,7 +100,9 @@ def ecg_batch(n_signals: int = 256, length: int = 65536, seed: int = 2000,
     lam = np.empty((n_signals, length))
     for b in range(n_signals):
         s = ecg_signal(rng, length)
-        lam[b] = np.maximum(baseline + (peak - baseline) * s / s.max(), 0.0)
+        smax = s.max()
+        shape = s / smax if smax > 0 else np.zeros_like(s)  # no beat in very short signals
+        lam[b] = np.maximum(baseline + (peak - baseline) * shape, 0.0)
     return _observe(rng, lam, peak)
 
 

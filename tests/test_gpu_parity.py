@@ -335,3 +335,40 @@ def test_profile_variants_stagewise(var):
     assert rel_err(pilot, pil_o) < REL_OUT
     out_r = O.run_stage(wie, O.STAGE_WIENER, y, pilot.astype(np.float64))
     assert rel_err(out, out_r) < REL_OUT
+
+
+# ------------------------------------------------------------ 1-D variants
+
+ONE_D = [
+    # length, step, search, noise
+    (3000, 4, 256, "gaussian"),
+    (2000, 3, 17, "poisson"),
+    (100, 4, 256, "poisson"),
+    (777, 7, 64, "poisson"),
+]
+
+
+@pytest.mark.parametrize("case", ONE_D, ids=lambda c: f"L{c[0]}-h{c[1]}-W{c[2]}-{c[3]}")
+def test_denoise_1d_variants(case):
+    L, h, W, noise_kind = case
+    _say(f"1-D {case}")
+    rng = np.random.default_rng(13)
+    shape, patch, step, search = (L,), (32,), (h,), (W,)
+    s = synth.ecg_batch(n_signals=2, length=L, seed=2100 + L)
+    p = params_for(shape, patch, step, search, group=(16, 16))
+    ht, wie = oracle_stages(shape, patch, step, search, s.s_p, group=(16, 16))
+    if noise_kind == "gaussian":
+        sigma = 0.05
+        y = (s.x + rng.normal(0, sigma, s.x.shape)).astype(np.float32)
+        noise = B.gaussian(sigma)
+        ht.noise = wie.noise = "gaussian"
+        ht.sigma = wie.sigma = sigma
+    else:
+        y = s.y
+        noise = B.poisson(s.s_p)
+    out, pilot = gpu_denoise(dev(y), B.geometry(shape, batch=2), noise, p)
+    for b in range(2):
+        pil_o = O.run_stage(ht, O.STAGE_HT, y[b])
+        assert rel_err(pilot[b], pil_o) < REL_OUT, b
+        out_r = O.run_stage(wie, O.STAGE_WIENER, y[b], pilot[b].astype(np.float64))
+        assert rel_err(out[b], out_r) < REL_OUT, b
