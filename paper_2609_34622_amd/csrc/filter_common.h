@@ -31,6 +31,10 @@ struct FilterArgs {
 constexpr int ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
 
 bool cube_filter_supported(const Geo& g, int gmax);
-hipError_t launch_filter_cube(const FilterArgs& a, long groups, hipStream_t s);
+hipError_t launch_filter_cube(const FilterArgs& a, int step_last, hipStream_t s);
+// 32-sample patches (leading patch extents 1), groups of at most 16, filtering
+// launches only (not the aggregate-only entry point)
+bool filter_1d_supported(const Geo& g, int gmax, bool patches_in);
+hipError_t launch_filter_1d(const FilterArgs& a, int step_last, hipStream_t s);
 
 }  // namespace bmnd

@@ -860,7 +860,8 @@ hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, co
     a.numd = static_cast<double*>(num);
     a.dend = static_cast<double*>(den);
     const long groups = long(c.g.batch) * n_refs;
-    if (cube_filter_supported(c.g, c.gmax)) return launch_filter_cube(a, groups, s);
+    if (filter_1d_supported(c.g, c.gmax, false)) return launch_filter_1d(a, c.step_last, s);
+    if (cube_filter_supported(c.g, c.gmax)) return launch_filter_cube(a, c.step_last, s);
     const size_t lds = FilterLds(c.g, c.gmax).bytes;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter),
@@ -887,7 +888,7 @@ hipError_t launch_aggregate(const StageCfg& c, const DevTables& t, int out_mode,
     a.numd = static_cast<double*>(num);
     a.dend = static_cast<double*>(den);
     const long groups = long(c.g.batch) * n_refs;
-    if (cube_filter_supported(c.g, c.gmax)) return launch_filter_cube(a, groups, s);
+    if (cube_filter_supported(c.g, c.gmax)) return launch_filter_cube(a, c.step_last, s);
     const size_t lds = FilterLds(c.g, c.gmax).bytes;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter),

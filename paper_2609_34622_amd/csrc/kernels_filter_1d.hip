@@ -1,0 +1,563 @@
+// Collaborative filtering of 32-sample patches on the matrix cores
+// (section Collaborative Filtering, 3-D transform of a group).
+//
+// A group of K <= 16 members is the 16 x 32 matrix X (rows: members, zero
+// rows past K).  Its 3-D transform is the pair of contractions
+//     Y = H (X T^T)        (spatial transform T per member, Haar H over members)
+// and the synthesis is  X^ = (H^T C) U^T.  The variance of every coefficient
+// is (H o H) (M (T o T)^T) for the per-sample variance map M.  Every one of
+// these products runs as v_mfma_f32_16x16x4f32 on one wavefront, with the
+// operands in registers:
+//   * A operand, lane l: row l%16, depth l/16;  B operand, lane l: depth
+//     l/16, column l%16;  result, lane l, register r: row 4(l/16)+r,
+//     column l%16.
+//   * The spatial depth (sample index i) is spread as i = 8(l/16) + s over
+//     the eight steps s, so each lane gathers eight contiguous samples of
+//     one member.
+//   * A result feeds the next product as its B operand when the next
+//     contraction runs over the result's rows: step s then takes register
+//     s, which holds row 4(l/16)+s, and the A operand is permuted to match.
+//   * The synthesis contracts over the columns of H^T C, so that matrix goes
+//     through a 16 x 32 LDS buffer once (write by rows, read by rows of the
+//     transpose).
+// Shrinkage, risk surrogates, weights and the aggregation work on the
+// result layout (8 coefficients per lane).  Hard-threshold decisions within
+// the FP32 error band of the threshold are recomputed in FP64 from the
+// input samples, as in the generic filter.
+#include <hip/hip_runtime.h>
+
+#include "bmnd_internal.h"
+#include "filter_common.h"
+
+namespace bmnd {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kJ = 32;        // patch length
+constexpr int kWaves = 4;     // wavefronts per workgroup
+constexpr int kChunk = 256;   // references per workgroup
+constexpr int kZs = 36;       // row stride (floats) of the transpose buffer
+constexpr float kRsqrt2 = 0.70710678118654752440f;
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Orders the LDS accesses of one wavefront.
+__device__ __forceinline__ void wsync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// 2^(-e/2) rounded once from 1/sqrt(2)
+__device__ __forceinline__ float pow_rsqrt2(int e)
+{
+    const float v = ldexpf(1.f, -(e >> 1));
+    return (e & 1) ? v * kRsqrt2 : v;
+}
+
+// Haar entry H[l][j] for K = 2^lk members (rows: scaling, then detail rows
+// with support K, K/2, ..., 2); zero outside the K x K block.
+__device__ __forceinline__ float haar_f(int lk, int l, int j)
+{
+    const int K = 1 << lk;
+    if (l >= K || j >= K) return 0.f;
+    if (l == 0) return pow_rsqrt2(lk);
+    const int t = 31 - __clz(l);
+    const int e = lk - t;  // log2 of the row support
+    const int first = (l - (1 << t)) << e;
+    if (j < first || j >= first + (1 << e)) return 0.f;
+    const float v = pow_rsqrt2(e);
+    return (j - first) < (1 << (e - 1)) ? v : -v;
+}
+
+__device__ __forceinline__ double haar_d(int lk, int l, int j)
+{
+    const int K = 1 << lk;
+    if (l >= K || j >= K) return 0.0;
+    if (l == 0) return 1.0 / sqrt(double(K));
+    const int t = 31 - __clz(l);
+    const int e = lk - t;
+    const int first = (l - (1 << t)) << e;
+    if (j < first || j >= first + (1 << e)) return 0.0;
+    const double v = 1.0 / sqrt(double(1 << e));
+    return (j - first) < (1 << (e - 1)) ? v : -v;
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// sum over the 16 lanes of a row (every lane gets it): pairs, quads, then
+// rotations of the row by 4 and 8
+__device__ __forceinline__ float sum16(float v)
+{
+    v += dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp<0x124>(v);  // row_ror 4
+    v += dpp<0x128>(v);  // row_ror 8
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v = sum16(v);
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum64(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Operand tables in LDS: matrix m (T, T o T, U), column block c, depth
+// half h, lane, 4 depth steps; lane (m16, lg) finds its eight B operands
+// for block c at depth 8lg + s, s = 4h + k, as two 16-byte reads.
+__device__ __forceinline__ int opnd_index(int m, int c, int h, int lane)
+{
+    return (((m * 2 + c) * 2 + h) * kWave + lane) * 4;
+}
+
+__device__ __forceinline__ void opnd_load(const float* ops, int m, int c, int lane, float* r)
+{
+    const float4 u0 = *reinterpret_cast<const float4*>(ops + opnd_index(m, c, 0, lane));
+    const float4 u1 = *reinterpret_cast<const float4*>(ops + opnd_index(m, c, 1, lane));
+    r[0] = u0.x; r[1] = u0.y; r[2] = u0.z; r[3] = u0.w;
+    r[4] = u1.x; r[5] = u1.y; r[6] = u1.z; r[7] = u1.w;
+}
+
+template <int SH>
+__global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int tile_cap,
+                                                              int tile_back)
+{
+    constexpr bool wiener = SH == BMND_SHRINK_WIENER;
+    __shared__ __align__(16) float ops[3 * 2 * 2 * kWave * 4];
+    __shared__ __align__(16) float ztr_[kWaves][16 * kZs];
+    __shared__ float rl_[kWaves][16];
+    // [4][tile_cap]: numerator, denominator, staged samples, staged pilot
+    extern __shared__ __align__(16) float tile[];
+
+    const Geo& g = a.g;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int m16 = lane & 15;
+    const int lg = lane >> 4;
+    float* ztr = ztr_[wave];
+    float* rl = rl_[wave];
+
+    // ---- operands of the spatial products: T[q][i], (T o T)[q][i] and
+    // U[i][q] at q (or i) = 16c + m16 and depth i (or q) = 8lg + s
+    for (int e = threadIdx.x; e < 3 * 2 * 2 * kWave * 4; e += kWave * kWaves) {
+        const int k = e & 3;
+        const int ln = (e >> 2) & (kWave - 1);
+        const int h = (e >> 8) & 1;
+        const int c = (e >> 9) & 1;
+        const int m = e >> 10;
+        const int off = m == 0 ? a.t.T[kAx - 1] : (m == 1 ? a.t.T2[kAx - 1] : a.t.U[kAx - 1]);
+        ops[e] = a.t.f32[off + (16 * c + (ln & 15)) * kJ + 8 * (ln >> 4) + 4 * h + k];
+    }
+    float w0 = 1.f, rn0 = 1.f;  // leading axes have one-sample patches
+#pragma unroll
+    for (int d = 0; d < kAx - 1; ++d) {
+        w0 *= a.t.f32[a.t.win[d]];
+        rn0 *= a.t.f32[a.t.rn[d]];
+    }
+    float wq[2], rq[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        wq[c] = w0 * a.t.f32[a.t.win[kAx - 1] + 16 * c + m16];
+        rq[c] = rn0 * a.t.f32[a.t.rn[kAx - 1] + 16 * c + m16];
+    }
+    const double* T64 = a.t.f64 + a.t.T64[kAx - 1];
+
+    const int nchunk = (a.n_refs + kChunk - 1) / kChunk;
+    const int b = blockIdx.x / nchunk;
+    const int g0 = (blockIdx.x - b * nchunk) * kChunk;
+    const int g1 = min(a.n_refs, g0 + kChunk);
+    const long vb = long(b) * g.V;
+    const int tile_lo = tile_cap > 0 ? a.match[(long(b) * a.n_refs + g0) * a.gmax] - tile_back : 0;
+    float* tnum = tile;
+    float* tden = tile + tile_cap;
+    float* ysm = tile + 2 * tile_cap;
+    float* psm = tile + 3 * tile_cap;
+    const bool poisson = a.noise == BMND_NOISE_POISSON;
+    const bool acc_tile = tile_cap > 0 && a.out_mode == 1;
+    const float* yb = a.y + vb;
+    const float* pb = a.pilot ? a.pilot + vb : nullptr;
+    // 1-D arrays: the samples around the chunk's references, staged once
+    for (int i = threadIdx.x; i < tile_cap; i += kWave * kWaves) {
+        const int u = tile_lo + i;
+        const bool inb = u >= 0 && u < g.V;
+        tnum[i] = 0.f;
+        tden[i] = 0.f;
+        ysm[i] = inb ? yb[u] : 0.f;
+        if constexpr (wiener) psm[i] = inb ? pb[u] : 0.f;
+    }
+    __syncthreads();
+
+    // the next group's size and this lane's entry of its match list are
+    // loaded one group ahead
+    int gi = g0 + wave;
+    int Knext = 0, mnext = 0;
+    if (gi < g1) {
+        const long grp = long(b) * a.n_refs + gi;
+        Knext = a.count[grp];
+        mnext = a.match[grp * a.gmax + min(m16, a.gmax - 1)];
+    }
+    for (; gi < g1; gi += kWaves) {
+        const long grp = long(b) * a.n_refs + gi;
+        const int K = Knext;
+        const int mv0 = mnext;
+        if (gi + kWaves < g1) {
+            const long gn = grp + kWaves;
+            Knext = a.count[gn];
+            mnext = a.match[gn * a.gmax + min(m16, a.gmax - 1)];
+        }
+        const int lk = 31 - __clz(K);
+        const bool av = m16 < K;  // this lane's member in the A layout
+        // lanes past K read the samples at a valid origin inside the staged
+        // range (tile_lo <= the chunk's first reference) and drop them
+        const int oa = av ? mv0 : max(tile_lo, 0);
+
+        // ---- gather: samples, variance map (from y, or from the pilot)
+        float x[8], pv[8], mv[8];
+        const int ol = oa - tile_lo + 8 * lg;
+        if (__all(ol >= 0 && ol + 8 <= tile_cap)) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                x[s] = ysm[ol + s];
+                pv[s] = wiener ? psm[ol + s] : 0.f;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                x[s] = yb[oa + 8 * lg + s];
+                pv[s] = wiener ? pb[oa + 8 * lg + s] : 0.f;
+            }
+        }
+        float gn2 = 0.f;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            x[s] = av ? x[s] : 0.f;
+            pv[s] = av ? pv[s] : 0.f;
+            gn2 = __builtin_fmaf(x[s], x[s], gn2);
+            const float src = wiener ? pv[s] : x[s];
+            mv[s] = av ? (poisson ? a.s_p * fmaxf(src, 0.f) : a.sigma2) : 0.f;
+        }
+
+        // ---- analysis: spatial rows 16c + m16 of every member, then Haar over
+        // the members with A[row m16][depth (lg, s)] = H[m16][4lg + s]
+        float ha[4], h2[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            ha[s] = haar_f(lk, m16, 4 * lg + s);
+            h2[s] = ha[s] * ha[s];
+        }
+        f4 Y[2], V[2], G[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            float tb[8];
+            f4 y1 = {0.f, 0.f, 0.f, 0.f}, v1 = y1, p1 = y1;
+            opnd_load(ops, 0, c, lane, tb);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                y1 = mfma(x[s], tb[s], y1);
+                if constexpr (wiener) p1 = mfma(pv[s], tb[s], p1);
+            }
+            opnd_load(ops, 1, c, lane, tb);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) v1 = mfma(mv[s], tb[s], v1);
+            Y[c] = V[c] = G[c] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                Y[c] = mfma(ha[s], y1[s], Y[c]);
+                V[c] = mfma(h2[s], v1[s], V[c]);
+                if constexpr (wiener) G[c] = mfma(ha[s], p1[s], G[c]);
+            }
+        }
+
+        // ---- shrinkage; coefficient (c, r), bit 4c + r: Haar row 4lg + r,
+        // spatial row 16c + m16
+        unsigned keep = 0, near = 0;
+        if constexpr (SH == BMND_SHRINK_HARD) {
+            const float gn = sqrtf(wave_sum(gn2));
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float Yv = Y[c][r];
+                    const float v = fmaxf(V[c][r], 0.f);
+                    const float thr = a.lambda * sqrtf(v);
+                    const bool lv = 4 * lg + r < K;
+                    if (lv && fabsf(Yv) > thr) keep |= 1u << (4 * c + r);
+                    // FP32 error band of the decision (transform round-off is
+                    // bounded by the row norm times the group norm)
+                    if (lv && v > 0.f && fabsf(fabsf(Yv) - thr) <= 1e-5f * (rq[c] * gn + thr))
+                        near |= 1u << (4 * c + r);
+                }
+            // FP64 decisions for the coefficients in the error band, one at a time
+            for (;;) {
+                const unsigned long long mk = __ballot(near != 0);
+                if (mk == 0) break;
+                const int src = __ffsll(mk) - 1;
+                const int bit = __ffs(__shfl(int(near), src)) - 1;
+                const int l = 4 * (src >> 4) + (bit & 3);
+                const int q = 16 * (bit >> 2) + (src & 15);
+                const double h = haar_d(lk, l, m16);
+                double sy = 0.0, sv = 0.0;
+                if (av) {
+                    for (int s = 0; s < 8; ++s) {
+                        const double w = h * T64[q * kJ + 8 * lg + s];
+                        const double xs = double(x[s]);
+                        sy += w * xs;
+                        sv += w * w * (poisson ? a.s_p64 * fmax(xs, 0.0) : a.sigma2_64);
+                    }
+                }
+                sy = wave_sum64(sy);
+                sv = wave_sum64(sv);
+                // strict inequality with the 1e-9 relative tie margin
+                const bool kp = fabs(sy) > a.lambda64 * sqrt(sv) * (1.0 + 1e-9);
+                if (lane == src) {
+                    near &= ~(1u << bit);
+                    keep = kp ? (keep | (1u << bit)) : (keep & ~(1u << bit));
+                }
+            }
+        }
+        float C[2][4];
+        float rr[4];  // per-plane risk surrogates r_l, l = 4lg + r
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float t = 0.f;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const bool lv = 4 * lg + r < K;
+                const float Yv = Y[c][r];
+                const float v = fmaxf(V[c][r], 0.f);
+                float at, Cv, shat = 0.f;
+                if constexpr (SH == BMND_SHRINK_HARD) {
+                    at = (keep >> (4 * c + r)) & 1u ? 1.f : 0.f;
+                    Cv = at != 0.f ? Yv : 0.f;
+                } else if constexpr (SH == BMND_SHRINK_SOFT) {
+                    const float m = fmaxf(fabsf(Yv) - a.lambda * sqrtf(v), 0.f);
+                    Cv = Yv > 0.f ? m : (Yv < 0.f ? -m : 0.f);
+                    at = Yv != 0.f ? m / fabsf(Yv) : 0.f;
+                } else {
+                    const float gam = G[c][r];
+                    shat = fmaxf(gam * gam - a.power_a * v, 0.f);
+                    const float den = shat + a.s_v * v;
+                    at = den > 0.f ? shat / den : 0.f;
+                    Cv = at * Yv;
+                }
+                C[c][r] = Cv;
+                if (lv) {
+                    if (a.wmodel == BMND_WEIGHT_CLASSIC) t += at * at;
+                    else if (a.wmodel == BMND_WEIGHT_VARIANCE) t += at * at * v;
+                    else t += at * at * v + (1.f - at) * (1.f - at) * shat;
+                }
+            }
+            rr[r] = sum16(t);
+        }
+
+        // ---- member weights
+        float wA;  // weight of member m16
+        if (a.wscope == BMND_SCOPE_GROUP) {
+            float R = rr[0] + rr[1] + rr[2] + rr[3];
+            R += __shfl_xor(R, 16);
+            R += __shfl_xor(R, 32);
+            wA = R > 0.f ? 1.f / R : 1.f;
+        } else {
+            // R_j = sum_l H[l][j]^2 r_l: the scaling row and one detail row
+            // per level hold member j
+            if (m16 == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) rl[4 * lg + r] = rr[r];
+            }
+            wsync();
+            float R = rl[0] / float(K);
+            for (int t = 0; t < lk; ++t) {
+                const int e = lk - t;
+                R += rl[(1 << t) + (m16 >> e)] / float(1 << e);
+            }
+            wA = R > 0.f ? 1.f / R : 1.f;
+            wsync();
+        }
+
+        // ---- synthesis: Z = H^T C (A[row m16][depth (lg, s)] = H[4lg + s][m16]) ...
+        f4 Z[2];
+        {
+            float hi[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) hi[s] = haar_f(lk, 4 * lg + s, m16);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                Z[c] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < 4; ++s) Z[c] = mfma(hi[s], C[c][s], Z[c]);
+            }
+        }
+        // ... through LDS into the A layout, then X^ = Z U^T
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ztr[(4 * lg + r) * kZs + 16 * c + m16] = Z[c][r];
+        wsync();
+        float za[8];
+        {
+            const float4 u0 = *reinterpret_cast<const float4*>(ztr + m16 * kZs + 8 * lg);
+            const float4 u1 = *reinterpret_cast<const float4*>(ztr + m16 * kZs + 8 * lg + 4);
+            za[0] = u0.x; za[1] = u0.y; za[2] = u0.z; za[3] = u0.w;
+            za[4] = u1.x; za[5] = u1.y; za[6] = u1.z; za[7] = u1.w;
+        }
+        wsync();
+        f4 o[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            float ub[8];
+            opnd_load(ops, 2, c, lane, ub);
+            o[c] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 8; ++s) o[c] = mfma(za[s], ub[s], o[c]);
+        }
+
+        // ---- outputs; o[c][r] is sample 16c + m16 of member 4lg + r
+        int od[4];
+        float wd[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            od[r] = __shfl(oa, 4 * lg + r);
+            wd[r] = __shfl(wA, 4 * lg + r);
+        }
+        if (a.out_mode == 0) {
+            float* pout = a.patches + grp * long(a.gmax) * kJ;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = 4 * lg + r;
+                if (k < a.gmax) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) pout[k * kJ + 16 * c + m16] = k < K ? o[c][r] : 0.f;
+                }
+            }
+            if (lane < a.gmax) a.weights[grp * a.gmax + lane] = lane < K ? wA : 0.f;
+        } else if (a.out_mode == 1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (4 * lg + r < K) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int u = od[r] + 16 * c + m16;
+                        const float ww = wd[r] * wq[c];
+                        const int tl = u - tile_lo;
+                        if (acc_tile && tl >= 0 && tl < tile_cap) {
+                            atomicAdd(&tnum[tl], ww * o[c][r]);
+                            atomicAdd(&tden[tl], ww);
+                        } else {
+                            unsafeAtomicAdd(&a.numf[vb + u], ww * o[c][r]);
+                            unsafeAtomicAdd(&a.denf[vb + u], ww);
+                        }
+                    }
+                }
+            }
+        } else if (a.out_mode == 2) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (4 * lg + r < K) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const long u = vb + od[r] + 16 * c + m16;
+                        unsafeAtomicAdd(&a.dend[u], double(wd[r]) * double(wq[c]));
+                    }
+                }
+            }
+        } else {
+            double zs = 0.0, zr = 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (4 * lg + r < K) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const long u = vb + od[r] + 16 * c + m16;
+                        const double zeta = double(wd[r]) * double(wq[c]) / a.dend[u];
+                        zs += zeta;
+                        zr += zeta * (double(a.y[u]) - double(o[c][r]));
+                    }
+                }
+            }
+            zs = wave_sum64(zs);
+            zr = wave_sum64(zr);
+            const double alpha = zs > 0.0 ? zr / zs : 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (4 * lg + r < K) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const long u = vb + od[r] + 16 * c + m16;
+                        unsafeAtomicAdd(&a.numd[u], double(wd[r]) * double(wq[c]) *
+                                                        (double(o[c][r]) + alpha));
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- flush the accumulation tile
+    if (acc_tile) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < tile_cap; i += kWave * kWaves) {
+            const float d = tden[i];
+            const int u = tile_lo + i;
+            if (d != 0.f && u >= 0 && u < g.V) {
+                unsafeAtomicAdd(&a.numf[vb + u], tnum[i]);
+                unsafeAtomicAdd(&a.denf[vb + u], d);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+bool filter_1d_supported(const Geo& g, int gmax, bool patches_in)
+{
+    return !patches_in && g.j[0] == 1 && g.j[1] == 1 && g.j[2] == 1 && g.j[kAx - 1] == kJ &&
+           gmax <= 16;
+}
+
+hipError_t launch_filter_1d(const FilterArgs& a, int step_last, hipStream_t s)
+{
+    const Geo& g = a.g;
+    // 1-D arrays: the windows of a chunk of references fall into a short lin
+    // range, staged (samples) and accumulated (aggregation) in LDS; elsewhere
+    // the tile is off
+    int tile_cap = 0, tile_back = 0;
+    const bool one_d = g.L[0] == 1 && g.L[1] == 1 && g.L[2] == 1;
+    if (one_d) {
+        tile_back = g.W[kAx - 1] / 2;
+        tile_cap = (kChunk - 1) * max(step_last, 1) + g.W[kAx - 1] + kJ;
+        if (tile_cap > 2560) tile_cap = 2560;  // 40 KiB of dynamic LDS
+    }
+    const int nchunk = (a.n_refs + kChunk - 1) / kChunk;
+    const dim3 grid(unsigned(long(nchunk) * g.batch));
+    const size_t lds = sizeof(float) * 4 * size_t(tile_cap);
+    if (a.shrink == BMND_SHRINK_HARD)
+        hipLaunchKernelGGL(k_filter_1d<BMND_SHRINK_HARD>, grid, dim3(kWave * kWaves), lds, s, a,
+                           tile_cap, tile_back);
+    else if (a.shrink == BMND_SHRINK_SOFT)
+        hipLaunchKernelGGL(k_filter_1d<BMND_SHRINK_SOFT>, grid, dim3(kWave * kWaves), lds, s, a,
+                           tile_cap, tile_back);
+    else
+        hipLaunchKernelGGL(k_filter_1d<BMND_SHRINK_WIENER>, grid, dim3(kWave * kWaves), lds, s, a,
+                           tile_cap, tile_back);
+    return hipGetLastError();
+}
+
+}  // namespace bmnd

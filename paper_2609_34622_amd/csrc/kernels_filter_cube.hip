@@ -22,6 +22,14 @@ namespace {
 constexpr int kWave = 64;
 constexpr float kRsqrt2 = 0.70710678118654752440f;
 
+// Orders the LDS accesses of one wavefront (its LDS operations complete in
+// issue order; this keeps the compiler from moving accesses across).
+__device__ __forceinline__ void wsync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int J>
 __device__ __forceinline__ void load_row(const float* __restrict__ M, int q, float* r)
 {
@@ -30,38 +38,55 @@ __device__ __forceinline__ void load_row(const float* __restrict__ M, int q, flo
 }
 
 // One transform pass along the innermost axis of the current layout
-// (k, rest, t) -> (k, q, rest).
+// (k, rest, t) -> (k, q, rest).  Each lane sweeps up to NF fibres at once,
+// each with two partial sums (even and odd t), so the multiply-adds form
+// independent chains instead of one serial chain per fibre.
 template <int J, int P>
 __device__ __forceinline__ void pass_axis(const float* __restrict__ in, float* __restrict__ out,
                                           const float* row, int K)
 {
     constexpr int FPI = kWave / J;   // fibres per sweep step
     constexpr int R = P / J;         // fibres per member
-    const int lane = threadIdx.x;
+    constexpr int NF = 4;            // fibres per lane per step
+    const int lane = threadIdx.x % kWave;
     const int q = lane % J;
     const int fs = lane / J;
     const int F = K * R;
-    for (int fb = 0; fb < F; fb += FPI) {
-        const int f = fb + fs;
-        if (f < F) {
-            const float* x = in + f * J;
-            float s = 0.f;
-            if constexpr (J >= 4) {
+    for (int fb = 0; fb < F; fb += FPI * NF) {
+        float se[NF], so[NF];
 #pragma unroll
-                for (int t = 0; t < J; t += 4) {
-                    const float4 v = *reinterpret_cast<const float4*>(x + t);
-                    s = __builtin_fmaf(row[t], v.x, s);
-                    s = __builtin_fmaf(row[t + 1], v.y, s);
-                    s = __builtin_fmaf(row[t + 2], v.z, s);
-                    s = __builtin_fmaf(row[t + 3], v.w, s);
+        for (int k = 0; k < NF; ++k) {
+            se[k] = 0.f;
+            so[k] = 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            const int f = fb + fs + k * FPI;
+            if (f < F) {
+                const float* x = in + f * J;
+                if constexpr (J >= 4) {
+#pragma unroll
+                    for (int t = 0; t < J; t += 4) {
+                        const float4 v = *reinterpret_cast<const float4*>(x + t);
+                        se[k] = __builtin_fmaf(row[t], v.x, se[k]);
+                        so[k] = __builtin_fmaf(row[t + 1], v.y, so[k]);
+                        se[k] = __builtin_fmaf(row[t + 2], v.z, se[k]);
+                        so[k] = __builtin_fmaf(row[t + 3], v.w, so[k]);
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < J; ++t) se[k] = __builtin_fmaf(row[t], x[t], se[k]);
                 }
-            } else {
-#pragma unroll
-                for (int t = 0; t < J; ++t) s = __builtin_fmaf(row[t], x[t], s);
             }
-            const int k = f / R;
-            const int rest = f - k * R;
-            out[k * P + q * R + rest] = s;
+        }
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            const int f = fb + fs + k * FPI;
+            if (f < F) {
+                const int kk = f / R;
+                const int rest = f - kk * R;
+                out[kk * P + q * R + rest] = se[k] + so[k];
+            }
         }
     }
 }
@@ -77,7 +102,7 @@ __device__ __forceinline__ float* spatial(float* x, float* tmp, const float* __r
 #pragma unroll
     for (int s = 0; s < D; ++s) {
         pass_axis<J, P>(in, out, row, K);
-        __syncthreads();
+        wsync();
         float* t = in;
         in = out;
         out = t;
@@ -175,7 +200,7 @@ __device__ __forceinline__ void haar_column(float* X, int p, int mode)
 template <int GM, int P>
 __device__ void haar_arrays(float* x0, float* x1, float* x2, int narr, bool inverse, int K)
 {
-    for (int idx = threadIdx.x; idx < narr * P; idx += kWave) {
+    for (int idx = threadIdx.x % kWave; idx < narr * P; idx += kWave) {
         const int a = idx / P;
         const int p = idx - a * P;
         float* X = a == 0 ? x0 : (a == 1 ? x1 : x2);
@@ -189,7 +214,7 @@ __device__ void haar_arrays(float* x0, float* x1, float* x2, int narr, bool inve
         default: break;  // K = 1: identity
         }
     }
-    __syncthreads();
+    wsync();
 }
 
 __device__ __forceinline__ float wave_sum(float v)
@@ -219,26 +244,44 @@ __device__ __forceinline__ double haar64(int K, int l, int j)
     return (j - first) < support / 2 ? v : -v;
 }
 
+// Waves per workgroup: up to four groups of K x P <= 512 samples share one
+// workgroup (and its accumulation tile); larger groups get fewer waves.
+template <int KP>
+constexpr int waves_for() { return KP <= 512 ? 4 : (KP <= 1024 ? 2 : 1); }
+
 template <int D, int J, int GM>
-__global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
+__global__ __launch_bounds__(kWave * waves_for<GM * ipow_c(J, D)>())
+void k_filter_cube(FilterArgs a, int chunk_refs, int tile_cap, int tile_back)
 {
     constexpr int P = ipow_c(J, D);
     constexpr int KP = GM * P;
-    __shared__ __align__(16) float A[KP];
-    __shared__ __align__(16) float Bb[KP];
-    __shared__ __align__(16) float Vb[KP];
-    __shared__ __align__(16) float Tb[KP];
+    constexpr int NW = waves_for<KP>();
+    __shared__ __align__(16) float A_[NW][KP];
+    __shared__ __align__(16) float B_[NW][KP];
+    __shared__ __align__(16) float V_[NW][KP];
+    __shared__ __align__(16) float T_[NW][KP];
     __shared__ int off[P];
     __shared__ float win[P];
-    __shared__ int org[GM];
-    __shared__ float rpl[GM];
-    __shared__ float wj[GM];
-    __shared__ int nres;
+    __shared__ int org_[NW][GM];
+    __shared__ float rpl_[NW][GM];
+    __shared__ float wj_[NW][GM];
+    __shared__ int nres_[NW];
+    extern __shared__ __align__(16) float tile[];  // [2][tile_cap]: numerator, denominator
 
     const Geo& g = a.g;
-    const int lane = threadIdx.x;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    float* A = A_[wave];
+    float* Bb = B_[wave];
+    float* Vb = V_[wave];
+    float* Tb = T_[wave];
+    int* org = org_[wave];
+    float* rpl = rpl_[wave];
+    float* wj = wj_[wave];
+    int& nres = nres_[wave];
+
     const int cax = kAx - D;  // first canonical axis of the patch
-    for (int p = lane; p < P; p += kWave) {
+    for (int p = threadIdx.x; p < P; p += kWave * NW) {
         int rem = p, o = 0;
         float w = 1.f;
 #pragma unroll
@@ -251,30 +294,37 @@ __global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
         off[p] = o;
         win[p] = w;
     }
+    for (int i = threadIdx.x; i < 2 * tile_cap; i += kWave * NW) tile[i] = 0.f;
     const float* Tm = a.t.f32 + a.t.T[kAx - 1];
     const float* T2m = a.t.f32 + a.t.T2[kAx - 1];
     const float* Um = a.t.f32 + a.t.U[kAx - 1];
     const float* rn1 = a.t.f32 + a.t.rn[kAx - 1];
     const double* T64 = a.t.f64 + a.t.T64[kAx - 1];
+
+    // this workgroup: references [g0, g1) of array b
+    const int nchunk = (a.n_refs + chunk_refs - 1) / chunk_refs;
+    const int b = blockIdx.x / nchunk;
+    const int g0 = (blockIdx.x - b * nchunk) * chunk_refs;
+    const int g1 = min(a.n_refs, g0 + chunk_refs);
+    const long vb = long(b) * g.V;
+    // the tile covers lins [tile_lo, tile_lo + tile_cap)
+    const int tile_lo = tile_cap > 0 ? a.match[(long(b) * a.n_refs + g0) * a.gmax] - tile_back : 0;
+    float* tnum = tile;
+    float* tden = tile + tile_cap;
     __syncthreads();
 
-    // each workgroup takes a contiguous run of groups (neighbouring
-    // references share source samples in its XCD's L2)
-    const long ngroups = long(g.batch) * a.n_refs;
-    const long chunk = (ngroups + gridDim.x - 1) / gridDim.x;
-    const long g_end = min(ngroups, long(blockIdx.x + 1) * chunk);
-    for (long grp = long(blockIdx.x) * chunk; grp < g_end; ++grp) {
-        const int b = int(grp / a.n_refs);
+    for (int gi = g0 + wave; gi < g1; gi += NW) {
+        const long grp = long(b) * a.n_refs + gi;
         const int K = a.count[grp];
         const int n = K * P;
-        const float* yb = a.y + long(b) * g.V;
-        const float* pb = a.pilot ? a.pilot + long(b) * g.V : nullptr;
+        const float* yb = a.y + vb;
+        const float* pb = a.pilot ? a.pilot + vb : nullptr;
         if (lane < K) {
             org[lane] = a.match[grp * a.gmax + lane];
             rpl[lane] = 0.f;
         }
         if (lane == 0) nres = 0;
-        __syncthreads();
+        wsync();
 
         float* res = A;
         if (a.patches_in == nullptr) {
@@ -292,24 +342,24 @@ __global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
                 Vb[e] = a.noise == BMND_NOISE_POISSON ? a.s_p * fmaxf(mvsrc[u], 0.f) : a.sigma2;
             }
             const float gn = sqrtf(wave_sum(gn2));
-            __syncthreads();
+            wsync();
 
             // ---- forward transforms: spatial passes, then Haar
             float* Y = spatial<D, J, P>(A, Tb, Tm, K);
             if (Y != A) {
                 for (int e = lane; e < n; e += kWave) A[e] = Y[e];
-                __syncthreads();
+                wsync();
             }
             float* Vr = spatial<D, J, P>(Vb, Tb, T2m, K);
             if (Vr != Vb) {
                 for (int e = lane; e < n; e += kWave) Vb[e] = Vr[e];
-                __syncthreads();
+                wsync();
             }
             if (wiener) {
                 float* Gr = spatial<D, J, P>(Bb, Tb, Tm, K);
                 if (Gr != Bb) {
                     for (int e = lane; e < n; e += kWave) Bb[e] = Gr[e];
-                    __syncthreads();
+                    wsync();
                 }
             }
             haar_arrays<GM, P>(A, Vb, Bb, wiener ? 3 : 2, false, K);
@@ -319,7 +369,7 @@ __global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
                 const int l = e / P;
                 const float Yv = A[e];
                 const float v = fmaxf(Vb[e], 0.f);
-                float att, C, shat = 0.f;
+                float att, C;
                 if (a.shrink == BMND_SHRINK_HARD) {
                     const float thr = a.lambda * sqrtf(v);
                     const bool keep = fabsf(Yv) > thr;
@@ -330,6 +380,8 @@ __global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
                         rn *= rn1[qq % J];
                         qq /= J;
                     }
+                    // FP32 error band of the decision (transform round-off
+                    // is bounded by the row norm times the group norm)
                     const float band = 1e-5f * (rn * gn + thr);
                     if (v > 0.f && fabsf(fabsf(Yv) - thr) <= band) {
                         const int slot = atomicAdd(&nres, 1);
@@ -343,7 +395,7 @@ __global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
                     att = Yv != 0.f ? m / fabsf(Yv) : 0.f;
                 } else {
                     const float gam = Bb[e];
-                    shat = fmaxf(gam * gam - a.power_a * v, 0.f);
+                    const float shat = fmaxf(gam * gam - a.power_a * v, 0.f);
                     const float den = shat + a.s_v * v;
                     att = den > 0.f ? shat / den : 0.f;
                     C = att * Yv;
@@ -353,7 +405,7 @@ __global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
                 Tb[e] = att;
                 Vb[e] = v;
             }
-            __syncthreads();
+            wsync();
             if (a.shrink == BMND_SHRINK_HARD) {
                 const int nr = nres;
                 for (int r = 0; r < nr; ++r) {
@@ -388,13 +440,14 @@ __global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
                     }
                     sy = wave_sum64(sy);
                     sv = wave_sum64(sv);
+                    // strict inequality with the 1e-9 relative tie margin
                     const bool keep = fabs(sy) > a.lambda64 * sqrt(sv) * (1.0 + 1e-9);
                     if (lane == 0) Tb[e] = keep ? 1.f : 0.f;
-                    __syncthreads();
+                    wsync();
                 }
                 for (int e = lane; e < n; e += kWave)
                     if (Tb[e] == 0.f) A[e] = 0.f;
-                __syncthreads();
+                wsync();
             }
             for (int e = lane; e < n; e += kWave) {
                 const int l = e / P;
@@ -406,7 +459,7 @@ __global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
                 else r = at * at * v + (1.f - at) * (1.f - at) * Bb[e];
                 atomicAdd(&rpl[l], r);
             }
-            __syncthreads();
+            wsync();
             if (a.wscope == BMND_SCOPE_GROUP) {
                 float R = 0.f;
                 for (int l = 0; l < K; ++l) R += rpl[l];
@@ -420,7 +473,7 @@ __global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
                 }
                 wj[lane] = R > 0.f ? 1.f / R : 1.f;
             }
-            __syncthreads();
+            wsync();
 
             // ---- synthesis: Haar^T, then U along every axis
             haar_arrays<GM, P>(A, nullptr, nullptr, 1, true, K);
@@ -429,11 +482,10 @@ __global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
             const float* pin = a.patches_in + grp * long(a.gmax) * P;
             for (int e = lane; e < n; e += kWave) A[e] = pin[e];
             if (lane < K) wj[lane] = a.weights_in[grp * a.gmax + lane];
-            __syncthreads();
+            wsync();
         }
 
         // ---- outputs
-        const long vb = long(b) * g.V;
         if (a.out_mode == 0) {
             float* pout = a.patches + grp * long(a.gmax) * P;
             for (int e = lane; e < a.gmax * P; e += kWave) pout[e] = e < n ? res[e] : 0.f;
@@ -442,10 +494,16 @@ __global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
             for (int e = lane; e < n; e += kWave) {
                 const int k = e / P;
                 const int p = e - k * P;
-                const long u = vb + org[k] + off[p];
+                const int u = org[k] + off[p];
                 const float ww = wj[k] * win[p];
-                unsafeAtomicAdd(&a.numf[u], ww * res[e]);
-                unsafeAtomicAdd(&a.denf[u], ww);
+                const int tl = u - tile_lo;
+                if (tl >= 0 && tl < tile_cap) {
+                    atomicAdd(&tnum[tl], ww * res[e]);
+                    atomicAdd(&tden[tl], ww);
+                } else {
+                    unsafeAtomicAdd(&a.numf[vb + u], ww * res[e]);
+                    unsafeAtomicAdd(&a.denf[vb + u], ww);
+                }
             }
         } else if (a.out_mode == 2) {
             for (int e = lane; e < n; e += kWave) {
@@ -475,27 +533,53 @@ __global__ __launch_bounds__(kWave) void k_filter_cube(FilterArgs a)
                                 double(wj[k]) * double(win[p]) * (double(res[e]) + alpha));
             }
         }
+        wsync();
+    }
+
+    // ---- flush the accumulation tile
+    if (tile_cap > 0 && a.out_mode == 1) {
         __syncthreads();
+        for (int i = threadIdx.x; i < tile_cap; i += kWave * NW) {
+            const float d = tden[i];
+            const int u = tile_lo + i;
+            if (d != 0.f && u >= 0 && u < g.V) {
+                unsafeAtomicAdd(&a.numf[vb + u], tnum[i]);
+                unsafeAtomicAdd(&a.denf[vb + u], d);
+            }
+        }
     }
 }
 
 template <int D, int J>
-hipError_t launch_cube_gm(const FilterArgs& a, long groups, hipStream_t s)
+hipError_t launch_cube_gm(const FilterArgs& a, int step_last, hipStream_t s)
 {
-    int dev = 0, ncu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (ncu <= 0) ncu = 256;
-    const long cap = long(ncu) * 32;
-    const dim3 grid(unsigned(groups < cap ? groups : cap));
-    switch (a.gmax) {
-    case 1: hipLaunchKernelGGL((k_filter_cube<D, J, 1>), grid, dim3(kWave), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_filter_cube<D, J, 2>), grid, dim3(kWave), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_filter_cube<D, J, 4>), grid, dim3(kWave), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_filter_cube<D, J, 8>), grid, dim3(kWave), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_filter_cube<D, J, 16>), grid, dim3(kWave), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_filter_cube<D, J, 32>), grid, dim3(kWave), 0, s, a); break;
+    constexpr int chunk = 256;
+    const Geo& g = a.g;
+    // 1-D arrays: the patches of a chunk of references fall into a short lin
+    // range, accumulated in LDS; elsewhere the tile is off
+    int tile_cap = 0, tile_back = 0;
+    const bool one_d = g.L[0] == 1 && g.L[1] == 1 && g.L[2] == 1;
+    if (one_d && a.out_mode == 1) {
+        tile_back = g.W[kAx - 1] / 2;
+        tile_cap = (chunk - 1) * max(step_last, 1) + g.W[kAx - 1] + g.j[kAx - 1];
+        if (tile_cap > 8192) tile_cap = 8192;
     }
+    const int nchunk = (a.n_refs + chunk - 1) / chunk;
+    const dim3 grid(unsigned(long(nchunk) * g.batch));
+    const size_t lds = sizeof(float) * 2 * size_t(tile_cap);
+#define BMND_CUBE_LAUNCH(GMV)                                                              \
+    hipLaunchKernelGGL((k_filter_cube<D, J, GMV>),                                          \
+                       dim3(grid), dim3(kWave * waves_for<GMV * ipow_c(J, D)>()), lds, s, a, \
+                       chunk, tile_cap, tile_back)
+    switch (a.gmax) {
+    case 1: BMND_CUBE_LAUNCH(1); break;
+    case 2: BMND_CUBE_LAUNCH(2); break;
+    case 4: BMND_CUBE_LAUNCH(4); break;
+    case 8: BMND_CUBE_LAUNCH(8); break;
+    case 16: BMND_CUBE_LAUNCH(16); break;
+    default: BMND_CUBE_LAUNCH(32); break;
+    }
+#undef BMND_CUBE_LAUNCH
     return hipGetLastError();
 }
 
@@ -515,12 +599,12 @@ bool cube_filter_supported(const Geo& g, int gmax)
     return shape_ok && gmax * g.P <= kMaxKP && g.P * gmax * 16 <= 65536;
 }
 
-hipError_t launch_filter_cube(const FilterArgs& a, long groups, hipStream_t s)
+hipError_t launch_filter_cube(const FilterArgs& a, int step_last, hipStream_t s)
 {
     const Geo& g = a.g;
-    if (g.P == 32) return launch_cube_gm<1, 32>(a, groups, s);
-    if (g.j[kAx - 1] == 8) return launch_cube_gm<2, 8>(a, groups, s);
-    return launch_cube_gm<3, 4>(a, groups, s);
+    if (g.P == 32) return launch_cube_gm<1, 32>(a, step_last, s);
+    if (g.j[kAx - 1] == 8) return launch_cube_gm<2, 8>(a, step_last, s);
+    return launch_cube_gm<3, 4>(a, step_last, s);
 }
 
 }  // namespace bmnd
