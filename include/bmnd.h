@@ -189,9 +189,12 @@ bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noi
  *   d_match [batch][n_refs][group_max] int32 lin of the members; -1 beyond K
  *   d_count [batch][n_refs] int32 K
  *   d_ws    workspace of bmnd_match_workspace_size() bytes
+ * Non-finite scores are never selected; a group then shrinks to the
+ * largest power of two its selected members fill, so every entry below K
+ * is a valid origin.  Reference origins are clamped into the array.
  * Errors: BMND_E_ARG / _SHAPE / _UNSUPPORTED / _WORKSPACE / _HIP;
- * counts too large for exact int32 scoring raise BMND_E_RANGE from
- * bmnd_stream_status(). */
+ * counts too large for exact int32 scoring, and non-finite observations in
+ * count-domain HT matching, raise BMND_E_RANGE from bmnd_stream_status(). */
 bmnd_status bmnd_match(int32_t stage, const float* d_src, const bmnd_geometry* geom,
                        const bmnd_noise* noise, const bmnd_stage_params* sp,
                        const int64_t* d_refs, int64_t n_refs, int32_t* d_match,
@@ -210,7 +213,9 @@ bmnd_status bmnd_match(int32_t stage, const float* d_src, const bmnd_geometry* g
  * Wiener weighting models, Def. aggregation-weight scope) and synthesize
  * p = U C with U = T^-1 (Def. pilot group).
  *   d_pilot    [batch][V] (Wiener only; NULL in the HT stage)
- *   d_match, d_count as produced by bmnd_match
+ *   d_match, d_count as produced by bmnd_match (other contents are read
+ *              memory-safely: K is cut to a power of two in [1, group_max]
+ *              and origins into the array; the result is then unspecified)
  *   d_patches  [batch][n_refs][group_max][P] synthesized patches, no window
  *   d_weights  [batch][n_refs][group_max] patch weights (0 beyond K)
  * Errors: BMND_E_ARG / _SHAPE / _UNSUPPORTED / _HIP. */
@@ -227,6 +232,7 @@ bmnd_status bmnd_filter(int32_t stage, const float* d_y, const float* d_pilot,
  * the constant alpha_g = zeta_g^T (y_g - p_g) / zeta_g^T 1 that satisfies
  * eq. dc-group-constraint, so that sum x^ = sum y (Thm. mass conservation
  * after normalized overlap-add).  Voxels no patch covers are set to 0.
+ *   d_match, d_count as for bmnd_filter
  *   d_y    [batch][V] observation (read only with mass conservation)
  *   d_out  [batch][V] result
  *   d_ws   workspace of bmnd_aggregate_workspace_size() bytes */
@@ -260,7 +266,8 @@ bmnd_status bmnd_profile_end(double* ms, int64_t* launches, int32_t n_ids);
 
 /* Synchronise `stream` and report asynchronous failures: BMND_E_HIP for a
  * device fault, BMND_E_RANGE if a matching kernel saw counts outside the
- * exact int32 range since the last call.  Clears the range flag. */
+ * exact int32 range (or non-finite counts) since the last call.  Clears the
+ * range flag. */
 bmnd_status bmnd_stream_status(void* stream);
 
 #ifdef __cplusplus

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "bmnd_internal.h"
+#include "safe_index.h"
 
 namespace bmnd {
 
@@ -29,6 +30,7 @@ struct FilterArgs {
 };
 
 constexpr int ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
+
 
 bool cube_filter_supported(const Geo& g, int gmax);
 hipError_t launch_filter_cube(const FilterArgs& a, int step_last, hipStream_t s);

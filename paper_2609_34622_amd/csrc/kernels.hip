@@ -38,9 +38,11 @@ __global__ void k_counts(Geo g, const float* __restrict__ y, float inv_sp, int k
     const long n = long(g.batch) * g.V;
     for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += long(gridDim.x) * blockDim.x) {
-        const int k = int(rintf(y[i] * inv_sp));
-        if (k < 0 || k > kmax) atomicOr(flag, 1);
-        kappa[i] = k;
+        // non-finite or out-of-range counts are flagged (and scored as 0)
+        const float rk = rintf(y[i] * inv_sp);
+        const bool ok = rk >= 0.f && rk <= float(kmax);
+        if (!ok) atomicOr(flag, 1);
+        kappa[i] = ok ? int(rk) : 0;
     }
 }
 
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
     if (t >= long(g.batch) * a.n_refs) return;
     const int b = int(t / a.n_refs);
     const int gi = int(t - long(b) * a.n_refs);
-    const int r = int(a.refs[gi]);
+    const int r = safe_origin(int(a.refs[gi]), last_origin(g));
     const float* src = a.src + long(b) * g.V;
     const int* kap = MODE == kCount ? a.kappa + long(b) * g.V : nullptr;
 
@@ -211,8 +213,10 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
     int* out = a.match + t * a.gmax;
     out[0] = r;
     for (int m = 1; m < a.gmax; ++m) out[m] = -1;
-    a.count[t] = K;
-    if (need == 0) return;
+    if (need == 0) {
+        a.count[t] = K;
+        return;
+    }
 
     S theta = s[0];
     int n_less = 0;
@@ -244,6 +248,10 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
                         ++got;
                     }
                 }
+    // non-finite scores select fewer members than asked: the group is cut to
+    // the largest power of two they fill, so every listed member is valid
+    if (got < need) K = pow2floor(1 + got);
+    a.count[t] = K;
     // ---- sort the members by (score, lin); insertion keeps lin order on ties
     for (int m = 1; m < got; ++m) {
         const int ks = sel_s[m][threadIdx.x], kl = sel_l[m][threadIdx.x];
@@ -257,7 +265,7 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
         sel_s[p + 1][threadIdx.x] = ks;
         sel_l[p + 1][threadIdx.x] = kl;
     }
-    for (int m = 0; m < got; ++m) out[1 + m] = sel_l[m][threadIdx.x];
+    for (int m = 0; m < K - 1; ++m) out[1 + m] = sel_l[m][threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -436,7 +444,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
 
     const long grp = blockIdx.x;
     const int b = int(grp / a.n_refs);
-    const int K = a.count[grp];
+    const int K = safe_count(a.count[grp], a.gmax);
     const int P = g.P;
     const int n = K * P;
     const float* yb = a.y + long(b) * g.V;
@@ -482,7 +490,8 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
             off[i] = o2;
             win[i] = w;
         }
-        for (int j = threadIdx.x; j < K; j += kFilterThreads) org[j] = a.match[grp * a.gmax + j];
+        for (int j = threadIdx.x; j < K; j += kFilterThreads)
+            org[j] = safe_origin(a.match[grp * a.gmax + j], last_origin(g));
         for (int l = threadIdx.x; l < K; l += kFilterThreads) rpl[l] = 0.f;
         if (threadIdx.x == 0) misc[0] = 0;
     }

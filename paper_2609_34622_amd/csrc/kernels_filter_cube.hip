@@ -281,6 +281,7 @@ void k_filter_cube(FilterArgs a, int chunk_refs, int tile_cap, int tile_back)
     int& nres = nres_[wave];
 
     const int cax = kAx - D;  // first canonical axis of the patch
+    const int omax = last_origin(g);
     for (int p = threadIdx.x; p < P; p += kWave * NW) {
         int rem = p, o = 0;
         float w = 1.f;
@@ -315,12 +316,12 @@ void k_filter_cube(FilterArgs a, int chunk_refs, int tile_cap, int tile_back)
 
     for (int gi = g0 + wave; gi < g1; gi += NW) {
         const long grp = long(b) * a.n_refs + gi;
-        const int K = a.count[grp];
+        const int K = safe_count(a.count[grp], a.gmax);
         const int n = K * P;
         const float* yb = a.y + vb;
         const float* pb = a.pilot ? a.pilot + vb : nullptr;
         if (lane < K) {
-            org[lane] = a.match[grp * a.gmax + lane];
+            org[lane] = safe_origin(a.match[grp * a.gmax + lane], omax);
             rpl[lane] = 0.f;
         }
         if (lane == 0) nres = 0;

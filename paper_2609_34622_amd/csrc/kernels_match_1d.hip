@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kWave) void k_match_1d(MatchArgs a, int cap_span, i
     const int lane = threadIdx.x;
     const int gi = chunk * kWave + lane;
     const bool have = gi < a.n_refs;
-    const int r = have ? int(a.refs[gi]) : 0;
+    const int r = have ? safe_origin(int(a.refs[gi]), last_origin(g)) : 0;
     const float* src = a.src + long(b) * g.V;
     const long t = long(b) * a.n_refs + gi;
     const float inv_sp = a.inv_sp;
@@ -97,7 +97,8 @@ __global__ __launch_bounds__(kWave) void k_match_1d(MatchArgs a, int cap_span, i
     while (__any(pending)) {
         // ---- stage the window of the first pending reference onward
         const int r0 = __shfl(r, __ffsll(__ballot(pending)) - 1);
-        const bool mine = pending && (r - r0) <= cap_span;
+        // references below r0 (unsorted lists) wait for a later round
+        const bool mine = pending && r >= r0 && (r - r0) <= cap_span;
         const int base = r0 + wlo;
         const int len = cap_span + W + 2 * kJ;  // covers the last 64-sample block
         for (int i = lane; i < len; i += kWave) {
@@ -106,9 +107,12 @@ __global__ __launch_bounds__(kWave) void k_match_1d(MatchArgs a, int cap_span, i
             if (pos >= 0 && pos < L) {
                 const float x = src[pos];
                 if constexpr (MODE == kCount) {
-                    const int k = int(rintf(x * inv_sp));
-                    if (k < 0 || k > kmax) atomicOr(a.range_flag, 1);
-                    v = k;
+                    // non-finite or out-of-range counts are flagged (and
+                    // scored as 0)
+                    const float rk = rintf(x * inv_sp);
+                    const bool ok = rk >= 0.f && rk <= float(kmax);
+                    if (!ok) atomicOr(a.range_flag, 1);
+                    v = ok ? int(rk) : 0;
                 } else {
                     v = __float_as_int(x);
                 }
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(kWave) void k_match_1d(MatchArgs a, int cap_span, i
             int* out = a.match + t * a.gmax;
             out[0] = r;
             for (int m = 1; m < a.gmax; ++m) out[m] = -1;
-            a.count[t] = K;
+            if (need == 0) a.count[t] = K;
             if (need > 0) {
                 S theta = s[0];
 #pragma unroll
@@ -215,6 +219,10 @@ __global__ __launch_bounds__(kWave) void k_match_1d(MatchArgs a, int cap_span, i
                     for (int d = dlo; d <= dhi && got < need; ++d)
                         if (d != 0) consider(d);
                 }
+                // non-finite scores select fewer members than asked: the
+                // group is cut to the largest power of two they fill
+                if (got < need) K = p2floor(1 + got);
+                a.count[t] = K;
                 for (int m = 1; m < got; ++m) {
                     const int ks = sel_s[m][lane], kl = sel_l[m][lane];
                     const S kv = from_bits<S>(ks);
@@ -227,7 +235,7 @@ __global__ __launch_bounds__(kWave) void k_match_1d(MatchArgs a, int cap_span, i
                     sel_s[p + 1][lane] = ks;
                     sel_l[p + 1][lane] = kl;
                 }
-                for (int m = 0; m < got; ++m) out[1 + m] = sel_l[m][lane];
+                for (int m = 0; m < K - 1; ++m) out[1 + m] = sel_l[m][lane];
             }
         }
         pending = pending && !mine;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "bmnd_internal.h"
+#include "safe_index.h"
 
 namespace bmnd {
 
