@@ -36,7 +36,8 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kJ = 32;        // patch length
 constexpr int kWaves = 4;     // wavefronts per workgroup
-constexpr int kChunk = 256;   // references per workgroup
+constexpr int kSub = 48;      // references per wavefront (a contiguous run)
+constexpr int kChunk = kSub * kWaves;  // references per workgroup
 constexpr int kZs = 36;       // row stride (floats) of the transpose buffer
 constexpr float kRsqrt2 = 0.70710678118654752440f;
 
@@ -89,6 +90,10 @@ __device__ __forceinline__ double haar_d(int lk, int l, int j)
     return (j - first) < (1 << (e - 1)) ? v : -v;
 }
 
+// hardware square root and reciprocal (about 1 ulp)
+__device__ __forceinline__ float fsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+__device__ __forceinline__ float frcp(float v) { return __builtin_amdgcn_rcpf(v); }
+
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v)
 {
@@ -121,7 +126,7 @@ __device__ __forceinline__ double wave_sum64(double v)
     return v;
 }
 
-// Operand tables in LDS: matrix m (T, T o T, U), column block c, depth
+// Operand tables in LDS: matrix m (T, U), column block c, depth
 // half h, lane, 4 depth steps; lane (m16, lg) finds its eight B operands
 // for block c at depth 8lg + s, s = 4h + k, as two 16-byte reads.
 __device__ __forceinline__ int opnd_index(int m, int c, int h, int lane)
@@ -138,14 +143,18 @@ __device__ __forceinline__ void opnd_load(const float* ops, int m, int c, int la
 }
 
 template <int SH>
-__global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int tile_cap,
-                                                              int tile_back)
+__global__ __launch_bounds__(kWave * kWaves) __attribute__((amdgpu_waves_per_eu(3)))
+void k_filter_1d(FilterArgs a, int tile_cap, int tile_back, int wcap)
 {
     constexpr bool wiener = SH == BMND_SHRINK_WIENER;
-    __shared__ __align__(16) float ops[3 * 2 * 2 * kWave * 4];
+    __shared__ __align__(16) float ops[2 * 2 * 2 * kWave * 4];
+    // Haar operands per group size 2^lk and lane: H[m16][4lg + s] (analysis)
+    // and H[4lg + s][m16] (synthesis), s = 0..3
+    __shared__ __align__(16) float hops[5][kWave][8];
     __shared__ __align__(16) float ztr_[kWaves][16 * kZs];
     __shared__ float rl_[kWaves][16];
-    // [4][tile_cap]: numerator, denominator, staged samples, staged pilot
+    // per wavefront [2][wcap] (numerator, denominator of its accumulation
+    // tile), then [tile_cap] staged samples and [tile_cap] staged pilot
     extern __shared__ __align__(16) float tile[];
 
     const Geo& g = a.g;
@@ -156,16 +165,25 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
     float* ztr = ztr_[wave];
     float* rl = rl_[wave];
 
-    // ---- operands of the spatial products: T[q][i], (T o T)[q][i] and
-    // U[i][q] at q (or i) = 16c + m16 and depth i (or q) = 8lg + s
-    for (int e = threadIdx.x; e < 3 * 2 * 2 * kWave * 4; e += kWave * kWaves) {
+    // ---- operands of the spatial products: T[q][i] and U[i][q] at q (or i)
+    // = 16c + m16 and depth i (or q) = 8lg + s; (T o T) is squared on use
+    for (int e = threadIdx.x; e < 2 * 2 * 2 * kWave * 4; e += kWave * kWaves) {
         const int k = e & 3;
         const int ln = (e >> 2) & (kWave - 1);
         const int h = (e >> 8) & 1;
         const int c = (e >> 9) & 1;
         const int m = e >> 10;
-        const int off = m == 0 ? a.t.T[kAx - 1] : (m == 1 ? a.t.T2[kAx - 1] : a.t.U[kAx - 1]);
+        const int off = m == 0 ? a.t.T[kAx - 1] : a.t.U[kAx - 1];
         ops[e] = a.t.f32[off + (16 * c + (ln & 15)) * kJ + 8 * (ln >> 4) + 4 * h + k];
+    }
+    for (int e = threadIdx.x; e < 5 * kWave; e += kWave * kWaves) {
+        const int lk = e / kWave;
+        const int ln = e % kWave;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            hops[lk][ln][s] = haar_f(lk, ln & 15, 4 * (ln >> 4) + s);
+            hops[lk][ln][4 + s] = haar_f(lk, 4 * (ln >> 4) + s, ln & 15);
+        }
     }
     float w0 = 1.f, rn0 = 1.f;  // leading axes have one-sample patches
 #pragma unroll
@@ -186,41 +204,46 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
     const int g0 = (blockIdx.x - b * nchunk) * kChunk;
     const int g1 = min(a.n_refs, g0 + kChunk);
     const long vb = long(b) * g.V;
+    // this wavefront: references [w0g, w1g), accumulated in its own tile
+    // [wlo, wlo + wcap); the workgroup stages [tile_lo, tile_lo + tile_cap)
+    const int w0g = min(g1, g0 + wave * kSub);
+    const int w1g = min(g1, w0g + kSub);
     const int tile_lo = tile_cap > 0 ? a.match[(long(b) * a.n_refs + g0) * a.gmax] - tile_back : 0;
-    float* tnum = tile;
-    float* tden = tile + tile_cap;
-    float* ysm = tile + 2 * tile_cap;
-    float* psm = tile + 3 * tile_cap;
+    const int wlo = (wcap > 0 && w0g < w1g) ? a.match[(long(b) * a.n_refs + w0g) * a.gmax] - tile_back : 0;
+    float* tnum = tile + wave * 2 * wcap;
+    float* tden = tnum + wcap;
+    float* ysm = tile + kWaves * 2 * wcap;
+    float* psm = ysm + tile_cap;
     const bool poisson = a.noise == BMND_NOISE_POISSON;
-    const bool acc_tile = tile_cap > 0 && a.out_mode == 1;
+    const int omax = last_origin(g);
+    const bool acc_tile = wcap > 0 && a.out_mode == 1;
     const float* yb = a.y + vb;
     const float* pb = a.pilot ? a.pilot + vb : nullptr;
     // 1-D arrays: the samples around the chunk's references, staged once
     for (int i = threadIdx.x; i < tile_cap; i += kWave * kWaves) {
         const int u = tile_lo + i;
         const bool inb = u >= 0 && u < g.V;
-        tnum[i] = 0.f;
-        tden[i] = 0.f;
         ysm[i] = inb ? yb[u] : 0.f;
         if constexpr (wiener) psm[i] = inb ? pb[u] : 0.f;
     }
+    for (int i = lane; i < 2 * wcap; i += kWave) tnum[i] = 0.f;
     __syncthreads();
 
     // the next group's size and this lane's entry of its match list are
     // loaded one group ahead
-    int gi = g0 + wave;
+    int gi = w0g;
     int Knext = 0, mnext = 0;
-    if (gi < g1) {
+    if (gi < w1g) {
         const long grp = long(b) * a.n_refs + gi;
         Knext = a.count[grp];
         mnext = a.match[grp * a.gmax + min(m16, a.gmax - 1)];
     }
-    for (; gi < g1; gi += kWaves) {
+    for (; gi < w1g; ++gi) {
         const long grp = long(b) * a.n_refs + gi;
-        const int K = Knext;
-        const int mv0 = mnext;
-        if (gi + kWaves < g1) {
-            const long gn = grp + kWaves;
+        const int K = safe_count(Knext, a.gmax);
+        const int mv0 = safe_origin(mnext, omax);
+        if (gi + 1 < w1g) {
+            const long gn = grp + 1;
             Knext = a.count[gn];
             mnext = a.match[gn * a.gmax + min(m16, a.gmax - 1)];
         }
@@ -228,7 +251,7 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
         const bool av = m16 < K;  // this lane's member in the A layout
         // lanes past K read the samples at a valid origin inside the staged
         // range (tile_lo <= the chunk's first reference) and drop them
-        const int oa = av ? mv0 : max(tile_lo, 0);
+        const int oa = av ? mv0 : safe_origin(tile_lo, omax);
 
         // ---- gather: samples, variance map (from y, or from the pilot)
         float x[8], pv[8], mv[8];
@@ -258,12 +281,15 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
 
         // ---- analysis: spatial rows 16c + m16 of every member, then Haar over
         // the members with A[row m16][depth (lg, s)] = H[m16][4lg + s]
-        float ha[4], h2[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            ha[s] = haar_f(lk, m16, 4 * lg + s);
-            h2[s] = ha[s] * ha[s];
+        float ha[4], h2[4], hi[4];
+        {
+            const float4 u0 = *reinterpret_cast<const float4*>(&hops[lk][lane][0]);
+            const float4 u1 = *reinterpret_cast<const float4*>(&hops[lk][lane][4]);
+            ha[0] = u0.x; ha[1] = u0.y; ha[2] = u0.z; ha[3] = u0.w;
+            hi[0] = u1.x; hi[1] = u1.y; hi[2] = u1.z; hi[3] = u1.w;
         }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) h2[s] = ha[s] * ha[s];
         f4 Y[2], V[2], G[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -275,9 +301,8 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
                 y1 = mfma(x[s], tb[s], y1);
                 if constexpr (wiener) p1 = mfma(pv[s], tb[s], p1);
             }
-            opnd_load(ops, 1, c, lane, tb);
 #pragma unroll
-            for (int s = 0; s < 8; ++s) v1 = mfma(mv[s], tb[s], v1);
+            for (int s = 0; s < 8; ++s) v1 = mfma(mv[s], tb[s] * tb[s], v1);
             Y[c] = V[c] = G[c] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
@@ -298,13 +323,16 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
                 for (int r = 0; r < 4; ++r) {
                     const float Yv = Y[c][r];
                     const float v = fmaxf(V[c][r], 0.f);
-                    const float thr = a.lambda * sqrtf(v);
+                    const float thr = a.lambda * fsqrt(v);
                     const bool lv = 4 * lg + r < K;
-                    if (lv && fabsf(Yv) > thr) keep |= 1u << (4 * c + r);
-                    // FP32 error band of the decision (transform round-off is
-                    // bounded by the row norm times the group norm)
-                    if (lv && v > 0.f && fabsf(fabsf(Yv) - thr) <= 1e-5f * (rq[c] * gn + thr))
-                        near |= 1u << (4 * c + r);
+                    const bool kp = lv & (fabsf(Yv) > thr);
+                    // FP32 error band of the decision (transform and square
+                    // root round-off are bounded by the row norm times the
+                    // group norm, and by the threshold)
+                    const bool nr = lv & (v > 0.f) &
+                                    (fabsf(fabsf(Yv) - thr) <= 1e-5f * (rq[c] * gn + thr));
+                    keep |= unsigned(kp) << (4 * c + r);
+                    near |= unsigned(nr) << (4 * c + r);
                 }
             // FP64 decisions for the coefficients in the error band, one at a time
             for (;;) {
@@ -349,22 +377,22 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
                     at = (keep >> (4 * c + r)) & 1u ? 1.f : 0.f;
                     Cv = at != 0.f ? Yv : 0.f;
                 } else if constexpr (SH == BMND_SHRINK_SOFT) {
-                    const float m = fmaxf(fabsf(Yv) - a.lambda * sqrtf(v), 0.f);
+                    const float m = fmaxf(fabsf(Yv) - a.lambda * fsqrt(v), 0.f);
                     Cv = Yv > 0.f ? m : (Yv < 0.f ? -m : 0.f);
-                    at = Yv != 0.f ? m / fabsf(Yv) : 0.f;
+                    at = Yv != 0.f ? m * frcp(fabsf(Yv)) : 0.f;
                 } else {
                     const float gam = G[c][r];
                     shat = fmaxf(gam * gam - a.power_a * v, 0.f);
                     const float den = shat + a.s_v * v;
-                    at = den > 0.f ? shat / den : 0.f;
+                    at = den > 0.f ? shat * frcp(den) : 0.f;
                     Cv = at * Yv;
                 }
                 C[c][r] = Cv;
-                if (lv) {
-                    if (a.wmodel == BMND_WEIGHT_CLASSIC) t += at * at;
-                    else if (a.wmodel == BMND_WEIGHT_VARIANCE) t += at * at * v;
-                    else t += at * at * v + (1.f - at) * (1.f - at) * shat;
-                }
+                float tr;
+                if (a.wmodel == BMND_WEIGHT_CLASSIC) tr = at * at;
+                else if (a.wmodel == BMND_WEIGHT_VARIANCE) tr = at * at * v;
+                else tr = at * at * v + (1.f - at) * (1.f - at) * shat;
+                t += lv ? tr : 0.f;
             }
             rr[r] = sum16(t);
         }
@@ -375,7 +403,7 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
             float R = rr[0] + rr[1] + rr[2] + rr[3];
             R += __shfl_xor(R, 16);
             R += __shfl_xor(R, 32);
-            wA = R > 0.f ? 1.f / R : 1.f;
+            wA = R > 0.f ? frcp(R) : 1.f;
         } else {
             // R_j = sum_l H[l][j]^2 r_l: the scaling row and one detail row
             // per level hold member j
@@ -389,22 +417,17 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
                 const int e = lk - t;
                 R += rl[(1 << t) + (m16 >> e)] / float(1 << e);
             }
-            wA = R > 0.f ? 1.f / R : 1.f;
+            wA = R > 0.f ? frcp(R) : 1.f;
             wsync();
         }
 
         // ---- synthesis: Z = H^T C (A[row m16][depth (lg, s)] = H[4lg + s][m16]) ...
         f4 Z[2];
-        {
-            float hi[4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) hi[s] = haar_f(lk, 4 * lg + s, m16);
+        for (int c = 0; c < 2; ++c) {
+            Z[c] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                Z[c] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s = 0; s < 4; ++s) Z[c] = mfma(hi[s], C[c][s], Z[c]);
-            }
+            for (int s = 0; s < 4; ++s) Z[c] = mfma(hi[s], C[c][s], Z[c]);
         }
         // ... through LDS into the A layout, then X^ = Z U^T
 #pragma unroll
@@ -424,7 +447,7 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             float ub[8];
-            opnd_load(ops, 2, c, lane, ub);
+            opnd_load(ops, 1, c, lane, ub);
             o[c] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < 8; ++s) o[c] = mfma(za[s], ub[s], o[c]);
@@ -438,6 +461,12 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
             od[r] = __shfl(oa, 4 * lg + r);
             wd[r] = __shfl(wA, 4 * lg + r);
         }
+        // every member of the group inside the accumulation tile (members
+        // past K sit at the staged fallback origin)
+        bool in_tile = acc_tile;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            in_tile = in_tile & (od[r] - wlo >= 0) & (od[r] - wlo + kJ <= wcap);
         if (a.out_mode == 0) {
             float* pout = a.patches + grp * long(a.gmax) * kJ;
 #pragma unroll
@@ -449,6 +478,29 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
                 }
             }
             if (lane < a.gmax) a.weights[grp * a.gmax + lane] = lane < K ? wA : 0.f;
+        } else if (a.out_mode == 1 && __all(in_tile)) {
+            // every member inside this wavefront's tile (members past K add
+            // zeros at the fallback origin).  The lanes of one lane group
+            // write 16 distinct samples; lane groups take turns, so no two
+            // lanes of one instruction update the same sample.
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (lg == q) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const bool lv = 4 * lg + r < K;
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const int tl = od[r] - wlo + 16 * c + m16;
+                            const float ww = lv ? wd[r] * wq[c] : 0.f;
+                            tnum[tl] += ww * o[c][r];
+                            tden[tl] += ww;
+                        }
+                        wsync();
+                    }
+                }
+                wsync();
+            }
         } else if (a.out_mode == 1) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -457,14 +509,8 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
                     for (int c = 0; c < 2; ++c) {
                         const int u = od[r] + 16 * c + m16;
                         const float ww = wd[r] * wq[c];
-                        const int tl = u - tile_lo;
-                        if (acc_tile && tl >= 0 && tl < tile_cap) {
-                            atomicAdd(&tnum[tl], ww * o[c][r]);
-                            atomicAdd(&tden[tl], ww);
-                        } else {
-                            unsafeAtomicAdd(&a.numf[vb + u], ww * o[c][r]);
-                            unsafeAtomicAdd(&a.denf[vb + u], ww);
-                        }
+                        unsafeAtomicAdd(&a.numf[vb + u], ww * o[c][r]);
+                        unsafeAtomicAdd(&a.denf[vb + u], ww);
                     }
                 }
             }
@@ -510,12 +556,12 @@ __global__ __launch_bounds__(kWave * kWaves) void k_filter_1d(FilterArgs a, int 
         }
     }
 
-    // ---- flush the accumulation tile
+    // ---- flush this wavefront's tile
     if (acc_tile) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < tile_cap; i += kWave * kWaves) {
+        wsync();
+        for (int i = lane; i < wcap; i += kWave) {
             const float d = tden[i];
-            const int u = tile_lo + i;
+            const int u = wlo + i;
             if (d != 0.f && u >= 0 && u < g.V) {
                 unsafeAtomicAdd(&a.numf[vb + u], tnum[i]);
                 unsafeAtomicAdd(&a.denf[vb + u], d);
@@ -536,27 +582,32 @@ hipError_t launch_filter_1d(const FilterArgs& a, int step_last, hipStream_t s)
 {
     const Geo& g = a.g;
     // 1-D arrays: the windows of a chunk of references fall into a short lin
-    // range, staged (samples) and accumulated (aggregation) in LDS; elsewhere
-    // the tile is off
-    int tile_cap = 0, tile_back = 0;
+    // range, staged in LDS; each wavefront accumulates its own run of
+    // references in an LDS tile.  Elsewhere both are off.
+    constexpr int kDynFloats = 9216;  // dynamic LDS (36 KiB) beside the static arrays
+    int tile_cap = 0, tile_back = 0, wcap = 0;
     const bool one_d = g.L[0] == 1 && g.L[1] == 1 && g.L[2] == 1;
+    const int nstage = a.shrink == BMND_SHRINK_WIENER ? 2 : 1;  // staged arrays
     if (one_d) {
+        const int st = max(step_last, 1);
         tile_back = g.W[kAx - 1] / 2;
-        tile_cap = (kChunk - 1) * max(step_last, 1) + g.W[kAx - 1] + kJ;
-        if (tile_cap > 2560) tile_cap = 2560;  // 40 KiB of dynamic LDS
+        tile_cap = (kChunk - 1) * st + g.W[kAx - 1] + kJ;
+        if (a.out_mode == 1) wcap = (kSub - 1) * st + g.W[kAx - 1] + kJ;
+        if (kWaves * 2 * wcap + nstage * tile_cap > kDynFloats) wcap = 0;
+        tile_cap = min(tile_cap, kDynFloats / nstage);
     }
     const int nchunk = (a.n_refs + kChunk - 1) / kChunk;
     const dim3 grid(unsigned(long(nchunk) * g.batch));
-    const size_t lds = sizeof(float) * 4 * size_t(tile_cap);
+    const size_t lds = sizeof(float) * size_t(kWaves * 2 * wcap + nstage * tile_cap);
     if (a.shrink == BMND_SHRINK_HARD)
         hipLaunchKernelGGL(k_filter_1d<BMND_SHRINK_HARD>, grid, dim3(kWave * kWaves), lds, s, a,
-                           tile_cap, tile_back);
+                           tile_cap, tile_back, wcap);
     else if (a.shrink == BMND_SHRINK_SOFT)
         hipLaunchKernelGGL(k_filter_1d<BMND_SHRINK_SOFT>, grid, dim3(kWave * kWaves), lds, s, a,
-                           tile_cap, tile_back);
+                           tile_cap, tile_back, wcap);
     else
         hipLaunchKernelGGL(k_filter_1d<BMND_SHRINK_WIENER>, grid, dim3(kWave * kWaves), lds, s, a,
-                           tile_cap, tile_back);
+                           tile_cap, tile_back, wcap);
     return hipGetLastError();
 }
 
