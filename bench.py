@@ -25,9 +25,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3     # published FP32 vector peak (packed)
-PEAK_VALU_TOPS = 78.6        # 32-bit VALU ops/s with a multiply-add counted as 2
+PEAK_FP32_TFLOPS = 157.3     # published FP32 peak (vector, packed; dense matrix cores alike)
+PEAK_VALU_TOPS = 78.6        # 32-bit integer VALU ops/s, multiply-add counted as 2:
+                             # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2
 PEAK_HBM_GBS = 8000.0
+# kernels whose contractions run on the matrix cores (v_mfma_f32_16x16x4f32)
+MFMA_KERNELS = {"filter_ht", "filter_wiener"}
+COPY_KERNEL_HINT = "MulFunctor"   # the calibration kernel: dst = src * 1
 
 WORKLOADS = {
     "ecg-1d-batch": dict(shape=(65536,), batch=256, patch=(32,), step=(4,), search=(256,),
@@ -77,6 +81,81 @@ def candidates_per_ref(shape, patch, search, refs):
     return n - 1
 
 
+# kernel name fragments of the library's kernels in rocprofv3 output
+KERNEL_SYMBOLS = {"filter_ht": ("k_filter", "<0>"), "filter_wiener": ("k_filter", "<2>"),
+                  "match_ht": ("k_match", "<0,"), "match_wiener": ("k_match", "<3,")}
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
+
+
+def _kernel_sources_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2609_34622_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def summarize_pmc(dbs, copy_mib: int):
+    """Per-launch FETCH_SIZE / WRITE_SIZE (KiB) of the library kernels and of
+    the calibration copy, scaled to bytes by the copy's known traffic."""
+    import sqlite3
+
+    vals = {}
+    copy_bytes = None
+    for db in dbs:
+        con = sqlite3.connect(db)
+        rows = con.execute("select kernel_name, counter_name, sum(value), count(distinct dispatch_id) "
+                           "from counters_collection group by kernel_name, counter_name").fetchall()
+        grid = con.execute("select kernel_name, max(grid_size) from counters_collection "
+                           "group by kernel_name").fetchall()
+        grid = dict(grid)
+        for kname, cname, total, ndisp in rows:
+            key = None
+            for k, (frag, tmpl) in KERNEL_SYMBOLS.items():
+                if frag in kname and tmpl in kname.replace(" ", ""):
+                    key = k
+            if key is None and COPY_KERNEL_HINT in kname and grid.get(kname, 0) > (1 << 20):
+                key = "copy"
+            if key is None:
+                continue
+            vals.setdefault(key, {})[cname] = float(total) / max(int(ndisp), 1)
+    out = {"kernel_sources": _kernel_sources_digest(), "copy_probe_mib": copy_mib, "kernels": {}}
+    cp = vals.get("copy", {})
+    out["copy_probe_kib"] = cp
+    for k, v in vals.items():
+        if k == "copy":
+            continue
+        out["kernels"][k] = {"fetch_kib": v.get("FETCH_SIZE"), "write_kib": v.get("WRITE_SIZE")}
+    out["note"] = ("scale: bytes = KiB * 1024 * (copy bytes / copy KiB*1024) per counter; "
+                   "copy bytes = --copy-probe-mib MiB read and written")
+    return out
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if absent or taken on other kernel sources."""
+    path = os.path.join(TRAFFIC_DIR, f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_sources") != _kernel_sources_digest():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    cp = t.get("copy_probe_kib", {})
+    mib = t.get("copy_probe_mib")
+    if not k or not cp or not mib or not cp.get("FETCH_SIZE") or not cp.get("WRITE_SIZE"):
+        return None
+    nbytes = mib * (1 << 20)
+    f_scale = nbytes / (cp["FETCH_SIZE"] * 1024.0)
+    w_scale = nbytes / (cp["WRITE_SIZE"] * 1024.0)
+    return round(k["fetch_kib"] * 1024.0 * f_scale + k["write_kib"] * 1024.0 * w_scale)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,7 +164,16 @@ def main():
     ap.add_argument("--workload", default="ecg-1d-batch", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=8,
                     help="arrays of the workload the oracle denoises for cpu_baseline (0: skip)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed region, copy this many MiB device to device once "
+                         "(calibrates HBM byte counters under rocprofv3)")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="DB",
+                    help="summarize rocprofv3 databases (FETCH_SIZE / WRITE_SIZE runs of a "
+                         "--copy-probe-mib bench) into per-launch HBM bytes, print JSON, exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(args.summarize_pmc, args.copy_probe_mib), indent=1))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -163,10 +251,18 @@ def main():
     achieved = flops / (dom_ms * 1e-3) / 1e12
     is_int = work[dom][1].startswith("int32")
     peak = PEAK_VALU_TOPS if is_int else PEAK_FP32_TFLOPS
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
+    roofline = {"bound": "mfma" if dom in MFMA_KERNELS else "alu", "kernel": dom,
+                "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TOP/s" if is_int else "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": None, "avg_ms": round(dom_ms, 4),
+                "traffic": measured_traffic(args.workload, dom), "avg_ms": round(dom_ms, 4),
                 "work_per_launch": flops, "work_unit": work[dom][1]}
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)  # reads and writes n floats once
+        torch.cuda.synchronize()
+        del src, dst
     kernels = {k: {"ms_per_step": round(v[0] / max(args.steps, 1), 4), "launches": v[1]}
                for k, v in prof.items() if v[1]}
 
