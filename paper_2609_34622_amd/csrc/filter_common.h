@@ -12,6 +12,7 @@ struct FilterArgs {
     float s_p, sigma2, lambda, s_v, power_a;
     double s_p64, sigma2_64, lambda64;
     int wmodel, wscope;
+    int kex;       // exact covariance planes (leading Haar planes l < kex)
     int gmax, n_refs;
     int out_mode;  // 0 patches, 1 aggregate f32, 2 mc sweep 1, 3 mc sweep 2
     const float* y;
@@ -36,7 +37,7 @@ bool cube_filter_supported(const Geo& g, int gmax);
 hipError_t launch_filter_cube(const FilterArgs& a, int step_last, hipStream_t s);
 // 32-sample patches (leading patch extents 1), groups of at most 16, filtering
 // launches only (not the aggregate-only entry point)
-bool filter_1d_supported(const Geo& g, int gmax, bool patches_in);
+bool filter_1d_supported(const Geo& g, int gmax, bool patches_in, int kex);
 hipError_t launch_filter_1d(const FilterArgs& a, int step_last, hipStream_t s);
 
 }  // namespace bmnd

@@ -90,7 +90,6 @@ bmnd_status check_stage(const bmnd_geometry* g, const bmnd_stage_params* sp, int
     if (sp->weight_scope != BMND_SCOPE_GROUP && sp->weight_scope != BMND_SCOPE_PATCH)
         return fail(BMND_E_ARG, "unknown weight scope");
     if (sp->k_exact < 0) return fail(BMND_E_ARG, "k_exact must be >= 0");
-    if (sp->k_exact > 0) return fail(BMND_E_UNSUPPORTED, "exact covariance planes not built yet");
     if (!(sp->kaiser_beta >= 0.0)) return fail(BMND_E_ARG, "kaiser_beta must be >= 0");
     return BMND_OK;
 }

@@ -6,6 +6,8 @@
 // j2 x j3 tensor in LDS (member axis slowest).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cfloat>
 #include <climits>
@@ -13,6 +15,7 @@
 
 #include "bmnd_internal.h"
 #include "filter_common.h"
+#include "exact_planes.h"
 #include "match_common.h"
 
 namespace bmnd {
@@ -133,6 +136,30 @@ __device__ __forceinline__ typename ScoreT<MODE>::type score_of(const MatchArgs&
     }
 }
 
+// FP64 score of a float-mode candidate (the re-scored near-ties)
+template <int MODE>
+__device__ inline double score64_of(const MatchArgs& a, const float* src, int r, int c)
+{
+    const Geo& g = a.g;
+    double ssd = 0.0, b = 0.0;
+    for (int i0 = 0; i0 < g.j[0]; ++i0)
+        for (int i1 = 0; i1 < g.j[1]; ++i1)
+            for (int i2 = 0; i2 < g.j[2]; ++i2) {
+                const int o = i0 * g.st[0] + i1 * g.st[1] + i2 * g.st[2];
+                for (int i3 = 0; i3 < g.j[3]; ++i3) {
+                    // separately rounded products and sums (no contraction):
+                    // the plain FP64 sum in patch order
+                    const double p = src[r + o + i3], q = src[c + o + i3];
+                    const double d = __dsub_rn(q, p);
+                    ssd = __dadd_rn(ssd, __dmul_rn(d, d));
+                    if constexpr (MODE == kPoissonF) b = __dadd_rn(b, fmax(__dadd_rn(p, q), 0.0));
+                }
+            }
+    if constexpr (MODE == kPoissonF) return __dsub_rn(ssd, __dmul_rn(a.gamma_sp_d, b));
+    if constexpr (MODE == kGauss) return __dsub_rn(ssd, a.bias_d);
+    return ssd;
+}
+
 template <typename S>
 __device__ __forceinline__ S max_score();
 template <>
@@ -163,8 +190,10 @@ template <int MODE, int GM>
 __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
 {
     using S = typename ScoreT<MODE>::type;
+    constexpr bool kF = MODE != kCount;  // float scores, FP64 near-tie re-scoring
+    using Key = typename std::conditional<kF, double, int>::type;
     constexpr int M = GM > 1 ? GM - 1 : 1;
-    __shared__ int sel_s[M][kMatchThreads];
+    __shared__ Key sel_s[M][kMatchThreads];
     __shared__ int sel_l[M][kMatchThreads];
 
     const Geo& g = a.g;
@@ -186,11 +215,29 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
     }
     ncand -= 1;  // the reference itself is not a candidate
 
+    // magnitude of the terms beside the score (bias, Poisson correction) for
+    // the float-mode tie band: near the K-th value q ~ p, so the correction
+    // is at most about twice the reference's
+    float bmag = 0.f;
+    if constexpr (MODE == kGauss) bmag = fabsf(a.bias);
+    if constexpr (MODE == kPoissonF) {
+        float sp = 0.f;
+        for (int i0 = 0; i0 < g.j[0]; ++i0)
+            for (int i1 = 0; i1 < g.j[1]; ++i1)
+                for (int i2 = 0; i2 < g.j[2]; ++i2)
+                    for (int i3 = 0; i3 < g.j[3]; ++i3)
+                        sp += fmaxf(src[r + i0 * g.st[0] + i1 * g.st[1] + i2 * g.st[2] + i3], 0.f);
+        bmag = 4.f * fabsf(a.gamma_sp) * sp;
+    }
+    auto band = [&](float v) { return float(kTieBand) * (fabsf(v) + bmag); };
+
     // ---- pass 1: accepted count and the M smallest values
     S s[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) s[m] = max_score<S>();
-    int acc = 0;
+    int acc = 0, namb = 0;
+    float tau_band = 0.f;
+    if constexpr (kF) tau_band = band(a.tau_f);
     for (int c0 = lo[0]; c0 <= hi[0]; ++c0)
         for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
             for (int c2 = lo[2]; c2 <= hi[2]; ++c2)
@@ -198,16 +245,43 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
                     const int c = c0 * g.st[0] + c1 * g.st[1] + c2 * g.st[2] + c3;
                     if (c == r) continue;
                     const S x = score_of<MODE>(a, src, kap, r, c);
-                    if constexpr (MODE == kCount) acc += x < a.tau_i;
-                    else acc += x < a.tau_f;
+                    if constexpr (MODE == kCount) {
+                        acc += x < a.tau_i;
+                    } else {
+                        acc += x < a.tau_f;
+                        namb += fabsf(x - a.tau_f) <= tau_band;
+                    }
 #pragma unroll
                     for (int m = M - 1; m >= 1; --m) s[m] = smin(s[m], smax(s[m - 1], x));
                     s[0] = smin(s[0], x);
                 }
 
-    int K = pow2floor(min(1 + acc, a.gmax));
-    K = max(K, a.gmin);
-    K = min(K, pow2floor(1 + ncand));
+    auto group_size = [&](int acc_) {
+        int k = pow2floor(min(1 + acc_, a.gmax));
+        k = max(k, a.gmin);
+        return min(k, pow2floor(1 + ncand));
+    };
+    int K = group_size(acc);
+    if constexpr (kF) {
+        // scores within the band of tau are accepted or not in FP64, when
+        // that can change the group size
+        if (namb > 0 && group_size(acc + namb) != K) {
+            acc = 0;
+            for (int c0 = lo[0]; c0 <= hi[0]; ++c0)
+                for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
+                    for (int c2 = lo[2]; c2 <= hi[2]; ++c2)
+                        for (int c3 = lo[3]; c3 <= hi[3]; ++c3) {
+                            const int c = c0 * g.st[0] + c1 * g.st[1] + c2 * g.st[2] + c3;
+                            if (c == r) continue;
+                            const float x = score_of<MODE>(a, src, kap, r, c);
+                            if (fabsf(x - a.tau_f) <= tau_band)
+                                acc += score64_of<MODE>(a, src, r, c) < a.tau_d;
+                            else
+                                acc += x < a.tau_f;
+                        }
+            K = group_size(acc);
+        }
+    }
     const int need = GM > 1 ? K - 1 : 0;
 
     int* out = a.match + t * a.gmax;
@@ -219,52 +293,80 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
     }
 
     S theta = s[0];
-    int n_less = 0;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         if (m == need - 1) theta = s[m];
     }
-#pragma unroll
-    for (int m = 0; m < M; ++m) n_less += (m < need && s[m] < theta) ? 1 : 0;
-    int eq_left = need - n_less;
 
-    // ---- pass 2: collect the members in lin order
     int got = 0;
-    for (int c0 = lo[0]; c0 <= hi[0] && got < need; ++c0)
-        for (int c1 = lo[1]; c1 <= hi[1] && got < need; ++c1)
-            for (int c2 = lo[2]; c2 <= hi[2] && got < need; ++c2)
-                for (int c3 = lo[3]; c3 <= hi[3] && got < need; ++c3) {
-                    const int c = c0 * g.st[0] + c1 * g.st[1] + c2 * g.st[2] + c3;
-                    if (c == r) continue;
-                    const S x = score_of<MODE>(a, src, kap, r, c);
-                    bool take = x < theta;
-                    if (!take && x == theta && eq_left > 0) {
-                        take = true;
-                        --eq_left;
+    if constexpr (MODE == kCount) {
+        // ---- pass 2 (exact integers): the members below theta and the
+        // first ties at theta, in lin order; then sort by (score, lin)
+        int n_less = 0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) n_less += (m < need && s[m] < theta) ? 1 : 0;
+        int eq_left = need - n_less;
+        for (int c0 = lo[0]; c0 <= hi[0] && got < need; ++c0)
+            for (int c1 = lo[1]; c1 <= hi[1] && got < need; ++c1)
+                for (int c2 = lo[2]; c2 <= hi[2] && got < need; ++c2)
+                    for (int c3 = lo[3]; c3 <= hi[3] && got < need; ++c3) {
+                        const int c = c0 * g.st[0] + c1 * g.st[1] + c2 * g.st[2] + c3;
+                        if (c == r) continue;
+                        const S x = score_of<MODE>(a, src, kap, r, c);
+                        bool take = x < theta;
+                        if (!take && x == theta && eq_left > 0) {
+                            take = true;
+                            --eq_left;
+                        }
+                        if (take) {
+                            sel_s[got][threadIdx.x] = x;
+                            sel_l[got][threadIdx.x] = c;
+                            ++got;
+                        }
                     }
-                    if (take) {
-                        sel_s[got][threadIdx.x] = to_bits(x);
-                        sel_l[got][threadIdx.x] = c;
-                        ++got;
+        for (int m = 1; m < got; ++m) {
+            const int ks = sel_s[m][threadIdx.x], kl = sel_l[m][threadIdx.x];
+            int p = m - 1;
+            while (p >= 0 && sel_s[p][threadIdx.x] > ks) {
+                sel_s[p + 1][threadIdx.x] = sel_s[p][threadIdx.x];
+                sel_l[p + 1][threadIdx.x] = sel_l[p][threadIdx.x];
+                --p;
+            }
+            sel_s[p + 1][threadIdx.x] = ks;
+            sel_l[p + 1][threadIdx.x] = kl;
+        }
+    } else {
+        // ---- pass 2 (float): every candidate up to theta plus the band is
+        // re-scored in FP64 and the best `need` are kept, ordered by (FP64
+        // score, lin); candidates arrive in lin order, so a strict
+        // comparison keeps the lower lin first on equal scores
+        const float thr = float(theta) + band(float(theta));
+        for (int c0 = lo[0]; c0 <= hi[0]; ++c0)
+            for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
+                for (int c2 = lo[2]; c2 <= hi[2]; ++c2)
+                    for (int c3 = lo[3]; c3 <= hi[3]; ++c3) {
+                        const int c = c0 * g.st[0] + c1 * g.st[1] + c2 * g.st[2] + c3;
+                        if (c == r) continue;
+                        const float x = score_of<MODE>(a, src, kap, r, c);
+                        if (!(x <= thr)) continue;
+                        const double xd = score64_of<MODE>(a, src, r, c);
+                        if (!(xd == xd)) continue;
+                        if (got == need && !(xd < sel_s[need - 1][threadIdx.x])) continue;
+                        int p = got < need ? got : need - 1;
+                        while (p > 0 && sel_s[p - 1][threadIdx.x] > xd) {
+                            sel_s[p][threadIdx.x] = sel_s[p - 1][threadIdx.x];
+                            sel_l[p][threadIdx.x] = sel_l[p - 1][threadIdx.x];
+                            --p;
+                        }
+                        sel_s[p][threadIdx.x] = xd;
+                        sel_l[p][threadIdx.x] = c;
+                        if (got < need) ++got;
                     }
-                }
+    }
     // non-finite scores select fewer members than asked: the group is cut to
     // the largest power of two they fill, so every listed member is valid
     if (got < need) K = pow2floor(1 + got);
     a.count[t] = K;
-    // ---- sort the members by (score, lin); insertion keeps lin order on ties
-    for (int m = 1; m < got; ++m) {
-        const int ks = sel_s[m][threadIdx.x], kl = sel_l[m][threadIdx.x];
-        const S kv = from_bits<S>(ks);
-        int p = m - 1;
-        while (p >= 0 && from_bits<S>(sel_s[p][threadIdx.x]) > kv) {
-            sel_s[p + 1][threadIdx.x] = sel_s[p][threadIdx.x];
-            sel_l[p + 1][threadIdx.x] = sel_l[p][threadIdx.x];
-            --p;
-        }
-        sel_s[p + 1][threadIdx.x] = ks;
-        sel_l[p + 1][threadIdx.x] = kl;
-    }
     for (int m = 0; m < K - 1; ++m) out[1 + m] = sel_l[m][threadIdx.x];
 }
 
@@ -390,9 +492,11 @@ __device__ __forceinline__ void patch_coords(const Geo& g, int i, int* c)
 
 // FP64 recomputation of one transform coefficient and its noise variance
 // (hard-threshold decisions within the FP32 error band of lambda sigma).
+template <bool EXACT>
 __device__ bool rescue_keep(const FilterArgs& a, const float* yb, const float* mvsrc, int K,
                             const int* org, const int* off, int l, int qidx, double* red)
 {
+    const bool exact = EXACT && l < a.kex;  // exact shared-source plane
     const Geo& g = a.g;
     int q[kAx];
     patch_coords(g, qidx, q);
@@ -415,13 +519,17 @@ __device__ bool rescue_keep(const FilterArgs& a, const float* yb, const float* m
         double mv;
         if (a.noise == BMND_NOISE_POISSON) mv = a.s_p64 * fmax(double(mvsrc[u]), 0.0);
         else mv = a.sigma2_64;
-        sv += w * w * mv;
+        if (!exact) sv += w * w * mv;
+    }
+    if constexpr (EXACT) {
+        if (exact) sv = exact_partial(a, mvsrc, org, K, l, qidx, threadIdx.x, kFilterThreads);
     }
     double v;
     const double Y = block_sum2(red, sy, sv, &v);
     return fabs(Y) > a.lambda64 * sqrt(v) * (1.0 + kTieRel);
 }
 
+template <bool EXACT>
 __global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -532,6 +640,12 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
             for (int e = threadIdx.x; e < n; e += kFilterThreads) Vb[e] = Vc[e];
             __syncthreads();
         }
+        // exact shared-source variances of the leading planes
+        if constexpr (EXACT) {
+            const int kex = min(a.kex, K);
+            exact_plane_variances(a, mvsrc, org, K, kex, Vb, threadIdx.x, kFilterThreads);
+            __syncthreads();
+        }
         if (a.stage == BMND_STAGE_WIENER) {
             float* Gc = apply_separable(B, Tb, gs, H, spT);
             if (Gc != B) {
@@ -591,7 +705,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
             for (int k = 0; k < nres; ++k) {
                 const int e = rescue[k];
                 const int l = e / P;
-                const bool keep = rescue_keep(a, yb, yb, K, org, off, l, e - l * P, red);
+                const bool keep = rescue_keep<EXACT>(a, yb, yb, K, org, off, l, e - l * P, red);
                 if (threadIdx.x == 0) Tb[e] = keep ? 1.f : 0.f;
                 __syncthreads();
             }
@@ -794,6 +908,7 @@ hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* ps
     if (c.stage == BMND_STAGE_WIENER) {
         mode = kPlain;
         a.tau_f = float(c.tau);
+        a.tau_d = c.tau;
     } else if (c.integral) {
         mode = kCount;
         a.gamma_i = int(c.gamma);
@@ -806,11 +921,15 @@ hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* ps
     } else if (c.noise == BMND_NOISE_POISSON) {
         mode = kPoissonF;
         a.gamma_sp = float(c.gamma * c.s_p);
+        a.gamma_sp_d = c.gamma * c.s_p;
         a.tau_f = float(c.tau);
+        a.tau_d = c.tau;
     } else {
         mode = kGauss;
-        a.bias = float(c.gamma * 2.0 * c.g.P * c.sigma * c.sigma);
+        a.bias_d = c.gamma * 2.0 * c.g.P * c.sigma * c.sigma;
+        a.bias = float(a.bias_d);
         a.tau_f = float(c.tau);
+        a.tau_d = c.tau;
     }
     if (match_1d_supported(c.g, mode))
         return launch_match_1d(a, mode, c.step_last, count_limit(c), s);
@@ -844,6 +963,7 @@ static FilterArgs filter_args(const StageCfg& c, const DevTables& t, int out_mod
     a.lambda64 = c.lambda;
     a.wmodel = c.wmodel;
     a.wscope = c.wscope;
+    a.kex = c.k_exact;
     a.gmax = c.gmax;
     a.out_mode = out_mode;
     a.t = t;
@@ -851,6 +971,21 @@ static FilterArgs filter_args(const StageCfg& c, const DevTables& t, int out_mod
 }
 
 size_t filter_lds_bytes(const Geo& g, int gmax) { return FilterLds(g, gmax).bytes; }
+
+static hipError_t launch_generic_filter(const FilterArgs& a, size_t lds, long groups, hipStream_t s)
+{
+    const void* fn = a.kex > 0 ? reinterpret_cast<const void*>(&k_filter<true>)
+                               : reinterpret_cast<const void*>(&k_filter<false>);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    if (a.kex > 0)
+        hipLaunchKernelGGL(k_filter<true>, dim3(unsigned(groups)), dim3(kFilterThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_filter<false>, dim3(unsigned(groups)), dim3(kFilterThreads), lds, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
                          const float* pilot, int n_refs, const int* match, const int* count,
@@ -869,16 +1004,9 @@ hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, co
     a.numd = static_cast<double*>(num);
     a.dend = static_cast<double*>(den);
     const long groups = long(c.g.batch) * n_refs;
-    if (filter_1d_supported(c.g, c.gmax, false)) return launch_filter_1d(a, c.step_last, s);
+    if (filter_1d_supported(c.g, c.gmax, false, c.k_exact)) return launch_filter_1d(a, c.step_last, s);
     if (cube_filter_supported(c.g, c.gmax)) return launch_filter_cube(a, c.step_last, s);
-    const size_t lds = FilterLds(c.g, c.gmax).bytes;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_filter, dim3(unsigned(groups)), dim3(kFilterThreads), lds, s, a);
-    return hipGetLastError();
+    return launch_generic_filter(a, FilterLds(c.g, c.gmax).bytes, groups, s);
 }
 
 hipError_t launch_aggregate(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
@@ -898,14 +1026,7 @@ hipError_t launch_aggregate(const StageCfg& c, const DevTables& t, int out_mode,
     a.dend = static_cast<double*>(den);
     const long groups = long(c.g.batch) * n_refs;
     if (cube_filter_supported(c.g, c.gmax)) return launch_filter_cube(a, c.step_last, s);
-    const size_t lds = FilterLds(c.g, c.gmax).bytes;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_filter, dim3(unsigned(groups)), dim3(kFilterThreads), lds, s, a);
-    return hipGetLastError();
+    return launch_generic_filter(a, FilterLds(c.g, c.gmax).bytes, groups, s);
 }
 
 hipError_t launch_normalize(const StageCfg& c, const void* num, const void* den, float* out,

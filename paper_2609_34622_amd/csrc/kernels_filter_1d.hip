@@ -572,9 +572,9 @@ void k_filter_1d(FilterArgs a, int tile_cap, int tile_back, int wcap)
 
 }  // namespace
 
-bool filter_1d_supported(const Geo& g, int gmax, bool patches_in)
+bool filter_1d_supported(const Geo& g, int gmax, bool patches_in, int kex)
 {
-    return !patches_in && g.j[0] == 1 && g.j[1] == 1 && g.j[2] == 1 && g.j[kAx - 1] == kJ &&
+    return !patches_in && kex == 0 && g.j[0] == 1 && g.j[1] == 1 && g.j[2] == 1 && g.j[kAx - 1] == kJ &&
            gmax <= 16;
 }
 

@@ -14,6 +14,7 @@
 
 #include "bmnd_internal.h"
 #include "filter_common.h"
+#include "exact_planes.h"
 
 namespace bmnd {
 
@@ -249,7 +250,7 @@ __device__ __forceinline__ double haar64(int K, int l, int j)
 template <int KP>
 constexpr int waves_for() { return KP <= 512 ? 4 : (KP <= 1024 ? 2 : 1); }
 
-template <int D, int J, int GM>
+template <int D, int J, int GM, bool EXACT>
 __global__ __launch_bounds__(kWave * waves_for<GM * ipow_c(J, D)>())
 void k_filter_cube(FilterArgs a, int chunk_refs, int tile_cap, int tile_back)
 {
@@ -364,6 +365,12 @@ void k_filter_cube(FilterArgs a, int chunk_refs, int tile_cap, int tile_back)
                 }
             }
             haar_arrays<GM, P>(A, Vb, Bb, wiener ? 3 : 2, false, K);
+            // exact shared-source variances of the leading planes
+            const int kex = EXACT ? min(a.kex, K) : 0;
+            if constexpr (EXACT) {
+                exact_plane_variances(a, mvsrc, org, K, kex, Vb, lane, kWave);
+                wsync();
+            }
 
             // ---- shrinkage and per-plane risk surrogates
             for (int e = lane; e < n; e += kWave) {
@@ -438,6 +445,9 @@ void k_filter_cube(FilterArgs a, int chunk_refs, int tile_cap, int tile_back)
                                               ? a.s_p64 * fmax(double(yb[u]), 0.0)
                                               : a.sigma2_64;
                         sv += w * w * mv;
+                    }
+                    if constexpr (EXACT) {
+                        if (l < kex) sv = exact_partial(a, yb, org, K, l, e - l * P, lane, kWave);
                     }
                     sy = wave_sum64(sy);
                     sv = wave_sum64(sv);
@@ -569,7 +579,12 @@ hipError_t launch_cube_gm(const FilterArgs& a, int step_last, hipStream_t s)
     const dim3 grid(unsigned(long(nchunk) * g.batch));
     const size_t lds = sizeof(float) * 2 * size_t(tile_cap);
 #define BMND_CUBE_LAUNCH(GMV)                                                              \
-    hipLaunchKernelGGL((k_filter_cube<D, J, GMV>),                                          \
+    if (a.kex > 0)                                                                          \
+        hipLaunchKernelGGL((k_filter_cube<D, J, GMV, true>),                                \
+                           dim3(grid), dim3(kWave * waves_for<GMV * ipow_c(J, D)>()), lds, s, a, \
+                           chunk, tile_cap, tile_back);                                     \
+    else                                                                                    \
+    hipLaunchKernelGGL((k_filter_cube<D, J, GMV, false>),                                   \
                        dim3(grid), dim3(kWave * waves_for<GMV * ipow_c(J, D)>()), lds, s, a, \
                        chunk, tile_cap, tile_back)
     switch (a.gmax) {

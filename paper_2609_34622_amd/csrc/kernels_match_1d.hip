@@ -17,6 +17,7 @@
 
 #include <cfloat>
 #include <climits>
+#include <type_traits>
 
 #include "bmnd_internal.h"
 #include "match_common.h"
@@ -67,13 +68,34 @@ __device__ __forceinline__ typename Sc<MODE>::T ssd_lds(const typename Sc<MODE>:
     return s;
 }
 
+// FP64 score of a float-mode candidate (re-scored near-ties), summed in the
+// same order
+template <int MODE>
+__device__ __forceinline__ double score64_lds(const MatchArgs& a, const float* rp, const int* sx,
+                                              int c)
+{
+    // separately rounded products and sums (no contraction), so the value
+    // is the plain FP64 sum in patch order
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kJ; ++i) {
+        const double d = __dsub_rn(double(__int_as_float(sx[c + i])), double(rp[i]));
+        s = __dadd_rn(s, __dmul_rn(d, d));
+    }
+    if constexpr (MODE == kGauss) s = __dsub_rn(s, a.bias_d);
+    return s;
+}
+
 template <int MODE, int GM>
-__global__ __launch_bounds__(kWave) void k_match_1d(MatchArgs a, int cap_span, int kmax)
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3)))
+void k_match_1d(MatchArgs a, int cap_span, int kmax)
 {
     using S = typename Sc<MODE>::T;
+    constexpr bool kF = MODE != kCount;  // float scores, FP64 near-tie re-scoring
+    using Key = typename std::conditional<kF, double, int>::type;
     constexpr int M = GM > 1 ? GM - 1 : 1;
     extern __shared__ __align__(16) int sx[];   // staged samples
-    __shared__ int sel_s[M][kWave];
+    __shared__ Key sel_s[M][kWave];
     __shared__ int sel_l[M][kWave];
     __shared__ unsigned char rec[kRec][kWave];
 
@@ -135,7 +157,11 @@ __global__ __launch_bounds__(kWave) void k_match_1d(MatchArgs a, int cap_span, i
             S s[M];
 #pragma unroll
             for (int m = 0; m < M; ++m) s[m] = big<S>();
-            int acc = 0, nrec = 0;
+            int acc = 0, nrec = 0, namb = 0;
+            // float modes: band of FP32 round-off around a value (relative
+            // to the score's terms; the Gaussian bias is one of them)
+            const float bmag = MODE == kGauss ? fabsf(a.bias) : 0.f;
+            const float tau_band = float(kTieBand) * (fabsf(a.tau_f) + bmag);
             for (int d0 = wlo; d0 <= whi; d0 += kJ) {
                 S buf[2 * kJ];
 #pragma unroll
@@ -162,9 +188,16 @@ __global__ __launch_bounds__(kWave) void k_match_1d(MatchArgs a, int cap_span, i
                         x -= a.bias;
                     }
                     if (d >= dlo && d <= dhi && d != 0) {
-                        if constexpr (MODE == kCount) acc += x < a.tau_i;
-                        else acc += x < a.tau_f;
-                        if (x <= s[M - 1]) {
+                        if constexpr (MODE == kCount) {
+                            acc += x < a.tau_i;
+                        } else {
+                            acc += x < a.tau_f;
+                            namb += fabsf(x - a.tau_f) <= tau_band;
+                        }
+                        bool rec_it;
+                        if constexpr (MODE == kCount) rec_it = x <= s[M - 1];
+                        else rec_it = x <= s[M - 1] + float(kTieBand) * (fabsf(s[M - 1]) + bmag);
+                        if (rec_it) {
                             if (nrec < kRec) rec[nrec][lane] = (unsigned char)(d - wlo);
                             ++nrec;
                         }
@@ -175,9 +208,29 @@ __global__ __launch_bounds__(kWave) void k_match_1d(MatchArgs a, int cap_span, i
                 }
             }
 
-            int K = p2floor(min(1 + acc, a.gmax));
-            K = max(K, a.gmin);
-            K = min(K, p2floor(1 + ncand));
+            auto group_size = [&](int acc_) {
+                int k = p2floor(min(1 + acc_, a.gmax));
+                k = max(k, a.gmin);
+                return min(k, p2floor(1 + ncand));
+            };
+            int K = group_size(acc);
+            if constexpr (kF) {
+                // scores within the band of tau are accepted or not in FP64,
+                // when that can change the group size
+                if (namb > 0 && group_size(acc + namb) != K) {
+                    acc = 0;
+                    for (int d = dlo; d <= dhi; ++d) {
+                        if (d == 0) continue;
+                        S x = ssd_lds<MODE>(rp, sx, rl + d);
+                        if constexpr (MODE == kGauss) x -= a.bias;
+                        if (fabsf(x - a.tau_f) <= tau_band)
+                            acc += score64_lds<MODE>(a, rp, sx, rl + d) < a.tau_d;
+                        else
+                            acc += x < a.tau_f;
+                    }
+                    K = group_size(acc);
+                }
+            }
             const int need = GM > 1 ? K - 1 : 0;
             int* out = a.match + t * a.gmax;
             out[0] = r;
@@ -188,53 +241,79 @@ __global__ __launch_bounds__(kWave) void k_match_1d(MatchArgs a, int cap_span, i
 #pragma unroll
                 for (int m = 0; m < M; ++m)
                     if (m == need - 1) theta = s[m];
-                int n_less = 0;
-#pragma unroll
-                for (int m = 0; m < M; ++m) n_less += (m < need && s[m] < theta) ? 1 : 0;
-                int eq_left = need - n_less;
                 int got = 0;
-                auto consider = [&](int d) {
-                    S x = ssd_lds<MODE>(rp, sx, rl + d);
-                    if constexpr (MODE == kCount) {
+                if constexpr (MODE == kCount) {
+                    int n_less = 0;
+#pragma unroll
+                    for (int m = 0; m < M; ++m) n_less += (m < need && s[m] < theta) ? 1 : 0;
+                    int eq_left = need - n_less;
+                    auto consider = [&](int d) {
+                        S x = ssd_lds<MODE>(rp, sx, rl + d);
                         int sc2 = 0;
                         for (int i = 0; i < kJ; ++i) sc2 += sx[rl + d + i];
                         x -= a.gamma_i * (sr + sc2);
-                    } else if constexpr (MODE == kGauss) {
-                        x -= a.bias;
+                        bool take = x < theta;
+                        if (!take && x == theta && eq_left > 0) {
+                            take = true;
+                            --eq_left;
+                        }
+                        if (take) {
+                            sel_s[got][lane] = x;
+                            sel_l[got][lane] = r + d;
+                            ++got;
+                        }
+                    };
+                    if (nrec <= kRec) {
+                        for (int k = 0; k < nrec && got < need; ++k) consider(int(rec[k][lane]) + wlo);
+                    } else {
+                        for (int d = dlo; d <= dhi && got < need; ++d)
+                            if (d != 0) consider(d);
                     }
-                    bool take = x < theta;
-                    if (!take && x == theta && eq_left > 0) {
-                        take = true;
-                        --eq_left;
+                    for (int m = 1; m < got; ++m) {
+                        const int ks = sel_s[m][lane], kl = sel_l[m][lane];
+                        int p = m - 1;
+                        while (p >= 0 && sel_s[p][lane] > ks) {
+                            sel_s[p + 1][lane] = sel_s[p][lane];
+                            sel_l[p + 1][lane] = sel_l[p][lane];
+                            --p;
+                        }
+                        sel_s[p + 1][lane] = ks;
+                        sel_l[p + 1][lane] = kl;
                     }
-                    if (take) {
-                        sel_s[got][lane] = as_bits(x);
-                        sel_l[got][lane] = r + d;
-                        ++got;
-                    }
-                };
-                if (nrec <= kRec) {
-                    for (int k = 0; k < nrec && got < need; ++k) consider(int(rec[k][lane]) + wlo);
                 } else {
-                    for (int d = dlo; d <= dhi && got < need; ++d)
-                        if (d != 0) consider(d);
+                    // every candidate up to theta plus the band is re-scored
+                    // in FP64; the best `need` are kept by (FP64 score, lin)
+                    // (candidates arrive in lin order, a strict comparison
+                    // keeps the lower lin first on equal scores)
+                    const float thr = theta + float(kTieBand) * (fabsf(theta) + bmag);
+                    auto consider = [&](int d) {
+                        S x = ssd_lds<MODE>(rp, sx, rl + d);
+                        if constexpr (MODE == kGauss) x -= a.bias;
+                        if (!(x <= thr)) return;
+                        const double xd = score64_lds<MODE>(a, rp, sx, rl + d);
+                        if (!(xd == xd)) return;
+                        if (got == need && !(xd < sel_s[need - 1][lane])) return;
+                        int p = got < need ? got : need - 1;
+                        while (p > 0 && sel_s[p - 1][lane] > xd) {
+                            sel_s[p][lane] = sel_s[p - 1][lane];
+                            sel_l[p][lane] = sel_l[p - 1][lane];
+                            --p;
+                        }
+                        sel_s[p][lane] = xd;
+                        sel_l[p][lane] = r + d;
+                        if (got < need) ++got;
+                    };
+                    if (nrec <= kRec) {
+                        for (int k = 0; k < nrec; ++k) consider(int(rec[k][lane]) + wlo);
+                    } else {
+                        for (int d = dlo; d <= dhi; ++d)
+                            if (d != 0) consider(d);
+                    }
                 }
                 // non-finite scores select fewer members than asked: the
                 // group is cut to the largest power of two they fill
                 if (got < need) K = p2floor(1 + got);
                 a.count[t] = K;
-                for (int m = 1; m < got; ++m) {
-                    const int ks = sel_s[m][lane], kl = sel_l[m][lane];
-                    const S kv = from_bits<S>(ks);
-                    int p = m - 1;
-                    while (p >= 0 && from_bits<S>(sel_s[p][lane]) > kv) {
-                        sel_s[p + 1][lane] = sel_s[p][lane];
-                        sel_l[p + 1][lane] = sel_l[p][lane];
-                        --p;
-                    }
-                    sel_s[p + 1][lane] = ks;
-                    sel_l[p + 1][lane] = kl;
-                }
                 for (int m = 0; m < K - 1; ++m) out[1 + m] = sel_l[m][lane];
             }
         }

@@ -25,7 +25,16 @@ struct MatchArgs {
     float tau_f;         // float modes: accept iff score < tau_f
     float inv_sp;        // 1 / s_P
     int* range_flag;     // set when a count leaves the exact int32 range
+    // float modes: FP64 twins of the constants for the re-scored near-ties
+    double tau_d, bias_d, gamma_sp_d;
 };
+
+// Float-mode scores within this relative band of the K-th value or of tau
+// (relative to the magnitude of the terms) are re-scored in FP64, which
+// decides membership, order and acceptance exactly as an FP64 evaluation
+// would; FP32 round-off of a 32- to 64-term sum of squares stays below
+// 1e-6 of the term magnitude.
+constexpr double kTieBand = 1e-5;
 
 bool match_1d_supported(const Geo& g, int mode);
 hipError_t launch_match_1d(const MatchArgs& a, int mode, int step, int kmax, hipStream_t s);

@@ -187,6 +187,9 @@ def test_wiener_match_filter_2d(img):
     bad = check_wiener_lists(pil32.astype(np.float64), img["shape"], img["patch"],
                              img["wie"].cfg(1).tau, mg[0], cg[0], mo, co, so)
     assert bad == 0
+    # near-ties are re-scored in FP64 on the GPU: the lists are identical
+    assert np.array_equal(cg[0], co)
+    assert np.array_equal(mg[0], mo)
     pg, wg = gpu_filter(B.STAGE_WIENER, y, pil, img["geom"], img["noise"], img["p"].wiener, mg, cg)
     po, wo = O.filter(img["wie"], O.STAGE_WIENER, s.y, pil32, mg[0], cg[0])
     for g in range(len(cg[0])):
@@ -397,3 +400,139 @@ def test_denoise_1d_variants(case):
         assert rel_err(pilot[b], pil_o) < REL_OUT, b
         out_r = O.run_stage(wie, O.STAGE_WIENER, y[b], pilot[b].astype(np.float64))
         assert rel_err(out[b], out_r) < REL_OUT, b
+
+
+# ------------------------------------------- standard profile (exact planes)
+
+def std_params(shape, patch, step, search, group=(16, 32)):
+    p = B.bmnd_params_default(B.PRESET_STANDARD, len(shape))
+    for sp in (p.ht, p.wiener):
+        B.set_axes(sp, patch=patch, step=step, search=search)
+    p.ht.group_max, p.wiener.group_max = group
+    return p
+
+
+def test_standard_profile_stagewise_2d(img):
+    _say("standard profile stage-wise 128x128")
+    s = img["s"]
+    shape, patch = img["shape"], img["patch"]
+    p = std_params(shape, patch, (3, 3), (39, 39))
+    assert p.ht.k_exact == 4 and p.wiener.k_exact == 4
+    ht, wie = O.standard_profile(shape, patch, (3, 3), (39, 39), s_p=s.s_p)
+    y = dev(s.y)
+    mg, cg = gpu_match(B.STAGE_HT, y, img["geom"], img["noise"], p.ht, img["refs"])
+    pg, wg = gpu_filter(B.STAGE_HT, y, None, img["geom"], img["noise"], p.ht, mg, cg)
+    po, wo = O.filter(ht, O.STAGE_HT, s.y, None, mg[0], cg[0])
+    for g in range(len(cg[0])):
+        K = cg[0][g]
+        scale = max(np.abs(po[g, :K]).max(), 1e-30)
+        assert np.abs(pg[0, g, :K] - po[g, :K]).max() <= REL_PATCH * scale, g
+        assert np.allclose(wg[0, g, :K], wo[g, :K], rtol=2e-5), g
+    _say("standard profile Wiener filter 128x128")
+    pil32 = O.run_stage(ht, O.STAGE_HT, s.y).astype(np.float32)
+    pil = dev(pil32)
+    mg, cg = gpu_match(B.STAGE_WIENER, pil, img["geom"], img["noise"], p.wiener, img["refs"])
+    pg, wg = gpu_filter(B.STAGE_WIENER, y, pil, img["geom"], img["noise"], p.wiener, mg, cg)
+    po, wo = O.filter(wie, O.STAGE_WIENER, s.y, pil32, mg[0], cg[0])
+    for g in range(len(cg[0])):
+        K = cg[0][g]
+        scale = max(np.abs(po[g, :K]).max(), 1e-30)
+        assert np.abs(pg[0, g, :K] - po[g, :K]).max() <= REL_PATCH * scale, g
+        assert np.allclose(wg[0, g, :K], wo[g, :K], rtol=2e-5), g
+
+
+def test_standard_profile_end_to_end_2d(img):
+    _say("standard profile denoise 128x128")
+    s = img["s"]
+    shape, patch = img["shape"], img["patch"]
+    p = std_params(shape, patch, (3, 3), (39, 39))
+    ht, wie = O.standard_profile(shape, patch, (3, 3), (39, 39), s_p=s.s_p)
+    out, pilot = gpu_denoise(dev(s.y), img["geom"], img["noise"], p)
+    pil_o, out_o = O.denoise(ht, wie, s.y)
+    assert rel_err(pilot, pil_o) < REL_OUT
+    out_r = O.run_stage(wie, O.STAGE_WIENER, s.y, pilot.astype(np.float64))
+    assert rel_err(out, out_r) < REL_OUT
+    err = np.abs(out.astype(np.float64) - out_o) / np.abs(out_o).max()
+    if err.max() >= REL_OUT:
+        mask, flips = flip_mask(wie, shape, patch, img["refs"], s.y, pil_o,
+                                pilot.astype(np.float64))
+        _say(f"end-to-end max rel err {err.max():.2e}, {flips} flipped Wiener groups")
+        assert flips > 0
+        assert err[~mask].max() < REL_OUT
+
+
+STANDARD_SHAPES = [
+    # shape, patch, step, search, group, batch
+    ((3000,), (32,), (4,), (64,), (16, 16), 2),
+    ((16, 14, 12), (4, 4, 4), (3, 3, 3), (5, 5, 5), (16, 32), 1),
+    ((30, 26), (4, 6), (2, 3), (9, 7), (8, 16), 1),
+]
+
+
+@pytest.mark.parametrize("case", STANDARD_SHAPES, ids=lambda c: "x".join(map(str, c[0])))
+def test_standard_profile_shapes(case):
+    shape, patch, step, search, group, batch = case
+    _say(f"standard profile {case}")
+    if len(shape) == 1:
+        s = synth.ecg_batch(n_signals=batch, length=shape[0], seed=2200)
+        ys, s_p = s.y, s.s_p
+    else:
+        rng = np.random.default_rng(31)
+        lam = 1.0 + 9.0 * rng.uniform(size=(batch,) + shape)
+        lam[..., : shape[-1] // 2] *= 0.3
+        s_p = 0.1
+        ys = (rng.poisson(lam) * s_p).astype(np.float32)
+    p = std_params(shape, patch, step, search, group)
+    ht, wie = O.standard_profile(shape, patch, step, search, s_p=s_p, group=group)
+    ht.group_min, wie.group_min = p.ht.group_min, p.wiener.group_min
+    out, pilot = gpu_denoise(dev(ys), B.geometry(shape, batch=batch), B.poisson(s_p), p)
+    for b in range(batch):
+        pil_o = O.run_stage(ht, O.STAGE_HT, ys[b])
+        assert rel_err(pilot[b], pil_o) < REL_OUT, b
+        out_r = O.run_stage(wie, O.STAGE_WIENER, ys[b], pilot[b].astype(np.float64))
+        assert rel_err(out[b], out_r) < REL_OUT, b
+
+
+# ------------------------------------------ float-mode matching: exact lists
+
+FLOAT_MATCH = [
+    # shape, patch, step, search, stage, noise
+    ((6000,), (32,), (4,), (256,), "wiener", "poisson"),
+    ((6000,), (32,), (4,), (256,), "ht", "gaussian"),
+    ((40, 36), (8, 8), (3, 3), (15, 15), "ht", "gaussian"),
+    ((40, 36), (8, 8), (3, 3), (15, 15), "ht", "poisson-nonintegral"),
+    ((12, 11, 10), (4, 4, 4), (3, 3, 3), (5, 5, 5), "wiener", "poisson"),
+]
+
+
+@pytest.mark.parametrize("case", FLOAT_MATCH, ids=lambda c: "x".join(map(str, c[0])) + "-" + c[4] + "-" + c[5])
+def test_float_match_lists_identical(case):
+    shape, patch, step, search, stage, noise_kind = case
+    _say(f"float-mode matching {case}")
+    rng = np.random.default_rng(44)
+    if len(shape) == 1:
+        src = synth.ecg_batch(n_signals=1, length=shape[0], seed=2300).x[0]
+    else:
+        src = synth.image_2d_small(1007, size=64).x[: shape[0], : shape[1]] if len(shape) == 2 \
+            else rng.uniform(0.2, 1.0, size=shape)
+    src = (np.asarray(src, np.float64) + rng.normal(0, 0.05, shape)).astype(np.float32)
+    st_id = B.STAGE_WIENER if stage == "wiener" else B.STAGE_HT
+    gm = 16
+    p = params_for(shape, patch, step, search, group=(gm, gm))
+    sp = p.wiener if stage == "wiener" else p.ht
+    ht, wie = oracle_stages(shape, patch, step, search, 0.02, group=(gm, gm))
+    st_o = wie if stage == "wiener" else ht
+    if noise_kind == "gaussian":
+        noise = B.gaussian(0.05)
+        st_o.noise, st_o.sigma = "gaussian", 0.05
+    elif noise_kind == "poisson-nonintegral":
+        noise = B.poisson(0.02, counts_integral=False)
+        st_o.counts_integral = False
+    else:
+        noise = B.poisson(0.02)
+    geom = B.geometry(shape)
+    refs = B.bmnd_reference_origins(geom, sp)
+    mg, cg = gpu_match(st_id, dev(src), geom, noise, sp, refs)
+    mo, co, _, _ = O.match(st_o, O.STAGE_WIENER if stage == "wiener" else O.STAGE_HT, src, src, refs)
+    assert np.array_equal(cg[0], co)
+    assert np.array_equal(mg[0], mo)
