@@ -231,10 +231,13 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
     }
     auto band = [&](float v) { return float(kTieBand) * (fabsf(v) + bmag); };
 
-    // ---- pass 1: accepted count and the M smallest values
-    S s[M];
+    // ---- pass 1: accepted count and the M smallest values (in float modes
+    // one more: the value after the K-th tells whether the K-th boundary is
+    // a near-tie)
+    constexpr int NS = kF ? M + 1 : M;
+    S s[NS];
 #pragma unroll
-    for (int m = 0; m < M; ++m) s[m] = max_score<S>();
+    for (int m = 0; m < NS; ++m) s[m] = max_score<S>();
     int acc = 0, namb = 0;
     float tau_band = 0.f;
     if constexpr (kF) tau_band = band(a.tau_f);
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
                         namb += fabsf(x - a.tau_f) <= tau_band;
                     }
 #pragma unroll
-                    for (int m = M - 1; m >= 1; --m) s[m] = smin(s[m], smax(s[m - 1], x));
+                    for (int m = NS - 1; m >= 1; --m) s[m] = smin(s[m], smax(s[m - 1], x));
                     s[0] = smin(s[0], x);
                 }
 
@@ -292,16 +295,17 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
         return;
     }
 
-    S theta = s[0];
+    S theta = s[0], next = s[0];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
+    for (int m = 0; m < NS; ++m) {
         if (m == need - 1) theta = s[m];
+        if (m == need) next = s[m];
     }
 
+    // ---- pass 2: the members below theta and the first ties at theta, in
+    // lin order; then sorted by (score, lin)
     int got = 0;
-    if constexpr (MODE == kCount) {
-        // ---- pass 2 (exact integers): the members below theta and the
-        // first ties at theta, in lin order; then sort by (score, lin)
+    {
         int n_less = 0;
 #pragma unroll
         for (int m = 0; m < M; ++m) n_less += (m < need && s[m] < theta) ? 1 : 0;
@@ -319,13 +323,14 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
                             --eq_left;
                         }
                         if (take) {
-                            sel_s[got][threadIdx.x] = x;
+                            sel_s[got][threadIdx.x] = Key(x);
                             sel_l[got][threadIdx.x] = c;
                             ++got;
                         }
                     }
         for (int m = 1; m < got; ++m) {
-            const int ks = sel_s[m][threadIdx.x], kl = sel_l[m][threadIdx.x];
+            const Key ks = sel_s[m][threadIdx.x];
+            const int kl = sel_l[m][threadIdx.x];
             int p = m - 1;
             while (p >= 0 && sel_s[p][threadIdx.x] > ks) {
                 sel_s[p + 1][threadIdx.x] = sel_s[p][threadIdx.x];
@@ -335,33 +340,45 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
             sel_s[p + 1][threadIdx.x] = ks;
             sel_l[p + 1][threadIdx.x] = kl;
         }
-    } else {
-        // ---- pass 2 (float): every candidate up to theta plus the band is
-        // re-scored in FP64 and the best `need` are kept, ordered by (FP64
-        // score, lin); candidates arrive in lin order, so a strict
-        // comparison keeps the lower lin first on equal scores
-        const float thr = float(theta) + band(float(theta));
-        for (int c0 = lo[0]; c0 <= hi[0]; ++c0)
-            for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
-                for (int c2 = lo[2]; c2 <= hi[2]; ++c2)
-                    for (int c3 = lo[3]; c3 <= hi[3]; ++c3) {
-                        const int c = c0 * g.st[0] + c1 * g.st[1] + c2 * g.st[2] + c3;
-                        if (c == r) continue;
-                        const float x = score_of<MODE>(a, src, kap, r, c);
-                        if (!(x <= thr)) continue;
-                        const double xd = score64_of<MODE>(a, src, r, c);
-                        if (!(xd == xd)) continue;
-                        if (got == need && !(xd < sel_s[need - 1][threadIdx.x])) continue;
-                        int p = got < need ? got : need - 1;
-                        while (p > 0 && sel_s[p - 1][threadIdx.x] > xd) {
-                            sel_s[p][threadIdx.x] = sel_s[p - 1][threadIdx.x];
-                            sel_l[p][threadIdx.x] = sel_l[p - 1][threadIdx.x];
-                            --p;
+    }
+    if constexpr (kF) {
+        // The FP32 ranking equals the FP64 one unless the value after the
+        // K-th, or two neighbours in the list, lie within the round-off band
+        // (equal zeros are exact).  Otherwise every candidate up to theta
+        // plus the band is re-scored in FP64 and the best `need` are kept by
+        // (FP64 score, lin); candidates arrive in lin order, so a strict
+        // comparison keeps the lower lin first on equal scores.
+        auto near = [&](float lo_, float hi_) {
+            return hi_ - lo_ <= band(hi_) && !(lo_ == 0.f && hi_ == 0.f);
+        };
+        bool amb = got == need && near(float(theta), float(next));
+        for (int m = 1; m < got; ++m)
+            amb = amb || near(float(sel_s[m - 1][threadIdx.x]), float(sel_s[m][threadIdx.x]));
+        if (amb) {
+            got = 0;
+            const float thr = float(theta) + band(float(theta));
+            for (int c0 = lo[0]; c0 <= hi[0]; ++c0)
+                for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
+                    for (int c2 = lo[2]; c2 <= hi[2]; ++c2)
+                        for (int c3 = lo[3]; c3 <= hi[3]; ++c3) {
+                            const int c = c0 * g.st[0] + c1 * g.st[1] + c2 * g.st[2] + c3;
+                            if (c == r) continue;
+                            const float x = score_of<MODE>(a, src, kap, r, c);
+                            if (!(x <= thr)) continue;
+                            const double xd = score64_of<MODE>(a, src, r, c);
+                            if (!(xd == xd)) continue;
+                            if (got == need && !(xd < sel_s[need - 1][threadIdx.x])) continue;
+                            int p = got < need ? got : need - 1;
+                            while (p > 0 && sel_s[p - 1][threadIdx.x] > xd) {
+                                sel_s[p][threadIdx.x] = sel_s[p - 1][threadIdx.x];
+                                sel_l[p][threadIdx.x] = sel_l[p - 1][threadIdx.x];
+                                --p;
+                            }
+                            sel_s[p][threadIdx.x] = xd;
+                            sel_l[p][threadIdx.x] = c;
+                            if (got < need) ++got;
                         }
-                        sel_s[p][threadIdx.x] = xd;
-                        sel_l[p][threadIdx.x] = c;
-                        if (got < need) ++got;
-                    }
+        }
     }
     // non-finite scores select fewer members than asked: the group is cut to
     // the largest power of two they fill, so every listed member is valid

@@ -48,6 +48,15 @@ template <typename S> __device__ __forceinline__ S big();
 template <> __device__ __forceinline__ int big<int>() { return INT_MAX; }
 template <> __device__ __forceinline__ float big<float>() { return FLT_MAX; }
 
+// median of three (one VALU instruction)
+__device__ __forceinline__ float med3(float a, float b, float c) { return __builtin_amdgcn_fmed3f(a, b, c); }
+__device__ __forceinline__ int med3(int a, int b, int c)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 __device__ __forceinline__ int p2floor(int x) { return x <= 1 ? 1 : (1 << (31 - __clz(x))); }
 
 // squared distance of the reference patch rp and the candidate starting
@@ -154,57 +163,81 @@ void k_match_1d(MatchArgs a, int cap_span, int kmax)
             }
             const int dlo = max(wlo, -r), dhi = min(whi, ell - r);
             const int ncand = dhi - dlo;  // window size minus the reference
-            S s[M];
+            // the M smallest values, and in float modes one more (the value
+            // after the K-th tells whether the K-th boundary is a near-tie)
+            constexpr int NS = kF ? M + 1 : M;
+            S s[NS];
 #pragma unroll
-            for (int m = 0; m < M; ++m) s[m] = big<S>();
+            for (int m = 0; m < NS; ++m) s[m] = big<S>();
             int acc = 0, nrec = 0, namb = 0;
             // float modes: band of FP32 round-off around a value (relative
             // to the score's terms; the Gaussian bias is one of them)
             const float bmag = MODE == kGauss ? fabsf(a.bias) : 0.f;
             const float tau_band = float(kTieBand) * (fabsf(a.tau_f) + bmag);
+            // count mode: the SSD of integer counts is evaluated exactly as
+            // sum p^2 + sum q^2 - 2 sum pq (wrapping uint32 arithmetic; the
+            // result is below 2^31), with sliding sums over the candidate
+            unsigned sp2 = 0;
+            if constexpr (MODE == kCount) {
+#pragma unroll
+                for (int i = 0; i < kJ; ++i) sp2 += unsigned(__mul24(rp[i], rp[i]));
+            }
             for (int d0 = wlo; d0 <= whi; d0 += kJ) {
                 S buf[2 * kJ];
 #pragma unroll
                 for (int i = 0; i < 2 * kJ; ++i) buf[i] = from_bits<S>(sx[rl + d0 + i]);
                 S sc = 0;
+                unsigned sq2 = 0;
                 if constexpr (MODE == kCount) {
 #pragma unroll
-                    for (int i = 0; i < kJ; ++i) sc += buf[i];
+                    for (int i = 0; i < kJ; ++i) {
+                        sc += buf[i];
+                        sq2 += unsigned(__mul24(buf[i], buf[i]));
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < kJ; ++u) {
                     const int d = d0 + u;
                     S x = 0;
-#pragma unroll
-                    for (int i = 0; i < kJ; ++i) {
-                        const S df = buf[u + i] - rp[i];
-                        if constexpr (MODE == kCount) x += __mul24(df, df);
-                        else x = __builtin_fmaf(df, df, x);
-                    }
                     if constexpr (MODE == kCount) {
-                        x -= a.gamma_i * (sr + sc);
-                        sc += buf[u + kJ] - buf[u];
-                    } else if constexpr (MODE == kGauss) {
-                        x -= a.bias;
-                    }
-                    if (d >= dlo && d <= dhi && d != 0) {
-                        if constexpr (MODE == kCount) {
-                            acc += x < a.tau_i;
-                        } else {
-                            acc += x < a.tau_f;
-                            namb += fabsf(x - a.tau_f) <= tau_band;
-                        }
-                        bool rec_it;
-                        if constexpr (MODE == kCount) rec_it = x <= s[M - 1];
-                        else rec_it = x <= s[M - 1] + float(kTieBand) * (fabsf(s[M - 1]) + bmag);
-                        if (rec_it) {
-                            if (nrec < kRec) rec[nrec][lane] = (unsigned char)(d - wlo);
-                            ++nrec;
-                        }
+                        unsigned spq = 0;
 #pragma unroll
-                        for (int m = M - 1; m >= 1; --m) s[m] = smin(s[m], smax(s[m - 1], x));
-                        s[0] = smin(s[0], x);
+                        for (int i = 0; i < kJ; ++i) spq += unsigned(__mul24(buf[u + i], rp[i]));
+                        x = int(sp2 + sq2 - 2u * spq) - a.gamma_i * (sr + sc);
+                        sq2 += unsigned(__mul24(buf[u + kJ], buf[u + kJ]) - __mul24(buf[u], buf[u]));
+                        sc += buf[u + kJ] - buf[u];
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < kJ; ++i) {
+                            const S df = buf[u + i] - rp[i];
+                            x = __builtin_fmaf(df, df, x);
+                        }
+                        if constexpr (MODE == kGauss) x -= a.bias;
+                        x = x == x ? x : big<S>();  // non-finite scores are never selected
                     }
+                    // offsets outside the clipped window and the reference
+                    // itself score as the largest value (never counted, never
+                    // selected)
+                    const bool valid = d >= dlo && d <= dhi && d != 0;
+                    x = valid ? x : big<S>();
+                    if constexpr (MODE == kCount) {
+                        acc += x < a.tau_i;
+                    } else {
+                        acc += x < a.tau_f;
+                        namb += fabsf(x - a.tau_f) <= tau_band;
+                    }
+                    bool rec_it;
+                    if constexpr (MODE == kCount) rec_it = valid && x <= s[M - 1];
+                    else rec_it = valid && x <= s[M - 1] + float(kTieBand) * (fabsf(s[M - 1]) + bmag);
+                    if (rec_it) {
+                        if (nrec < kRec) rec[nrec][lane] = (unsigned char)(d - wlo);
+                        ++nrec;
+                    }
+                    // insertion into the sorted M smallest: slot m takes the
+                    // median of (s[m-1], x, s[m]) since s[m-1] <= s[m]
+#pragma unroll
+                    for (int m = NS - 1; m >= 1; --m) s[m] = med3(s[m - 1], x, s[m]);
+                    s[0] = smin(s[0], x);
                 }
             }
 
@@ -237,28 +270,38 @@ void k_match_1d(MatchArgs a, int cap_span, int kmax)
             for (int m = 1; m < a.gmax; ++m) out[m] = -1;
             if (need == 0) a.count[t] = K;
             if (need > 0) {
-                S theta = s[0];
+                S theta = s[0], next = s[0];
 #pragma unroll
-                for (int m = 0; m < M; ++m)
+                for (int m = 0; m < NS; ++m) {
                     if (m == need - 1) theta = s[m];
+                    if (m == need) next = s[m];
+                }
                 int got = 0;
-                if constexpr (MODE == kCount) {
+                // FP32 (exact in count mode) selection: the members below
+                // theta and the first ties at theta, in lin order; then sorted
+                // by (score, lin)
+                {
                     int n_less = 0;
 #pragma unroll
                     for (int m = 0; m < M; ++m) n_less += (m < need && s[m] < theta) ? 1 : 0;
                     int eq_left = need - n_less;
                     auto consider = [&](int d) {
                         S x = ssd_lds<MODE>(rp, sx, rl + d);
-                        int sc2 = 0;
-                        for (int i = 0; i < kJ; ++i) sc2 += sx[rl + d + i];
-                        x -= a.gamma_i * (sr + sc2);
+                        if constexpr (MODE == kCount) {
+                            int sc2 = 0;
+                            for (int i = 0; i < kJ; ++i) sc2 += sx[rl + d + i];
+                            x -= a.gamma_i * (sr + sc2);
+                        } else {
+                            if constexpr (MODE == kGauss) x -= a.bias;
+                            x = x == x ? x : big<S>();
+                        }
                         bool take = x < theta;
                         if (!take && x == theta && eq_left > 0) {
                             take = true;
                             --eq_left;
                         }
                         if (take) {
-                            sel_s[got][lane] = x;
+                            sel_s[got][lane] = Key(x);
                             sel_l[got][lane] = r + d;
                             ++got;
                         }
@@ -270,7 +313,8 @@ void k_match_1d(MatchArgs a, int cap_span, int kmax)
                             if (d != 0) consider(d);
                     }
                     for (int m = 1; m < got; ++m) {
-                        const int ks = sel_s[m][lane], kl = sel_l[m][lane];
+                        const Key ks = sel_s[m][lane];
+                        const int kl = sel_l[m][lane];
                         int p = m - 1;
                         while (p >= 0 && sel_s[p][lane] > ks) {
                             sel_s[p + 1][lane] = sel_s[p][lane];
@@ -280,34 +324,48 @@ void k_match_1d(MatchArgs a, int cap_span, int kmax)
                         sel_s[p + 1][lane] = ks;
                         sel_l[p + 1][lane] = kl;
                     }
-                } else {
-                    // every candidate up to theta plus the band is re-scored
-                    // in FP64; the best `need` are kept by (FP64 score, lin)
-                    // (candidates arrive in lin order, a strict comparison
-                    // keeps the lower lin first on equal scores)
-                    const float thr = theta + float(kTieBand) * (fabsf(theta) + bmag);
-                    auto consider = [&](int d) {
-                        S x = ssd_lds<MODE>(rp, sx, rl + d);
-                        if constexpr (MODE == kGauss) x -= a.bias;
-                        if (!(x <= thr)) return;
-                        const double xd = score64_lds<MODE>(a, rp, sx, rl + d);
-                        if (!(xd == xd)) return;
-                        if (got == need && !(xd < sel_s[need - 1][lane])) return;
-                        int p = got < need ? got : need - 1;
-                        while (p > 0 && sel_s[p - 1][lane] > xd) {
-                            sel_s[p][lane] = sel_s[p - 1][lane];
-                            sel_l[p][lane] = sel_l[p - 1][lane];
-                            --p;
-                        }
-                        sel_s[p][lane] = xd;
-                        sel_l[p][lane] = r + d;
-                        if (got < need) ++got;
+                }
+                if constexpr (kF) {
+                    // The FP32 ranking equals the FP64 one unless the value
+                    // after the K-th, or two neighbours in the list, lie
+                    // within the round-off band (equal zeros are exact).
+                    auto near = [&](float lo, float hi) {
+                        return hi - lo <= float(kTieBand) * (fabsf(hi) + bmag) &&
+                               !(lo == 0.f && hi == 0.f);
                     };
-                    if (nrec <= kRec) {
-                        for (int k = 0; k < nrec; ++k) consider(int(rec[k][lane]) + wlo);
-                    } else {
-                        for (int d = dlo; d <= dhi; ++d)
-                            if (d != 0) consider(d);
+                    bool amb = got == need && near(float(theta), float(next));
+                    for (int m = 1; m < got; ++m)
+                        amb = amb || near(float(sel_s[m - 1][lane]), float(sel_s[m][lane]));
+                    if (amb) {
+                        // every candidate up to theta plus the band is
+                        // re-scored in FP64; the best `need` are kept by (FP64
+                        // score, lin) (candidates arrive in lin order, a strict
+                        // comparison keeps the lower lin first on equal scores)
+                        got = 0;
+                        const float thr = theta + float(kTieBand) * (fabsf(theta) + bmag);
+                        auto consider = [&](int d) {
+                            S x = ssd_lds<MODE>(rp, sx, rl + d);
+                            if constexpr (MODE == kGauss) x -= a.bias;
+                            if (!(x <= thr)) return;
+                            const double xd = score64_lds<MODE>(a, rp, sx, rl + d);
+                            if (!(xd == xd)) return;
+                            if (got == need && !(xd < sel_s[need - 1][lane])) return;
+                            int p = got < need ? got : need - 1;
+                            while (p > 0 && sel_s[p - 1][lane] > xd) {
+                                sel_s[p][lane] = sel_s[p - 1][lane];
+                                sel_l[p][lane] = sel_l[p - 1][lane];
+                                --p;
+                            }
+                            sel_s[p][lane] = xd;
+                            sel_l[p][lane] = r + d;
+                            if (got < need) ++got;
+                        };
+                        if (nrec <= kRec) {
+                            for (int k = 0; k < nrec; ++k) consider(int(rec[k][lane]) + wlo);
+                        } else {
+                            for (int d = dlo; d <= dhi; ++d)
+                                if (d != 0) consider(d);
+                        }
                     }
                 }
                 // non-finite scores select fewer members than asked: the
