@@ -252,6 +252,45 @@ bmnd_status bmnd_denoise(const float* d_y, const bmnd_geometry* geom,
                          const bmnd_noise* noise, const bmnd_params* params, float* d_out,
                          float* d_pilot, void* d_ws, size_t ws_bytes, void* stream);
 
+/* A batch of independent denoises (the serving and batching form of
+ * bmnd_denoise, section Method Overview applied per array): any mix of
+ * dimensionality, size, noise model and parameters.  Each job is exactly
+ * the computation of bmnd_denoise on its own arrays.
+ *   d_y, d_out  [geom.batch][V] device arrays of the job
+ *   d_pilot     [geom.batch][V] receives the pilot, or NULL */
+typedef struct {
+    const float* d_y;
+    float* d_out;
+    float* d_pilot;
+    bmnd_geometry geom;
+    bmnd_noise noise;
+    bmnd_params params;
+} bmnd_job;
+
+enum { BMND_BATCH_GRAPH = 1 };  /* capture the launch sequence, replay it */
+
+/* Workspace bytes for bmnd_denoise_batch on this job table.  Jobs are
+ * assigned to the library's concurrent streams (longest first, least
+ * loaded stream); jobs on one stream share that stream's workspace, so the
+ * size is the sum over streams of the largest job workspace on each.
+ * Errors: those of bmnd_workspace_size, naming the job. */
+bmnd_status bmnd_batch_workspace_size(int32_t n_jobs, const bmnd_job* jobs, size_t* bytes);
+
+/* Queue all jobs: the library's streams (default priority, one per
+ * hardware queue) wait for the work already on `stream`, run the jobs
+ * concurrently, and `stream` waits for all of them, so the call behaves as
+ * an ordinary stream-ordered operation on `stream`.  With
+ * BMND_BATCH_GRAPH the launch sequence of a job table (pointers, shapes,
+ * parameters and d_ws alike) is captured once into a hipGraph and
+ * replayed by later calls with the same table; graphs are cached per
+ * device (the 16 most recent tables).  Calls are serialized by the
+ * library.  The caller owns every buffer; d_ws must hold
+ * bmnd_batch_workspace_size() bytes.
+ * Errors: BMND_E_ARG (NULL pointers, unknown flags), BMND_E_WORKSPACE,
+ * per-job validation errors, BMND_E_HIP. */
+bmnd_status bmnd_denoise_batch(int32_t n_jobs, const bmnd_job* jobs, void* d_ws, size_t ws_bytes,
+                               int32_t flags, void* stream);
+
 /* Kernel tracing.  Between bmnd_profile_begin() and bmnd_profile_end() the
  * library records a pair of HIP events on the launch stream around every
  * kernel that bmnd_denoise launches.  bmnd_profile_end() synchronises those

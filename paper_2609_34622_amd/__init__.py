@@ -66,12 +66,21 @@ class Params(C.Structure):
     _fields_ = [("ht", StageParams), ("wiener", StageParams)]
 
 
+class Job(C.Structure):
+    """One entry of a batch (``bmnd_job``)."""
+    _fields_ = [("d_y", C.c_void_p), ("d_out", C.c_void_p), ("d_pilot", C.c_void_p),
+                ("geom", Geometry), ("noise", Noise), ("params", Params)]
+
+
+BATCH_GRAPH = 1
+
+
 EXPORTS = [
     "bmnd_last_error", "bmnd_version", "bmnd_params_default", "bmnd_reference_origins",
     "bmnd_match_workspace_size", "bmnd_aggregate_workspace_size", "bmnd_workspace_size",
     "bmnd_match", "bmnd_filter", "bmnd_aggregate", "bmnd_denoise", "bmnd_stream_status",
     "bmnd_transform_matrices", "bmnd_haar_matrix", "bmnd_kaiser_window",
-    "bmnd_profile_begin", "bmnd_profile_end",
+    "bmnd_profile_begin", "bmnd_profile_end", "bmnd_batch_workspace_size", "bmnd_denoise_batch",
 ]
 KERNEL_IDS = ["counts", "patch_sums", "match_ht", "match_wiener", "filter_ht", "filter_wiener",
               "zero", "normalize"]
@@ -108,6 +117,8 @@ def lib() -> C.CDLL:
         "bmnd_kaiser_window": (i32, [i32, C.c_double, vp]),
         "bmnd_profile_begin": (i32, []),
         "bmnd_profile_end": (i32, [vp, vp, i32]),
+        "bmnd_batch_workspace_size": (i32, [i32, C.POINTER(Job), C.POINTER(sz)]),
+        "bmnd_denoise_batch": (i32, [i32, C.POINTER(Job), vp, sz, i32, vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -322,3 +333,29 @@ def denoise(y, noise: Noise, params: Optional[Params] = None, batched: bool = Fa
     pilot = torch.empty_like(y)
     bmnd_denoise(y.contiguous(), geom, noise, params, out, pilot, ws)
     return (out, pilot) if return_pilot else out
+
+
+def make_jobs(entries) -> "C.Array":
+    """A ``bmnd_job`` table from (y, out, pilot_or_None, geom, noise, params)
+    tuples of device tensors and parameter structs."""
+    import torch
+
+    arr = (Job * len(entries))()
+    for i, (y, out, pilot, geom, noise, params) in enumerate(entries):
+        _require(y, torch.float32, name="y")
+        _require(out, torch.float32, name="out")
+        _require(pilot, torch.float32, name="pilot")
+        arr[i].d_y, arr[i].d_out, arr[i].d_pilot = _ptr(y), _ptr(out), _ptr(pilot)
+        arr[i].geom, arr[i].noise, arr[i].params = geom, noise, params
+    return arr
+
+
+def bmnd_batch_workspace_size(jobs) -> int:
+    n = C.c_size_t(0)
+    _check(lib().bmnd_batch_workspace_size(len(jobs), jobs, C.byref(n)))
+    return n.value
+
+
+def bmnd_denoise_batch(jobs, ws, flags: int = 0, stream=None):
+    _check(lib().bmnd_denoise_batch(len(jobs), jobs, _ptr(ws), ws.numel() * ws.element_size(),
+                                    int(flags), _stream(stream)))

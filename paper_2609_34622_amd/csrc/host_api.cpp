@@ -5,7 +5,9 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
+#include <vector>
 
 #include "bmnd_internal.h"
 
@@ -296,7 +298,7 @@ struct KernelSpan {
     hipEvent_t a = nullptr, b = nullptr;
     KernelSpan(int id_, hipStream_t s_) : id(id_), s(s_)
     {
-        if (!g_prof_on) return;
+        if (!g_prof_on || id < 0) return;
         if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
             (void)hipEventRecord(a, s);
     }
@@ -583,58 +585,92 @@ bmnd_status bmnd_aggregate(const float* d_y, const bmnd_geometry* geom,
     return BMND_OK;
 }
 
-bmnd_status bmnd_denoise(const float* d_y, const bmnd_geometry* geom,
-                         const bmnd_noise* noise, const bmnd_params* params, float* d_out,
-                         float* d_pilot, void* d_ws, size_t ws_bytes, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Everything one denoise needs, resolved before any launch: tables and
+// reference origins are built (and uploaded) here, so enqueueing allocates
+// nothing and can be captured into a graph.
+struct DenoisePlan {
+    StageCfg c1, c2;
+    const int64_t* r1 = nullptr;
+    const int64_t* r2 = nullptr;
+    int64_t n1 = 0, n2 = 0;
+    const DevTables* t1 = nullptr;
+    const DevTables* t2 = nullptr;
+    size_t offs[8] = {};
+    size_t total = 0;
+};
+
+// host part: configurations, reference counts and the workspace layout
+bmnd_status plan_denoise_host(const bmnd_geometry* geom, const bmnd_noise* noise,
+                              const bmnd_params* params, DenoisePlan* pl)
 {
     if (!params) return fail(BMND_E_ARG, "params is NULL");
-    StageCfg c1, c2;
-    bmnd_status st = make_stage(geom, noise, &params->ht, BMND_STAGE_HT, c1);
+    bmnd_status st = make_stage(geom, noise, &params->ht, BMND_STAGE_HT, pl->c1);
     if (st != BMND_OK) return st;
-    if ((st = make_stage(geom, noise, &params->wiener, BMND_STAGE_WIENER, c2)) != BMND_OK) return st;
+    if ((st = make_stage(geom, noise, &params->wiener, BMND_STAGE_WIENER, pl->c2)) != BMND_OK)
+        return st;
     if (!noise) return fail(BMND_E_ARG, "noise is NULL");
-    if (!d_y || !d_out) return fail(BMND_E_ARG, "NULL device pointer");
-    std::string err;
-    int64_t n1 = 0, n2 = 0;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     bmnd_geometry one = *geom;
     one.batch = 1;
-    const int64_t* r1 = device_origins(one, params->ht, &n1, s, err);
-    const int64_t* r2 = r1 ? device_origins(one, params->wiener, &n2, s, err) : nullptr;
-    if (!r1 || !r2) return fail(BMND_E_NOMEM, err);
-    const DevTables* t1 = device_tables(c1, err);
-    const DevTables* t2 = t1 ? device_tables(c2, err) : nullptr;
-    if (!t1 || !t2) return fail(BMND_E_NOMEM, err);
-    size_t offs[8], total = 0;
-    denoise_layout(geom, params, n1, n2, offs, &total);
-    if (!d_ws || ws_bytes < total)
-        return fail(BMND_E_WORKSPACE, "workspace missing or smaller than bmnd_workspace_size");
-    char* ws = static_cast<char*>(d_ws);
-    int* match = reinterpret_cast<int*>(ws + offs[0]);
-    int* count = reinterpret_cast<int*>(ws + offs[1]);
-    int* kappa = reinterpret_cast<int*>(ws + offs[2]);
-    int* psum = reinterpret_cast<int*>(ws + offs[3]);
-    void* num = ws + offs[4];
-    void* den = ws + offs[5];
-    float* pilot = d_pilot ? d_pilot : reinterpret_cast<float*>(ws + offs[6]);
-    const size_t vox = size_t(c1.g.batch) * c1.g.V;
+    pl->n1 = int64_t(reference_origins(one, params->ht).size());
+    pl->n2 = int64_t(reference_origins(one, params->wiener).size());
+    return denoise_layout(geom, params, pl->n1, pl->n2, pl->offs, &pl->total);
+}
+
+bmnd_status plan_denoise(const bmnd_geometry* geom, const bmnd_noise* noise,
+                         const bmnd_params* params, DenoisePlan* pl)
+{
+    if (!params) return fail(BMND_E_ARG, "params is NULL");
+    bmnd_status st = make_stage(geom, noise, &params->ht, BMND_STAGE_HT, pl->c1);
+    if (st != BMND_OK) return st;
+    if ((st = make_stage(geom, noise, &params->wiener, BMND_STAGE_WIENER, pl->c2)) != BMND_OK)
+        return st;
+    if (!noise) return fail(BMND_E_ARG, "noise is NULL");
+    std::string err;
+    bmnd_geometry one = *geom;
+    one.batch = 1;
+    pl->r1 = device_origins(one, params->ht, &pl->n1, nullptr, err);
+    pl->r2 = pl->r1 ? device_origins(one, params->wiener, &pl->n2, nullptr, err) : nullptr;
+    if (!pl->r1 || !pl->r2) return fail(BMND_E_NOMEM, err);
+    pl->t1 = device_tables(pl->c1, err);
+    pl->t2 = pl->t1 ? device_tables(pl->c2, err) : nullptr;
+    if (!pl->t1 || !pl->t2) return fail(BMND_E_NOMEM, err);
+    return denoise_layout(geom, params, pl->n1, pl->n2, pl->offs, &pl->total);
+}
+
+// The two stages of one denoise on stream s (workspace ws of pl.total bytes).
+hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out,
+                           float* d_pilot, char* ws, hipStream_t s, bool spans)
+{
+    int* match = reinterpret_cast<int*>(ws + pl.offs[0]);
+    int* count = reinterpret_cast<int*>(ws + pl.offs[1]);
+    int* kappa = reinterpret_cast<int*>(ws + pl.offs[2]);
+    int* psum = reinterpret_cast<int*>(ws + pl.offs[3]);
+    void* num = ws + pl.offs[4];
+    void* den = ws + pl.offs[5];
+    float* pilot = d_pilot ? d_pilot : reinterpret_cast<float*>(ws + pl.offs[6]);
+    const size_t vox = size_t(pl.c1.g.batch) * pl.c1.g.V;
+    const int no_span = -1;
 
     auto run_stage = [&](const StageCfg& c, const DevTables& t, const int64_t* refs, int64_t nr,
                          const float* src, const float* pil, float* out) -> hipError_t {
         const bool ht = c.stage == BMND_STAGE_HT;
         hipError_t e = hipSuccess;
         {
-            KernelSpan k(ht ? BMND_KID_MATCH_HT : BMND_KID_MATCH_WIENER, s);
+            KernelSpan k(spans ? (ht ? BMND_KID_MATCH_HT : BMND_KID_MATCH_WIENER) : no_span, s);
             e = launch_match(c, src, kappa, psum, refs, int(nr), match, count, s);
         }
         if (e == hipSuccess) {
-            KernelSpan k(BMND_KID_ZERO, s);
+            KernelSpan k(spans ? BMND_KID_ZERO : no_span, s);
             e = launch_zero(num, vox * (c.mc ? 16 : 8) / 2, s);
             if (e == hipSuccess) e = launch_zero(den, vox * (c.mc ? 16 : 8) / 2, s);
         }
         if (e != hipSuccess) return e;
         {
-            KernelSpan k(ht ? BMND_KID_FILTER_HT : BMND_KID_FILTER_WIENER, s);
+            KernelSpan k(spans ? (ht ? BMND_KID_FILTER_HT : BMND_KID_FILTER_WIENER) : no_span, s);
             if (c.mc) {
                 e = launch_filter(c, t, 2, d_y, pil, int(nr), match, count, nullptr, nullptr, num,
                                   den, s);
@@ -647,15 +683,229 @@ bmnd_status bmnd_denoise(const float* d_y, const bmnd_geometry* geom,
             }
         }
         if (e == hipSuccess) {
-            KernelSpan k(BMND_KID_NORMALIZE, s);
+            KernelSpan k(spans ? BMND_KID_NORMALIZE : no_span, s);
             e = launch_normalize(c, num, den, out, nullptr, s);
         }
         return e;
     };
-    hipError_t e = run_stage(c1, *t1, r1, n1, d_y, nullptr, pilot);
-    if (e != hipSuccess) return hip_fail(e, "HT stage");
-    e = run_stage(c2, *t2, r2, n2, pilot, pilot, d_out);
-    if (e != hipSuccess) return hip_fail(e, "Wiener stage");
+    hipError_t e = run_stage(pl.c1, *pl.t1, pl.r1, pl.n1, d_y, nullptr, pilot);
+    if (e != hipSuccess) return e;
+    return run_stage(pl.c2, *pl.t2, pl.r2, pl.n2, pilot, pilot, d_out);
+}
+
+// ------------------------------------------------------------- batches
+
+constexpr int kBatchStreams = 4;  // concurrent streams (the device's hardware queues)
+
+// Library streams and events of one device for batches; calls of
+// bmnd_denoise_batch are serialized per process.
+struct BatchPool {
+    hipStream_t work[kBatchStreams] = {};
+    hipStream_t capture = nullptr;
+    hipEvent_t fork = nullptr, in = nullptr, out = nullptr;
+    hipEvent_t join[kBatchStreams] = {};
+    std::map<std::string, hipGraphExec_t> graphs;  // launch sequences by job table
+    std::vector<std::string> order;                // insertion order (eviction)
+};
+std::mutex g_batch_mu;
+std::map<int, BatchPool> g_pools;
+constexpr size_t kMaxGraphs = 16;
+
+hipError_t pool_for_device(BatchPool** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    auto it = g_pools.find(dev);
+    if (it != g_pools.end()) {
+        *out = &it->second;
+        return hipSuccess;
+    }
+    BatchPool p;
+    for (int i = 0; i < kBatchStreams && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&p.work[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p.join[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p.capture, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p.in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p.out, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    *out = &(g_pools[dev] = p);
+    return hipSuccess;
+}
+
+// Work estimate of a job (candidate patch-samples of both stages).
+double job_work(const DenoisePlan& pl)
+{
+    double cand = 1.0;
+    for (int d = 0; d < kAx; ++d) cand *= pl.c1.g.W[d];
+    return double(pl.c1.g.batch) * double(pl.n1 + pl.n2) * cand * pl.c1.g.P + 1.0;
+}
+
+// Jobs go to streams longest first, each to the least loaded stream; jobs
+// on one stream run one after another and share that stream's workspace.
+struct BatchLayout {
+    std::vector<DenoisePlan> plans;
+    std::vector<int> stream_of;
+    std::vector<size_t> ws_off;  // per stream
+    size_t total = 0;
+};
+
+bmnd_status layout_batch(int32_t n_jobs, const bmnd_job* jobs, BatchLayout* L, bool device)
+{
+    if (n_jobs < 0) return fail(BMND_E_ARG, "n_jobs < 0");
+    if (n_jobs > 0 && !jobs) return fail(BMND_E_ARG, "jobs is NULL");
+    L->plans.assign(size_t(n_jobs), DenoisePlan{});
+    std::vector<int> idx(static_cast<size_t>(n_jobs));
+    std::vector<double> work(static_cast<size_t>(n_jobs));
+    for (int i = 0; i < n_jobs; ++i) {
+        DenoisePlan* pl = &L->plans[size_t(i)];
+        const bmnd_status st = device ? plan_denoise(&jobs[i].geom, &jobs[i].noise, &jobs[i].params, pl)
+                                      : plan_denoise_host(&jobs[i].geom, &jobs[i].noise, &jobs[i].params, pl);
+        if (st != BMND_OK) {
+            set_error("job " + std::to_string(i) + ": " + bmnd_last_error());
+            return st;
+        }
+        idx[size_t(i)] = i;
+        work[size_t(i)] = job_work(L->plans[size_t(i)]);
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return work[size_t(a)] > work[size_t(b)]; });
+    double load[kBatchStreams] = {};
+    size_t need[kBatchStreams] = {};
+    L->stream_of.assign(size_t(n_jobs), 0);
+    for (int i : idx) {
+        int best = 0;
+        for (int k = 1; k < kBatchStreams; ++k)
+            if (load[k] < load[best]) best = k;
+        load[best] += work[size_t(i)];
+        need[best] = std::max(need[best], L->plans[size_t(i)].total);
+        L->stream_of[size_t(i)] = best;
+    }
+    L->ws_off.assign(kBatchStreams, 0);
+    size_t o = 0;
+    for (int k = 0; k < kBatchStreams; ++k) {
+        L->ws_off[size_t(k)] = o;
+        o += align256(need[k]);
+    }
+    L->total = o;
+    return BMND_OK;
+}
+
+// Fork from `from` onto the work streams, enqueue every job in stream
+// order (longest first), join back into `from`.
+hipError_t enqueue_batch(BatchPool& P, const BatchLayout& L, int32_t n_jobs, const bmnd_job* jobs,
+                         char* ws, hipStream_t from)
+{
+    hipError_t e = hipEventRecord(P.fork, from);
+    for (int k = 0; k < kBatchStreams && e == hipSuccess; ++k) e = hipStreamWaitEvent(P.work[k], P.fork, 0);
+    std::vector<int> idx(static_cast<size_t>(n_jobs));
+    for (int i = 0; i < n_jobs; ++i) idx[size_t(i)] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        return job_work(L.plans[size_t(a)]) > job_work(L.plans[size_t(b)]);
+    });
+    for (int i : idx) {
+        if (e != hipSuccess) break;
+        const int k = L.stream_of[size_t(i)];
+        e = enqueue_denoise(L.plans[size_t(i)], jobs[i].d_y, jobs[i].d_out, jobs[i].d_pilot,
+                            ws + L.ws_off[size_t(k)], P.work[k], false);
+    }
+    for (int k = 0; k < kBatchStreams && e == hipSuccess; ++k) {
+        e = hipEventRecord(P.join[k], P.work[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(from, P.join[k], 0);
+    }
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+bmnd_status bmnd_denoise(const float* d_y, const bmnd_geometry* geom,
+                         const bmnd_noise* noise, const bmnd_params* params, float* d_out,
+                         float* d_pilot, void* d_ws, size_t ws_bytes, void* stream)
+{
+    DenoisePlan pl;
+    bmnd_status st = plan_denoise(geom, noise, params, &pl);
+    if (st != BMND_OK) return st;
+    if (!d_y || !d_out) return fail(BMND_E_ARG, "NULL device pointer");
+    if (!d_ws || ws_bytes < pl.total)
+        return fail(BMND_E_WORKSPACE, "workspace missing or smaller than bmnd_workspace_size");
+    hipError_t e = enqueue_denoise(pl, d_y, d_out, d_pilot, static_cast<char*>(d_ws),
+                                   static_cast<hipStream_t>(stream), true);
+    if (e != hipSuccess) return hip_fail(e, "denoise");
+    return BMND_OK;
+}
+
+bmnd_status bmnd_batch_workspace_size(int32_t n_jobs, const bmnd_job* jobs, size_t* bytes)
+{
+    if (!bytes) return fail(BMND_E_ARG, "bytes is NULL");
+    BatchLayout L;
+    bmnd_status st = layout_batch(n_jobs, jobs, &L, false);
+    if (st != BMND_OK) return st;
+    *bytes = L.total;
+    return BMND_OK;
+}
+
+bmnd_status bmnd_denoise_batch(int32_t n_jobs, const bmnd_job* jobs, void* d_ws, size_t ws_bytes,
+                               int32_t flags, void* stream)
+{
+    BatchLayout L;
+    bmnd_status st = layout_batch(n_jobs, jobs, &L, true);
+    if (st != BMND_OK) return st;
+    if (n_jobs == 0) return BMND_OK;
+    for (int i = 0; i < n_jobs; ++i)
+        if (!jobs[i].d_y || !jobs[i].d_out) return fail(BMND_E_ARG, "NULL device pointer in a job");
+    if (!d_ws || ws_bytes < L.total)
+        return fail(BMND_E_WORKSPACE, "workspace missing or smaller than bmnd_batch_workspace_size");
+    if (flags & ~BMND_BATCH_GRAPH) return fail(BMND_E_ARG, "unknown batch flags");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(d_ws);
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchPool* P = nullptr;
+    hipError_t e = pool_for_device(&P);
+    if (e != hipSuccess) return hip_fail(e, "batch streams");
+    if (!(flags & BMND_BATCH_GRAPH)) {
+        e = enqueue_batch(*P, L, n_jobs, jobs, ws, s);
+        if (e != hipSuccess) return hip_fail(e, "batch");
+        return BMND_OK;
+    }
+    // graph: keyed by the job table and the workspace (the launch sequence
+    // depends on nothing else); captured on the library's capture stream
+    std::string key(reinterpret_cast<const char*>(jobs), sizeof(bmnd_job) * size_t(n_jobs));
+    key.append(reinterpret_cast<const char*>(&d_ws), sizeof(d_ws));
+    hipGraphExec_t exec = nullptr;
+    auto it = P->graphs.find(key);
+    if (it != P->graphs.end()) exec = it->second;
+    e = hipEventRecord(P->in, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(P->capture, P->in, 0);
+    if (e == hipSuccess && !exec) {
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(P->capture, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e2 = enqueue_batch(*P, L, n_jobs, jobs, ws, P->capture);
+            e = hipStreamEndCapture(P->capture, &graph);
+            if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e == hipSuccess) {
+            if (P->order.size() >= kMaxGraphs) {
+                auto old = P->graphs.find(P->order.front());
+                if (old != P->graphs.end()) {
+                    (void)hipGraphExecDestroy(old->second);
+                    P->graphs.erase(old);
+                }
+                P->order.erase(P->order.begin());
+            }
+            P->graphs[key] = exec;
+            P->order.push_back(key);
+        }
+    }
+    if (e == hipSuccess) e = hipGraphLaunch(exec, P->capture);
+    if (e == hipSuccess) e = hipEventRecord(P->out, P->capture);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, P->out, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch graph");
     return BMND_OK;
 }
 

@@ -109,3 +109,26 @@ def test_validation_errors():
     g0.batch = 0
     assert _status(B.bmnd_workspace_size, g0, noise, p) == B.E_SHAPE
     assert "batch" in B.lib().bmnd_last_error().decode()
+
+
+def test_batch_workspace_layout():
+    """Jobs go to four streams, longest first; a stream's jobs share its
+    workspace, so the size is the sum of the per-stream maxima."""
+    def job(shape, batch=1):
+        j = B.Job()
+        j.geom = B.geometry(shape, batch)
+        j.noise = B.poisson(0.1)
+        j.params = B.bmnd_params_default(B.PRESET_PLAIN, len(shape))
+        return j
+
+    one = [job((4096,)), job((64, 64)), job((24, 24, 24))]
+    arr = (B.Job * 3)(*one)
+    sizes = [B.bmnd_workspace_size(j.geom, j.noise, j.params) for j in one]
+    assert B.bmnd_batch_workspace_size(arr) == sum(sizes)
+    same = (B.Job * 6)(*[job((64, 64)) for _ in range(6)])
+    assert B.bmnd_batch_workspace_size(same) == 4 * sizes[1]
+    assert B.bmnd_batch_workspace_size((B.Job * 0)()) == 0
+    bad = (B.Job * 2)(job((64, 64)), job((64, 64)))
+    bad[1].noise = B.poisson(0.0)
+    with pytest.raises(B.BmndError, match="job 1"):
+        B.bmnd_batch_workspace_size(bad)
