@@ -156,6 +156,82 @@ def measured_traffic(workload: str, kernel: str):
     return round(k["fetch_kib"] * 1024.0 * f_scale + k["write_kib"] * 1024.0 * w_scale)
 
 
+def _mixed_arrays(seed: int, n_each: int, len_1d, side_2d, side_3d):
+    """Uneven arrays for the batched comparison: n_each 1-D signals, 2-D
+    images and 3-D volumes of log-uniform sizes, as in the serving trace."""
+    from paper_2609_34622_amd import serving
+
+    return serving.make_trace(3 * n_each, 1.0, seed, len_1d=len_1d, side_2d=side_2d,
+                              side_3d=side_3d, mix=(1, 1, 1))
+
+
+def bench_batched(B, torch, reps: int = 3) -> dict:
+    """The plain per-array path (one bmnd_denoise after another on one stream)
+    against bmnd_denoise_batch (concurrent streams, replayed graph) on the
+    same device-resident mixed arrays."""
+    from paper_2609_34622_amd import serving
+
+    reqs = _mixed_arrays(6000, 8, (16384, 65536), (128, 384), (32, 56))
+    ys = [torch.from_numpy(r.y).cuda() for r in reqs]
+    outs = [torch.empty_like(y) for y in ys]
+    geoms = [B.geometry(r.y.shape) for r in reqs]
+    noises = [B.poisson(r.s_p) for r in reqs]
+    wss = [torch.empty(serving.request_bytes(r) - 2 * r.y.nbytes, dtype=torch.uint8, device="cuda")
+           for r in reqs]
+    jobs = B.make_jobs([(ys[i], outs[i], None, geoms[i], noises[i], reqs[i].params)
+                        for i in range(len(reqs))])
+    bws = torch.empty(B.bmnd_batch_workspace_size(jobs), dtype=torch.uint8, device="cuda")
+    vox = sum(r.voxels for r in reqs)
+
+    def plain():
+        for i in range(len(reqs)):
+            B.bmnd_denoise(ys[i], geoms[i], noises[i], reqs[i].params, outs[i], None, wss[i])
+
+    def batched():
+        B.bmnd_denoise_batch(jobs, bws, flags=B.BATCH_GRAPH)
+
+    res = {}
+    for name, fn in (("plain", plain), ("batched", batched)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[name] = {"mvox_per_s": round(vox / dt / 1e6, 3), "ms": round(dt * 1e3, 3)}
+    B.bmnd_stream_status()
+    return {"arrays": len(reqs), "voxels": vox,
+            "mix": "8 1-D (16k-64k samples), 8 2-D (128^2-384^2), 8 3-D (32^3-56^3, mass "
+                   "conservation), seeded log-uniform sizes; device-resident",
+            "plain": res["plain"], "batched": res["batched"],
+            "speedup": round(res["plain"]["ms"] / res["batched"]["ms"], 3)}
+
+
+def bench_serving(B, torch, n: int = 60) -> dict:
+    """Continuous batching against the plain one-at-a-time path on one seeded
+    trace of mixed requests (host arrays in, host results out); the arrival
+    rate is 0.7 of the plain path's measured capacity."""
+    from paper_2609_34622_amd import serving
+
+    kw = dict(len_1d=(8192, 131072), side_2d=(128, 512), side_3d=(32, 64))
+    calib = serving.make_trace(12, 1e6, 7000, **kw)
+    cap = serving.serve_fifo(calib)
+    rate = 0.7 * cap["requests"] / cap["makespan_s"]
+    trace = serving.make_trace(n, rate, 7001, **kw)
+    budget = 32 << 30
+    srv = serving.Server(budget_bytes=budget, slots=4)
+    cont = srv.run(trace)
+    for r in trace:
+        r.out = None
+    fifo = serving.serve_fifo(trace)
+    return {"requests": n, "arrival_rate_per_s": round(rate, 3), "hbm_budget_gib": budget >> 30,
+            "trace": "seeded Poisson arrivals; 40% 1-D (8k-128k), 40% 2-D (128^2-512^2), "
+                     "20% 3-D (32^3-64^3, mass conservation); peaks log-uniform [2, 100]",
+            "continuous": {k: round(v, 3) for k, v in cont.items()},
+            "plain_fifo": {k: round(v, 3) for k, v in fifo.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +243,9 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, copy this many MiB device to device once "
                          "(calibrates HBM byte counters under rocprofv3)")
+    ap.add_argument("--mixed", type=int, default=1,
+                    help="also time the batched path and the serving path on mixed 1-D/2-D/3-D "
+                         "workloads (0: skip)")
     ap.add_argument("--summarize-pmc", nargs="+", metavar="DB",
                     help="summarize rocprofv3 databases (FETCH_SIZE / WRITE_SIZE runs of a "
                          "--copy-probe-mib bench) into per-launch HBM bytes, print JSON, exit")
@@ -282,6 +361,11 @@ def main():
                "sample": f"{n} of {batch} arrays of the same workload, both stages, "
                          f"{dt:.1f} s single-threaded"}
 
+    batched = serving_row = None
+    if args.mixed:
+        batched = bench_batched(B, torch)
+        serving_row = bench_serving(B, torch)
+
     line = {
         "metric": "denoised Mvox/s (both stages)",
         "value": round(value, 3), "unit": "Mvox/s", "n_gpus": 1, "steps": args.steps,
@@ -295,6 +379,8 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "serving": serving_row,
     }
     print(json.dumps(line), flush=True)
 
