@@ -81,7 +81,7 @@ hipError_t launch_counts(const StageCfg& c, const float* y, int* kappa, int* psu
 // the generic count-domain path and may be NULL otherwise.
 hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* psum,
                         const int64_t* refs, int n_refs, int* match, int* count, hipStream_t s);
-// out_mode: 0 write patches/weights, 1 aggregate (float), 2 mc sweep 1, 3 mc sweep 2
+// out_mode: 0 write patches/weights, 1 aggregate (FP64 sums), 2 mc sweep 1, 3 mc sweep 2
 hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
                          const float* pilot, int n_refs, const int* match, const int* count,
                          float* patches, float* weights, void* num, void* den, hipStream_t s);

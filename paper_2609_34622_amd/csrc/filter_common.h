@@ -14,7 +14,7 @@ struct FilterArgs {
     int wmodel, wscope;
     int kex;       // exact covariance planes (leading Haar planes l < kex)
     int gmax, n_refs;
-    int out_mode;  // 0 patches, 1 aggregate f32, 2 mc sweep 1, 3 mc sweep 2
+    int out_mode;  // 0 patches, 1 aggregate (FP64 sums), 2 mc sweep 1, 3 mc sweep 2
     const float* y;
     const float* pilot;
     const int* match;
@@ -24,8 +24,6 @@ struct FilterArgs {
     DevTables t;
     float* patches;
     float* weights;
-    float* numf;
-    float* denf;
     double* numd;
     double* dend;
 };

@@ -665,8 +665,8 @@ hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out
         }
         if (e == hipSuccess) {
             KernelSpan k(spans ? BMND_KID_ZERO : no_span, s);
-            e = launch_zero(num, vox * (c.mc ? 16 : 8) / 2, s);
-            if (e == hipSuccess) e = launch_zero(den, vox * (c.mc ? 16 : 8) / 2, s);
+            e = launch_zero(num, vox * sizeof(double), s);
+            if (e == hipSuccess) e = launch_zero(den, vox * sizeof(double), s);
         }
         if (e != hipSuccess) return e;
         {

@@ -787,8 +787,9 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
             const int j = e / P, i = e - j * P;
             const long u = vb + org[j] + off[i];
             const float ww = wj[j] * win[i];
-            unsafeAtomicAdd(&a.numf[u], ww * res[e]);
-            unsafeAtomicAdd(&a.denf[u], ww);
+            // FP64 sums: the float result does not depend on the order
+            unsafeAtomicAdd(&a.numd[u], double(ww * res[e]));
+            unsafeAtomicAdd(&a.dend[u], double(ww));
         }
     } else if (a.out_mode == 2) {
         for (int e = threadIdx.x; e < n; e += kFilterThreads) {
@@ -950,6 +951,7 @@ hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* ps
     }
     if (match_1d_supported(c.g, mode))
         return launch_match_1d(a, mode, c.step_last, count_limit(c), s);
+    if (match_nd_supported(c.g)) return launch_match_nd(a, mode, count_limit(c), s);
     if (mode == kCount) {
         if (!kappa || !psum) return hipErrorInvalidValue;
         hipError_t e = launch_counts(c, src, kappa, psum, s);
@@ -1016,8 +1018,6 @@ hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, co
     a.count = count;
     a.patches = patches;
     a.weights = weights;
-    a.numf = static_cast<float*>(num);
-    a.denf = static_cast<float*>(den);
     a.numd = static_cast<double*>(num);
     a.dend = static_cast<double*>(den);
     const long groups = long(c.g.batch) * n_refs;
@@ -1037,8 +1037,6 @@ hipError_t launch_aggregate(const StageCfg& c, const DevTables& t, int out_mode,
     a.count = count;
     a.patches_in = patches;
     a.weights_in = weights;
-    a.numf = static_cast<float*>(num);
-    a.denf = static_cast<float*>(den);
     a.numd = static_cast<double*>(num);
     a.dend = static_cast<double*>(den);
     const long groups = long(c.g.batch) * n_refs;
@@ -1049,15 +1047,12 @@ hipError_t launch_aggregate(const StageCfg& c, const DevTables& t, int out_mode,
 hipError_t launch_normalize(const StageCfg& c, const void* num, const void* den, float* out,
                             float* out2, hipStream_t s)
 {
+    // numerator and denominator are FP64 sums in every mode
+    (void)c.mc;
     const long n = long(c.g.batch) * c.g.V;
-    if (c.mc)
-        hipLaunchKernelGGL(k_normalize<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, n,
-                           static_cast<const double*>(num), static_cast<const double*>(den), out,
-                           out2);
-    else
-        hipLaunchKernelGGL(k_normalize<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, n,
-                           static_cast<const float*>(num), static_cast<const float*>(den), out,
-                           out2);
+    hipLaunchKernelGGL(k_normalize<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, n,
+                       static_cast<const double*>(num), static_cast<const double*>(den), out,
+                       out2);
     return hipGetLastError();
 }
 

@@ -26,6 +26,8 @@
 // input samples, as in the generic filter.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "bmnd_internal.h"
 #include "filter_common.h"
 
@@ -36,8 +38,8 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kJ = 32;        // patch length
 constexpr int kWaves = 4;     // wavefronts per workgroup
-constexpr int kSub = 48;      // references per wavefront (a contiguous run)
-constexpr int kChunk = kSub * kWaves;  // references per workgroup
+constexpr int kSubMax = 48;   // references per wavefront (a contiguous run), at most
+constexpr int kTargetWaves = 16384;  // enough wavefronts to fill the device
 constexpr int kZs = 36;       // row stride (floats) of the transpose buffer
 constexpr float kRsqrt2 = 0.70710678118654752440f;
 
@@ -144,8 +146,9 @@ __device__ __forceinline__ void opnd_load(const float* ops, int m, int c, int la
 
 template <int SH>
 __global__ __launch_bounds__(kWave * kWaves) __attribute__((amdgpu_waves_per_eu(3)))
-void k_filter_1d(FilterArgs a, int tile_cap, int tile_back, int wcap)
+void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
 {
+    const int chunk = sub * kWaves;  // references per workgroup
     constexpr bool wiener = SH == BMND_SHRINK_WIENER;
     __shared__ __align__(16) float ops[2 * 2 * 2 * kWave * 4];
     // Haar operands per group size 2^lk and lane: H[m16][4lg + s] (analysis)
@@ -199,15 +202,15 @@ void k_filter_1d(FilterArgs a, int tile_cap, int tile_back, int wcap)
     }
     const double* T64 = a.t.f64 + a.t.T64[kAx - 1];
 
-    const int nchunk = (a.n_refs + kChunk - 1) / kChunk;
+    const int nchunk = (a.n_refs + chunk - 1) / chunk;
     const int b = blockIdx.x / nchunk;
-    const int g0 = (blockIdx.x - b * nchunk) * kChunk;
-    const int g1 = min(a.n_refs, g0 + kChunk);
+    const int g0 = (blockIdx.x - b * nchunk) * chunk;
+    const int g1 = min(a.n_refs, g0 + chunk);
     const long vb = long(b) * g.V;
     // this wavefront: references [w0g, w1g), accumulated in its own tile
     // [wlo, wlo + wcap); the workgroup stages [tile_lo, tile_lo + tile_cap)
-    const int w0g = min(g1, g0 + wave * kSub);
-    const int w1g = min(g1, w0g + kSub);
+    const int w0g = min(g1, g0 + wave * sub);
+    const int w1g = min(g1, w0g + sub);
     const int tile_lo = tile_cap > 0 ? a.match[(long(b) * a.n_refs + g0) * a.gmax] - tile_back : 0;
     const int wlo = (wcap > 0 && w0g < w1g) ? a.match[(long(b) * a.n_refs + w0g) * a.gmax] - tile_back : 0;
     float* tnum = tile + wave * 2 * wcap;
@@ -509,8 +512,8 @@ void k_filter_1d(FilterArgs a, int tile_cap, int tile_back, int wcap)
                     for (int c = 0; c < 2; ++c) {
                         const int u = od[r] + 16 * c + m16;
                         const float ww = wd[r] * wq[c];
-                        unsafeAtomicAdd(&a.numf[vb + u], ww * o[c][r]);
-                        unsafeAtomicAdd(&a.denf[vb + u], ww);
+                        unsafeAtomicAdd(&a.numd[vb + u], double(ww * o[c][r]));
+                        unsafeAtomicAdd(&a.dend[vb + u], double(ww));
                     }
                 }
             }
@@ -563,8 +566,9 @@ void k_filter_1d(FilterArgs a, int tile_cap, int tile_back, int wcap)
             const float d = tden[i];
             const int u = wlo + i;
             if (d != 0.f && u >= 0 && u < g.V) {
-                unsafeAtomicAdd(&a.numf[vb + u], tnum[i]);
-                unsafeAtomicAdd(&a.denf[vb + u], d);
+                // FP64 sums: the float result does not depend on the order
+                unsafeAtomicAdd(&a.numd[vb + u], double(tnum[i]));
+                unsafeAtomicAdd(&a.dend[vb + u], double(d));
             }
         }
     }
@@ -588,26 +592,31 @@ hipError_t launch_filter_1d(const FilterArgs& a, int step_last, hipStream_t s)
     int tile_cap = 0, tile_back = 0, wcap = 0;
     const bool one_d = g.L[0] == 1 && g.L[1] == 1 && g.L[2] == 1;
     const int nstage = a.shrink == BMND_SHRINK_WIENER ? 2 : 1;  // staged arrays
+    // references per wavefront: up to kSubMax, fewer for small arrays so
+    // that the launch still fills the device
+    const long groups = long(a.n_refs) * g.batch;
+    const int sub = int(std::max(1L, std::min<long>(kSubMax, groups / kTargetWaves)));
+    const int chunk = sub * kWaves;
     if (one_d) {
         const int st = max(step_last, 1);
         tile_back = g.W[kAx - 1] / 2;
-        tile_cap = (kChunk - 1) * st + g.W[kAx - 1] + kJ;
-        if (a.out_mode == 1) wcap = (kSub - 1) * st + g.W[kAx - 1] + kJ;
+        tile_cap = (chunk - 1) * st + g.W[kAx - 1] + kJ;
+        if (a.out_mode == 1) wcap = (sub - 1) * st + g.W[kAx - 1] + kJ;
         if (kWaves * 2 * wcap + nstage * tile_cap > kDynFloats) wcap = 0;
         tile_cap = min(tile_cap, kDynFloats / nstage);
     }
-    const int nchunk = (a.n_refs + kChunk - 1) / kChunk;
+    const int nchunk = (a.n_refs + chunk - 1) / chunk;
     const dim3 grid(unsigned(long(nchunk) * g.batch));
     const size_t lds = sizeof(float) * size_t(kWaves * 2 * wcap + nstage * tile_cap);
     if (a.shrink == BMND_SHRINK_HARD)
         hipLaunchKernelGGL(k_filter_1d<BMND_SHRINK_HARD>, grid, dim3(kWave * kWaves), lds, s, a,
-                           tile_cap, tile_back, wcap);
+                           sub, tile_cap, tile_back, wcap);
     else if (a.shrink == BMND_SHRINK_SOFT)
         hipLaunchKernelGGL(k_filter_1d<BMND_SHRINK_SOFT>, grid, dim3(kWave * kWaves), lds, s, a,
-                           tile_cap, tile_back, wcap);
+                           sub, tile_cap, tile_back, wcap);
     else
         hipLaunchKernelGGL(k_filter_1d<BMND_SHRINK_WIENER>, grid, dim3(kWave * kWaves), lds, s, a,
-                           tile_cap, tile_back, wcap);
+                           sub, tile_cap, tile_back, wcap);
     return hipGetLastError();
 }
 

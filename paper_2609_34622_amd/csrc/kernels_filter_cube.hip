@@ -12,6 +12,8 @@
 // scaling, coarsest ... finest detail), block sums for the squared rows.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "bmnd_internal.h"
 #include "filter_common.h"
 #include "exact_planes.h"
@@ -246,13 +248,13 @@ __device__ __forceinline__ double haar64(int K, int l, int j)
 }
 
 // Waves per workgroup: up to four groups of K x P <= 512 samples share one
-// workgroup (and its accumulation tile); larger groups get fewer waves.
+// workgroup; larger groups get fewer waves.
 template <int KP>
 constexpr int waves_for() { return KP <= 512 ? 4 : (KP <= 1024 ? 2 : 1); }
 
 template <int D, int J, int GM, bool EXACT>
 __global__ __launch_bounds__(kWave * waves_for<GM * ipow_c(J, D)>())
-void k_filter_cube(FilterArgs a, int chunk_refs, int tile_cap, int tile_back)
+void k_filter_cube(FilterArgs a, int chunk_refs)
 {
     constexpr int P = ipow_c(J, D);
     constexpr int KP = GM * P;
@@ -267,7 +269,6 @@ void k_filter_cube(FilterArgs a, int chunk_refs, int tile_cap, int tile_back)
     __shared__ float rpl_[NW][GM];
     __shared__ float wj_[NW][GM];
     __shared__ int nres_[NW];
-    extern __shared__ __align__(16) float tile[];  // [2][tile_cap]: numerator, denominator
 
     const Geo& g = a.g;
     const int wave = threadIdx.x / kWave;
@@ -296,7 +297,6 @@ void k_filter_cube(FilterArgs a, int chunk_refs, int tile_cap, int tile_back)
         off[p] = o;
         win[p] = w;
     }
-    for (int i = threadIdx.x; i < 2 * tile_cap; i += kWave * NW) tile[i] = 0.f;
     const float* Tm = a.t.f32 + a.t.T[kAx - 1];
     const float* T2m = a.t.f32 + a.t.T2[kAx - 1];
     const float* Um = a.t.f32 + a.t.U[kAx - 1];
@@ -309,10 +309,6 @@ void k_filter_cube(FilterArgs a, int chunk_refs, int tile_cap, int tile_back)
     const int g0 = (blockIdx.x - b * nchunk) * chunk_refs;
     const int g1 = min(a.n_refs, g0 + chunk_refs);
     const long vb = long(b) * g.V;
-    // the tile covers lins [tile_lo, tile_lo + tile_cap)
-    const int tile_lo = tile_cap > 0 ? a.match[(long(b) * a.n_refs + g0) * a.gmax] - tile_back : 0;
-    float* tnum = tile;
-    float* tden = tile + tile_cap;
     __syncthreads();
 
     for (int gi = g0 + wave; gi < g1; gi += NW) {
@@ -505,16 +501,11 @@ void k_filter_cube(FilterArgs a, int chunk_refs, int tile_cap, int tile_back)
             for (int e = lane; e < n; e += kWave) {
                 const int k = e / P;
                 const int p = e - k * P;
-                const int u = org[k] + off[p];
+                const long u = vb + org[k] + off[p];
+                // FP64 sums: the float result does not depend on the order
                 const float ww = wj[k] * win[p];
-                const int tl = u - tile_lo;
-                if (tl >= 0 && tl < tile_cap) {
-                    atomicAdd(&tnum[tl], ww * res[e]);
-                    atomicAdd(&tden[tl], ww);
-                } else {
-                    unsafeAtomicAdd(&a.numf[vb + u], ww * res[e]);
-                    unsafeAtomicAdd(&a.denf[vb + u], ww);
-                }
+                unsafeAtomicAdd(&a.numd[u], double(ww * res[e]));
+                unsafeAtomicAdd(&a.dend[u], double(ww));
             }
         } else if (a.out_mode == 2) {
             for (int e = lane; e < n; e += kWave) {
@@ -547,46 +538,27 @@ void k_filter_cube(FilterArgs a, int chunk_refs, int tile_cap, int tile_back)
         wsync();
     }
 
-    // ---- flush the accumulation tile
-    if (tile_cap > 0 && a.out_mode == 1) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < tile_cap; i += kWave * NW) {
-            const float d = tden[i];
-            const int u = tile_lo + i;
-            if (d != 0.f && u >= 0 && u < g.V) {
-                unsafeAtomicAdd(&a.numf[vb + u], tnum[i]);
-                unsafeAtomicAdd(&a.denf[vb + u], d);
-            }
-        }
-    }
 }
 
 template <int D, int J>
 hipError_t launch_cube_gm(const FilterArgs& a, int step_last, hipStream_t s)
 {
-    constexpr int chunk = 256;
+    // references per workgroup: up to 256, fewer for small arrays so that
+    // the launch still fills the device
     const Geo& g = a.g;
-    // 1-D arrays: the patches of a chunk of references fall into a short lin
-    // range, accumulated in LDS; elsewhere the tile is off
-    int tile_cap = 0, tile_back = 0;
-    const bool one_d = g.L[0] == 1 && g.L[1] == 1 && g.L[2] == 1;
-    if (one_d && a.out_mode == 1) {
-        tile_back = g.W[kAx - 1] / 2;
-        tile_cap = (chunk - 1) * max(step_last, 1) + g.W[kAx - 1] + g.j[kAx - 1];
-        if (tile_cap > 8192) tile_cap = 8192;
-    }
+    const long groups = long(a.n_refs) * g.batch;
+    const int chunk = int(std::max(1L, std::min(256L, groups / 8192)));
     const int nchunk = (a.n_refs + chunk - 1) / chunk;
     const dim3 grid(unsigned(long(nchunk) * g.batch));
-    const size_t lds = sizeof(float) * 2 * size_t(tile_cap);
 #define BMND_CUBE_LAUNCH(GMV)                                                              \
     if (a.kex > 0)                                                                          \
         hipLaunchKernelGGL((k_filter_cube<D, J, GMV, true>),                                \
-                           dim3(grid), dim3(kWave * waves_for<GMV * ipow_c(J, D)>()), lds, s, a, \
-                           chunk, tile_cap, tile_back);                                     \
+                           dim3(grid), dim3(kWave * waves_for<GMV * ipow_c(J, D)>()), 0, s, a, \
+                           chunk);                                                          \
     else                                                                                    \
     hipLaunchKernelGGL((k_filter_cube<D, J, GMV, false>),                                   \
-                       dim3(grid), dim3(kWave * waves_for<GMV * ipow_c(J, D)>()), lds, s, a, \
-                       chunk, tile_cap, tile_back)
+                       dim3(grid), dim3(kWave * waves_for<GMV * ipow_c(J, D)>()), 0, s, a, \
+                       chunk)
     switch (a.gmax) {
     case 1: BMND_CUBE_LAUNCH(1); break;
     case 2: BMND_CUBE_LAUNCH(2); break;

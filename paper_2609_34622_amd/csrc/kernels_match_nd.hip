@@ -1,0 +1,603 @@
+// Block matching for N-D arrays (section Block Matching): one wavefront
+// scores every candidate of one reference.
+//
+// The clipped search region of the reference (window origins plus a patch)
+// is staged once in LDS: raw counts for exact count-domain HT scores, the
+// observation or the pilot otherwise.  The reference patch sits in
+// registers, one row (run along the last axis) per register array.  Lanes
+// take runs of RB consecutive candidates along the last axis: for every
+// patch row a segment of J + RB - 1 staged samples is read once and gives
+// the row terms of all RB candidates.  Every candidate's score is kept in
+// LDS, in C order over the window.
+//
+// Selection (Def. matched group): the count of accepted scores gives K; the
+// K-1 smallest (score, lin) follow from the (K-1)-th smallest value, found
+// by a radix select over order-preserving 32-bit keys, and the first ties
+// at it in lin order (prefix counts across lanes); the members are ranked
+// by (score, lin).  Float scores within the round-off band of the K-th
+// value (or of tau, when that changes K) are re-scored in FP64, which then
+// decides membership and order.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <climits>
+#include <algorithm>
+#include <type_traits>
+
+#include "bmnd_internal.h"
+#include "match_common.h"
+
+namespace bmnd {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kRB = 8;          // candidates per run along the last axis
+constexpr int kMaxRegion = 4096;
+constexpr int kMaxCand = 4096;
+constexpr int kBandCap = 128;   // FP64 re-scored candidates per chunk
+
+template <int MODE>
+struct ScT { using T = float; };
+template <>
+struct ScT<kCount> { using T = int; };
+
+__device__ __forceinline__ unsigned okey(int v) { return unsigned(v) ^ 0x80000000u; }
+__device__ __forceinline__ unsigned okey(float v)
+{
+    const unsigned b = __float_as_uint(v);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+// inverse of okey for float scores
+__device__ __forceinline__ float key_float(unsigned k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+template <typename S> __device__ __forceinline__ S bigv();
+template <> __device__ __forceinline__ int bigv<int>() { return INT_MAX; }
+template <> __device__ __forceinline__ float bigv<float>() { return FLT_MAX; }
+__device__ __forceinline__ int as_int(int v) { return v; }
+__device__ __forceinline__ int as_int(float v) { return __float_as_int(v); }
+template <typename S> __device__ __forceinline__ S from_int(int v);
+template <> __device__ __forceinline__ int from_int<int>(int v) { return v; }
+template <> __device__ __forceinline__ float from_int<float>(int v) { return __int_as_float(v); }
+
+__device__ __forceinline__ int p2fl(int x) { return x <= 1 ? 1 : (1 << (31 - __clz(x))); }
+
+__device__ __forceinline__ int wsum(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// exclusive prefix sum over the lanes of the wave
+__device__ __forceinline__ int wscan_ex(int v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    int s = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(s, o);
+        if (lane >= o) s += t;
+    }
+    return s - v;
+}
+
+// Orders the LDS accesses of one wavefront.
+__device__ __forceinline__ void wsync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int MODE, int GM, int J3>
+__global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
+{
+    using S = typename ScT<MODE>::T;
+    constexpr bool kF = MODE != kCount;
+    constexpr int MR = 64 / J3;              // most patch rows (P <= 64)
+    constexpr int SEG = J3 + kRB - 1;
+    constexpr int M = GM > 1 ? GM - 1 : 1;
+    extern __shared__ __align__(16) int smem[];
+    __shared__ unsigned hist[256];
+    __shared__ int sel_lin[M];
+    __shared__ int sel_key[M];
+    __shared__ double band_x[kBandCap];
+    __shared__ int band_l[kBandCap];
+    __shared__ double best_x[M];
+    __shared__ int best_l[M];
+    __shared__ int misc[4];
+
+    const Geo& g = a.g;
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x / a.n_refs;
+    const int gi = blockIdx.x - b * a.n_refs;
+    const long t = long(b) * a.n_refs + gi;
+    const int r = safe_origin(int(a.refs[gi]), last_origin(g));
+    const float* src = a.src + long(b) * g.V;
+
+    // ---- window origins (clipped) and the staged region
+    int lo[kAx], n[kAx], R[kAx], rc[kAx];
+    int ncand = 1, nreg = 1;
+#pragma unroll
+    for (int d = 0; d < kAx; ++d) {
+        rc[d] = (r / g.st[d]) % g.L[d];
+        lo[d] = max(rc[d] - g.W[d] / 2, 0);
+        const int hi = min(rc[d] + g.W[d] - 1 - g.W[d] / 2, g.ell[d]);
+        n[d] = hi - lo[d] + 1;
+        R[d] = n[d] + g.j[d] - 1;
+        ncand *= n[d];
+        nreg *= R[d];
+    }
+    int* sx = smem;                       // [nreg + kRB] staged samples
+    int* xs = smem + nreg + kRB;          // [ncand] scores (bit patterns)
+    int base = 0;                         // lin of the region's first sample
+#pragma unroll
+    for (int d = 0; d < kAx; ++d) base += lo[d] * g.st[d];
+    for (int e = lane; e < nreg + kRB; e += kWave) {
+        int v = 0;
+        if (e < nreg) {
+            int rem = e, off = 0;
+#pragma unroll
+            for (int d = kAx - 1; d >= 0; --d) {
+                off += (rem % R[d]) * g.st[d];
+                rem /= R[d];
+            }
+            const float x = src[base + off];
+            if constexpr (MODE == kCount) {
+                // non-finite or out-of-range counts are flagged (scored as 0)
+                const float rk = rintf(x * a.inv_sp);
+                const bool ok = rk >= 0.f && rk <= float(kmax);
+                if (!ok) atomicOr(a.range_flag, 1);
+                v = ok ? int(rk) : 0;
+            } else {
+                v = __float_as_int(x);
+            }
+        }
+        sx[e] = v;
+    }
+    wsync();
+
+    // ---- reference patch (rows along the last axis) and its region offsets
+    const int rows = g.P / g.j[kAx - 1];
+    int roff[MR];
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+        int rem = q < rows ? q : 0, o = 0;
+#pragma unroll
+        for (int d = kAx - 2; d >= 0; --d) {
+            const int i = rem % g.j[d];
+            rem /= g.j[d];
+            int stride = 1;
+#pragma unroll
+            for (int e = d + 1; e < kAx; ++e) stride *= R[e];
+            o += i * stride;
+        }
+        roff[q] = o;
+    }
+    int rb = 0;  // the reference's own origin in the region
+    {
+        int stride = 1;
+#pragma unroll
+        for (int d = kAx - 1; d >= 0; --d) {
+            rb += (rc[d] - lo[d]) * stride;
+            stride *= R[d];
+        }
+    }
+    S rp[MR][J3];
+    S sr = 0;
+#pragma unroll
+    for (int q = 0; q < MR; ++q)
+#pragma unroll
+        for (int i = 0; i < J3; ++i) {
+            rp[q][i] = q < rows ? from_int<S>(sx[rb + roff[q] + i]) : S(0);
+            sr += rp[q][i];
+        }
+    int rci = 0;  // the reference's candidate index
+    {
+        int stride = 1;
+#pragma unroll
+        for (int d = kAx - 1; d >= 0; --d) {
+            rci += (rc[d] - lo[d]) * stride;
+            stride *= n[d];
+        }
+    }
+
+    // ---- scores of every candidate
+    const float bmag = MODE == kGauss ? fabsf(a.bias) : 0.f;
+    const int n3 = n[kAx - 1];
+    const int rpr = (n3 + kRB - 1) / kRB;  // runs per line
+    const int nruns = (ncand / n3) * rpr;
+    for (int run = lane; run < nruns; run += kWave) {
+        const int line = run / rpr;
+        const int c3 = (run - line * rpr) * kRB;
+        int cb = c3, rem = line;
+        {
+            int stride = R[kAx - 1];
+#pragma unroll
+            for (int d = kAx - 2; d >= 0; --d) {
+                cb += (rem % n[d]) * stride;
+                rem /= n[d];
+                stride *= R[d];
+            }
+        }
+        S acc[kRB], sq[kRB], bq[kRB];
+#pragma unroll
+        for (int u = 0; u < kRB; ++u) acc[u] = sq[u] = bq[u] = S(0);
+#pragma unroll
+        for (int q = 0; q < MR; ++q) {
+            if (q < rows) {
+                S seg[SEG];
+#pragma unroll
+                for (int k = 0; k < SEG; ++k) seg[k] = from_int<S>(sx[cb + roff[q] + k]);
+#pragma unroll
+                for (int u = 0; u < kRB; ++u) {
+#pragma unroll
+                    for (int i = 0; i < J3; ++i) {
+                        const S df = seg[u + i] - rp[q][i];
+                        if constexpr (MODE == kCount) acc[u] += __mul24(df, df);
+                        else acc[u] = __builtin_fmaf(df, df, acc[u]);
+                        if constexpr (MODE == kCount) sq[u] += seg[u + i];
+                        if constexpr (MODE == kPoissonF) bq[u] += fmaxf(seg[u + i] + rp[q][i], 0.f);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kRB; ++u) {
+            const int ci = line * n3 + c3 + u;
+            if (c3 + u < n3) {
+                S x = acc[u];
+                if constexpr (MODE == kCount) x -= a.gamma_i * (sr + sq[u]);
+                if constexpr (MODE == kGauss) x -= a.bias;
+                if constexpr (MODE == kPoissonF) x = __builtin_fmaf(-a.gamma_sp, bq[u], x);
+                if constexpr (kF) x = x == x ? x : bigv<S>();
+                if (ci == rci) x = bigv<S>();
+                xs[ci] = as_int(x);
+            }
+        }
+    }
+    wsync();
+
+    // ---- accepted count -> group size
+    float tau_band = 0.f;
+    if constexpr (kF) tau_band = float(kTieBand) * (fabsf(a.tau_f) + bmag);
+    const unsigned kbig = okey(bigv<S>());  // excluded: the reference, non-finite scores
+    int acc = 0, namb = 0, nfin = 0;
+    for (int ci = lane; ci < ncand; ci += kWave) {
+        const S x = from_int<S>(xs[ci]);
+        if (ci == rci || okey(x) == kbig) continue;
+        ++nfin;
+        if constexpr (MODE == kCount) {
+            acc += x < a.tau_i;
+        } else {
+            acc += x < a.tau_f;
+            namb += fabsf(x - a.tau_f) <= tau_band;
+        }
+    }
+    acc = wsum(acc);
+    nfin = wsum(nfin);
+    const int ncand_nr = ncand - 1;  // without the reference
+    auto group_size = [&](int acc_) {
+        int k = p2fl(min(1 + acc_, a.gmax));
+        k = max(k, a.gmin);
+        return min(k, p2fl(1 + ncand_nr));
+    };
+    int K = group_size(acc);
+    if constexpr (kF) {
+        namb = wsum(namb);
+        if (namb > 0 && group_size(acc + namb) != K) {
+            // scores within the band of tau are accepted or not in FP64
+            int acc2 = 0;
+            for (int ci = lane; ci < ncand; ci += kWave) {
+                if (ci == rci) continue;
+                const float x = __int_as_float(xs[ci]);
+                if (fabsf(x - a.tau_f) <= tau_band) {
+                    // FP64 score of candidate ci (lin order = C order)
+                    int rem = ci, cbo = 0, stride = 1;
+#pragma unroll
+                    for (int d = kAx - 1; d >= 0; --d) {
+                        cbo += (rem % n[d]) * stride;
+                        rem /= n[d];
+                        stride *= R[d];
+                    }
+                    double s = 0.0, bb = 0.0;
+                    for (int q = 0; q < rows; ++q)
+                        for (int i = 0; i < g.j[kAx - 1]; ++i) {
+                            const double pv = __int_as_float(sx[rb + roff[q] + i]);
+                            const double qv = __int_as_float(sx[cbo + roff[q] + i]);
+                            const double df = __dsub_rn(qv, pv);
+                            s = __dadd_rn(s, __dmul_rn(df, df));
+                            if constexpr (MODE == kPoissonF) bb = __dadd_rn(bb, fmax(__dadd_rn(pv, qv), 0.0));
+                        }
+                    if constexpr (MODE == kGauss) s = __dsub_rn(s, a.bias_d);
+                    if constexpr (MODE == kPoissonF) s = __dsub_rn(s, __dmul_rn(a.gamma_sp_d, bb));
+                    acc2 += s < a.tau_d;
+                } else {
+                    acc2 += x < a.tau_f;
+                }
+            }
+            K = group_size(wsum(acc2));
+        }
+    }
+    // non-finite scores are never selected: fewer finite candidates than
+    // asked cut the group to the largest power of two they fill
+    if (GM > 1 && nfin < K - 1) K = p2fl(1 + nfin);
+    const int need = GM > 1 ? K - 1 : 0;
+    int* out = a.match + t * a.gmax;
+    if (need == 0) {
+        for (int m = lane; m < a.gmax; m += kWave) out[m] = m == 0 ? r : -1;
+        if (lane == 0) a.count[t] = K;
+        return;
+    }
+
+    // ---- the need-th smallest key: radix select, 8 bits at a time
+    unsigned prefix = 0, pmask = 0;
+    int rank = need;  // 1-based rank of the target within the current prefix
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int h = lane; h < 256; h += kWave) hist[h] = 0u;
+        wsync();
+        for (int ci = lane; ci < ncand; ci += kWave) {
+            if (ci == rci) continue;
+            const unsigned k = okey(from_int<S>(xs[ci]));
+            if (k != kbig && (k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+        }
+        wsync();
+        // the bin holding the rank-th key (one lane scans 256 bins)
+        if (lane == 0) {
+            int c = 0, bin = 255;
+            for (int h = 0; h < 256; ++h) {
+                const int hv = int(hist[h]);
+                if (c + hv >= rank) {
+                    bin = h;
+                    break;
+                }
+                c += hv;
+            }
+            misc[0] = bin;
+            misc[1] = rank - c;
+        }
+        wsync();
+        prefix |= unsigned(misc[0]) << shift;
+        pmask |= 255u << shift;
+        rank = misc[1];
+        wsync();
+    }
+    const unsigned theta_key = prefix;
+    // members: keys below theta, then the first ties at theta in lin order
+    const int per = (ncand + kWave - 1) / kWave;  // contiguous index range per lane
+    const int c_lo = min(ncand, lane * per), c_hi = min(ncand, c_lo + per);
+    int n_less = 0, n_eq = 0;
+    for (int ci = c_lo; ci < c_hi; ++ci) {
+        if (ci == rci) continue;
+        const unsigned k = okey(from_int<S>(xs[ci]));
+        if (k == kbig) continue;
+        n_less += k < theta_key;
+        n_eq += k == theta_key;
+    }
+    const int less_total = wsum(n_less);
+    const int eq_before = wscan_ex(n_eq);
+    int ties_left = need - less_total - eq_before;  // ties this lane may still take
+    const int slot0 = wscan_ex(n_less + max(0, min(n_eq, ties_left)));
+    {
+        int slot = slot0;
+        for (int ci = c_lo; ci < c_hi; ++ci) {
+            if (ci == rci) continue;
+            const unsigned k = okey(from_int<S>(xs[ci]));
+            if (k == kbig) continue;
+            bool take = k < theta_key;
+            if (!take && k == theta_key && ties_left > 0) {
+                take = true;
+                --ties_left;
+            }
+            if (take) {
+                // lin of candidate ci (C order over the window)
+                int rem = ci, lin = 0;
+#pragma unroll
+                for (int d = kAx - 1; d >= 0; --d) {
+                    lin += (lo[d] + rem % n[d]) * g.st[d];
+                    rem /= n[d];
+                }
+                sel_lin[slot] = lin;
+                sel_key[slot] = int(k ^ 0x80000000u);  // signed order = key order
+                ++slot;
+            }
+        }
+    }
+    wsync();
+    int got = need;
+
+    bool fp64 = false;
+    if constexpr (kF) {
+        // FP32 ranking = FP64 ranking unless a non-member lies within the
+        // band above theta, or two members lie within the band of each other
+        // (equal zeros are exact)
+        const float th = key_float(theta_key);
+        const float thr = th + float(kTieBand) * (fabsf(th) + bmag);
+        int nb = 0;
+        for (int ci = lane; ci < ncand; ci += kWave) {
+            if (ci == rci) continue;
+            const float x = __int_as_float(xs[ci]);
+            nb += x <= thr && !(x == 0.f && th == 0.f);
+        }
+        nb = wsum(nb);
+        int members_in_band = 0, close = 0;
+        for (int m = lane; m < need; m += kWave) {
+            const float xm = key_float(unsigned(sel_key[m]) ^ 0x80000000u);
+            members_in_band += xm <= thr && !(xm == 0.f && th == 0.f);
+            for (int o = 0; o < need; ++o) {
+                if (o == m) continue;
+                const float xo = key_float(unsigned(sel_key[o]) ^ 0x80000000u);
+                const float hi_ = fmaxf(xm, xo), lo_ = fminf(xm, xo);
+                close += hi_ - lo_ <= float(kTieBand) * (fabsf(hi_) + bmag) &&
+                         !(hi_ == 0.f && lo_ == 0.f);
+            }
+        }
+        const bool amb = nb > wsum(members_in_band) || wsum(close) > 0;
+        fp64 = amb;
+        if (fp64) {
+            // every candidate up to theta plus the band, re-scored in FP64 in
+            // lin order, chunk by chunk; the best `need` by (FP64 score, lin)
+            if (lane == 0) misc[2] = 0;  // entries in best_x
+            wsync();
+            for (int c0 = 0; c0 < ncand; c0 += kBandCap) {
+                if (lane == 0) misc[3] = 0;
+                wsync();
+                for (int ci = c0 + lane; ci < min(ncand, c0 + kBandCap); ci += kWave) {
+                    if (ci == rci) continue;
+                    const float x = __int_as_float(xs[ci]);
+                    if (!(x <= thr)) continue;
+                    int rem = ci, cbo = 0, stride = 1, lin = 0;
+#pragma unroll
+                    for (int d = kAx - 1; d >= 0; --d) {
+                        cbo += (rem % n[d]) * stride;
+                        lin += (lo[d] + rem % n[d]) * g.st[d];
+                        rem /= n[d];
+                        stride *= R[d];
+                    }
+                    double s = 0.0, bb = 0.0;
+                    for (int q = 0; q < rows; ++q)
+                        for (int i = 0; i < g.j[kAx - 1]; ++i) {
+                            const double pv = __int_as_float(sx[rb + roff[q] + i]);
+                            const double qv = __int_as_float(sx[cbo + roff[q] + i]);
+                            const double df = __dsub_rn(qv, pv);
+                            s = __dadd_rn(s, __dmul_rn(df, df));
+                            if constexpr (MODE == kPoissonF) bb = __dadd_rn(bb, fmax(__dadd_rn(pv, qv), 0.0));
+                        }
+                    if constexpr (MODE == kGauss) s = __dsub_rn(s, a.bias_d);
+                    if constexpr (MODE == kPoissonF) s = __dsub_rn(s, __dmul_rn(a.gamma_sp_d, bb));
+                    if (!(s == s)) continue;
+                    const int slot = atomicAdd(&misc[3], 1);
+                    band_x[slot] = s;
+                    band_l[slot] = lin;
+                }
+                wsync();
+                // merge the chunk into the running best list: rank counting
+                const int nb_c = misc[3], nbest = misc[2];
+                const int tot = nb_c + nbest;
+                double my_x[4];
+                int my_l[4], my_r[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int e = lane + k * kWave;
+                    my_r[k] = INT_MAX;
+                    if (e < tot) {
+                        my_x[k] = e < nbest ? best_x[e] : band_x[e - nbest];
+                        my_l[k] = e < nbest ? best_l[e] : band_l[e - nbest];
+                        int rk = 0;
+                        for (int o = 0; o < tot; ++o) {
+                            const double xo = o < nbest ? best_x[o] : band_x[o - nbest];
+                            const int lo_ = o < nbest ? best_l[o] : band_l[o - nbest];
+                            rk += xo < my_x[k] || (xo == my_x[k] && lo_ < my_l[k]);
+                        }
+                        my_r[k] = rk;
+                    }
+                }
+                wsync();
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (my_r[k] < need) {
+                        best_x[my_r[k]] = my_x[k];
+                        best_l[my_r[k]] = my_l[k];
+                    }
+                }
+                if (lane == 0) misc[2] = min(tot, need);
+                wsync();
+            }
+            got = misc[2];
+            wsync();
+        }
+    }
+
+    // ---- output: members ranked by (score, lin)
+    if (got < need) K = p2fl(1 + got);
+    if (lane == 0) {
+        a.count[t] = K;
+        out[0] = r;
+    }
+    for (int m = K + lane; m < a.gmax; m += kWave) out[m] = -1;
+    if (fp64) {
+        for (int m = lane; m < K - 1; m += kWave) out[1 + m] = best_l[m];
+    } else {
+        for (int m = lane; m < need; m += kWave) {
+            const int km = sel_key[m], lm = sel_lin[m];
+            int rk = 0;
+            for (int o = 0; o < need; ++o) {
+                const int ko = sel_key[o], lo_ = sel_lin[o];
+                rk += ko < km || (ko == km && lo_ < lm);
+            }
+            if (rk < K - 1) out[1 + rk] = lm;
+        }
+    }
+}
+
+}  // namespace
+
+namespace {
+
+template <int MODE, int J3>
+hipError_t launch_nd_mode(const MatchArgs& a, int kmax, size_t lds, hipStream_t s)
+{
+    const dim3 grid(unsigned(long(a.n_refs) * a.g.batch));
+    switch (a.gmax) {
+    case 1: hipLaunchKernelGGL((k_match_nd<MODE, 1, J3>), grid, dim3(kWave), lds, s, a, kmax); break;
+    case 2: hipLaunchKernelGGL((k_match_nd<MODE, 2, J3>), grid, dim3(kWave), lds, s, a, kmax); break;
+    case 4: hipLaunchKernelGGL((k_match_nd<MODE, 4, J3>), grid, dim3(kWave), lds, s, a, kmax); break;
+    case 8: hipLaunchKernelGGL((k_match_nd<MODE, 8, J3>), grid, dim3(kWave), lds, s, a, kmax); break;
+    case 16: hipLaunchKernelGGL((k_match_nd<MODE, 16, J3>), grid, dim3(kWave), lds, s, a, kmax); break;
+    default: hipLaunchKernelGGL((k_match_nd<MODE, 32, J3>), grid, dim3(kWave), lds, s, a, kmax); break;
+    }
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_nd_j(const MatchArgs& a, int kmax, size_t lds, hipStream_t s)
+{
+    const int j3 = a.g.j[kAx - 1];
+    if (j3 == 4) return launch_nd_mode<MODE, 4>(a, kmax, lds, s);
+    if (j3 == 8) return launch_nd_mode<MODE, 8>(a, kmax, lds, s);
+    return launch_nd_mode<MODE, 16>(a, kmax, lds, s);
+}
+
+}  // namespace
+
+// window region (window origins plus a patch) and candidate counts of the
+// largest window, for the LDS size
+static void nd_sizes(const Geo& g, int* region, int* cand)
+{
+    int rg = 1, cd = 1;
+    for (int d = 0; d < kAx; ++d) {
+        const int nw = std::min(g.W[d], g.ell[d] + 1);
+        rg *= nw + g.j[d] - 1;
+        cd *= nw;
+    }
+    *region = rg;
+    *cand = cd;
+}
+
+bool match_nd_supported(const Geo& g)
+{
+    const int j3 = g.j[kAx - 1];
+    // the row loops run over exactly the last-axis extent
+    if (g.P > 64 || (j3 != 4 && j3 != 8 && j3 != 16)) return false;
+    int region = 0, cand = 0;
+    nd_sizes(g, &region, &cand);
+    return region <= kMaxRegion && cand <= kMaxCand;
+}
+
+hipError_t launch_match_nd(const MatchArgs& a, int mode, int kmax, hipStream_t s)
+{
+    int region = 0, cand = 0;
+    nd_sizes(a.g, &region, &cand);
+    const size_t lds = sizeof(int) * size_t(region + kRB + cand);
+    switch (mode) {
+    case kCount: return launch_nd_j<kCount>(a, kmax, lds, s);
+    case kPoissonF: return launch_nd_j<kPoissonF>(a, kmax, lds, s);
+    case kGauss: return launch_nd_j<kGauss>(a, kmax, lds, s);
+    default: return launch_nd_j<kPlain>(a, kmax, lds, s);
+    }
+}
+
+}  // namespace bmnd

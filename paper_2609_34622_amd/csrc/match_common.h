@@ -37,6 +37,10 @@ struct MatchArgs {
 constexpr double kTieBand = 1e-5;
 
 bool match_1d_supported(const Geo& g, int mode);
+// N-D arrays: P <= 64, last-axis patch extent 4, 8 or 16, staged window
+// region and candidate count up to 4096
+bool match_nd_supported(const Geo& g);
+hipError_t launch_match_nd(const MatchArgs& a, int mode, int kmax, hipStream_t s);
 hipError_t launch_match_1d(const MatchArgs& a, int mode, int step, int kmax, hipStream_t s);
 
 }  // namespace bmnd
