@@ -1,6 +1,7 @@
 """Build the BMND HIP library (libbmnd.so) in-tree for gfx950 with hipcc."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -18,7 +19,7 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
+    objs, cmds = [], []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(HERE, "_build", src + ".o")
@@ -28,8 +29,13 @@ def build(verbose: bool = False) -> str:
             cmd[1:1] = DEVICE_FLAGS
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd, cwd=CSRC)
+        cmds.append(cmd)
         objs.append(obj)
+    # the translation units compile independently
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 1, 16))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        for f in [pool.submit(subprocess.check_call, c, cwd=CSRC) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     if verbose:
