@@ -502,12 +502,16 @@ FLOAT_MATCH = [
     ((40, 36), (8, 8), (3, 3), (15, 15), "ht", "gaussian"),
     ((40, 36), (8, 8), (3, 3), (15, 15), "ht", "poisson-nonintegral"),
     ((12, 11, 10), (4, 4, 4), (3, 3, 3), (5, 5, 5), "wiener", "poisson"),
+    ((3000,), (32,), (4,), (256,), "wiener", "poisson", 32),
+    ((1500,), (32,), (2,), (100,), "ht", "gaussian", 4),
 ]
 
 
-@pytest.mark.parametrize("case", FLOAT_MATCH, ids=lambda c: "x".join(map(str, c[0])) + "-" + c[4] + "-" + c[5])
+@pytest.mark.parametrize("case", FLOAT_MATCH, ids=lambda c: "x".join(map(str, c[0])) + "-" + c[4] + "-" + c[5]
+                         + (f"-g{c[6]}" if len(c) > 6 else ""))
 def test_float_match_lists_identical(case):
-    shape, patch, step, search, stage, noise_kind = case
+    shape, patch, step, search, stage, noise_kind = case[:6]
+    gm = case[6] if len(case) > 6 else 16
     _say(f"float-mode matching {case}")
     rng = np.random.default_rng(44)
     if len(shape) == 1:
@@ -517,7 +521,6 @@ def test_float_match_lists_identical(case):
             else rng.uniform(0.2, 1.0, size=shape)
     src = (np.asarray(src, np.float64) + rng.normal(0, 0.05, shape)).astype(np.float32)
     st_id = B.STAGE_WIENER if stage == "wiener" else B.STAGE_HT
-    gm = 16
     p = params_for(shape, patch, step, search, group=(gm, gm))
     sp = p.wiener if stage == "wiener" else p.ht
     ht, wie = oracle_stages(shape, patch, step, search, 0.02, group=(gm, gm))
@@ -534,5 +537,45 @@ def test_float_match_lists_identical(case):
     refs = B.bmnd_reference_origins(geom, sp)
     mg, cg = gpu_match(st_id, dev(src), geom, noise, sp, refs)
     mo, co, _, _ = O.match(st_o, O.STAGE_WIENER if stage == "wiener" else O.STAGE_HT, src, src, refs)
+    assert np.array_equal(cg[0], co)
+    assert np.array_equal(mg[0], mo)
+
+
+# ------------------------------------------- count-mode matching: exact lists
+
+COUNT_MATCH_1D = [
+    # length, step, search, peak of the second half, gamma, group_max
+    (6000, 4, 256, 50.0, 3.0, 16),     # byte-count path throughout
+    (6000, 4, 256, 900.0, 3.0, 16),    # counts above 255 in part of the waves
+    (777, 7, 64, 40.0, 3.0, 16),       # ragged tail, short window
+    (2000, 3, 17, 20.0, 3.0, 8),
+    (3000, 4, 256, 30.0, 400.0, 16),   # gamma above the byte path's limit
+    (3000, 4, 200, 50.0, 3.0, 32),
+    (1500, 1, 256, 50.0, 0.0, 2),
+]
+
+
+@pytest.mark.parametrize("case", COUNT_MATCH_1D, ids=lambda c: f"L{c[0]}-h{c[1]}-W{c[2]}-pk{c[3]:g}-g{c[4]:g}-G{c[5]}")
+def test_count_match_lists_bit_exact_1d(case):
+    """Integral Poisson counts: the score is an exact integer on both sides,
+    so lists and group sizes agree bit for bit, with counts below and above
+    255 in one array (two kernels share the references)."""
+    L, h, W, peak2, gamma, gm = case
+    _say(f"count-mode 1-D matching {case}")
+    s = synth.ecg_batch(n_signals=1, length=L, seed=2400 + L, peak=50.0)
+    y = s.y[0].astype(np.float32).copy()
+    if peak2 != 50.0:
+        rng = np.random.default_rng(7)
+        lam = np.asarray(s.x[0][L // 2:], np.float64) / s.s_p * (peak2 / 50.0)
+        y[L // 2:] = (rng.poisson(lam) * s.s_p).astype(np.float32)
+    shape, patch, step, search = (L,), (32,), (h,), (W,)
+    p = params_for(shape, patch, step, search, group=(gm, gm))
+    p.ht.gamma = gamma
+    ht, _ = oracle_stages(shape, patch, step, search, s.s_p, group=(gm, gm))
+    ht.gamma = gamma
+    geom = B.geometry(shape)
+    refs = B.bmnd_reference_origins(geom, p.ht)
+    mg, cg = gpu_match(B.STAGE_HT, dev(y[None]), geom, B.poisson(s.s_p), p.ht, refs)
+    mo, co, _, _ = O.match(ht, O.STAGE_HT, y, y, refs)
     assert np.array_equal(cg[0], co)
     assert np.array_equal(mg[0], mo)
