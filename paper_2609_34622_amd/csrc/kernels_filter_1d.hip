@@ -156,8 +156,9 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     __shared__ __align__(16) float hops[5][kWave][8];
     __shared__ __align__(16) float ztr_[kWaves][16 * kZs];
     __shared__ float rl_[kWaves][16];
-    // per wavefront [2][wcap] (numerator, denominator of its accumulation
-    // tile), then [tile_cap] staged samples and [tile_cap] staged pilot
+    // per wavefront [wcap] (numerator, denominator) pairs of its
+    // accumulation tile, then [tile_cap] staged samples and [tile_cap]
+    // staged pilot
     extern __shared__ __align__(16) float tile[];
 
     const Geo& g = a.g;
@@ -213,8 +214,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     const int w1g = min(g1, w0g + sub);
     const int tile_lo = tile_cap > 0 ? a.match[(long(b) * a.n_refs + g0) * a.gmax] - tile_back : 0;
     const int wlo = (wcap > 0 && w0g < w1g) ? a.match[(long(b) * a.n_refs + w0g) * a.gmax] - tile_back : 0;
-    float* tnum = tile + wave * 2 * wcap;
-    float* tden = tnum + wcap;
+    float2* tacc = reinterpret_cast<float2*>(tile + wave * 2 * wcap);
     float* ysm = tile + kWaves * 2 * wcap;
     float* psm = ysm + tile_cap;
     const bool poisson = a.noise == BMND_NOISE_POISSON;
@@ -229,7 +229,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         ysm[i] = inb ? yb[u] : 0.f;
         if constexpr (wiener) psm[i] = inb ? pb[u] : 0.f;
     }
-    for (int i = lane; i < 2 * wcap; i += kWave) tnum[i] = 0.f;
+    for (int i = lane; i < wcap; i += kWave) tacc[i] = make_float2(0.f, 0.f);
     __syncthreads();
 
     // the next group's size and this lane's entry of its match list are
@@ -345,12 +345,19 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                 const int bit = __ffs(__shfl(int(near), src)) - 1;
                 const int l = 4 * (src >> 4) + (bit & 3);
                 const int q = 16 * (bit >> 2) + (src & 15);
-                const double h = haar_d(lk, l, m16);
+                // opaque copies keep the FP64 set-up inside this rarely
+                // taken loop (the compiler would otherwise hoist it into
+                // every group)
+                int lkv = lk;
+                asm volatile("" : "+v"(lkv));
+                const double h = haar_d(lkv, l, m16);
                 double sy = 0.0, sv = 0.0;
                 if (av) {
                     for (int s = 0; s < 8; ++s) {
+                        float xv = x[s];
+                        asm volatile("" : "+v"(xv));
                         const double w = h * T64[q * kJ + 8 * lg + s];
-                        const double xs = double(x[s]);
+                        const double xs = double(xv);
                         sy += w * xs;
                         sv += w * w * (poisson ? a.s_p64 * fmax(xs, 0.0) : a.sigma2_64);
                     }
@@ -366,13 +373,13 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             }
         }
         float C[2][4];
-        float rr[4];  // per-plane risk surrogates r_l, l = 4lg + r
+        // shrinkage factor a_t, estimated signal power and variance per
+        // coefficient, then the risk surrogates (one weight model per call)
+        float at_[2][4], v_[2][4], sh_[2][4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            float t = 0.f;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const bool lv = 4 * lg + r < K;
                 const float Yv = Y[c][r];
                 const float v = fmaxf(V[c][r], 0.f);
                 float at, Cv, shat = 0.f;
@@ -391,34 +398,61 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                     Cv = at * Yv;
                 }
                 C[c][r] = Cv;
-                float tr;
-                if (a.wmodel == BMND_WEIGHT_CLASSIC) tr = at * at;
-                else if (a.wmodel == BMND_WEIGHT_VARIANCE) tr = at * at * v;
-                else tr = at * at * v + (1.f - at) * (1.f - at) * shat;
-                t += lv ? tr : 0.f;
+                at_[c][r] = at;
+                v_[c][r] = v;
+                sh_[c][r] = shat;
             }
-            rr[r] = sum16(t);
+        }
+        float tr[2][4];
+        if (a.wmodel == BMND_WEIGHT_CLASSIC) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) tr[c][r] = at_[c][r] * at_[c][r];
+        } else if (a.wmodel == BMND_WEIGHT_VARIANCE) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) tr[c][r] = at_[c][r] * at_[c][r] * v_[c][r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const float at = at_[c][r];
+                    tr[c][r] = at * at * v_[c][r] + (1.f - at) * (1.f - at) * sh_[c][r];
+                }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool lv = 4 * lg + r < K;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) tr[c][r] = lv ? tr[c][r] : 0.f;
         }
 
         // ---- member weights
         float wA;  // weight of member m16
         if (a.wscope == BMND_SCOPE_GROUP) {
-            float R = rr[0] + rr[1] + rr[2] + rr[3];
-            R += __shfl_xor(R, 16);
-            R += __shfl_xor(R, 32);
+            float t = 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) t += tr[0][r] + tr[1][r];
+            const float R = wave_sum(t);
             wA = R > 0.f ? frcp(R) : 1.f;
         } else {
-            // R_j = sum_l H[l][j]^2 r_l: the scaling row and one detail row
-            // per level hold member j
+            // per-plane surrogates r_l, l = 4lg + r; R_j = sum_l H[l][j]^2 r_l:
+            // the scaling row and one detail row per level hold member j
+            float rr[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) rr[r] = sum16(tr[0][r] + tr[1][r]);
             if (m16 == 0) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) rl[4 * lg + r] = rr[r];
             }
             wsync();
-            float R = rl[0] / float(K);
+            float R = ldexpf(rl[0], -lk);
             for (int t = 0; t < lk; ++t) {
                 const int e = lk - t;
-                R += rl[(1 << t) + (m16 >> e)] / float(1 << e);
+                R += ldexpf(rl[(1 << t) + (m16 >> e)], -e);
             }
             wA = R > 0.f ? frcp(R) : 1.f;
             wsync();
@@ -486,18 +520,29 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             // zeros at the fallback origin).  The lanes of one lane group
             // write 16 distinct samples; lane groups take turns, so no two
             // lanes of one instruction update the same sample.
+            float2 add[4][2];
+            int tl[4][2];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const bool lv = 4 * lg + r < K;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const float ww = lv ? wd[r] * wq[c] : 0.f;
+                    add[r][c] = make_float2(ww * o[c][r], ww);
+                    tl[r][c] = od[r] - wlo + 16 * c + m16;
+                }
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (lg == q) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const bool lv = 4 * lg + r < K;
 #pragma unroll
                         for (int c = 0; c < 2; ++c) {
-                            const int tl = od[r] - wlo + 16 * c + m16;
-                            const float ww = lv ? wd[r] * wq[c] : 0.f;
-                            tnum[tl] += ww * o[c][r];
-                            tden[tl] += ww;
+                            float2 v = tacc[tl[r][c]];
+                            v.x += add[r][c].x;
+                            v.y += add[r][c].y;
+                            tacc[tl[r][c]] = v;
                         }
                         wsync();
                     }
@@ -563,12 +608,12 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     if (acc_tile) {
         wsync();
         for (int i = lane; i < wcap; i += kWave) {
-            const float d = tden[i];
+            const float2 v = tacc[i];
             const int u = wlo + i;
-            if (d != 0.f && u >= 0 && u < g.V) {
+            if (v.y != 0.f && u >= 0 && u < g.V) {
                 // FP64 sums: the float result does not depend on the order
-                unsafeAtomicAdd(&a.numd[vb + u], double(tnum[i]));
-                unsafeAtomicAdd(&a.dend[vb + u], double(d));
+                unsafeAtomicAdd(&a.numd[vb + u], double(v.x));
+                unsafeAtomicAdd(&a.dend[vb + u], double(v.y));
             }
         }
     }
