@@ -81,9 +81,22 @@ def candidates_per_ref(shape, patch, search, refs):
     return n - 1
 
 
-# kernel name fragments of the library's kernels in rocprofv3 output
-KERNEL_SYMBOLS = {"filter_ht": ("k_filter", "<0>"), "filter_wiener": ("k_filter", "<2>"),
-                  "match_ht": ("k_match", "<0,"), "match_wiener": ("k_match", "<3,")}
+# kernel name fragments of the library's kernels in rocprofv3 output (a
+# stage may run two kernels: byte-count matching and its record fallback)
+KERNEL_SYMBOLS = {"filter_ht": [("k_filter_1d", "<0>")],
+                  "filter_wiener": [("k_filter_1d", "<2>")],
+                  "match_ht": [("k_match_1d_u8", ""), ("k_match_1d_rec", ""), ("k_match_1d_f", "<2,"),
+                               ("k_match_nd", "<0,")],
+                  "match_wiener": [("k_match_1d_f", "<3,"), ("k_match_nd", "<3,")]}
+
+
+def kernel_label(kname: str):
+    flat = kname.replace(" ", "")
+    for k, pats in KERNEL_SYMBOLS.items():
+        for frag, tmpl in pats:
+            if frag + "<" in flat and tmpl in flat:
+                return k
+    return None
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 
 
@@ -114,15 +127,14 @@ def summarize_pmc(dbs, copy_mib: int):
                            "group by kernel_name").fetchall()
         grid = dict(grid)
         for kname, cname, total, ndisp in rows:
-            key = None
-            for k, (frag, tmpl) in KERNEL_SYMBOLS.items():
-                if frag in kname and tmpl in kname.replace(" ", ""):
-                    key = k
+            key = kernel_label(kname)
             if key is None and COPY_KERNEL_HINT in kname and grid.get(kname, 0) > (1 << 20):
                 key = "copy"
             if key is None:
                 continue
-            vals.setdefault(key, {})[cname] = float(total) / max(int(ndisp), 1)
+            # per launch of the stage: the stage's kernels summed
+            d = vals.setdefault(key, {})
+            d[cname] = d.get(cname, 0.0) + float(total) / max(int(ndisp), 1)
     out = {"kernel_sources": _kernel_sources_digest(), "copy_probe_mib": copy_mib, "kernels": {}}
     cp = vals.get("copy", {})
     out["copy_probe_kib"] = cp

@@ -499,11 +499,11 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             wd[r] = __shfl(wA, 4 * lg + r);
         }
         // every member of the group inside the accumulation tile (members
-        // past K sit at the staged fallback origin)
+        // past K add zeros at the tile's start instead)
         bool in_tile = acc_tile;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            in_tile = in_tile & (od[r] - wlo >= 0) & (od[r] - wlo + kJ <= wcap);
+            in_tile = in_tile & ((4 * lg + r >= K) | ((od[r] - wlo >= 0) & (od[r] - wlo + kJ <= wcap)));
         if (a.out_mode == 0) {
             float* pout = a.patches + grp * long(a.gmax) * kJ;
 #pragma unroll
@@ -529,7 +529,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                 for (int c = 0; c < 2; ++c) {
                     const float ww = lv ? wd[r] * wq[c] : 0.f;
                     add[r][c] = make_float2(ww * o[c][r], ww);
-                    tl[r][c] = od[r] - wlo + 16 * c + m16;
+                    tl[r][c] = (lv ? od[r] - wlo : 0) + 16 * c + m16;
                 }
             }
 #pragma unroll
