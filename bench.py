@@ -244,6 +244,39 @@ def bench_serving(B, torch, n: int = 60) -> dict:
             "plain_fifo": {k: round(v, 3) for k, v in fifo.items()}}
 
 
+def bench_standard(B, torch, workload: str = "image-2d-128", reps: int = 10) -> dict:
+    """The standard profile (exact shared-source planes k_ex = 4, variance
+    weights in patch scope) beside the plain profile on the same
+    device-resident input."""
+    w = WORKLOADS[workload]
+    y_np, s_p = make_input(workload, w)
+    shape, batch = w["shape"], w["batch"]
+    y = torch.from_numpy(np.ascontiguousarray(y_np)).cuda()
+    geom = B.geometry(shape, batch)
+    noise = B.poisson(s_p)
+    res = {}
+    for name, preset in (("plain", B.PRESET_PLAIN), ("standard", B.PRESET_STANDARD)):
+        p = B.bmnd_params_default(preset, len(shape))
+        for sp in (p.ht, p.wiener):
+            B.set_axes(sp, patch=w["patch"], step=w["step"], search=w["search"])
+        p.ht.group_max, p.wiener.group_max = w["group"]
+        p.ht.mass_conservation, p.wiener.mass_conservation = map(int, w["mc"])
+        ws = torch.empty(B.bmnd_workspace_size(geom, noise, p), dtype=torch.uint8, device="cuda")
+        out = torch.empty_like(y)
+        B.bmnd_denoise(y, geom, noise, p, out, None, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            B.bmnd_denoise(y, geom, noise, p, out, None, ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[name] = {"mvox_per_s": round(batch * int(np.prod(shape)) / dt / 1e6, 3),
+                     "ms": round(dt * 1e3, 3), "k_exact": int(p.ht.k_exact)}
+        del ws, out
+    B.bmnd_stream_status()
+    return {"workload": workload, **res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,10 +406,11 @@ def main():
                "sample": f"{n} of {batch} arrays of the same workload, both stages, "
                          f"{dt:.1f} s single-threaded"}
 
-    batched = serving_row = None
+    batched = serving_row = standard = None
     if args.mixed:
         batched = bench_batched(B, torch)
         serving_row = bench_serving(B, torch)
+        standard = bench_standard(B, torch)
 
     line = {
         "metric": "denoised Mvox/s (both stages)",
@@ -393,6 +427,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "serving": serving_row,
+        "standard_profile": standard,
     }
     print(json.dumps(line), flush=True)
 
