@@ -128,29 +128,76 @@ __device__ __forceinline__ double wave_sum64(double v)
     return v;
 }
 
-// Operand tables in LDS: matrix m (T, U), column block c, depth
-// half h, lane, 4 depth steps; lane (m16, lg) finds its eight B operands
-// for block c at depth 8lg + s, s = 4h + k, as two 16-byte reads.
-__device__ __forceinline__ int opnd_index(int m, int c, int h, int lane)
+// ---- spatial products in split half precision.  An FP32 operand v is
+// scaled by a power of two 2^k (so |v 2^k| < 2^14) and written as
+// hi + lo, hi = fp16(v 2^k), lo = fp16(v 2^k - hi), both rounded to nearest:
+// |v 2^k - hi - lo| <= 2^-22 |v 2^k| (lo below the fp16 normal range loses
+// at most 2^-25 absolutely).  A product a . b over 32 depth steps is
+// ah.bh + (ah.bl + al.bh) on v_mfma_f32_16x16x32_f16 (fp16 products are
+// exact in FP32; the small cross terms accumulate apart from the main
+// term), then unscaled exactly.  Its error is within 2^-21 + 32 u (u =
+// 2^-24) of sum |a_i| |b_i|, which the hard-threshold error band covers.
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f4 mfma_h(h8 a, h8 b, f4 c)
 {
-    return (((m * 2 + c) * 2 + h) * kWave + lane) * 4;
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ void opnd_load(const float* ops, int m, int c, int lane, float* r)
+// 2^(14 - e) for a bound B = m 2^e (0.5 <= m < 1) of the values to split,
+// and its inverse
+__device__ __forceinline__ float split_scale(float bound, float* inv)
 {
-    const float4 u0 = *reinterpret_cast<const float4*>(ops + opnd_index(m, c, 0, lane));
-    const float4 u1 = *reinterpret_cast<const float4*>(ops + opnd_index(m, c, 1, lane));
-    r[0] = u0.x; r[1] = u0.y; r[2] = u0.z; r[3] = u0.w;
-    r[4] = u1.x; r[5] = u1.y; r[6] = u1.z; r[7] = u1.w;
+    int e;
+    (void)frexpf(bound, &e);
+    *inv = ldexpf(1.f, e - 14);
+    return ldexpf(1.f, 14 - e);
 }
 
-template <int SH>
+__device__ __forceinline__ void split8(const float* v, float sc, h8& hi, h8& lo)
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const float t = v[i] * sc;
+        const _Float16 h = (_Float16)t;
+        hi[i] = h;
+        lo[i] = (_Float16)(t - (float)h);
+    }
+}
+
+// sum over the 32 depth steps of (ah + al)(bh + bl), dropping al.bl
+__device__ __forceinline__ f4 mul3(h8 ah, h8 al, h8 bh, h8 bl)
+{
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    const f4 d = mfma_h(ah, bh, z);
+    f4 x = mfma_h(ah, bl, z);
+    x = mfma_h(al, bh, x);
+    return d + x;
+}
+
+// Operand tables in LDS: matrix m (T, T o T, U), part (hi, lo), column
+// block c, lane; lane (m16, lg) holds the eight B operands of block c at
+// depth 8lg + s (one 16-byte read).
+__device__ __forceinline__ int opnd_index(int m, int part, int c, int lane)
+{
+    return (((m * 2 + part) * 2 + c) * kWave + lane) * 8;
+}
+
+__device__ __forceinline__ h8 opnd_h(const _Float16* ops, int m, int part, int c, int lane)
+{
+    return *reinterpret_cast<const h8*>(ops + opnd_index(m, part, c, lane));
+}
+
+// SH: shrinkage; STAGED: 1-D arrays whose chunk windows are staged in LDS;
+// WPLAIN: classic weights in group scope
+template <int SH, bool STAGED, bool WPLAIN>
 __global__ __launch_bounds__(kWave * kWaves) __attribute__((amdgpu_waves_per_eu(3)))
 void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
 {
     const int chunk = sub * kWaves;  // references per workgroup
     constexpr bool wiener = SH == BMND_SHRINK_WIENER;
-    __shared__ __align__(16) float ops[2 * 2 * 2 * kWave * 4];
+    __shared__ __align__(16) _Float16 ops[3 * 2 * 2 * kWave * 8];
+    __shared__ unsigned omax_[3];  // bit patterns of max |T|, |T o T|, |U|
     // Haar operands per group size 2^lk and lane: H[m16][4lg + s] (analysis)
     // and H[4lg + s][m16] (synthesis), s = 0..3
     __shared__ __align__(16) float hops[5][kWave][8];
@@ -169,16 +216,38 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     float* ztr = ztr_[wave];
     float* rl = rl_[wave];
 
-    // ---- operands of the spatial products: T[q][i] and U[i][q] at q (or i)
-    // = 16c + m16 and depth i (or q) = 8lg + s; (T o T) is squared on use
-    for (int e = threadIdx.x; e < 2 * 2 * 2 * kWave * 4; e += kWave * kWaves) {
-        const int k = e & 3;
-        const int ln = (e >> 2) & (kWave - 1);
-        const int h = (e >> 8) & 1;
+    // ---- operands of the spatial products: T[q][i], (T o T)[q][i] and
+    // U[i][q] at q (or i) = 16c + m16 and depth i (or q) = 8lg + s, split
+    // into halves at a power-of-two scale per matrix
+    if (threadIdx.x < 3) omax_[threadIdx.x] = 0u;
+    __syncthreads();
+    {
+        float mt = 0.f, mu = 0.f;
+        for (int e = threadIdx.x; e < kJ * kJ; e += kWave * kWaves) {
+            mt = fmaxf(mt, fabsf(a.t.f32[a.t.T[kAx - 1] + e]));
+            mu = fmaxf(mu, fabsf(a.t.f32[a.t.U[kAx - 1] + e]));
+        }
+        // non-negative floats order as their bit patterns
+        atomicMax(&omax_[0], __float_as_uint(mt));
+        atomicMax(&omax_[1], __float_as_uint(mt * mt));
+        atomicMax(&omax_[2], __float_as_uint(mu));
+    }
+    __syncthreads();
+    float osc[3], oinv[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) osc[m] = split_scale(__uint_as_float(omax_[m]), &oinv[m]);
+    for (int e = threadIdx.x; e < 3 * 2 * kWave * 8; e += kWave * kWaves) {
+        const int k = e & 7;
+        const int ln = (e >> 3) & (kWave - 1);
         const int c = (e >> 9) & 1;
         const int m = e >> 10;
-        const int off = m == 0 ? a.t.T[kAx - 1] : a.t.U[kAx - 1];
-        ops[e] = a.t.f32[off + (16 * c + (ln & 15)) * kJ + 8 * (ln >> 4) + 4 * h + k];
+        const int off = m == 2 ? a.t.U[kAx - 1] : a.t.T[kAx - 1];
+        float v = a.t.f32[off + (16 * c + (ln & 15)) * kJ + 8 * (ln >> 4) + k];
+        if (m == 1) v = v * v;
+        const float t = v * osc[m];
+        const _Float16 h = (_Float16)t;
+        ops[opnd_index(m, 0, c, ln) + k] = h;
+        ops[opnd_index(m, 1, c, ln) + k] = (_Float16)(t - (float)h);
     }
     for (int e = threadIdx.x; e < 5 * kWave; e += kWave * kWaves) {
         const int lk = e / kWave;
@@ -232,375 +301,449 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     for (int i = lane; i < wcap; i += kWave) tacc[i] = make_float2(0.f, 0.f);
     __syncthreads();
 
-    // the next group's size and this lane's entry of its match list are
-    // loaded one group ahead
-    int gi = w0g;
-    int Knext = 0, mnext = 0;
-    if (gi < w1g) {
-        const long grp = long(b) * a.n_refs + gi;
-        Knext = a.count[grp];
-        mnext = a.match[grp * a.gmax + min(m16, a.gmax - 1)];
-    }
-    for (; gi < w1g; ++gi) {
-        const long grp = long(b) * a.n_refs + gi;
-        const int K = safe_count(Knext, a.gmax);
-        const int mv0 = safe_origin(mnext, omax);
-        if (gi + 1 < w1g) {
-            const long gn = grp + 1;
-            Knext = a.count[gn];
-            mnext = a.match[gn * a.gmax + min(m16, a.gmax - 1)];
-        }
-        const int lk = 31 - __clz(K);
-        const bool av = m16 < K;  // this lane's member in the A layout
+    // ---- front end of one group: its size and origin, the gather of its
+    // samples (and pilot) and the forward products on the matrix cores.
+    // The loop below runs the front end of group gi + 1 in the same basic
+    // block as the shrinkage of group gi, so the scheduler interleaves the
+    // matrix-core chain of one with the vector work of the other.
+    struct Front {
+        f4 Y[2], V[2], G[2];
+        float gn;   // norm of the group's samples
+        int K, lk, oa;
+        bool ok;    // every lane's samples came from the staged range
+    };
+    auto front = [&](int kraw, int mraw, bool lds) __attribute__((always_inline)) -> Front {
+        Front f;
+        f.K = safe_count(kraw, a.gmax);
+        f.lk = 31 - __clz(f.K);
+        const bool av = m16 < f.K;  // this lane's member in the A layout
         // lanes past K read the samples at a valid origin inside the staged
         // range (tile_lo <= the chunk's first reference) and drop them
-        const int oa = av ? mv0 : safe_origin(tile_lo, omax);
-
-        // ---- gather: samples, variance map (from y, or from the pilot)
+        f.oa = av ? safe_origin(mraw, omax) : safe_origin(tile_lo, omax);
         float x[8], pv[8], mv[8];
-        const int ol = oa - tile_lo + 8 * lg;
-        if (__all(ol >= 0 && ol + 8 <= tile_cap)) {
+        f.ok = true;
+        if (lds) {
+            // clamped reads keep the block branch-free; a group reaching
+            // outside the staged range is redone from global memory
+            const int ol = f.oa - tile_lo + 8 * lg;
+            f.ok = __all(ol >= 0 && ol + 8 <= tile_cap);
+            const int olc = max(min(ol, tile_cap - 8), 0);
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                x[s] = ysm[ol + s];
-                pv[s] = wiener ? psm[ol + s] : 0.f;
+                x[s] = ysm[olc + s];
+                pv[s] = wiener ? psm[olc + s] : 0.f;
             }
         } else {
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                x[s] = yb[oa + 8 * lg + s];
-                pv[s] = wiener ? pb[oa + 8 * lg + s] : 0.f;
+                x[s] = yb[f.oa + 8 * lg + s];
+                pv[s] = wiener ? pb[f.oa + 8 * lg + s] : 0.f;
             }
         }
-        float gn2 = 0.f;
+        float gn2 = 0.f, gp2 = 0.f;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             x[s] = av ? x[s] : 0.f;
             pv[s] = av ? pv[s] : 0.f;
             gn2 = __builtin_fmaf(x[s], x[s], gn2);
+            if constexpr (wiener) gp2 = __builtin_fmaf(pv[s], pv[s], gp2);
             const float src = wiener ? pv[s] : x[s];
             mv[s] = av ? (poisson ? a.s_p * fmaxf(src, 0.f) : a.sigma2) : 0.f;
         }
-
-        // ---- analysis: spatial rows 16c + m16 of every member, then Haar over
-        // the members with A[row m16][depth (lg, s)] = H[m16][4lg + s]
-        float ha[4], h2[4], hi[4];
+        f.gn = fsqrt(wave_sum(gn2));
+        // split operands; the group norms bound every entry
+        h8 xh, xl, mh, ml, ph, pl;
+        float ix, ip = 1.f, im;
+        split8(x, split_scale(f.gn, &ix), xh, xl);
+        float gp = 0.f;
+        if constexpr (wiener) {
+            gp = fsqrt(wave_sum(gp2));
+            split8(pv, split_scale(gp, &ip), ph, pl);
+        }
+        split8(mv, split_scale(poisson ? a.s_p * (wiener ? gp : f.gn) : a.sigma2, &im), mh, ml);
+        const float uy = oinv[0] * ix, uv = oinv[1] * im, up = oinv[0] * ip;
+        // ---- analysis: spatial rows 16c + m16 of every member, then Haar
+        // over the members with A[row m16][depth (lg, s)] = H[m16][4lg + s]
+        float ha[4], h2[4];
         {
-            const float4 u0 = *reinterpret_cast<const float4*>(&hops[lk][lane][0]);
-            const float4 u1 = *reinterpret_cast<const float4*>(&hops[lk][lane][4]);
+            const float4 u0 = *reinterpret_cast<const float4*>(&hops[f.lk][lane][0]);
             ha[0] = u0.x; ha[1] = u0.y; ha[2] = u0.z; ha[3] = u0.w;
-            hi[0] = u1.x; hi[1] = u1.y; hi[2] = u1.z; hi[3] = u1.w;
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) h2[s] = ha[s] * ha[s];
-        f4 Y[2], V[2], G[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            float tb[8];
-            f4 y1 = {0.f, 0.f, 0.f, 0.f}, v1 = y1, p1 = y1;
-            opnd_load(ops, 0, c, lane, tb);
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                y1 = mfma(x[s], tb[s], y1);
-                if constexpr (wiener) p1 = mfma(pv[s], tb[s], p1);
-            }
-#pragma unroll
-            for (int s = 0; s < 8; ++s) v1 = mfma(mv[s], tb[s] * tb[s], v1);
-            Y[c] = V[c] = G[c] = f4{0.f, 0.f, 0.f, 0.f};
+            const h8 th = opnd_h(ops, 0, 0, c, lane), tl = opnd_h(ops, 0, 1, c, lane);
+            const f4 y1 = mul3(xh, xl, th, tl) * uy;
+            const f4 v1 = mul3(mh, ml, opnd_h(ops, 1, 0, c, lane), opnd_h(ops, 1, 1, c, lane)) * uv;
+            f4 p1 = {0.f, 0.f, 0.f, 0.f};
+            if constexpr (wiener) p1 = mul3(ph, pl, th, tl) * up;
+            f.Y[c] = f.V[c] = f.G[c] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                Y[c] = mfma(ha[s], y1[s], Y[c]);
-                V[c] = mfma(h2[s], v1[s], V[c]);
-                if constexpr (wiener) G[c] = mfma(ha[s], p1[s], G[c]);
+                f.Y[c] = mfma(ha[s], y1[s], f.Y[c]);
+                f.V[c] = mfma(h2[s], v1[s], f.V[c]);
+                if constexpr (wiener) f.G[c] = mfma(ha[s], p1[s], f.G[c]);
             }
         }
+        return f;
+    };
 
-        // ---- shrinkage; coefficient (c, r), bit 4c + r: Haar row 4lg + r,
-        // spatial row 16c + m16
-        unsigned keep = 0, near = 0;
-        if constexpr (SH == BMND_SHRINK_HARD) {
-            const float gn = sqrtf(wave_sum(gn2));
+    const long grp_base = long(b) * a.n_refs;
+    // group gidx's size and this lane's entry of its match list
+    auto list = [&](int gidx, int& kr, int& mr) __attribute__((always_inline)) {
+        const long grp = grp_base + gidx;
+        kr = a.count[grp];
+        mr = a.match[grp * a.gmax + min(m16, a.gmax - 1)];
+    };
+    if (w0g < w1g) {
+        int kr0, mr0, kr1, mr1;
+        list(w0g, kr0, mr0);
+        list(min(w0g + 1, w1g - 1), kr1, mr1);
+        Front F = front(kr0, mr0, STAGED);
+        if (!F.ok) F = front(kr0, mr0, false);
+        for (int gi = w0g; gi < w1g; ++gi) {
+            const long grp = grp_base + gi;
+            const int K = F.K, lk = F.lk, oa = F.oa;
+            // ---- block A: the next group's front end (the last group
+            // repeats itself) beside this group's shrinkage; the match-list
+            // entries are loaded two groups ahead
+            Front N = front(kr1, mr1, STAGED);
+            const int krn = kr1, mrn = mr1;
+            list(min(gi + 2, w1g - 1), kr1, mr1);
+
+            // shrinkage; coefficient (c, r), bit 4c + r: Haar row 4lg + r,
+            // spatial row 16c + m16
+            float C[2][4], at_[2][4], v_[2][4], sh_[2][4];
+            unsigned keep = 0, near = 0;
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
+            for (int r = 0; r < 4; ++r) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float Yv = Y[c][r];
-                    const float v = fmaxf(V[c][r], 0.f);
-                    const float thr = a.lambda * fsqrt(v);
-                    const bool lv = 4 * lg + r < K;
-                    const bool kp = lv & (fabsf(Yv) > thr);
+                for (int c = 0; c < 2; ++c) {
+                    const float Yv = F.Y[c][r];
+                    const float v = fmaxf(F.V[c][r], 0.f);
+                    float at = 0.f, Cv = 0.f, shat = 0.f;
+                    if constexpr (SH == BMND_SHRINK_SOFT) {
+                        const float m = fmaxf(fabsf(Yv) - a.lambda * fsqrt(v), 0.f);
+                        Cv = Yv > 0.f ? m : (Yv < 0.f ? -m : 0.f);
+                        at = Yv != 0.f ? m * frcp(fabsf(Yv)) : 0.f;
+                    } else if constexpr (SH == BMND_SHRINK_WIENER) {
+                        const float gam = F.G[c][r];
+                        shat = fmaxf(gam * gam - a.power_a * v, 0.f);
+                        const float den = shat + a.s_v * v;
+                        at = den > 0.f ? shat * frcp(den) : 0.f;
+                        Cv = at * Yv;
+                    }
+                    C[c][r] = Cv;
+                    at_[c][r] = at;
+                    v_[c][r] = v;
+                    sh_[c][r] = shat;
+                }
+            }
+            float gn = 0.f;
+            if constexpr (SH == BMND_SHRINK_HARD) {
+                gn = F.gn;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
                     // FP32 error band of the decision (transform and square
                     // root round-off are bounded by the row norm times the
                     // group norm, and by the threshold)
-                    const bool nr = lv & (v > 0.f) &
-                                    (fabsf(fabsf(Yv) - thr) <= 1e-5f * (rq[c] * gn + thr));
-                    keep |= unsigned(kp) << (4 * c + r);
-                    near |= unsigned(nr) << (4 * c + r);
-                }
-            // FP64 decisions for the coefficients in the error band, one at a time
-            for (;;) {
-                const unsigned long long mk = __ballot(near != 0);
-                if (mk == 0) break;
-                const int src = __ffsll(mk) - 1;
-                const int bit = __ffs(__shfl(int(near), src)) - 1;
-                const int l = 4 * (src >> 4) + (bit & 3);
-                const int q = 16 * (bit >> 2) + (src & 15);
-                // opaque copies keep the FP64 set-up inside this rarely
-                // taken loop (the compiler would otherwise hoist it into
-                // every group)
-                int lkv = lk;
-                asm volatile("" : "+v"(lkv));
-                const double h = haar_d(lkv, l, m16);
-                double sy = 0.0, sv = 0.0;
-                if (av) {
-                    for (int s = 0; s < 8; ++s) {
-                        float xv = x[s];
-                        asm volatile("" : "+v"(xv));
-                        const double w = h * T64[q * kJ + 8 * lg + s];
-                        const double xs = double(xv);
-                        sy += w * xs;
-                        sv += w * w * (poisson ? a.s_p64 * fmax(xs, 0.0) : a.sigma2_64);
-                    }
-                }
-                sy = wave_sum64(sy);
-                sv = wave_sum64(sv);
-                // strict inequality with the 1e-9 relative tie margin
-                const bool kp = fabs(sy) > a.lambda64 * sqrt(sv) * (1.0 + 1e-9);
-                if (lane == src) {
-                    near &= ~(1u << bit);
-                    keep = kp ? (keep | (1u << bit)) : (keep & ~(1u << bit));
-                }
-            }
-        }
-        float C[2][4];
-        // shrinkage factor a_t, estimated signal power and variance per
-        // coefficient, then the risk surrogates (one weight model per call)
-        float at_[2][4], v_[2][4], sh_[2][4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const float Yv = Y[c][r];
-                const float v = fmaxf(V[c][r], 0.f);
-                float at, Cv, shat = 0.f;
-                if constexpr (SH == BMND_SHRINK_HARD) {
-                    at = (keep >> (4 * c + r)) & 1u ? 1.f : 0.f;
-                    Cv = at != 0.f ? Yv : 0.f;
-                } else if constexpr (SH == BMND_SHRINK_SOFT) {
-                    const float m = fmaxf(fabsf(Yv) - a.lambda * fsqrt(v), 0.f);
-                    Cv = Yv > 0.f ? m : (Yv < 0.f ? -m : 0.f);
-                    at = Yv != 0.f ? m * frcp(fabsf(Yv)) : 0.f;
-                } else {
-                    const float gam = G[c][r];
-                    shat = fmaxf(gam * gam - a.power_a * v, 0.f);
-                    const float den = shat + a.s_v * v;
-                    at = den > 0.f ? shat * frcp(den) : 0.f;
-                    Cv = at * Yv;
-                }
-                C[c][r] = Cv;
-                at_[c][r] = at;
-                v_[c][r] = v;
-                sh_[c][r] = shat;
-            }
-        }
-        float tr[2][4];
-        if (a.wmodel == BMND_WEIGHT_CLASSIC) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) tr[c][r] = at_[c][r] * at_[c][r];
-        } else if (a.wmodel == BMND_WEIGHT_VARIANCE) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) tr[c][r] = at_[c][r] * at_[c][r] * v_[c][r];
-        } else {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const float at = at_[c][r];
-                    tr[c][r] = at * at * v_[c][r] + (1.f - at) * (1.f - at) * sh_[c][r];
-                }
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const bool lv = 4 * lg + r < K;
-#pragma unroll
-            for (int c = 0; c < 2; ++c) tr[c][r] = lv ? tr[c][r] : 0.f;
-        }
-
-        // ---- member weights
-        float wA;  // weight of member m16
-        if (a.wscope == BMND_SCOPE_GROUP) {
-            float t = 0.f;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) t += tr[0][r] + tr[1][r];
-            const float R = wave_sum(t);
-            wA = R > 0.f ? frcp(R) : 1.f;
-        } else {
-            // per-plane surrogates r_l, l = 4lg + r; R_j = sum_l H[l][j]^2 r_l:
-            // the scaling row and one detail row per level hold member j
-            float rr[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) rr[r] = sum16(tr[0][r] + tr[1][r]);
-            if (m16 == 0) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) rl[4 * lg + r] = rr[r];
-            }
-            wsync();
-            float R = ldexpf(rl[0], -lk);
-            for (int t = 0; t < lk; ++t) {
-                const int e = lk - t;
-                R += ldexpf(rl[(1 << t) + (m16 >> e)], -e);
-            }
-            wA = R > 0.f ? frcp(R) : 1.f;
-            wsync();
-        }
-
-        // ---- synthesis: Z = H^T C (A[row m16][depth (lg, s)] = H[4lg + s][m16]) ...
-        f4 Z[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            Z[c] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int s = 0; s < 4; ++s) Z[c] = mfma(hi[s], C[c][s], Z[c]);
-        }
-        // ... through LDS into the A layout, then X^ = Z U^T
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) ztr[(4 * lg + r) * kZs + 16 * c + m16] = Z[c][r];
-        wsync();
-        float za[8];
-        {
-            const float4 u0 = *reinterpret_cast<const float4*>(ztr + m16 * kZs + 8 * lg);
-            const float4 u1 = *reinterpret_cast<const float4*>(ztr + m16 * kZs + 8 * lg + 4);
-            za[0] = u0.x; za[1] = u0.y; za[2] = u0.z; za[3] = u0.w;
-            za[4] = u1.x; za[5] = u1.y; za[6] = u1.z; za[7] = u1.w;
-        }
-        wsync();
-        f4 o[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            float ub[8];
-            opnd_load(ops, 1, c, lane, ub);
-            o[c] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int s = 0; s < 8; ++s) o[c] = mfma(za[s], ub[s], o[c]);
-        }
-
-        // ---- outputs; o[c][r] is sample 16c + m16 of member 4lg + r
-        int od[4];
-        float wd[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            od[r] = __shfl(oa, 4 * lg + r);
-            wd[r] = __shfl(wA, 4 * lg + r);
-        }
-        // every member of the group inside the accumulation tile (members
-        // past K add zeros at the tile's start instead)
-        bool in_tile = acc_tile;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            in_tile = in_tile & ((4 * lg + r >= K) | ((od[r] - wlo >= 0) & (od[r] - wlo + kJ <= wcap)));
-        if (a.out_mode == 0) {
-            float* pout = a.patches + grp * long(a.gmax) * kJ;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int k = 4 * lg + r;
-                if (k < a.gmax) {
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) pout[k * kJ + 16 * c + m16] = k < K ? o[c][r] : 0.f;
-                }
-            }
-            if (lane < a.gmax) a.weights[grp * a.gmax + lane] = lane < K ? wA : 0.f;
-        } else if (a.out_mode == 1 && __all(in_tile)) {
-            // every member inside this wavefront's tile (members past K add
-            // zeros at the fallback origin).  The lanes of one lane group
-            // write 16 distinct samples; lane groups take turns, so no two
-            // lanes of one instruction update the same sample.
-            float2 add[4][2];
-            int tl[4][2];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const bool lv = 4 * lg + r < K;
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const float ww = lv ? wd[r] * wq[c] : 0.f;
-                    add[r][c] = make_float2(ww * o[c][r], ww);
-                    tl[r][c] = (lv ? od[r] - wlo : 0) + 16 * c + m16;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (lg == q) {
+                    const float e = rq[c] * gn;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
+                        const float Yv = F.Y[c][r];
+                        const float v = v_[c][r];
+                        const float thr = a.lambda * fsqrt(v);
+                        const bool lv = 4 * lg + r < K;
+                        const bool kp = lv & (fabsf(Yv) > thr);
+                        const bool nr = lv & (v > 0.f) & (fabsf(fabsf(Yv) - thr) <= 1e-5f * (e + thr));
+                        keep |= unsigned(kp) << (4 * c + r);
+                        near |= unsigned(nr) << (4 * c + r);
+                    }
+                }
+            }
+
+            if constexpr (SH == BMND_SHRINK_HARD) {
+                // FP64 decisions for the coefficients in the error band, one
+                // at a time, from the group's samples read again
+                if (__any(near != 0)) {
+                    float x[8];
+                    {
+                        const bool av = m16 < K;
+                        const int ol = oa - tile_lo + 8 * lg;
+                        const bool lds = STAGED && __all(ol >= 0 && ol + 8 <= tile_cap);
+#pragma unroll
+                        for (int s = 0; s < 8; ++s) {
+                            const float xs = lds ? ysm[max(min(ol, tile_cap - 8), 0) + s]
+                                                 : yb[oa + 8 * lg + s];
+                            x[s] = av ? xs : 0.f;
+                        }
+                    }
+                    for (;;) {
+                        const unsigned long long mk = __ballot(near != 0);
+                        if (mk == 0) break;
+                        const int src = __ffsll(mk) - 1;
+                        const int bit = __ffs(__shfl(int(near), src)) - 1;
+                        const int l = 4 * (src >> 4) + (bit & 3);
+                        const int q = 16 * (bit >> 2) + (src & 15);
+                        // opaque copies keep the FP64 set-up inside this
+                        // rarely taken loop
+                        int lkv = lk;
+                        asm volatile("" : "+v"(lkv));
+                        const double h = haar_d(lkv, l, m16);
+                        double sy = 0.0, sv = 0.0;
+                        if (m16 < K) {
+                            for (int s = 0; s < 8; ++s) {
+                                float xv = x[s];
+                                asm volatile("" : "+v"(xv));
+                                const double w = h * T64[q * kJ + 8 * lg + s];
+                                const double xs = double(xv);
+                                sy += w * xs;
+                                sv += w * w * (poisson ? a.s_p64 * fmax(xs, 0.0) : a.sigma2_64);
+                            }
+                        }
+                        sy = wave_sum64(sy);
+                        sv = wave_sum64(sv);
+                        // strict inequality with the 1e-9 relative tie margin
+                        const bool kp = fabs(sy) > a.lambda64 * sqrt(sv) * (1.0 + 1e-9);
+                        if (lane == src) {
+                            near &= ~(1u << bit);
+                            keep = kp ? (keep | (1u << bit)) : (keep & ~(1u << bit));
+                        }
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const float at = (keep >> (4 * c + r)) & 1u ? 1.f : 0.f;
+                        at_[c][r] = at;
+                        C[c][r] = at != 0.f ? F.Y[c][r] : 0.f;
+                    }
+            }
+
+            // ---- block C: risk surrogates and weights beside the synthesis
+            // products.  Synthesis: Z = H^T C (A[row m16][depth (lg, s)] =
+            // H[4lg + s][m16]) ...
+            float hi[4];
+            {
+                const float4 u1 = *reinterpret_cast<const float4*>(&hops[lk][lane][4]);
+                hi[0] = u1.x; hi[1] = u1.y; hi[2] = u1.z; hi[3] = u1.w;
+            }
+            f4 Z[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                Z[c] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < 4; ++s) Z[c] = mfma(hi[s], C[c][s], Z[c]);
+            }
+            float wA;  // weight of member m16
+            if constexpr (WPLAIN) {
+                // classic model, group scope: R = sum of a_t^2 over the group
+                float t = 0.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const bool lv = 4 * lg + r < K;
+                    t += lv ? at_[0][r] * at_[0][r] + at_[1][r] * at_[1][r] : 0.f;
+                }
+                const float R = wave_sum(t);
+                wA = R > 0.f ? frcp(R) : 1.f;
+            } else {
+                float tr[2][4];
+                if (a.wmodel == BMND_WEIGHT_CLASSIC) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) tr[c][r] = at_[c][r] * at_[c][r];
+                } else if (a.wmodel == BMND_WEIGHT_VARIANCE) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) tr[c][r] = at_[c][r] * at_[c][r] * v_[c][r];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
 #pragma unroll
                         for (int c = 0; c < 2; ++c) {
-                            float2 v = tacc[tl[r][c]];
-                            v.x += add[r][c].x;
-                            v.y += add[r][c].y;
-                            tacc[tl[r][c]] = v;
+                            const float at = at_[c][r];
+                            tr[c][r] = at * at * v_[c][r] + (1.f - at) * (1.f - at) * sh_[c][r];
                         }
-                        wsync();
-                    }
                 }
-                wsync();
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const bool lv = 4 * lg + r < K;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) tr[c][r] = lv ? tr[c][r] : 0.f;
+                }
+                if (a.wscope == BMND_SCOPE_GROUP) {
+                    float t = 0.f;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) t += tr[0][r] + tr[1][r];
+                    const float R = wave_sum(t);
+                    wA = R > 0.f ? frcp(R) : 1.f;
+                } else {
+                    // per-plane surrogates r_l, l = 4lg + r; R_j = sum_l
+                    // H[l][j]^2 r_l: the scaling row and one detail row per
+                    // level hold member j
+                    float rr[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) rr[r] = sum16(tr[0][r] + tr[1][r]);
+                    if (m16 == 0) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) rl[4 * lg + r] = rr[r];
+                    }
+                    wsync();
+                    float R = ldexpf(rl[0], -lk);
+                    for (int t = 0; t < lk; ++t) {
+                        const int e = lk - t;
+                        R += ldexpf(rl[(1 << t) + (m16 >> e)], -e);
+                    }
+                    wA = R > 0.f ? frcp(R) : 1.f;
+                    wsync();
+                }
             }
-        } else if (a.out_mode == 1) {
+            // ... through LDS into the A layout, then X^ = Z U^T
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ztr[(4 * lg + r) * kZs + 16 * c + m16] = Z[c][r];
+            wsync();
+            float za[8];
+            {
+                const float4 u0 = *reinterpret_cast<const float4*>(ztr + m16 * kZs + 8 * lg);
+                const float4 u1 = *reinterpret_cast<const float4*>(ztr + m16 * kZs + 8 * lg + 4);
+                za[0] = u0.x; za[1] = u0.y; za[2] = u0.z; za[3] = u0.w;
+                za[4] = u1.x; za[5] = u1.y; za[6] = u1.z; za[7] = u1.w;
+            }
+            wsync();
+            // |Z| <= ||Z||_F = ||C||_F (the Haar block is orthonormal)
+            float c2 = 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) c2 += C[0][r] * C[0][r] + C[1][r] * C[1][r];
+            float iz;
+            const float scz = split_scale(fsqrt(wave_sum(c2)), &iz);
+            h8 zh, zl;
+            split8(za, scz, zh, zl);
+            const float uz = oinv[2] * iz;
+            f4 o[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                o[c] = mul3(zh, zl, opnd_h(ops, 2, 0, c, lane), opnd_h(ops, 2, 1, c, lane)) * uz;
+
+            // ---- outputs; o[c][r] is sample 16c + m16 of member 4lg + r
+            int od[4];
+            float wd[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                if (4 * lg + r < K) {
+                od[r] = __shfl(oa, 4 * lg + r);
+                wd[r] = __shfl(wA, 4 * lg + r);
+            }
+            // every member of the group inside the accumulation tile (members
+            // past K add zeros at the tile's start instead)
+            bool in_tile = acc_tile;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                in_tile = in_tile & ((4 * lg + r >= K) | ((od[r] - wlo >= 0) & (od[r] - wlo + kJ <= wcap)));
+            if (a.out_mode == 0) {
+                float* pout = a.patches + grp * long(a.gmax) * kJ;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 4 * lg + r;
+                    if (k < a.gmax) {
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) pout[k * kJ + 16 * c + m16] = k < K ? o[c][r] : 0.f;
+                    }
+                }
+                if (lane < a.gmax) a.weights[grp * a.gmax + lane] = lane < K ? wA : 0.f;
+            } else if (a.out_mode == 1 && __all(in_tile)) {
+                // every member inside this wavefront's tile (members past K add
+                // zeros at the fallback origin).  The lanes of one lane group
+                // write 16 distinct samples; lane groups take turns, so no two
+                // lanes of one instruction update the same sample.
+                float2 add[4][2];
+                int tl[4][2];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const bool lv = 4 * lg + r < K;
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
-                        const int u = od[r] + 16 * c + m16;
-                        const float ww = wd[r] * wq[c];
-                        unsafeAtomicAdd(&a.numd[vb + u], double(ww * o[c][r]));
-                        unsafeAtomicAdd(&a.dend[vb + u], double(ww));
+                        const float ww = lv ? wd[r] * wq[c] : 0.f;
+                        add[r][c] = make_float2(ww * o[c][r], ww);
+                        tl[r][c] = (lv ? od[r] - wlo : 0) + 16 * c + m16;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (lg == q) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+                            for (int c = 0; c < 2; ++c) {
+                                float2 v = tacc[tl[r][c]];
+                                v.x += add[r][c].x;
+                                v.y += add[r][c].y;
+                                tacc[tl[r][c]] = v;
+                            }
+                            wsync();
+                        }
+                    }
+                    wsync();
+                }
+            } else if (a.out_mode == 1) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (4 * lg + r < K) {
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const int u = od[r] + 16 * c + m16;
+                            const float ww = wd[r] * wq[c];
+                            unsafeAtomicAdd(&a.numd[vb + u], double(ww * o[c][r]));
+                            unsafeAtomicAdd(&a.dend[vb + u], double(ww));
+                        }
+                    }
+                }
+            } else if (a.out_mode == 2) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (4 * lg + r < K) {
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const long u = vb + od[r] + 16 * c + m16;
+                            unsafeAtomicAdd(&a.dend[u], double(wd[r]) * double(wq[c]));
+                        }
+                    }
+                }
+            } else {
+                double zs = 0.0, zr = 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (4 * lg + r < K) {
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const long u = vb + od[r] + 16 * c + m16;
+                            const double zeta = double(wd[r]) * double(wq[c]) / a.dend[u];
+                            zs += zeta;
+                            zr += zeta * (double(a.y[u]) - double(o[c][r]));
+                        }
+                    }
+                }
+                zs = wave_sum64(zs);
+                zr = wave_sum64(zr);
+                const double alpha = zs > 0.0 ? zr / zs : 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (4 * lg + r < K) {
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const long u = vb + od[r] + 16 * c + m16;
+                            unsafeAtomicAdd(&a.numd[u], double(wd[r]) * double(wq[c]) *
+                                                            (double(o[c][r]) + alpha));
+                        }
                     }
                 }
             }
-        } else if (a.out_mode == 2) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (4 * lg + r < K) {
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const long u = vb + od[r] + 16 * c + m16;
-                        unsafeAtomicAdd(&a.dend[u], double(wd[r]) * double(wq[c]));
-                    }
-                }
-            }
-        } else {
-            double zs = 0.0, zr = 0.0;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (4 * lg + r < K) {
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const long u = vb + od[r] + 16 * c + m16;
-                        const double zeta = double(wd[r]) * double(wq[c]) / a.dend[u];
-                        zs += zeta;
-                        zr += zeta * (double(a.y[u]) - double(o[c][r]));
-                    }
-                }
-            }
-            zs = wave_sum64(zs);
-            zr = wave_sum64(zr);
-            const double alpha = zs > 0.0 ? zr / zs : 0.0;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (4 * lg + r < K) {
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const long u = vb + od[r] + 16 * c + m16;
-                        unsafeAtomicAdd(&a.numd[u], double(wd[r]) * double(wq[c]) *
-                                                        (double(o[c][r]) + alpha));
-                    }
-                }
-            }
+            if (!N.ok) N = front(krn, mrn, false);
+            F = N;
         }
     }
 
@@ -637,10 +780,12 @@ hipError_t launch_filter_1d(const FilterArgs& a, int step_last, hipStream_t s)
     int tile_cap = 0, tile_back = 0, wcap = 0;
     const bool one_d = g.L[0] == 1 && g.L[1] == 1 && g.L[2] == 1;
     const int nstage = a.shrink == BMND_SHRINK_WIENER ? 2 : 1;  // staged arrays
-    // references per wavefront: up to kSubMax, fewer for small arrays so
-    // that the launch still fills the device
+    // references per wavefront: up to kSubMax (two thirds of it with a
+    // staged pilot, so that three workgroups share a compute unit's LDS),
+    // fewer for small arrays so that the launch still fills the device
     const long groups = long(a.n_refs) * g.batch;
-    const int sub = int(std::max(1L, std::min<long>(kSubMax, groups / kTargetWaves)));
+    const int sub_max = nstage == 2 ? 2 * kSubMax / 3 : kSubMax;
+    const int sub = int(std::max(1L, std::min<long>(sub_max, groups / kTargetWaves)));
     const int chunk = sub * kWaves;
     if (one_d) {
         const int st = max(step_last, 1);
@@ -653,15 +798,23 @@ hipError_t launch_filter_1d(const FilterArgs& a, int step_last, hipStream_t s)
     const int nchunk = (a.n_refs + chunk - 1) / chunk;
     const dim3 grid(unsigned(long(nchunk) * g.batch));
     const size_t lds = sizeof(float) * size_t(kWaves * 2 * wcap + nstage * tile_cap);
-    if (a.shrink == BMND_SHRINK_HARD)
-        hipLaunchKernelGGL(k_filter_1d<BMND_SHRINK_HARD>, grid, dim3(kWave * kWaves), lds, s, a,
-                           sub, tile_cap, tile_back, wcap);
-    else if (a.shrink == BMND_SHRINK_SOFT)
-        hipLaunchKernelGGL(k_filter_1d<BMND_SHRINK_SOFT>, grid, dim3(kWave * kWaves), lds, s, a,
-                           sub, tile_cap, tile_back, wcap);
-    else
-        hipLaunchKernelGGL(k_filter_1d<BMND_SHRINK_WIENER>, grid, dim3(kWave * kWaves), lds, s, a,
-                           sub, tile_cap, tile_back, wcap);
+    const bool staged = tile_cap >= 8;
+    const bool wplain = a.wmodel == BMND_WEIGHT_CLASSIC && a.wscope == BMND_SCOPE_GROUP;
+#define BMND_F1D(SH, ST, WP)                                                                     \
+    hipLaunchKernelGGL((k_filter_1d<SH, ST, WP>), grid, dim3(kWave * kWaves), lds, s, a, sub,   \
+                       tile_cap, tile_back, wcap)
+#define BMND_F1D_SH(SH)                                                                          \
+    do {                                                                                         \
+        if (staged && wplain) BMND_F1D(SH, true, true);                                          \
+        else if (staged) BMND_F1D(SH, true, false);                                              \
+        else if (wplain) BMND_F1D(SH, false, true);                                              \
+        else BMND_F1D(SH, false, false);                                                         \
+    } while (0)
+    if (a.shrink == BMND_SHRINK_HARD) BMND_F1D_SH(BMND_SHRINK_HARD);
+    else if (a.shrink == BMND_SHRINK_SOFT) BMND_F1D_SH(BMND_SHRINK_SOFT);
+    else BMND_F1D_SH(BMND_SHRINK_WIENER);
+#undef BMND_F1D_SH
+#undef BMND_F1D
     return hipGetLastError();
 }
 

@@ -579,3 +579,44 @@ def test_count_match_lists_bit_exact_1d(case):
     mo, co, _, _ = O.match(ht, O.STAGE_HT, y, y, refs)
     assert np.array_equal(cg[0], co)
     assert np.array_equal(mg[0], mo)
+
+
+# ------------------------------- 1-D filter: lists reaching outside the stage
+
+@pytest.mark.parametrize("stage", ["ht", "wiener"])
+def test_filter_1d_far_members(stage):
+    """Members anywhere in the signal (outside the workgroup's staged
+    samples) and group sizes 1..16: the matrix-core filter redoes such groups
+    from global memory; patches and weights match the oracle's."""
+    _say(f"1-D filter, far members, {stage}")
+    L = 12000
+    s = synth.ecg_batch(n_signals=1, length=L, seed=2500)
+    shape, patch, step, search = (L,), (32,), (4,), (256,)
+    p = params_for(shape, patch, step, search, group=(16, 16))
+    ht, wie = oracle_stages(shape, patch, step, search, s.s_p, group=(16, 16))
+    geom = B.geometry(shape)
+    refs = B.bmnd_reference_origins(geom, p.ht)
+    rng = np.random.default_rng(91)
+    n = len(refs)
+    match = np.full((1, n, 16), -1, np.int32)
+    count = np.zeros((1, n), np.int32)
+    for g in range(n):
+        K = int(2 ** rng.integers(0, 5))
+        others = rng.choice(L - 31, size=K - 1, replace=False) if g % 3 else \
+            np.clip(refs[g] + rng.integers(-100, 100, size=K - 1), 0, L - 32)
+        match[0, g, 0] = refs[g]
+        match[0, g, 1:K] = others
+        count[0, g] = K
+    y = s.y[0].astype(np.float32)
+    pilot = np.asarray(s.x[0], np.float32) if stage == "wiener" else None
+    st_id = B.STAGE_WIENER if stage == "wiener" else B.STAGE_HT
+    sp = p.wiener if stage == "wiener" else p.ht
+    pg, wg = gpu_filter(st_id, dev(y[None]), None if pilot is None else dev(pilot[None]), geom,
+                        B.poisson(s.s_p), sp, match, count)
+    po, wo = O.filter(wie if stage == "wiener" else ht,
+                      O.STAGE_WIENER if stage == "wiener" else O.STAGE_HT, y, pilot, match[0], count[0])
+    for g in range(n):
+        K = count[0, g]
+        scale = max(np.abs(po[g, :K]).max(), 1e-30)
+        assert np.abs(pg[0, g, :K] - po[g, :K]).max() <= REL_PATCH * scale, g
+        assert np.allclose(wg[0, g, :K], wo[g, :K], rtol=1e-5), g
