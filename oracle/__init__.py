@@ -29,6 +29,8 @@ SHRINK = {"hard": 0, "soft": 1, "wiener": 2}
 WMODEL = {"classic": 0, "variance": 1, "risk": 2}
 WSCOPE = {"group": 0, "patch": 1}
 NOISE = {"gaussian": 0, "poisson": 1}
+METRIC = {"ssd": 0, "deviance": 1, "pearson": 2, "anscombe": 3}
+POLICY = {"fixed": 0, "reference": 1, "standardized": 2}
 STAGE_HT, STAGE_WIENER = 0, 1
 
 
@@ -55,6 +57,8 @@ class _Cfg(C.Structure):
         ("kaiser_beta", C.c_double),
         ("noise_kind", C.c_int32), ("counts_integral", C.c_int32),
         ("sigma", C.c_double), ("s_p", C.c_double),
+        ("metric", C.c_int32), ("policy", C.c_int32),
+        ("match_t", C.c_double), ("struct_beta", C.c_double), ("struct_kappa", C.c_double),
     ]
 
 
@@ -80,6 +84,9 @@ def lib():
             "orc_aggregate": (C.c_int, [P, vp, i64, vp, vp, vp, vp, vp, vp]),
             "orc_run_stage": (C.c_int, [P, i32, vp, vp, vp]),
             "orc_denoise": (C.c_int, [P, P, vp, vp, vp]),
+            "orc_phi": (d, [i32, d, d]),
+            "orc_count_moments": (C.c_int, [i32, i32, vp, vp]),
+            "orc_pair_score": (C.c_int, [i32, i32, d, d, d, i32, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -123,6 +130,11 @@ class Stage:
     passes: int = 2
     noise: str = "poisson"
     counts_integral: bool = True
+    metric: str = "ssd"         # HT matching distance (Poisson noise)
+    policy: str = "fixed"       # acceptance calibration of a Poisson metric
+    match_t: float = 3.0        # threshold multiplier t
+    struct_beta: float = 0.1    # structural allowance beta_s (reference policy)
+    struct_kappa: float = 1.0   # its intensity exponent kappa_s
     sigma: float = 0.0
     s_p: float = 1.0
 
@@ -159,6 +171,8 @@ class Stage:
         c.noise_kind = NOISE[self.noise]
         c.counts_integral = int(bool(self.counts_integral))
         c.sigma, c.s_p = self.sigma, self.s_p
+        c.metric, c.policy = METRIC[self.metric], POLICY[self.policy]
+        c.match_t, c.struct_beta, c.struct_kappa = self.match_t, self.struct_beta, self.struct_kappa
         return c
 
 
@@ -250,6 +264,29 @@ def match(st: Stage, stage: int, src, y, refs):
     _check(lib().orc_match(C.byref(c), stage, _ptr(src), _ptr(y), _ptr(refs), n, _ptr(m),
                            _ptr(cnt), _ptr(sc), _ptr(acc)), "match")
     return m, cnt, sc, acc
+
+
+def phi(metric: str, r: float, c: float) -> float:
+    """Per-entry contribution of a Poisson metric (eq. varphi)."""
+    return lib().orc_phi(METRIC[metric], float(r), float(c))
+
+
+def count_moments(metric: str, n: int):
+    """Exact finite-count conditional mean and variance of phi given the
+    pooled count n (Prop. universal finite-count moments)."""
+    mu, v = C.c_double(), C.c_double()
+    _check(lib().orc_count_moments(METRIC[metric], int(n), C.byref(mu), C.byref(v)), "moments")
+    return mu.value, v.value
+
+
+def pair_score(metric: str, policy: str, r, c, t=3.0, beta=0.1, kappa=1.0):
+    """(score, threshold) of one reference / candidate pair of raw counts."""
+    r = _f64(r).ravel()
+    c = _f64(c).ravel()
+    s, th = C.c_double(), C.c_double()
+    _check(lib().orc_pair_score(METRIC[metric], POLICY[policy], t, beta, kappa, len(r), _ptr(r),
+                                _ptr(c), C.byref(s), C.byref(th)), "pair_score")
+    return s.value, th.value
 
 
 def filter(st: Stage, stage: int, y, pilot, match_, count):

@@ -457,6 +457,140 @@ static int cmp_cand(const void* a, const void* b)
     return (x->lin > y->lin) - (x->lin < y->lin);
 }
 
+/* ---- Poisson-likelihood matching (section Metrics; subsection Exact
+ * Finite-Count Moment Calibration) */
+
+/* Anscombe transform A(n) = 2 sqrt(n + 3/8) (Def. Anscombe-SSD matching
+ * statistic) */
+static double anscombe(double n) { return 2.0 * sqrt(n + 0.375); }
+
+/* Per-entry contribution phi_m(r, c) (eq. varphi) on raw counts r, c >= 0
+ * (eq. raw-counts): the entrywise likelihood-ratio statistic of the
+ * symmetric deviance (Prop. deviance as likelihood ratio; 0 log 0 = 0 and
+ * zero when r + c = 0), the pooled Pearson term (zero when r + c = 0), or
+ * half the squared difference of Anscombe transforms. */
+double orc_phi(int32_t metric, double r, double c)
+{
+    const double s = r + c;
+    if (metric == ORC_METRIC_DEVIANCE) {
+        if (s <= 0.0) return 0.0;
+        double v = 0.0;
+        if (r > 0.0) v += r * log(2.0 * r / s);
+        if (c > 0.0) v += c * log(2.0 * c / s);
+        return 2.0 * v;
+    }
+    if (metric == ORC_METRIC_PEARSON) {
+        if (s <= 0.0) return 0.0;
+        return (c - r) * (c - r) / s;
+    }
+    if (metric == ORC_METRIC_ANSCOMBE) {
+        const double d = anscombe(c) - anscombe(r);
+        return 0.5 * d * d;
+    }
+    return (c - r) * (c - r);
+}
+
+/* Exact conditional moments of phi_m given the pooled count n (Prop.
+ * universal finite-count moments): under the equal-rate null the reference
+ * count is Bin(n, 1/2) given r + c = n (Lemma conditional Poisson
+ * splitting), so mu = sum_x C(n, x) 2^-n phi(x, n - x) and v = sum_x
+ * C(n, x) 2^-n phi(x, n - x)^2 - mu^2. */
+int orc_count_moments(int32_t metric, int32_t n, double* mu, double* v)
+{
+    if (n < 0 || !mu || !v) return -1;
+    double m1 = 0.0, m2 = 0.0;
+    for (int32_t x = 0; x <= n; ++x) {
+        const double w = exp(lgamma(n + 1.0) - lgamma(x + 1.0) - lgamma(n - x + 1.0) -
+                             n * log(2.0));
+        const double f = orc_phi(metric, (double)x, (double)(n - x));
+        m1 += w * f;
+        m2 += w * f * f;
+    }
+    *mu = m1;
+    *v = m2 - m1 * m1;
+    return 0;
+}
+
+/* Score and threshold of one pair under a policy, given the moments of
+ * every pooled count that occurs (mu_tab, v_tab for n <= nmax):
+ *   fixed:        d_m = sum phi / P against 1 + t sqrt(2 / P), the
+ *                 high-count mean 1 and variance 2 per entry (Thm. common
+ *                 high-count limit);
+ *   reference:    d_m against T_ref = mean mu(2 r_i) + t sqrt(sum v(2 r_i)
+ *                 / P^2) + beta rbar^kappa (Def. reference finite-count
+ *                 threshold);
+ *   standardized: Z = (sum phi - sum mu(r_i + c_i)) / sqrt(sum v(r_i +
+ *                 c_i)), 0 when the variance sum is 0, against t (Def.
+ *                 candidate-standardized distance).
+ * The calibrated policies need integral counts. */
+static int pair_score_tab(int32_t metric, int32_t policy, double t, double beta, double kappa,
+                          int32_t P, const double* r, const double* c, const double* mu_tab,
+                          const double* v_tab, int64_t nmax, double* score, double* threshold)
+{
+    double A = 0.0;
+    for (int32_t i = 0; i < P; ++i) A += orc_phi(metric, r[i], c[i]);
+    if (policy == ORC_POLICY_FIXED) {
+        *score = A / P;
+        *threshold = 1.0 + t * sqrt(2.0 / P);
+        return 0;
+    }
+    if (policy == ORC_POLICY_REFERENCE) {
+        double mu = 0.0, v = 0.0, rs = 0.0;
+        for (int32_t i = 0; i < P; ++i) {
+            const int64_t n = (int64_t)(2.0 * r[i]);
+            if (n < 0 || n > nmax) return -1;
+            mu += mu_tab[n];
+            v += v_tab[n];
+            rs += r[i];
+        }
+        *score = A / P;
+        *threshold = mu / P + t * sqrt(v / ((double)P * P)) + beta * pow(rs / P, kappa);
+        return 0;
+    }
+    double M = 0.0, S = 0.0;
+    for (int32_t i = 0; i < P; ++i) {
+        const int64_t n = (int64_t)(r[i] + c[i]);
+        if (n < 0 || n > nmax) return -1;
+        M += mu_tab[n];
+        S += v_tab[n];
+    }
+    *score = S > 0.0 ? (A - M) / sqrt(S) : 0.0;
+    *threshold = t;
+    return 0;
+}
+
+static int moment_tables(int32_t metric, int64_t nmax, double** mu, double** v)
+{
+    *mu = (double*)malloc(sizeof(double) * (size_t)(nmax + 1));
+    *v = (double*)malloc(sizeof(double) * (size_t)(nmax + 1));
+    if (!*mu || !*v) return -2;
+    for (int64_t n = 0; n <= nmax; ++n)
+        if (orc_count_moments(metric, (int32_t)n, &(*mu)[n], &(*v)[n]) != 0) return -1;
+    return 0;
+}
+
+int orc_pair_score(int32_t metric, int32_t policy, double t, double beta, double kappa,
+                   int32_t P, const double* r, const double* c, double* score, double* threshold)
+{
+    if (P < 1 || !r || !c || !score || !threshold) return -1;
+    if (metric < ORC_METRIC_DEVIANCE || metric > ORC_METRIC_ANSCOMBE) return -1;
+    double nmax = 0.0;
+    for (int32_t i = 0; i < P; ++i) {
+        if (r[i] < 0.0 || c[i] < 0.0) return -1;
+        if (2.0 * r[i] > nmax) nmax = 2.0 * r[i];
+        if (r[i] + c[i] > nmax) nmax = r[i] + c[i];
+    }
+    double *mu = NULL, *v = NULL;
+    int rc = 0;
+    if (policy != ORC_POLICY_FIXED) rc = moment_tables(metric, (int64_t)nmax, &mu, &v);
+    if (rc == 0)
+        rc = pair_score_tab(metric, policy, t, beta, kappa, P, r, c, mu, v, (int64_t)nmax, score,
+                            threshold);
+    free(mu);
+    free(v);
+    return rc;
+}
+
 /* For every reference origin: score every candidate origin of the clipped
  * search window (section Block Matching), keep the reference in slot 0 and
  * the best others by (score, lin).
@@ -499,6 +633,42 @@ int orc_match(const orc_cfg* c, int32_t stage, const double* src, const double* 
     }
     double tau_eff = c->tau;
     if (integral) tau_eff = c->tau / (c->s_p * c->s_p);
+    /* Poisson-likelihood metrics in the HT stage: raw counts [y / s_P]_+
+     * (integral counts rounded), scores and thresholds per pair */
+    const int pois = stage == ORC_STAGE_HT && c->noise_kind == ORC_NOISE_POISSON &&
+                     c->metric != ORC_METRIC_SSD;
+    double *rawc = NULL, *mu_tab = NULL, *v_tab = NULL, *rr = NULL, *cc = NULL;
+    int64_t nmax = 0;
+    if (stage == ORC_STAGE_HT && c->metric != ORC_METRIC_SSD && !pois) {
+        free(kap); free(off); free(cand);
+        return -1;
+    }
+    if (pois) {
+        if (c->policy != ORC_POLICY_FIXED && !c->counts_integral) {
+            free(kap); free(off); free(cand);
+            return -1;
+        }
+        rawc = (double*)malloc(sizeof(double) * (size_t)V);
+        rr = (double*)malloc(sizeof(double) * (size_t)P);
+        cc = (double*)malloc(sizeof(double) * (size_t)P);
+        if (!rawc || !rr || !cc) {
+            free(kap); free(off); free(cand); free(rawc); free(rr); free(cc);
+            return -2;
+        }
+        double mx = 0.0;
+        for (int64_t u = 0; u < V; ++u) {
+            double k = c->counts_integral ? nearbyint(y[u] / c->s_p) : y[u] / c->s_p;
+            rawc[u] = k > 0.0 ? k : 0.0;
+            if (rawc[u] > mx) mx = rawc[u];
+        }
+        nmax = (int64_t)(2.0 * mx);
+        if (c->policy != ORC_POLICY_FIXED &&
+            moment_tables(c->metric, nmax, &mu_tab, &v_tab) != 0) {
+            free(kap); free(off); free(cand); free(rawc); free(rr); free(cc);
+            free(mu_tab); free(v_tab);
+            return -2;
+        }
+    }
 
     for (int64_t g = 0; g < nrefs; ++g) {
         const int64_t r = refs[g];
@@ -516,6 +686,7 @@ int orc_match(const orc_cfg* c, int32_t stage, const double* src, const double* 
             ncand_box *= ext[d];
         }
         int64_t nc = 0;
+        double thr_ref = 0.0;  /* Poisson metrics: the reference's threshold */
         for (int64_t t = 0; t < ncand_box; ++t) {
             int64_t tr = t, clin = 0;
             for (int d = D - 1; d >= 0; --d) {
@@ -524,7 +695,20 @@ int orc_match(const orc_cfg* c, int32_t stage, const double* src, const double* 
             }
             if (clin == r) continue;
             double s = 0.0;
-            if (stage == ORC_STAGE_WIENER) {
+            if (pois) {
+                for (int i = 0; i < P; ++i) {
+                    rr[i] = rawc[r + off[i]];
+                    cc[i] = rawc[clin + off[i]];
+                }
+                double thr = 0.0;
+                if (pair_score_tab(c->metric, c->policy, c->match_t, c->struct_beta,
+                                   c->struct_kappa, P, rr, cc, mu_tab, v_tab, nmax, &s, &thr) != 0) {
+                    free(kap); free(off); free(cand); free(rawc); free(rr); free(cc);
+                    free(mu_tab); free(v_tab);
+                    return -1;
+                }
+                thr_ref = thr;
+            } else if (stage == ORC_STAGE_WIENER) {
                 for (int i = 0; i < P; ++i) {
                     double df = src[clin + off[i]] - src[r + off[i]];
                     s += df * df;
@@ -559,8 +743,9 @@ int orc_match(const orc_cfg* c, int32_t stage, const double* src, const double* 
         }
         qsort(cand, (size_t)nc, sizeof(cand_t), cmp_cand);
         int64_t acc = 0;
+        const double tau_g = pois ? thr_ref : tau_eff;
         for (int64_t i = 0; i < nc; ++i)
-            if (cand[i].score < tau_eff) ++acc;
+            if (cand[i].score < tau_g) ++acc;
         int64_t kacc = 1 + acc;
         if (kacc > gmax) kacc = gmax;
         int64_t K = pow2floor64(kacc);
@@ -577,13 +762,18 @@ int orc_match(const orc_cfg* c, int32_t stage, const double* src, const double* 
         for (int64_t t = 1; t < K; ++t) {
             match[g * gmax + t] = (int32_t)cand[t - 1].lin;
             if (score)
-                score[g * gmax + t] = integral ? cand[t - 1].score * c->s_p * c->s_p
+                score[g * gmax + t] = (integral && !pois) ? cand[t - 1].score * c->s_p * c->s_p
                                                : cand[t - 1].score;
         }
     }
     free(kap);
     free(off);
     free(cand);
+    free(rawc);
+    free(rr);
+    free(cc);
+    free(mu_tab);
+    free(v_tab);
     return 0;
 }
 

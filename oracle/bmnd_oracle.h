@@ -36,6 +36,11 @@ enum { ORC_W_CLASSIC = 0, ORC_W_VARIANCE = 1, ORC_W_RISK = 2 };
 enum { ORC_SCOPE_GROUP = 0, ORC_SCOPE_PATCH = 1 };
 enum { ORC_NOISE_GAUSSIAN = 0, ORC_NOISE_POISSON = 1 };
 enum { ORC_STAGE_HT = 0, ORC_STAGE_WIENER = 1 };
+/* HT matching distance and acceptance policy (section Metrics, subsection
+ * Exact Finite-Count Moment Calibration) */
+enum { ORC_METRIC_SSD = 0, ORC_METRIC_DEVIANCE = 1, ORC_METRIC_PEARSON = 2,
+       ORC_METRIC_ANSCOMBE = 3 };
+enum { ORC_POLICY_FIXED = 0, ORC_POLICY_REFERENCE = 1, ORC_POLICY_STANDARDIZED = 2 };
 
 /* One stage's full configuration (geometry + noise + stage profile). */
 typedef struct {
@@ -66,6 +71,11 @@ typedef struct {
     int32_t counts_integral; /* y / s_P is integral (Poisson)             */
     double  sigma;           /* Gaussian standard deviation               */
     double  s_p;             /* Poisson scale                             */
+    int32_t metric;          /* ORC_METRIC_* (HT stage, Poisson noise)    */
+    int32_t policy;          /* ORC_POLICY_*                              */
+    double  match_t;         /* threshold multiplier t                    */
+    double  struct_beta;     /* structural allowance beta_s               */
+    double  struct_kappa;    /* its intensity exponent kappa_s            */
 } orc_cfg;
 
 /* All functions return 0 on success, <0 on bad arguments / allocation. */
@@ -75,6 +85,16 @@ int     orc_haar_matrix(int32_t K, double* H);
 int     orc_spatial_matrices(int32_t kind, int32_t n, double* T, double* U);
 int     orc_bior15_filters(double* dec_lo10, double* rec_lo2);
 int     orc_kaiser(int32_t n, double beta, double* w);
+/* Per-entry contribution phi_m(r, c) of a Poisson metric (eq. varphi), the
+ * finite-count moments mu_m(n), v_m(n) (eq. finite-count-moments), and the
+ * score and acceptance threshold of one reference / candidate pair of P
+ * entries under a policy (fixed, Def. reference finite-count threshold,
+ * Def. candidate-standardized distance). */
+double  orc_phi(int32_t metric, double r, double c);
+int     orc_count_moments(int32_t metric, int32_t n, double* mu, double* v);
+int     orc_pair_score(int32_t metric, int32_t policy, double t, double beta, double kappa,
+                       int32_t P, const double* r, const double* c, double* score,
+                       double* threshold);
 int     orc_match(const orc_cfg* c, int32_t stage, const double* src, const double* y,
                   const int64_t* refs, int64_t nrefs, int32_t* match, int32_t* count,
                   double* score, int32_t* accepted);

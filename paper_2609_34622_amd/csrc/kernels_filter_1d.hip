@@ -347,8 +347,6 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             pv[s] = av ? pv[s] : 0.f;
             gn2 = __builtin_fmaf(x[s], x[s], gn2);
             if constexpr (wiener) gp2 = __builtin_fmaf(pv[s], pv[s], gp2);
-            const float src = wiener ? pv[s] : x[s];
-            mv[s] = av ? (poisson ? a.s_p * fmaxf(src, 0.f) : a.sigma2) : 0.f;
         }
         f.gn = fsqrt(wave_sum(gn2));
         // split operands; the group norms bound every entry
@@ -360,30 +358,41 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             gp = fsqrt(wave_sum(gp2));
             split8(pv, split_scale(gp, &ip), ph, pl);
         }
-        split8(mv, split_scale(poisson ? a.s_p * (wiener ? gp : f.gn) : a.sigma2, &im), mh, ml);
-        const float uy = oinv[0] * ix, uv = oinv[1] * im, up = oinv[0] * ip;
+        // variance map s_P [src]_+ (Poisson) or sigma^2, scaled while formed
+        const float scm = split_scale(poisson ? a.s_p * (wiener ? gp : f.gn) : a.sigma2, &im);
+        const float mp = poisson ? a.s_p * scm : 0.f, mg = poisson ? 0.f : a.sigma2 * scm;
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+            mv[s] = __builtin_fmaf(fmaxf(wiener ? pv[s] : x[s], 0.f), mp, av ? mg : 0.f);
+        split8(mv, 1.f, mh, ml);
         // ---- analysis: spatial rows 16c + m16 of every member, then Haar
-        // over the members with A[row m16][depth (lg, s)] = H[m16][4lg + s]
-        float ha[4], h2[4];
+        // over the members with A[row m16][depth (lg, s)] = H[m16][4lg + s];
+        // the split scales are undone on the Haar operands (powers of two)
+        float ha[4], hy[4], h2[4], hp[4];
         {
             const float4 u0 = *reinterpret_cast<const float4*>(&hops[f.lk][lane][0]);
             ha[0] = u0.x; ha[1] = u0.y; ha[2] = u0.z; ha[3] = u0.w;
         }
+        const float uy = oinv[0] * ix, uv = oinv[1] * im, up = oinv[0] * ip;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) h2[s] = ha[s] * ha[s];
+        for (int s = 0; s < 4; ++s) {
+            hy[s] = ha[s] * uy;
+            h2[s] = ha[s] * ha[s] * uv;
+            hp[s] = ha[s] * up;
+        }
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const h8 th = opnd_h(ops, 0, 0, c, lane), tl = opnd_h(ops, 0, 1, c, lane);
-            const f4 y1 = mul3(xh, xl, th, tl) * uy;
-            const f4 v1 = mul3(mh, ml, opnd_h(ops, 1, 0, c, lane), opnd_h(ops, 1, 1, c, lane)) * uv;
+            const f4 y1 = mul3(xh, xl, th, tl);
+            const f4 v1 = mul3(mh, ml, opnd_h(ops, 1, 0, c, lane), opnd_h(ops, 1, 1, c, lane));
             f4 p1 = {0.f, 0.f, 0.f, 0.f};
-            if constexpr (wiener) p1 = mul3(ph, pl, th, tl) * up;
+            if constexpr (wiener) p1 = mul3(ph, pl, th, tl);
             f.Y[c] = f.V[c] = f.G[c] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                f.Y[c] = mfma(ha[s], y1[s], f.Y[c]);
+                f.Y[c] = mfma(hy[s], y1[s], f.Y[c]);
                 f.V[c] = mfma(h2[s], v1[s], f.V[c]);
-                if constexpr (wiener) f.G[c] = mfma(ha[s], p1[s], f.G[c]);
+                if constexpr (wiener) f.G[c] = mfma(hp[s], p1[s], f.G[c]);
             }
         }
         return f;
