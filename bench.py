@@ -277,6 +277,46 @@ def bench_standard(B, torch, workload: str = "image-2d-128", reps: int = 10) -> 
     return {"workload": workload, **res}
 
 
+def bench_poisson_metrics(B, torch, n_signals: int = 16, reps: int = 3) -> dict:
+    """HT matching with the Poisson-likelihood metrics (deviance, Pearson,
+    Anscombe-SSD; fixed and candidate-standardized policies) beside SSD on
+    ECG signals of the headline workload's shape (fewer of them)."""
+    from paper_2609_34622_amd import synth
+
+    w = WORKLOADS["ecg-1d-batch"]
+    s = synth.ecg_batch(n_signals=n_signals, length=w["shape"][0], seed=2000)
+    shape = w["shape"]
+    y = torch.from_numpy(np.ascontiguousarray(s.y, np.float32)).cuda()
+    geom = B.geometry(shape, n_signals)
+    noise = B.poisson(s.s_p)
+    res = {}
+    for name, metric, policy in (("ssd", B.METRIC_SSD, B.POLICY_FIXED),
+                                 ("deviance", B.METRIC_DEVIANCE, B.POLICY_FIXED),
+                                 ("deviance_standardized", B.METRIC_DEVIANCE, B.POLICY_STANDARDIZED),
+                                 ("pearson_standardized", B.METRIC_PEARSON, B.POLICY_STANDARDIZED),
+                                 ("anscombe_reference", B.METRIC_ANSCOMBE, B.POLICY_REFERENCE)):
+        p = B.bmnd_params_default(B.PRESET_PLAIN, 1)
+        B.set_axes(p.ht, patch=w["patch"], step=w["step"], search=w["search"])
+        p.ht.group_max = w["group"][0]
+        p.ht.match_metric, p.ht.match_policy = metric, policy
+        refs = B.bmnd_reference_origins(B.geometry(shape), p.ht)
+        m = torch.empty((n_signals, len(refs), p.ht.group_max), dtype=torch.int32, device="cuda")
+        c = torch.empty((n_signals, len(refs)), dtype=torch.int32, device="cuda")
+        ws = torch.empty(B.bmnd_match_workspace_size(geom, p.ht), dtype=torch.uint8, device="cuda")
+        d_refs = torch.from_numpy(refs).cuda()
+        B.bmnd_match(B.STAGE_HT, y, geom, noise, p.ht, d_refs, m, c, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            B.bmnd_match(B.STAGE_HT, y, geom, noise, p.ht, d_refs, m, c, ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[name] = {"ms": round(dt * 1e3, 3),
+                     "mrefs_per_s": round(n_signals * len(refs) / dt / 1e6, 3)}
+    B.bmnd_stream_status()
+    return {"signals": n_signals, "shape": list(shape), "search": list(w["search"]), **res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -406,11 +446,12 @@ def main():
                "sample": f"{n} of {batch} arrays of the same workload, both stages, "
                          f"{dt:.1f} s single-threaded"}
 
-    batched = serving_row = standard = None
+    batched = serving_row = standard = pois = None
     if args.mixed:
         batched = bench_batched(B, torch)
         serving_row = bench_serving(B, torch)
         standard = bench_standard(B, torch)
+        pois = bench_poisson_metrics(B, torch)
 
     line = {
         "metric": "denoised Mvox/s (both stages)",
@@ -428,6 +469,7 @@ def main():
         "batched": batched,
         "serving": serving_row,
         "standard_profile": standard,
+        "poisson_metrics": pois,
     }
     print(json.dumps(line), flush=True)
 

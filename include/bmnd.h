@@ -68,6 +68,14 @@ enum { BMND_SHRINK_HARD = 0, BMND_SHRINK_SOFT = 1, BMND_SHRINK_WIENER = 2 };
 enum { BMND_WEIGHT_CLASSIC = 0, BMND_WEIGHT_VARIANCE = 1, BMND_WEIGHT_RISK = 2 };
 enum { BMND_SCOPE_GROUP = 0, BMND_SCOPE_PATCH = 1 };
 enum { BMND_PRESET_PLAIN = 0, BMND_PRESET_STANDARD = 1 };
+/* HT matching distance (section Metrics) and, for the Poisson-likelihood
+ * distances, the acceptance calibration (subsection Exact Finite-Count
+ * Moment Calibration). */
+enum { BMND_METRIC_SSD = 0, BMND_METRIC_DEVIANCE = 1, BMND_METRIC_PEARSON = 2,
+       BMND_METRIC_ANSCOMBE = 3 };
+enum { BMND_POLICY_FIXED = 0, BMND_POLICY_REFERENCE = 1, BMND_POLICY_STANDARDIZED = 2 };
+/* pooled counts up to which the finite-count moment tables are exact */
+enum { BMND_MOMENT_MAX_COUNT = 4096 };
 
 /* Observed array(s): sampling domain Omega of ndim axes (Notation, Method
  * Overview), `batch` arrays of that shape stored back to back. */
@@ -119,6 +127,13 @@ typedef struct {
     int32_t weight_scope;            /* BMND_SCOPE_*                           */
     int32_t mass_conservation;       /* 0 / 1                                  */
     double kaiser_beta;              /* Kaiser window beta                     */
+    /* HT matching on Poisson data (ignored by SSD with the fixed policy):  */
+    int32_t match_metric;            /* BMND_METRIC_*; non-SSD: HT, Poisson    */
+    int32_t match_policy;            /* BMND_POLICY_*; non-FIXED needs a       */
+                                     /* Poisson metric and integral counts     */
+    double match_t;                  /* threshold multiplier t >= 0            */
+    double struct_beta;              /* structural allowance beta_s >= 0       */
+    double struct_kappa;             /* its intensity exponent kappa_s > 0     */
 } bmnd_stage_params;
 
 typedef struct {
@@ -162,6 +177,14 @@ bmnd_status bmnd_transform_matrices(int32_t spatial, int32_t n, double* T, doubl
 bmnd_status bmnd_haar_matrix(int32_t K, double* H);
 bmnd_status bmnd_kaiser_window(int32_t n, double beta, double* w);
 
+/* Exact finite-count moments of a Poisson matching metric's per-entry
+ * contribution (Prop. universal finite-count moments), the tables the
+ * calibrated policies use: mu[n], v[n] for pooled counts n = 0..nmax (host
+ * arrays of nmax + 1 doubles, caller owned).  Host call.  BMND_E_ARG for a
+ * metric other than DEVIANCE / PEARSON / ANSCOMBE or nmax outside
+ * [0, BMND_MOMENT_MAX_COUNT]. */
+bmnd_status bmnd_count_moments(int32_t metric, int32_t nmax, double* mu, double* v);
+
 /* Workspace bytes for bmnd_match / bmnd_aggregate / bmnd_denoise. */
 bmnd_status bmnd_match_workspace_size(const bmnd_geometry* geom, const bmnd_stage_params* sp,
                                       size_t* bytes);
@@ -181,6 +204,22 @@ bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noi
  *                 the raw counts when counts_integral is set;
  *   Wiener:       SSD on d_src, the pilot (Def. paired pilot and
  *                 observation groups).
+ * With a Poisson-likelihood metric (HT stage, Poisson noise) the score of
+ * a candidate is built from the raw counts r = [p / s_P]_+, c = [q / s_P]_+
+ * (eq. raw-counts; rint(y / s_P) with integral counts) and the per-entry
+ * contributions phi of the deviance, Pearson or Anscombe-SSD statistic
+ * (eq. varphi):
+ *   FIXED:        d = sum phi / P, accepted if d < 1 + t sqrt(2 / P), the
+ *                 high-count mean 1 and variance 2 per entry (Thm. common
+ *                 high-count limit);
+ *   REFERENCE:    d accepted if d < mean mu(2 r_i) + t sqrt(sum v(2 r_i)) / P
+ *                 + beta_s rbar^kappa_s (Def. reference finite-count
+ *                 threshold);
+ *   STANDARDIZED: Z = (sum phi - sum mu(r_i + c_i)) / sqrt(sum v(r_i +
+ *                 c_i)) (0 if the variance sum is 0), accepted if Z < t
+ *                 (Def. candidate-standardized distance);
+ * with the exact finite-count moments mu, v of phi (Prop. universal
+ * finite-count moments) for pooled counts up to BMND_MOMENT_MAX_COUNT.
  * The group is the reference in slot 0 followed by the other candidates
  * in ascending (score, lin); its size K is pow2floor(min(1 + #{score <
  * tau}, group_max)), clamped to [group_min, pow2floor(1 + candidates)].
@@ -193,8 +232,9 @@ bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noi
  * largest power of two its selected members fill, so every entry below K
  * is a valid origin.  Reference origins are clamped into the array.
  * Errors: BMND_E_ARG / _SHAPE / _UNSUPPORTED / _WORKSPACE / _HIP;
- * counts too large for exact int32 scoring, and non-finite observations in
- * count-domain HT matching, raise BMND_E_RANGE from bmnd_stream_status(). */
+ * counts too large for exact int32 scoring, non-finite observations in
+ * count-domain HT matching, and pooled counts beyond the moment tables
+ * raise BMND_E_RANGE from bmnd_stream_status(). */
 bmnd_status bmnd_match(int32_t stage, const float* d_src, const bmnd_geometry* geom,
                        const bmnd_noise* noise, const bmnd_stage_params* sp,
                        const int64_t* d_refs, int64_t n_refs, int32_t* d_match,

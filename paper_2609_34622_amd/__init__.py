@@ -29,6 +29,9 @@ SHRINK = {"hard": 0, "soft": 1, "wiener": 2}
 WEIGHT = {"classic": 0, "variance": 1, "risk": 2}
 SCOPE = {"group": 0, "patch": 1}
 PRESET_PLAIN, PRESET_STANDARD = 0, 1
+METRIC_SSD, METRIC_DEVIANCE, METRIC_PEARSON, METRIC_ANSCOMBE = 0, 1, 2, 3
+POLICY_FIXED, POLICY_REFERENCE, POLICY_STANDARDIZED = 0, 1, 2
+MOMENT_MAX_COUNT = 4096
 
 
 class BmndError(RuntimeError):
@@ -59,6 +62,8 @@ class StageParams(C.Structure):
         ("k_exact", C.c_int32), ("weight_model", C.c_int32), ("weight_scope", C.c_int32),
         ("mass_conservation", C.c_int32),
         ("kaiser_beta", C.c_double),
+        ("match_metric", C.c_int32), ("match_policy", C.c_int32),
+        ("match_t", C.c_double), ("struct_beta", C.c_double), ("struct_kappa", C.c_double),
     ]
 
 
@@ -79,7 +84,7 @@ EXPORTS = [
     "bmnd_last_error", "bmnd_version", "bmnd_params_default", "bmnd_reference_origins",
     "bmnd_match_workspace_size", "bmnd_aggregate_workspace_size", "bmnd_workspace_size",
     "bmnd_match", "bmnd_filter", "bmnd_aggregate", "bmnd_denoise", "bmnd_stream_status",
-    "bmnd_transform_matrices", "bmnd_haar_matrix", "bmnd_kaiser_window",
+    "bmnd_transform_matrices", "bmnd_haar_matrix", "bmnd_kaiser_window", "bmnd_count_moments",
     "bmnd_profile_begin", "bmnd_profile_end", "bmnd_batch_workspace_size", "bmnd_denoise_batch",
 ]
 KERNEL_IDS = ["counts", "patch_sums", "match_ht", "match_wiener", "filter_ht", "filter_wiener",
@@ -115,6 +120,7 @@ def lib() -> C.CDLL:
         "bmnd_transform_matrices": (i32, [i32, i32, vp, vp]),
         "bmnd_haar_matrix": (i32, [i32, vp]),
         "bmnd_kaiser_window": (i32, [i32, C.c_double, vp]),
+        "bmnd_count_moments": (i32, [i32, i32, vp, vp]),
         "bmnd_profile_begin": (i32, []),
         "bmnd_profile_end": (i32, [vp, vp, i32]),
         "bmnd_batch_workspace_size": (i32, [i32, C.POINTER(Job), C.POINTER(sz)]),
@@ -236,6 +242,14 @@ def bmnd_kaiser_window(n: int, beta: float) -> np.ndarray:
     w = np.zeros(n)
     _check(lib().bmnd_kaiser_window(n, beta, w.ctypes.data))
     return w
+
+
+def bmnd_count_moments(metric: int, nmax: int):
+    """The library's finite-count moment tables mu[0..nmax], v[0..nmax]."""
+    mu = np.zeros(nmax + 1)
+    v = np.zeros(nmax + 1)
+    _check(lib().bmnd_count_moments(metric, nmax, mu.ctypes.data, v.ctypes.data))
+    return mu, v
 
 
 def bmnd_match_workspace_size(geom: Geometry, sp: StageParams) -> int:

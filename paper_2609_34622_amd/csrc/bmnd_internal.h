@@ -46,6 +46,10 @@ struct StageCfg {
     int k_exact, wmodel, wscope, mc;
     double beta;
     int step_last;   // reference step along the last axis
+    // HT matching distance and its acceptance calibration
+    int metric = BMND_METRIC_SSD, policy = BMND_POLICY_FIXED;
+    double match_t = 3.0, sbeta = 0.1, skappa = 1.0;
+    bool counts_integral = false;
 };
 
 // Device-resident immutable tables for one (spatial transform, patch, beta).
@@ -70,6 +74,19 @@ void spatial_matrices(int kind, int n, std::vector<double>& T, std::vector<doubl
 void haar_matrix(int K, std::vector<double>& H);
 std::vector<double> kaiser_window(int n, double beta);
 
+// Exact finite-count moments mu(n), v(n) of a Poisson matching metric's
+// per-entry contribution for pooled counts 0..nmax (device copies, FP32 and
+// FP64; library owned).
+struct MomentTables {
+    const float* mu = nullptr;
+    const float* v = nullptr;
+    const double* mu64 = nullptr;
+    const double* v64 = nullptr;
+    int nmax = 0;
+};
+void count_moments_host(int metric, int nmax, std::vector<double>& mu, std::vector<double>& v);
+const MomentTables* device_moments(int metric, std::string& err);
+
 // Cached device copies (library owned, never freed before process exit).
 const DevTables* device_tables(const StageCfg& c, std::string& err);
 const int64_t* device_origins(const bmnd_geometry& geom, const bmnd_stage_params& sp,
@@ -80,7 +97,8 @@ hipError_t launch_counts(const StageCfg& c, const float* y, int* kappa, int* psu
 // Matching; kappa/psum (workspace, one int per voxel each) are used by
 // the generic count-domain path and may be NULL otherwise.
 hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* psum,
-                        const int64_t* refs, int n_refs, int* match, int* count, hipStream_t s);
+                        const int64_t* refs, int n_refs, int* match, int* count, hipStream_t s,
+                        const MomentTables* mom = nullptr);
 // out_mode: 0 write patches/weights, 1 aggregate (FP64 sums), 2 mc sweep 1, 3 mc sweep 2
 hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
                          const float* pilot, int n_refs, const int* match, const int* count,

@@ -93,6 +93,19 @@ bmnd_status check_stage(const bmnd_geometry* g, const bmnd_stage_params* sp, int
         return fail(BMND_E_ARG, "unknown weight scope");
     if (sp->k_exact < 0) return fail(BMND_E_ARG, "k_exact must be >= 0");
     if (!(sp->kaiser_beta >= 0.0)) return fail(BMND_E_ARG, "kaiser_beta must be >= 0");
+    if (sp->match_metric < BMND_METRIC_SSD || sp->match_metric > BMND_METRIC_ANSCOMBE)
+        return fail(BMND_E_ARG, "unknown matching metric");
+    if (sp->match_policy < BMND_POLICY_FIXED || sp->match_policy > BMND_POLICY_STANDARDIZED)
+        return fail(BMND_E_ARG, "unknown matching policy");
+    if (sp->match_metric != BMND_METRIC_SSD && stage != BMND_STAGE_HT)
+        return fail(BMND_E_ARG, "Poisson-likelihood matching is an HT-stage option");
+    if (sp->match_metric == BMND_METRIC_SSD && sp->match_policy != BMND_POLICY_FIXED)
+        return fail(BMND_E_ARG, "SSD matching uses the fixed policy");
+    if (sp->match_metric != BMND_METRIC_SSD &&
+        (!(sp->match_t >= 0.0) || !(sp->struct_beta >= 0.0) || !(sp->struct_kappa > 0.0) ||
+         !std::isfinite(sp->match_t) || !std::isfinite(sp->struct_beta) ||
+         !std::isfinite(sp->struct_kappa)))
+        return fail(BMND_E_ARG, "match_t and struct_beta must be >= 0, struct_kappa > 0");
     return BMND_OK;
 }
 
@@ -138,6 +151,12 @@ bmnd_status make_stage(const bmnd_geometry* g, const bmnd_noise* n, const bmnd_s
     if (st != BMND_OK) return st;
     if ((st = check_stage(g, sp, stage)) != BMND_OK) return st;
     if (n && (st = check_noise(n)) != BMND_OK) return st;
+    if (n && sp->match_metric != BMND_METRIC_SSD) {
+        if (n->kind != BMND_NOISE_POISSON)
+            return fail(BMND_E_ARG, "Poisson-likelihood matching needs Poisson noise");
+        if (sp->match_policy != BMND_POLICY_FIXED && !n->counts_integral)
+            return fail(BMND_E_ARG, "finite-count calibration needs integral counts");
+    }
     c = StageCfg{};
     c.g = make_geo(g, sp);
     c.stage = stage;
@@ -162,6 +181,12 @@ bmnd_status make_stage(const bmnd_geometry* g, const bmnd_noise* n, const bmnd_s
     c.mc = sp->mass_conservation ? 1 : 0;
     c.beta = sp->kaiser_beta;
     c.step_last = sp->step[g->ndim - 1];
+    c.metric = sp->match_metric;
+    c.policy = sp->match_policy;
+    c.match_t = sp->match_t;
+    c.sbeta = sp->struct_beta;
+    c.skappa = sp->struct_kappa;
+    c.counts_integral = n && n->kind == BMND_NOISE_POISSON && n->counts_integral;
     return BMND_OK;
 }
 
@@ -357,6 +382,11 @@ bmnd_stage_params preset_stage(int32_t preset, int32_t ndim, int stage)
     p.weight_scope = preset == BMND_PRESET_STANDARD ? BMND_SCOPE_PATCH : BMND_SCOPE_GROUP;
     p.mass_conservation = 0;
     p.kaiser_beta = 2.0;
+    p.match_metric = BMND_METRIC_SSD;
+    p.match_policy = BMND_POLICY_FIXED;
+    p.match_t = 3.0;
+    p.struct_beta = 0.1;
+    p.struct_kappa = 1.0;
     return p;
 }
 
@@ -409,6 +439,19 @@ bmnd_status bmnd_transform_matrices(int32_t spatial, int32_t n, double* T, doubl
     spatial_matrices(spatial, n, t, u);
     if (T) std::memcpy(T, t.data(), sizeof(double) * t.size());
     if (U) std::memcpy(U, u.data(), sizeof(double) * u.size());
+    return BMND_OK;
+}
+
+bmnd_status bmnd_count_moments(int32_t metric, int32_t nmax, double* mu, double* v)
+{
+    if (metric < BMND_METRIC_DEVIANCE || metric > BMND_METRIC_ANSCOMBE)
+        return fail(BMND_E_ARG, "moments exist for the Poisson metrics only");
+    if (nmax < 0 || nmax > BMND_MOMENT_MAX_COUNT || !mu || !v)
+        return fail(BMND_E_ARG, "nmax out of range or NULL output");
+    std::vector<double> m, w;
+    count_moments_host(metric, nmax, m, w);
+    std::copy(m.begin(), m.end(), mu);
+    std::copy(w.begin(), w.end(), v);
     return BMND_OK;
 }
 
@@ -511,7 +554,13 @@ bmnd_status bmnd_match(int32_t stage, const float* d_src, const bmnd_geometry* g
         kappa = static_cast<int*>(d_ws);
         psum = reinterpret_cast<int*>(static_cast<char*>(d_ws) + match_ws(c.g) / 2);
     }
-    hipError_t e = launch_match(c, d_src, kappa, psum, d_refs, int(n_refs), d_match, d_count, s);
+    const MomentTables* mom = nullptr;
+    if (c.metric != BMND_METRIC_SSD) {
+        std::string err;
+        if (!(mom = device_moments(c.metric, err))) return fail(BMND_E_NOMEM, err);
+    }
+    hipError_t e = launch_match(c, d_src, kappa, psum, d_refs, int(n_refs), d_match, d_count, s,
+                                mom);
     if (e != hipSuccess) return hip_fail(e, "matching kernel");
     return BMND_OK;
 }
@@ -599,6 +648,7 @@ struct DenoisePlan {
     int64_t n1 = 0, n2 = 0;
     const DevTables* t1 = nullptr;
     const DevTables* t2 = nullptr;
+    const MomentTables* m1 = nullptr;  // HT Poisson-likelihood matching
     size_t offs[8] = {};
     size_t total = 0;
 };
@@ -638,6 +688,8 @@ bmnd_status plan_denoise(const bmnd_geometry* geom, const bmnd_noise* noise,
     pl->t1 = device_tables(pl->c1, err);
     pl->t2 = pl->t1 ? device_tables(pl->c2, err) : nullptr;
     if (!pl->t1 || !pl->t2) return fail(BMND_E_NOMEM, err);
+    if (pl->c1.metric != BMND_METRIC_SSD && !(pl->m1 = device_moments(pl->c1.metric, err)))
+        return fail(BMND_E_NOMEM, err);
     return denoise_layout(geom, params, pl->n1, pl->n2, pl->offs, &pl->total);
 }
 
@@ -661,7 +713,8 @@ hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out
         hipError_t e = hipSuccess;
         {
             KernelSpan k(spans ? (ht ? BMND_KID_MATCH_HT : BMND_KID_MATCH_WIENER) : no_span, s);
-            e = launch_match(c, src, kappa, psum, refs, int(nr), match, count, s);
+            e = launch_match(c, src, kappa, psum, refs, int(nr), match, count, s,
+                             ht ? pl.m1 : nullptr);
         }
         if (e == hipSuccess) {
             KernelSpan k(spans ? BMND_KID_ZERO : no_span, s);

@@ -907,8 +907,41 @@ static hipError_t launch_match_mode(const MatchArgs& a, hipStream_t s)
 }
 
 hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* psum,
-                        const int64_t* refs, int n_refs, int* match, int* count, hipStream_t s)
+                        const int64_t* refs, int n_refs, int* match, int* count, hipStream_t s,
+                        const MomentTables* mom)
 {
+    if (c.metric != BMND_METRIC_SSD) {
+        // Poisson-likelihood metrics (HT stage, Poisson noise)
+        if (!mom) return hipErrorInvalidValue;
+        MatchArgs a{};
+        a.g = c.g;
+        a.src = src;
+        a.refs = refs;
+        a.n_refs = n_refs;
+        a.match = match;
+        a.count = count;
+        a.gmin = c.gmin;
+        a.gmax = c.gmax;
+        a.inv_sp = float(1.0 / c.s_p);
+        a.range_flag = range_flag_ptr();
+        a.policy = c.policy;
+        a.integral = c.counts_integral ? 1 : 0;
+        a.s_p_d = c.s_p;
+        a.t_d = c.match_t;
+        a.sbeta_d = c.sbeta;
+        a.skappa_d = c.skappa;
+        a.mu_f = mom->mu;
+        a.v_f = mom->v;
+        a.mu_d = mom->mu64;
+        a.v_d = mom->v64;
+        a.nmom = mom->nmax;
+        // fixed: the high-count calibration 1 + t sqrt(2 / P); standardized: t;
+        // reference: per reference in the kernel
+        a.tau_d = c.policy == BMND_POLICY_FIXED ? 1.0 + c.match_t * std::sqrt(2.0 / c.g.P)
+                                                 : c.match_t;
+        a.tau_f = float(a.tau_d);
+        return launch_match_pois(a, c.metric, 1 << 23, s);
+    }
     MatchArgs a{};
     a.g = c.g;
     a.src = src;

@@ -27,6 +27,17 @@ struct MatchArgs {
     int* range_flag;     // set when a count leaves the exact int32 range
     // float modes: FP64 twins of the constants for the re-scored near-ties
     double tau_d, bias_d, gamma_sp_d;
+    // Poisson-likelihood matching (HT stage): policy, raw-count rule, the
+    // policy's constants and the finite-count moment tables
+    int policy;
+    int integral;        // raw counts rint(y / s_P), else [y / s_P]_+
+    double s_p_d;        // s_P
+    double t_d, sbeta_d, skappa_d;
+    const float* mu_f;
+    const float* v_f;
+    const double* mu_d;
+    const double* v_d;
+    int nmom;            // largest tabulated pooled count
 };
 
 // Float-mode scores within this relative band of the K-th value or of tau
@@ -42,5 +53,7 @@ bool match_1d_supported(const Geo& g, int mode);
 bool match_nd_supported(const Geo& g);
 hipError_t launch_match_nd(const MatchArgs& a, int mode, int kmax, hipStream_t s);
 hipError_t launch_match_1d(const MatchArgs& a, int mode, int step, int kmax, hipStream_t s);
+// Poisson deviance / Pearson / Anscombe-SSD matching, any shape
+hipError_t launch_match_pois(const MatchArgs& a, int metric, int kmax, hipStream_t s);
 
 }  // namespace bmnd

@@ -132,3 +132,46 @@ def test_batch_workspace_layout():
     bad[1].noise = B.poisson(0.0)
     with pytest.raises(B.BmndError, match="job 1"):
         B.bmnd_batch_workspace_size(bad)
+
+
+def test_poisson_metric_validation():
+    g = B.geometry((64, 64))
+    noise = B.poisson(0.1)
+    p = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    assert p.ht.match_metric == B.METRIC_SSD and p.ht.match_policy == B.POLICY_FIXED
+    assert (p.ht.match_t, p.ht.struct_beta, p.ht.struct_kappa) == (3.0, 0.1, 1.0)
+    for m in (B.METRIC_DEVIANCE, B.METRIC_PEARSON, B.METRIC_ANSCOMBE):
+        for pol in (B.POLICY_FIXED, B.POLICY_REFERENCE, B.POLICY_STANDARDIZED):
+            ok = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+            ok.ht.match_metric, ok.ht.match_policy = m, pol
+            assert B.bmnd_workspace_size(g, noise, ok) > 0
+    bad = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    bad.wiener.match_metric = B.METRIC_DEVIANCE           # HT-stage option only
+    assert _status(B.bmnd_workspace_size, g, noise, bad) == B.E_ARG
+    bad = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    bad.ht.match_policy = B.POLICY_REFERENCE               # SSD uses the fixed policy
+    assert _status(B.bmnd_workspace_size, g, noise, bad) == B.E_ARG
+    bad = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    bad.ht.match_metric = B.METRIC_PEARSON
+    assert _status(B.bmnd_workspace_size, g, B.gaussian(0.1), bad) == B.E_ARG
+    bad.ht.match_policy = B.POLICY_STANDARDIZED            # needs integral counts
+    assert _status(B.bmnd_workspace_size, g, B.poisson(0.1, counts_integral=False), bad) == B.E_ARG
+    bad.ht.match_t = -1.0
+    assert _status(B.bmnd_workspace_size, g, noise, bad) == B.E_ARG
+    bad.ht.match_t, bad.ht.struct_kappa = 3.0, 0.0
+    assert _status(B.bmnd_workspace_size, g, noise, bad) == B.E_ARG
+    bad.ht.struct_kappa, bad.ht.match_metric = 1.0, 7
+    assert _status(B.bmnd_workspace_size, g, noise, bad) == B.E_ARG
+
+
+@pytest.mark.parametrize("metric", ["deviance", "pearson", "anscombe"])
+def test_library_moment_tables_equal_oracle(metric):
+    code = {"deviance": B.METRIC_DEVIANCE, "pearson": B.METRIC_PEARSON,
+            "anscombe": B.METRIC_ANSCOMBE}[metric]
+    mu, v = B.bmnd_count_moments(code, 300)
+    for n in list(range(0, 60)) + [127, 128, 299, 300]:
+        mo, vo = O.count_moments(metric, n)
+        assert abs(mu[n] - mo) <= 1e-12 * max(1.0, abs(mo)), n
+        assert abs(v[n] - vo) <= 1e-11 * max(1.0, abs(vo)), n
+    assert _status(B.bmnd_count_moments, B.METRIC_SSD, 10) == B.E_ARG
+    assert _status(B.bmnd_count_moments, code, B.MOMENT_MAX_COUNT + 1) == B.E_ARG
