@@ -31,6 +31,7 @@ WSCOPE = {"group": 0, "patch": 1}
 NOISE = {"gaussian": 0, "poisson": 1}
 METRIC = {"ssd": 0, "deviance": 1, "pearson": 2, "anscombe": 3}
 POLICY = {"fixed": 0, "reference": 1, "standardized": 2}
+WDOMAIN = {"coefficient": 0, "windowed": 1}
 STAGE_HT, STAGE_WIENER = 0, 1
 
 
@@ -59,6 +60,7 @@ class _Cfg(C.Structure):
         ("sigma", C.c_double), ("s_p", C.c_double),
         ("metric", C.c_int32), ("policy", C.c_int32),
         ("match_t", C.c_double), ("struct_beta", C.c_double), ("struct_kappa", C.c_double),
+        ("weight_domain", C.c_int32), ("pad1", C.c_int32),
     ]
 
 
@@ -135,6 +137,7 @@ class Stage:
     match_t: float = 3.0        # threshold multiplier t
     struct_beta: float = 0.1    # structural allowance beta_s (reference policy)
     struct_kappa: float = 1.0   # its intensity exponent kappa_s
+    weight_domain: str = "coefficient"  # or "windowed" (synthesized domain)
     sigma: float = 0.0
     s_p: float = 1.0
 
@@ -173,6 +176,7 @@ class Stage:
         c.sigma, c.s_p = self.sigma, self.s_p
         c.metric, c.policy = METRIC[self.metric], POLICY[self.policy]
         c.match_t, c.struct_beta, c.struct_kappa = self.match_t, self.struct_beta, self.struct_kappa
+        c.weight_domain = WDOMAIN[self.weight_domain]
         return c
 
 

@@ -1055,7 +1055,38 @@ static int filter_group(stage_ctx* x, const orc_cfg* c, int stage, const double*
     }
 
     /* reliability weights (Defs. hard-thresholding / Wiener weighting
-     * models, coefficient domain; Def. aggregation-weight scope) */
+     * models, coefficient domain; Def. aggregation-weight scope).
+     * Windowed synthesized domain (Def. windowed synthesis metrics, Def.
+     * windowed synthesized-domain weighting models): the surrogate is
+     * tr(H F Sigma F^H) with the diagonal filter F and the diagonal of the
+     * selected noise model, i.e. sum_k H_kk t_k with t_k the coefficient
+     * term.  H = L^H L, L = W_g U_g; the column of L for coefficient k =
+     * (l, q) is U_g e_k windowed: member j holds H_lj (U_sp e_q)(i) w(i),
+     * so the patch-j diagonal entry is H_lj^2 h_q with h_q = sum_i (w(i)
+     * (U_sp e_q)(i))^2, and the group entry sums it over j. */
+    double* hq = NULL;
+    if (c->weight_domain == ORC_WDOMAIN_WINDOWED) {
+        hq = (double*)malloc(sizeof(double) * (size_t)P);
+        if (!hq) { free(mv); free(gam); free(shat); free(att); return -2; }
+        for (int q = 0; q < P; ++q) {
+            int qd[ORC_MAXD];
+            int rem = q;
+            for (int d = x->D - 1; d >= 0; --d) { qd[d] = rem % c->patch[d]; rem /= c->patch[d]; }
+            double s = 0.0;
+            for (int i = 0; i < P; ++i) {
+                int ri = i;
+                double col = 1.0;
+                for (int d = x->D - 1; d >= 0; --d) {
+                    const int n = c->patch[d];
+                    col *= x->Usp[d][(ri % n) * n + qd[d]];
+                    ri /= n;
+                }
+                const double v = x->omega[i] * col;
+                s += v * v;
+            }
+            hq[q] = s;
+        }
+    }
     double* rl = x->tmp + 2048;   /* per-plane surrogates r_l, K <= 32 */
     for (int l = 0; l < K; ++l) {
         double s = 0.0;
@@ -1063,13 +1094,25 @@ static int filter_group(stage_ctx* x, const orc_cfg* c, int stage, const double*
             int e = l * P + q;
             double a2 = att[e] * att[e];
             double sig2 = var[e] > 0.0 ? var[e] : 0.0;
-            if (c->weight_model == ORC_W_CLASSIC) s += a2;
-            else if (c->weight_model == ORC_W_VARIANCE) s += a2 * sig2;
-            else s += a2 * sig2 + (1.0 - att[e]) * (1.0 - att[e]) * shat[e];
+            double tk;
+            if (c->weight_model == ORC_W_CLASSIC) tk = a2;
+            else if (c->weight_model == ORC_W_VARIANCE) tk = a2 * sig2;
+            else tk = a2 * sig2 + (1.0 - att[e]) * (1.0 - att[e]) * shat[e];
+            s += hq ? hq[q] * tk : tk;
         }
         rl[l] = s;
     }
-    if (c->weight_scope == ORC_SCOPE_GROUP) {
+    if (hq && c->weight_scope == ORC_SCOPE_GROUP) {
+        /* group diagonal: sum_j H_lj^2 h_q */
+        double R = 0.0;
+        for (int l = 0; l < K; ++l) {
+            double hl = 0.0;
+            for (int j = 0; j < K; ++j) hl += x->H2[l * K + j];
+            R += hl * rl[l];
+        }
+        double wg = R > 0.0 ? 1.0 / R : 1.0;
+        for (int j = 0; j < K; ++j) w[j] = wg;
+    } else if (c->weight_scope == ORC_SCOPE_GROUP) {
         double R = 0.0;
         for (int l = 0; l < K; ++l) R += rl[l];
         double wg = R > 0.0 ? 1.0 / R : 1.0;
@@ -1082,6 +1125,7 @@ static int filter_group(stage_ctx* x, const orc_cfg* c, int stage, const double*
             w[j] = R > 0.0 ? 1.0 / R : 1.0;
         }
     }
+    free(hq);
     free(mv);
     free(gam);
     free(shat);

@@ -41,6 +41,9 @@ enum { ORC_STAGE_HT = 0, ORC_STAGE_WIENER = 1 };
 enum { ORC_METRIC_SSD = 0, ORC_METRIC_DEVIANCE = 1, ORC_METRIC_PEARSON = 2,
        ORC_METRIC_ANSCOMBE = 3 };
 enum { ORC_POLICY_FIXED = 0, ORC_POLICY_REFERENCE = 1, ORC_POLICY_STANDARDIZED = 2 };
+/* domain of the aggregation-weight surrogates (Def. windowed synthesized-
+ * domain weighting models) */
+enum { ORC_WDOMAIN_COEFFICIENT = 0, ORC_WDOMAIN_WINDOWED = 1 };
 
 /* One stage's full configuration (geometry + noise + stage profile). */
 typedef struct {
@@ -76,6 +79,8 @@ typedef struct {
     double  match_t;         /* threshold multiplier t                    */
     double  struct_beta;     /* structural allowance beta_s               */
     double  struct_kappa;    /* its intensity exponent kappa_s            */
+    int32_t weight_domain;   /* ORC_WDOMAIN_*                             */
+    int32_t pad1;
 } orc_cfg;
 
 /* All functions return 0 on success, <0 on bad arguments / allocation. */
