@@ -74,6 +74,10 @@ enum { BMND_PRESET_PLAIN = 0, BMND_PRESET_STANDARD = 1 };
 enum { BMND_METRIC_SSD = 0, BMND_METRIC_DEVIANCE = 1, BMND_METRIC_PEARSON = 2,
        BMND_METRIC_ANSCOMBE = 3 };
 enum { BMND_POLICY_FIXED = 0, BMND_POLICY_REFERENCE = 1, BMND_POLICY_STANDARDIZED = 2 };
+/* domain of the aggregation-weight surrogates: the coefficient domain, or
+ * the windowed synthesized domain (Def. windowed synthesized-domain
+ * weighting models) */
+enum { BMND_WDOMAIN_COEFFICIENT = 0, BMND_WDOMAIN_WINDOWED = 1 };
 /* pooled counts up to which the finite-count moment tables are exact */
 enum { BMND_MOMENT_MAX_COUNT = 4096 };
 
@@ -134,6 +138,8 @@ typedef struct {
     double match_t;                  /* threshold multiplier t >= 0            */
     double struct_beta;              /* structural allowance beta_s >= 0       */
     double struct_kappa;             /* its intensity exponent kappa_s > 0     */
+    int32_t weight_domain;           /* BMND_WDOMAIN_*                         */
+    int32_t reserved2;               /* must be 0                              */
 } bmnd_stage_params;
 
 typedef struct {
@@ -250,8 +256,12 @@ bmnd_status bmnd_match(int32_t stage, const float* d_src, const bmnd_geometry* g
  * Poisson variance model), shrink (eq. hard-threshold / soft-threshold,
  * or eq. wiener-gain with eq. pilot-power-family), compute the patch
  * reliability weights (Defs. coefficient-domain hard-thresholding /
- * Wiener weighting models, Def. aggregation-weight scope) and synthesize
- * p = U C with U = T^-1 (Def. pilot group).
+ * Wiener weighting models, Def. aggregation-weight scope; with
+ * BMND_WDOMAIN_WINDOWED every coefficient's term is weighted by the
+ * diagonal of the windowed synthesis metric H = U^H W^2 U, Def. windowed
+ * synthesis metrics, Def. windowed synthesized-domain weighting models,
+ * using the diagonal of the noise model) and synthesize p = U C with
+ * U = T^-1 (Def. pilot group).
  *   d_pilot    [batch][V] (Wiener only; NULL in the HT stage)
  *   d_match, d_count as produced by bmnd_match (other contents are read
  *              memory-safely: K is cut to a power of two in [1, group_max]

@@ -32,6 +32,7 @@ PRESET_PLAIN, PRESET_STANDARD = 0, 1
 METRIC_SSD, METRIC_DEVIANCE, METRIC_PEARSON, METRIC_ANSCOMBE = 0, 1, 2, 3
 POLICY_FIXED, POLICY_REFERENCE, POLICY_STANDARDIZED = 0, 1, 2
 MOMENT_MAX_COUNT = 4096
+WDOMAIN_COEFFICIENT, WDOMAIN_WINDOWED = 0, 1
 
 
 class BmndError(RuntimeError):
@@ -64,6 +65,7 @@ class StageParams(C.Structure):
         ("kaiser_beta", C.c_double),
         ("match_metric", C.c_int32), ("match_policy", C.c_int32),
         ("match_t", C.c_double), ("struct_beta", C.c_double), ("struct_kappa", C.c_double),
+        ("weight_domain", C.c_int32), ("reserved2", C.c_int32),
     ]
 
 

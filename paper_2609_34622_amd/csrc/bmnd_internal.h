@@ -50,6 +50,7 @@ struct StageCfg {
     int metric = BMND_METRIC_SSD, policy = BMND_POLICY_FIXED;
     double match_t = 3.0, sbeta = 0.1, skappa = 1.0;
     bool counts_integral = false;
+    int wdomain = BMND_WDOMAIN_COEFFICIENT;
 };
 
 // Device-resident immutable tables for one (spatial transform, patch, beta).
@@ -57,6 +58,7 @@ struct DevTables {
     const float* f32 = nullptr;   // packed float tables
     const double* f64 = nullptr;  // packed double tables
     int T[kAx], U[kAx], T2[kAx], win[kAx], rn[kAx];  // float offsets per axis
+    int hw[kAx];  // float offsets: windowed synthesis metric diagonal per coefficient
     int T64[kAx], T264[kAx];                         // double offsets per axis
     int haar;      // float offset of Haar H (32 x 32, row-major, for K = 32 .. 1 packed)
     int haar64;    // double offset of Haar H

@@ -12,6 +12,7 @@ struct FilterArgs {
     float s_p, sigma2, lambda, s_v, power_a;
     double s_p64, sigma2_64, lambda64;
     int wmodel, wscope;
+    int wdomain;   // BMND_WDOMAIN_*
     int kex;       // exact covariance planes (leading Haar planes l < kex)
     int gmax, n_refs;
     int out_mode;  // 0 patches, 1 aggregate (FP64 sums), 2 mc sweep 1, 3 mc sweep 2
@@ -29,6 +30,20 @@ struct FilterArgs {
 };
 
 constexpr int ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
+
+// diagonal of the windowed synthesis metric for spatial coefficient q (the
+// product over the axes of sum_i (w_i U[i][q_d])^2)
+__device__ inline float window_metric(const FilterArgs& a, int q)
+{
+    float h = 1.f;
+#pragma unroll
+    for (int d = kAx - 1; d >= 0; --d) {
+        const int n = a.g.j[d];
+        h *= a.t.f32[a.t.hw[d] + q % n];
+        q /= n;
+    }
+    return h;
+}
 
 
 bool cube_filter_supported(const Geo& g, int gmax);

@@ -93,6 +93,9 @@ bmnd_status check_stage(const bmnd_geometry* g, const bmnd_stage_params* sp, int
         return fail(BMND_E_ARG, "unknown weight scope");
     if (sp->k_exact < 0) return fail(BMND_E_ARG, "k_exact must be >= 0");
     if (!(sp->kaiser_beta >= 0.0)) return fail(BMND_E_ARG, "kaiser_beta must be >= 0");
+    if (sp->weight_domain != BMND_WDOMAIN_COEFFICIENT && sp->weight_domain != BMND_WDOMAIN_WINDOWED)
+        return fail(BMND_E_ARG, "unknown weight domain");
+    if (sp->reserved2 != 0) return fail(BMND_E_ARG, "reserved field must be 0");
     if (sp->match_metric < BMND_METRIC_SSD || sp->match_metric > BMND_METRIC_ANSCOMBE)
         return fail(BMND_E_ARG, "unknown matching metric");
     if (sp->match_policy < BMND_POLICY_FIXED || sp->match_policy > BMND_POLICY_STANDARDIZED)
@@ -187,6 +190,7 @@ bmnd_status make_stage(const bmnd_geometry* g, const bmnd_noise* n, const bmnd_s
     c.sbeta = sp->struct_beta;
     c.skappa = sp->struct_kappa;
     c.counts_integral = n && n->kind == BMND_NOISE_POISSON && n->counts_integral;
+    c.wdomain = sp->weight_domain;
     return BMND_OK;
 }
 
@@ -230,6 +234,20 @@ const DevTables* device_tables(const StageCfg& c, std::string& err)
         for (double v : T) f.push_back(float(v * v));
         t.win[d] = int(f.size());
         for (double v : kaiser_window(n, c.beta)) f.push_back(float(v));
+        // diagonal of the windowed synthesis metric per coefficient q:
+        // sum_i (w_i U[i][q])^2 (U stored sample-major, U[i][q] = U[i * n + q])
+        t.hw[d] = int(f.size());
+        {
+            const std::vector<double> w = kaiser_window(n, c.beta);
+            for (int q = 0; q < n; ++q) {
+                double s = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    const double v = w[size_t(i)] * U[size_t(i * n + q)];
+                    s += v * v;
+                }
+                f.push_back(float(s));
+            }
+        }
         t.rn[d] = int(f.size());
         for (int q = 0; q < n; ++q) {
             double s = 0.0;
@@ -387,6 +405,7 @@ bmnd_stage_params preset_stage(int32_t preset, int32_t ndim, int stage)
     p.match_t = 3.0;
     p.struct_beta = 0.1;
     p.struct_kappa = 1.0;
+    p.weight_domain = BMND_WDOMAIN_COEFFICIENT;
     return p;
 }
 

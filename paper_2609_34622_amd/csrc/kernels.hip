@@ -739,6 +739,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
             if (a.wmodel == BMND_WEIGHT_CLASSIC) r = at * at;
             else if (a.wmodel == BMND_WEIGHT_VARIANCE) r = at * at * v;
             else r = at * at * v + (1.f - at) * (1.f - at) * B[e];
+            if (a.wdomain == BMND_WDOMAIN_WINDOWED) r *= window_metric(a, e - l * P);
             atomicAdd(&rpl[l], r);
         }
         __syncthreads();
@@ -1015,6 +1016,7 @@ static FilterArgs filter_args(const StageCfg& c, const DevTables& t, int out_mod
     a.lambda64 = c.lambda;
     a.wmodel = c.wmodel;
     a.wscope = c.wscope;
+    a.wdomain = c.wdomain;
     a.kex = c.k_exact;
     a.gmax = c.gmax;
     a.out_mode = out_mode;

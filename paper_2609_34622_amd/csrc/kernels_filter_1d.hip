@@ -189,7 +189,7 @@ __device__ __forceinline__ h8 opnd_h(const _Float16* ops, int m, int part, int c
 }
 
 // SH: shrinkage; STAGED: 1-D arrays whose chunk windows are staged in LDS;
-// WPLAIN: classic weights in group scope
+// WPLAIN: classic weights in group scope, coefficient domain
 template <int SH, bool STAGED, bool WPLAIN>
 __global__ __launch_bounds__(kWave * kWaves) __attribute__((amdgpu_waves_per_eu(3)))
 void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
@@ -578,11 +578,18 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                             tr[c][r] = at * at * v_[c][r] + (1.f - at) * (1.f - at) * sh_[c][r];
                         }
                 }
+                // windowed synthesized domain: each term weighted by the
+                // metric's diagonal at its spatial coefficient
+                float hq[2] = {1.f, 1.f};
+                if (a.wdomain == BMND_WDOMAIN_WINDOWED) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) hq[c] = window_metric(a, 16 * c + m16);
+                }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const bool lv = 4 * lg + r < K;
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) tr[c][r] = lv ? tr[c][r] : 0.f;
+                    for (int c = 0; c < 2; ++c) tr[c][r] = lv ? tr[c][r] * hq[c] : 0.f;
                 }
                 if (a.wscope == BMND_SCOPE_GROUP) {
                     float t = 0.f;
@@ -808,7 +815,8 @@ hipError_t launch_filter_1d(const FilterArgs& a, int step_last, hipStream_t s)
     const dim3 grid(unsigned(long(nchunk) * g.batch));
     const size_t lds = sizeof(float) * size_t(kWaves * 2 * wcap + nstage * tile_cap);
     const bool staged = tile_cap >= 8;
-    const bool wplain = a.wmodel == BMND_WEIGHT_CLASSIC && a.wscope == BMND_SCOPE_GROUP;
+    const bool wplain = a.wmodel == BMND_WEIGHT_CLASSIC && a.wscope == BMND_SCOPE_GROUP &&
+                        a.wdomain == BMND_WDOMAIN_COEFFICIENT;
 #define BMND_F1D(SH, ST, WP)                                                                     \
     hipLaunchKernelGGL((k_filter_1d<SH, ST, WP>), grid, dim3(kWave * kWaves), lds, s, a, sub,   \
                        tile_cap, tile_back, wcap)

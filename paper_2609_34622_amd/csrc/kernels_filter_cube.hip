@@ -464,6 +464,7 @@ void k_filter_cube(FilterArgs a, int chunk_refs)
                 if (a.wmodel == BMND_WEIGHT_CLASSIC) r = at * at;
                 else if (a.wmodel == BMND_WEIGHT_VARIANCE) r = at * at * v;
                 else r = at * at * v + (1.f - at) * (1.f - at) * Bb[e];
+                if (a.wdomain == BMND_WDOMAIN_WINDOWED) r *= window_metric(a, e - l * P);
                 atomicAdd(&rpl[l], r);
             }
             wsync();

@@ -315,6 +315,9 @@ VARIANTS = [
     dict(wweights=("risk", "patch"), power_a=0.4),
     dict(power_a=1.0),
     dict(spatial=("dct", "bior1.5")),
+    dict(domain="windowed"),
+    dict(weights=("variance", "patch"), domain="windowed"),
+    dict(wweights=("risk", "group"), domain="windowed"),
 ]
 
 
@@ -357,6 +360,9 @@ def test_profile_variants_stagewise(var):
         a, b = var["spatial"]
         p.ht.spatial, p.wiener.spatial = B.SPATIAL[a], B.SPATIAL[b]
         ht.spatial, wie.spatial = a, b
+    if var.get("domain") == "windowed":
+        p.ht.weight_domain = p.wiener.weight_domain = B.WDOMAIN_WINDOWED
+        ht.weight_domain = wie.weight_domain = "windowed"
     geom = B.geometry(shape)
     out, pilot = gpu_denoise(dev(y), geom, noise, p)
     pil_o = O.run_stage(ht, O.STAGE_HT, y)
@@ -617,6 +623,41 @@ def test_filter_1d_far_members(stage):
                       O.STAGE_WIENER if stage == "wiener" else O.STAGE_HT, y, pilot, match[0], count[0])
     for g in range(n):
         K = count[0, g]
+        scale = max(np.abs(po[g, :K]).max(), 1e-30)
+        assert np.abs(pg[0, g, :K] - po[g, :K]).max() <= REL_PATCH * scale, g
+        assert np.allclose(wg[0, g, :K], wo[g, :K], rtol=1e-5), g
+
+
+
+@pytest.mark.parametrize("stage", ["ht", "wiener"])
+def test_filter_1d_windowed_weights(stage):
+    """Windowed synthesized-domain weights on the 1-D matrix-core filter:
+    patches and weights on the GPU's own lists against the oracle's."""
+    _say(f"1-D windowed weights, {stage}")
+    L = 6000
+    s = synth.ecg_batch(n_signals=1, length=L, seed=2800)
+    shape, patch, step, search = (L,), (32,), (4,), (128,)
+    p = params_for(shape, patch, step, search, group=(16, 16))
+    ht, wie = oracle_stages(shape, patch, step, search, s.s_p, group=(16, 16))
+    p.ht.weight_domain = p.wiener.weight_domain = B.WDOMAIN_WINDOWED
+    ht.weight_domain = wie.weight_domain = "windowed"
+    if stage == "wiener":
+        p.wiener.weight_model = B.WEIGHT["variance"]
+        wie.weight_model = "variance"
+    geom = B.geometry(shape)
+    y = s.y[0].astype(np.float32)
+    pilot = np.asarray(s.x[0], np.float32) if stage == "wiener" else None
+    sp = p.wiener if stage == "wiener" else p.ht
+    st_id = B.STAGE_WIENER if stage == "wiener" else B.STAGE_HT
+    refs = B.bmnd_reference_origins(geom, sp)
+    src = dev(pilot[None]) if stage == "wiener" else dev(y[None])
+    mg, cg = gpu_match(st_id, src, geom, B.poisson(s.s_p), sp, refs)
+    pg, wg = gpu_filter(st_id, dev(y[None]), None if pilot is None else dev(pilot[None]), geom,
+                        B.poisson(s.s_p), sp, mg, cg)
+    po, wo = O.filter(wie if stage == "wiener" else ht,
+                      O.STAGE_WIENER if stage == "wiener" else O.STAGE_HT, y, pilot, mg[0], cg[0])
+    for g in range(len(refs)):
+        K = cg[0, g]
         scale = max(np.abs(po[g, :K]).max(), 1e-30)
         assert np.abs(pg[0, g, :K] - po[g, :K]).max() <= REL_PATCH * scale, g
         assert np.allclose(wg[0, g, :K], wo[g, :K], rtol=1e-5), g
