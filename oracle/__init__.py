@@ -28,7 +28,7 @@ SPATIAL = {"identity": 0, "dct": 1, "bior1.5": 2}
 SHRINK = {"hard": 0, "soft": 1, "wiener": 2}
 WMODEL = {"classic": 0, "variance": 1, "risk": 2}
 WSCOPE = {"group": 0, "patch": 1}
-NOISE = {"gaussian": 0, "poisson": 1}
+NOISE = {"gaussian": 0, "poisson": 1, "correlated": 2}
 METRIC = {"ssd": 0, "deviance": 1, "pearson": 2, "anscombe": 3}
 POLICY = {"fixed": 0, "reference": 1, "standardized": 2}
 WDOMAIN = {"coefficient": 0, "windowed": 1}
@@ -61,6 +61,7 @@ class _Cfg(C.Structure):
         ("metric", C.c_int32), ("policy", C.c_int32),
         ("match_t", C.c_double), ("struct_beta", C.c_double), ("struct_kappa", C.c_double),
         ("weight_domain", C.c_int32), ("pad1", C.c_int32),
+        ("acov", C.c_void_p),
     ]
 
 
@@ -140,6 +141,7 @@ class Stage:
     weight_domain: str = "coefficient"  # or "windowed" (synthesized domain)
     sigma: float = 0.0
     s_p: float = 1.0
+    psd: Optional[np.ndarray] = None   # correlated noise: PSD on the array's DFT grid
 
     @property
     def P(self) -> int:
@@ -177,16 +179,33 @@ class Stage:
         c.metric, c.policy = METRIC[self.metric], POLICY[self.policy]
         c.match_t, c.struct_beta, c.struct_kappa = self.match_t, self.struct_beta, self.struct_kappa
         c.weight_domain = WDOMAIN[self.weight_domain]
+        if self.noise == "correlated":
+            if self.psd is None:
+                raise ValueError("correlated noise needs a power spectral density")
+            acov = autocovariance(self.psd)
+            if acov.shape != tuple(int(v) for v in self.shape):
+                raise ValueError("the power spectral density must have the array's shape")
+            c.acov = acov.ctypes.data
+            c._keep = acov    # the C side reads it through the pointer
         return c
 
 
+def autocovariance(psd: np.ndarray) -> np.ndarray:
+    """Autocovariance c(tau) of stationary Gaussian noise from its power
+    spectral density on the array's DFT grid (discrete Wiener-Khinchin
+    relation, section Observation Models): c = ifftn(S) / |Omega|, real part
+    (the autocovariance of a real field is real and even)."""
+    S = np.asarray(psd, dtype=np.float64)
+    return np.ascontiguousarray(np.real(np.fft.ifftn(S)) / S.size)
+
+
 def plain_profile(shape, patch, step, search, s_p=1.0, group=(16, 32), mc=(False, False),
-                  noise="poisson", sigma=0.0, counts_integral=True):
+                  noise="poisson", sigma=0.0, counts_integral=True, psd=None):
     """The ablation reference levels ("plain"): SSD with gamma = 3 in the HT
     stage, no exact covariance planes, classic gain, classic group weights,
     hard threshold lambda = 3, s_v = 0.4, Kaiser beta = 2, generated (2, 2)."""
     common = dict(shape=tuple(shape), patch=tuple(patch), step=tuple(step), search=tuple(search),
-                  noise=noise, s_p=s_p, sigma=sigma, counts_integral=counts_integral)
+                  noise=noise, s_p=s_p, sigma=sigma, counts_integral=counts_integral, psd=psd)
     ht = Stage(**common, group_max=group[0], gamma=3.0, spatial="bior1.5", shrink="hard",
                mass_conservation=mc[0])
     wie = Stage(**common, group_max=group[1], gamma=0.0, spatial="dct", shrink="wiener",

@@ -74,7 +74,28 @@ static int check_cfg(const orc_cfg* c)
     if (c->weight_model < ORC_W_CLASSIC || c->weight_model > ORC_W_RISK) return -1;
     if (c->noise_kind == ORC_NOISE_POISSON && !(c->s_p > 0.0)) return -1;
     if (c->noise_kind == ORC_NOISE_GAUSSIAN && !(c->sigma >= 0.0)) return -1;
+    if (c->noise_kind == ORC_NOISE_CORRELATED && !c->acov) return -1;
+    if (c->noise_kind < ORC_NOISE_GAUSSIAN || c->noise_kind > ORC_NOISE_CORRELATED) return -1;
     return 0;
+}
+
+/* Autocovariance at a displacement (Def. wide-sense stationary Gaussian
+ * noise): the inverse DFT of the power spectral density samples c on the
+ * discrete torus, so every component is taken modulo the axis length. */
+static double acov_at(const orc_cfg* c, const int64_t* tau)
+{
+    int64_t idx = 0;
+    for (int d = 0; d < c->ndim; ++d) {
+        int64_t t = tau[d] % c->shape[d];
+        if (t < 0) t += c->shape[d];
+        idx = idx * c->shape[d] + t;
+    }
+    return c->acov[idx];
+}
+
+static void coords_of(const orc_cfg* c, int64_t lin, int64_t* co)
+{
+    for (int d = c->ndim - 1; d >= 0; --d) { co[d] = lin % c->shape[d]; lin /= c->shape[d]; }
 }
 
 static int64_t pow2floor64(int64_t x)
@@ -729,6 +750,20 @@ int orc_match(const orc_cfg* c, int32_t stage, const double* src, const double* 
                     b += (p + q > 0.0) ? (p + q) : 0.0;
                 }
                 s = ssd - c->gamma * c->s_p * b;
+            } else if (c->noise_kind == ORC_NOISE_CORRELATED) {
+                /* Prop. Gaussian SSD noise bias: B_G(Delta) = 2 P (c(0) -
+                 * c(Delta)), Delta the displacement from the reference's
+                 * origin to the candidate's */
+                double ssd = 0.0;
+                for (int i = 0; i < P; ++i) {
+                    double df = src[clin + off[i]] - src[r + off[i]];
+                    ssd += df * df;
+                }
+                int64_t cq[ORC_MAXD], dl[ORC_MAXD], z[ORC_MAXD];
+                coords_of(c, clin, cq);
+                for (int d = 0; d < D; ++d) { dl[d] = cq[d] - rc[d]; z[d] = 0; }
+                double bg = 2.0 * (double)P * (acov_at(c, z) - acov_at(c, dl));
+                s = ssd - c->gamma * bg;
             } else {
                 double ssd = 0.0;
                 for (int i = 0; i < P; ++i) {
@@ -975,10 +1010,46 @@ static int filter_group(stage_ctx* x, const orc_cfg* c, int stage, const double*
     mode_product(var, x->dims, x->D + 1, 0, x->H2, x->tmp);
     for (int d = 0; d < x->D; ++d) mode_product(var, x->dims, x->D + 1, d + 1, x->T2sp[d], x->tmp);
 
+    /* stationary correlated Gaussian noise: the group covariance is
+     * Sigma_g[a][b] = c(u_b - u_a) over the source locations of the group
+     * entries (Def. wide-sense stationary Gaussian noise; repeated voxels
+     * give c(0) and are fully correlated), and the coefficient variances are
+     * the diagonal of T Sigma_g T^H (Lemma covariance propagation), for
+     * every plane */
+    if (c->noise_kind == ORC_NOISE_CORRELATED) {
+        double* S = (double*)malloc(sizeof(double) * (size_t)n * (size_t)n);
+        int64_t* uc = (int64_t*)malloc(sizeof(int64_t) * (size_t)n * ORC_MAXD);
+        if (!S || !uc) { free(S); free(uc); free(mv); free(gam); free(shat); free(att); return -2; }
+        for (int e = 0; e < n; ++e)
+            coords_of(c, (int64_t)org[e / P] + x->off[e % P], uc + (size_t)e * ORC_MAXD);
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                int64_t dl[ORC_MAXD];
+                for (int d = 0; d < x->D; ++d)
+                    dl[d] = uc[(size_t)b * ORC_MAXD + d] - uc[(size_t)a * ORC_MAXD + d];
+                S[(size_t)a * n + b] = acov_at(c, dl);
+            }
+        /* rows of S (each a group-shaped array) times T^T, then the same on
+         * the transpose: the result is (T S T^T)^T */
+        for (int a = 0; a < n; ++a) apply_forward(x, S + (size_t)a * n);
+        for (int a = 0; a < n; ++a)
+            for (int b = a + 1; b < n; ++b) {
+                double t = S[(size_t)a * n + b];
+                S[(size_t)a * n + b] = S[(size_t)b * n + a];
+                S[(size_t)b * n + a] = t;
+            }
+        for (int a = 0; a < n; ++a) apply_forward(x, S + (size_t)a * n);
+        for (int e = 0; e < n; ++e) var[e] = S[(size_t)e * n + e];
+        free(S);
+        free(uc);
+    }
+
     /* exact shared-source planes l < k_ex (Def. effective transform weights,
      * Def. partial shared-source Poisson variance model): group entries from
-     * the same voxel are combined before squaring */
+     * the same voxel are combined before squaring.  The correlated model is
+     * exact already. */
     int kex = c->k_exact < K ? c->k_exact : K;
+    if (c->noise_kind == ORC_NOISE_CORRELATED) kex = 0;
     if (kex > 0) {
         int64_t* ulin = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
         int* order = (int*)malloc(sizeof(int) * (size_t)n);

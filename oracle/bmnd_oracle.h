@@ -34,7 +34,10 @@ enum { ORC_SPATIAL_IDENTITY = 0, ORC_SPATIAL_DCT = 1, ORC_SPATIAL_BIOR15 = 2 };
 enum { ORC_SHRINK_HARD = 0, ORC_SHRINK_SOFT = 1, ORC_SHRINK_WIENER = 2 };
 enum { ORC_W_CLASSIC = 0, ORC_W_VARIANCE = 1, ORC_W_RISK = 2 };
 enum { ORC_SCOPE_GROUP = 0, ORC_SCOPE_PATCH = 1 };
-enum { ORC_NOISE_GAUSSIAN = 0, ORC_NOISE_POISSON = 1 };
+/* noise models: white Gaussian, scaled Poisson, and stationary correlated
+ * Gaussian given by its periodic autocovariance (Def. wide-sense stationary
+ * Gaussian noise) */
+enum { ORC_NOISE_GAUSSIAN = 0, ORC_NOISE_POISSON = 1, ORC_NOISE_CORRELATED = 2 };
 enum { ORC_STAGE_HT = 0, ORC_STAGE_WIENER = 1 };
 /* HT matching distance and acceptance policy (section Metrics, subsection
  * Exact Finite-Count Moment Calibration) */
@@ -81,6 +84,10 @@ typedef struct {
     double  struct_kappa;    /* its intensity exponent kappa_s            */
     int32_t weight_domain;   /* ORC_WDOMAIN_*                             */
     int32_t pad1;
+    /* correlated Gaussian noise: the autocovariance c(tau) sampled on the
+     * array's own grid (prod(shape) doubles, C-order, tau_d in [0, L_d)),
+     * periodic, as the inverse DFT of the power spectral density gives it */
+    const double* acov;
 } orc_cfg;
 
 /* All functions return 0 on success, <0 on bad arguments / allocation. */
