@@ -317,6 +317,54 @@ def bench_poisson_metrics(B, torch, n_signals: int = 16, reps: int = 3) -> dict:
     return {"signals": n_signals, "shape": list(shape), "search": list(w["search"]), **res}
 
 
+def bench_correlated(B, torch, size: int = 1024, reps: int = 3) -> dict:
+    """Stationary correlated Gaussian noise on a 2-D image (Gaussian-filtered
+    white noise, sigma 0.1, correlation length 1 px): preparing the tables
+    from the spectral density, then the denoise, beside the white-Gaussian
+    model on the same input."""
+    from paper_2609_34622_amd import synth
+
+    w = WORKLOADS["microscopy-2d-16x1024"]
+    shape = (size, size)
+    s = synth.correlated_gaussian(shape, seed=8000, sigma=0.1, corr_len=1.0)
+    y = torch.from_numpy(np.ascontiguousarray(s.y)).cuda()
+    psd = torch.from_numpy(s.psd).cuda()
+    geom = B.geometry(shape)
+    p = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    for sp in (p.ht, p.wiener):
+        B.set_axes(sp, patch=w["patch"], step=w["step"], search=w["search"])
+    p.ht.group_max, p.wiener.group_max = w["group"]
+    tables = B.bmnd_correlated_prepare(psd, geom, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.bmnd_correlated_prepare(psd, geom, p, tables)
+    torch.cuda.synchronize()
+    prep = (time.perf_counter() - t0) / reps
+    res = {"prepare_ms": round(prep * 1e3, 3), "table_bytes": int(tables.numel())}
+    for name, noise in (("correlated", B.correlated(tables)), ("white", B.gaussian(s.sigma))):
+        ws = torch.empty(B.bmnd_workspace_size(geom, noise, p), dtype=torch.uint8, device="cuda")
+        out = torch.empty_like(y)
+        B.bmnd_denoise(y, geom, noise, p, out, None, ws)
+        torch.cuda.synchronize()
+        B.bmnd_profile_begin()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            B.bmnd_denoise(y, geom, noise, p, out, None, ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        prof = B.bmnd_profile_end()
+        res[name] = {"mvox_per_s": round(size * size / dt / 1e6, 3), "ms": round(dt * 1e3, 3),
+                     "kernels_ms": {k: round(v[0] / reps, 3) for k, v in prof.items() if v[1]}}
+        if name == "correlated":
+            o = out.cpu().numpy()
+            res["mse_ratio"] = round(float(np.mean((o - s.x) ** 2) / np.mean((s.y - s.x) ** 2)), 4)
+        del ws, out
+    B.bmnd_stream_status()
+    return {"workload": f"image-2d-{size}-correlated", "shape": list(shape),
+            "search": list(w["search"]), "group": list(w["group"]), **res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -446,12 +494,13 @@ def main():
                "sample": f"{n} of {batch} arrays of the same workload, both stages, "
                          f"{dt:.1f} s single-threaded"}
 
-    batched = serving_row = standard = pois = None
+    batched = serving_row = standard = pois = corr = None
     if args.mixed:
         batched = bench_batched(B, torch)
         serving_row = bench_serving(B, torch)
         standard = bench_standard(B, torch)
         pois = bench_poisson_metrics(B, torch)
+        corr = bench_correlated(B, torch)
 
     line = {
         "metric": "denoised Mvox/s (both stages)",
@@ -470,6 +519,7 @@ def main():
         "serving": serving_row,
         "standard_profile": standard,
         "poisson_metrics": pois,
+        "correlated_gaussian": corr,
     }
     print(json.dumps(line), flush=True)
 

@@ -60,7 +60,7 @@ enum {
 };
 
 enum { BMND_STAGE_HT = 0, BMND_STAGE_WIENER = 1 };
-enum { BMND_NOISE_GAUSSIAN = 0, BMND_NOISE_POISSON = 1 };
+enum { BMND_NOISE_GAUSSIAN = 0, BMND_NOISE_POISSON = 1, BMND_NOISE_CORRELATED = 2 };
 enum { BMND_SCHED_GENERATED = 0, BMND_SCHED_BALANCED = 1, BMND_SCHED_SPARSE = 2,
        BMND_SCHED_OFF = 3 };
 enum { BMND_SPATIAL_IDENTITY = 0, BMND_SPATIAL_DCT = 1, BMND_SPATIAL_BIOR15 = 2 };
@@ -97,12 +97,17 @@ typedef struct {
  *             model).  counts_integral != 0 declares that y / s_P is an
  *             integer up to float32 storage rounding; the HT-stage matching
  *             then runs exactly on the equivalent raw counts rint(y / s_P)
- *             (eq. raw-counts; unit invariance of count statistics). */
+ *             (eq. raw-counts; unit invariance of count statistics).
+ *   Correlated: y = x + n, n wide-sense stationary Gaussian (Def. wide-sense
+ *             stationary Gaussian noise) with the power spectral density
+ *             given to bmnd_correlated_prepare; d_corr points to the tables
+ *             that call wrote, for the same geometry and parameters. */
 typedef struct {
     int32_t kind;                    /* BMND_NOISE_*                           */
     int32_t counts_integral;         /* Poisson only: 0 / 1                    */
     double sigma;                    /* Gaussian: >= 0                         */
     double s_p;                      /* Poisson: > 0                           */
+    const void* d_corr;              /* Correlated: prepared tables (device)   */
 } bmnd_noise;
 
 /* Parameters of one stage (Appendix A standard profile; Appendix B
@@ -191,6 +196,41 @@ bmnd_status bmnd_kaiser_window(int32_t n, double beta, double* w);
  * [0, BMND_MOMENT_MAX_COUNT]. */
 bmnd_status bmnd_count_moments(int32_t metric, int32_t nmax, double* mu, double* v);
 
+/* Stationary correlated Gaussian noise (section Observation Models: Def.
+ * wide-sense stationary Gaussian noise and the discrete Wiener-Khinchin
+ * relation c = ifftn(S) / |Omega|; Prop. Gaussian SSD noise bias; Lemma
+ * covariance propagation).
+ *
+ * bmnd_correlated_size: bytes of the device tables for one array shape
+ * (geom->batch is ignored: every array of a batch has the same noise) and
+ * both stages of `params`.
+ *
+ * bmnd_correlated_prepare: from the power spectral density S on the
+ * array's own DFT grid (d_psd: device, prod(shape) doubles, C-order,
+ * S(omega) >= 0 is not checked), compute into d_tables (device, caller
+ * owned, `bytes` >= the size above, 256-byte aligned):
+ *   - the autocovariance c(tau) = Re ifftn(S)(tau) / |Omega| for every
+ *     displacement the method needs, tau taken modulo the shape;
+ *   - per stage, the variance table D(Delta, q) = sum_tau A_q(tau)
+ *     c(Delta + tau) over the member displacements Delta of the search
+ *     window and the spatial coefficients q, with A_q the autocorrelation of
+ *     row q of the stage's spatial transform, so that a group's coefficient
+ *     variances are sigma^2_(l,q) = sum_(j,j') H_lj H_lj' D(u_j' - u_j, q),
+ *     the diagonal of T Sigma_g T^T with Sigma_g[a][b] = c(u_b - u_a);
+ *   - for the HT stage, the matching bias gamma 2 P (c(0) - c(Delta)) of
+ *     every window offset.
+ * Stream-ordered on `stream`.  The tables stay valid until d_tables is
+ * freed or prepared again; bmnd_match / bmnd_filter / bmnd_denoise check
+ * that a noise model's d_corr was prepared by this call for the same shape
+ * and the same patch, search, spatial transform and gamma of the stage.
+ * Errors: BMND_E_ARG (NULL pointers, bad geometry or parameters),
+ * BMND_E_WORKSPACE (bytes too small or d_tables misaligned), BMND_E_HIP. */
+bmnd_status bmnd_correlated_size(const bmnd_geometry* geom, const bmnd_params* params,
+                                 size_t* bytes);
+bmnd_status bmnd_correlated_prepare(const double* d_psd, const bmnd_geometry* geom,
+                                    const bmnd_params* params, void* d_tables, size_t bytes,
+                                    void* stream);
+
 /* Workspace bytes for bmnd_match / bmnd_aggregate / bmnd_denoise. */
 bmnd_status bmnd_match_workspace_size(const bmnd_geometry* geom, const bmnd_stage_params* sp,
                                       size_t* bytes);
@@ -205,6 +245,9 @@ bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noi
  * origin of the clipped search window:
  *   HT, Gaussian: SSD - gamma 2 P sigma^2 (Prop. Gaussian SSD noise bias,
  *                 white noise; Def. noise-bias-corrected SSD);
+ *   HT, Correlated: SSD - gamma 2 P (c(0) - c(Delta)), Delta the
+ *                 displacement from the reference origin to the candidate's
+ *                 (Prop. Gaussian SSD noise bias);
  *   HT, Poisson:  SSD - gamma s_P sum[p + q]_+ (Prop. scaled-Poisson SSD
  *                 noise bias; Def. noise-bias-corrected SSD), computed on
  *                 the raw counts when counts_integral is set;
@@ -253,7 +296,10 @@ bmnd_status bmnd_match(int32_t stage, const float* d_src, const bmnd_geometry* g
  * (x) ..., propagate the noise variances sigma_k^2 = sum |T_ki|^2 m_v(u_i)
  * (Prop. diagonal Poisson variance propagation) with the leading k_exact
  * Haar planes from the shared-source model (Def. partial shared-source
- * Poisson variance model), shrink (eq. hard-threshold / soft-threshold,
+ * Poisson variance model); under correlated noise sigma_k^2 is the
+ * diagonal of T Sigma_g T^T for every plane (k_exact is ignored), and every
+ * member must lie within the search window of the group's reference (as
+ * bmnd_match places them; displacements beyond it are clamped), shrink (eq. hard-threshold / soft-threshold,
  * or eq. wiener-gain with eq. pilot-power-family), compute the patch
  * reliability weights (Defs. coefficient-domain hard-thresholding /
  * Wiener weighting models, Def. aggregation-weight scope; with

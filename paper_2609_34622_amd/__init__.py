@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libbmnd.so")
 MAX_AXES = 8
 OK, E_ARG, E_SHAPE, E_UNSUPPORTED, E_NOMEM, E_HIP, E_WORKSPACE, E_RANGE = 0, -1, -2, -3, -4, -5, -6, -7
 STAGE_HT, STAGE_WIENER = 0, 1
-NOISE_GAUSSIAN, NOISE_POISSON = 0, 1
+NOISE_GAUSSIAN, NOISE_POISSON, NOISE_CORRELATED = 0, 1, 2
 SCHED = {"generated": 0, "balanced": 1, "sparse": 2, "off": 3}
 SPATIAL = {"identity": 0, "dct": 1, "bior1.5": 2}
 SHRINK = {"hard": 0, "soft": 1, "wiener": 2}
@@ -48,7 +48,7 @@ class Geometry(C.Structure):
 
 class Noise(C.Structure):
     _fields_ = [("kind", C.c_int32), ("counts_integral", C.c_int32), ("sigma", C.c_double),
-                ("s_p", C.c_double)]
+                ("s_p", C.c_double), ("d_corr", C.c_void_p)]
 
 
 class StageParams(C.Structure):
@@ -88,6 +88,7 @@ EXPORTS = [
     "bmnd_match", "bmnd_filter", "bmnd_aggregate", "bmnd_denoise", "bmnd_stream_status",
     "bmnd_transform_matrices", "bmnd_haar_matrix", "bmnd_kaiser_window", "bmnd_count_moments",
     "bmnd_profile_begin", "bmnd_profile_end", "bmnd_batch_workspace_size", "bmnd_denoise_batch",
+    "bmnd_correlated_size", "bmnd_correlated_prepare",
 ]
 KERNEL_IDS = ["counts", "patch_sums", "match_ht", "match_wiener", "filter_ht", "filter_wiener",
               "zero", "normalize"]
@@ -127,6 +128,8 @@ def lib() -> C.CDLL:
         "bmnd_profile_end": (i32, [vp, vp, i32]),
         "bmnd_batch_workspace_size": (i32, [i32, C.POINTER(Job), C.POINTER(sz)]),
         "bmnd_denoise_batch": (i32, [i32, C.POINTER(Job), vp, sz, i32, vp]),
+        "bmnd_correlated_size": (i32, [G, PP, C.POINTER(sz)]),
+        "bmnd_correlated_prepare": (i32, [vp, G, PP, vp, sz, vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -197,6 +200,16 @@ def gaussian(sigma: float) -> Noise:
     return n
 
 
+def correlated(tables) -> Noise:
+    """Stationary correlated Gaussian noise described by the device tables
+    that ``bmnd_correlated_prepare`` wrote (the Noise keeps them alive)."""
+    n = Noise()
+    n.kind = NOISE_CORRELATED
+    n.d_corr = _ptr(tables)
+    n._keep = tables
+    return n
+
+
 def set_axes(sp: StageParams, patch=None, step=None, search=None):
     for name, vals in (("patch", patch), ("step", step), ("search", search)):
         if vals is not None:
@@ -252,6 +265,28 @@ def bmnd_count_moments(metric: int, nmax: int):
     v = np.zeros(nmax + 1)
     _check(lib().bmnd_count_moments(metric, nmax, mu.ctypes.data, v.ctypes.data))
     return mu, v
+
+
+def bmnd_correlated_size(geom: Geometry, params: Params) -> int:
+    b = C.c_size_t(0)
+    _check(lib().bmnd_correlated_size(C.byref(geom), C.byref(params), C.byref(b)))
+    return b.value
+
+
+def bmnd_correlated_prepare(psd, geom: Geometry, params: Params, tables=None, stream=None):
+    """Tables of stationary correlated Gaussian noise from its power spectral
+    density ``psd`` (device float64, the array's shape, C-order); returns
+    the uint8 device tensor that holds them (``tables`` if given)."""
+    import torch
+
+    n = bmnd_correlated_size(geom, params)
+    _require(psd, torch.float64, int(np.prod([geom.shape[d] for d in range(geom.ndim)])), "psd")
+    if tables is None:
+        tables = torch.empty(n, dtype=torch.uint8, device=psd.device)
+    _require(tables, torch.uint8, n, "tables")
+    _check(lib().bmnd_correlated_prepare(_ptr(psd), C.byref(geom), C.byref(params), _ptr(tables),
+                                         tables.numel(), _stream(stream)))
+    return tables
 
 
 def bmnd_match_workspace_size(geom: Geometry, sp: StageParams) -> int:

@@ -31,6 +31,16 @@ struct Geo {
     int batch;     // arrays
 };
 
+// Stationary correlated Gaussian noise: one stage's device tables, inside
+// the caller's prepared buffer.
+struct CorrStage {
+    const double* dtab = nullptr;       // D(Delta, q), [member box][P]
+    const double* bias = nullptr;       // HT: gamma 2 P (c(0) - c(Delta)) per window offset
+    const float* bias32 = nullptr;      // the same in FP32
+    const double* bias_bound = nullptr; // >= every |bias| (one value)
+    int bw[kAx] = {1, 1, 1, 1};         // member box extents 2 Wm_d - 1
+};
+
 // Host-side stage description after validation.
 struct StageCfg {
     Geo g;
@@ -51,6 +61,7 @@ struct StageCfg {
     double match_t = 3.0, sbeta = 0.1, skappa = 1.0;
     bool counts_integral = false;
     int wdomain = BMND_WDOMAIN_COEFFICIENT;
+    CorrStage corr;  // correlated noise only
 };
 
 // Device-resident immutable tables for one (spatial transform, patch, beta).
@@ -60,6 +71,9 @@ struct DevTables {
     int T[kAx], U[kAx], T2[kAx], win[kAx], rn[kAx];  // float offsets per axis
     int hw[kAx];  // float offsets: windowed synthesis metric diagonal per coefficient
     int T64[kAx], T264[kAx];                         // double offsets per axis
+    // double offsets: autocorrelation of each row of T, A[q][tau + j - 1] =
+    // sum_i T[q][i] T[q][i + tau], j x (2 j - 1) per axis
+    int ac64[kAx];
     int haar;      // float offset of Haar H (32 x 32, row-major, for K = 32 .. 1 packed)
     int haar64;    // double offset of Haar H
     int f32_count = 0, f64_count = 0;
@@ -112,5 +126,15 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_normalize(const StageCfg& c, const void* num, const void* den, float* out,
                             float* out2, hipStream_t s);
 hipError_t read_and_clear_range_flag(int* flag);
+
+// Correlated-noise tables (corr_noise.hip): layout size, preparation, and
+// the lookup that validates a prepared buffer for a stage and fills
+// StageCfg::corr.
+bmnd_status correlated_size(const bmnd_geometry* geom, const bmnd_params* params, size_t* bytes);
+bmnd_status correlated_prepare(const double* d_psd, const bmnd_geometry* geom,
+                               const bmnd_params* params, void* d_tables, size_t bytes,
+                               hipStream_t s);
+bmnd_status correlated_bind(const void* d_corr, const bmnd_geometry* geom,
+                            const bmnd_stage_params* sp, int stage, StageCfg& c);
 
 }  // namespace bmnd

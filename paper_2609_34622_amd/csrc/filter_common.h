@@ -27,6 +27,10 @@ struct FilterArgs {
     float* weights;
     double* numd;
     double* dend;
+    // correlated Gaussian noise: variance table D(Delta, q) over the member
+    // box of extents cbw (null otherwise)
+    const double* cdtab;
+    int cbw[kAx];
 };
 
 constexpr int ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }

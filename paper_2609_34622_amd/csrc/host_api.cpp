@@ -119,6 +119,8 @@ bmnd_status check_noise(const bmnd_noise* n)
         if (!(n->s_p > 0.0)) return fail(BMND_E_ARG, "Poisson s_p must be > 0");
     } else if (n->kind == BMND_NOISE_GAUSSIAN) {
         if (!(n->sigma >= 0.0)) return fail(BMND_E_ARG, "Gaussian sigma must be >= 0");
+    } else if (n->kind == BMND_NOISE_CORRELATED) {
+        if (!n->d_corr) return fail(BMND_E_ARG, "correlated noise needs prepared tables");
     } else {
         return fail(BMND_E_ARG, "unknown noise kind");
     }
@@ -191,6 +193,10 @@ bmnd_status make_stage(const bmnd_geometry* g, const bmnd_noise* n, const bmnd_s
     c.skappa = sp->struct_kappa;
     c.counts_integral = n && n->kind == BMND_NOISE_POISSON && n->counts_integral;
     c.wdomain = sp->weight_domain;
+    if (n && n->kind == BMND_NOISE_CORRELATED) {
+        c.k_exact = 0;  // the full covariance is exact in every plane
+        return correlated_bind(n->d_corr, g, sp, stage, c);
+    }
     return BMND_OK;
 }
 
@@ -258,6 +264,16 @@ const DevTables* device_tables(const StageCfg& c, std::string& err)
         for (double v : T) f64.push_back(v);
         t.T264[d] = int(f64.size());
         for (double v : T) f64.push_back(v * v);
+        // autocorrelation of every row of T: A[q][tau + n - 1] =
+        // sum_i T[q][i] T[q][i + tau] over the i with both inside the patch
+        t.ac64[d] = int(f64.size());
+        for (int q = 0; q < n; ++q)
+            for (int tau = 1 - n; tau < n; ++tau) {
+                double s = 0.0;
+                for (int i = std::max(0, -tau); i < n && i + tau < n; ++i)
+                    s += T[size_t(q * n + i)] * T[size_t(q * n + i + tau)];
+                f64.push_back(s);
+            }
     }
     t.haar = int(f.size());
     t.haar64 = int(f64.size());
@@ -411,6 +427,217 @@ bmnd_stage_params preset_stage(int32_t preset, int32_t ndim, int stage)
 
 }  // namespace
 
+// ------------------------------------------------ correlated Gaussian noise
+
+namespace bmnd {
+
+hipError_t launch_corr_autocov(const double* psd, const int L[kAx], const int R[kAx], double2* tw,
+                               double2* x0, double2* x1, double* cbox, hipStream_t s);
+hipError_t launch_corr_dtab(const double* cbox, const int Bc[kAx], const int R[kAx],
+                            const int j[kAx], const int bw[kAx], int P,
+                            const double* const ac[kAx], double* dtab, hipStream_t s);
+hipError_t launch_corr_bias(const double* cbox, const int Bc[kAx], const int R[kAx],
+                            const int W[kAx], int P, double gamma, double* b64, float* b32,
+                            double* bound, hipStream_t s);
+
+namespace {
+
+// Layout of a prepared table buffer (every region 256-byte aligned).
+struct CorrLayout {
+    int L[kAx], R[kAx], Bc[kAx];
+    size_t off_c = 0, off_tw = 0, off_x0 = 0, off_x1 = 0, off_bound = 0;
+    struct Stage {
+        int j[kAx], W[kAx], bw[kAx];
+        int P = 1, spatial = 0;
+        double gamma = 0.0;
+        long rows = 1, nwin = 1;
+        size_t off_d = 0, off_b64 = 0, off_b32 = 0;
+    } st[2];
+    size_t bytes = 0;
+};
+
+bmnd_status corr_layout(const bmnd_geometry* geom, const bmnd_params* params, CorrLayout& o,
+                        StageCfg cfg[2])
+{
+    if (!geom || !params) return fail(BMND_E_ARG, "NULL argument");
+    bmnd_geometry g1 = *geom;
+    g1.batch = 1;
+    bmnd_status st = make_stage(&g1, nullptr, &params->ht, BMND_STAGE_HT, cfg[0]);
+    if (st != BMND_OK) return st;
+    if ((st = make_stage(&g1, nullptr, &params->wiener, BMND_STAGE_WIENER, cfg[1])) != BMND_OK)
+        return st;
+    o = CorrLayout{};
+    for (int d = 0; d < kAx; ++d) {
+        o.L[d] = cfg[0].g.L[d];
+        int r = 0;
+        for (int k = 0; k < 2; ++k) {
+            const Geo& gg = cfg[k].g;
+            const int wm = std::min(gg.W[d], gg.L[d] - gg.j[d] + 1);  // member origins per axis
+            r = std::max(r, wm - 1 + gg.j[d] - 1);
+            o.st[k].j[d] = gg.j[d];
+            o.st[k].W[d] = gg.W[d];
+            o.st[k].bw[d] = 2 * wm - 1;
+        }
+        o.R[d] = r;
+        o.Bc[d] = 2 * r + 1;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    long nc = 1, lmax = 1;
+    for (int d = 0; d < kAx; ++d) {
+        nc *= o.Bc[d];
+        lmax = std::max<long>(lmax, o.L[d]);
+    }
+    // largest intermediate of the separable DFT (every pass but the last)
+    long scratch = 1;
+    {
+        long cur[kAx];
+        for (int d = 0; d < kAx; ++d) cur[d] = o.L[d];
+        int last = -1;
+        for (int d = 0; d < kAx && last < 0; ++d)
+            if (o.L[d] > 1) last = d;
+        for (int axis = kAx - 1; axis > last; --axis) {
+            if (o.L[axis] == 1) continue;
+            cur[axis] = o.Bc[axis];
+            long n = 1;
+            for (int d = 0; d < kAx; ++d) n *= cur[d];
+            scratch = std::max(scratch, n);
+        }
+    }
+    o.off_c = take(sizeof(double) * size_t(nc));
+    o.off_tw = take(2 * sizeof(double) * size_t(lmax));
+    o.off_x0 = take(2 * sizeof(double) * size_t(scratch));
+    o.off_x1 = take(2 * sizeof(double) * size_t(scratch));
+    o.off_bound = take(sizeof(double));
+    for (int k = 0; k < 2; ++k) {
+        CorrLayout::Stage& S = o.st[k];
+        S.P = cfg[k].g.P;
+        S.spatial = cfg[k].spatial;
+        S.gamma = cfg[k].gamma;
+        S.rows = 1;
+        S.nwin = 1;
+        for (int d = 0; d < kAx; ++d) {
+            S.rows *= S.bw[d];
+            S.nwin *= S.W[d];
+        }
+        if (double(S.rows) * S.P >= 2147483647.0 || double(S.nwin) >= 2147483647.0)
+            return fail(BMND_E_UNSUPPORTED, "correlated-noise tables too large for this window");
+        S.off_d = take(sizeof(double) * size_t(S.rows) * size_t(S.P));
+        if (k == 0) {
+            S.off_b64 = take(sizeof(double) * size_t(S.nwin));
+            S.off_b32 = take(sizeof(float) * size_t(S.nwin));
+        }
+    }
+    o.bytes = off;
+    return BMND_OK;
+}
+
+struct CorrEntry {
+    int ndim = 0;
+    int64_t shape[BMND_MAX_AXES] = {};
+    CorrLayout lay;
+};
+
+std::map<const void*, CorrEntry> g_corr;
+
+bool same_shape(const CorrEntry& e, const bmnd_geometry* g)
+{
+    if (e.ndim != g->ndim) return false;
+    for (int d = 0; d < g->ndim; ++d)
+        if (e.shape[d] != g->shape[d]) return false;
+    return true;
+}
+
+}  // namespace
+
+bmnd_status correlated_size(const bmnd_geometry* geom, const bmnd_params* params, size_t* bytes)
+{
+    if (!bytes) return fail(BMND_E_ARG, "NULL argument");
+    CorrLayout lay;
+    StageCfg cfg[2];
+    bmnd_status st = corr_layout(geom, params, lay, cfg);
+    if (st != BMND_OK) return st;
+    *bytes = lay.bytes;
+    return BMND_OK;
+}
+
+bmnd_status correlated_prepare(const double* d_psd, const bmnd_geometry* geom,
+                               const bmnd_params* params, void* d_tables, size_t bytes,
+                               hipStream_t s)
+{
+    if (!d_psd || !d_tables) return fail(BMND_E_ARG, "NULL device pointer");
+    CorrLayout lay;
+    StageCfg cfg[2];
+    bmnd_status st = corr_layout(geom, params, lay, cfg);
+    if (st != BMND_OK) return st;
+    if (bytes < lay.bytes) return fail(BMND_E_WORKSPACE, "correlated-noise table buffer too small");
+    if ((reinterpret_cast<uintptr_t>(d_tables) & 255u) != 0)
+        return fail(BMND_E_WORKSPACE, "correlated-noise table buffer must be 256-byte aligned");
+    unsigned char* base = static_cast<unsigned char*>(d_tables);
+    double* cbox = reinterpret_cast<double*>(base + lay.off_c);
+    hipError_t e = launch_corr_autocov(d_psd, lay.L, lay.R,
+                                       reinterpret_cast<double2*>(base + lay.off_tw),
+                                       reinterpret_cast<double2*>(base + lay.off_x0),
+                                       reinterpret_cast<double2*>(base + lay.off_x1), cbox, s);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        std::string err;
+        const DevTables* t = device_tables(cfg[k], err);
+        if (!t) return fail(BMND_E_NOMEM, err);
+        const double* ac[kAx];
+        for (int d = 0; d < kAx; ++d) ac[d] = t->f64 + t->ac64[d];
+        const CorrLayout::Stage& S = lay.st[k];
+        e = launch_corr_dtab(cbox, lay.Bc, lay.R, S.j, S.bw, S.P, ac,
+                             reinterpret_cast<double*>(base + S.off_d), s);
+    }
+    if (e == hipSuccess)
+        e = launch_corr_bias(cbox, lay.Bc, lay.R, lay.st[0].W, lay.st[0].P, lay.st[0].gamma,
+                             reinterpret_cast<double*>(base + lay.st[0].off_b64),
+                             reinterpret_cast<float*>(base + lay.st[0].off_b32),
+                             reinterpret_cast<double*>(base + lay.off_bound), s);
+    if (e != hipSuccess) return fail(BMND_E_HIP, std::string("HIP: ") + hipGetErrorString(e));
+    CorrEntry ent;
+    ent.ndim = geom->ndim;
+    for (int d = 0; d < geom->ndim; ++d) ent.shape[d] = geom->shape[d];
+    ent.lay = lay;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_corr[d_tables] = ent;
+    return BMND_OK;
+}
+
+bmnd_status correlated_bind(const void* d_corr, const bmnd_geometry* geom,
+                            const bmnd_stage_params* sp, int stage, StageCfg& c)
+{
+    CorrEntry ent;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_corr.find(d_corr);
+        if (it == g_corr.end())
+            return fail(BMND_E_ARG, "noise.d_corr was not written by bmnd_correlated_prepare");
+        ent = it->second;
+    }
+    const int k = stage == BMND_STAGE_HT ? 0 : 1;
+    const CorrLayout::Stage& S = ent.lay.st[k];
+    bool same = same_shape(ent, geom) && S.spatial == sp->spatial && S.gamma == sp->gamma;
+    for (int d = 0; d < kAx; ++d) same = same && S.j[d] == c.g.j[d] && S.W[d] == c.g.W[d];
+    if (!same)
+        return fail(BMND_E_ARG, "noise.d_corr was prepared for another shape or stage parameters");
+    const unsigned char* base = static_cast<const unsigned char*>(d_corr);
+    c.corr.dtab = reinterpret_cast<const double*>(base + S.off_d);
+    if (k == 0) {
+        c.corr.bias = reinterpret_cast<const double*>(base + S.off_b64);
+        c.corr.bias32 = reinterpret_cast<const float*>(base + S.off_b32);
+        c.corr.bias_bound = reinterpret_cast<const double*>(base + ent.lay.off_bound);
+    }
+    for (int d = 0; d < kAx; ++d) c.corr.bw[d] = S.bw[d];
+    return BMND_OK;
+}
+
+}  // namespace bmnd
+
 extern "C" {
 
 const char* bmnd_last_error(void) { return t_error.c_str(); }
@@ -472,6 +699,22 @@ bmnd_status bmnd_count_moments(int32_t metric, int32_t nmax, double* mu, double*
     std::copy(m.begin(), m.end(), mu);
     std::copy(w.begin(), w.end(), v);
     return BMND_OK;
+}
+
+bmnd_status bmnd_correlated_size(const bmnd_geometry* geom, const bmnd_params* params,
+                                 size_t* bytes)
+{
+    set_error("");
+    return correlated_size(geom, params, bytes);
+}
+
+bmnd_status bmnd_correlated_prepare(const double* d_psd, const bmnd_geometry* geom,
+                                    const bmnd_params* params, void* d_tables, size_t bytes,
+                                    void* stream)
+{
+    set_error("");
+    return correlated_prepare(d_psd, geom, params, d_tables, bytes,
+                              static_cast<hipStream_t>(stream));
 }
 
 bmnd_status bmnd_haar_matrix(int32_t K, double* H)

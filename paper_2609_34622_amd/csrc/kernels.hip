@@ -16,6 +16,7 @@
 #include "bmnd_internal.h"
 #include "filter_common.h"
 #include "exact_planes.h"
+#include "corr_noise.h"
 #include "match_common.h"
 
 namespace bmnd {
@@ -95,6 +96,19 @@ struct ScoreT { using type = float; };
 template <>
 struct ScoreT<kCount> { using type = int; };
 
+// Window-offset index of candidate c of reference r (C-order over the W_d
+// offsets, o_d = c_d - r_d + floor(W_d / 2)): the row of the correlated-noise
+// bias table.
+__device__ inline int window_offset(const Geo& g, int r, int c)
+{
+    int o = 0, st = 1;
+    for (int d = kAx - 1; d >= 0; --d) {
+        o += ((c / g.st[d]) % g.L[d] - (r / g.st[d]) % g.L[d] + g.W[d] / 2) * st;
+        st *= g.W[d];
+    }
+    return o;
+}
+
 template <int MODE>
 __device__ __forceinline__ typename ScoreT<MODE>::type score_of(const MatchArgs& a,
                                                                  const float* src,
@@ -131,7 +145,8 @@ __device__ __forceinline__ typename ScoreT<MODE>::type score_of(const MatchArgs&
                     }
                 }
         if constexpr (MODE == kPoissonF) return __builtin_fmaf(-a.gamma_sp, b, ssd);
-        if constexpr (MODE == kGauss) return ssd - a.bias;
+        if constexpr (MODE == kGauss)
+            return ssd - (a.bias_t ? a.bias_t[window_offset(g, r, c)] : a.bias);
         return ssd;
     }
 }
@@ -156,7 +171,8 @@ __device__ inline double score64_of(const MatchArgs& a, const float* src, int r,
                 }
             }
     if constexpr (MODE == kPoissonF) return __dsub_rn(ssd, __dmul_rn(a.gamma_sp_d, b));
-    if constexpr (MODE == kGauss) return __dsub_rn(ssd, a.bias_d);
+    if constexpr (MODE == kGauss)
+        return __dsub_rn(ssd, a.bias_td ? a.bias_td[window_offset(g, r, c)] : a.bias_d);
     return ssd;
 }
 
@@ -167,14 +183,6 @@ __device__ __forceinline__ int max_score<int>() { return INT_MAX; }
 template <>
 __device__ __forceinline__ float max_score<float>() { return FLT_MAX; }
 
-__device__ __forceinline__ int to_bits(int v) { return v; }
-__device__ __forceinline__ int to_bits(float v) { return __float_as_int(v); }
-template <typename S>
-__device__ __forceinline__ S from_bits(int v);
-template <>
-__device__ __forceinline__ int from_bits<int>(int v) { return v; }
-template <>
-__device__ __forceinline__ float from_bits<float>(int v) { return __int_as_float(v); }
 
 __device__ __forceinline__ int smin(int a, int b) { return min(a, b); }
 __device__ __forceinline__ int smax(int a, int b) { return max(a, b); }
@@ -219,7 +227,7 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
     // the float-mode tie band: near the K-th value q ~ p, so the correction
     // is at most about twice the reference's
     float bmag = 0.f;
-    if constexpr (MODE == kGauss) bmag = fabsf(a.bias);
+    if constexpr (MODE == kGauss) bmag = a.bias_t ? float(*a.bias_bound) : fabsf(a.bias);
     if constexpr (MODE == kPoissonF) {
         float sp = 0.f;
         for (int i0 = 0; i0 < g.j[0]; ++i0)
@@ -399,7 +407,7 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
 struct FilterLds {
     int kp, p, gm;
     size_t off_red, off_A, off_B, off_V, off_T, off_tab, off_H, off_H2, off_win, off_r, off_w,
-        off_off, off_org, off_misc, bytes;
+        off_off, off_org, off_misc, off_key, off_pix, bytes;
     __host__ __device__ FilterLds(const Geo& g, int gmax)
     {
         p = g.P;
@@ -421,6 +429,9 @@ struct FilterLds {
         off_off = o; o += sizeof(int) * g.P;
         off_org = o; o += sizeof(int) * gmax;
         off_misc = o; o += sizeof(int) * 8;
+        // correlated noise: member keys and the table rows of member pairs
+        off_key = o; o += sizeof(unsigned) * gmax;
+        off_pix = o; o += sizeof(int) * size_t(corr_npairs(gmax));
         bytes = (o + 15) & ~size_t(15);
     }
 };
@@ -536,8 +547,11 @@ __device__ bool rescue_keep(const FilterArgs& a, const float* yb, const float* m
         double mv;
         if (a.noise == BMND_NOISE_POISSON) mv = a.s_p64 * fmax(double(mvsrc[u]), 0.0);
         else mv = a.sigma2_64;
-        if (!exact) sv += w * w * mv;
+        if (!exact && !a.cdtab) sv += w * w * mv;
     }
+    if (a.cdtab)
+        sv = corr_var_part(a, org, K, l, qidx, [&](int r, int j) { return H[r * K + j]; },
+                           threadIdx.x, kFilterThreads);
     if constexpr (EXACT) {
         if (exact) sv = exact_partial(a, mvsrc, org, K, l, qidx, threadIdx.x, kFilterThreads);
     }
@@ -652,10 +666,22 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
             for (int e = threadIdx.x; e < n; e += kFilterThreads) A[e] = Yc[e];
             __syncthreads();
         }
-        float* Vc = apply_separable(Vb, Tb, gs, H2, spT2);
-        if (Vc != Vb) {
-            for (int e = threadIdx.x; e < n; e += kFilterThreads) Vb[e] = Vc[e];
+        if (a.cdtab) {
+            // correlated noise: sigma^2 from the variance table
+            unsigned* keys = reinterpret_cast<unsigned*>(lds + L.off_key);
+            int* pix = reinterpret_cast<int*>(lds + L.off_pix);
+            for (int j = threadIdx.x; j < K; j += kFilterThreads) keys[j] = corr_member_key(a, org[j]);
             __syncthreads();
+            corr_pair_rows(a, keys, K, pix, threadIdx.x, kFilterThreads);
+            __syncthreads();
+            corr_group_variances<kMaxGroup>(a, pix, K, Vb, threadIdx.x, kFilterThreads);
+            __syncthreads();
+        } else {
+            float* Vc = apply_separable(Vb, Tb, gs, H2, spT2);
+            if (Vc != Vb) {
+                for (int e = threadIdx.x; e < n; e += kFilterThreads) Vb[e] = Vc[e];
+                __syncthreads();
+            }
         }
         // exact shared-source variances of the leading planes
         if constexpr (EXACT) {
@@ -978,12 +1004,19 @@ hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* ps
         a.tau_d = c.tau;
     } else {
         mode = kGauss;
-        a.bias_d = c.gamma * 2.0 * c.g.P * c.sigma * c.sigma;
-        a.bias = float(a.bias_d);
+        if (c.noise == BMND_NOISE_CORRELATED) {
+            // the bias depends on the candidate's window offset
+            a.bias_t = c.corr.bias32;
+            a.bias_td = c.corr.bias;
+            a.bias_bound = c.corr.bias_bound;
+        } else {
+            a.bias_d = c.gamma * 2.0 * c.g.P * c.sigma * c.sigma;
+            a.bias = float(a.bias_d);
+        }
         a.tau_f = float(c.tau);
         a.tau_d = c.tau;
     }
-    if (match_1d_supported(c.g, mode))
+    if (!a.bias_t && match_1d_supported(c.g, mode))
         return launch_match_1d(a, mode, c.step_last, count_limit(c), s);
     if (match_nd_supported(c.g)) return launch_match_nd(a, mode, count_limit(c), s);
     if (mode == kCount) {
@@ -1021,6 +1054,11 @@ static FilterArgs filter_args(const StageCfg& c, const DevTables& t, int out_mod
     a.gmax = c.gmax;
     a.out_mode = out_mode;
     a.t = t;
+    if (c.noise == BMND_NOISE_CORRELATED) {
+        a.cdtab = c.corr.dtab;
+        for (int d = 0; d < kAx; ++d) a.cbw[d] = c.corr.bw[d];
+        a.kex = 0;
+    }
     return a;
 }
 
@@ -1056,7 +1094,8 @@ hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, co
     a.numd = static_cast<double*>(num);
     a.dend = static_cast<double*>(den);
     const long groups = long(c.g.batch) * n_refs;
-    if (filter_1d_supported(c.g, c.gmax, false, c.k_exact)) return launch_filter_1d(a, c.step_last, s);
+    if (!a.cdtab && filter_1d_supported(c.g, c.gmax, false, c.k_exact))
+        return launch_filter_1d(a, c.step_last, s);
     if (cube_filter_supported(c.g, c.gmax)) return launch_filter_cube(a, c.step_last, s);
     return launch_generic_filter(a, FilterLds(c.g, c.gmax).bytes, groups, s);
 }

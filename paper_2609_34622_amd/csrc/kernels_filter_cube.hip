@@ -17,6 +17,7 @@
 #include "bmnd_internal.h"
 #include "filter_common.h"
 #include "exact_planes.h"
+#include "corr_noise.h"
 
 namespace bmnd {
 
@@ -252,10 +253,14 @@ __device__ __forceinline__ double haar64(int K, int l, int j)
 template <int KP>
 constexpr int waves_for() { return KP <= 512 ? 4 : (KP <= 1024 ? 2 : 1); }
 
-template <int D, int J, int GM, bool EXACT>
+// VM: variance model, 0 diagonal, 1 with exact shared-source planes,
+// 2 stationary correlated Gaussian noise
+template <int D, int J, int GM, int VM>
 __global__ __launch_bounds__(kWave * waves_for<GM * ipow_c(J, D)>())
 void k_filter_cube(FilterArgs a, int chunk_refs)
 {
+    constexpr bool EXACT = VM == 1;
+    constexpr bool CORR = VM == 2;
     constexpr int P = ipow_c(J, D);
     constexpr int KP = GM * P;
     constexpr int NW = waves_for<KP>();
@@ -269,6 +274,7 @@ void k_filter_cube(FilterArgs a, int chunk_refs)
     __shared__ float rpl_[NW][GM];
     __shared__ float wj_[NW][GM];
     __shared__ int nres_[NW];
+    __shared__ unsigned keys_[CORR ? NW : 1][CORR ? GM : 1];
 
     const Geo& g = a.g;
     const int wave = threadIdx.x / kWave;
@@ -348,10 +354,12 @@ void k_filter_cube(FilterArgs a, int chunk_refs)
                 for (int e = lane; e < n; e += kWave) A[e] = Y[e];
                 wsync();
             }
-            float* Vr = spatial<D, J, P>(Vb, Tb, T2m, K);
-            if (Vr != Vb) {
-                for (int e = lane; e < n; e += kWave) Vb[e] = Vr[e];
-                wsync();
+            if constexpr (!CORR) {
+                float* Vr = spatial<D, J, P>(Vb, Tb, T2m, K);
+                if (Vr != Vb) {
+                    for (int e = lane; e < n; e += kWave) Vb[e] = Vr[e];
+                    wsync();
+                }
             }
             if (wiener) {
                 float* Gr = spatial<D, J, P>(Bb, Tb, Tm, K);
@@ -361,6 +369,17 @@ void k_filter_cube(FilterArgs a, int chunk_refs)
                 }
             }
             haar_arrays<GM, P>(A, Vb, Bb, wiener ? 3 : 2, false, K);
+            if constexpr (CORR) {
+                // correlated noise: sigma^2 from the variance table; the pair
+                // rows live in Tb until the shrinkage reuses it
+                int* pix = reinterpret_cast<int*>(Tb);
+                if (lane < K) keys_[wave][lane] = corr_member_key(a, org[lane]);
+                wsync();
+                corr_pair_rows(a, keys_[wave], K, pix, lane, kWave);
+                wsync();
+                corr_group_variances<GM>(a, pix, K, Vb, lane, kWave);
+                wsync();
+            }
             // exact shared-source variances of the leading planes
             const int kex = EXACT ? min(a.kex, K) : 0;
             if constexpr (EXACT) {
@@ -442,6 +461,10 @@ void k_filter_cube(FilterArgs a, int chunk_refs)
                                               : a.sigma2_64;
                         sv += w * w * mv;
                     }
+                    if constexpr (CORR)
+                        sv = corr_var_part(a, org, K, l, e - l * P,
+                                           [&](int r, int j) { return haar64(K, r, j); }, lane,
+                                           kWave);
                     if constexpr (EXACT) {
                         if (l < kex) sv = exact_partial(a, yb, org, K, l, e - l * P, lane, kWave);
                     }
@@ -552,12 +575,16 @@ hipError_t launch_cube_gm(const FilterArgs& a, int step_last, hipStream_t s)
     const int nchunk = (a.n_refs + chunk - 1) / chunk;
     const dim3 grid(unsigned(long(nchunk) * g.batch));
 #define BMND_CUBE_LAUNCH(GMV)                                                              \
-    if (a.kex > 0)                                                                          \
-        hipLaunchKernelGGL((k_filter_cube<D, J, GMV, true>),                                \
+    if (a.cdtab)                                                                            \
+        hipLaunchKernelGGL((k_filter_cube<D, J, GMV, 2>),                                   \
+                           dim3(grid), dim3(kWave * waves_for<GMV * ipow_c(J, D)>()), 0, s, a, \
+                           chunk);                                                          \
+    else if (a.kex > 0)                                                                     \
+        hipLaunchKernelGGL((k_filter_cube<D, J, GMV, 1>),                                   \
                            dim3(grid), dim3(kWave * waves_for<GMV * ipow_c(J, D)>()), 0, s, a, \
                            chunk);                                                          \
     else                                                                                    \
-    hipLaunchKernelGGL((k_filter_cube<D, J, GMV, false>),                                   \
+    hipLaunchKernelGGL((k_filter_cube<D, J, GMV, 0>),                                       \
                        dim3(grid), dim3(kWave * waves_for<GMV * ipow_c(J, D)>()), 0, s, a, \
                        chunk)
     switch (a.gmax) {

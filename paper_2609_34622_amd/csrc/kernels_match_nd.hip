@@ -205,8 +205,29 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
         }
     }
 
+    // window-offset index of a candidate (correlated noise: the bias of the
+    // displacement from the reference), C-order over the W_d offsets
+    int wst[kAx];
+    {
+        int st = 1;
+#pragma unroll
+        for (int d = kAx - 1; d >= 0; --d) {
+            wst[d] = st;
+            st *= g.W[d];
+        }
+    }
+    auto woff = [&](int ci) {
+        int rem = ci, o = 0;
+#pragma unroll
+        for (int d = kAx - 1; d >= 0; --d) {
+            o += (lo[d] + rem % n[d] - rc[d] + g.W[d] / 2) * wst[d];
+            rem /= n[d];
+        }
+        return o;
+    };
+
     // ---- scores of every candidate
-    const float bmag = MODE == kGauss ? fabsf(a.bias) : 0.f;
+    const float bmag = MODE == kGauss ? (a.bias_t ? float(*a.bias_bound) : fabsf(a.bias)) : 0.f;
     const int n3 = n[kAx - 1];
     const int rpr = (n3 + kRB - 1) / kRB;  // runs per line
     const int nruns = (ncand / n3) * rpr;
@@ -221,6 +242,16 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
                 cb += (rem % n[d]) * stride;
                 rem /= n[d];
                 stride *= R[d];
+            }
+        }
+        // window offset of the run's first candidate
+        int wb = (lo[kAx - 1] + c3 - rc[kAx - 1] + g.W[kAx - 1] / 2);
+        {
+            int rem2 = line;
+#pragma unroll
+            for (int d = kAx - 2; d >= 0; --d) {
+                wb += (lo[d] + rem2 % n[d] - rc[d] + g.W[d] / 2) * wst[d];
+                rem2 /= n[d];
             }
         }
         S acc[kRB], sq[kRB], bq[kRB];
@@ -251,7 +282,7 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
             if (c3 + u < n3) {
                 S x = acc[u];
                 if constexpr (MODE == kCount) x -= a.gamma_i * (sr + sq[u]);
-                if constexpr (MODE == kGauss) x -= a.bias;
+                if constexpr (MODE == kGauss) x -= a.bias_t ? a.bias_t[wb + u] : a.bias;
                 if constexpr (MODE == kPoissonF) x = __builtin_fmaf(-a.gamma_sp, bq[u], x);
                 if constexpr (kF) x = x == x ? x : bigv<S>();
                 if (ci == rci) x = bigv<S>();
@@ -312,7 +343,7 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
                             s = __dadd_rn(s, __dmul_rn(df, df));
                             if constexpr (MODE == kPoissonF) bb = __dadd_rn(bb, fmax(__dadd_rn(pv, qv), 0.0));
                         }
-                    if constexpr (MODE == kGauss) s = __dsub_rn(s, a.bias_d);
+                    if constexpr (MODE == kGauss) s = __dsub_rn(s, a.bias_td ? a.bias_td[woff(ci)] : a.bias_d);
                     if constexpr (MODE == kPoissonF) s = __dsub_rn(s, __dmul_rn(a.gamma_sp_d, bb));
                     acc2 += s < a.tau_d;
                 } else {
@@ -466,7 +497,7 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
                             s = __dadd_rn(s, __dmul_rn(df, df));
                             if constexpr (MODE == kPoissonF) bb = __dadd_rn(bb, fmax(__dadd_rn(pv, qv), 0.0));
                         }
-                    if constexpr (MODE == kGauss) s = __dsub_rn(s, a.bias_d);
+                    if constexpr (MODE == kGauss) s = __dsub_rn(s, a.bias_td ? a.bias_td[woff(ci)] : a.bias_d);
                     if constexpr (MODE == kPoissonF) s = __dsub_rn(s, __dmul_rn(a.gamma_sp_d, bb));
                     if (!(s == s)) continue;
                     const int slot = atomicAdd(&misc[3], 1);

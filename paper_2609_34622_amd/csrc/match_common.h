@@ -38,6 +38,12 @@ struct MatchArgs {
     const double* mu_d;
     const double* v_d;
     int nmom;            // largest tabulated pooled count
+    // correlated Gaussian noise (HT, kGauss): the bias of every window
+    // offset (C-order over the W_d offsets, o_d = candidate - reference +
+    // floor(W_d / 2)) in FP32 and FP64, and a bound on its magnitude
+    const float* bias_t;
+    const double* bias_td;
+    const double* bias_bound;
 };
 
 // Float-mode scores within this relative band of the K-th value or of tau

@@ -191,3 +191,48 @@ def phantom_3d(seed: int = 4000, shape=(256, 256, 128)) -> Sample:
         sub[inside] = act
     lam_pk = float(lam.max())
     return _observe(rng, lam, lam_pk)
+
+
+@dataclass
+class GaussianSample:
+    y: np.ndarray        # float32 observation x + n
+    x: np.ndarray        # float32 clean signal
+    psd: np.ndarray      # float64 power spectral density of n on the array's DFT grid
+    sigma: float         # marginal standard deviation of n
+
+
+def correlated_gaussian(shape, seed: int = 8000, sigma: float = 0.1, corr_len=1.0) -> GaussianSample:
+    """Clean signal (the 1-D ECG beats, the 2-D disc/rectangle scene, the
+    3-D ellipsoid phantom, scaled to peak 1) plus stationary correlated
+    Gaussian noise n = h (*) w: white unit noise w filtered circularly by a
+    separable Gaussian kernel h of standard deviation ``corr_len`` samples
+    per axis (truncated at 3 corr_len), scaled so that n has standard
+    deviation ``sigma``.  Its spectral density samples are |Omega| |DFT(h)|^2
+    (unnormalised DFT; a white field of variance s^2 has |Omega| s^2)."""
+    shape = tuple(int(v) for v in shape)
+    if len(shape) == 1:
+        x = ecg_batch(n_signals=1, length=shape[0], seed=seed).x[0]
+    elif len(shape) == 2:
+        x = image_2d_small(seed, size=max(shape)).x[: shape[0], : shape[1]]
+    else:
+        x = phantom_3d(seed, shape=shape).x
+    x = np.asarray(x, np.float64)
+    x = x / max(float(x.max()), 1e-30)
+    cl = np.broadcast_to(np.asarray(corr_len, np.float64), (len(shape),))
+    h = np.ones((1,) * len(shape))
+    for d, n in enumerate(shape):
+        r = int(np.ceil(3 * cl[d])) if cl[d] > 0 else 0
+        t = np.arange(-r, r + 1, dtype=np.float64)
+        k = np.exp(-0.5 * (t / cl[d]) ** 2) if cl[d] > 0 else np.ones(1)
+        kk = np.zeros(n)
+        for v, tt in zip(k, t):
+            kk[int(tt) % n] += v
+        h = h * kk.reshape((1,) * d + (n,) + (1,) * (len(shape) - d - 1))
+    h *= sigma / np.sqrt((h ** 2).sum())
+    Hf = np.fft.fftn(h)
+    rng = _rng(seed + 1)
+    w = rng.normal(0.0, 1.0, shape)
+    n = np.real(np.fft.ifftn(np.fft.fftn(w) * Hf))
+    psd = float(np.prod(shape)) * np.abs(Hf) ** 2
+    return GaussianSample(y=(x + n).astype(np.float32), x=x.astype(np.float32),
+                          psd=np.ascontiguousarray(psd), sigma=float(sigma))

@@ -661,3 +661,24 @@ def test_filter_1d_windowed_weights(stage):
         scale = max(np.abs(po[g, :K]).max(), 1e-30)
         assert np.abs(pg[0, g, :K] - po[g, :K]).max() <= REL_PATCH * scale, g
         assert np.allclose(wg[0, g, :K], wo[g, :K], rtol=1e-5), g
+
+
+@pytest.mark.parametrize("model", ["classic", "risk"])
+def test_windowed_weights_generic_filter(model):
+    """Windowed synthesized-domain weights on the generic filter (a 6x5
+    patch, which neither the cube nor the 1-D kernel takes), end to end."""
+    _say(f"windowed generic filter, {model}")
+    shape, patch, step, search = (40, 36), (6, 5), (2, 2), (11, 11)
+    s = synth.image_2d_small(1007, size=40)
+    y = np.ascontiguousarray(s.y[:, :36])
+    p = params_for(shape, patch, step, search)
+    ht, wie = oracle_stages(shape, patch, step, search, s.s_p)
+    p.ht.weight_domain = p.wiener.weight_domain = B.WDOMAIN_WINDOWED
+    ht.weight_domain = wie.weight_domain = "windowed"
+    p.wiener.weight_model = B.WEIGHT[model]
+    wie.weight_model = model
+    out, pilot = gpu_denoise(dev(y), B.geometry(shape), B.poisson(s.s_p), p)
+    pil_o = O.run_stage(ht, O.STAGE_HT, y)
+    assert rel_err(pilot, pil_o) < REL_OUT
+    out_r = O.run_stage(wie, O.STAGE_WIENER, y, pilot.astype(np.float64))
+    assert rel_err(out, out_r) < REL_OUT

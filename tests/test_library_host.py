@@ -175,3 +175,28 @@ def test_library_moment_tables_equal_oracle(metric):
         assert abs(v[n] - vo) <= 1e-11 * max(1.0, abs(vo)), n
     assert _status(B.bmnd_count_moments, B.METRIC_SSD, 10) == B.E_ARG
     assert _status(B.bmnd_count_moments, code, B.MOMENT_MAX_COUNT + 1) == B.E_ARG
+
+
+def test_correlated_noise_validation():
+    """Table sizes of the correlated model and the host-side checks of a
+    noise model's table pointer (no device work)."""
+    g = B.geometry((64, 48))
+    p = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    n1 = B.bmnd_correlated_size(g, p)
+    assert n1 > 0 and n1 % 256 == 0
+    # batch does not change the tables; a wider window needs more
+    assert B.bmnd_correlated_size(B.geometry((64, 48), batch=3), p) == n1
+    wide = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    for sp in (wide.ht, wide.wiener):
+        B.set_axes(sp, search=(31, 31))
+    assert B.bmnd_correlated_size(g, wide) > n1
+    # a pointer that no prepare call wrote is refused before any launch
+    fake = B.Noise()
+    fake.kind = B.NOISE_CORRELATED
+    fake.d_corr = 4096
+    assert _status(B.bmnd_workspace_size, g, fake, p) == B.E_ARG
+    fake.d_corr = None
+    assert _status(B.bmnd_workspace_size, g, fake, p) == B.E_ARG
+    bad = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    bad.ht.group_max = 3
+    assert _status(B.bmnd_correlated_size, g, bad) == B.E_ARG
