@@ -83,8 +83,8 @@ def candidates_per_ref(shape, patch, search, refs):
 
 # kernel name fragments of the library's kernels in rocprofv3 output (a
 # stage may run two kernels: byte-count matching and its record fallback)
-KERNEL_SYMBOLS = {"filter_ht": [("k_filter_1d", "<0>")],
-                  "filter_wiener": [("k_filter_1d", "<2>")],
+KERNEL_SYMBOLS = {"filter_ht": [("k_filter_1d", "<0,"), ("k_filter_1d", "<1,")],
+                  "filter_wiener": [("k_filter_1d", "<2,")],
                   "match_ht": [("k_match_1d_u8", ""), ("k_match_1d_rec", ""), ("k_match_1d_f", "<2,"),
                                ("k_match_nd", "<0,")],
                   "match_wiener": [("k_match_1d_f", "<3,"), ("k_match_nd", "<3,")]}
