@@ -232,7 +232,7 @@ def bench_serving(B, torch, n: int = 60) -> dict:
     rate = 0.7 * cap["requests"] / cap["makespan_s"]
     trace = serving.make_trace(n, rate, 7001, **kw)
     budget = 32 << 30
-    srv = serving.Server(budget_bytes=budget, slots=4)
+    srv = serving.Server(budget_bytes=budget, slots=4)   # in-flight work cap: "auto"
     cont = srv.run(trace)
     for r in trace:
         r.out = None
@@ -240,6 +240,8 @@ def bench_serving(B, torch, n: int = 60) -> dict:
     return {"requests": n, "arrival_rate_per_s": round(rate, 3), "hbm_budget_gib": budget >> 30,
             "trace": "seeded Poisson arrivals; 40% 1-D (8k-128k), 40% 2-D (128^2-512^2), "
                      "20% 3-D (32^3-64^3, mass conservation); peaks log-uniform [2, 100]",
+            "admission": "4 streams, HBM budget, in-flight work at most the largest request "
+                         "seen so far",
             "continuous": {k: round(v, 3) for k, v in cont.items()},
             "plain_fifo": {k: round(v, 3) for k, v in fifo.items()}}
 

@@ -53,6 +53,25 @@ def request_bytes(req: Request) -> int:
     return req.nbytes
 
 
+def request_work(req: Request) -> float:
+    """Relative cost of a request: reference origins x patch samples x
+    (clipped window candidates + a filtering term per group member), the
+    scale of both stages' matching and filtering."""
+    sp = req.params.ht
+    refs = cand = P = 1.0
+    for d, L in enumerate(req.y.shape):
+        refs *= -(-L // max(sp.step[d], 1))
+        cand *= min(sp.search[d], L - sp.patch[d] + 1)
+        P *= sp.patch[d]
+    return refs * P * (cand + 4.0 * (sp.group_max + req.params.wiener.group_max))
+
+
+def admits(in_flight: float, work: float, cap: Optional[float], busy: bool) -> bool:
+    """Admission rule of the work cap: an idle device takes any request; a
+    busy one only while the work in flight stays within the cap."""
+    return not busy or cap is None or in_flight + work <= cap
+
+
 def default_params(ndim: int, mc: bool) -> Params:
     """Per-dimensionality parameters of the mixed workload: 1-D patch 32,
     step 4, search 256, group 16/16; 2-D 8x8, step 3, search 39x39, group
@@ -120,18 +139,26 @@ class _Slot:
 
 class Server:
     """Continuous batching over `slots` concurrent streams within an HBM
-    budget of `budget_bytes`."""
+    budget of `budget_bytes`.  A request is admitted only while the work in
+    flight (``request_work``) stays within `work_cap`, or when nothing runs:
+    small requests still overlap, but two large ones do not stretch each
+    other's latency by sharing the device.  The default cap ("auto") is the
+    largest single request seen so far; None admits whatever fits."""
 
     def __init__(self, budget_bytes: int, slots: int = 4,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter,
+                 work_cap="auto"):
         import torch
 
         self.torch = torch
         self.budget = int(budget_bytes)
         self.slots = [_Slot(torch) for _ in range(slots)]
         self.clock = clock
+        self.work_cap = work_cap
         self.in_use = 0
         self.peak_in_use = 0
+        self.work = 0.0
+        self.seen_max = 0.0
 
     def _admit(self, slot: _Slot, req: Request, now: float):
         torch = self.torch
@@ -150,12 +177,16 @@ class Server:
         req.admitted = now
         self.in_use += nbytes
         self.peak_in_use = max(self.peak_in_use, self.in_use)
+        self.work += request_work(req)
 
     def _retire(self, slot: _Slot, now: float):
         req = slot.req
         req.out = slot.host_out.numpy().copy()
         req.done = now
         self.in_use -= slot.bytes
+        self.work = max(self.work - request_work(req), 0.0)
+        if all(s.req is None or s is slot for s in self.slots):
+            self.work = 0.0
         slot.req, slot.bufs, slot.host_out, slot.bytes = None, None, None, 0
 
     def run(self, trace: Sequence[Request]) -> dict:
@@ -179,6 +210,12 @@ class Server:
             while pending and pending[0].arrival <= now:
                 free = [s for s in self.slots if s.req is None]
                 if not free or self.in_use + request_bytes(pending[0]) > self.budget:
+                    break
+                busy = len(free) < len(self.slots)
+                w = request_work(pending[0])
+                self.seen_max = max(self.seen_max, w)
+                cap = self.seen_max if self.work_cap == "auto" else self.work_cap
+                if not admits(self.work, w, cap, busy):
                     break
                 self._admit(free[0], pending.popleft(), now)
                 progressed = True

@@ -200,3 +200,23 @@ def test_correlated_noise_validation():
     bad = B.bmnd_params_default(B.PRESET_PLAIN, 2)
     bad.ht.group_max = 3
     assert _status(B.bmnd_correlated_size, g, bad) == B.E_ARG
+
+
+def test_serving_work_cap_rule():
+    """The serving admission rule: the work estimate grows with the array
+    and the window, and a busy device admits only within the cap."""
+    from paper_2609_34622_amd import serving
+
+    def req(shape, ndim):
+        return serving.Request(0, 0.0, np.zeros(shape, np.float32), 0.1,
+                               serving.default_params(ndim, False))
+
+    small, big = req((64, 64), 2), req((512, 512), 2)
+    assert serving.request_work(big) > 50 * serving.request_work(small)
+    one_d = req((65536,), 1)
+    assert serving.request_work(one_d) > 0
+    w = serving.request_work(big)
+    assert serving.admits(0.0, w, w / 10, busy=False)      # idle: always
+    assert not serving.admits(w, w, w, busy=True)         # two large ones: no
+    assert serving.admits(w / 4, w / 4, w, busy=True)     # small beside small: yes
+    assert serving.admits(w, w, None, busy=True)          # no cap
