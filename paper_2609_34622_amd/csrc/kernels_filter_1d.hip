@@ -95,6 +95,8 @@ __device__ __forceinline__ double haar_d(int lk, int l, int j)
 // hardware square root and reciprocal (about 1 ulp)
 __device__ __forceinline__ float fsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ __forceinline__ float frcp(float v) { return __builtin_amdgcn_rcpf(v); }
+// [v]_+ in one instruction (v_med3_f32; +inf becomes the largest float)
+__device__ __forceinline__ float relu(float v) { return __builtin_amdgcn_fmed3f(v, 0.f, 3.40282347e38f); }
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v)
@@ -244,7 +246,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         const int off = m == 2 ? a.t.U[kAx - 1] : a.t.T[kAx - 1];
         float v = a.t.f32[off + (16 * c + (ln & 15)) * kJ + 8 * (ln >> 4) + k];
         if (m == 1) v = v * v;
-        const float t = v * osc[m];
+        const float t = v * (m == 0 ? osc[0] : (m == 1 ? osc[1] : osc[2]));
         const _Float16 h = (_Float16)t;
         ops[opnd_index(m, 0, c, ln) + k] = h;
         ops[opnd_index(m, 1, c, ln) + k] = (_Float16)(t - (float)h);
@@ -363,7 +365,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         const float mp = poisson ? a.s_p * scm : 0.f, mg = poisson ? 0.f : a.sigma2 * scm;
 #pragma unroll
         for (int s = 0; s < 8; ++s)
-            mv[s] = __builtin_fmaf(fmaxf(wiener ? pv[s] : x[s], 0.f), mp, av ? mg : 0.f);
+            mv[s] = __builtin_fmaf(relu(wiener ? pv[s] : x[s]), mp, av ? mg : 0.f);
         split8(mv, 1.f, mh, ml);
         // ---- analysis: spatial rows 16c + m16 of every member, then Haar
         // over the members with A[row m16][depth (lg, s)] = H[m16][4lg + s];
@@ -424,13 +426,12 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             // shrinkage; coefficient (c, r), bit 4c + r: Haar row 4lg + r,
             // spatial row 16c + m16
             float C[2][4], at_[2][4], v_[2][4], sh_[2][4];
-            unsigned keep = 0, near = 0;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     const float Yv = F.Y[c][r];
-                    const float v = fmaxf(F.V[c][r], 0.f);
+                    const float v = relu(F.V[c][r]);
                     float at = 0.f, Cv = 0.f, shat = 0.f;
                     if constexpr (SH == BMND_SHRINK_SOFT) {
                         const float m = fmaxf(fabsf(Yv) - a.lambda * fsqrt(v), 0.f);
@@ -438,7 +439,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                         at = Yv != 0.f ? m * frcp(fabsf(Yv)) : 0.f;
                     } else if constexpr (SH == BMND_SHRINK_WIENER) {
                         const float gam = F.G[c][r];
-                        shat = fmaxf(gam * gam - a.power_a * v, 0.f);
+                        shat = relu(gam * gam - a.power_a * v);
                         const float den = shat + a.s_v * v;
                         at = den > 0.f ? shat * frcp(den) : 0.f;
                         Cv = at * Yv;
@@ -449,25 +450,30 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                     sh_[c][r] = shat;
                 }
             }
-            float gn = 0.f;
+            // hard threshold on squares: |Y| > lambda sqrt(v) iff Y^2 >
+            // lambda^2 v.  The FP32 error band: transform round-off is bounded
+            // by the row norm times the group norm (e), so a decision can be
+            // wrong only if ||Y| - thr| <= d = 1e-5 (e + thr); then thr <=
+            // |Y| + d, d <= d' = 1.0001e-5 (e + |Y|), and |Y^2 - thr^2| =
+            // ||Y| - thr| (|Y| + thr) <= d' (2 |Y| + d'), the test below.
+            const float l2 = a.lambda * a.lambda;
+            bool anynear = false;
             if constexpr (SH == BMND_SHRINK_HARD) {
-                gn = F.gn;
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    // FP32 error band of the decision (transform and square
-                    // root round-off are bounded by the row norm times the
-                    // group norm, and by the threshold)
-                    const float e = rq[c] * gn;
+                    const float e = rq[c] * F.gn;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const float Yv = F.Y[c][r];
                         const float v = v_[c][r];
-                        const float thr = a.lambda * fsqrt(v);
+                        const float q = __builtin_fmaf(Yv, Yv, -l2 * v);
                         const bool lv = 4 * lg + r < K;
-                        const bool kp = lv & (fabsf(Yv) > thr);
-                        const bool nr = lv & (v > 0.f) & (fabsf(fabsf(Yv) - thr) <= 1e-5f * (e + thr));
-                        keep |= unsigned(kp) << (4 * c + r);
-                        near |= unsigned(nr) << (4 * c + r);
+                        const bool kp = lv & (q > 0.f);
+                        const float ay = fabsf(Yv);
+                        const float d = 1.0001e-5f * (e + ay);
+                        anynear |= lv & (v > 0.f) & (fabsf(q) <= d * (2.f * ay + d));
+                        at_[c][r] = kp ? 1.f : 0.f;
+                        C[c][r] = kp ? Yv : 0.f;
                     }
                 }
             }
@@ -475,7 +481,24 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             if constexpr (SH == BMND_SHRINK_HARD) {
                 // FP64 decisions for the coefficients in the error band, one
                 // at a time, from the group's samples read again
-                if (__any(near != 0)) {
+                if (__any(anynear)) {
+                    unsigned keep = 0, near = 0;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const float e = rq[c] * F.gn;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float Yv = F.Y[c][r];
+                            const float v = v_[c][r];
+                            const float q = __builtin_fmaf(Yv, Yv, -l2 * v);
+                            const bool lv = 4 * lg + r < K;
+                            const float ay = fabsf(Yv);
+                            const float d = 1.0001e-5f * (e + ay);
+                            const bool nr = lv & (v > 0.f) & (fabsf(q) <= d * (2.f * ay + d));
+                            keep |= unsigned(at_[c][r] != 0.f) << (4 * c + r);
+                            near |= unsigned(nr) << (4 * c + r);
+                        }
+                    }
                     float x[8];
                     {
                         const bool av = m16 < K;
@@ -502,6 +525,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                         const double h = haar_d(lkv, l, m16);
                         double sy = 0.0, sv = 0.0;
                         if (m16 < K) {
+#pragma unroll
                             for (int s = 0; s < 8; ++s) {
                                 float xv = x[s];
                                 asm volatile("" : "+v"(xv));
@@ -520,15 +544,15 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                             keep = kp ? (keep | (1u << bit)) : (keep & ~(1u << bit));
                         }
                     }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const float at = (keep >> (4 * c + r)) & 1u ? 1.f : 0.f;
+                            at_[c][r] = at;
+                            C[c][r] = at != 0.f ? F.Y[c][r] : 0.f;
+                        }
                 }
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const float at = (keep >> (4 * c + r)) & 1u ? 1.f : 0.f;
-                        at_[c][r] = at;
-                        C[c][r] = at != 0.f ? F.Y[c][r] : 0.f;
-                    }
             }
 
             // ---- block C: risk surrogates and weights beside the synthesis
