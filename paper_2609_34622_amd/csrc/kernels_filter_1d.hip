@@ -2,22 +2,22 @@
 // (section Collaborative Filtering, 3-D transform of a group).
 //
 // A group of K <= 16 members is the 16 x 32 matrix X (rows: members, zero
-// rows past K).  Its 3-D transform is the pair of contractions
+// rows past K).  Its 3-D transform is
 //     Y = H (X T^T)        (spatial transform T per member, Haar H over members)
 // and the synthesis is  X^ = (H^T C) U^T.  The variance of every coefficient
-// is (H o H) (M (T o T)^T) for the per-sample variance map M.  Every one of
-// these products runs as v_mfma_f32_16x16x4f32 on one wavefront, with the
-// operands in registers:
-//   * A operand, lane l: row l%16, depth l/16;  B operand, lane l: depth
-//     l/16, column l%16;  result, lane l, register r: row 4(l/16)+r,
-//     column l%16.
-//   * The spatial depth (sample index i) is spread as i = 8(l/16) + s over
-//     the eight steps s, so each lane gathers eight contiguous samples of
-//     one member.
-//   * A result feeds the next product as its B operand when the next
-//     contraction runs over the result's rows: step s then takes register
-//     s, which holds row 4(l/16)+s, and the A operand is permuted to match.
-//   * The synthesis contracts over the columns of H^T C, so that matrix goes
+// is (H o H) (M (T o T)^T) for the per-sample variance map M.  One wavefront
+// filters one group:
+//   * The spatial products (X T^T, M (T o T)^T and the synthesis' Z U^T)
+//     run as split half-precision products on v_mfma_f32_16x16x32_f16 (see
+//     below).  Operand layout: A, lane l: row l%16, depth 8(l/16)..+7;
+//     B, lane l: depth 8(l/16)..+7, column l%16; result, lane l, register r:
+//     row 4(l/16)+r, column l%16.  The spatial depth (sample index i) is
+//     i = 8(l/16) + s, so each lane gathers eight contiguous samples of one
+//     member.
+//   * A result holds member 4(l/16)+r in register r, so the Haar transform
+//     over the members runs in registers: the first two levels inside a
+//     lane, the last two between lane groups (permlane swaps).
+//   * The synthesis contracts over the members' samples, so H^T C goes
 //     through a 16 x 32 LDS buffer once (write by rows, read by rows of the
 //     transpose).
 // Shrinkage, risk surrogates, weights and the aggregation work on the
@@ -64,19 +64,97 @@ __device__ __forceinline__ float pow_rsqrt2(int e)
     return (e & 1) ? v * kRsqrt2 : v;
 }
 
-// Haar entry H[l][j] for K = 2^lk members (rows: scaling, then detail rows
-// with support K, K/2, ..., 2); zero outside the K x K block.
-__device__ __forceinline__ float haar_f(int lk, int l, int j)
+// ---- Haar transform over the members, in registers.  Member m = 4 lg + r
+// of a group is register r of lane group lg (lanes 16 lg .. 16 lg + 15), so
+// the first two levels pair registers of one lane and the last two pair lane
+// groups (v_permlane16_swap, v_permlane32_swap).  Butterflies are
+// unnormalised and in place: the sum of a block stays at its first member,
+// the detail of a block at the first member of its second half, so the
+// detail row of level t (support 2^t) of block b sits at position
+// b 2^t + 2^(t - 1) and the scaling row at position 0.  The orthonormal
+// coefficient at position p is the butterfly value times 2^(-t/2) (t the
+// level of p; lk for position 0), the same factor that H^T needs before the
+// inverse butterflies.
+
+// (value at the even lane group, value at the odd one) of the lane-group
+// pair (0, 1) or (2, 3) this lane belongs to
+__device__ __forceinline__ void pair16(float v, float& a, float& b)
 {
-    const int K = 1 << lk;
-    if (l >= K || j >= K) return 0.f;
-    if (l == 0) return pow_rsqrt2(lk);
-    const int t = 31 - __clz(l);
-    const int e = lk - t;  // log2 of the row support
-    const int first = (l - (1 << t)) << e;
-    if (j < first || j >= first + (1 << e)) return 0.f;
-    const float v = pow_rsqrt2(e);
-    return (j - first) < (1 << (e - 1)) ? v : -v;
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+
+// (value at lane group 0 or 1, value at lane group 2 or 3) of the pair
+// (0, 2) or (1, 3) this lane belongs to
+__device__ __forceinline__ void pair32(float v, float& a, float& b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+
+// One butterfly of the last two levels on register 0: the first block of
+// the pair takes a + b, the second a - b (s = +1 or -1 per lane group).
+// The forward and inverse transforms both use these levels (the butterfly
+// is its own inverse up to the factor 2).
+__device__ __forceinline__ float level3(float v, float s3)
+{
+    float a, b;
+    pair16(v, a, b);
+    return __builtin_fmaf(s3, b, a);
+}
+
+__device__ __forceinline__ float level4(float v, float s4, bool odd)
+{
+    float a, b;
+    pair32(v, a, b);
+    return odd ? v : __builtin_fmaf(s4, b, a);
+}
+
+// Forward butterflies over all 16 member slots.  Slots past K hold zeros,
+// and a level that pairs a block with an all-zero block leaves the valid
+// positions unchanged, so the four levels serve every K = 2^lk; only the
+// normalisation of position 0 depends on K.
+__device__ __forceinline__ f4 haar_fwd(f4 v, float s3, float s4, bool odd)
+{
+    const float a0 = v[0] + v[1], a1 = v[0] - v[1];
+    const float a2 = v[2] + v[3], a3 = v[2] - v[3];
+    const float b0 = a0 + a2, b2 = a0 - a2;
+    return f4{level4(level3(b0, s3), s4, odd), a1, b2, a3};
+}
+
+// the squared Haar rows on non-negative values: every row keeps the sum of
+// its support (the detail positions included)
+__device__ __forceinline__ f4 haar_fwd_sq(f4 v, bool odd)
+{
+    const float a0 = v[0] + v[1], a2 = v[2] + v[3];
+    const float b0 = a0 + a2;
+    return f4{level4(level3(b0, 1.f), 1.f, odd), a0, b0, a2};
+}
+
+// inverse butterflies (levels in the reverse order); positions past K must
+// hold zeros
+__device__ __forceinline__ f4 haar_inv(f4 v, float s3, float s4, bool odd)
+{
+    const float c0 = level3(level4(v[0], s4, odd), s3);
+    const float b0 = c0 + v[2], b2 = c0 - v[2];
+    return f4{b0 + v[1], b0 - v[1], b2 + v[3], b2 - v[3]};
+}
+
+// normalisation 2^(-t/2) of position 4 lg (register 0) for 2^lk members
+__device__ __forceinline__ float haar_norm0(int lg, int lk)
+{
+    return (lg & 1) ? 0.35355339059327376f : (lg == 2 ? 0.25f : pow_rsqrt2(lk));
+}
+
+// standard Haar row (scaling, then detail rows with support K, K/2, ..., 2)
+// held at position p
+__device__ __forceinline__ int haar_row_of(int p, int lk)
+{
+    if (p == 0) return 0;
+    const int t = __ffs(p);  // level: p = b 2^t + 2^(t - 1)
+    return (1 << (lk - t)) + (p >> t);
 }
 
 __device__ __forceinline__ double haar_d(int lk, int l, int j)
@@ -200,9 +278,6 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     constexpr bool wiener = SH == BMND_SHRINK_WIENER;
     __shared__ __align__(16) _Float16 ops[3 * 2 * 2 * kWave * 8];
     __shared__ unsigned omax_[3];  // bit patterns of max |T|, |T o T|, |U|
-    // Haar operands per group size 2^lk and lane: H[m16][4lg + s] (analysis)
-    // and H[4lg + s][m16] (synthesis), s = 0..3
-    __shared__ __align__(16) float hops[5][kWave][8];
     __shared__ __align__(16) float ztr_[kWaves][16 * kZs];
     __shared__ float rl_[kWaves][16];
     // per wavefront [wcap] (numerator, denominator) pairs of its
@@ -251,15 +326,6 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         ops[opnd_index(m, 0, c, ln) + k] = h;
         ops[opnd_index(m, 1, c, ln) + k] = (_Float16)(t - (float)h);
     }
-    for (int e = threadIdx.x; e < 5 * kWave; e += kWave * kWaves) {
-        const int lk = e / kWave;
-        const int ln = e % kWave;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            hops[lk][ln][s] = haar_f(lk, ln & 15, 4 * (ln >> 4) + s);
-            hops[lk][ln][4 + s] = haar_f(lk, 4 * (ln >> 4) + s, ln & 15);
-        }
-    }
     float w0 = 1.f, rn0 = 1.f;  // leading axes have one-sample patches
 #pragma unroll
     for (int d = 0; d < kAx - 1; ++d) {
@@ -273,6 +339,10 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         rq[c] = rn0 * a.t.f32[a.t.rn[kAx - 1] + 16 * c + m16];
     }
     const double* T64 = a.t.f64 + a.t.T64[kAx - 1];
+    // signs of the cross-lane Haar levels and the lane groups that keep
+    // their level-3 value at level 4
+    const float s3 = (lg & 1) ? -1.f : 1.f, s4 = (lg & 2) ? -1.f : 1.f;
+    const bool odd = (lg & 1) != 0;
 
     const int nchunk = (a.n_refs + chunk - 1) / chunk;
     const int b = blockIdx.x / nchunk;
@@ -316,7 +386,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     };
     auto front = [&](int kraw, int mraw, bool lds) __attribute__((always_inline)) -> Front {
         Front f;
-        f.K = safe_count(kraw, a.gmax);
+        f.K = __builtin_amdgcn_readfirstlane(safe_count(kraw, a.gmax));
         f.lk = 31 - __clz(f.K);
         const bool av = m16 < f.K;  // this lane's member in the A layout
         // lanes past K read the samples at a valid origin inside the staged
@@ -367,35 +437,24 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         for (int s = 0; s < 8; ++s)
             mv[s] = __builtin_fmaf(relu(wiener ? pv[s] : x[s]), mp, av ? mg : 0.f);
         split8(mv, 1.f, mh, ml);
-        // ---- analysis: spatial rows 16c + m16 of every member, then Haar
-        // over the members with A[row m16][depth (lg, s)] = H[m16][4lg + s];
-        // the split scales are undone on the Haar operands (powers of two)
-        float ha[4], hy[4], h2[4], hp[4];
-        {
-            const float4 u0 = *reinterpret_cast<const float4*>(&hops[f.lk][lane][0]);
-            ha[0] = u0.x; ha[1] = u0.y; ha[2] = u0.z; ha[3] = u0.w;
-        }
+        // ---- analysis: spatial rows 16c + m16 of every member (split
+        // half-precision products), then the Haar transform over the members
+        // in registers; the split scales are undone together with the Haar
+        // normalisation 2^(-t/2) of each position
+        const float d0 = haar_norm0(lg, f.lk);
         const float uy = oinv[0] * ix, uv = oinv[1] * im, up = oinv[0] * ip;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            hy[s] = ha[s] * uy;
-            h2[s] = ha[s] * ha[s] * uv;
-            hp[s] = ha[s] * up;
-        }
+        const f4 ny = {uy * d0, uy * kRsqrt2, uy * 0.5f, uy * kRsqrt2};
+        const f4 nv = {uv * d0 * d0, uv * 0.5f, uv * 0.25f, uv * 0.5f};
+        const f4 np = {up * d0, up * kRsqrt2, up * 0.5f, up * kRsqrt2};
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const h8 th = opnd_h(ops, 0, 0, c, lane), tl = opnd_h(ops, 0, 1, c, lane);
             const f4 y1 = mul3(xh, xl, th, tl);
             const f4 v1 = mul3(mh, ml, opnd_h(ops, 1, 0, c, lane), opnd_h(ops, 1, 1, c, lane));
-            f4 p1 = {0.f, 0.f, 0.f, 0.f};
-            if constexpr (wiener) p1 = mul3(ph, pl, th, tl);
-            f.Y[c] = f.V[c] = f.G[c] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                f.Y[c] = mfma(hy[s], y1[s], f.Y[c]);
-                f.V[c] = mfma(h2[s], v1[s], f.V[c]);
-                if constexpr (wiener) f.G[c] = mfma(hp[s], p1[s], f.G[c]);
-            }
+            f.Y[c] = haar_fwd(y1, s3, s4, odd) * ny;
+            f.V[c] = haar_fwd_sq(v1, odd) * nv;
+            f.G[c] = f4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (wiener) f.G[c] = haar_fwd(mul3(ph, pl, th, tl), s3, s4, odd) * np;
         }
         return f;
     };
@@ -423,8 +482,8 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             const int krn = kr1, mrn = mr1;
             list(min(gi + 2, w1g - 1), kr1, mr1);
 
-            // shrinkage; coefficient (c, r), bit 4c + r: Haar row 4lg + r,
-            // spatial row 16c + m16
+            // shrinkage; coefficient (c, r), bit 4c + r: Haar position
+            // 4lg + r, spatial row 16c + m16
             float C[2][4], at_[2][4], v_[2][4], sh_[2][4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -444,7 +503,9 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                         at = den > 0.f ? shat * frcp(den) : 0.f;
                         Cv = at * Yv;
                     }
-                    C[c][r] = Cv;
+                    // positions past K carry no coefficient (the inverse
+                    // butterflies need zeros there)
+                    C[c][r] = 4 * lg + r < F.K ? Cv : 0.f;
                     at_[c][r] = at;
                     v_[c][r] = v;
                     sh_[c][r] = shat;
@@ -516,7 +577,8 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                         if (mk == 0) break;
                         const int src = __ffsll(mk) - 1;
                         const int bit = __ffs(__shfl(int(near), src)) - 1;
-                        const int l = 4 * (src >> 4) + (bit & 3);
+                        // standard Haar row of the coefficient's position
+                        const int l = haar_row_of(4 * (src >> 4) + (bit & 3), lk);
                         const int q = 16 * (bit >> 2) + (src & 15);
                         // opaque copies keep the FP64 set-up inside this
                         // rarely taken loop
@@ -558,18 +620,12 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             // ---- block C: risk surrogates and weights beside the synthesis
             // products.  Synthesis: Z = H^T C (A[row m16][depth (lg, s)] =
             // H[4lg + s][m16]) ...
-            float hi[4];
-            {
-                const float4 u1 = *reinterpret_cast<const float4*>(&hops[lk][lane][4]);
-                hi[0] = u1.x; hi[1] = u1.y; hi[2] = u1.z; hi[3] = u1.w;
-            }
+            const float d0 = haar_norm0(lg, lk);
+            const f4 nz = {d0, kRsqrt2, 0.5f, kRsqrt2};
             f4 Z[2];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                Z[c] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s = 0; s < 4; ++s) Z[c] = mfma(hi[s], C[c][s], Z[c]);
-            }
+            for (int c = 0; c < 2; ++c)
+                Z[c] = haar_inv(f4{C[c][0], C[c][1], C[c][2], C[c][3]} * nz, s3, s4, odd);
             float wA;  // weight of member m16
             if constexpr (WPLAIN) {
                 // classic model, group scope: R = sum of a_t^2 over the group
@@ -622,7 +678,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                     const float R = wave_sum(t);
                     wA = R > 0.f ? frcp(R) : 1.f;
                 } else {
-                    // per-plane surrogates r_l, l = 4lg + r; R_j = sum_l
+                    // per-plane surrogates r_l by Haar position 4lg + r; R_j = sum_l
                     // H[l][j]^2 r_l: the scaling row and one detail row per
                     // level hold member j
                     float rr[4];
@@ -633,11 +689,11 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                         for (int r = 0; r < 4; ++r) rl[4 * lg + r] = rr[r];
                     }
                     wsync();
+                    // (rl by coefficient position: the detail row of level
+                    // e holding member j sits at ((j >> e) << e) + 2^(e-1))
                     float R = ldexpf(rl[0], -lk);
-                    for (int t = 0; t < lk; ++t) {
-                        const int e = lk - t;
-                        R += ldexpf(rl[(1 << t) + (m16 >> e)], -e);
-                    }
+                    for (int e = 1; e <= lk; ++e)
+                        R += ldexpf(rl[((m16 >> e) << e) + (1 << (e - 1))], -e);
                     wA = R > 0.f ? frcp(R) : 1.f;
                     wsync();
                 }
