@@ -755,7 +755,9 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                 // every member inside this wavefront's tile (members past K add
                 // zeros at the fallback origin).  The lanes of one lane group
                 // write 16 distinct samples; lane groups take turns, so no two
-                // lanes of one instruction update the same sample.
+                // lanes of one instruction update the same sample.  LDS
+                // requests of a wavefront are served in issue order, so each
+                // read sees every earlier write without a wait between them.
                 float2 add[4][2];
                 int tl[4][2];
 #pragma unroll
@@ -780,11 +782,10 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                                 v.y += add[r][c].y;
                                 tacc[tl[r][c]] = v;
                             }
-                            wsync();
                         }
                     }
-                    wsync();
                 }
+                wsync();
             } else if (a.out_mode == 1) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
