@@ -445,7 +445,26 @@ __device__ __forceinline__ float float_of_ord(int m) { return __int_as_float(m >
 // Float modes (plain SSD of the pilot, Gaussian bias): one lane per
 // reference, keys of truncated scores, FP32 re-scoring of the K-1 members and
 // the next candidate, FP64 re-scoring of near-ties.
-template <int MODE, int GM>
+//
+// SHARE (references 4 samples apart): a window of 32 samples is 8 blocks of
+// 4, and block k of the reference of lane l is block 0 of lane l + k.  Each
+// lane squares the differences of its first block only, and the window sum
+// b0 + (b1 + (b2 + ... + (b6 + b7))) is folded from the next lanes by seven
+// adds of the value one lane up (DPP wave shift); the per-lane re-scoring
+// nests its sum the same way, so a member's re-scored value equals its key's
+// value bit for bit.  The last 7 lanes of a wavefront only supply blocks (57
+// references per wavefront).  A wavefront whose references are not 4 apart
+// scores them one lane each.
+constexpr int kShareBlk = 4;
+constexpr int kShareRefs = kWave - kJ / kShareBlk + 1;
+
+// the value of lane + 1 (0 in the last lane): DPP wave shift left by one
+__device__ __forceinline__ float from_next_lane(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+
+template <int MODE, int GM, bool SHARE>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3)))
 void k_match_1d_f(MatchArgs a, int cap_span)
 {
@@ -459,17 +478,27 @@ void k_match_1d_f(MatchArgs a, int cap_span)
     const int W = g.W[kAx - 1];
     const int ell = L - kJ;
     const int wlo = -(W / 2), whi = W - 1 - W / 2;
-    const int nchunk = (a.n_refs + kWave - 1) / kWave;
+    constexpr int rpw = SHARE ? kShareRefs : kWave;  // references per wavefront
+    const int nchunk = (a.n_refs + rpw - 1) / rpw;
     const int b = blockIdx.x / nchunk;
     const int chunk = blockIdx.x - b * nchunk;
     const int lane = threadIdx.x;
-    const int gi = chunk * kWave + lane;
-    const bool have = gi < a.n_refs;
-    const int r = have ? safe_origin(int(a.refs[gi]), last_origin(g)) : 0;
+    const int gi = chunk * rpw + lane;
+    const bool have = lane < rpw && gi < a.n_refs;
+    int r = have ? safe_origin(int(a.refs[gi]), last_origin(g)) : 0;
     const float* src = a.src + long(b) * g.V;
     const long t = long(b) * a.n_refs + gi;
+    // shared blocks: every reference of the wavefront 4 after the previous;
+    // lanes without one take the next positions of that run (their samples
+    // lie inside the staged span, which covers 64 lanes)
+    bool share = false;
+    if constexpr (SHARE) {
+        const int rf = __shfl(r, 0);
+        share = __all(!have || r == rf + kShareBlk * lane);
+        if (share) r = rf + kShareBlk * lane;
+    }
 
-    bool pending = have;
+    bool pending = have || share;
     while (__any(pending)) {
         const int r0 = __shfl(r, __ffsll(__ballot(pending)) - 1);
         const bool mine = pending && r >= r0 && (r - r0) <= cap_span;
@@ -499,14 +528,89 @@ void k_match_1d_f(MatchArgs a, int cap_span)
             const float tau_band = band * (fabsf(a.tau_f) + bmag);
             auto score = [&](int c) {
                 float x = 0.f;
+                if (SHARE && share) {
+                    float bs[kJ / kShareBlk];
 #pragma unroll
-                for (int i = 0; i < kJ; ++i) {
-                    const float df = __int_as_float(sx[c + i]) - rp[i];
-                    x = __builtin_fmaf(df, df, x);
+                    for (int k = 0; k < kJ / kShareBlk; ++k) {
+                        float bk = 0.f;
+#pragma unroll
+                        for (int i = 0; i < kShareBlk; ++i) {
+                            const float df = __int_as_float(sx[c + kShareBlk * k + i]) - rp[kShareBlk * k + i];
+                            bk = __builtin_fmaf(df, df, bk);
+                        }
+                        bs[k] = bk;
+                    }
+                    x = bs[kJ / kShareBlk - 1];
+#pragma unroll
+                    for (int k = kJ / kShareBlk - 2; k >= 0; --k) x = bs[k] + x;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kJ; ++i) {
+                        const float df = __int_as_float(sx[c + i]) - rp[i];
+                        x = __builtin_fmaf(df, df, x);
+                    }
                 }
                 if constexpr (MODE == kGauss) x -= a.bias;
                 return x;
             };
+            // one candidate: counts, record, insertion network
+            auto take = [&](int d, float x, int rec_key) __attribute__((always_inline)) {
+                const bool valid = d >= dlo && d <= dhi && d != 0 && fabsf(x) <= FLT_MAX;
+                acc += (valid && x < a.tau_f) ? 1 : 0;
+                namb += (valid && fabsf(x - a.tau_f) <= tau_band) ? 1 : 0;
+                const int key = valid ? ((ord_of(x) & ~255) | (d - wlo)) : INT_MAX;
+                if (key <= rec_key) {
+                    if (nrec < kRec) rec[nrec][lane] = (unsigned char)(d - wlo);
+                    ++nrec;
+                }
+#pragma unroll
+                for (int m = NS - 1; m >= 1; --m) s[m] = med3(s[m - 1], key, s[m]);
+                s[0] = min(s[0], key);
+            };
+            // candidates within the band of the running M-th value are
+            // recorded (the value at the start of a run of offsets bounds
+            // the later ones)
+            auto record_bound = [&]() __attribute__((always_inline)) {
+                int rk = INT_MAX - 1;
+                if (s[M - 1] != INT_MAX) {
+                    const float ub = float_of_ord(s[M - 1] | 255);
+                    const float lim = ub + band * (fabsf(ub) + bmag);
+                    if (fabsf(lim) <= FLT_MAX) rk = ord_of(lim) | 255;
+                }
+                return rk;
+            };
+            if (SHARE && share) {
+                constexpr int kRun = 8;  // offsets per pass (kept short: code size)
+                for (int d0 = wlo; d0 <= whi; d0 += kRun) {
+                    float buf[kRun + kShareBlk];
+#pragma unroll
+                    for (int i = 0; i < kRun + kShareBlk; ++i) buf[i] = __int_as_float(sx[rl + d0 + i]);
+                    const int rec_key = record_bound();
+#pragma unroll
+                    for (int u = 0; u < kRun; ++u) {
+                        // this lane's block, then the window sum over the
+                        // blocks of the next lanes
+                        float x = 0.f;
+#pragma unroll
+                        for (int i = 0; i < kShareBlk; ++i) {
+                            const float df = buf[u + i] - rp[i];
+                            x = __builtin_fmaf(df, df, x);
+                        }
+                        const float blk = x;
+#pragma unroll
+                        for (int k = 1; k < kJ / kShareBlk; ++k) x = blk + from_next_lane(x);
+                        if constexpr (MODE == kGauss) x -= a.bias;
+                        take(d0 + u, x, rec_key);
+                    }
+                }
+            } else if (SHARE) {
+                // references not 4 apart: one candidate at a time
+                int rec_key = INT_MAX - 1;
+                for (int d = wlo; d <= whi; ++d) {
+                    if (((d - wlo) & (kJ - 1)) == 0) rec_key = record_bound();
+                    take(d, score(rl + d), rec_key);
+                }
+            } else
             for (int d0 = wlo; d0 <= whi; d0 += kJ) {
                 float buf[2 * kJ];
 #pragma unroll
@@ -545,6 +649,9 @@ void k_match_1d_f(MatchArgs a, int cap_span)
                 }
             }
 
+            // lanes that only supplied blocks stop here (their window sums
+            // are partial, and a wavefront pays for any lane's fallback work)
+            if (have) {
             int K = group_size_of(a, acc, ncand);
             // scores within the band of tau are accepted or not in FP64, when
             // that can change the group size
@@ -672,6 +779,7 @@ void k_match_1d_f(MatchArgs a, int cap_span)
 #pragma unroll
             for (int m = 1; m < GM; ++m) out[m] = m < K ? ml[m - 1] : -1;
             a.count[t] = K;
+            }
         }
         pending = pending && !mine;
         __syncthreads();
@@ -679,18 +787,33 @@ void k_match_1d_f(MatchArgs a, int cap_span)
 }
 
 template <int GM>
-hipError_t launch_1d_gm(const MatchArgs& a, int mode, int cap_span, int kmax, hipStream_t s)
+hipError_t launch_1d_gm(const MatchArgs& a, int mode, int cap_span, int kmax, int step,
+                        hipStream_t s)
 {
     const int nchunk = (a.n_refs + kWave - 1) / kWave;
     const dim3 grid(unsigned(long(nchunk) * a.g.batch));
     const int W = a.g.W[kAx - 1];
     const size_t lds = sizeof(int) * size_t(cap_span + W + 2 * kJ);
-    if (mode == kGauss) {
-        hipLaunchKernelGGL((k_match_1d_f<kGauss, GM>), grid, dim3(kWave), lds, s, a, cap_span);
-        return hipGetLastError();
-    }
     if (mode != kCount) {
-        hipLaunchKernelGGL((k_match_1d_f<kPlain, GM>), grid, dim3(kWave), lds, s, a, cap_span);
+        // shared blocks when the references are 4 apart (the staged span of
+        // 64 steps covers the helper lanes)
+        const bool share = step == kShareBlk;
+        const int ns = (a.n_refs + kShareRefs - 1) / kShareRefs;
+        const dim3 grid_s(unsigned(long(ns) * a.g.batch));
+        if (mode == kGauss) {
+            if (share)
+                hipLaunchKernelGGL((k_match_1d_f<kGauss, GM, true>), grid_s, dim3(kWave), lds, s, a,
+                                   cap_span);
+            else
+                hipLaunchKernelGGL((k_match_1d_f<kGauss, GM, false>), grid, dim3(kWave), lds, s, a,
+                                   cap_span);
+        } else if (share) {
+            hipLaunchKernelGGL((k_match_1d_f<kPlain, GM, true>), grid_s, dim3(kWave), lds, s, a,
+                               cap_span);
+        } else {
+            hipLaunchKernelGGL((k_match_1d_f<kPlain, GM, false>), grid, dim3(kWave), lds, s, a,
+                               cap_span);
+        }
         return hipGetLastError();
     }
     // byte counts first (scores below 2^23 in magnitude need gamma <= 256);
@@ -722,12 +845,12 @@ hipError_t launch_match_1d(const MatchArgs& a, int mode, int step, int kmax, hip
 {
     const int cap_span = kWave * max(step, 1);
     switch (a.gmax) {
-    case 1: return launch_1d_gm<1>(a, mode, cap_span, kmax, s);
-    case 2: return launch_1d_gm<2>(a, mode, cap_span, kmax, s);
-    case 4: return launch_1d_gm<4>(a, mode, cap_span, kmax, s);
-    case 8: return launch_1d_gm<8>(a, mode, cap_span, kmax, s);
-    case 16: return launch_1d_gm<16>(a, mode, cap_span, kmax, s);
-    default: return launch_1d_gm<32>(a, mode, cap_span, kmax, s);
+    case 1: return launch_1d_gm<1>(a, mode, cap_span, kmax, step, s);
+    case 2: return launch_1d_gm<2>(a, mode, cap_span, kmax, step, s);
+    case 4: return launch_1d_gm<4>(a, mode, cap_span, kmax, step, s);
+    case 8: return launch_1d_gm<8>(a, mode, cap_span, kmax, step, s);
+    case 16: return launch_1d_gm<16>(a, mode, cap_span, kmax, step, s);
+    default: return launch_1d_gm<32>(a, mode, cap_span, kmax, step, s);
     }
 }
 
