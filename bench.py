@@ -231,8 +231,17 @@ def bench_serving(B, torch, n: int = 60) -> dict:
     cap = serving.serve_fifo(calib)
     rate = 0.7 * cap["requests"] / cap["makespan_s"]
     trace = serving.make_trace(n, rate, 7001, **kw)
+    # one untimed pass of each path: the per-shape library caches (reference
+    # origins, tables), the streams' queues and the pinned host buffers exist
+    # before either path is timed
     budget = 32 << 30
     srv = serving.Server(budget_bytes=budget, slots=4)   # in-flight work cap: "auto"
+    serving.serve_fifo(trace)
+    for r in trace:
+        r.out = None
+    srv.run(trace)
+    for r in trace:
+        r.out = None
     cont = srv.run(trace)
     for r in trace:
         r.out = None
@@ -240,8 +249,8 @@ def bench_serving(B, torch, n: int = 60) -> dict:
     return {"requests": n, "arrival_rate_per_s": round(rate, 3), "hbm_budget_gib": budget >> 30,
             "trace": "seeded Poisson arrivals; 40% 1-D (8k-128k), 40% 2-D (128^2-512^2), "
                      "20% 3-D (32^3-64^3, mass conservation); peaks log-uniform [2, 100]",
-            "admission": "4 streams, HBM budget, in-flight work at most the largest request "
-                         "seen so far",
+            "admission": "4 streams, HBM budget, in-flight work at most half the largest "
+                         "request seen so far; one untimed pass of each path first",
             "continuous": {k: round(v, 3) for k, v in cont.items()},
             "plain_fifo": {k: round(v, 3) for k, v in fifo.items()}}
 

@@ -128,13 +128,17 @@ def make_trace(n: int, rate: float, seed: int, len_1d=(8192, 262144), side_2d=(2
 
 
 class _Slot:
-    def __init__(self, torch):
+    def __init__(self, torch, staging_bytes: int):
         self.stream = torch.cuda.Stream()          # default priority
         self.done = torch.cuda.Event()
         self.req: Optional[Request] = None
         self.bufs = None
         self.host_out = None
         self.bytes = 0
+        # pinned staging for the input and the result, allocated once
+        n = max(int(staging_bytes) // 4, 1)
+        self.pin_in = torch.empty(n, dtype=torch.float32, pin_memory=True)
+        self.pin_out = torch.empty(n, dtype=torch.float32, pin_memory=True)
 
 
 class Server:
@@ -142,17 +146,23 @@ class Server:
     budget of `budget_bytes`.  A request is admitted only while the work in
     flight (``request_work``) stays within `work_cap`, or when nothing runs:
     small requests still overlap, but two large ones do not stretch each
-    other's latency by sharing the device.  The default cap ("auto") is the
-    largest single request seen so far; None admits whatever fits."""
+    other's latency by sharing the device.  The default cap ("auto") is
+    half the largest single request seen so far; None admits whatever fits."""
 
     def __init__(self, budget_bytes: int, slots: int = 4,
                  clock: Callable[[], float] = time.perf_counter,
-                 work_cap="auto"):
+                 work_cap="auto", staging_bytes: int = 4 << 20):
         import torch
 
         self.torch = torch
         self.budget = int(budget_bytes)
-        self.slots = [_Slot(torch) for _ in range(slots)]
+        self.slots = [_Slot(torch, staging_bytes) for _ in range(slots)]
+        # the first work on a new stream sets up its queue: do that now,
+        # not inside the first request's latency
+        for slot in self.slots:
+            with torch.cuda.stream(slot.stream):
+                torch.zeros(1, device="cuda")
+            slot.stream.synchronize()
         self.clock = clock
         self.work_cap = work_cap
         self.in_use = 0
@@ -165,12 +175,22 @@ class Server:
         nbytes = request_bytes(req)
         geom = geometry(req.y.shape)
         noise = poisson(req.s_p)
+        n = req.y.size
+        staged = n <= slot.pin_in.numel()
         with torch.cuda.stream(slot.stream):
-            y = torch.from_numpy(req.y).pin_memory().to("cuda", non_blocking=True)
+            if staged:
+                # the slot's pinned buffers: no host allocation per request
+                slot.pin_in[:n].numpy()[:] = req.y.ravel()
+                y = slot.pin_in[:n].view(req.y.shape).to("cuda", non_blocking=True)
+            else:
+                y = torch.from_numpy(req.y).pin_memory().to("cuda", non_blocking=True)
             out = torch.empty_like(y)
             ws = torch.empty(nbytes - 2 * req.y.nbytes, dtype=torch.uint8, device="cuda")
             bmnd_denoise(y, geom, noise, req.params, out, None, ws, stream=slot.stream.cuda_stream)
-            host = torch.empty(out.shape, dtype=torch.float32, pin_memory=True)
+            if staged:
+                host = slot.pin_out[:n].view(req.y.shape)
+            else:
+                host = torch.empty(out.shape, dtype=torch.float32, pin_memory=True)
             host.copy_(out, non_blocking=True)
             slot.done.record(slot.stream)
         slot.req, slot.bufs, slot.host_out, slot.bytes = req, (y, out, ws), host, nbytes
@@ -214,7 +234,7 @@ class Server:
                 busy = len(free) < len(self.slots)
                 w = request_work(pending[0])
                 self.seen_max = max(self.seen_max, w)
-                cap = self.seen_max if self.work_cap == "auto" else self.work_cap
+                cap = 0.5 * self.seen_max if self.work_cap == "auto" else self.work_cap
                 if not admits(self.work, w, cap, busy):
                     break
                 self._admit(free[0], pending.popleft(), now)
