@@ -586,21 +586,30 @@ void k_match_1d_f(MatchArgs a, int cap_span)
 #pragma unroll
                     for (int i = 0; i < kRun + kShareBlk; ++i) buf[i] = __int_as_float(sx[rl + d0 + i]);
                     const int rec_key = record_bound();
+                    // this lane's block of every offset of the run, then the
+                    // window sums over the blocks of the next lanes (the
+                    // run's folds interleave, so no fold waits on its own
+                    // previous step)
+                    float blk[kRun], x[kRun];
 #pragma unroll
                     for (int u = 0; u < kRun; ++u) {
-                        // this lane's block, then the window sum over the
-                        // blocks of the next lanes
-                        float x = 0.f;
+                        float b = 0.f;
 #pragma unroll
                         for (int i = 0; i < kShareBlk; ++i) {
                             const float df = buf[u + i] - rp[i];
-                            x = __builtin_fmaf(df, df, x);
+                            b = __builtin_fmaf(df, df, b);
                         }
-                        const float blk = x;
+                        blk[u] = x[u] = b;
+                    }
 #pragma unroll
-                        for (int k = 1; k < kJ / kShareBlk; ++k) x = blk + from_next_lane(x);
-                        if constexpr (MODE == kGauss) x -= a.bias;
-                        take(d0 + u, x, rec_key);
+                    for (int k = 1; k < kJ / kShareBlk; ++k)
+#pragma unroll
+                        for (int u = 0; u < kRun; ++u) x[u] = blk[u] + from_next_lane(x[u]);
+#pragma unroll
+                    for (int u = 0; u < kRun; ++u) {
+                        float xu = x[u];
+                        if constexpr (MODE == kGauss) xu -= a.bias;
+                        take(d0 + u, xu, rec_key);
                     }
                 }
             } else if (SHARE) {
