@@ -201,6 +201,18 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+// max over the wavefront of non-negative values (the row by DPP as in
+// sum16, then the four rows)
+__device__ __forceinline__ float wave_max(float v)
+{
+    v = fmaxf(v, dpp<0xB1>(v));
+    v = fmaxf(v, dpp<0x4E>(v));
+    v = fmaxf(v, dpp<0x124>(v));
+    v = fmaxf(v, dpp<0x128>(v));
+    v = fmaxf(v, __shfl_xor(v, 16));
+    return fmaxf(v, __shfl_xor(v, 32));
+}
+
 __device__ __forceinline__ double wave_sum64(double v)
 {
 #pragma unroll
@@ -379,7 +391,10 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     // block as the shrinkage of group gi, so the scheduler interleaves the
     // matrix-core chain of one with the vector work of the other.
     struct Front {
+        // Wiener stage: butterfly values as they come (see the shrinkage);
+        // other stages: orthonormal coefficients and their variances
         f4 Y[2], V[2], G[2];
+        float uy, uv, up;  // split unscales (powers of two)
         float gn;   // norm of the group's samples
         int K, lk, oa;
         bool ok;    // every lane's samples came from the staged range
@@ -441,20 +456,26 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         // half-precision products), then the Haar transform over the members
         // in registers; the split scales are undone together with the Haar
         // normalisation 2^(-t/2) of each position
+        f.uy = oinv[0] * ix;
+        f.uv = oinv[1] * im;
+        f.up = oinv[0] * ip;
         const float d0 = haar_norm0(lg, f.lk);
-        const float uy = oinv[0] * ix, uv = oinv[1] * im, up = oinv[0] * ip;
-        const f4 ny = {uy * d0, uy * kRsqrt2, uy * 0.5f, uy * kRsqrt2};
-        const f4 nv = {uv * d0 * d0, uv * 0.5f, uv * 0.25f, uv * 0.5f};
-        const f4 np = {up * d0, up * kRsqrt2, up * 0.5f, up * kRsqrt2};
+        const f4 ny = {f.uy * d0, f.uy * kRsqrt2, f.uy * 0.5f, f.uy * kRsqrt2};
+        const f4 nv = {f.uv * d0 * d0, f.uv * 0.5f, f.uv * 0.25f, f.uv * 0.5f};
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const h8 th = opnd_h(ops, 0, 0, c, lane), tl = opnd_h(ops, 0, 1, c, lane);
             const f4 y1 = mul3(xh, xl, th, tl);
             const f4 v1 = mul3(mh, ml, opnd_h(ops, 1, 0, c, lane), opnd_h(ops, 1, 1, c, lane));
-            f.Y[c] = haar_fwd(y1, s3, s4, odd) * ny;
-            f.V[c] = haar_fwd_sq(v1, odd) * nv;
+            f.Y[c] = haar_fwd(y1, s3, s4, odd);
+            f.V[c] = haar_fwd_sq(v1, odd);
             f.G[c] = f4{0.f, 0.f, 0.f, 0.f};
-            if constexpr (wiener) f.G[c] = haar_fwd(mul3(ph, pl, th, tl), s3, s4, odd) * np;
+            if constexpr (wiener) {
+                f.G[c] = haar_fwd(mul3(ph, pl, th, tl), s3, s4, odd);
+            } else {
+                f.Y[c] = f.Y[c] * ny;
+                f.V[c] = f.V[c] * nv;
+            }
         }
         return f;
     };
@@ -485,6 +506,16 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             // shrinkage; coefficient (c, r), bit 4c + r: Haar position
             // 4lg + r, spatial row 16c + m16
             float C[2][4], at_[2][4], v_[2][4], sh_[2][4];
+            // Wiener stage on butterfly values: at position p, Gamma = Gb up
+            // D and V = Vb uv D^2 (D the Haar normalisation of p), so the gain
+            // shat / (shat + s_v V), shat = [Gamma^2 - a V]_+, is that of
+            // Gb^2 - kA Vb and kS Vb with kA = a uv / up^2, kS = s_v uv / up^2
+            // (up, uv powers of two).  C is kept pre-multiplied by D, as the
+            // inverse butterflies need it: C D = at Yb uy D^2.
+            const float dq = haar_norm0(lg, lk);
+            const float kA = a.power_a * (F.uv / (F.up * F.up));
+            const float kS = a.s_v * (F.uv / (F.up * F.up));
+            const f4 d2 = {dq * dq, 0.5f, 0.25f, 0.5f};
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
 #pragma unroll
@@ -498,16 +529,20 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                         at = Yv != 0.f ? m * frcp(fabsf(Yv)) : 0.f;
                     } else if constexpr (SH == BMND_SHRINK_WIENER) {
                         const float gam = F.G[c][r];
-                        shat = relu(gam * gam - a.power_a * v);
-                        const float den = shat + a.s_v * v;
+                        shat = relu(__builtin_fmaf(-kA, v, gam * gam));
+                        const float den = __builtin_fmaf(kS, v, shat);
                         at = den > 0.f ? shat * frcp(den) : 0.f;
-                        Cv = at * Yv;
+                        Cv = at * Yv * (F.uy * d2[r]);
+                        if constexpr (!WPLAIN) {
+                            // the weighting models need the true scales
+                            shat *= F.up * F.up * d2[r];
+                        }
                     }
                     // positions past K carry no coefficient (the inverse
                     // butterflies need zeros there)
                     C[c][r] = 4 * lg + r < F.K ? Cv : 0.f;
                     at_[c][r] = at;
-                    v_[c][r] = v;
+                    v_[c][r] = SH == BMND_SHRINK_WIENER && !WPLAIN ? v * (F.uv * d2[r]) : v;
                     sh_[c][r] = shat;
                 }
             }
@@ -620,8 +655,9 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             // ---- block C: risk surrogates and weights beside the synthesis
             // products.  Synthesis: Z = H^T C (A[row m16][depth (lg, s)] =
             // H[4lg + s][m16]) ...
-            const float d0 = haar_norm0(lg, lk);
-            const f4 nz = {d0, kRsqrt2, 0.5f, kRsqrt2};
+            // (the Wiener stage's C is pre-multiplied by D already)
+            const f4 nz = SH == BMND_SHRINK_WIENER ? f4{1.f, 1.f, 1.f, 1.f}
+                                                   : f4{dq, kRsqrt2, 0.5f, kRsqrt2};
             f4 Z[2];
 #pragma unroll
             for (int c = 0; c < 2; ++c)
@@ -712,12 +748,12 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                 za[4] = u1.x; za[5] = u1.y; za[6] = u1.z; za[7] = u1.w;
             }
             wsync();
-            // |Z| <= ||Z||_F = ||C||_F (the Haar block is orthonormal)
-            float c2 = 0.f;
+            // the split bound: the largest |Z| of the group
+            float zm = 0.f;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) c2 += C[0][r] * C[0][r] + C[1][r] * C[1][r];
+            for (int i = 0; i < 8; ++i) zm = fmaxf(zm, fabsf(za[i]));
             float iz;
-            const float scz = split_scale(fsqrt(wave_sum(c2)), &iz);
+            const float scz = split_scale(wave_max(zm), &iz);
             h8 zh, zl;
             split8(za, scz, zh, zl);
             const float uz = oinv[2] * iz;
