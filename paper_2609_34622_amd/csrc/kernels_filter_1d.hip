@@ -445,13 +445,29 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             gp = fsqrt(wave_sum(gp2));
             split8(pv, split_scale(gp, &ip), ph, pl);
         }
-        // variance map s_P [src]_+ (Poisson) or sigma^2, scaled while formed
-        const float scm = split_scale(poisson ? a.s_p * (wiener ? gp : f.gn) : a.sigma2, &im);
-        const float mp = poisson ? a.s_p * scm : 0.f, mg = poisson ? 0.f : a.sigma2 * scm;
+        // variance map s_P [src]_+ (Poisson) or sigma^2, scaled while formed.
+        // Poisson with no negative source sample in the group (always so
+        // for counts): the map is s_P src, whose split is the source's own
+        // with s_P in the unscale.
+        bool nonneg = false;
+        if (poisson) {
+            float mn = 0.f;
 #pragma unroll
-        for (int s = 0; s < 8; ++s)
-            mv[s] = __builtin_fmaf(relu(wiener ? pv[s] : x[s]), mp, av ? mg : 0.f);
-        split8(mv, 1.f, mh, ml);
+            for (int s = 0; s < 8; ++s) mn = fminf(mn, wiener ? pv[s] : x[s]);
+            nonneg = __all(mn >= 0.f);
+        }
+        if (nonneg) {
+            mh = wiener ? ph : xh;
+            ml = wiener ? pl : xl;
+            im = (wiener ? ip : ix) * a.s_p;
+        } else {
+            const float scm = split_scale(poisson ? a.s_p * (wiener ? gp : f.gn) : a.sigma2, &im);
+            const float mp = poisson ? a.s_p * scm : 0.f, mg = poisson ? 0.f : a.sigma2 * scm;
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+                mv[s] = __builtin_fmaf(relu(wiener ? pv[s] : x[s]), mp, av ? mg : 0.f);
+            split8(mv, 1.f, mh, ml);
+        }
         // ---- analysis: spatial rows 16c + m16 of every member (split
         // half-precision products), then the Haar transform over the members
         // in registers; the split scales are undone together with the Haar
