@@ -292,9 +292,9 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     __shared__ unsigned omax_[3];  // bit patterns of max |T|, |T o T|, |U|
     __shared__ __align__(16) float ztr_[kWaves][16 * kZs];
     __shared__ float rl_[kWaves][16];
-    // per wavefront [wcap] (numerator, denominator) pairs of its
-    // accumulation tile, then [tile_cap] staged samples and [tile_cap]
-    // staged pilot
+    // per wavefront its accumulation tile: two [wcap] numerator copies and
+    // [wcap] member weights by origin; then [tile_cap] staged samples and
+    // [tile_cap] staged pilot
     extern __shared__ __align__(16) float tile[];
 
     const Geo& g = a.g;
@@ -367,8 +367,9 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     const int w1g = min(g1, w0g + sub);
     const int tile_lo = tile_cap > 0 ? a.match[(long(b) * a.n_refs + g0) * a.gmax] - tile_back : 0;
     const int wlo = (wcap > 0 && w0g < w1g) ? a.match[(long(b) * a.n_refs + w0g) * a.gmax] - tile_back : 0;
-    float2* tacc = reinterpret_cast<float2*>(tile + wave * 2 * wcap);
-    float* ysm = tile + kWaves * 2 * wcap;
+    float* tnum = tile + wave * 3 * wcap;  // copies [0, wcap) and [wcap, 2 wcap)
+    float* twt = tnum + 2 * wcap;
+    float* ysm = tile + kWaves * 3 * wcap;
     float* psm = ysm + tile_cap;
     const bool poisson = a.noise == BMND_NOISE_POISSON;
     const int omax = last_origin(g);
@@ -382,7 +383,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         ysm[i] = inb ? yb[u] : 0.f;
         if constexpr (wiener) psm[i] = inb ? pb[u] : 0.f;
     }
-    for (int i = lane; i < wcap; i += kWave) tacc[i] = make_float2(0.f, 0.f);
+    for (int i = lane; i < 3 * wcap; i += kWave) tnum[i] = 0.f;
     __syncthreads();
 
     // ---- front end of one group: its size and origin, the gather of its
@@ -805,38 +806,34 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                 if (lane < a.gmax) a.weights[grp * a.gmax + lane] = lane < K ? wA : 0.f;
             } else if (a.out_mode == 1 && __all(in_tile)) {
                 // every member inside this wavefront's tile (members past K add
-                // zeros at the fallback origin).  The lanes of one lane group
-                // write 16 distinct samples; lane groups take turns, so no two
-                // lanes of one instruction update the same sample.  LDS
-                // requests of a wavefront are served in issue order, so each
-                // read sees every earlier write without a wait between them.
-                float2 add[4][2];
-                int tl[4][2];
+                // zeros at the tile's start instead).  Numerators: lane groups
+                // 0 and 2 update the first copy, 1 and 3 the second, and the
+                // pairs (0, 1) and (2, 3) take turns, so no instruction updates
+                // a sample twice.  LDS requests of a wavefront are served in
+                // issue order, so each read sees every earlier write without a
+                // wait between them.  Denominators: the weight of each member
+                // at its origin (the members of a group have distinct origins);
+                // the flush applies the window.
+                float add[4][2];
+                int tl[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const bool lv = 4 * lg + r < K;
+                    tl[r] = (lv ? od[r] - wlo : 0) + m16 + ((lg & 1) ? wcap : 0);
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const float ww = lv ? wd[r] * wq[c] : 0.f;
-                        add[r][c] = make_float2(ww * o[c][r], ww);
-                        tl[r][c] = (lv ? od[r] - wlo : 0) + 16 * c + m16;
-                    }
+                    for (int c = 0; c < 2; ++c) add[r][c] = lv ? wd[r] * wq[c] * o[c][r] : 0.f;
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (lg == q) {
+                for (int q = 0; q < 2; ++q) {
+                    if ((lg >> 1) == q) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
 #pragma unroll
-                            for (int c = 0; c < 2; ++c) {
-                                float2 v = tacc[tl[r][c]];
-                                v.x += add[r][c].x;
-                                v.y += add[r][c].y;
-                                tacc[tl[r][c]] = v;
-                            }
+                            for (int c = 0; c < 2; ++c) tnum[tl[r] + 16 * c] += add[r][c];
                         }
                     }
                 }
+                if (lane < K) twt[oa - wlo] += wA;
                 wsync();
             } else if (a.out_mode == 1) {
 #pragma unroll
@@ -896,16 +893,22 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         }
     }
 
-    // ---- flush this wavefront's tile
+    // ---- flush this wavefront's tile; the denominator at i is the member
+    // weights at origins i - t times the patch window at t
     if (acc_tile) {
         wsync();
         for (int i = lane; i < wcap; i += kWave) {
-            const float2 v = tacc[i];
+            float den = 0.f;
+#pragma unroll
+            for (int t = 0; t < kJ; ++t) {
+                const float wt = i >= t ? twt[i - t] : 0.f;
+                den = __builtin_fmaf(wt, w0 * a.t.f32[a.t.win[kAx - 1] + t], den);
+            }
             const int u = wlo + i;
-            if (v.y != 0.f && u >= 0 && u < g.V) {
+            if (den != 0.f && u >= 0 && u < g.V) {
                 // FP64 sums: the float result does not depend on the order
-                unsafeAtomicAdd(&a.numd[vb + u], double(v.x));
-                unsafeAtomicAdd(&a.dend[vb + u], double(v.y));
+                unsafeAtomicAdd(&a.numd[vb + u], double(tnum[i] + tnum[wcap + i]));
+                unsafeAtomicAdd(&a.dend[vb + u], double(den));
             }
         }
     }
@@ -941,12 +944,12 @@ hipError_t launch_filter_1d(const FilterArgs& a, int step_last, hipStream_t s)
         tile_back = g.W[kAx - 1] / 2;
         tile_cap = (chunk - 1) * st + g.W[kAx - 1] + kJ;
         if (a.out_mode == 1) wcap = (sub - 1) * st + g.W[kAx - 1] + kJ;
-        if (kWaves * 2 * wcap + nstage * tile_cap > kDynFloats) wcap = 0;
+        if (kWaves * 3 * wcap + nstage * tile_cap > kDynFloats) wcap = 0;
         tile_cap = min(tile_cap, kDynFloats / nstage);
     }
     const int nchunk = (a.n_refs + chunk - 1) / chunk;
     const dim3 grid(unsigned(long(nchunk) * g.batch));
-    const size_t lds = sizeof(float) * size_t(kWaves * 2 * wcap + nstage * tile_cap);
+    const size_t lds = sizeof(float) * size_t(kWaves * 3 * wcap + nstage * tile_cap);
     const bool staged = tile_cap >= 8;
     const bool wplain = a.wmodel == BMND_WEIGHT_CLASSIC && a.wscope == BMND_SCOPE_GROUP &&
                         a.wdomain == BMND_WDOMAIN_COEFFICIENT;
