@@ -182,35 +182,48 @@ __device__ __forceinline__ float dpp(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
 
-// sum over the 16 lanes of a row (every lane gets it): pairs, quads, then
-// rotations of the row by 4 and 8
+// sum over the 16 lanes of a row: pairs, quads, then the quad pairs (0, 1),
+// (2, 3) and the two halves, each step adding the same two values in every
+// lane, so that all lanes of the row get the same sum
 __device__ __forceinline__ float sum16(float v)
 {
     v += dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]
     v += dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-    v += dpp<0x124>(v);  // row_ror 4
-    v += dpp<0x128>(v);  // row_ror 8
+    v += dpp<0x141>(v);  // row_half_mirror
+    v += dpp<0x140>(v);  // row_mirror
     return v;
 }
 
+// sum over the wavefront: the row by DPP, then the lane-group pairs (0, 1),
+// (2, 3) and (0, 2), (1, 3) by permlane swaps (every lane adds the same two
+// values, so all get the same sum)
 __device__ __forceinline__ float wave_sum(float v)
 {
-    v = sum16(v);
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
+    float a, b;
+    pair16(sum16(v), a, b);
+    pair32(a + b, a, b);
+    return a + b;
 }
 
-// max over the wavefront of non-negative values (the row by DPP as in
-// sum16, then the four rows)
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+// max over the wavefront of non-negative values, which order as their bit
+// patterns (integer maxima need no canonicalisation)
 __device__ __forceinline__ float wave_max(float v)
 {
-    v = fmaxf(v, dpp<0xB1>(v));
-    v = fmaxf(v, dpp<0x4E>(v));
-    v = fmaxf(v, dpp<0x124>(v));
-    v = fmaxf(v, dpp<0x128>(v));
-    v = fmaxf(v, __shfl_xor(v, 16));
-    return fmaxf(v, __shfl_xor(v, 32));
+    int x = __float_as_int(v);
+    x = max(x, dpp_i<0xB1>(x));
+    x = max(x, dpp_i<0x4E>(x));
+    x = max(x, dpp_i<0x141>(x));
+    x = max(x, dpp_i<0x140>(x));
+    float a, b;
+    pair16(__int_as_float(x), a, b);
+    pair32(__int_as_float(max(__float_as_int(a), __float_as_int(b))), a, b);
+    return __int_as_float(max(__float_as_int(a), __float_as_int(b)));
 }
 
 __device__ __forceinline__ double wave_sum64(double v)
@@ -782,10 +795,12 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             // ---- outputs; o[c][r] is sample 16c + m16 of member 4lg + r
             int od[4];
             float wd[4];
+            // group-scope weights are the same for every member
+            const bool wuni = WPLAIN || a.wscope == BMND_SCOPE_GROUP;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 od[r] = __shfl(oa, 4 * lg + r);
-                wd[r] = __shfl(wA, 4 * lg + r);
+                wd[r] = wuni ? wA : __shfl(wA, 4 * lg + r);
             }
             // every member of the group inside the accumulation tile (members
             // past K add zeros at the tile's start instead)
