@@ -259,8 +259,11 @@ __global__ __launch_bounds__(kMatchThreads) void k_match(MatchArgs a)
                     if constexpr (MODE == kCount) {
                         acc += x < a.tau_i;
                     } else {
-                        acc += x < a.tau_f;
-                        namb += fabsf(x - a.tau_f) <= tau_band;
+                        // acc: certain acceptances; namb: the band around
+                        // tau, decided in FP64 when it matters
+                        const bool amb = fabsf(x - a.tau_f) <= tau_band;
+                        acc += x < a.tau_f && !amb;
+                        namb += amb;
                     }
 #pragma unroll
                     for (int m = NS - 1; m >= 1; --m) s[m] = smin(s[m], smax(s[m - 1], x));

@@ -556,8 +556,10 @@ void k_match_1d_f(MatchArgs a, int cap_span)
             // one candidate: counts, record, insertion network
             auto take = [&](int d, float x, int rec_key) __attribute__((always_inline)) {
                 const bool valid = d >= dlo && d <= dhi && d != 0 && fabsf(x) <= FLT_MAX;
-                acc += (valid && x < a.tau_f) ? 1 : 0;
-                namb += (valid && fabsf(x - a.tau_f) <= tau_band) ? 1 : 0;
+                // acc: certain acceptances; namb: the band around tau
+                const bool amb = valid && fabsf(x - a.tau_f) <= tau_band;
+                acc += (valid && x < a.tau_f && !amb) ? 1 : 0;
+                namb += amb ? 1 : 0;
                 const int key = valid ? ((ord_of(x) & ~255) | (d - wlo)) : INT_MAX;
                 if (key <= rec_key) {
                     if (nrec < kRec) rec[nrec][lane] = (unsigned char)(d - wlo);
@@ -645,8 +647,9 @@ void k_match_1d_f(MatchArgs a, int cap_span)
                     // offsets outside the clipped window, the reference itself
                     // and non-finite scores are never counted or selected
                     const bool valid = d >= dlo && d <= dhi && d != 0 && fabsf(x) <= FLT_MAX;
-                    acc += (valid && x < a.tau_f) ? 1 : 0;
-                    namb += (valid && fabsf(x - a.tau_f) <= tau_band) ? 1 : 0;
+                    const bool amb = valid && fabsf(x - a.tau_f) <= tau_band;
+                    acc += (valid && x < a.tau_f && !amb) ? 1 : 0;
+                    namb += amb ? 1 : 0;
                     const int key = valid ? ((ord_of(x) & ~255) | (d - wlo)) : INT_MAX;
                     if (key <= rec_key) {
                         if (nrec < kRec) rec[nrec][lane] = (unsigned char)(d - wlo);

@@ -304,8 +304,10 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
         if constexpr (MODE == kCount) {
             acc += x < a.tau_i;
         } else {
-            acc += x < a.tau_f;
-            namb += fabsf(x - a.tau_f) <= tau_band;
+            // acc: certain acceptances; namb: the band around tau
+            const bool amb = fabsf(x - a.tau_f) <= tau_band;
+            acc += x < a.tau_f && !amb;
+            namb += amb;
         }
     }
     acc = wsum(acc);

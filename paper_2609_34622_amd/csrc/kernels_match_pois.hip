@@ -226,8 +226,10 @@ __global__ __launch_bounds__(kPoisThreads) void k_match_pois(MatchArgs a, int km
                     float bx;
                     float x = score(c, &bx);
                     if (!(fabsf(x) <= FLT_MAX)) x = FLT_MAX;  // never selected
-                    acc += x < tau_f ? 1 : 0;
-                    namb += fabsf(x - tau_f) <= bx + tau_eps ? 1 : 0;
+                    // acc: certain acceptances; namb: the band around tau
+                    const bool amb = fabsf(x - tau_f) <= bx + tau_eps;
+                    acc += x < tau_f && !amb ? 1 : 0;
+                    namb += amb ? 1 : 0;
                     bmax = fmaxf(bmax, bx);
 #pragma unroll
                     for (int m = NS - 1; m >= 1; --m) s[m] = fminf(s[m], fmaxf(s[m - 1], x));

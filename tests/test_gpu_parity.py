@@ -547,6 +547,59 @@ def test_float_match_lists_identical(case):
     assert np.array_equal(mg[0], mo)
 
 
+# ------------------------------------ acceptance at tau: FP32 below, FP64 not
+
+TAU_EDGE = [
+    # shape, patch, step, search, target origin, two exact copies, near copy
+    ((2048,), (32,), (4,), (256,), (1000,), [(40,), (-72,)], (80,)),
+    ((48, 48), (8, 8), (3, 3), (31, 31), (20, 20), [(0, 9), (9, 0)], (9, 9)),
+]
+
+
+@pytest.mark.parametrize("case", TAU_EDGE, ids=lambda c: "x".join(map(str, c[0])))
+def test_float_match_tau_band_both_sides(case):
+    """Two exact copies of a reference patch and a near copy whose exact
+    score equals tau: FP32 rounds that score below tau (its six small squares
+    follow the unit term and are each lost), FP64 does not accept it.  The
+    exact count is 2 (group size 2); counting the near copy would give 4."""
+    shape, patch, step, search, target, copies, near = case
+    _say(f"tau band both sides {shape}")
+    tau = 1.0 + 6 * 2.0 ** -26  # the near copy's exact score
+    assert np.float32(tau) > np.float32(1.0)
+    p = params_for(shape, patch, step, search, group=(16, 16))
+    sp = p.wiener
+    sp.tau = tau
+    geom = B.geometry(shape)
+    refs = np.asarray(B.bmnd_reference_origins(geom, sp))
+    # the reference origin nearest the target whose copies stay inside
+    offs = np.array(copies + [near] + [(0,) * len(shape)])
+    coords = np.stack(np.unravel_index(refs, shape), axis=1)
+    fits = np.all((coords[:, None, :] + offs[None]) >= 0, axis=(1, 2)) & \
+        np.all((coords[:, None, :] + offs[None] + np.array(patch)) <= np.array(shape), axis=(1, 2))
+    dist = np.where(fits, np.abs(coords - np.array(target)).sum(axis=1), 1 << 30)
+    idx = int(np.argmin(dist))
+    r0 = tuple(int(v) for v in coords[idx])
+    rng = np.random.default_rng(71)
+    # multiples of 2^-10 in [0, 3): every difference below is exact in FP32
+    src = (np.floor(rng.uniform(0.0, 3.0, shape) * 1024.0) / 1024.0).astype(np.float32)
+    sl = lambda o: tuple(slice(r + d, r + d + j) for r, d, j in zip(r0, o, patch))
+    ref = src[sl((0,) * len(shape))].astype(np.float64).copy()
+    for o in copies:
+        src[sl(o)] = ref
+    d = np.zeros(patch)
+    d[(0,) * len(shape)] = 1.0
+    d.reshape(-1)[1:7] = 2.0 ** -13
+    src[sl(near)] = (ref + d).astype(np.float32)
+    assert np.array_equal(src[sl(near)].astype(np.float64) - ref, d)
+    ht, wie = oracle_stages(shape, patch, step, search, 0.02, group=(16, 16))
+    wie.tau = tau
+    mg, cg = gpu_match(B.STAGE_WIENER, dev(src), geom, B.poisson(0.02), sp, refs)
+    mo, co, _, _ = O.match(wie, O.STAGE_WIENER, src, src, refs)
+    assert co[idx] == 2
+    assert np.array_equal(cg[0], co)
+    assert np.array_equal(mg[0], mo)
+
+
 # ------------------------------------------- count-mode matching: exact lists
 
 COUNT_MATCH_1D = [
