@@ -520,6 +520,10 @@ void k_match_1d_f(MatchArgs a, int cap_span)
             int s[NS];
 #pragma unroll
             for (int m = 0; m < NS; ++m) s[m] = INT_MAX;
+            // INT_MAX held in a scalar register: the key select takes it as
+            // an operand instead of building the constant per candidate
+            int kEmpty;
+            asm volatile("s_mov_b32 %0, 0x7fffffff" : "=s"(kEmpty));
             int acc = 0, nrec = 0, namb = 0;
             // FP32 round-off band around a value (relative to the score's
             // terms; the Gaussian bias is one of them)
@@ -556,11 +560,14 @@ void k_match_1d_f(MatchArgs a, int cap_span)
             // one candidate: counts, record, insertion network
             auto take = [&](int d, float x, int rec_key) __attribute__((always_inline)) {
                 const bool valid = d >= dlo && d <= dhi && d != 0 && fabsf(x) <= FLT_MAX;
+                // plain SSD scores are never negative: their order is that of
+                // their bit patterns (the same key, fewer instructions)
+                const int ord = MODE == kPlain ? __float_as_int(x) : ord_of(x);
                 // acc: certain acceptances; namb: the band around tau
                 const bool amb = valid && fabsf(x - a.tau_f) <= tau_band;
                 acc += (valid && x < a.tau_f && !amb) ? 1 : 0;
                 namb += amb ? 1 : 0;
-                const int key = valid ? ((ord_of(x) & ~255) | (d - wlo)) : INT_MAX;
+                const int key = valid ? ((ord & ~255) | (d - wlo)) : kEmpty;
                 if (key <= rec_key) {
                     if (nrec < kRec) rec[nrec][lane] = (unsigned char)(d - wlo);
                     ++nrec;
