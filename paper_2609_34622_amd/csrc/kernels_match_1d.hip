@@ -504,9 +504,13 @@ void k_match_1d_f(MatchArgs a, int cap_span)
         const bool mine = pending && r >= r0 && (r - r0) <= cap_span;
         const int base = r0 + wlo;
         const int len = cap_span + W + 2 * kJ;
+        // positions outside the array are staged as NaN: a candidate reaching
+        // them scores NaN and fails the finiteness test, so the shared paths
+        // need no window bounds per candidate (a reference's sum only reads
+        // its candidate's samples)
         for (int i = lane; i < len; i += kWave) {
             const int pos = base + i;
-            sx[i] = (pos >= 0 && pos < L) ? __float_as_int(src[pos]) : 0;
+            sx[i] = (pos >= 0 && pos < L) ? __float_as_int(src[pos]) : 0x7FC00000;
         }
         __syncthreads();
 
@@ -559,7 +563,7 @@ void k_match_1d_f(MatchArgs a, int cap_span)
             };
             // one candidate: counts, record, insertion network
             auto take = [&](int d, float x, int rec_key) __attribute__((always_inline)) {
-                const bool valid = d >= dlo && d <= dhi && d != 0 && fabsf(x) <= FLT_MAX;
+                const bool valid = d != 0 && fabsf(x) <= FLT_MAX;
                 // plain SSD scores are never negative: their order is that of
                 // their bit patterns (the same key, fewer instructions)
                 const int ord = MODE == kPlain ? __float_as_int(x) : ord_of(x);
