@@ -253,6 +253,29 @@ def test_denoise_1d_batch():
         assert rel_err(out[b], out_r) < REL_OUT, b
 
 
+def test_full_size_ecg_batch_sampled():
+    """The ECG batch at its full size (256 signals of 65536 samples, patch 32,
+    step 4, search 256, groups of 16, seed 2000) in one bmnd_denoise launch,
+    the launch configuration the benchmark times (the largest runs of
+    references per wavefront); the oracle denoises three of the signals one
+    by one."""
+    n, L = 256, 65536
+    _say(f"full-size ECG batch {n} x {L}")
+    s = synth.ecg_batch(n_signals=n, length=L, seed=2000)
+    shape, patch, step, search = (L,), (32,), (4,), (256,)
+    p = params_for(shape, patch, step, search, group=(16, 16))
+    geom = B.geometry(shape, batch=n)
+    out, pilot = gpu_denoise(dev(s.y), geom, B.poisson(s.s_p), p)
+    assert np.all(np.isfinite(out)) and np.all(np.isfinite(pilot))
+    ht, wie = oracle_stages(shape, patch, step, search, s.s_p, group=(16, 16))
+    for b in (0, 131, n - 1):
+        _say(f"  oracle on signal {b}")
+        pil_o, _ = O.denoise(ht, wie, s.y[b])
+        assert rel_err(pilot[b], pil_o) < REL_OUT, b
+        out_r = O.run_stage(wie, O.STAGE_WIENER, s.y[b], pilot[b].astype(np.float64))
+        assert rel_err(out[b], out_r) < REL_OUT, b
+
+
 # ------------------------------------------------------- 3-D with mass cons.
 
 def test_denoise_3d_mass_conservation():
