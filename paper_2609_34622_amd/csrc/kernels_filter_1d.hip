@@ -38,7 +38,7 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kJ = 32;        // patch length
 constexpr int kWaves = 4;     // wavefronts per workgroup
-constexpr int kSubMax = 48;   // references per wavefront (a contiguous run), at most
+constexpr int kSubMax = 48;   // references per wavefront with a staged pilot, at most
 constexpr int kTargetWaves = 16384;  // enough wavefronts to fill the device
 constexpr int kZs = 36;       // row stride (floats) of the transpose buffer
 constexpr float kRsqrt2 = 0.70710678118654752440f;
@@ -947,11 +947,11 @@ hipError_t launch_filter_1d(const FilterArgs& a, int step_last, hipStream_t s)
     int tile_cap = 0, tile_back = 0, wcap = 0;
     const bool one_d = g.L[0] == 1 && g.L[1] == 1 && g.L[2] == 1;
     const int nstage = a.shrink == BMND_SHRINK_WIENER ? 2 : 1;  // staged arrays
-    // references per wavefront: up to kSubMax (two thirds of it with a
-    // staged pilot, so that three workgroups share a compute unit's LDS),
-    // fewer for small arrays so that the launch still fills the device
+    // references per wavefront: up to 64 (48 with a staged pilot), the most
+    // for which three workgroups share a compute unit's LDS with a 256-offset
+    // window; fewer for small arrays so that the launch still fills the device
     const long groups = long(a.n_refs) * g.batch;
-    const int sub_max = nstage == 2 ? 2 * kSubMax / 3 : kSubMax;
+    const int sub_max = nstage == 2 ? kSubMax : 4 * kSubMax / 3;
     const int sub = int(std::max(1L, std::min<long>(sub_max, groups / kTargetWaves)));
     const int chunk = sub * kWaves;
     if (one_d) {
