@@ -386,6 +386,10 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     float* psm = ysm + tile_cap;
     const bool poisson = a.noise == BMND_NOISE_POISSON;
     const int omax = last_origin(g);
+    // lanes past a group's K gather (and add zeros) at the wavefront's first
+    // reference origin (slot 0 of its first group), which lies inside the
+    // chunk's staged range and the wavefront's tile
+    const int fall = safe_origin(w0g < w1g ? a.match[(long(b) * a.n_refs + w0g) * a.gmax] : tile_lo, omax);
     const bool acc_tile = wcap > 0 && a.out_mode == 1;
     const float* yb = a.y + vb;
     const float* pb = a.pilot ? a.pilot + vb : nullptr;
@@ -418,9 +422,8 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         f.K = __builtin_amdgcn_readfirstlane(safe_count(kraw, a.gmax));
         f.lk = 31 - __clz(f.K);
         const bool av = m16 < f.K;  // this lane's member in the A layout
-        // lanes past K read the samples at a valid origin inside the staged
-        // range (tile_lo <= the chunk's first reference) and drop them
-        f.oa = av ? safe_origin(mraw, omax) : safe_origin(tile_lo, omax);
+        // lanes past K read the samples at the fallback origin and drop them
+        f.oa = av ? safe_origin(mraw, omax) : fall;
         float x[8], pv[8], mv[8];
         f.ok = true;
         if (lds) {
@@ -803,11 +806,10 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                 wd[r] = wuni ? wA : __shfl(wA, 4 * lg + r);
             }
             // every member of the group inside the accumulation tile (members
-            // past K add zeros at the tile's start instead)
+            // past K sit at the fallback origin and add zeros)
             bool in_tile = acc_tile;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                in_tile = in_tile & ((4 * lg + r >= K) | ((od[r] - wlo >= 0) & (od[r] - wlo + kJ <= wcap)));
+            for (int r = 0; r < 4; ++r) in_tile = in_tile & (unsigned(od[r] - wlo) <= unsigned(wcap - kJ));
             if (a.out_mode == 0) {
                 float* pout = a.patches + grp * long(a.gmax) * kJ;
 #pragma unroll
@@ -821,7 +823,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                 if (lane < a.gmax) a.weights[grp * a.gmax + lane] = lane < K ? wA : 0.f;
             } else if (a.out_mode == 1 && __all(in_tile)) {
                 // every member inside this wavefront's tile (members past K add
-                // zeros at the tile's start instead).  Numerators: lane groups
+                // zeros at the fallback origin).  Numerators: lane groups
                 // 0 and 2 update the first copy, 1 and 3 the second, and the
                 // pairs (0, 1) and (2, 3) take turns, so no instruction updates
                 // a sample twice.  LDS requests of a wavefront are served in
@@ -834,7 +836,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const bool lv = 4 * lg + r < K;
-                    tl[r] = (lv ? od[r] - wlo : 0) + m16 + ((lg & 1) ? wcap : 0);
+                    tl[r] = od[r] - wlo + m16 + ((lg & 1) ? wcap : 0);
 #pragma unroll
                     for (int c = 0; c < 2; ++c) add[r][c] = lv ? wd[r] * wq[c] * o[c][r] : 0.f;
                 }
