@@ -413,12 +413,14 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         // other stages: orthonormal coefficients and their variances
         f4 Y[2], V[2], G[2];
         float uy, uv, up;  // split unscales (powers of two)
+        float rp;          // 1 / up (exact: the product of the forward scales)
         float gn;   // norm of the group's samples
         int K, lk, oa;
         bool ok;    // every lane's samples came from the staged range
     };
     auto front = [&](int kraw, int mraw, bool lds) __attribute__((always_inline)) -> Front {
         Front f;
+        f.rp = 1.f;
         f.K = __builtin_amdgcn_readfirstlane(safe_count(kraw, a.gmax));
         f.lk = 31 - __clz(f.K);
         const bool av = m16 < f.K;  // this lane's member in the A layout
@@ -460,7 +462,9 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         float gp = 0.f;
         if constexpr (wiener) {
             gp = fsqrt(wave_sum(gp2));
-            split8(pv, split_scale(gp, &ip), ph, pl);
+            const float scp = split_scale(gp, &ip);
+            split8(pv, scp, ph, pl);
+            f.rp = osc[0] * scp;
         }
         // variance map s_P [src]_+ (Poisson) or sigma^2, scaled while formed.
         // Poisson with no negative source sample in the group (always so
@@ -546,8 +550,9 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             // (up, uv powers of two).  C is kept pre-multiplied by D, as the
             // inverse butterflies need it: C D = at Yb uy D^2.
             const float dq = haar_norm0(lg, lk);
-            const float kA = a.power_a * (F.uv / (F.up * F.up));
-            const float kS = a.s_v * (F.uv / (F.up * F.up));
+            const float kuv = F.uv * (F.rp * F.rp);  // uv / up^2, no division
+            const float kA = a.power_a * kuv;
+            const float kS = a.s_v * kuv;
             const f4 d2 = {dq * dq, 0.5f, 0.25f, 0.5f};
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
