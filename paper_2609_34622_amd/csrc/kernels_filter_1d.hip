@@ -303,6 +303,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     constexpr bool wiener = SH == BMND_SHRINK_WIENER;
     __shared__ __align__(16) _Float16 ops[3 * 2 * 2 * kWave * 8];
     __shared__ unsigned omax_[3];  // bit patterns of max |T|, |T o T|, |U|
+    __shared__ unsigned negs_;     // some staged variance-map source is negative
     __shared__ __align__(16) float ztr_[kWaves][16 * kZs];
     __shared__ float rl_[kWaves][16];
     // per wavefront its accumulation tile: two [wcap] numerator copies and
@@ -322,6 +323,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     // U[i][q] at q (or i) = 16c + m16 and depth i (or q) = 8lg + s, split
     // into halves at a power-of-two scale per matrix
     if (threadIdx.x < 3) omax_[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) negs_ = 0u;
     __syncthreads();
     {
         float mt = 0.f, mu = 0.f;
@@ -394,14 +396,27 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     const float* yb = a.y + vb;
     const float* pb = a.pilot ? a.pilot + vb : nullptr;
     // 1-D arrays: the samples around the chunk's references, staged once
-    for (int i = threadIdx.x; i < tile_cap; i += kWave * kWaves) {
-        const int u = tile_lo + i;
-        const bool inb = u >= 0 && u < g.V;
-        ysm[i] = inb ? yb[u] : 0.f;
-        if constexpr (wiener) psm[i] = inb ? pb[u] : 0.f;
+    {
+        bool neg = false;
+        for (int i = threadIdx.x; i < tile_cap; i += kWave * kWaves) {
+            const int u = tile_lo + i;
+            const bool inb = u >= 0 && u < g.V;
+            const float yv = inb ? yb[u] : 0.f;
+            ysm[i] = yv;
+            float src = yv;
+            if constexpr (wiener) {
+                src = inb ? pb[u] : 0.f;
+                psm[i] = src;
+            }
+            neg = neg || src < 0.f;
+        }
+        if (neg) atomicOr(&negs_, 1u);
     }
     for (int i = lane; i < 3 * wcap; i += kWave) tnum[i] = 0.f;
     __syncthreads();
+    // Poisson: no negative source sample in the staged range, so the groups
+    // read from it need no test of their own
+    const bool staged_nonneg = poisson && __builtin_amdgcn_readfirstlane(negs_) == 0u;
 
     // ---- front end of one group: its size and origin, the gather of its
     // samples (and pilot) and the forward products on the matrix cores.
@@ -470,8 +485,8 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         // Poisson with no negative source sample in the group (always so
         // for counts): the map is s_P src, whose split is the source's own
         // with s_P in the unscale.
-        bool nonneg = false;
-        if (poisson) {
+        bool nonneg = lds && staged_nonneg;
+        if (poisson && !nonneg) {
             float mn = 0.f;
 #pragma unroll
             for (int s = 0; s < 8; ++s) mn = fminf(mn, wiener ? pv[s] : x[s]);
