@@ -304,6 +304,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     __shared__ __align__(16) _Float16 ops[3 * 2 * 2 * kWave * 8];
     __shared__ unsigned omax_[3];  // bit patterns of max |T|, |T o T|, |U|
     __shared__ unsigned negs_;     // some staged variance-map source is negative
+    __shared__ unsigned smax_[2];  // bit patterns of the largest staged |y|, |pilot|
     __shared__ __align__(16) float ztr_[kWaves][16 * kZs];
     __shared__ float rl_[kWaves][16];
     // per wavefront its accumulation tile: two [wcap] numerator copies and
@@ -324,6 +325,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     // into halves at a power-of-two scale per matrix
     if (threadIdx.x < 3) omax_[threadIdx.x] = 0u;
     if (threadIdx.x == 0) negs_ = 0u;
+    if (threadIdx.x < 2) smax_[threadIdx.x] = 0u;
     __syncthreads();
     {
         float mt = 0.f, mu = 0.f;
@@ -398,6 +400,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     // 1-D arrays: the samples around the chunk's references, staged once
     {
         bool neg = false;
+        float my = 0.f, mp = 0.f;
         for (int i = threadIdx.x; i < tile_cap; i += kWave * kWaves) {
             const int u = tile_lo + i;
             const bool inb = u >= 0 && u < g.V;
@@ -407,16 +410,29 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             if constexpr (wiener) {
                 src = inb ? pb[u] : 0.f;
                 psm[i] = src;
+                my = fmaxf(my, fabsf(yv));
+                mp = fmaxf(mp, fabsf(src));
             }
             neg = neg || src < 0.f;
         }
         if (neg) atomicOr(&negs_, 1u);
+        if constexpr (wiener) {
+            // non-negative floats order as their bit patterns
+            atomicMax(&smax_[0], __float_as_uint(my));
+            atomicMax(&smax_[1], __float_as_uint(mp));
+        }
     }
     for (int i = lane; i < 3 * wcap; i += kWave) tnum[i] = 0.f;
     __syncthreads();
     // Poisson: no negative source sample in the staged range, so the groups
     // read from it need no test of their own
     const bool staged_nonneg = poisson && __builtin_amdgcn_readfirstlane(negs_) == 0u;
+    // the Wiener stage bounds the split scales of groups read from the staged
+    // range by its largest magnitudes instead of the group norms (a split
+    // keeps 22 bits of every value above 2^-17 of its bound; the
+    // hard-threshold stage keeps the group norm, its error band needs it)
+    const float ymax = __uint_as_float(__builtin_amdgcn_readfirstlane(smax_[0]));
+    const float pmax = __uint_as_float(__builtin_amdgcn_readfirstlane(smax_[1]));
 
     // ---- front end of one group: its size and origin, the gather of its
     // samples (and pilot) and the forward products on the matrix cores.
@@ -461,22 +477,31 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                 pv[s] = wiener ? pb[f.oa + 8 * lg + s] : 0.f;
             }
         }
-        float gn2 = 0.f, gp2 = 0.f;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             x[s] = av ? x[s] : 0.f;
             pv[s] = av ? pv[s] : 0.f;
-            gn2 = __builtin_fmaf(x[s], x[s], gn2);
-            if constexpr (wiener) gp2 = __builtin_fmaf(pv[s], pv[s], gp2);
         }
-        f.gn = fsqrt(wave_sum(gn2));
-        // split operands; the group norms bound every entry
+        // split operands; the group norms (or the staged maxima) bound every
+        // entry
+        float gp = 0.f;
+        if (wiener && lds) {
+            f.gn = ymax;
+            gp = pmax;
+        } else {
+            float gn2 = 0.f, gp2 = 0.f;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                gn2 = __builtin_fmaf(x[s], x[s], gn2);
+                if constexpr (wiener) gp2 = __builtin_fmaf(pv[s], pv[s], gp2);
+            }
+            f.gn = fsqrt(wave_sum(gn2));
+            if constexpr (wiener) gp = fsqrt(wave_sum(gp2));
+        }
         h8 xh, xl, mh, ml, ph, pl;
         float ix, ip = 1.f, im;
         split8(x, split_scale(f.gn, &ix), xh, xl);
-        float gp = 0.f;
         if constexpr (wiener) {
-            gp = fsqrt(wave_sum(gp2));
             const float scp = split_scale(gp, &ip);
             split8(pv, scp, ph, pl);
             f.rp = osc[0] * scp;
