@@ -534,6 +534,9 @@ void k_match_1d_f(MatchArgs a, int cap_span)
             const float bmag = MODE == kGauss ? fabsf(a.bias) : 0.f;
             const float band = float(kTieBand);
             const float tau_band = band * (fabsf(a.tau_f) + bmag);
+            // the band around tau is [tau_lo, tau_hi]: below it a score is
+            // accepted, above it rejected, inside it decided in FP64
+            const float tau_lo = a.tau_f - tau_band, tau_hi = a.tau_f + tau_band;
             auto score = [&](int c) {
                 float x = 0.f;
                 if (SHARE && share) {
@@ -567,10 +570,10 @@ void k_match_1d_f(MatchArgs a, int cap_span)
                 // plain SSD scores are never negative: their order is that of
                 // their bit patterns (the same key, fewer instructions)
                 const int ord = MODE == kPlain ? __float_as_int(x) : ord_of(x);
-                // acc: certain acceptances; namb: the band around tau
-                const bool amb = valid && fabsf(x - a.tau_f) <= tau_band;
-                acc += (valid && x < a.tau_f && !amb) ? 1 : 0;
-                namb += amb ? 1 : 0;
+                // acc: certain acceptances; namb (less acc at the end): up to
+                // the band's top
+                acc += (valid && x < tau_lo) ? 1 : 0;
+                namb += (valid && x <= tau_hi) ? 1 : 0;
                 const int key = valid ? ((ord & ~255) | (d - wlo)) : kEmpty;
                 if (key <= rec_key) {
                     if (nrec < kRec) rec[nrec][lane] = (unsigned char)(d - wlo);
@@ -658,9 +661,8 @@ void k_match_1d_f(MatchArgs a, int cap_span)
                     // offsets outside the clipped window, the reference itself
                     // and non-finite scores are never counted or selected
                     const bool valid = d >= dlo && d <= dhi && d != 0 && fabsf(x) <= FLT_MAX;
-                    const bool amb = valid && fabsf(x - a.tau_f) <= tau_band;
-                    acc += (valid && x < a.tau_f && !amb) ? 1 : 0;
-                    namb += amb ? 1 : 0;
+                    acc += (valid && x < tau_lo) ? 1 : 0;
+                    namb += (valid && x <= tau_hi) ? 1 : 0;
                     const int key = valid ? ((ord_of(x) & ~255) | (d - wlo)) : INT_MAX;
                     if (key <= rec_key) {
                         if (nrec < kRec) rec[nrec][lane] = (unsigned char)(d - wlo);
@@ -678,13 +680,14 @@ void k_match_1d_f(MatchArgs a, int cap_span)
             int K = group_size_of(a, acc, ncand);
             // scores within the band of tau are accepted or not in FP64, when
             // that can change the group size
+            namb -= acc;
             if (namb > 0 && group_size_of(a, acc + namb, ncand) != K) {
                 acc = 0;
                 for (int d = dlo; d <= dhi; ++d) {
                     if (d == 0) continue;
                     const float x = score(rl + d);
                     if (!(fabsf(x) <= FLT_MAX)) continue;
-                    if (fabsf(x - a.tau_f) <= tau_band)
+                    if (x >= tau_lo && x <= tau_hi)
                         acc += score64_lds<MODE>(a, rp, sx, rl + d) < a.tau_d ? 1 : 0;
                     else
                         acc += x < a.tau_f ? 1 : 0;
