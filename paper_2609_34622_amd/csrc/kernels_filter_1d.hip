@@ -78,9 +78,13 @@ __device__ __forceinline__ float pow_rsqrt2(int e)
 
 // (value at the even lane group, value at the odd one) of the lane-group
 // pair (0, 1) or (2, 3) this lane belongs to
+// (the swap overwrites both of its operands: an opaque second copy lets the
+// value itself be the other one, one register move instead of two)
 __device__ __forceinline__ void pair16(float v, float& a, float& b)
 {
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    float w = v;
+    asm("" : "+v"(w));
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(w), false, false);
     a = __uint_as_float(r[0]);
     b = __uint_as_float(r[1]);
 }
@@ -89,7 +93,9 @@ __device__ __forceinline__ void pair16(float v, float& a, float& b)
 // (0, 2) or (1, 3) this lane belongs to
 __device__ __forceinline__ void pair32(float v, float& a, float& b)
 {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    float w = v;
+    asm("" : "+v"(w));
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(w), false, false);
     a = __uint_as_float(r[0]);
     b = __uint_as_float(r[1]);
 }
@@ -105,39 +111,42 @@ __device__ __forceinline__ float level3(float v, float s3)
     return __builtin_fmaf(s3, b, a);
 }
 
-__device__ __forceinline__ float level4(float v, float s4, bool odd)
+// Level 4 as cA a + sB b: lane groups 0 and 2 take a +- b; 1 and 3 keep
+// their own value, which is a in lane group 1 and b in 3 (cA = 1, sB = 0
+// and cA = 0, sB = 1), so the value before the swap is not needed after it
+__device__ __forceinline__ float level4(float v, float sB, float cA)
 {
     float a, b;
     pair32(v, a, b);
-    return odd ? v : __builtin_fmaf(s4, b, a);
+    return __builtin_fmaf(sB, b, a * cA);
 }
 
 // Forward butterflies over all 16 member slots.  Slots past K hold zeros,
 // and a level that pairs a block with an all-zero block leaves the valid
 // positions unchanged, so the four levels serve every K = 2^lk; only the
 // normalisation of position 0 depends on K.
-__device__ __forceinline__ f4 haar_fwd(f4 v, float s3, float s4, bool odd)
+__device__ __forceinline__ f4 haar_fwd(f4 v, float s3, float sB, float cA)
 {
     const float a0 = v[0] + v[1], a1 = v[0] - v[1];
     const float a2 = v[2] + v[3], a3 = v[2] - v[3];
     const float b0 = a0 + a2, b2 = a0 - a2;
-    return f4{level4(level3(b0, s3), s4, odd), a1, b2, a3};
+    return f4{level4(level3(b0, s3), sB, cA), a1, b2, a3};
 }
 
 // the squared Haar rows on non-negative values: every row keeps the sum of
 // its support (the detail positions included)
-__device__ __forceinline__ f4 haar_fwd_sq(f4 v, bool odd)
+__device__ __forceinline__ f4 haar_fwd_sq(f4 v, float sBq, float cA)
 {
     const float a0 = v[0] + v[1], a2 = v[2] + v[3];
     const float b0 = a0 + a2;
-    return f4{level4(level3(b0, 1.f), 1.f, odd), a0, b0, a2};
+    return f4{level4(level3(b0, 1.f), sBq, cA), a0, b0, a2};
 }
 
 // inverse butterflies (levels in the reverse order); positions past K must
 // hold zeros
-__device__ __forceinline__ f4 haar_inv(f4 v, float s3, float s4, bool odd)
+__device__ __forceinline__ f4 haar_inv(f4 v, float s3, float sB, float cA)
 {
-    const float c0 = level3(level4(v[0], s4, odd), s3);
+    const float c0 = level3(level4(v[0], sB, cA), s3);
     const float b0 = c0 + v[2], b2 = c0 - v[2];
     return f4{b0 + v[1], b0 - v[1], b2 + v[3], b2 - v[3]};
 }
@@ -370,8 +379,11 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     const double* T64 = a.t.f64 + a.t.T64[kAx - 1];
     // signs of the cross-lane Haar levels and the lane groups that keep
     // their level-3 value at level 4
-    const float s3 = (lg & 1) ? -1.f : 1.f, s4 = (lg & 2) ? -1.f : 1.f;
-    const bool odd = (lg & 1) != 0;
+    const float s3 = (lg & 1) ? -1.f : 1.f;
+    // level 4 as cA a + sB b (sBq: the squared rows, all signs +)
+    const float sB = lg == 0 ? 1.f : (lg == 1 ? 0.f : (lg == 2 ? -1.f : 1.f));
+    const float sBq = lg == 1 ? 0.f : 1.f;
+    const float cA = lg == 3 ? 0.f : 1.f;
 
     const int nchunk = (a.n_refs + chunk - 1) / chunk;
     const int b = blockIdx.x / nchunk;
@@ -544,11 +556,11 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             const h8 th = opnd_h(ops, 0, 0, c, lane), tl = opnd_h(ops, 0, 1, c, lane);
             const f4 y1 = mul3(xh, xl, th, tl);
             const f4 v1 = mul3(mh, ml, opnd_h(ops, 1, 0, c, lane), opnd_h(ops, 1, 1, c, lane));
-            f.Y[c] = haar_fwd(y1, s3, s4, odd);
-            f.V[c] = haar_fwd_sq(v1, odd);
+            f.Y[c] = haar_fwd(y1, s3, sB, cA);
+            f.V[c] = haar_fwd_sq(v1, sBq, cA);
             f.G[c] = f4{0.f, 0.f, 0.f, 0.f};
             if constexpr (wiener) {
-                f.G[c] = haar_fwd(mul3(ph, pl, th, tl), s3, s4, odd);
+                f.G[c] = haar_fwd(mul3(ph, pl, th, tl), s3, sB, cA);
             } else {
                 f.Y[c] = f.Y[c] * ny;
                 f.V[c] = f.V[c] * nv;
@@ -739,7 +751,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             f4 Z[2];
 #pragma unroll
             for (int c = 0; c < 2; ++c)
-                Z[c] = haar_inv(f4{C[c][0], C[c][1], C[c][2], C[c][3]} * nz, s3, s4, odd);
+                Z[c] = haar_inv(f4{C[c][0], C[c][1], C[c][2], C[c][3]} * nz, s3, sB, cA);
             float wA;  // weight of member m16
             if constexpr (WPLAIN) {
                 // classic model, group scope: R = sum of a_t^2 over the group
