@@ -317,8 +317,8 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     __shared__ __align__(16) float ztr_[kWaves][16 * kZs];
     __shared__ float rl_[kWaves][16];
     // per wavefront its accumulation tile: two [wcap] numerator copies and
-    // [wcap] member weights by origin; then [tile_cap] staged samples and
-    // [tile_cap] staged pilot
+    // [wcap] member weights by origin; then 8 zeros and [tile_cap] staged
+    // samples, 8 zeros and [tile_cap] staged pilot
     extern __shared__ __align__(16) float tile[];
 
     const Geo& g = a.g;
@@ -398,8 +398,9 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     const int wlo = (wcap > 0 && w0g < w1g) ? a.match[(long(b) * a.n_refs + w0g) * a.gmax] - tile_back : 0;
     float* tnum = tile + wave * 3 * wcap;  // copies [0, wcap) and [wcap, 2 wcap)
     float* twt = tnum + 2 * wcap;
-    float* ysm = tile + kWaves * 3 * wcap;
-    float* psm = ysm + tile_cap;
+    // each staged array follows 8 zeros, which lanes past a group's K read
+    float* ysm = tile + kWaves * 3 * wcap + 8;
+    float* psm = ysm + tile_cap + 8;
     const bool poisson = a.noise == BMND_NOISE_POISSON;
     const int omax = last_origin(g);
     // lanes past a group's K gather (and add zeros) at the wavefront's first
@@ -435,6 +436,10 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         }
     }
     for (int i = lane; i < 3 * wcap; i += kWave) tnum[i] = 0.f;
+    if (threadIdx.x < 8) {
+        ysm[int(threadIdx.x) - 8] = 0.f;
+        if constexpr (wiener) psm[int(threadIdx.x) - 8] = 0.f;
+    }
     __syncthreads();
     // Poisson: no negative source sample in the staged range, so the groups
     // read from it need no test of their own
@@ -474,9 +479,10 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         if (lds) {
             // clamped reads keep the block branch-free; a group reaching
             // outside the staged range is redone from global memory
+            // (lanes past K read the zeros before the arrays)
             const int ol = f.oa - tile_lo + 8 * lg;
-            f.ok = __all(ol >= 0 && ol + 8 <= tile_cap);
-            const int olc = max(min(ol, tile_cap - 8), 0);
+            f.ok = __all(!av || (ol >= 0 && ol + 8 <= tile_cap));
+            const int olc = av ? max(min(ol, tile_cap - 8), 0) : -8;
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 x[s] = ysm[olc + s];
@@ -485,14 +491,9 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
         } else {
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                x[s] = yb[f.oa + 8 * lg + s];
-                pv[s] = wiener ? pb[f.oa + 8 * lg + s] : 0.f;
+                x[s] = av ? yb[f.oa + 8 * lg + s] : 0.f;
+                pv[s] = wiener && av ? pb[f.oa + 8 * lg + s] : 0.f;
             }
-        }
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            x[s] = av ? x[s] : 0.f;
-            pv[s] = av ? pv[s] : 0.f;
         }
         // split operands; the group norms (or the staged maxima) bound every
         // entry
@@ -1018,12 +1019,12 @@ hipError_t launch_filter_1d(const FilterArgs& a, int step_last, hipStream_t s)
         tile_back = g.W[kAx - 1] / 2;
         tile_cap = (chunk - 1) * st + g.W[kAx - 1] + kJ;
         if (a.out_mode == 1) wcap = (sub - 1) * st + g.W[kAx - 1] + kJ;
-        if (kWaves * 3 * wcap + nstage * tile_cap > kDynFloats) wcap = 0;
-        tile_cap = min(tile_cap, kDynFloats / nstage);
+        if (kWaves * 3 * wcap + nstage * (tile_cap + 8) > kDynFloats) wcap = 0;
+        tile_cap = min(tile_cap, kDynFloats / nstage - 8);
     }
     const int nchunk = (a.n_refs + chunk - 1) / chunk;
     const dim3 grid(unsigned(long(nchunk) * g.batch));
-    const size_t lds = sizeof(float) * size_t(kWaves * 3 * wcap + nstage * tile_cap);
+    const size_t lds = sizeof(float) * size_t(kWaves * 3 * wcap + nstage * (tile_cap + 8));
     const bool staged = tile_cap >= 8;
     const bool wplain = a.wmodel == BMND_WEIGHT_CLASSIC && a.wscope == BMND_SCOPE_GROUP &&
                         a.wdomain == BMND_WDOMAIN_COEFFICIENT;
