@@ -833,8 +833,11 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             wsync();
             float za[8];
             {
-                const float4 u0 = *reinterpret_cast<const float4*>(ztr + m16 * kZs + 8 * lg);
-                const float4 u1 = *reinterpret_cast<const float4*>(ztr + m16 * kZs + 8 * lg + 4);
+                // members past K read the zeros before the staged samples, so
+                // their synthesized samples are 0
+                const float* zs = m16 < K ? ztr + m16 * kZs + 8 * lg : ysm - 8;
+                const float4 u0 = *reinterpret_cast<const float4*>(zs);
+                const float4 u1 = *reinterpret_cast<const float4*>(zs + 4);
                 za[0] = u0.x; za[1] = u0.y; za[2] = u0.z; za[3] = u0.w;
                 za[4] = u1.x; za[5] = u1.y; za[6] = u1.z; za[7] = u1.w;
             }
@@ -893,10 +896,9 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                 int tl[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const bool lv = 4 * lg + r < K;
                     tl[r] = od[r] - wlo + m16 + ((lg & 1) ? wcap : 0);
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) add[r][c] = lv ? wd[r] * wq[c] * o[c][r] : 0.f;
+                    for (int c = 0; c < 2; ++c) add[r][c] = wd[r] * wq[c] * o[c][r];
                 }
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
