@@ -607,6 +607,11 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
             const float kA = a.power_a * kuv;
             const float kS = a.s_v * kuv;
             const f4 d2 = {dq * dq, 0.5f, 0.25f, 0.5f};
+            // 1 at Haar positions below K, 0 past it (the Wiener gain is 0
+            // there, which zeroes C and the weight terms)
+            float lvf[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lvf[r] = 4 * lg + r < F.K ? 1.f : 0.f;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
 #pragma unroll
@@ -620,7 +625,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                         at = Yv != 0.f ? m * frcp(fabsf(Yv)) : 0.f;
                     } else if constexpr (SH == BMND_SHRINK_WIENER) {
                         const float gam = F.G[c][r];
-                        shat = relu(__builtin_fmaf(-kA, v, gam * gam));
+                        shat = relu(__builtin_fmaf(-kA, v, gam * gam)) * lvf[r];
                         const float den = __builtin_fmaf(kS, v, shat);
                         at = den > 0.f ? shat * frcp(den) : 0.f;
                         Cv = at * Yv * (F.uy * d2[r]);
@@ -631,7 +636,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                     }
                     // positions past K carry no coefficient (the inverse
                     // butterflies need zeros there)
-                    C[c][r] = 4 * lg + r < F.K ? Cv : 0.f;
+                    C[c][r] = SH == BMND_SHRINK_WIENER || 4 * lg + r < F.K ? Cv : 0.f;
                     at_[c][r] = at;
                     v_[c][r] = SH == BMND_SHRINK_WIENER && !WPLAIN ? v * (F.uv * d2[r]) : v;
                     sh_[c][r] = shat;
@@ -759,7 +764,8 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                 float t = 0.f;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const bool lv = 4 * lg + r < K;
+                    // (hard-threshold and Wiener gains are 0 past K already)
+                    const bool lv = SH != BMND_SHRINK_SOFT || 4 * lg + r < K;
                     t += lv ? at_[0][r] * at_[0][r] + at_[1][r] * at_[1][r] : 0.f;
                 }
                 const float R = wave_sum(t);
