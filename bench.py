@@ -29,7 +29,8 @@ PEAK_FP32_TFLOPS = 157.3     # published FP32 peak (vector, packed; dense matrix
 PEAK_VALU_TOPS = 78.6        # 32-bit integer VALU ops/s, multiply-add counted as 2:
                              # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2
 PEAK_HBM_GBS = 8000.0
-# kernels whose contractions run on the matrix cores (v_mfma_f32_16x16x4f32)
+# kernels whose contractions run on the matrix cores (split half-precision
+# products on v_mfma_f32_16x16x32_f16)
 MFMA_KERNELS = {"filter_ht", "filter_wiener"}
 COPY_KERNEL_HINT = "MulFunctor"   # the calibration kernel: dst = src * 1
 

@@ -45,11 +45,6 @@ constexpr float kRsqrt2 = 0.70710678118654752440f;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ f4 mfma(float a, float b, f4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
 // Orders the LDS accesses of one wavefront.
 __device__ __forceinline__ void wsync()
 {
