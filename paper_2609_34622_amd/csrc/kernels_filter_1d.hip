@@ -562,6 +562,23 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                 f.V[c] = f.V[c] * nv;
             }
         }
+        if constexpr (wiener && WPLAIN) {
+            // the group weight needs only the gains: they replace G here (the
+            // shrinkage below explains the folded scales), and V is not kept
+            const float kuv = f.uv * (f.rp * f.rp);
+            const float kA = a.power_a * kuv, kS = a.s_v * kuv;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float lv = 4 * lg + r < f.K ? 1.f : 0.f;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const float v = relu(f.V[c][r]), gam = f.G[c][r];
+                    const float shat = relu(__builtin_fmaf(-kA, v, gam * gam)) * lv;
+                    const float den = __builtin_fmaf(kS, v, shat);
+                    f.G[c][r] = den > 0.f ? shat * frcp(den) : 0.f;
+                }
+            }
+        }
         return f;
     };
 
@@ -618,6 +635,9 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                         const float m = fmaxf(fabsf(Yv) - a.lambda * fsqrt(v), 0.f);
                         Cv = Yv > 0.f ? m : (Yv < 0.f ? -m : 0.f);
                         at = Yv != 0.f ? m * frcp(fabsf(Yv)) : 0.f;
+                    } else if constexpr (SH == BMND_SHRINK_WIENER && WPLAIN) {
+                        at = F.G[c][r];  // the gain, from the front end
+                        Cv = at * Yv * (F.uy * d2[r]);
                     } else if constexpr (SH == BMND_SHRINK_WIENER) {
                         const float gam = F.G[c][r];
                         shat = relu(__builtin_fmaf(-kA, v, gam * gam)) * lvf[r];
