@@ -706,6 +706,65 @@ def test_filter_1d_far_members(stage):
 
 
 @pytest.mark.parametrize("stage", ["ht", "wiener"])
+def test_filter_1d_negative_region(stage):
+    """Poisson noise with the variance-map source (y in the hard-threshold
+    stage, the pilot in the Wiener stage) negative over part of the signal:
+    workgroups whose staged samples reach it test every group's samples,
+    the others take the non-negative fast path; patches match the oracle's
+    (which clips the map at 0), and weights too except where zero variance
+    leaves a decision to rounding (see below)."""
+    _say(f"1-D filter, negative region, {stage}")
+    L = 12000
+    s = synth.ecg_batch(n_signals=1, length=L, seed=2600)
+    shape, patch, step, search = (L,), (32,), (4,), (256,)
+    p = params_for(shape, patch, step, search, group=(16, 16))
+    ht, wie = oracle_stages(shape, patch, step, search, s.s_p, group=(16, 16))
+    geom = B.geometry(shape)
+    refs = B.bmnd_reference_origins(geom, p.ht)
+    rng = np.random.default_rng(92)
+    n = len(refs)
+    match = np.full((1, n, 16), -1, np.int32)
+    count = np.zeros((1, n), np.int32)
+    for g in range(n):
+        K = int(2 ** rng.integers(1, 5))
+        others = rng.choice(np.setdiff1d(np.arange(max(0, refs[g] - 120), min(L - 31, refs[g] + 120)),
+                                         [refs[g]]), size=K - 1, replace=False)
+        match[0, g, 0] = refs[g]
+        match[0, g, 1:K] = others
+        count[0, g] = K
+    y = s.y[0].astype(np.float64)
+    pilot = np.asarray(s.x[0], np.float64)
+    if stage == "wiener":
+        pilot[5000:5400] -= 1.5 * pilot[5000:5400].max()
+    else:
+        y[5000:5400] -= 1.5 * y[5000:5400].max()
+    y = y.astype(np.float32)
+    pilot = pilot.astype(np.float32) if stage == "wiener" else None
+    assert (pilot if stage == "wiener" else y)[5000:5400].min() < 0
+    st_id = B.STAGE_WIENER if stage == "wiener" else B.STAGE_HT
+    sp = p.wiener if stage == "wiener" else p.ht
+    pg, wg = gpu_filter(st_id, dev(y[None]), None if pilot is None else dev(pilot[None]), geom,
+                        B.poisson(s.s_p), sp, match, count)
+    po, wo = O.filter(wie if stage == "wiener" else ht,
+                      O.STAGE_WIENER if stage == "wiener" else O.STAGE_HT, y, pilot, match[0], count[0])
+    for g in range(n):
+        K = count[0, g]
+        scale = max(np.abs(po[g, :K]).max(), 1e-30)
+        assert np.abs(pg[0, g, :K] - po[g, :K]).max() <= REL_PATCH * scale, g
+        if not np.allclose(wg[0, g, :K], wo[g, :K], rtol=1e-5):
+            # zero variance makes the threshold 0, and a coefficient that is
+            # 0 in exact arithmetic sits exactly at it: rounding decides it in
+            # either precision (the oracle's too), so either decision is
+            # correct; the kept counts (1 / weight) may differ by at most the
+            # number of such coefficients
+            assert stage == "ht", g
+            Yo, vo, _, _ = O.group_coeffs(ht, O.STAGE_HT, y, None, match[0, g, :K])
+            ndeg = int(np.sum((vo == 0) & (np.abs(Yo) <= 1e-6 * np.abs(Yo).max())))
+            kg, ko = round(1 / float(wg[0, g, 0])), round(1 / float(wo[g, 0]))
+            assert abs(kg - ko) <= ndeg, (g, kg, ko, ndeg)
+
+
+@pytest.mark.parametrize("stage", ["ht", "wiener"])
 def test_filter_1d_windowed_weights(stage):
     """Windowed synthesized-domain weights on the 1-D matrix-core filter:
     patches and weights on the GPU's own lists against the oracle's."""
