@@ -381,8 +381,16 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
     const float cA = lg == 3 ? 0.f : 1.f;
 
     const int nchunk = (a.n_refs + chunk - 1) / chunk;
-    const int b = blockIdx.x / nchunk;
-    const int g0 = (blockIdx.x - b * nchunk) * chunk;
+    // workgroups are dealt to the 8 XCDs in turn: give each XCD a contiguous
+    // run of chunks, so neighbours (whose windows and tiles overlap) share an
+    // L2 (a bijection; the last gridDim.x % 8 workgroups keep their index)
+    int bid = int(blockIdx.x);
+    {
+        const int q = int(gridDim.x) / 8;
+        if (bid < 8 * q) bid = (bid % 8) * q + bid / 8;
+    }
+    const int b = bid / nchunk;
+    const int g0 = (bid - b * nchunk) * chunk;
     const int g1 = min(a.n_refs, g0 + chunk);
     const long vb = long(b) * g.V;
     // this wavefront: references [w0g, w1g), accumulated in its own tile
