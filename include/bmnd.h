@@ -387,6 +387,28 @@ bmnd_status bmnd_batch_workspace_size(int32_t n_jobs, const bmnd_job* jobs, size
 bmnd_status bmnd_denoise_batch(int32_t n_jobs, const bmnd_job* jobs, void* d_ws, size_t ws_bytes,
                                int32_t flags, void* stream);
 
+/* Allocation-free denoise, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Computes exactly what bmnd_denoise computes, with the same
+ * kernels, but takes every piece of device scratch -- match lists, counts,
+ * the FP64 numerator and denominator, the pilot when d_pilot is NULL, the
+ * reference-origin lists and the transform tables -- from one static device
+ * array of BMND_NOALLOC_SCRATCH_BYTES bytes that the library holds on each
+ * device it runs on until the process ends.  The library allocates no
+ * device memory in this call (host-side plan caches only); tables and
+ * origin lists are copied into the array on `stream` each call.
+ *   d_y, d_out  [batch][V] caller arrays;  d_pilot [batch][V] or NULL
+ * Every call on one device shares that device's array and overwrites it:
+ * calls that overlap in time on one device (different streams or threads)
+ * race and give undefined results; calls on one stream are ordered.
+ * Errors: those of bmnd_denoise; BMND_E_WORKSPACE when the denoise needs
+ * more than BMND_NOALLOC_SCRATCH_BYTES of scratch (the message states the
+ * need); BMND_E_UNSUPPORTED for Poisson-likelihood matching metrics. */
+#define BMND_NOALLOC_SCRATCH_BYTES (64u << 20)
+bmnd_status bmnd_denoise_noalloc(const float* d_y, const bmnd_geometry* geom,
+                                 const bmnd_noise* noise, const bmnd_params* params, float* d_out,
+                                 float* d_pilot, void* stream);
+
 /* Kernel tracing.  Between bmnd_profile_begin() and bmnd_profile_end() the
  * library records a pair of HIP events on the launch stream around every
  * kernel that bmnd_denoise launches.  bmnd_profile_end() synchronises those

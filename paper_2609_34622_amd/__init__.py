@@ -88,7 +88,7 @@ EXPORTS = [
     "bmnd_match", "bmnd_filter", "bmnd_aggregate", "bmnd_denoise", "bmnd_stream_status",
     "bmnd_transform_matrices", "bmnd_haar_matrix", "bmnd_kaiser_window", "bmnd_count_moments",
     "bmnd_profile_begin", "bmnd_profile_end", "bmnd_batch_workspace_size", "bmnd_denoise_batch",
-    "bmnd_correlated_size", "bmnd_correlated_prepare",
+    "bmnd_correlated_size", "bmnd_correlated_prepare", "bmnd_denoise_noalloc",
 ]
 KERNEL_IDS = ["counts", "patch_sums", "match_ht", "match_wiener", "filter_ht", "filter_wiener",
               "zero", "normalize"]
@@ -130,6 +130,7 @@ def lib() -> C.CDLL:
         "bmnd_denoise_batch": (i32, [i32, C.POINTER(Job), vp, sz, i32, vp]),
         "bmnd_correlated_size": (i32, [G, PP, C.POINTER(sz)]),
         "bmnd_correlated_prepare": (i32, [vp, G, PP, vp, sz, vp]),
+        "bmnd_denoise_noalloc": (i32, [vp, G, N, PP, vp, vp, vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -346,6 +347,21 @@ def bmnd_denoise(y, geom, noise, params, out, pilot, ws, stream=None):
     _check(lib().bmnd_denoise(_ptr(y), C.byref(geom), C.byref(noise), C.byref(params), _ptr(out),
                               _ptr(pilot), _ptr(ws), ws.numel() * ws.element_size(),
                               _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def bmnd_denoise_noalloc(y, geom, noise, params, out, pilot=None, stream=None):
+    """bmnd_denoise with all device scratch in the library's static array
+    (no workspace argument, no device allocation by the library)."""
+    import torch
+
+    _require(y, torch.float32, name="y")
+    _require(out, torch.float32, name="out")
+    _require(pilot, torch.float32, name="pilot")
+    _check(lib().bmnd_denoise_noalloc(_ptr(y), C.byref(geom), C.byref(noise), C.byref(params),
+                                      _ptr(out), _ptr(pilot), _stream(stream)))
 
 
 def bmnd_profile_begin():

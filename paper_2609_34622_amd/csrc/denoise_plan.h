@@ -1,0 +1,53 @@
+// The launch plan of one two-stage denoise (section Method Overview), shared
+// by bmnd_denoise, the batch call and the allocation-free entry point: the
+// validated stage configurations, where the reference origins and the
+// transform tables live on the device, and the workspace layout.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "bmnd_internal.h"
+
+namespace bmnd {
+
+struct DenoisePlan {
+    StageCfg c1, c2;
+    const int64_t* r1 = nullptr;
+    const int64_t* r2 = nullptr;
+    int64_t n1 = 0, n2 = 0;
+    const DevTables* t1 = nullptr;
+    const DevTables* t2 = nullptr;
+    const MomentTables* m1 = nullptr;  // HT Poisson-likelihood matching
+    size_t offs[8] = {};
+    size_t total = 0;
+};
+
+// Host part of a plan: stage configurations, reference counts and the
+// workspace layout (no device pointers are set).
+bmnd_status plan_denoise_host(const bmnd_geometry* geom, const bmnd_noise* noise,
+                              const bmnd_params* params, DenoisePlan* pl);
+
+// The two stages of one denoise on stream s; ws holds pl.total bytes laid
+// out as pl.offs.  With spans, kernel times are recorded for tracing.
+hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out,
+                           float* d_pilot, char* ws, hipStream_t s, bool spans);
+
+// Transform, window and Haar tables of one stage configuration in host
+// memory, with their offsets (t.f32 / t.f64 left null).
+struct HostTables {
+    std::vector<float> f;
+    std::vector<double> f64;
+    DevTables t;
+};
+void build_tables_host(const StageCfg& c, std::vector<float>& f, std::vector<double>& f64,
+                       DevTables& t);
+
+// Process-lifetime host caches (entries are never removed, so references
+// stay valid for asynchronous copies).
+const HostTables& host_tables_cached(const StageCfg& c);
+const std::vector<int64_t>& host_origins_cached(const bmnd_geometry& geom,
+                                                const bmnd_stage_params& sp);
+
+
+}  // namespace bmnd

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "bmnd_internal.h"
+#include "denoise_plan.h"
 
 namespace bmnd {
 
@@ -213,21 +214,12 @@ std::map<OrgKey, std::pair<int64_t*, int64_t>> g_origins;
 
 }  // namespace
 
-const DevTables* device_tables(const StageCfg& c, std::string& err)
+void build_tables_host(const StageCfg& c, std::vector<float>& f, std::vector<double>& f64,
+                       DevTables& t)
 {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) {
-        err = "hipGetDevice failed";
-        return nullptr;
-    }
-    TabKey key{dev, c.spatial, c.g.j[0], c.g.j[1], c.g.j[2], c.g.j[3], c.beta};
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    auto it = g_tables.find(key);
-    if (it != g_tables.end()) return &it->second;
-
-    DevTables t{};
-    std::vector<float> f;
-    std::vector<double> f64;
+    t = DevTables{};
+    f.clear();
+    f64.clear();
     for (int d = 0; d < kAx; ++d) {
         const int n = c.g.j[d];
         std::vector<double> T, U;
@@ -285,6 +277,26 @@ const DevTables* device_tables(const StageCfg& c, std::string& err)
             f64.push_back(v);
         }
     }
+    t.f32_count = int(f.size());
+    t.f64_count = int(f64.size());
+}
+
+const DevTables* device_tables(const StageCfg& c, std::string& err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        err = "hipGetDevice failed";
+        return nullptr;
+    }
+    TabKey key{dev, c.spatial, c.g.j[0], c.g.j[1], c.g.j[2], c.g.j[3], c.beta};
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_tables.find(key);
+    if (it != g_tables.end()) return &it->second;
+
+    DevTables t{};
+    std::vector<float> f;
+    std::vector<double> f64;
+    build_tables_host(c, f, f64, t);
     float* df = nullptr;
     double* dd = nullptr;
     if (hipMalloc(&df, f.size() * sizeof(float)) != hipSuccess ||
@@ -305,6 +317,50 @@ const DevTables* device_tables(const StageCfg& c, std::string& err)
     return &(g_tables[key] = t);
 }
 
+namespace {
+
+using HostOrgKey = std::tuple<std::vector<int64_t>, std::vector<int>, int, int, double>;
+std::map<HostOrgKey, std::vector<int64_t>> g_host_origins;
+std::map<TabKey, HostTables> g_host_tables;
+
+HostOrgKey host_org_key(const bmnd_geometry& geom, const bmnd_stage_params& sp)
+{
+    std::vector<int64_t> shape(geom.shape, geom.shape + geom.ndim);
+    std::vector<int> ps(size_t(2 * geom.ndim));
+    for (int d = 0; d < geom.ndim; ++d) {
+        ps[size_t(d)] = sp.patch[d];
+        ps[size_t(geom.ndim + d)] = sp.step[d];
+    }
+    return HostOrgKey{shape, ps, sp.schedule, sp.passes, sp.shift_density};
+}
+
+}  // namespace
+
+const std::vector<int64_t>& host_origins_cached(const bmnd_geometry& geom,
+                                                const bmnd_stage_params& sp)
+{
+    const HostOrgKey key = host_org_key(geom, sp);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_host_origins.find(key);
+        if (it != g_host_origins.end()) return it->second;
+    }
+    std::vector<int64_t> o = reference_origins(geom, sp);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    return g_host_origins.emplace(key, std::move(o)).first->second;
+}
+
+const HostTables& host_tables_cached(const StageCfg& c)
+{
+    TabKey key{-1, c.spatial, c.g.j[0], c.g.j[1], c.g.j[2], c.g.j[3], c.beta};
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_host_tables.find(key);
+    if (it != g_host_tables.end()) return it->second;
+    HostTables h;
+    build_tables_host(c, h.f, h.f64, h.t);
+    return g_host_tables.emplace(key, std::move(h)).first->second;
+}
+
 const int64_t* device_origins(const bmnd_geometry& geom, const bmnd_stage_params& sp,
                               int64_t* n_refs, hipStream_t, std::string& err)
 {
@@ -320,13 +376,21 @@ const int64_t* device_origins(const bmnd_geometry& geom, const bmnd_stage_params
         ps[size_t(geom.ndim + d)] = sp.step[d];
     }
     OrgKey key{dev, shape, ps, {}, sp.schedule, sp.passes, sp.shift_density};
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_origins.find(key);
+        if (it != g_origins.end()) {
+            *n_refs = it->second.second;
+            return it->second.first;
+        }
+    }
+    const std::vector<int64_t>& o = host_origins_cached(geom, sp);
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_origins.find(key);
     if (it != g_origins.end()) {
         *n_refs = it->second.second;
         return it->second.first;
     }
-    std::vector<int64_t> o = reference_origins(geom, sp);
     int64_t* d = nullptr;
     if (hipMalloc(&d, std::max<size_t>(1, o.size()) * sizeof(int64_t)) != hipSuccess ||
         hipMemcpy(d, o.data(), o.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
@@ -787,8 +851,8 @@ bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noi
     if ((st = make_stage(geom, noise, &params->wiener, BMND_STAGE_WIENER, c2)) != BMND_OK) return st;
     bmnd_geometry one = *geom;
     one.batch = 1;
-    const int64_t n1 = int64_t(reference_origins(one, params->ht).size());
-    const int64_t n2 = int64_t(reference_origins(one, params->wiener).size());
+    const int64_t n1 = int64_t(host_origins_cached(one, params->ht).size());
+    const int64_t n2 = int64_t(host_origins_cached(one, params->wiener).size());
     size_t offs[8];
     return denoise_layout(geom, params, n1, n2, offs, bytes);
 }
@@ -898,22 +962,7 @@ bmnd_status bmnd_aggregate(const float* d_y, const bmnd_geometry* geom,
 
 }  // extern "C"
 
-namespace {
-
-// Everything one denoise needs, resolved before any launch: tables and
-// reference origins are built (and uploaded) here, so enqueueing allocates
-// nothing and can be captured into a graph.
-struct DenoisePlan {
-    StageCfg c1, c2;
-    const int64_t* r1 = nullptr;
-    const int64_t* r2 = nullptr;
-    int64_t n1 = 0, n2 = 0;
-    const DevTables* t1 = nullptr;
-    const DevTables* t2 = nullptr;
-    const MomentTables* m1 = nullptr;  // HT Poisson-likelihood matching
-    size_t offs[8] = {};
-    size_t total = 0;
-};
+namespace bmnd {
 
 // host part: configurations, reference counts and the workspace layout
 bmnd_status plan_denoise_host(const bmnd_geometry* geom, const bmnd_noise* noise,
@@ -927,8 +976,8 @@ bmnd_status plan_denoise_host(const bmnd_geometry* geom, const bmnd_noise* noise
     if (!noise) return fail(BMND_E_ARG, "noise is NULL");
     bmnd_geometry one = *geom;
     one.batch = 1;
-    pl->n1 = int64_t(reference_origins(one, params->ht).size());
-    pl->n2 = int64_t(reference_origins(one, params->wiener).size());
+    pl->n1 = int64_t(host_origins_cached(one, params->ht).size());
+    pl->n2 = int64_t(host_origins_cached(one, params->wiener).size());
     return denoise_layout(geom, params, pl->n1, pl->n2, pl->offs, &pl->total);
 }
 
@@ -1007,6 +1056,10 @@ hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out
     if (e != hipSuccess) return e;
     return run_stage(pl.c2, *pl.t2, pl.r2, pl.n2, pilot, pilot, d_out);
 }
+
+}  // namespace bmnd
+
+namespace {
 
 // ------------------------------------------------------------- batches
 
