@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
     constexpr int SEG = J3 + kRB - 1;
     constexpr int M = GM > 1 ? GM - 1 : 1;
     extern __shared__ __align__(16) int smem[];
-    __shared__ unsigned hist[256];
+    __shared__ __align__(16) unsigned hist[256];
     __shared__ int sel_lin[M];
     __shared__ int sel_key[M];
     __shared__ double band_x[kBandCap];
@@ -378,19 +378,31 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
             if (k != kbig && (k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
         }
         wsync();
-        // the bin holding the rank-th key (one lane scans 256 bins)
-        if (lane == 0) {
-            int c = 0, bin = 255;
-            for (int h = 0; h < 256; ++h) {
-                const int hv = int(hist[h]);
-                if (c + hv >= rank) {
-                    bin = h;
-                    break;
+        // the bin holding the rank-th key: each lane owns 4 consecutive bins,
+        // a wave prefix sum gives the keys below each lane's bins, and the
+        // one lane whose range holds the rank writes the bin
+        {
+            const uint4 h4 = *reinterpret_cast<const uint4*>(&hist[4 * lane]);
+            const int c0 = int(h4.x), c1 = int(h4.y), c2 = int(h4.z), c3 = int(h4.w);
+            const int tot = c0 + c1 + c2 + c3;
+            const int below = wscan_ex(tot);
+            if (below < rank && below + tot >= rank) {
+                int c = below, bin = 4 * lane;
+                if (c + c0 < rank) {
+                    c += c0;
+                    ++bin;
+                    if (c + c1 < rank) {
+                        c += c1;
+                        ++bin;
+                        if (c + c2 < rank) {
+                            c += c2;
+                            ++bin;
+                        }
+                    }
                 }
-                c += hv;
+                misc[0] = bin;
+                misc[1] = rank - c;
             }
-            misc[0] = bin;
-            misc[1] = rank - c;
         }
         wsync();
         prefix |= unsigned(misc[0]) << shift;
