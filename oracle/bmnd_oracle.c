@@ -1089,6 +1089,34 @@ static int filter_group(stage_ctx* x, const orc_cfg* c, int stage, const double*
         free(mvu);
     }
 
+    /* magnitude of the terms of every coefficient, M_k = sum_i |T_ki| |y_i|
+     * (the transform with absolute entries applied to |y|): the scale of
+     * the rounding residue of Y_k, used by the hard threshold when
+     * sigma_k = 0 */
+    double* mag = NULL;
+    if (c->shrink == ORC_SHRINK_HARD) {
+        mag = (double*)malloc(sizeof(double) * (size_t)n);
+        double* aH = (double*)malloc(sizeof(double) * (size_t)K * K);
+        double* aT[ORC_MAXD] = {0};
+        int ok = mag && aH;
+        for (int d = 0; d < x->D && ok; ++d) {
+            const int m = c->patch[d];
+            aT[d] = (double*)malloc(sizeof(double) * (size_t)m * m);
+            ok = aT[d] != NULL;
+            for (int i = 0; ok && i < m * m; ++i) aT[d][i] = fabs(x->Tsp[d][i]);
+        }
+        if (ok) {
+            for (int i = 0; i < K * K; ++i) aH[i] = fabs(x->H[i]);
+            for (int j = 0; j < K; ++j)
+                for (int i = 0; i < P; ++i) mag[j * P + i] = fabs(y[(int64_t)org[j] + x->off[i]]);
+            mode_product(mag, x->dims, x->D + 1, 0, aH, x->tmp);
+            for (int d = 0; d < x->D; ++d) mode_product(mag, x->dims, x->D + 1, d + 1, aT[d], x->tmp);
+        }
+        free(aH);
+        for (int d = 0; d < x->D; ++d) free(aT[d]);
+        if (!ok) { free(mag); free(mv); free(gam); free(shat); free(att); return -2; }
+    }
+
     /* shrinkage */
     for (int e = 0; e < n; ++e) {
         double sig2 = var[e] > 0.0 ? var[e] : 0.0;
@@ -1099,8 +1127,14 @@ static int filter_group(stage_ctx* x, const orc_cfg* c, int stage, const double*
              * sample with kappa = lambda^2 has |Y| = lambda sigma exactly),
              * and the strict inequality drops them; the comparison is made
              * with a relative margin of 1e-9 so that a tie is not decided by
-             * the rounding of Y and sigma. */
-            double a = (fabs(Y) > c->lambda * sqrt(sig2) * (1.0 + ORC_TIE_REL)) ? 1.0 : 0.0;
+             * the rounding of Y and sigma.  With sigma_k = 0 the threshold is
+             * 0 and a coefficient that is 0 in exact arithmetic keeps a
+             * rounding residue; |Y_k| up to 1e-9 M_k counts as 0. */
+            double a;
+            if (sig2 > 0.0)
+                a = (fabs(Y) > c->lambda * sqrt(sig2) * (1.0 + ORC_TIE_REL)) ? 1.0 : 0.0;
+            else
+                a = (fabs(Y) > ORC_TIE_REL * mag[e]) ? 1.0 : 0.0;
             att[e] = a;
             C[e] = a * Y;
             shat[e] = 0.0;
@@ -1138,7 +1172,7 @@ static int filter_group(stage_ctx* x, const orc_cfg* c, int stage, const double*
     double* hq = NULL;
     if (c->weight_domain == ORC_WDOMAIN_WINDOWED) {
         hq = (double*)malloc(sizeof(double) * (size_t)P);
-        if (!hq) { free(mv); free(gam); free(shat); free(att); return -2; }
+        if (!hq) { free(mag); free(mv); free(gam); free(shat); free(att); return -2; }
         for (int q = 0; q < P; ++q) {
             int qd[ORC_MAXD];
             int rem = q;
@@ -1197,6 +1231,7 @@ static int filter_group(stage_ctx* x, const orc_cfg* c, int stage, const double*
         }
     }
     free(hq);
+    free(mag);
     free(mv);
     free(gam);
     free(shat);

@@ -12,7 +12,9 @@ LIB = os.path.join(HERE, "libbmnd.so")
 SOURCES = ["host_api.cpp", "host_schedule.cpp", "host_tables.cpp", "kernels.hip",
            "kernels_filter_cube.hip", "kernels_filter_1d.hip", "kernels_match_1d.hip",
            "kernels_match_nd.hip",
-           "kernels_match_pois.hip", "host_moments.cpp", "corr_noise.hip", "noalloc.hip"]
+           "kernels_match_pois.hip", "host_moments.cpp", "corr_noise.hip", "noalloc.hip",
+           "kernels_filter_nd.hip", "kernels_filter_nd_2d_ht.hip", "kernels_filter_nd_2d_wie.hip",
+           "kernels_filter_nd_3d_ht.hip", "kernels_filter_nd_3d_wie.hip"]
 
 # Packed FP32 VALU instructions are kept out of the generated code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -119,6 +119,15 @@ hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* ps
 hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
                          const float* pilot, int n_refs, const int* match, const int* count,
                          float* patches, float* weights, void* num, void* den, hipStream_t s);
+// N-D filter with per-origin weights W (FP64, one value per origin) and the
+// numerator accumulated in LDS boxes of the spatial blocks `blk` (the
+// origin list must be in blk's order); out_mode 1 (W and numerator), 2 (W
+// only), 3 (numerator with the mass-conservation shift, eta in den)
+struct NdBlocks;
+hipError_t launch_filter_blocked(const StageCfg& c, const DevTables& t, int out_mode,
+                                 const float* y, const float* pilot, int n_refs, const int* match,
+                                 const int* count, void* num, void* den, double* wfield,
+                                 const NdBlocks* blk, hipStream_t s);
 hipError_t launch_aggregate(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
                             int n_refs, const int* match, const int* count, const float* patches,
                             const float* weights, void* num, void* den, hipStream_t s);

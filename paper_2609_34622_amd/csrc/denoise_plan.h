@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "bmnd_internal.h"
+#include "filter_nd.h"
 
 namespace bmnd {
 
@@ -19,6 +20,10 @@ struct DenoisePlan {
     const DevTables* t1 = nullptr;
     const DevTables* t2 = nullptr;
     const MomentTables* m1 = nullptr;  // HT Poisson-likelihood matching
+    // N-D filter with per-origin weights and LDS boxes: the stage's origins
+    // are listed block by block (r1 / r2 then point to that order)
+    bool nd1 = false, nd2 = false;
+    NdBlocks blk1, blk2;
     size_t offs[8] = {};
     size_t total = 0;
 };
@@ -49,5 +54,16 @@ const HostTables& host_tables_cached(const StageCfg& c);
 const std::vector<int64_t>& host_origins_cached(const bmnd_geometry& geom,
                                                 const bmnd_stage_params& sp);
 
+// Origins of a stage in the N-D filter's block order, with the block
+// offsets and box geometry (blk.start left null).
+struct HostBlocks {
+    std::vector<int64_t> refs;
+    std::vector<int> start;
+    NdBlocks blk;
+};
+const HostBlocks& host_blocks_cached(const bmnd_geometry& geom, const bmnd_stage_params& sp,
+                                     const Geo& g);
+// whether a stage runs the N-D filter with per-origin weights
+bool stage_uses_nd(const StageCfg& c);
 
 }  // namespace bmnd

@@ -27,6 +27,7 @@ struct FilterArgs {
     float* weights;
     double* numd;
     double* dend;
+    double* wfield;   // per-origin weight sums (N-D filter: eta = W * window)
     // correlated Gaussian noise: variance table D(Delta, q) over the member
     // box of extents cbw (null otherwise)
     const double* cdtab;

@@ -1,0 +1,39 @@
+// Spatial blocks of reference origins for the N-D filter's LDS overlap-add
+// boxes (kernels_filter_nd.hip).
+#pragma once
+
+#include "bmnd_internal.h"
+
+namespace bmnd {
+
+// References grouped by block: block c (C-order over nb) holds the origins
+// r with floor(r_d / B_d) = c_d on every canonical axis, list positions
+// start[c] .. start[c + 1] - 1.  The box of a block spans, per axis, the
+// block, the search window and a patch: E_d = B_d + W_d + j_d - 2 samples
+// from c_d B_d - floor(W_d / 2); S_d are its C-order strides.
+struct NdBlocks {
+    const int* start = nullptr;  // [nblocks + 1] (device)
+    int nblocks = 0;
+    int nb[kAx] = {1, 1, 1, 1};
+    int B[kAx] = {1, 1, 1, 1};
+    int E[kAx] = {1, 1, 1, 1};
+    int S[kAx] = {1, 1, 1, 1};
+    int box_size = 0;
+};
+
+struct FilterArgs;
+bool nd_filter_supported(const Geo& g, int gmax, int kex, bool corr, int noise, int shrink);
+// whether the blocks' boxes fit a compute unit's LDS (else the older filter runs)
+bool nd_blocks_fit(const NdBlocks& blk);
+hipError_t launch_filter_nd(const FilterArgs& a, const NdBlocks* blk, hipStream_t s);
+// eta = W convolved with the patch window (the overlap-add denominator from
+// the per-origin weights W)
+hipError_t launch_window_conv(const Geo& g, const DevTables& t, const double* W, double* eta,
+                              hipStream_t s);
+
+// Host: block sizes for a geometry and the block order of a sorted origin
+// list (refs_out: the origins in block order, start: block offsets).
+void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, bool fp64_box,
+                    std::vector<int64_t>& refs_out, std::vector<int>& start, NdBlocks& blk);
+
+}  // namespace bmnd

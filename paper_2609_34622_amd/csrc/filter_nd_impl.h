@@ -1,0 +1,693 @@
+// Collaborative filtering for 2-D 8x8 and 3-D 4x4x4 patches (P = 64) with
+// the diagonal variance model: one lane per group member, its whole patch
+// in registers.  Included by the translation units that instantiate it
+// (one per patch shape and stage).
+//
+// Layout.  A wavefront holds 64 / GM groups ("segments" of GM lanes, GM the
+// stage's group_max); lane j of a segment owns member j of its group.
+//   - The separable spatial transform (T on every patch axis, section Method
+//     Overview: T = H_K (x) T_0 (x) ...) runs inside the lane: J-point
+//     products along each axis, the matrix entries uniform (scalar
+//     registers).  The variance map goes through T o T (Prop. diagonal
+//     Poisson variance propagation).
+//   - The orthonormal Haar transform over the K members runs across the
+//     segment's lanes as unnormalised butterflies (sum on the low lane,
+//     difference on the high lane, pair distances 1, 2, ..., K/2), then one
+//     scale per lane: lane 0 ends with the scaling coefficient (support K),
+//     lane p > 0 with the detail coefficient of support 2 lowbit(p).  The
+//     squared Haar of the variances are block sums over the same supports.
+//     The synthesis runs the same butterflies in reverse order on the
+//     rescaled coefficients (H = F B, B the butterfly network, F the scales,
+//     so H^-1 = H^T = B^T F, and every level of B is symmetric).
+//   - Lanes past a group's K take no part: the butterflies of a group of K
+//     never pair a member below K with one above it.
+//   - Wiener stage: the gains G come from the pilot (eq. pilot-power-family,
+//     eq. wiener-gain) before the observation is read, so at most two
+//     64-sample arrays are live in a lane at any time.
+// Shrinkage and the weight surrogates are per coefficient inside the lane;
+// group sums are segment reductions.
+//
+// Overlap-add (Def. weighted overlap-add).  The denominator is not summed
+// per sample: every member adds its weight at its origin to a per-origin
+// field W, and eta = W convolved with the patch window, which is the same
+// sum.  The numerator: inside bmnd_denoise a workgroup owns a spatial block
+// of references, so every sample its groups touch lies in one box (the
+// block, the search window and a patch); the workgroup accumulates into that
+// box in LDS (FP64) and adds it once
+// to the FP64 numerator with coalesced atomics.  A member outside the box
+// (only for lists that bmnd_match did not produce) adds its samples to the
+// numerator directly.
+//
+// Mass conservation (section Aggregation-Aware Mass Conservation): sweep 1
+// only needs the weights (forward transforms, shrinkage, W); sweep 2 filters
+// again, forms alpha_g = sum zeta (y - p) / sum zeta with zeta = w omega / eta
+// in FP64 and accumulates w omega (p + alpha_g) in an FP64 box.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "bmnd_internal.h"
+#include "filter_common.h"
+#include "filter_nd.h"
+
+namespace bmnd {
+namespace nd {
+
+constexpr int kWave = 64;
+constexpr int kWaves = 4;                 // wavefronts per workgroup
+constexpr int kThreads = kWave * kWaves;
+
+__device__ __forceinline__ float fsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+
+// value of the lane `lane ^ d` (d < 32): quad permutations for 1 and 2,
+// bit-mode swizzles (xor within 32 lanes) above
+template <int d>
+__device__ __forceinline__ float xlane(float v)
+{
+    const int x = __float_as_int(v);
+    if constexpr (d == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xf, 0xf, false));
+    else if constexpr (d == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xf, 0xf, false));
+    else return __int_as_float(__builtin_amdgcn_ds_swizzle(x, 0x1F | (d << 10)));
+}
+template <int d>
+__device__ __forceinline__ double xlane64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __float_as_int(xlane<d>(__int_as_float(int(b & 0xffffffffll))));
+    const int hi = __float_as_int(xlane<d>(__int_as_float(int(b >> 32))));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// sum over the lanes of a segment of GM lanes
+template <int GM>
+__device__ __forceinline__ float seg_sum(float v)
+{
+    if constexpr (GM > 1) v += xlane<1>(v);
+    if constexpr (GM > 2) v += xlane<2>(v);
+    if constexpr (GM > 4) v += xlane<4>(v);
+    if constexpr (GM > 8) v += xlane<8>(v);
+    if constexpr (GM > 16) v += xlane<16>(v);
+    return v;
+}
+template <int GM>
+__device__ __forceinline__ double seg_sum64(double v)
+{
+    if constexpr (GM > 1) v += xlane64<1>(v);
+    if constexpr (GM > 2) v += xlane64<2>(v);
+    if constexpr (GM > 4) v += xlane64<4>(v);
+    if constexpr (GM > 8) v += xlane64<8>(v);
+    if constexpr (GM > 16) v += xlane64<16>(v);
+    return v;
+}
+
+// one J-point product along a fibre (samples base + b * stride):
+// out[a] = sum_b M[a J + b] in[b]
+template <int J, int stride>
+__device__ __forceinline__ void fibre(float* x, int base, const float* __restrict__ M)
+{
+    float t[J];
+#pragma unroll
+    for (int a = 0; a < J; ++a) {
+        float s = 0.f;
+#pragma unroll
+        for (int b = 0; b < J; ++b) s = __builtin_fmaf(M[a * J + b], x[base + b * stride], s);
+        t[a] = s;
+    }
+#pragma unroll
+    for (int a = 0; a < J; ++a) x[base + a * stride] = t[a];
+}
+
+// separable spatial transform inside a lane: the same J x J matrix along
+// every patch axis (samples in C order)
+template <int D, int J>
+__device__ __forceinline__ void spatial_reg(float* x, const float* __restrict__ M)
+{
+    if constexpr (D == 2) {
+#pragma unroll
+        for (int r = 0; r < J; ++r) fibre<J, 1>(x, r * J, M);
+#pragma unroll
+        for (int c = 0; c < J; ++c) fibre<J, J>(x, c, M);
+    } else {
+#pragma unroll
+        for (int i0 = 0; i0 < J; ++i0)
+#pragma unroll
+            for (int i1 = 0; i1 < J; ++i1) fibre<J, 1>(x, (i0 * J + i1) * J, M);
+#pragma unroll
+        for (int i0 = 0; i0 < J; ++i0)
+#pragma unroll
+            for (int i2 = 0; i2 < J; ++i2) fibre<J, J>(x, i0 * J * J + i2, M);
+#pragma unroll
+        for (int i1 = 0; i1 < J; ++i1)
+#pragma unroll
+            for (int i2 = 0; i2 < J; ++i2) fibre<J, J * J>(x, i1 * J + i2, M);
+    }
+}
+
+// one butterfly level at pair distance d: lanes aligned to d take part
+// (while d < K), the low lane of a pair gets the sum, the high lane the
+// difference (low - high)
+template <int d, int N>
+__device__ __forceinline__ void bfly(float* x, int jl, int lk)
+{
+    constexpr int t = d == 1 ? 0 : (d == 2 ? 1 : (d == 4 ? 2 : (d == 8 ? 3 : 4)));
+    const bool part = t < lk && (jl & (d - 1)) == 0;
+    const float sg = (jl & d) ? -1.f : 1.f;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const float p = xlane<d>(x[k]);
+        const float r = __builtin_fmaf(sg, x[k], p);   // low: x + p; high: p - x
+        x[k] = part ? r : x[k];
+        // at most 16 lane exchanges in flight (register pressure)
+        if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+// block sums: both lanes of a pair get the sum
+template <int d, int N>
+__device__ __forceinline__ void bsum(float* x, int jl, int lk)
+{
+    constexpr int t = d == 1 ? 0 : (d == 2 ? 1 : (d == 4 ? 2 : (d == 8 ? 3 : 4)));
+    const bool part = t < lk && (jl & (d - 1)) == 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const float p = xlane<d>(x[k]);
+        x[k] = part ? x[k] + p : x[k];
+        if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+template <int GM, int N>
+__device__ __forceinline__ void haar_fwd(float* x, int jl, int lk)
+{
+    if constexpr (GM > 1) bfly<1, N>(x, jl, lk);
+    if constexpr (GM > 2) bfly<2, N>(x, jl, lk);
+    if constexpr (GM > 4) bfly<4, N>(x, jl, lk);
+    if constexpr (GM > 8) bfly<8, N>(x, jl, lk);
+    if constexpr (GM > 16) bfly<16, N>(x, jl, lk);
+}
+template <int GM, int N>
+__device__ __forceinline__ void haar_inv(float* x, int jl, int lk)
+{
+    if constexpr (GM > 16) bfly<16, N>(x, jl, lk);
+    if constexpr (GM > 8) bfly<8, N>(x, jl, lk);
+    if constexpr (GM > 4) bfly<4, N>(x, jl, lk);
+    if constexpr (GM > 2) bfly<2, N>(x, jl, lk);
+    if constexpr (GM > 1) bfly<1, N>(x, jl, lk);
+}
+template <int GM, int N>
+__device__ __forceinline__ void haar_sq(float* x, int jl, int lk)
+{
+    if constexpr (GM > 1) bsum<1, N>(x, jl, lk);
+    if constexpr (GM > 2) bsum<2, N>(x, jl, lk);
+    if constexpr (GM > 4) bsum<4, N>(x, jl, lk);
+    if constexpr (GM > 8) bsum<8, N>(x, jl, lk);
+    if constexpr (GM > 16) bsum<16, N>(x, jl, lk);
+}
+
+// FP64 Haar entry H[row of lane p][member j] for a group of K
+__device__ __forceinline__ double haar_entry64(int p, int j, int K)
+{
+    if (j >= K) return 0.0;
+    if (p == 0) return 1.0 / sqrt(double(K));
+    const int d = p & -p;
+    const double v = 1.0 / sqrt(double(2 * d));
+    if (j >= p - d && j < p) return v;
+    if (j >= p && j < p + d) return -v;
+    return 0.0;
+}
+
+template <int D, int J>
+__device__ __forceinline__ int patch_off(int i, const Geo& g)
+{
+    if constexpr (D == 2) return (i / J) * g.st[kAx - 2] + (i % J);
+    else return (i / (J * J)) * g.st[kAx - 3] + ((i / J) % J) * g.st[kAx - 2] + (i % J);
+}
+
+// product over the patch axes of a per-axis table entry tab[axis][c_axis]
+// for sample (or coefficient) index i, C-order over the D patch axes
+template <int D, int J>
+__device__ __forceinline__ float axis_prod(const float* __restrict__ tab, const int* off, int i)
+{
+    float w = 1.f;
+#pragma unroll
+    for (int d = D - 1; d >= 0; --d) {
+        w *= tab[off[kAx - D + d] + i % J];
+        i /= J;
+    }
+    return w;
+}
+
+// diagonal of the windowed synthesis metric for coefficient q (the product
+// over the patch axes of sum_i (w_i U[i][q_d])^2)
+template <int D, int J>
+__device__ __forceinline__ float nd_window_metric(const float* __restrict__ tab, const FilterArgs& a,
+                                                  int q)
+{
+    return axis_prod<D, J>(tab, a.t.hw, q);
+}
+
+// FP64 decision of one hard-threshold coefficient (lane src's row, spatial
+// coefficient q): the segment's lanes add their members' terms in a rolled
+// loop (it runs only for coefficients in the FP32 error band).  Returns the
+// decision and, in cy / cv, the FP64 coefficient and its variance.
+template <int D, int J, int GM>
+__device__ __forceinline__ bool ht_decide64(const FilterArgs& a,
+                                                      const double* __restrict__ tab64,
+                                                      const float* __restrict__ yo, bool mine,
+                                                      int p, int jl, int K, int q, double* cy,
+                                                      double* cv)
+{
+    constexpr int P = D == 2 ? J * J : J * J * J;
+    const double* __restrict__ T64 = tab64 + a.t.T64[kAx - 1];
+    const bool poisson = a.noise == BMND_NOISE_POISSON;
+    double sy = 0.0, sv = 0.0, sm = 0.0;
+    if (mine) {
+        const double h = haar_entry64(p, jl, K);
+        if (h != 0.0) {
+#pragma unroll 1
+            for (int i = 0; i < P; ++i) {
+                double w = h;
+                int qq = q, ii = i;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    w *= T64[(qq % J) * J + (ii % J)];
+                    qq /= J;
+                    ii /= J;
+                }
+                const double yv = double(yo[patch_off<D, J>(i, a.g)]);
+                sy += w * yv;
+                sm += fabs(w * yv);
+                sv += w * w * (poisson ? a.s_p64 * fmax(yv, 0.0) : a.sigma2_64);
+            }
+        }
+    }
+    sy = seg_sum64<GM>(sy);
+    sv = seg_sum64<GM>(sv);
+    sm = seg_sum64<GM>(sm);
+    *cy = sy;
+    *cv = sv;
+    // strict inequality with the 1e-9 relative tie margin; with zero
+    // variance, coefficients up to 1e-9 of the magnitude of their terms are
+    // rounding residues of exact zeros
+    return sv > 0.0 ? fabs(sy) > a.lambda64 * sqrt(sv) * (1.0 + 1e-9) : fabs(sy) > 1e-9 * sm;
+}
+
+// OM: output mode (0 patches and weights, 1 overlap-add, 2 mass-conservation
+// sweep 1, 3 mass-conservation sweep 2); SH: shrinkage; BLK: references come
+// in spatial blocks (one per workgroup) with an LDS box for the numerator
+// The arrays and tables come as separate restrict-qualified arguments:
+// loads from them are then known not to be clobbered by the kernel's stores,
+// so uniform table entries are read with scalar loads and samples with global
+// (not generic) loads.
+template <int D, int J, int GM, int SH, int OM, bool BLK>
+__global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
+    FilterArgs a, NdBlocks blk, const float* __restrict__ y_, const float* __restrict__ pilot_,
+    const int* __restrict__ match_, const int* __restrict__ count_, const float* __restrict__ tab,
+    const double* __restrict__ tab64, const int* __restrict__ bstart, double* __restrict__ numd,
+    const double* __restrict__ dend, double* __restrict__ wfield)
+{
+    constexpr int P = D == 2 ? J * J : J * J * J;
+    static_assert(P == 64, "64-sample patches");
+    constexpr int NG = kWave / GM;                 // groups per wavefront
+    constexpr bool WIE = SH == BMND_SHRINK_WIENER;
+    // FP64 box: sums that do not depend on the order of the LDS atomics
+    // beyond FP64 round-off, so an array's result is the same in every run
+    // and in every batch or serving mix
+    using Acc = double;
+    extern __shared__ __align__(16) unsigned char nd_smem[];
+    Acc* box = reinterpret_cast<Acc*>(nd_smem);
+
+    const Geo& g = a.g;
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const int seg = lane / GM;
+    const int jl = lane % GM;
+    const int omax = last_origin(g);
+
+    // ---- this workgroup's references and (with blocks) its box
+    int b = 0, r0 = 0, r1 = 0;
+    int blo[kAx] = {0, 0, 0, 0};
+    if constexpr (BLK) {
+        const int blkid = blockIdx.x % blk.nblocks;
+        b = blockIdx.x / blk.nblocks;
+        r0 = bstart[blkid];
+        r1 = bstart[blkid + 1];
+        if (r0 >= r1) return;   // an empty block (uniform over the workgroup)
+        int rem = blkid;
+#pragma unroll
+        for (int d = kAx - 1; d >= 0; --d) {
+            const int bc = rem % blk.nb[d];
+            rem /= blk.nb[d];
+            blo[d] = bc * blk.B[d] - g.W[d] / 2;
+        }
+        if constexpr (OM == 1 || OM == 3) {
+            for (int e = threadIdx.x; e < blk.box_size; e += kThreads) box[e] = Acc(0);
+            __syncthreads();
+        }
+    } else {
+        const long per = long(kWaves) * NG;
+        const long nchunk = (a.n_refs + per - 1) / per;
+        b = int(blockIdx.x / nchunk);
+        r0 = int((blockIdx.x - long(b) * nchunk) * per);
+        r1 = min(a.n_refs, int(r0 + per));
+    }
+    const long vb = long(b) * g.V;
+    const float* __restrict__ yb = y_ + vb;
+    const float* __restrict__ pb = WIE ? pilot_ + vb : nullptr;
+    const float* __restrict__ Tm = tab + a.t.T[kAx - 1];
+    const float* __restrict__ T2m = tab + a.t.T2[kAx - 1];
+    const float* __restrict__ Um = tab + a.t.U[kAx - 1];
+    const bool poisson = a.noise == BMND_NOISE_POISSON;
+
+    for (int gbase = r0 + wave * NG; gbase < r1; gbase += kWaves * NG) {
+        const int gi = gbase + seg;
+        const bool gvalid = gi < r1;
+        const long grp = long(b) * a.n_refs + (gvalid ? gi : r0);
+        const int K = gvalid ? safe_count(count_[grp], a.gmax) : 0;
+        const int lk = 31 - __clz(max(K, 1));
+        const bool act = jl < K;
+        const int org = safe_origin(act ? match_[grp * a.gmax + jl] : 0, omax);
+        const float* __restrict__ yo = yb + org;   // the member's first sample
+        const int sup = jl == 0 ? max(K, 1) : 2 * (jl & -jl);   // support of the lane's Haar row
+        const float f = 1.f / fsqrt(float(sup));
+        const float f2 = 1.f / float(sup);
+
+        float x[P];      // observation -> Y -> C -> p
+        float v[P];      // variance source -> sigma^2 (HT); Wiener: gains
+        float rl = 0.f;  // weight surrogate of the lane's Haar row
+        float gn2 = 0.f;
+
+        if constexpr (WIE) {
+            // ---- pilot: Gamma and sigma^2, then the gains
+            float gm[P];
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const float ld = pb[org + patch_off<D, J>(i, g)];
+                const float pv = act ? ld : 0.f;
+                gm[i] = pv;
+                v[i] = fmaxf(pv, 0.f);
+            }
+            if (poisson) {
+                spatial_reg<D, J>(v, T2m);
+                haar_sq<GM, P>(v, jl, lk);
+                const float sc = a.s_p * f2;
+#pragma unroll
+                for (int i = 0; i < P; ++i) v[i] *= sc;
+            } else {
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    const float rn = axis_prod<D, J>(tab, a.t.rn, i);
+                    v[i] = a.sigma2 * rn * rn;
+                }
+            }
+            spatial_reg<D, J>(gm, Tm);
+            haar_fwd<GM, P>(gm, jl, lk);
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const float vv = fmaxf(v[i], 0.f);
+                const float gam = gm[i] * f;
+                const float shat = fmaxf(gam * gam - a.power_a * vv, 0.f);
+                const float den = shat + a.s_v * vv;
+                const float G = den > 0.f ? shat / den : 0.f;
+                float t;
+                if (a.wmodel == BMND_WEIGHT_CLASSIC) t = G * G;
+                else if (a.wmodel == BMND_WEIGHT_VARIANCE) t = G * G * vv;
+                else t = G * G * vv + (1.f - G) * (1.f - G) * shat;
+                if (a.wdomain == BMND_WDOMAIN_WINDOWED) t *= nd_window_metric<D, J>(tab, a, i);
+                rl += act ? t : 0.f;
+                v[i] = G * f;   // the gain with the row scale of Y folded in
+            }
+            if constexpr (OM != 2) {
+                // ---- observation: C = G Y
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    const float ld = yo[patch_off<D, J>(i, g)];
+                    x[i] = act ? ld : 0.f;
+                }
+                spatial_reg<D, J>(x, Tm);
+                haar_fwd<GM, P>(x, jl, lk);
+#pragma unroll
+                for (int i = 0; i < P; ++i) x[i] *= v[i];
+            }
+        } else {
+            // ---- observation and its variance map
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const float ld = yo[patch_off<D, J>(i, g)];
+                const float yv = act ? ld : 0.f;
+                x[i] = yv;
+                gn2 = __builtin_fmaf(yv, yv, gn2);
+                v[i] = fmaxf(yv, 0.f);
+            }
+            spatial_reg<D, J>(x, Tm);
+            haar_fwd<GM, P>(x, jl, lk);
+            if (poisson) {
+                spatial_reg<D, J>(v, T2m);
+                haar_sq<GM, P>(v, jl, lk);
+                const float sc = a.s_p * f2;
+#pragma unroll
+                for (int i = 0; i < P; ++i) v[i] *= sc;
+            } else {
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    const float rn = axis_prod<D, J>(tab, a.t.rn, i);
+                    v[i] = a.sigma2 * rn * rn;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i) x[i] *= f;
+            if constexpr (SH == BMND_SHRINK_HARD) {
+                const float gn = fsqrt(seg_sum<GM>(gn2));
+                // FP32 decisions and weight terms at once (the variances die
+                // here); the coefficients in the FP32 error band are recorded
+                unsigned long long keep = 0, near = 0;
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    const float vv = fmaxf(v[i], 0.f);
+                    const float thr = a.lambda * fsqrt(vv);
+                    const float ay = fabsf(x[i]);
+                    // FP32 error band (transform round-off is bounded by the
+                    // row norm times the group norm)
+                    const float band = 1e-5f * (axis_prod<D, J>(tab, a.t.rn, i) * gn + thr);
+                    const bool kp = act && ay > thr;
+                    keep |= (unsigned long long)kp << i;
+                    near |= (unsigned long long)(act && fabsf(ay - thr) <= band) << i;
+                    float t = kp ? 1.f : 0.f;
+                    if (a.wmodel == BMND_WEIGHT_VARIANCE) t *= vv;
+                    if (a.wdomain == BMND_WDOMAIN_WINDOWED) t *= nd_window_metric<D, J>(tab, a, i);
+                    rl += t;
+                    x[i] = kp ? x[i] : 0.f;
+                }
+                // FP64 decisions in the band, one coefficient at a time; a
+                // changed decision sets the coefficient from its FP64 value
+                // and corrects the weight term
+                for (;;) {
+                    const unsigned long long mk = __ballot(near != 0);
+                    if (mk == 0) break;
+                    const int src = __ffsll((long long)mk) - 1;
+                    const unsigned nlo = unsigned(__shfl(int(unsigned(near & 0xffffffffull)), src));
+                    const unsigned nhi = unsigned(__shfl(int(unsigned(near >> 32)), src));
+                    const int q = nlo != 0 ? __ffs(int(nlo)) - 1 : 32 + __ffs(int(nhi)) - 1;
+                    double cy = 0.0, cv = 0.0;
+                    const bool kp = ht_decide64<D, J, GM>(a, tab64, yo, seg == src / GM && act,
+                                                          src % GM, jl, K, q, &cy, &cv);
+                    if (lane == src) {
+                        near &= ~(1ull << q);
+                        const bool was = (keep >> q) & 1ull;
+                        if (kp != was) {
+                            keep ^= 1ull << q;
+                            float t = 1.f;
+                            if (a.wmodel == BMND_WEIGHT_VARIANCE) t *= float(fmax(cv, 0.0));
+                            if (a.wdomain == BMND_WDOMAIN_WINDOWED)
+                                t *= nd_window_metric<D, J>(tab, a, q);
+                            rl += kp ? t : -t;
+                            const float cq = kp ? float(cy) : 0.f;
+#pragma unroll
+                            for (int i = 0; i < P; ++i) x[i] = i == q ? cq : x[i];
+                        }
+                    }
+                }
+            } else {
+                // soft threshold (eq. soft-threshold), attenuation |C| / |Y|
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    const float vv = fmaxf(v[i], 0.f);
+                    const float Yv = x[i];
+                    const float m = fmaxf(fabsf(Yv) - a.lambda * fsqrt(vv), 0.f);
+                    const float at = Yv != 0.f ? m / fabsf(Yv) : 0.f;
+                    float t = at * at;
+                    if (a.wmodel == BMND_WEIGHT_VARIANCE) t *= vv;
+                    if (a.wdomain == BMND_WDOMAIN_WINDOWED) t *= nd_window_metric<D, J>(tab, a, i);
+                    rl += act ? t : 0.f;
+                    x[i] = Yv > 0.f ? m : (Yv < 0.f ? -m : 0.f);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i) x[i] *= f;   // B^T F: the synthesis scale
+        }
+        if constexpr (WIE && OM != 2) {
+            // x holds G f Y; the synthesis scale f again
+#pragma unroll
+            for (int i = 0; i < P; ++i) x[i] *= f;
+        }
+
+        // ---- weights (Def. aggregation-weight scope): group R = sum_l r_l;
+        // patch R_j = sum over the rows whose support holds j of r_l / support
+        float wj;
+        if (a.wscope == BMND_SCOPE_GROUP) {
+            const float R = seg_sum<GM>(rl);
+            wj = R > 0.f ? 1.f / R : 1.f;
+        } else {
+            const float rs = rl * f2;     // r_l / support of the lane's row
+            const int sbase = seg * GM;
+            float R = __shfl(rs, sbase);  // scaling row
+#pragma unroll
+            for (int t = 0; (1 << t) < GM; ++t) {
+                const int d = 1 << t;
+                const float r = __shfl(rs, sbase + ((jl & ~(2 * d - 1)) | d));
+                R += t < lk ? r : 0.f;
+            }
+            wj = R > 0.f ? 1.f / R : 1.f;
+        }
+        wj = act ? wj : 0.f;
+
+        if constexpr (OM == 2) {
+            // mass conservation, sweep 1: the weights only
+            if (act) unsafeAtomicAdd(&wfield[vb + org], double(wj));
+            continue;
+        } else {
+            // ---- synthesis: B^T (scales applied above), then U on every axis
+            haar_inv<GM, P>(x, jl, lk);
+            spatial_reg<D, J>(x, Um);
+            if constexpr (OM == 0) {
+                // patches (no window) and weights of every slot up to group_max
+                if (gvalid) {
+                    float* po = a.patches + (grp * a.gmax + jl) * long(P);
+#pragma unroll
+                    for (int i = 0; i < P; ++i) po[i] = act ? x[i] : 0.f;
+                    a.weights[grp * a.gmax + jl] = wj;
+                }
+                continue;
+            } else {
+                double alpha = 0.0;
+                if constexpr (OM == 3) {
+                    // alpha_g = sum zeta (y - p) / sum zeta, zeta = w omega / eta
+                    double zs = 0.0, zr = 0.0;
+                    if (act) {
+#pragma unroll 8
+                        for (int i = 0; i < P; ++i) {
+                            const int u = org + patch_off<D, J>(i, g);
+                            const float w = axis_prod<D, J>(tab, a.t.win, i);
+                            const double zeta = double(wj) * double(w) / dend[vb + u];
+                            zs += zeta;
+                            zr += zeta * (double(yb[u]) - double(x[i]));
+                        }
+                    }
+                    zs = seg_sum64<GM>(zs);
+                    zr = seg_sum64<GM>(zr);
+                    alpha = zs > 0.0 ? zr / zs : 0.0;
+                }
+                if (!act) continue;
+                if constexpr (OM == 1) unsafeAtomicAdd(&wfield[vb + org], double(wj));
+                // ---- overlap-add of w omega (p [+ alpha]) into the box (or the array)
+                bool inbox = BLK;
+                int tb = 0;
+                if constexpr (BLK) {
+                    int rem = org;
+#pragma unroll
+                    for (int d = kAx - 1; d >= 0; --d) {
+                        const int c = rem % g.L[d] - blo[d];
+                        rem /= g.L[d];
+                        inbox = inbox && c >= 0 && c + g.j[d] <= blk.E[d];
+                        tb += c * blk.S[d];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    int qq = i, toff = 0;
+#pragma unroll
+                    for (int d = D - 1; d >= 0; --d) {
+                        toff += (qq % J) * blk.S[kAx - D + d];
+                        qq /= J;
+                    }
+                    const float ww = wj * axis_prod<D, J>(tab, a.t.win, i);
+                    if constexpr (OM == 3) {
+                        const double val = double(ww) * (double(x[i]) + alpha);
+                        if (inbox) atomicAdd(&box[tb + toff], val);
+                        else unsafeAtomicAdd(&numd[vb + org + patch_off<D, J>(i, g)], val);
+                    } else {
+                        const double val = double(ww) * double(x[i]);
+                        if (inbox) atomicAdd(&box[tb + toff], val);
+                        else unsafeAtomicAdd(&numd[vb + org + patch_off<D, J>(i, g)], val);
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- flush the box: one FP64 atomic per touched voxel, rows contiguous
+    if constexpr (BLK && (OM == 1 || OM == 3)) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < blk.box_size; e += kThreads) {
+            const Acc val = box[e];
+            if (val == Acc(0)) continue;
+            int rem = e, u = 0;
+            bool in = true;
+#pragma unroll
+            for (int d = kAx - 1; d >= 0; --d) {
+                const int c = rem % blk.E[d] + blo[d];
+                rem /= blk.E[d];
+                in = in && c >= 0 && c < g.L[d];
+                u += c * g.st[d];
+            }
+            if (in) unsafeAtomicAdd(&numd[vb + u], double(val));
+        }
+    }
+}
+
+inline size_t box_bytes(const NdBlocks& blk, int out_mode)
+{
+    if (out_mode != 1 && out_mode != 3) return 0;
+    return size_t(blk.box_size) * sizeof(double);
+}
+
+template <int D, int J, int GM, int SH, int OM>
+hipError_t launch_om(const FilterArgs& a, const NdBlocks* blk, hipStream_t s)
+{
+    const Geo& g = a.g;
+    if constexpr (OM != 0) {
+        const size_t lds = box_bytes(*blk, OM);
+        const void* fn = reinterpret_cast<const void*>(&k_filter_nd<D, J, GM, SH, OM, true>);
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+            if (e != hipSuccess) return e;
+        }
+        const dim3 grid(unsigned(long(blk->nblocks) * g.batch));
+        hipLaunchKernelGGL((k_filter_nd<D, J, GM, SH, OM, true>), grid, dim3(kThreads), lds, s, a,
+                           *blk, a.y, a.pilot, a.match, a.count, a.t.f32, a.t.f64, blk->start,
+                           a.numd, a.dend, a.wfield);
+    } else {
+        const long per = long(kWaves) * (kWave / GM);
+        const long nchunk = (a.n_refs + per - 1) / per;
+        NdBlocks none{};
+        hipLaunchKernelGGL((k_filter_nd<D, J, GM, SH, 0, false>), dim3(unsigned(nchunk * g.batch)),
+                           dim3(kThreads), 0, s, a, none, a.y, a.pilot, a.match, a.count, a.t.f32,
+                           a.t.f64, nullptr, a.numd, a.dend, a.wfield);
+    }
+    return hipGetLastError();
+}
+
+template <int D, int J, int GM, int SH>
+hipError_t launch_sh(const FilterArgs& a, const NdBlocks* blk, hipStream_t s)
+{
+    switch (a.out_mode) {
+    case 0: return launch_om<D, J, GM, SH, 0>(a, blk, s);
+    case 1: return launch_om<D, J, GM, SH, 1>(a, blk, s);
+    case 2: return launch_om<D, J, GM, SH, 2>(a, blk, s);
+    default: return launch_om<D, J, GM, SH, 3>(a, blk, s);
+    }
+}
+
+}  // namespace nd
+}  // namespace bmnd

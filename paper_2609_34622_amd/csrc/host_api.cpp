@@ -361,6 +361,84 @@ const HostTables& host_tables_cached(const StageCfg& c)
     return g_host_tables.emplace(key, std::move(h)).first->second;
 }
 
+namespace {
+std::map<HostOrgKey, HostBlocks> g_host_blocks;
+struct DevBlocks {
+    const int64_t* refs = nullptr;
+    int64_t n = 0;
+    NdBlocks blk;
+};
+std::map<std::pair<int, HostOrgKey>, DevBlocks> g_dev_blocks;
+}  // namespace
+
+bool stage_uses_nd(const StageCfg& c)
+{
+    return nd_filter_supported(c.g, c.gmax, c.k_exact, c.noise == BMND_NOISE_CORRELATED, c.noise,
+                               c.shrink);
+}
+
+const HostBlocks& host_blocks_cached(const bmnd_geometry& geom, const bmnd_stage_params& sp,
+                                     const Geo& g)
+{
+    const HostOrgKey key = host_org_key(geom, sp);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_host_blocks.find(key);
+        if (it != g_host_blocks.end()) return it->second;
+    }
+    const std::vector<int64_t>& o = host_origins_cached(geom, sp);
+    HostBlocks h;
+    Geo g1 = g;
+    g1.batch = 1;
+    nd_make_blocks(g1, o, true, h.refs, h.start, h.blk);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    return g_host_blocks.emplace(key, std::move(h)).first->second;
+}
+
+// device copy of a stage's block-ordered origins and block offsets
+static const int64_t* device_blocks(const bmnd_geometry& geom, const bmnd_stage_params& sp,
+                                    const Geo& g, NdBlocks* blk, int64_t* n_refs,
+                                    std::string& err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        err = "hipGetDevice failed";
+        return nullptr;
+    }
+    const auto key = std::make_pair(dev, host_org_key(geom, sp));
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_dev_blocks.find(key);
+        if (it != g_dev_blocks.end()) {
+            *blk = it->second.blk;
+            *n_refs = it->second.n;
+            return it->second.refs;
+        }
+    }
+    const HostBlocks& h = host_blocks_cached(geom, sp, g);
+    int64_t* dr = nullptr;
+    int* ds = nullptr;
+    if (hipMalloc(&dr, std::max<size_t>(1, h.refs.size()) * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&ds, h.start.size() * sizeof(int)) != hipSuccess ||
+        hipMemcpy(dr, h.refs.data(), h.refs.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(ds, h.start.data(), h.start.size() * sizeof(int), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+        err = "allocation of the block-ordered origin list failed";
+        return nullptr;
+    }
+    DevBlocks d;
+    d.refs = dr;
+    d.n = int64_t(h.refs.size());
+    d.blk = h.blk;
+    d.blk.start = ds;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_dev_blocks[key] = d;
+    *blk = d.blk;
+    *n_refs = int64_t(h.refs.size());
+    return dr;
+}
+
 const int64_t* device_origins(const bmnd_geometry& geom, const bmnd_stage_params& sp,
                               int64_t* n_refs, hipStream_t, std::string& err)
 {
@@ -837,6 +915,7 @@ static bmnd_status denoise_layout(const bmnd_geometry* geom, const bmnd_params* 
     offs[4] = o; o += align256(vox * sizeof(double));                     // num
     offs[5] = o; o += align256(vox * sizeof(double));                     // den
     offs[6] = o; o += align256(vox * sizeof(float));                      // pilot
+    offs[7] = o; o += align256(vox * sizeof(double));                     // per-origin weights
     *total = o;
     return BMND_OK;
 }
@@ -978,6 +1057,9 @@ bmnd_status plan_denoise_host(const bmnd_geometry* geom, const bmnd_noise* noise
     one.batch = 1;
     pl->n1 = int64_t(host_origins_cached(one, params->ht).size());
     pl->n2 = int64_t(host_origins_cached(one, params->wiener).size());
+    pl->nd1 = stage_uses_nd(pl->c1) && nd_blocks_fit(host_blocks_cached(one, params->ht, pl->c1.g).blk);
+    pl->nd2 = stage_uses_nd(pl->c2) &&
+              nd_blocks_fit(host_blocks_cached(one, params->wiener, pl->c2.g).blk);
     return denoise_layout(geom, params, pl->n1, pl->n2, pl->offs, &pl->total);
 }
 
@@ -993,8 +1075,14 @@ bmnd_status plan_denoise(const bmnd_geometry* geom, const bmnd_noise* noise,
     std::string err;
     bmnd_geometry one = *geom;
     one.batch = 1;
-    pl->r1 = device_origins(one, params->ht, &pl->n1, nullptr, err);
-    pl->r2 = pl->r1 ? device_origins(one, params->wiener, &pl->n2, nullptr, err) : nullptr;
+    pl->nd1 = stage_uses_nd(pl->c1) && nd_blocks_fit(host_blocks_cached(one, params->ht, pl->c1.g).blk);
+    pl->nd2 = stage_uses_nd(pl->c2) &&
+              nd_blocks_fit(host_blocks_cached(one, params->wiener, pl->c2.g).blk);
+    pl->r1 = pl->nd1 ? device_blocks(one, params->ht, pl->c1.g, &pl->blk1, &pl->n1, err)
+                     : device_origins(one, params->ht, &pl->n1, nullptr, err);
+    if (pl->r1)
+        pl->r2 = pl->nd2 ? device_blocks(one, params->wiener, pl->c2.g, &pl->blk2, &pl->n2, err)
+                         : device_origins(one, params->wiener, &pl->n2, nullptr, err);
     if (!pl->r1 || !pl->r2) return fail(BMND_E_NOMEM, err);
     pl->t1 = device_tables(pl->c1, err);
     pl->t2 = pl->t1 ? device_tables(pl->c2, err) : nullptr;
@@ -1015,6 +1103,7 @@ hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out
     void* num = ws + pl.offs[4];
     void* den = ws + pl.offs[5];
     float* pilot = d_pilot ? d_pilot : reinterpret_cast<float*>(ws + pl.offs[6]);
+    double* wf = reinterpret_cast<double*>(ws + pl.offs[7]);
     const size_t vox = size_t(pl.c1.g.batch) * pl.c1.g.V;
     const int no_span = -1;
 
@@ -1027,15 +1116,31 @@ hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out
             e = launch_match(c, src, kappa, psum, refs, int(nr), match, count, s,
                              ht ? pl.m1 : nullptr);
         }
+        const bool nd = ht ? pl.nd1 : pl.nd2;
+        const NdBlocks* blk = ht ? &pl.blk1 : &pl.blk2;
         if (e == hipSuccess) {
             KernelSpan k(spans ? BMND_KID_ZERO : no_span, s);
             e = launch_zero(num, vox * sizeof(double), s);
-            if (e == hipSuccess) e = launch_zero(den, vox * sizeof(double), s);
+            if (e == hipSuccess) e = launch_zero(nd ? wf : den, vox * sizeof(double), s);
         }
         if (e != hipSuccess) return e;
         {
             KernelSpan k(spans ? (ht ? BMND_KID_FILTER_HT : BMND_KID_FILTER_WIENER) : no_span, s);
-            if (c.mc) {
+            if (nd) {
+                // per-origin weights W, eta = W * window, numerator in boxes
+                if (c.mc) {
+                    e = launch_filter_blocked(c, t, 2, d_y, pil, int(nr), match, count, num, den,
+                                              wf, blk, s);
+                    if (e == hipSuccess) e = launch_window_conv(c.g, t, wf, static_cast<double*>(den), s);
+                    if (e == hipSuccess)
+                        e = launch_filter_blocked(c, t, 3, d_y, pil, int(nr), match, count, num,
+                                                  den, wf, blk, s);
+                } else {
+                    e = launch_filter_blocked(c, t, 1, d_y, pil, int(nr), match, count, num, den,
+                                              wf, blk, s);
+                    if (e == hipSuccess) e = launch_window_conv(c.g, t, wf, static_cast<double*>(den), s);
+                }
+            } else if (c.mc) {
                 e = launch_filter(c, t, 2, d_y, pil, int(nr), match, count, nullptr, nullptr, num,
                                   den, s);
                 if (e == hipSuccess)

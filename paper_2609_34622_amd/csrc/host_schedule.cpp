@@ -11,6 +11,7 @@
 #include <cmath>
 
 #include "bmnd_internal.h"
+#include "filter_nd.h"
 
 namespace bmnd {
 
@@ -101,6 +102,76 @@ std::vector<int64_t> reference_origins(const bmnd_geometry& geom, const bmnd_sta
     std::sort(out.begin(), out.end());
     out.erase(std::unique(out.begin(), out.end()), out.end());
     return out;
+}
+
+// Spatial blocks for the N-D filter's overlap-add boxes.  Block extents
+// start at 3 and grow by 3 samples at a time, innermost axis first, while the box
+// (block + search window + patch per axis) stays within kBoxCap samples and
+// the launch keeps at least kMinBlocks workgroups.  The origins are listed
+// block by block (C-order over the block grid), ascending inside a block.
+void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, bool /*fp64_box*/,
+                    std::vector<int64_t>& refs_out, std::vector<int>& start, NdBlocks& blk)
+{
+    constexpr long kBoxCap = 9216;     // 72 KiB of FP64, two workgroups per compute unit
+    constexpr long kMinBlocks = 2048;  // workgroups per launch, summed over the batch
+    blk = NdBlocks{};
+    const long nref = long(refs.size());
+    const long max_refs = std::max(16L, nref * std::max(1, g.batch) / kMinBlocks);
+    int B[kAx];
+    for (int d = 0; d < kAx; ++d) B[d] = std::min(g.L[d], 3);
+    auto box = [&](const int* b) {
+        long v = 1;
+        for (int d = 0; d < kAx; ++d) v *= long(b[d] + g.W[d] + g.j[d] - 2);
+        return v;
+    };
+    auto refs_per_block = [&](const int* b) {
+        double f = 1.0;
+        for (int d = 0; d < kAx; ++d)
+            if (g.L[d] > 1) f *= double(b[d]) / double(std::max(1, g.L[d])) ;
+        return f * double(nref);
+    };
+    for (bool grew = true; grew;) {
+        grew = false;
+        for (int d = kAx - 1; d >= 0; --d) {
+            if (g.L[d] == 1 || B[d] >= g.L[d]) continue;
+            int t[kAx];
+            std::copy(B, B + kAx, t);
+            t[d] = std::min(g.L[d], B[d] + 3);
+            if (box(t) > kBoxCap || refs_per_block(t) > double(max_refs)) continue;
+            B[d] = t[d];
+            grew = true;
+        }
+    }
+    long nblocks = 1;
+    for (int d = 0; d < kAx; ++d) {
+        blk.B[d] = B[d];
+        blk.nb[d] = (g.L[d] + B[d] - 1) / B[d];
+        blk.E[d] = B[d] + g.W[d] + g.j[d] - 2;
+        nblocks *= blk.nb[d];
+    }
+    int s = 1;
+    for (int d = kAx - 1; d >= 0; --d) {
+        blk.S[d] = s;
+        s *= blk.E[d];
+    }
+    blk.box_size = s;
+    blk.nblocks = int(nblocks);
+    // counting sort by block
+    std::vector<int> bid(refs.size());
+    start.assign(size_t(nblocks) + 1, 0);
+    for (size_t k = 0; k < refs.size(); ++k) {
+        int id = 0;
+        for (int d = 0; d < kAx; ++d) {
+            const int c = int((refs[k] / g.st[d]) % g.L[d]);
+            id = id * blk.nb[d] + c / B[d];
+        }
+        bid[k] = id;
+        ++start[size_t(id) + 1];
+    }
+    for (long b = 0; b < nblocks; ++b) start[size_t(b) + 1] += start[size_t(b)];
+    refs_out.assign(refs.size(), 0);
+    std::vector<int> pos(start.begin(), start.end() - 1);
+    for (size_t k = 0; k < refs.size(); ++k) refs_out[size_t(pos[size_t(bid[k])]++)] = refs[k];
 }
 
 }  // namespace bmnd

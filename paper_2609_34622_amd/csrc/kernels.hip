@@ -15,6 +15,7 @@
 
 #include "bmnd_internal.h"
 #include "filter_common.h"
+#include "filter_nd.h"
 #include "exact_planes.h"
 #include "corr_noise.h"
 #include "match_common.h"
@@ -536,7 +537,7 @@ __device__ bool rescue_keep(const FilterArgs& a, const float* yb, const float* m
     int hoff = 0;
     for (int k = 1; k < K; k <<= 1) hoff += k * k;
     H += hoff;
-    double sy = 0.0, sv = 0.0;
+    double sy = 0.0, sv = 0.0, sm = 0.0;
     const int n = K * g.P;
     for (int e = threadIdx.x; e < n; e += kFilterThreads) {
         const int j = e / g.P, i = e - j * g.P;
@@ -547,6 +548,7 @@ __device__ bool rescue_keep(const FilterArgs& a, const float* yb, const float* m
             if (g.j[d] > 1) w *= a.t.f64[a.t.T64[d] + q[d] * g.j[d] + c[d]];
         const int u = org[j] + off[i];
         sy += w * double(yb[u]);
+        sm += fabs(w * double(yb[u]));
         double mv;
         if (a.noise == BMND_NOISE_POISSON) mv = a.s_p64 * fmax(double(mvsrc[u]), 0.0);
         else mv = a.sigma2_64;
@@ -558,9 +560,12 @@ __device__ bool rescue_keep(const FilterArgs& a, const float* yb, const float* m
     if constexpr (EXACT) {
         if (exact) sv = exact_partial(a, mvsrc, org, K, l, qidx, threadIdx.x, kFilterThreads);
     }
-    double v;
+    double v, unused;
     const double Y = block_sum2(red, sy, sv, &v);
-    return fabs(Y) > a.lambda64 * sqrt(v) * (1.0 + kTieRel);
+    const double M = block_sum2(red, sm, 0.0, &unused);
+    // zero variance: coefficients up to 1e-9 of the magnitude of their terms
+    // are rounding residues of exact zeros
+    return v > 0.0 ? fabs(Y) > a.lambda64 * sqrt(v) * (1.0 + kTieRel) : fabs(Y) > kTieRel * M;
 }
 
 template <bool EXACT>
@@ -720,9 +725,10 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter(FilterArgs a)
                 float rn = 1.f;
                 for (int d = 0; d < kAx; ++d) rn *= a.t.f32[a.t.rn[d] + q[d]];
                 const float band = 1e-5f * (rn * float(gn) + thr);
-                // v == 0 only if every source sample of the coefficient has
-                // zero variance; the decision is then Y != 0 on both sides
-                if (v > 0.f && fabsf(fabsf(Y) - thr) <= band) {
+                // v == 0 (every source sample of the coefficient has zero
+                // variance): the FP64 decision tells rounding residues of
+                // exact zeros from kept coefficients
+                if (fabsf(fabsf(Y) - thr) <= band) {
                     const int slot = atomicAdd(&misc[0], 1);
                     rescue[slot] = e;
                 }
@@ -1099,8 +1105,30 @@ hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, co
     const long groups = long(c.g.batch) * n_refs;
     if (!a.cdtab && filter_1d_supported(c.g, c.gmax, false, c.k_exact))
         return launch_filter_1d(a, c.step_last, s);
+    // per-sample denominators are needed here (out modes 1-3 of this entry
+    // point); the N-D filter serves the patch output
+    if (out_mode == 0 &&
+        nd_filter_supported(c.g, c.gmax, a.kex, a.cdtab != nullptr, c.noise, c.shrink))
+        return launch_filter_nd(a, nullptr, s);
     if (cube_filter_supported(c.g, c.gmax)) return launch_filter_cube(a, c.step_last, s);
     return launch_generic_filter(a, FilterLds(c.g, c.gmax).bytes, groups, s);
+}
+
+hipError_t launch_filter_blocked(const StageCfg& c, const DevTables& t, int out_mode,
+                                 const float* y, const float* pilot, int n_refs, const int* match,
+                                 const int* count, void* num, void* den, double* wfield,
+                                 const NdBlocks* blk, hipStream_t s)
+{
+    FilterArgs a = filter_args(c, t, out_mode);
+    a.n_refs = n_refs;
+    a.y = y;
+    a.pilot = pilot;
+    a.match = match;
+    a.count = count;
+    a.numd = static_cast<double*>(num);
+    a.dend = static_cast<double*>(den);
+    a.wfield = wfield;
+    return launch_filter_nd(a, blk, s);
 }
 
 hipError_t launch_aggregate(const StageCfg& c, const DevTables& t, int out_mode, const float* y,

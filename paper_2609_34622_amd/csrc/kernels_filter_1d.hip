@@ -686,7 +686,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                         const bool kp = lv & (q > 0.f);
                         const float ay = fabsf(Yv);
                         const float d = 1.0001e-5f * (e + ay);
-                        anynear |= lv & (v > 0.f) & (fabsf(q) <= d * (2.f * ay + d));
+                        anynear |= lv & (fabsf(q) <= d * (2.f * ay + d));
                         at_[c][r] = kp ? 1.f : 0.f;
                         C[c][r] = kp ? Yv : 0.f;
                     }
@@ -709,7 +709,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                             const bool lv = 4 * lg + r < K;
                             const float ay = fabsf(Yv);
                             const float d = 1.0001e-5f * (e + ay);
-                            const bool nr = lv & (v > 0.f) & (fabsf(q) <= d * (2.f * ay + d));
+                            const bool nr = lv & (fabsf(q) <= d * (2.f * ay + d));
                             keep |= unsigned(at_[c][r] != 0.f) << (4 * c + r);
                             near |= unsigned(nr) << (4 * c + r);
                         }
@@ -739,7 +739,7 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                         int lkv = lk;
                         asm volatile("" : "+v"(lkv));
                         const double h = haar_d(lkv, l, m16);
-                        double sy = 0.0, sv = 0.0;
+                        double sy = 0.0, sv = 0.0, sm = 0.0;
                         if (m16 < K) {
 #pragma unroll
                             for (int s = 0; s < 8; ++s) {
@@ -748,13 +748,19 @@ void k_filter_1d(FilterArgs a, int sub, int tile_cap, int tile_back, int wcap)
                                 const double w = h * T64[q * kJ + 8 * lg + s];
                                 const double xs = double(xv);
                                 sy += w * xs;
+                                sm += fabs(w * xs);
                                 sv += w * w * (poisson ? a.s_p64 * fmax(xs, 0.0) : a.sigma2_64);
                             }
                         }
                         sy = wave_sum64(sy);
                         sv = wave_sum64(sv);
-                        // strict inequality with the 1e-9 relative tie margin
-                        const bool kp = fabs(sy) > a.lambda64 * sqrt(sv) * (1.0 + 1e-9);
+                        sm = wave_sum64(sm);
+                        // strict inequality with the 1e-9 relative tie margin;
+                        // with zero variance, coefficients up to 1e-9 of the
+                        // magnitude of their terms are rounding residues of
+                        // exact zeros
+                        const bool kp = sv > 0.0 ? fabs(sy) > a.lambda64 * sqrt(sv) * (1.0 + 1e-9)
+                                                 : fabs(sy) > 1e-9 * sm;
                         if (lane == src) {
                             near &= ~(1u << bit);
                             keep = kp ? (keep | (1u << bit)) : (keep & ~(1u << bit));

@@ -406,7 +406,7 @@ void k_filter_cube(FilterArgs a, int chunk_refs)
                     // FP32 error band of the decision (transform round-off
                     // is bounded by the row norm times the group norm)
                     const float band = 1e-5f * (rn * gn + thr);
-                    if (v > 0.f && fabsf(fabsf(Yv) - thr) <= band) {
+                    if (fabsf(fabsf(Yv) - thr) <= band) {
                         const int slot = atomicAdd(&nres, 1);
                         reinterpret_cast<int*>(Bb)[slot] = e;
                     }
@@ -443,7 +443,7 @@ void k_filter_cube(FilterArgs a, int chunk_refs)
                             qq /= J;
                         }
                     }
-                    double sy = 0.0, sv = 0.0;
+                    double sy = 0.0, sv = 0.0, sm = 0.0;
                     for (int f = lane; f < n; f += kWave) {
                         const int j = f / P;
                         const int i = f - j * P;
@@ -456,6 +456,7 @@ void k_filter_cube(FilterArgs a, int chunk_refs)
                         }
                         const int u = org[j] + off[i];
                         sy += w * double(yb[u]);
+                        sm += fabs(w * double(yb[u]));
                         const double mv = a.noise == BMND_NOISE_POISSON
                                               ? a.s_p64 * fmax(double(yb[u]), 0.0)
                                               : a.sigma2_64;
@@ -470,8 +471,12 @@ void k_filter_cube(FilterArgs a, int chunk_refs)
                     }
                     sy = wave_sum64(sy);
                     sv = wave_sum64(sv);
-                    // strict inequality with the 1e-9 relative tie margin
-                    const bool keep = fabs(sy) > a.lambda64 * sqrt(sv) * (1.0 + 1e-9);
+                    sm = wave_sum64(sm);
+                    // strict inequality with the 1e-9 relative tie margin; with
+                    // zero variance, coefficients up to 1e-9 of the magnitude
+                    // of their terms are rounding residues of exact zeros
+                    const bool keep = sv > 0.0 ? fabs(sy) > a.lambda64 * sqrt(sv) * (1.0 + 1e-9)
+                                               : fabs(sy) > 1e-9 * sm;
                     if (lane == 0) Tb[e] = keep ? 1.f : 0.f;
                     wsync();
                 }

@@ -73,8 +73,11 @@ extern "C" bmnd_status bmnd_denoise_noalloc(const float* d_y, const bmnd_geometr
     // host copies of what the kernels read besides the arrays
     bmnd_geometry one = *geom;
     one.batch = 1;
-    const std::vector<int64_t>& o1 = host_origins_cached(one, params->ht);
-    const std::vector<int64_t>& o2 = host_origins_cached(one, params->wiener);
+    // N-D filter stages take their origins in block order, with block offsets
+    const HostBlocks* hb1 = pl.nd1 ? &host_blocks_cached(one, params->ht, pl.c1.g) : nullptr;
+    const HostBlocks* hb2 = pl.nd2 ? &host_blocks_cached(one, params->wiener, pl.c2.g) : nullptr;
+    const std::vector<int64_t>& o1 = hb1 ? hb1->refs : host_origins_cached(one, params->ht);
+    const std::vector<int64_t>& o2 = hb2 ? hb2->refs : host_origins_cached(one, params->wiener);
     const HostTables& h1 = host_tables_cached(pl.c1);
     const HostTables& h2 = host_tables_cached(pl.c2);
 
@@ -91,6 +94,8 @@ extern "C" bmnd_status bmnd_denoise_noalloc(const float* d_y, const bmnd_geometr
     const size_t o_t2d = take(h2.f64.size() * sizeof(double));
     const size_t o_r1 = take(std::max<size_t>(1, o1.size()) * sizeof(int64_t));
     const size_t o_r2 = take(std::max<size_t>(1, o2.size()) * sizeof(int64_t));
+    const size_t o_b1 = hb1 ? take(hb1->start.size() * sizeof(int)) : 0;
+    const size_t o_b2 = hb2 ? take(hb2->start.size() * sizeof(int)) : 0;
     const size_t o_ws = take(pl.total);
     if (off > kScratchBytes)
         return fail(BMND_E_WORKSPACE,
@@ -113,6 +118,8 @@ extern "C" bmnd_status bmnd_denoise_noalloc(const float* d_y, const bmnd_geometr
     up(o_t2d, h2.f64.data(), h2.f64.size() * sizeof(double));
     up(o_r1, o1.data(), o1.size() * sizeof(int64_t));
     up(o_r2, o2.data(), o2.size() * sizeof(int64_t));
+    if (hb1) up(o_b1, hb1->start.data(), hb1->start.size() * sizeof(int));
+    if (hb2) up(o_b2, hb2->start.data(), hb2->start.size() * sizeof(int));
     if (e != hipSuccess)
         return fail(BMND_E_HIP, std::string("upload to scratch: ") + hipGetErrorString(e));
 
@@ -125,6 +132,14 @@ extern "C" bmnd_status bmnd_denoise_noalloc(const float* d_y, const bmnd_geometr
     pl.t2 = &t2;
     pl.r1 = reinterpret_cast<const int64_t*>(base + o_r1);
     pl.r2 = reinterpret_cast<const int64_t*>(base + o_r2);
+    if (hb1) {
+        pl.blk1 = hb1->blk;
+        pl.blk1.start = reinterpret_cast<const int*>(base + o_b1);
+    }
+    if (hb2) {
+        pl.blk2 = hb2->blk;
+        pl.blk2.start = reinterpret_cast<const int*>(base + o_b2);
+    }
     e = enqueue_denoise(pl, d_y, d_out, d_pilot, reinterpret_cast<char*>(base + o_ws), s, false);
     if (e != hipSuccess) return fail(BMND_E_HIP, std::string("denoise: ") + hipGetErrorString(e));
     return BMND_OK;

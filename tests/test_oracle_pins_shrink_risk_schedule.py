@@ -1,4 +1,4 @@
-"""Pins of three oracle functions against what the paper and the mathematics
+"""Pins of four oracle functions against what the paper and the mathematics
 fix, each built independently of the oracle's code here:
 
 - the soft threshold (eq. soft-threshold) and its attenuation weights, on a
@@ -11,7 +11,10 @@ fix, each built independently of the oracle's code here:
   Monte-Carlo estimate of the risk of the diagonal Wiener filter under the
   diagonal signal model;
 - the balanced reference schedule (Def. balanced reference schedule), against
-  hand-worked origin sets and an independent vectorised enumeration.
+  hand-worked origin sets and an independent vectorised enumeration;
+- the hard threshold at zero variance (eq. hard-threshold with sigma_k = 0):
+  coefficients that are 0 in exact arithmetic are dropped whatever their
+  rounding residue, nonzero ones are kept.
 """
 import os
 
@@ -260,3 +263,41 @@ def test_balanced_schedule_equals_independent_enumeration(shape, patch, step, rh
     got = O.schedule(st)
     want = balanced_origins(shape, patch, step, rho, passes)
     assert np.array_equal(got, want)
+
+
+# ------------------------------------------------ zero-variance hard threshold
+
+@pytest.mark.parametrize("spatial", ["bior1.5", "dct"])
+@pytest.mark.parametrize("K", [2, 4, 8])
+def test_zero_variance_exact_zeros_are_dropped(spatial, K):
+    # a constant negative group: the Poisson variance map [y]_+ is 0, so every
+    # threshold is 0; in exact arithmetic only the DC coefficient of the
+    # scaling row is nonzero (detail rows of H and the high-pass rows of the
+    # spatial transform sum to zero), so exactly one coefficient is kept and
+    # the classic weight is 1 / 1 -- rounding residues of the others must not
+    # count as kept coefficients
+    shape = (12, 40)
+    y = np.full(shape, -0.37)
+    org = np.arange(K, dtype=np.int32) * 4
+    st = O.Stage(shape=shape, patch=(8, 8), step=(3, 3), search=(5, 5), s_p=0.5,
+                 spatial=spatial, shrink="hard", lam=3.0, kaiser_beta=2.0)
+    Y, var, Cc, w = O.group_coeffs(st, O.STAGE_HT, y, None, org)
+    assert np.all(var == 0.0)
+    assert np.count_nonzero(Cc) == 1
+    assert np.allclose(w, 1.0, rtol=0, atol=0)
+
+
+def test_zero_variance_nonzero_coefficients_are_kept():
+    # a negative ramp: zero variance everywhere, and every coefficient whose
+    # magnitude is well above the rounding scale of its terms is kept
+    shape = (12, 40)
+    yy, xx = np.meshgrid(np.arange(12), np.arange(40), indexing="ij")
+    y = -1.0 - 0.01 * xx - 0.02 * yy
+    org = np.array([0, 5], np.int32)
+    st = O.Stage(shape=shape, patch=(8, 8), step=(3, 3), search=(5, 5), s_p=0.5,
+                 spatial="dct", shrink="hard", lam=3.0)
+    Y, var, Cc, w = O.group_coeffs(st, O.STAGE_HT, y, None, org)
+    assert np.all(var == 0.0)
+    big = np.abs(Y) > 1e-6 * np.abs(Y).max()
+    assert np.array_equal(Cc != 0, big)
+    assert np.isclose(w[0], 1.0 / big.sum(), rtol=1e-12)
