@@ -112,9 +112,12 @@ const int64_t* device_origins(const bmnd_geometry& geom, const bmnd_stage_params
 hipError_t launch_counts(const StageCfg& c, const float* y, int* kappa, int* psum, hipStream_t s);
 // Matching; kappa/psum (workspace, one int per voxel each) are used by
 // the generic count-domain path and may be NULL otherwise.
+// blk (nullable): the reference list is in these spatial blocks' order
+// (N-D matching then stages each block's search box once per workgroup)
+struct NdBlocks;
 hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* psum,
                         const int64_t* refs, int n_refs, int* match, int* count, hipStream_t s,
-                        const MomentTables* mom = nullptr);
+                        const MomentTables* mom = nullptr, const NdBlocks* blk = nullptr);
 // out_mode: 0 write patches/weights, 1 aggregate (FP64 sums), 2 mc sweep 1, 3 mc sweep 2
 hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
                          const float* pilot, int n_refs, const int* match, const int* count,

@@ -247,40 +247,79 @@ __device__ __forceinline__ float nd_window_metric(const float* __restrict__ tab,
     return axis_prod<D, J>(tab, a.t.hw, q);
 }
 
-// FP64 decision of one hard-threshold coefficient (lane src's row, spatial
-// coefficient q): the segment's lanes add their members' terms in a rolled
-// loop (it runs only for coefficients in the FP32 error band).  Returns the
-// decision and, in cy / cv, the FP64 coefficient and its variance.
+// FP64 decision of one hard-threshold coefficient per segment (the row of
+// lane p of the segment, spatial coefficient q): the segment's lanes add
+// their members' terms, separably over the patch axes (Y, its variance and
+// the magnitude of its terms), then a segment reduction.  `mine`: the lane
+// takes part.  Returns the decision and, in cy / cv, the FP64 coefficient and
+// its variance.
 template <int D, int J, int GM>
 __device__ __forceinline__ bool ht_decide64(const FilterArgs& a,
-                                                      const double* __restrict__ tab64,
-                                                      const float* __restrict__ yo, bool mine,
-                                                      int p, int jl, int K, int q, double* cy,
-                                                      double* cv)
+                                            const double* __restrict__ tab64,
+                                            const float* __restrict__ yo, bool mine, int p,
+                                            int jl, int K, int q, double* cy, double* cv)
 {
-    constexpr int P = D == 2 ? J * J : J * J * J;
     const double* __restrict__ T64 = tab64 + a.t.T64[kAx - 1];
     const bool poisson = a.noise == BMND_NOISE_POISSON;
-    double sy = 0.0, sv = 0.0, sm = 0.0;
-    if (mine) {
-        const double h = haar_entry64(p, jl, K);
-        if (h != 0.0) {
-#pragma unroll 1
-            for (int i = 0; i < P; ++i) {
-                double w = h;
-                int qq = q, ii = i;
+    int qd[3] = {0, 0, 0};   // q's digit per patch axis
+    {
+        int qq = q;
 #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    w *= T64[(qq % J) * J + (ii % J)];
-                    qq /= J;
-                    ii /= J;
+        for (int d = D - 1; d >= 0; --d) {
+            qd[d] = qq % J;
+            qq /= J;
+        }
+    }
+    double sy = 0.0, sv = 0.0, sm = 0.0;
+    const double h = mine ? haar_entry64(p, jl, K) : 0.0;
+    if (h != 0.0) {
+        if constexpr (D == 2) {
+#pragma unroll 1
+            for (int i0 = 0; i0 < J; ++i0) {
+                double ty = 0.0, tv = 0.0, tm = 0.0;
+#pragma unroll
+                for (int i1 = 0; i1 < J; ++i1) {
+                    const double t = T64[qd[1] * J + i1];
+                    const double yv = double(yo[i0 * a.g.st[kAx - 2] + i1]);
+                    ty += t * yv;
+                    tm += fabs(t * yv);
+                    tv += t * t * (poisson ? a.s_p64 * fmax(yv, 0.0) : a.sigma2_64);
                 }
-                const double yv = double(yo[patch_off<D, J>(i, a.g)]);
-                sy += w * yv;
-                sm += fabs(w * yv);
-                sv += w * w * (poisson ? a.s_p64 * fmax(yv, 0.0) : a.sigma2_64);
+                const double t0 = T64[qd[0] * J + i0];
+                sy += t0 * ty;
+                sm += fabs(t0) * tm;
+                sv += t0 * t0 * tv;
+            }
+        } else {
+#pragma unroll 1
+            for (int i0 = 0; i0 < J; ++i0) {
+                double uy = 0.0, uv = 0.0, um = 0.0;
+#pragma unroll
+                for (int i1 = 0; i1 < J; ++i1) {
+                    double ty = 0.0, tv = 0.0, tm = 0.0;
+#pragma unroll
+                    for (int i2 = 0; i2 < J; ++i2) {
+                        const double t = T64[qd[2] * J + i2];
+                        const double yv =
+                            double(yo[i0 * a.g.st[kAx - 3] + i1 * a.g.st[kAx - 2] + i2]);
+                        ty += t * yv;
+                        tm += fabs(t * yv);
+                        tv += t * t * (poisson ? a.s_p64 * fmax(yv, 0.0) : a.sigma2_64);
+                    }
+                    const double t1 = T64[qd[1] * J + i1];
+                    uy += t1 * ty;
+                    um += fabs(t1) * tm;
+                    uv += t1 * t1 * tv;
+                }
+                const double t0 = T64[qd[0] * J + i0];
+                sy += t0 * uy;
+                sm += fabs(t0) * um;
+                sv += t0 * t0 * uv;
             }
         }
+        sy *= h;
+        sm *= fabs(h);
+        sv *= h * h;
     }
     sy = seg_sum64<GM>(sy);
     sv = seg_sum64<GM>(sv);
@@ -458,7 +497,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
 #pragma unroll
             for (int i = 0; i < P; ++i) x[i] *= f;
             if constexpr (SH == BMND_SHRINK_HARD) {
-                const float gn = fsqrt(seg_sum<GM>(gn2));
+                // the largest row norm of the spatial transform times the
+                // group norm bounds the magnitude of every coefficient's terms
+                float rnmax = 1.f;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    float m = 0.f;
+#pragma unroll
+                    for (int c = 0; c < J; ++c) m = fmaxf(m, tab[a.t.rn[kAx - D + d] + c]);
+                    rnmax *= m;
+                }
+                const float gb = rnmax * fsqrt(seg_sum<GM>(gn2));
                 // FP32 decisions and weight terms at once (the variances die
                 // here); the coefficients in the FP32 error band are recorded
                 unsigned long long keep = 0, near = 0;
@@ -467,9 +516,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                     const float vv = fmaxf(v[i], 0.f);
                     const float thr = a.lambda * fsqrt(vv);
                     const float ay = fabsf(x[i]);
-                    // FP32 error band (transform round-off is bounded by the
-                    // row norm times the group norm)
-                    const float band = 1e-5f * (axis_prod<D, J>(tab, a.t.rn, i) * gn + thr);
+                    // FP32 error band: the coefficient's round-off is at most
+                    // about 18 unit roundoffs (the transform's sequential
+                    // operations) times the magnitude of its terms, which is at
+                    // most the row norm times the group norm; the threshold's
+                    // relative error is half its variance's; 3e-6 keeps a
+                    // factor of 2 over both
+                    const float band = 3e-6f * (gb + thr);
                     const bool kp = act && ay > thr;
                     keep |= (unsigned long long)kp << i;
                     near |= (unsigned long long)(act && fabsf(ay - thr) <= band) << i;
@@ -479,20 +532,24 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                     rl += t;
                     x[i] = kp ? x[i] : 0.f;
                 }
-                // FP64 decisions in the band, one coefficient at a time; a
-                // changed decision sets the coefficient from its FP64 value
-                // and corrects the weight term
+                // FP64 decisions in the band, one coefficient per segment at a
+                // time; a changed decision sets the coefficient from its FP64
+                // value and corrects the weight term
+                const unsigned long long segbits =
+                    (GM >= 64 ? ~0ull : ((1ull << GM) - 1ull)) << (seg * GM);
                 for (;;) {
                     const unsigned long long mk = __ballot(near != 0);
                     if (mk == 0) break;
-                    const int src = __ffsll((long long)mk) - 1;
+                    const unsigned long long sk = mk & segbits;
+                    const bool segact = sk != 0;
+                    const int src = segact ? __ffsll((long long)sk) - 1 : lane;
                     const unsigned nlo = unsigned(__shfl(int(unsigned(near & 0xffffffffull)), src));
                     const unsigned nhi = unsigned(__shfl(int(unsigned(near >> 32)), src));
-                    const int q = nlo != 0 ? __ffs(int(nlo)) - 1 : 32 + __ffs(int(nhi)) - 1;
+                    const int q = nlo != 0 ? __ffs(int(nlo)) - 1 : (nhi != 0 ? 32 + __ffs(int(nhi)) - 1 : 0);
                     double cy = 0.0, cv = 0.0;
-                    const bool kp = ht_decide64<D, J, GM>(a, tab64, yo, seg == src / GM && act,
-                                                          src % GM, jl, K, q, &cy, &cv);
-                    if (lane == src) {
+                    const bool kp = ht_decide64<D, J, GM>(a, tab64, yo, segact && act, src % GM,
+                                                          jl, K, q, &cy, &cv);
+                    if (segact && lane == src) {
                         near &= ~(1ull << q);
                         const bool was = (keep >> q) & 1ull;
                         if (kp != was) {

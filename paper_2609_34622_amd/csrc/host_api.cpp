@@ -362,13 +362,19 @@ const HostTables& host_tables_cached(const StageCfg& c)
 }
 
 namespace {
-std::map<HostOrgKey, HostBlocks> g_host_blocks;
+// blocks depend on the search window too (the box spans it)
+using BlkKey = std::pair<HostOrgKey, std::vector<int>>;
+BlkKey blk_key(const bmnd_geometry& geom, const bmnd_stage_params& sp)
+{
+    return BlkKey{host_org_key(geom, sp), std::vector<int>(sp.search, sp.search + geom.ndim)};
+}
+std::map<BlkKey, HostBlocks> g_host_blocks;
 struct DevBlocks {
     const int64_t* refs = nullptr;
     int64_t n = 0;
     NdBlocks blk;
 };
-std::map<std::pair<int, HostOrgKey>, DevBlocks> g_dev_blocks;
+std::map<std::pair<int, BlkKey>, DevBlocks> g_dev_blocks;
 }  // namespace
 
 bool stage_uses_nd(const StageCfg& c)
@@ -380,7 +386,7 @@ bool stage_uses_nd(const StageCfg& c)
 const HostBlocks& host_blocks_cached(const bmnd_geometry& geom, const bmnd_stage_params& sp,
                                      const Geo& g)
 {
-    const HostOrgKey key = host_org_key(geom, sp);
+    const BlkKey key = blk_key(geom, sp);
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto it = g_host_blocks.find(key);
@@ -405,7 +411,7 @@ static const int64_t* device_blocks(const bmnd_geometry& geom, const bmnd_stage_
         err = "hipGetDevice failed";
         return nullptr;
     }
-    const auto key = std::make_pair(dev, host_org_key(geom, sp));
+    const auto key = std::make_pair(dev, blk_key(geom, sp));
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto it = g_dev_blocks.find(key);
@@ -1110,14 +1116,14 @@ hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out
     auto run_stage = [&](const StageCfg& c, const DevTables& t, const int64_t* refs, int64_t nr,
                          const float* src, const float* pil, float* out) -> hipError_t {
         const bool ht = c.stage == BMND_STAGE_HT;
+        const bool nd = ht ? pl.nd1 : pl.nd2;
+        const NdBlocks* blk = ht ? &pl.blk1 : &pl.blk2;
         hipError_t e = hipSuccess;
         {
             KernelSpan k(spans ? (ht ? BMND_KID_MATCH_HT : BMND_KID_MATCH_WIENER) : no_span, s);
             e = launch_match(c, src, kappa, psum, refs, int(nr), match, count, s,
-                             ht ? pl.m1 : nullptr);
+                             ht ? pl.m1 : nullptr, nd ? blk : nullptr);
         }
-        const bool nd = ht ? pl.nd1 : pl.nd2;
-        const NdBlocks* blk = ht ? &pl.blk1 : &pl.blk2;
         if (e == hipSuccess) {
             KernelSpan k(spans ? BMND_KID_ZERO : no_span, s);
             e = launch_zero(num, vox * sizeof(double), s);

@@ -944,7 +944,7 @@ static hipError_t launch_match_mode(const MatchArgs& a, hipStream_t s)
 
 hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* psum,
                         const int64_t* refs, int n_refs, int* match, int* count, hipStream_t s,
-                        const MomentTables* mom)
+                        const MomentTables* mom, const NdBlocks* blk)
 {
     if (c.metric != BMND_METRIC_SSD) {
         // Poisson-likelihood metrics (HT stage, Poisson noise)
@@ -1027,7 +1027,7 @@ hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* ps
     }
     if (!a.bias_t && match_1d_supported(c.g, mode))
         return launch_match_1d(a, mode, c.step_last, count_limit(c), s);
-    if (match_nd_supported(c.g)) return launch_match_nd(a, mode, count_limit(c), s);
+    if (match_nd_supported(c.g)) return launch_match_nd(a, mode, count_limit(c), blk, s);
     if (mode == kCount) {
         if (!kappa || !psum) return hipErrorInvalidValue;
         hipError_t e = launch_counts(c, src, kappa, psum, s);

@@ -26,6 +26,7 @@
 
 #include "bmnd_internal.h"
 #include "match_common.h"
+#include "filter_nd.h"
 
 namespace bmnd {
 
@@ -92,73 +93,64 @@ __device__ __forceinline__ void wsync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// Per-wavefront shared scratch of the selection.
+template <int GM>
+struct WaveSel {
+    static constexpr int M = GM > 1 ? GM - 1 : 1;
+    unsigned hist[256];
+    int sel_lin[M];
+    int sel_key[M];
+    double band_x[kBandCap];
+    int band_l[kBandCap];
+    double best_x[M];
+    int best_l[M];
+    int misc[4];
+};
+
+// Matching of reference gi of array b by one wavefront.  The samples of its
+// clipped search region (window origins plus a patch) are in sx (raw counts
+// or float bit patterns), sample (c_0, ..., c_3) of the array at
+// sum_d (c_d - sorg[d]) sst[d]; xs holds ncand ints of scratch.
 template <int MODE, int GM, int J3>
-__global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
+__device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, const int* sx,
+                                          const int* sorg, const int* sst, int* xs,
+                                          WaveSel<GM>& ws)
 {
     using S = typename ScT<MODE>::T;
     constexpr bool kF = MODE != kCount;
     constexpr int MR = 64 / J3;              // most patch rows (P <= 64)
     constexpr int SEG = J3 + kRB - 1;
-    constexpr int M = GM > 1 ? GM - 1 : 1;
-    extern __shared__ __align__(16) int smem[];
-    __shared__ __align__(16) unsigned hist[256];
-    __shared__ int sel_lin[M];
-    __shared__ int sel_key[M];
-    __shared__ double band_x[kBandCap];
-    __shared__ int band_l[kBandCap];
-    __shared__ double best_x[M];
-    __shared__ int best_l[M];
-    __shared__ int misc[4];
+    constexpr int M = WaveSel<GM>::M;
+    unsigned* hist = ws.hist;
+    int* sel_lin = ws.sel_lin;
+    int* sel_key = ws.sel_key;
+    double* band_x = ws.band_x;
+    int* band_l = ws.band_l;
+    double* best_x = ws.best_x;
+    int* best_l = ws.best_l;
+    int* misc = ws.misc;
+    (void)M;
 
     const Geo& g = a.g;
-    const int lane = threadIdx.x;
-    const int b = blockIdx.x / a.n_refs;
-    const int gi = blockIdx.x - b * a.n_refs;
+    const int lane = threadIdx.x % kWave;
     const long t = long(b) * a.n_refs + gi;
     const int r = safe_origin(int(a.refs[gi]), last_origin(g));
-    const float* src = a.src + long(b) * g.V;
 
-    // ---- window origins (clipped) and the staged region
-    int lo[kAx], n[kAx], R[kAx], rc[kAx];
-    int ncand = 1, nreg = 1;
+    // ---- window origins (clipped)
+    int lo[kAx], n[kAx], rc[kAx];
+    int ncand = 1;
 #pragma unroll
     for (int d = 0; d < kAx; ++d) {
         rc[d] = (r / g.st[d]) % g.L[d];
         lo[d] = max(rc[d] - g.W[d] / 2, 0);
         const int hi = min(rc[d] + g.W[d] - 1 - g.W[d] / 2, g.ell[d]);
         n[d] = hi - lo[d] + 1;
-        R[d] = n[d] + g.j[d] - 1;
         ncand *= n[d];
-        nreg *= R[d];
     }
-    int* sx = smem;                       // [nreg + kRB] staged samples
-    int* xs = smem + nreg + kRB;          // [ncand] scores (bit patterns)
-    int base = 0;                         // lin of the region's first sample
+    // offset in sx of the region's first sample
+    int rbase = 0;
 #pragma unroll
-    for (int d = 0; d < kAx; ++d) base += lo[d] * g.st[d];
-    for (int e = lane; e < nreg + kRB; e += kWave) {
-        int v = 0;
-        if (e < nreg) {
-            int rem = e, off = 0;
-#pragma unroll
-            for (int d = kAx - 1; d >= 0; --d) {
-                off += (rem % R[d]) * g.st[d];
-                rem /= R[d];
-            }
-            const float x = src[base + off];
-            if constexpr (MODE == kCount) {
-                // non-finite or out-of-range counts are flagged (scored as 0)
-                const float rk = rintf(x * a.inv_sp);
-                const bool ok = rk >= 0.f && rk <= float(kmax);
-                if (!ok) atomicOr(a.range_flag, 1);
-                v = ok ? int(rk) : 0;
-            } else {
-                v = __float_as_int(x);
-            }
-        }
-        sx[e] = v;
-    }
-    wsync();
+    for (int d = 0; d < kAx; ++d) rbase += (lo[d] - sorg[d]) * sst[d];
 
     // ---- reference patch (rows along the last axis) and its region offsets
     const int rows = g.P / g.j[kAx - 1];
@@ -170,22 +162,13 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
         for (int d = kAx - 2; d >= 0; --d) {
             const int i = rem % g.j[d];
             rem /= g.j[d];
-            int stride = 1;
-#pragma unroll
-            for (int e = d + 1; e < kAx; ++e) stride *= R[e];
-            o += i * stride;
+            o += i * sst[d];
         }
         roff[q] = o;
     }
-    int rb = 0;  // the reference's own origin in the region
-    {
-        int stride = 1;
+    int rb = 0;  // the reference's own origin in sx
 #pragma unroll
-        for (int d = kAx - 1; d >= 0; --d) {
-            rb += (rc[d] - lo[d]) * stride;
-            stride *= R[d];
-        }
-    }
+    for (int d = 0; d < kAx; ++d) rb += (rc[d] - sorg[d]) * sst[d];
     S rp[MR][J3];
     S sr = 0;
 #pragma unroll
@@ -234,15 +217,11 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
     for (int run = lane; run < nruns; run += kWave) {
         const int line = run / rpr;
         const int c3 = (run - line * rpr) * kRB;
-        int cb = c3, rem = line;
-        {
-            int stride = R[kAx - 1];
+        int cb = rbase + c3, rem = line;
 #pragma unroll
-            for (int d = kAx - 2; d >= 0; --d) {
-                cb += (rem % n[d]) * stride;
-                rem /= n[d];
-                stride *= R[d];
-            }
+        for (int d = kAx - 2; d >= 0; --d) {
+            cb += (rem % n[d]) * sst[d];
+            rem /= n[d];
         }
         // window offset of the run's first candidate
         int wb = (lo[kAx - 1] + c3 - rc[kAx - 1] + g.W[kAx - 1] / 2);
@@ -329,12 +308,11 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
                 const float x = __int_as_float(xs[ci]);
                 if (fabsf(x - a.tau_f) <= tau_band) {
                     // FP64 score of candidate ci (lin order = C order)
-                    int rem = ci, cbo = 0, stride = 1;
+                    int rem = ci, cbo = rbase;
 #pragma unroll
                     for (int d = kAx - 1; d >= 0; --d) {
-                        cbo += (rem % n[d]) * stride;
+                        cbo += (rem % n[d]) * sst[d];
                         rem /= n[d];
-                        stride *= R[d];
                     }
                     double s = 0.0, bb = 0.0;
                     for (int q = 0; q < rows; ++q)
@@ -494,13 +472,12 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
                     if (ci == rci) continue;
                     const float x = __int_as_float(xs[ci]);
                     if (!(x <= thr)) continue;
-                    int rem = ci, cbo = 0, stride = 1, lin = 0;
+                    int rem = ci, cbo = rbase, lin = 0;
 #pragma unroll
                     for (int d = kAx - 1; d >= 0; --d) {
-                        cbo += (rem % n[d]) * stride;
+                        cbo += (rem % n[d]) * sst[d];
                         lin += (lo[d] + rem % n[d]) * g.st[d];
                         rem /= n[d];
-                        stride *= R[d];
                     }
                     double s = 0.0, bb = 0.0;
                     for (int q = 0; q < rows; ++q)
@@ -578,6 +555,142 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
     }
 }
 
+// Stages the box of `ext` samples per axis from array coordinates `org`
+// (C order, thread tid of nthreads) into sx: raw counts for count-domain
+// scoring, float bit patterns otherwise; positions outside the array are 0
+// (no candidate reads them).  Coordinates advance by the thread stride with
+// carries, without a division per sample.
+template <int MODE>
+__device__ __forceinline__ void stage_box(const MatchArgs& a, int kmax, const float* src,
+                                          const int* org, const int* ext, int total, int* sx,
+                                          int tid, int nthreads)
+{
+    const Geo& g = a.g;
+    int c[kAx], dc[kAx];
+    {
+        int rem = tid, st = nthreads;
+#pragma unroll
+        for (int d = kAx - 1; d >= 0; --d) {
+            c[d] = rem % ext[d];
+            rem /= ext[d];
+            dc[d] = st % ext[d];
+            st /= ext[d];
+        }
+    }
+    for (int e = tid; e < total; e += nthreads) {
+        bool in = true;
+        int u = 0;
+#pragma unroll
+        for (int d = 0; d < kAx; ++d) {
+            const int x = org[d] + c[d];
+            in = in && x >= 0 && x < g.L[d];
+            u += x * g.st[d];
+        }
+        int v = 0;
+        if (in) {
+            const float x = src[u];
+            if constexpr (MODE == kCount) {
+                // non-finite or out-of-range counts are flagged (scored as 0)
+                const float rk = rintf(x * a.inv_sp);
+                const bool ok = rk >= 0.f && rk <= float(kmax);
+                if (!ok) atomicOr(a.range_flag, 1);
+                v = ok ? int(rk) : 0;
+            } else {
+                v = __float_as_int(x);
+            }
+        }
+        sx[e] = v;
+        // advance by nthreads: add the per-axis digits with carries
+        int carry = 0;
+#pragma unroll
+        for (int d = kAx - 1; d >= 0; --d) {
+            c[d] += dc[d] + carry;
+            carry = 0;
+            while (c[d] >= ext[d]) {
+                c[d] -= ext[d];
+                ++carry;
+            }
+        }
+    }
+}
+
+// One wavefront per reference (any reference list): the reference's own
+// clipped region staged alone.
+template <int MODE, int GM, int J3>
+__global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
+{
+    extern __shared__ __align__(16) int smem[];
+    __shared__ WaveSel<GM> ws;
+    const Geo& g = a.g;
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x / a.n_refs;
+    const int gi = blockIdx.x - b * a.n_refs;
+    const int r = safe_origin(int(a.refs[gi]), last_origin(g));
+    int lo[kAx], R[kAx], sst[kAx];
+    int nreg = 1;
+#pragma unroll
+    for (int d = 0; d < kAx; ++d) {
+        const int rc = (r / g.st[d]) % g.L[d];
+        lo[d] = max(rc - g.W[d] / 2, 0);
+        const int hi = min(rc + g.W[d] - 1 - g.W[d] / 2, g.ell[d]);
+        R[d] = hi - lo[d] + g.j[d];
+        nreg *= R[d];
+    }
+    {
+        int st = 1;
+#pragma unroll
+        for (int d = kAx - 1; d >= 0; --d) {
+            sst[d] = st;
+            st *= R[d];
+        }
+    }
+    int* sx = smem;                   // [nreg + kRB] staged samples
+    int* xs = smem + nreg + kRB;      // [ncand] scores (bit patterns)
+    stage_box<MODE>(a, kmax, a.src + long(b) * g.V, lo, R, nreg, sx, lane, kWave);
+    for (int e = nreg + lane; e < nreg + kRB; e += kWave) sx[e] = 0;
+    wsync();
+    match_one<MODE, GM, J3>(a, b, gi, sx, lo, sst, xs, ws);
+}
+
+// One workgroup per spatial block of references (the list in block order,
+// inside bmnd_denoise): the block's box (the block, the search window and a
+// patch per axis) is staged once and serves every reference of the block,
+// one wavefront per reference at a time.
+constexpr int kMWaves = 4;
+
+template <int MODE, int GM, int J3>
+__global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int kmax,
+                                                               NdBlocks blk, int ncand_max)
+{
+    extern __shared__ __align__(16) int smem[];
+    __shared__ WaveSel<GM> ws[kMWaves];
+    const Geo& g = a.g;
+    const int wave = threadIdx.x / kWave;
+    const int blkid = blockIdx.x % blk.nblocks;
+    const int b = blockIdx.x / blk.nblocks;
+    const int r0 = blk.start[blkid], r1 = blk.start[blkid + 1];
+    if (r0 >= r1) return;   // an empty block (uniform over the workgroup)
+    int blo[kAx];
+    {
+        int rem = blkid;
+#pragma unroll
+        for (int d = kAx - 1; d >= 0; --d) {
+            const int bc = rem % blk.nb[d];
+            rem /= blk.nb[d];
+            blo[d] = bc * blk.B[d] - g.W[d] / 2;
+        }
+    }
+    int* sx = smem;                                           // [box + kRB]
+    int* xs = smem + blk.box_size + kRB + wave * ncand_max;   // [ncand] per wavefront
+    stage_box<MODE>(a, kmax, a.src + long(b) * g.V, blo, blk.E, blk.box_size, sx, threadIdx.x,
+                    kMWaves * kWave);
+    for (int e = blk.box_size + int(threadIdx.x); e < blk.box_size + kRB; e += kMWaves * kWave)
+        sx[e] = 0;
+    __syncthreads();
+    for (int gi = r0 + wave; gi < r1; gi += kMWaves)
+        match_one<MODE, GM, J3>(a, b, gi, sx, blo, blk.S, xs, ws[wave]);
+}
+
 }  // namespace
 
 namespace {
@@ -595,6 +708,33 @@ hipError_t launch_nd_mode(const MatchArgs& a, int kmax, size_t lds, hipStream_t 
     default: hipLaunchKernelGGL((k_match_nd<MODE, 32, J3>), grid, dim3(kWave), lds, s, a, kmax); break;
     }
     return hipGetLastError();
+}
+
+template <int MODE, int GM, int J3>
+hipError_t launch_blk3(const MatchArgs& a, int kmax, const NdBlocks& blk, int ncand_max,
+                       size_t lds, hipStream_t s)
+{
+    const void* fn = reinterpret_cast<const void*>(&k_match_blk<MODE, GM, J3>);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid(unsigned(long(blk.nblocks) * a.g.batch));
+    hipLaunchKernelGGL((k_match_blk<MODE, GM, J3>), grid, dim3(kMWaves * kWave), lds, s, a, kmax,
+                       blk, ncand_max);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_blk(const MatchArgs& a, int kmax, const NdBlocks& blk, int ncand_max, size_t lds,
+                      hipStream_t s)
+{
+    const bool three = a.g.j[kAx - 1] == 4;
+    if (a.gmax == 16)
+        return three ? launch_blk3<MODE, 16, 4>(a, kmax, blk, ncand_max, lds, s)
+                     : launch_blk3<MODE, 16, 8>(a, kmax, blk, ncand_max, lds, s);
+    return three ? launch_blk3<MODE, 32, 4>(a, kmax, blk, ncand_max, lds, s)
+                 : launch_blk3<MODE, 32, 8>(a, kmax, blk, ncand_max, lds, s);
 }
 
 template <int MODE>
@@ -632,10 +772,25 @@ bool match_nd_supported(const Geo& g)
     return region <= kMaxRegion && cand <= kMaxCand;
 }
 
-hipError_t launch_match_nd(const MatchArgs& a, int mode, int kmax, hipStream_t s)
+hipError_t launch_match_nd(const MatchArgs& a, int mode, int kmax, const NdBlocks* blk,
+                           hipStream_t s)
 {
     int region = 0, cand = 0;
     nd_sizes(a.g, &region, &cand);
+    if (blk && (a.gmax == 16 || a.gmax == 32) &&
+        (a.g.j[kAx - 1] == 4 || a.g.j[kAx - 1] == 8)) {
+        // the block's box staged once per workgroup, beside one score array
+        // per wavefront; within a compute unit's LDS with the static scratch
+        const size_t lds = sizeof(int) * size_t(blk->box_size + kRB + kMWaves * cand);
+        if (lds + kMWaves * sizeof(WaveSel<32>) <= 160u * 1024u) {
+            switch (mode) {
+            case kCount: return launch_blk<kCount>(a, kmax, *blk, cand, lds, s);
+            case kPoissonF: return launch_blk<kPoissonF>(a, kmax, *blk, cand, lds, s);
+            case kGauss: return launch_blk<kGauss>(a, kmax, *blk, cand, lds, s);
+            default: return launch_blk<kPlain>(a, kmax, *blk, cand, lds, s);
+            }
+        }
+    }
     const size_t lds = sizeof(int) * size_t(region + kRB + cand);
     switch (mode) {
     case kCount: return launch_nd_j<kCount>(a, kmax, lds, s);

@@ -57,7 +57,11 @@ bool match_1d_supported(const Geo& g, int mode);
 // N-D arrays: P <= 64, last-axis patch extent 4, 8 or 16, staged window
 // region and candidate count up to 4096
 bool match_nd_supported(const Geo& g);
-hipError_t launch_match_nd(const MatchArgs& a, int mode, int kmax, hipStream_t s);
+// blk (nullable): the reference list is in these spatial blocks' order; one
+// workgroup per block then stages the block's box once
+struct NdBlocks;
+hipError_t launch_match_nd(const MatchArgs& a, int mode, int kmax, const NdBlocks* blk,
+                           hipStream_t s);
 hipError_t launch_match_1d(const MatchArgs& a, int mode, int step, int kmax, hipStream_t s);
 // Poisson deviance / Pearson / Anscombe-SSD matching, any shape
 hipError_t launch_match_pois(const MatchArgs& a, int metric, int kmax, hipStream_t s);

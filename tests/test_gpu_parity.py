@@ -236,6 +236,23 @@ def test_denoise_end_to_end_2d(img):
         assert err[~mask].max() < REL_OUT
 
 
+def test_denoise_same_shape_two_search_windows():
+    """One shape denoised with two search windows in turn (and the first
+    again): the spatial blocks of reference origins and their boxes, which
+    span the search window, are per window, so each result matches the
+    oracle stage by stage."""
+    s = synth.image_2d_small(1011, size=72)
+    shape, patch, step = (72, 72), (8, 8), (3, 3)
+    for search in ((15, 15), (21, 21), (15, 15)):
+        _say(f"72x72 search {search}")
+        p = params_for(shape, patch, step, search)
+        ht, wie = oracle_stages(shape, patch, step, search, s.s_p)
+        out, pilot = gpu_denoise(dev(s.y), B.geometry(shape), B.poisson(s.s_p), p)
+        assert rel_err(pilot, O.run_stage(ht, O.STAGE_HT, s.y)) < REL_OUT, search
+        out_r = O.run_stage(wie, O.STAGE_WIENER, s.y, pilot.astype(np.float64))
+        assert rel_err(out, out_r) < REL_OUT, search
+
+
 # ------------------------------------------------------------ 1-D batch
 
 def test_denoise_1d_batch():
