@@ -147,6 +147,9 @@ void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, bool /*fp64_
         blk.B[d] = B[d];
         blk.nb[d] = (g.L[d] + B[d] - 1) / B[d];
         blk.E[d] = B[d] + g.W[d] + g.j[d] - 2;
+        // last axis padded to a multiple of 4 samples: rows of a byte copy
+        // of the box then start on word boundaries
+        if (d == kAx - 1) blk.E[d] = (blk.E[d] + 3) & ~3;
         nblocks *= blk.nb[d];
     }
     int s = 1;

@@ -33,7 +33,8 @@ namespace bmnd {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kRB = 8;          // candidates per run along the last axis
+constexpr int kRB = 8;          // candidates per run along the last axis (one reference per workgroup)
+constexpr int kPad = 32;        // samples staged past a region or box (runs read beyond a row)
 constexpr int kMaxRegion = 4096;
 constexpr int kMaxCand = 4096;
 constexpr int kBandCap = 128;   // FP64 re-scored candidates per chunk
@@ -111,14 +112,19 @@ struct WaveSel {
 // clipped search region (window origins plus a patch) are in sx (raw counts
 // or float bit patterns), sample (c_0, ..., c_3) of the array at
 // sum_d (c_d - sorg[d]) sst[d]; xs holds ncand ints of scratch.
-template <int MODE, int GM, int J3>
+// sb (count mode, nullable): four byte copies of the staged counts, copy c
+// (at sb + c cst) holding staged sample k + c at byte k, so the 4 samples
+// from any sample index b form the aligned word b / 4 of copy b % 4; scores
+// then come from v_dot4_u32_u8 products (exact, counts up to 255).
+template <int MODE, int GM, int J3, int RB>
 __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, const int* sx,
                                           const int* sorg, const int* sst, int* xs,
-                                          WaveSel<GM>& ws)
+                                          WaveSel<GM>& ws, const unsigned char* sb, int cst)
 {
     using S = typename ScT<MODE>::T;
     constexpr bool kF = MODE != kCount;
     constexpr int MR = 64 / J3;              // most patch rows (P <= 64)
+    constexpr int kRB = RB;                  // candidates per run along the last axis
     constexpr int SEG = J3 + kRB - 1;
     constexpr int M = WaveSel<GM>::M;
     unsigned* hist = ws.hist;
@@ -169,15 +175,18 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     int rb = 0;  // the reference's own origin in sx
 #pragma unroll
     for (int d = 0; d < kAx; ++d) rb += (rc[d] - sorg[d]) * sst[d];
+    const bool bytes = MODE == kCount && sb != nullptr;
     S rp[MR][J3];
     S sr = 0;
+    if (!bytes) {
 #pragma unroll
-    for (int q = 0; q < MR; ++q)
+        for (int q = 0; q < MR; ++q)
 #pragma unroll
-        for (int i = 0; i < J3; ++i) {
-            rp[q][i] = q < rows ? from_int<S>(sx[rb + roff[q] + i]) : S(0);
-            sr += rp[q][i];
-        }
+            for (int i = 0; i < J3; ++i) {
+                rp[q][i] = q < rows ? from_int<S>(sx[rb + roff[q] + i]) : S(0);
+                sr += rp[q][i];
+            }
+    }
     int rci = 0;  // the reference's candidate index
     {
         int stride = 1;
@@ -214,7 +223,64 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     const int n3 = n[kAx - 1];
     const int rpr = (n3 + kRB - 1) / kRB;  // runs per line
     const int nruns = (ncand / n3) * rpr;
-    for (int run = lane; run < nruns; run += kWave) {
+    if constexpr (MODE == kCount) {
+        if (bytes) {
+            // count mode on bytes: SSD = sum p^2 + sum q^2 - 2 sum pq, bias
+            // gamma (sum p + sum q), every sum a v_dot4_u32_u8 chain
+            constexpr int NW = J3 / 4;     // words per patch row
+            constexpr unsigned kOnes = 0x01010101u;
+            unsigned rw[MR][NW];
+            unsigned sp2 = 0, sp1 = 0;
+            {
+                const unsigned* cr =
+                    reinterpret_cast<const unsigned*>(sb + (rb & 3) * cst) + (rb >> 2);
+#pragma unroll
+                for (int q = 0; q < MR; ++q)
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        rw[q][w] = q < rows ? cr[(roff[q] >> 2) + w] : 0u;
+                        sp2 = __builtin_amdgcn_udot4(rw[q][w], rw[q][w], sp2, false);
+                        sp1 = __builtin_amdgcn_udot4(rw[q][w], kOnes, sp1, false);
+                    }
+            }
+            for (int run = lane; run < nruns; run += kWave) {
+                const int line = run / rpr;
+                const int c3 = (run - line * rpr) * kRB;
+                int cb = rbase + c3, rem = line;
+#pragma unroll
+                for (int d = kAx - 2; d >= 0; --d) {
+                    cb += (rem % n[d]) * sst[d];
+                    rem /= n[d];
+                }
+#pragma unroll
+                for (int u = 0; u < kRB; ++u) {
+                    const int bb = cb + u;
+                    const unsigned* cp =
+                        reinterpret_cast<const unsigned*>(sb + (bb & 3) * cst) + (bb >> 2);
+                    unsigned pq = 0, q2 = 0, q1 = 0;
+#pragma unroll
+                    for (int q = 0; q < MR; ++q) {
+                        if (q < rows) {
+#pragma unroll
+                            for (int w = 0; w < NW; ++w) {
+                                const unsigned qw = cp[(roff[q] >> 2) + w];
+                                pq = __builtin_amdgcn_udot4(rw[q][w], qw, pq, false);
+                                q2 = __builtin_amdgcn_udot4(qw, qw, q2, false);
+                                q1 = __builtin_amdgcn_udot4(qw, kOnes, q1, false);
+                            }
+                        }
+                    }
+                    const int ci = line * n3 + c3 + u;
+                    if (c3 + u < n3) {
+                        int x = int(sp2 + q2 - 2u * pq) - a.gamma_i * int(sp1 + q1);
+                        if (ci == rci) x = INT_MAX;
+                        xs[ci] = x;
+                    }
+                }
+            }
+        }
+    }
+    for (int run = lane; run < (bytes ? 0 : nruns); run += kWave) {
         const int line = run / rpr;
         const int c3 = (run - line * rpr) * kRB;
         int cb = rbase + c3, rem = line;
@@ -644,12 +710,12 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
             st *= R[d];
         }
     }
-    int* sx = smem;                   // [nreg + kRB] staged samples
-    int* xs = smem + nreg + kRB;      // [ncand] scores (bit patterns)
+    int* sx = smem;                   // [nreg + kPad] staged samples
+    int* xs = smem + nreg + kPad;     // [ncand] scores (bit patterns)
     stage_box<MODE>(a, kmax, a.src + long(b) * g.V, lo, R, nreg, sx, lane, kWave);
-    for (int e = nreg + lane; e < nreg + kRB; e += kWave) sx[e] = 0;
+    for (int e = nreg + lane; e < nreg + kPad; e += kWave) sx[e] = 0;
     wsync();
-    match_one<MODE, GM, J3>(a, b, gi, sx, lo, sst, xs, ws);
+    match_one<MODE, GM, J3, kRB>(a, b, gi, sx, lo, sst, xs, ws, nullptr, 0);
 }
 
 // One workgroup per spatial block of references (the list in block order,
@@ -680,15 +746,82 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
             blo[d] = bc * blk.B[d] - g.W[d] / 2;
         }
     }
-    int* sx = smem;                                           // [box + kRB]
-    int* xs = smem + blk.box_size + kRB + wave * ncand_max;   // [ncand] per wavefront
-    stage_box<MODE>(a, kmax, a.src + long(b) * g.V, blo, blk.E, blk.box_size, sx, threadIdx.x,
-                    kMWaves * kWave);
-    for (int e = blk.box_size + int(threadIdx.x); e < blk.box_size + kRB; e += kMWaves * kWave)
-        sx[e] = 0;
+    constexpr int RB = J3 == 4 ? 11 : 13;   // runs fill 11- and 39-candidate lines
+    int* sx = smem;                                            // [box + kPad]
+    int* xs = smem + blk.box_size + kPad + wave * ncand_max;   // [ncand] per wavefront
+    const float* src = a.src + long(b) * g.V;
+    const unsigned char* sb = nullptr;
+    int cst = 0;
+    if constexpr (MODE == kCount) {
+        // counts of the box as four byte-shifted copies in the same LDS (each
+        // copy box + kPad bytes, zero past the box) when every count fits a
+        // byte; otherwise staged again as integers below
+        __shared__ int big;
+        if (threadIdx.x == 0) big = 0;
+        cst = (blk.box_size + kPad + 3) & ~3;
+        unsigned char* cb = reinterpret_cast<unsigned char*>(smem);
+        __syncthreads();
+        for (int e = blk.box_size + int(threadIdx.x); e < cst + 3; e += kMWaves * kWave)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (e - c >= 0 && e - c < cst) cb[c * cst + e - c] = 0;
+        {
+            int c[kAx], dc[kAx];
+            int rem = threadIdx.x, st = kMWaves * kWave;
+#pragma unroll
+            for (int d = kAx - 1; d >= 0; --d) {
+                c[d] = rem % blk.E[d];
+                rem /= blk.E[d];
+                dc[d] = st % blk.E[d];
+                st /= blk.E[d];
+            }
+            bool over = false;
+            for (int e = threadIdx.x; e < blk.box_size; e += kMWaves * kWave) {
+                bool in = true;
+                int u = 0;
+#pragma unroll
+                for (int d = 0; d < kAx; ++d) {
+                    const int x = blo[d] + c[d];
+                    in = in && x >= 0 && x < g.L[d];
+                    u += x * g.st[d];
+                }
+                int v = 0;
+                if (in) {
+                    const float rk = rintf(src[u] * a.inv_sp);
+                    const bool ok = rk >= 0.f && rk <= float(kmax);
+                    if (!ok) atomicOr(a.range_flag, 1);
+                    v = ok ? int(rk) : 0;
+                }
+                over = over || v > 255;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (e - k >= 0) cb[k * cst + e - k] = (unsigned char)(v & 255);
+                int carry = 0;
+#pragma unroll
+                for (int d = kAx - 1; d >= 0; --d) {
+                    c[d] += dc[d] + carry;
+                    carry = 0;
+                    while (c[d] >= blk.E[d]) {
+                        c[d] -= blk.E[d];
+                        ++carry;
+                    }
+                }
+            }
+            if (over) atomicOr(&big, 1);
+        }
+        __syncthreads();
+        if (big == 0) sb = cb;
+    }
+    if (sb == nullptr) {
+        if constexpr (MODE == kCount) __syncthreads();   // the byte copies are done with
+        stage_box<MODE>(a, kmax, src, blo, blk.E, blk.box_size, sx, threadIdx.x, kMWaves * kWave);
+        for (int e = blk.box_size + int(threadIdx.x); e < blk.box_size + kPad;
+             e += kMWaves * kWave)
+            sx[e] = 0;
+    }
     __syncthreads();
     for (int gi = r0 + wave; gi < r1; gi += kMWaves)
-        match_one<MODE, GM, J3>(a, b, gi, sx, blo, blk.S, xs, ws[wave]);
+        match_one<MODE, GM, J3, RB>(a, b, gi, sx, blo, blk.S, xs, ws[wave], sb, cst);
 }
 
 }  // namespace
@@ -781,7 +914,7 @@ hipError_t launch_match_nd(const MatchArgs& a, int mode, int kmax, const NdBlock
         (a.g.j[kAx - 1] == 4 || a.g.j[kAx - 1] == 8)) {
         // the block's box staged once per workgroup, beside one score array
         // per wavefront; within a compute unit's LDS with the static scratch
-        const size_t lds = sizeof(int) * size_t(blk->box_size + kRB + kMWaves * cand);
+        const size_t lds = sizeof(int) * size_t(blk->box_size + kPad + kMWaves * cand);
         if (lds + kMWaves * sizeof(WaveSel<32>) <= 160u * 1024u) {
             switch (mode) {
             case kCount: return launch_blk<kCount>(a, kmax, *blk, cand, lds, s);
@@ -791,7 +924,7 @@ hipError_t launch_match_nd(const MatchArgs& a, int mode, int kmax, const NdBlock
             }
         }
     }
-    const size_t lds = sizeof(int) * size_t(region + kRB + cand);
+    const size_t lds = sizeof(int) * size_t(region + kPad + cand);
     switch (mode) {
     case kCount: return launch_nd_j<kCount>(a, kmax, lds, s);
     case kPoissonF: return launch_nd_j<kPoissonF>(a, kmax, lds, s);
