@@ -162,22 +162,31 @@ def candidates_per_ref(shape, patch, search, refs):
     return n - 1
 
 
-# kernel name fragments of the library's kernels in rocprofv3 output (a
-# stage may run two kernels: byte-count matching and its record fallback)
-KERNEL_SYMBOLS = {"filter_ht": [("k_filter_1d", "<0,"), ("k_filter_1d", "<1,")],
-                  "filter_wiener": [("k_filter_1d", "<2,")],
-                  "match_ht": [("k_match_1d_u8", ""), ("k_match_1d_rec", ""), ("k_match_1d_f", "<2,"),
-                               ("k_match_nd", "<0,")],
-                  "match_wiener": [("k_match_1d_f", "<3,"), ("k_match_nd", "<3,")]}
+# kernel names of the library's kernels in rocprofv3 output, by stage (a
+# stage may run two kernels: byte-count matching and its record fallback;
+# the N-D filter runs two sweeps under mass conservation).  The window
+# convolution that turns per-origin weights into the denominator runs once in
+# each N-D filter stage; its counters are added to both filter stages.
+KERNEL_SYMBOLS = {
+    "filter_ht": [r"k_filter_1d<[01],", r"k_filter_nd<\d+,\d+,\d+,[01],"],
+    "filter_wiener": [r"k_filter_1d<2,", r"k_filter_nd<\d+,\d+,\d+,2,"],
+    "match_ht": [r"k_match_1d_u8<", r"k_match_1d_rec<", r"k_match_1d_f<2,", r"k_match_nd<0,",
+                 r"k_match_blk<0,"],
+    "match_wiener": [r"k_match_1d_f<3,", r"k_match_nd<3,", r"k_match_blk<3,"],
+    "window_conv": [r"k_window_conv<"],
+}
 
 
 def kernel_label(kname: str):
+    import re
+
     flat = kname.replace(" ", "")
     for k, pats in KERNEL_SYMBOLS.items():
-        for frag, tmpl in pats:
-            if frag + "<" in flat and tmpl in flat:
-                return k
+        if any(re.search(pat, flat) for pat in pats):
+            return k
     return None
+
+
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 
 
@@ -219,10 +228,17 @@ def summarize_pmc(dbs, copy_mib: int):
     out = {"kernel_sources": _kernel_sources_digest(), "copy_probe_mib": copy_mib, "kernels": {}}
     cp = vals.get("copy", {})
     out["copy_probe_kib"] = cp
+    conv = vals.get("window_conv", {})
     for k, v in vals.items():
         if k == "copy":
             continue
-        out["kernels"][k] = {"fetch_kib": v.get("FETCH_SIZE"), "write_kib": v.get("WRITE_SIZE")}
+        e = {"fetch_kib": v.get("FETCH_SIZE"), "write_kib": v.get("WRITE_SIZE")}
+        if k.startswith("filter") and conv:
+            # one window convolution per N-D filter stage launch
+            e = {"fetch_kib": e["fetch_kib"] + conv.get("FETCH_SIZE", 0.0),
+                 "write_kib": e["write_kib"] + conv.get("WRITE_SIZE", 0.0),
+                 "includes_window_conv": True}
+        out["kernels"][k] = e
     out["note"] = ("scale: bytes = KiB * 1024 * (copy bytes / copy KiB*1024) per counter; "
                    "copy bytes = --copy-probe-mib MiB read and written")
     return out
@@ -468,14 +484,15 @@ def _params(B, w):
 
 
 def _peak(kernel: str, workload: str):
-    """(bound, peak, unit) of a kernel by the instructions it issues: the 1-D
-    count matcher multiplies bytes with v_dot4_u32_u8, the other count
-    matchers with 32-bit integer VALU; the 1-D filter runs its spatial
-    products on the matrix cores (split half precision), every other kernel
-    on the FP32 VALU."""
+    """(bound, peak, unit) of a kernel by the instructions it issues: the
+    count matchers multiply bytes with v_dot4_u32_u8 (4 multiply-adds per
+    lane; the 32-bit integer path runs only where a count exceeds 255, so the
+    dot4 rate is the stricter peak); the 1-D filter runs its spatial products
+    on the matrix cores (split half precision), every other kernel on the
+    FP32 VALU."""
     one_d = workload.startswith("ecg")
     if kernel == "match_ht":
-        return ("alu", PEAK_DOT4_TOPS, "TOP/s") if one_d else ("alu", PEAK_INT32_TOPS, "TOP/s")
+        return "alu", PEAK_DOT4_TOPS, "TOP/s"
     if kernel.startswith("filter") and one_d:
         return "mfma", PEAK_FP32_TFLOPS, "TFLOP/s"
     return "alu", PEAK_FP32_TFLOPS, "TFLOP/s"

@@ -74,6 +74,39 @@ __device__ __forceinline__ int wsum(int v)
     return v;
 }
 
+__device__ __forceinline__ unsigned wmin_u(unsigned v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, unsigned(__shfl_xor(int(v), o)));
+    return v;
+}
+
+__device__ __forceinline__ unsigned wmax_u(unsigned v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, unsigned(__shfl_xor(int(v), o)));
+    return v;
+}
+
+// Offsets of the patch rows (runs along the last axis) of a patch in a
+// staged region of strides sst, rows in C order over the other axes.
+template <int MR>
+__device__ __forceinline__ void row_offsets(const Geo& g, const int* sst, int (&roff)[MR])
+{
+    const int rows = g.P / g.j[kAx - 1];
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+        int rem = q < rows ? q : 0, o = 0;
+#pragma unroll
+        for (int d = kAx - 2; d >= 0; --d) {
+            const int i = rem % g.j[d];
+            rem /= g.j[d];
+            o += i * sst[d];
+        }
+        roff[q] = o;
+    }
+}
+
 // exclusive prefix sum over the lanes of the wave
 __device__ __forceinline__ int wscan_ex(int v)
 {
@@ -118,7 +151,8 @@ struct WaveSel {
 // then come from v_dot4_u32_u8 products (exact, counts up to 255).
 template <int MODE, int GM, int J3, int RB>
 __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, const int* sx,
-                                          const int* sorg, const int* sst, int* xs,
+                                          const int* sorg, const int* sst,
+                                          const int (&roff)[64 / J3], int* xs,
                                           WaveSel<GM>& ws, const unsigned char* sb, int cst)
 {
     using S = typename ScT<MODE>::T;
@@ -158,20 +192,8 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
 #pragma unroll
     for (int d = 0; d < kAx; ++d) rbase += (lo[d] - sorg[d]) * sst[d];
 
-    // ---- reference patch (rows along the last axis) and its region offsets
+    // ---- reference patch (rows along the last axis, at offsets roff)
     const int rows = g.P / g.j[kAx - 1];
-    int roff[MR];
-#pragma unroll
-    for (int q = 0; q < MR; ++q) {
-        int rem = q < rows ? q : 0, o = 0;
-#pragma unroll
-        for (int d = kAx - 2; d >= 0; --d) {
-            const int i = rem % g.j[d];
-            rem /= g.j[d];
-            o += i * sst[d];
-        }
-        roff[q] = o;
-    }
     int rb = 0;  // the reference's own origin in sx
 #pragma unroll
     for (int d = 0; d < kAx; ++d) rb += (rc[d] - sorg[d]) * sst[d];
@@ -342,10 +364,14 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     if constexpr (kF) tau_band = float(kTieBand) * (fabsf(a.tau_f) + bmag);
     const unsigned kbig = okey(bigv<S>());  // excluded: the reference, non-finite scores
     int acc = 0, namb = 0, nfin = 0;
+    unsigned kmn = 0xFFFFFFFFu, kmx = 0u;   // range of the finite keys
     for (int ci = lane; ci < ncand; ci += kWave) {
         const S x = from_int<S>(xs[ci]);
-        if (ci == rci || okey(x) == kbig) continue;
+        const unsigned kx = okey(x);
+        if (ci == rci || kx == kbig) continue;
         ++nfin;
+        kmn = min(kmn, kx);
+        kmx = max(kmx, kx);
         if constexpr (MODE == kCount) {
             acc += x < a.tau_i;
         } else {
@@ -410,10 +436,21 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
         return;
     }
 
-    // ---- the need-th smallest key: radix select, 8 bits at a time
-    unsigned prefix = 0, pmask = 0;
+    // ---- the need-th smallest key: radix select, 8 bits at a time, from
+    // the highest byte in which the finite keys differ (the bytes above it
+    // are common to all of them)
+    kmn = wmin_u(kmn);
+    kmx = wmax_u(kmx);
+    const unsigned kdiff = kmn ^ kmx;
+    int shift0 = -8;   // all finite keys equal: that key is the need-th
+    unsigned pmask = 0xFFFFFFFFu;
+    if (kdiff != 0u) {
+        shift0 = ((31 - __clz(kdiff)) >> 3) << 3;
+        pmask = shift0 >= 24 ? 0u : (0xFFFFFFFFu << (shift0 + 8));
+    }
+    unsigned prefix = kmn & pmask;
     int rank = need;  // 1-based rank of the target within the current prefix
-    for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int shift = shift0; shift >= 0; shift -= 8) {
         for (int h = lane; h < 256; h += kWave) hist[h] = 0u;
         wsync();
         for (int ci = lane; ci < ncand; ci += kWave) {
@@ -715,7 +752,9 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
     stage_box<MODE>(a, kmax, a.src + long(b) * g.V, lo, R, nreg, sx, lane, kWave);
     for (int e = nreg + lane; e < nreg + kPad; e += kWave) sx[e] = 0;
     wsync();
-    match_one<MODE, GM, J3, kRB>(a, b, gi, sx, lo, sst, xs, ws, nullptr, 0);
+    int roff[64 / J3];
+    row_offsets(g, sst, roff);
+    match_one<MODE, GM, J3, kRB>(a, b, gi, sx, lo, sst, roff, xs, ws, nullptr, 0);
 }
 
 // One workgroup per spatial block of references (the list in block order,
@@ -820,8 +859,10 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
             sx[e] = 0;
     }
     __syncthreads();
+    int roff[64 / J3];
+    row_offsets(g, blk.S, roff);
     for (int gi = r0 + wave; gi < r1; gi += kMWaves)
-        match_one<MODE, GM, J3, RB>(a, b, gi, sx, blo, blk.S, xs, ws[wave], sb, cst);
+        match_one<MODE, GM, J3, RB>(a, b, gi, sx, blo, blk.S, roff, xs, ws[wave], sb, cst);
 }
 
 }  // namespace
