@@ -77,6 +77,7 @@ def lib():
         sig = {
             "orc_shift_list": (C.c_int, [i32, i32, d, vp, i32]),
             "orc_schedule": (i64, [P, vp, i64]),
+            "orc_coverage": (C.c_int, [P, vp, vp]),
             "orc_haar_matrix": (C.c_int, [i32, vp]),
             "orc_spatial_matrices": (C.c_int, [i32, i32, vp, vp]),
             "orc_bior15_filters": (C.c_int, [vp, vp]),
@@ -241,6 +242,17 @@ def schedule(st: Stage, stage: int = STAGE_HT) -> np.ndarray:
     out = np.zeros(max(n, 1), np.int64)
     lib().orc_schedule(C.byref(c), _ptr(out), n)
     return out[:n]
+
+
+def coverage(st: Stage, stage: int = STAGE_HT):
+    """Coverage map C of the stage's schedule (array shape, uint32) and its
+    (mean, standard deviation, CV): section Experiments, Shift Schedule
+    Analysis."""
+    c = st.cfg(stage)
+    cov = np.zeros(tuple(int(v) for v in st.shape), np.uint32)
+    stats = np.zeros(3)
+    _check(lib().orc_coverage(C.byref(c), _ptr(cov), _ptr(stats)), "coverage")
+    return cov, float(stats[0]), float(stats[1]), float(stats[2])
 
 
 def haar(K: int) -> np.ndarray:

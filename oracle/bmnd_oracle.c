@@ -219,6 +219,64 @@ int64_t orc_schedule(const orc_cfg* c, int64_t* out, int64_t cap)
     return nu;
 }
 
+/* Coverage map of a schedule (section Experiments, Shift Schedule
+ * Analysis): C(x) counts the scheduled reference patches r + B (r an origin
+ * of the schedule, B the patch support) that contain sample x; mean and
+ * population standard deviation of C over the whole array, and their ratio,
+ * the coefficient of variation.  Written as the definition: every origin
+ * adds one over its patch.  cov (V entries, may be NULL) receives C;
+ * stats[0..2] = mean, standard deviation, CV.  Returns 0, <0 on error. */
+int orc_coverage(const orc_cfg* c, uint32_t* cov, double* stats)
+{
+    int64_t n = orc_schedule(c, NULL, 0);
+    if (n < 0) return (int)n;
+    const int D = c->ndim;
+    int64_t st[ORC_MAXD];
+    strides_of(c, st);
+    int64_t V = 1, P = 1;
+    for (int d = 0; d < D; ++d) {
+        V *= c->shape[d];
+        P *= c->patch[d];
+    }
+    int64_t* refs = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    uint32_t* C = (uint32_t*)calloc((size_t)V, sizeof(uint32_t));
+    if (!refs || !C) {
+        free(refs);
+        free(C);
+        return -2;
+    }
+    orc_schedule(c, refs, n);
+    for (int64_t i = 0; i < n; ++i) {
+        /* every sample of the patch at origin refs[i] */
+        for (int64_t k = 0; k < P; ++k) {
+            int64_t rem = k, lin = refs[i];
+            for (int d = D - 1; d >= 0; --d) {
+                lin += (rem % c->patch[d]) * st[d];
+                rem /= c->patch[d];
+            }
+            C[lin] += 1u;
+        }
+    }
+    double sum = 0.0;
+    for (int64_t x = 0; x < V; ++x) sum += (double)C[x];
+    const double mean = sum / (double)V;
+    double ss = 0.0;
+    for (int64_t x = 0; x < V; ++x) {
+        const double dv = (double)C[x] - mean;
+        ss += dv * dv;
+    }
+    const double sd = sqrt(ss / (double)V);
+    if (stats) {
+        stats[0] = mean;
+        stats[1] = sd;
+        stats[2] = mean > 0.0 ? sd / mean : 0.0;
+    }
+    if (cov) memcpy(cov, C, sizeof(uint32_t) * (size_t)V);
+    free(refs);
+    free(C);
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Transforms (Appendix A: Haar group transform, bior1.5 / DCT spatial) */
 /* ------------------------------------------------------------------ */

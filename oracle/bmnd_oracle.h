@@ -93,6 +93,7 @@ typedef struct {
 /* All functions return 0 on success, <0 on bad arguments / allocation. */
 int     orc_shift_list(int32_t j, int32_t h, double rho, int32_t* out, int32_t cap);
 int64_t orc_schedule(const orc_cfg* c, int64_t* out, int64_t cap);
+int     orc_coverage(const orc_cfg* c, uint32_t* cov, double* stats);
 int     orc_haar_matrix(int32_t K, double* H);
 int     orc_spatial_matrices(int32_t kind, int32_t n, double* T, double* U);
 int     orc_bior15_filters(double* dec_lo10, double* rec_lo2);

@@ -8,6 +8,7 @@
 // number-shifts, eq. candidate-shift-list), indexed by the rule of the
 // selected schedule (Defs. generated / balanced / sparse / off).
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 
 #include "bmnd_internal.h"
@@ -175,6 +176,40 @@ void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, bool /*fp64_
     refs_out.assign(refs.size(), 0);
     std::vector<int> pos(start.begin(), start.end() - 1);
     for (size_t k = 0; k < refs.size(); ++k) refs_out[size_t(pos[size_t(bid[k])]++)] = refs[k];
+}
+
+// Coverage map of a schedule (section Experiments, Shift Schedule
+// Analysis): C(x) = number of scheduled reference patches containing x.
+// Built separably: a count of 1 at every origin, then along each axis the
+// running sum over the last j_d samples (a patch starting at r covers
+// r .. r + j_d - 1), so each axis costs one pass over the array.
+std::vector<uint32_t> coverage_map(const bmnd_geometry& geom, const bmnd_stage_params& sp)
+{
+    const int D = geom.ndim;
+    int64_t V = 1;
+    for (int d = 0; d < D; ++d) V *= geom.shape[d];
+    std::vector<uint32_t> c(size_t(V), 0u);
+    for (int64_t o : reference_origins(geom, sp)) c[size_t(o)] = 1u;
+    std::vector<uint32_t> line;
+    int64_t inner = 1;
+    for (int d = D - 1; d >= 0; --d) {
+        const int64_t L = geom.shape[d], j = sp.patch[d];
+        const int64_t outer = V / (L * inner);
+        line.resize(size_t(L));
+        for (int64_t a = 0; a < outer; ++a)
+            for (int64_t b = 0; b < inner; ++b) {
+                uint32_t* base = c.data() + a * L * inner + b;
+                for (int64_t i = 0; i < L; ++i) line[size_t(i)] = base[i * inner];
+                uint32_t run = 0;
+                for (int64_t i = 0; i < L; ++i) {
+                    run += line[size_t(i)];
+                    if (i >= j) run -= line[size_t(i - j)];
+                    base[i * inner] = run;
+                }
+            }
+        inner *= L;
+    }
+    return c;
 }
 
 }  // namespace bmnd
