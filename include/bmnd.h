@@ -45,7 +45,7 @@ extern "C" {
 #endif
 
 #define BMND_MAX_AXES 8   /* geometry structs carry up to 8 axes            */
-#define BMND_GPU_AXES 4   /* the GPU kernels accept ndim <= 4               */
+#define BMND_GPU_AXES 4   /* the GPU kernels take at most 4 axes of extent > 1 */
 
 typedef int32_t bmnd_status;
 enum {
@@ -56,7 +56,8 @@ enum {
     BMND_E_NOMEM = -4,        /* host allocation or library table failed       */
     BMND_E_HIP = -5,          /* HIP runtime error                             */
     BMND_E_WORKSPACE = -6,    /* workspace pointer NULL or too small           */
-    BMND_E_RANGE = -7         /* device detected counts outside exact range    */
+    BMND_E_RANGE = -7,        /* device detected counts outside exact range    */
+    BMND_E_BUDGET = -8        /* needs more device memory than the budget      */
 };
 
 enum { BMND_STAGE_HT = 0, BMND_STAGE_WIENER = 1 };
@@ -82,9 +83,15 @@ enum { BMND_WDOMAIN_COEFFICIENT = 0, BMND_WDOMAIN_WINDOWED = 1 };
 enum { BMND_MOMENT_MAX_COUNT = 4096 };
 
 /* Observed array(s): sampling domain Omega of ndim axes (Notation, Method
- * Overview), `batch` arrays of that shape stored back to back. */
+ * Overview), `batch` arrays of that shape stored back to back.  Any ndim up
+ * to BMND_MAX_AXES is accepted when at most BMND_GPU_AXES axes have extent
+ * > 1 (otherwise BMND_E_UNSUPPORTED): the kernels then run on the axes of
+ * extent > 1, which gives the same patches, windows and linear indices,
+ * while the reference schedule is built on all ndim axes (a singleton axis
+ * takes part in the generated schedule's axis hierarchy).  Patch extents
+ * on singleton axes are 1.  Correlated noise takes ndim <= BMND_GPU_AXES. */
 typedef struct {
-    int32_t ndim;                    /* 1 .. BMND_GPU_AXES                     */
+    int32_t ndim;                    /* 1 .. BMND_MAX_AXES                     */
     int32_t reserved;                /* must be 0                              */
     int64_t batch;                   /* >= 1                                   */
     int64_t shape[BMND_MAX_AXES];    /* L_d >= 1; batch * prod(L_d) < 2^31     */
@@ -179,6 +186,17 @@ bmnd_status bmnd_params_default(int32_t preset, int32_t ndim, bmnd_params* out);
 bmnd_status bmnd_reference_origins(const bmnd_geometry* geom, const bmnd_stage_params* sp,
                                    int64_t* out_lin, int64_t cap, int64_t* n_out);
 
+/* Coverage map of a stage's reference schedule (section Experiments, Shift
+ * Schedule Analysis): C(x), the number of scheduled reference patches
+ * (origin r, patch support B) with x in r + B, for every sample x of one
+ * array, and stats[0..2] = the spatial mean of C, its population standard
+ * deviation and their ratio, the coefficient of variation (0 when the
+ * mean is 0).  Host call.  out_map: host, prod(shape) uint32 in C order
+ * (may be NULL); stats: host, 3 doubles (may be NULL).  Errors: those of
+ * bmnd_reference_origins. */
+bmnd_status bmnd_reference_coverage(const bmnd_geometry* geom, const bmnd_stage_params* sp,
+                                    uint32_t* out_map, double* stats);
+
 /* The library's transform and window tables (host call, double precision):
  * T (n x n, row-major) the spatial analysis matrix of `spatial` on n points
  * (orthonormal DCT-II; full multilevel periodised bior1.5 DWT; identity)
@@ -239,6 +257,29 @@ bmnd_status bmnd_aggregate_workspace_size(const bmnd_geometry* geom,
 bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noise,
                                 const bmnd_params* params, size_t* bytes);
 
+/* Where bmnd_denoise leaves the FP64 sums of its last (Wiener) stage in
+ * its workspace (Def. weighted overlap-add; section Aggregation-Aware Mass
+ * Conservation): byte offsets into d_ws of two [batch][V] double arrays,
+ * the numerator (sum over groups and members of w omega (p + alpha), alpha
+ * = 0 without mass conservation) and the denominator eta; the output is
+ * their ratio rounded to float, 0 where eta = 0.  They let a caller check
+ * the conservation of the total in FP64, before the float rounding.  The
+ * arrays hold these sums from the end of a bmnd_denoise call (in stream
+ * order) until the workspace is used again.  Host call.  Errors: those of
+ * bmnd_workspace_size. */
+bmnd_status bmnd_workspace_sums(const bmnd_geometry* geom, const bmnd_noise* noise,
+                                const bmnd_params* params, size_t* num_offset,
+                                size_t* den_offset);
+
+/* Device memory one bmnd_denoise request holds while it runs (admission
+ * against an HBM budget when serving): the input and output arrays
+ * (2 batch V floats) plus bmnd_workspace_size().  Host call.  *bytes is
+ * always written on success of the size computation; BMND_E_BUDGET when
+ * budget > 0 and the request needs more than budget bytes (it can never be
+ * admitted within it); other errors as bmnd_workspace_size. */
+bmnd_status bmnd_request_bytes(const bmnd_geometry* geom, const bmnd_noise* noise,
+                               const bmnd_params* params, size_t budget, size_t* bytes);
+
 /* Block matching for one stage (section Block Matching).
  * For every array b < batch and reference g < n_refs with origin
  * d_refs[g] (lin, same origins for every array), score every candidate
@@ -276,6 +317,12 @@ bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noi
  *   d_refs  [n_refs] int64 origins (lin)
  *   d_match [batch][n_refs][group_max] int32 lin of the members; -1 beyond K
  *   d_count [batch][n_refs] int32 K
+ *   d_score [batch][n_refs][group_max] float, or NULL: the distance of each
+ *           member to its reference in the units tau is compared in (the
+ *           corrected SSD, or the Poisson-likelihood statistic of the
+ *           policy: d/P for FIXED and REFERENCE, Z for STANDARDIZED),
+ *           evaluated in FP64 from d_src by a second kernel and rounded
+ *           to float; 0 for the reference slot and at or beyond K
  *   d_ws    workspace of bmnd_match_workspace_size() bytes
  * Non-finite scores are never selected; a group then shrinks to the
  * largest power of two its selected members fill, so every entry below K
@@ -287,7 +334,8 @@ bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noi
 bmnd_status bmnd_match(int32_t stage, const float* d_src, const bmnd_geometry* geom,
                        const bmnd_noise* noise, const bmnd_stage_params* sp,
                        const int64_t* d_refs, int64_t n_refs, int32_t* d_match,
-                       int32_t* d_count, void* d_ws, size_t ws_bytes, void* stream);
+                       int32_t* d_count, float* d_score, void* d_ws, size_t ws_bytes,
+                       void* stream);
 
 /* Collaborative filtering of the matched groups (sections Hard
  * Thresholding, Wiener Shrinkage, Aggregation Weights).  For each group:
@@ -347,6 +395,19 @@ bmnd_status bmnd_aggregate(const float* d_y, const bmnd_geometry* geom,
 bmnd_status bmnd_denoise(const float* d_y, const bmnd_geometry* geom,
                          const bmnd_noise* noise, const bmnd_params* params, float* d_out,
                          float* d_pilot, void* d_ws, size_t ws_bytes, void* stream);
+
+/* The Wiener stage of bmnd_denoise alone, from a supplied pilot (section
+ * Method Overview: the second stage matches on the first stage's pilot and
+ * filters y with gains from it): for replaying or resuming a denoise from a
+ * stored pilot, or for a pilot from elsewhere.  With the pilot that
+ * bmnd_denoise wrote, d_out equals that call's output bit for bit.
+ *   d_y, d_pilot [batch][V] inputs (read only); d_out [batch][V];
+ *   d_ws of bmnd_workspace_size() bytes.
+ * Errors: those of bmnd_denoise; BMND_E_ARG when d_pilot is NULL. */
+bmnd_status bmnd_denoise_from_pilot(const float* d_y, const float* d_pilot,
+                                    const bmnd_geometry* geom, const bmnd_noise* noise,
+                                    const bmnd_params* params, float* d_out, void* d_ws,
+                                    size_t ws_bytes, void* stream);
 
 /* A batch of independent denoises (the serving and batching form of
  * bmnd_denoise, section Method Overview applied per array): any mix of

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libbmnd.so")
 
 MAX_AXES = 8
 OK, E_ARG, E_SHAPE, E_UNSUPPORTED, E_NOMEM, E_HIP, E_WORKSPACE, E_RANGE = 0, -1, -2, -3, -4, -5, -6, -7
+E_BUDGET = -8
 STAGE_HT, STAGE_WIENER = 0, 1
 NOISE_GAUSSIAN, NOISE_POISSON, NOISE_CORRELATED = 0, 1, 2
 SCHED = {"generated": 0, "balanced": 1, "sparse": 2, "off": 3}
@@ -84,11 +85,13 @@ BATCH_GRAPH = 1
 
 EXPORTS = [
     "bmnd_last_error", "bmnd_version", "bmnd_params_default", "bmnd_reference_origins",
+    "bmnd_reference_coverage",
     "bmnd_match_workspace_size", "bmnd_aggregate_workspace_size", "bmnd_workspace_size",
     "bmnd_match", "bmnd_filter", "bmnd_aggregate", "bmnd_denoise", "bmnd_stream_status",
     "bmnd_transform_matrices", "bmnd_haar_matrix", "bmnd_kaiser_window", "bmnd_count_moments",
     "bmnd_profile_begin", "bmnd_profile_end", "bmnd_batch_workspace_size", "bmnd_denoise_batch",
     "bmnd_correlated_size", "bmnd_correlated_prepare", "bmnd_denoise_noalloc",
+    "bmnd_denoise_from_pilot", "bmnd_request_bytes", "bmnd_workspace_sums",
 ]
 KERNEL_IDS = ["counts", "patch_sums", "match_ht", "match_wiener", "filter_ht", "filter_wiener",
               "zero", "normalize"]
@@ -112,10 +115,11 @@ def lib() -> C.CDLL:
         "bmnd_version": (C.c_char_p, []),
         "bmnd_params_default": (i32, [i32, i32, PP]),
         "bmnd_reference_origins": (i32, [G, S, vp, i64, C.POINTER(i64)]),
+        "bmnd_reference_coverage": (i32, [G, S, vp, vp]),
         "bmnd_match_workspace_size": (i32, [G, S, C.POINTER(sz)]),
         "bmnd_aggregate_workspace_size": (i32, [G, S, C.POINTER(sz)]),
         "bmnd_workspace_size": (i32, [G, N, PP, C.POINTER(sz)]),
-        "bmnd_match": (i32, [i32, vp, G, N, S, vp, i64, vp, vp, vp, sz, vp]),
+        "bmnd_match": (i32, [i32, vp, G, N, S, vp, i64, vp, vp, vp, vp, sz, vp]),
         "bmnd_filter": (i32, [i32, vp, vp, G, N, S, i64, vp, vp, vp, vp, vp]),
         "bmnd_aggregate": (i32, [vp, G, S, i64, vp, vp, vp, vp, vp, vp, sz, vp]),
         "bmnd_denoise": (i32, [vp, G, N, PP, vp, vp, vp, sz, vp]),
@@ -131,6 +135,9 @@ def lib() -> C.CDLL:
         "bmnd_correlated_size": (i32, [G, PP, C.POINTER(sz)]),
         "bmnd_correlated_prepare": (i32, [vp, G, PP, vp, sz, vp]),
         "bmnd_denoise_noalloc": (i32, [vp, G, N, PP, vp, vp, vp]),
+        "bmnd_denoise_from_pilot": (i32, [vp, vp, G, N, PP, vp, vp, sz, vp]),
+        "bmnd_request_bytes": (i32, [G, N, PP, sz, C.POINTER(sz)]),
+        "bmnd_workspace_sums": (i32, [G, N, PP, C.POINTER(sz), C.POINTER(sz)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -232,6 +239,17 @@ def bmnd_params_default(preset: int, ndim: int) -> Params:
     return p
 
 
+def bmnd_reference_coverage(geom: Geometry, sp: StageParams):
+    """Coverage map C of the stage's reference schedule (uint32, the array's
+    shape) and (mean, standard deviation, CV) of C."""
+    shape = tuple(int(geom.shape[d]) for d in range(geom.ndim))
+    cov = np.zeros(shape, np.uint32)
+    stats = np.zeros(3)
+    _check(lib().bmnd_reference_coverage(C.byref(geom), C.byref(sp), cov.ctypes.data,
+                                         stats.ctypes.data))
+    return cov, float(stats[0]), float(stats[1]), float(stats[2])
+
+
 def bmnd_reference_origins(geom: Geometry, sp: StageParams) -> np.ndarray:
     n = C.c_int64(0)
     _check(lib().bmnd_reference_origins(C.byref(geom), C.byref(sp), None, 0, C.byref(n)))
@@ -302,22 +320,47 @@ def bmnd_aggregate_workspace_size(geom: Geometry, sp: StageParams) -> int:
     return b.value
 
 
+def bmnd_workspace_sums(geom: Geometry, noise: Noise, params: Params):
+    """(numerator offset, denominator offset): bytes into a bmnd_denoise
+    workspace where the last stage's FP64 sums stay after the call."""
+    a, b = C.c_size_t(0), C.c_size_t(0)
+    _check(lib().bmnd_workspace_sums(C.byref(geom), C.byref(noise), C.byref(params), C.byref(a),
+                                     C.byref(b)))
+    return a.value, b.value
+
+
+def bmnd_request_bytes(geom: Geometry, noise: Noise, params: Params, budget: int = 0) -> int:
+    """Device bytes a denoise request holds (arrays and workspace); raises
+    BmndError(E_BUDGET) when budget > 0 and the request exceeds it."""
+    b = C.c_size_t(0)
+    _check(lib().bmnd_request_bytes(C.byref(geom), C.byref(noise), C.byref(params), budget,
+                                    C.byref(b)))
+    return b.value
+
+
 def bmnd_workspace_size(geom: Geometry, noise: Noise, params: Params) -> int:
     b = C.c_size_t(0)
     _check(lib().bmnd_workspace_size(C.byref(geom), C.byref(noise), C.byref(params), C.byref(b)))
     return b.value
 
 
-def bmnd_match(stage, src, geom, noise, sp, refs, match, count, ws, stream=None):
+def bmnd_match(stage, src, geom, noise, sp, refs, match, count, ws, stream=None, score=None):
+    """Block matching of the given references; `score` (float32, the shape
+    of `match`, optional) receives each member's distance to its reference
+    in the units of tau (0 for the reference and beyond the group size)."""
     import torch
 
     _require(src, torch.float32, name="src")
     _require(refs, torch.int64, name="refs")
     _require(match, torch.int32, name="match")
     _require(count, torch.int32, name="count")
+    if score is not None:
+        _require(score, torch.float32, name="score")
+        if score.numel() != match.numel():
+            raise ValueError("score must have as many entries as match")
     n_refs = int(refs.numel())
     _check(lib().bmnd_match(stage, _ptr(src), C.byref(geom), C.byref(noise), C.byref(sp),
-                            _ptr(refs), n_refs, _ptr(match), _ptr(count), _ptr(ws),
+                            _ptr(refs), n_refs, _ptr(match), _ptr(count), _ptr(score), _ptr(ws),
                             0 if ws is None else ws.numel() * ws.element_size(), _stream(stream)))
 
 
@@ -347,6 +390,17 @@ def bmnd_denoise(y, geom, noise, params, out, pilot, ws, stream=None):
     _check(lib().bmnd_denoise(_ptr(y), C.byref(geom), C.byref(noise), C.byref(params), _ptr(out),
                               _ptr(pilot), _ptr(ws), ws.numel() * ws.element_size(),
                               _stream(stream)))
+
+
+def bmnd_denoise_from_pilot(y, pilot, geom, noise, params, out, ws, stream=None):
+    """The Wiener stage of bmnd_denoise from a supplied pilot."""
+    import torch
+
+    for t, nm in ((y, "y"), (pilot, "pilot"), (out, "out")):
+        _require(t, torch.float32, name=nm)
+    _check(lib().bmnd_denoise_from_pilot(_ptr(y), _ptr(pilot), C.byref(geom), C.byref(noise),
+                                         C.byref(params), _ptr(out), _ptr(ws),
+                                         ws.numel() * ws.element_size(), _stream(stream)))
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20

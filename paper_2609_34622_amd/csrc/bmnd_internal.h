@@ -84,6 +84,7 @@ void set_error(const std::string& msg);
 
 // Host schedule (section Reference-Patch Schedule).
 std::vector<int64_t> reference_origins(const bmnd_geometry& geom, const bmnd_stage_params& sp);
+std::vector<uint32_t> coverage_map(const bmnd_geometry& geom, const bmnd_stage_params& sp);
 
 // Host tables (transform matrices, Kaiser window).
 void spatial_matrices(int kind, int n, std::vector<double>& T, std::vector<double>& U);
@@ -118,6 +119,11 @@ struct NdBlocks;
 hipError_t launch_match(const StageCfg& c, const float* src, int* kappa, int* psum,
                         const int64_t* refs, int n_refs, int* match, int* count, hipStream_t s,
                         const MomentTables* mom = nullptr, const NdBlocks* blk = nullptr);
+// The score of every selected member (FP64, stored as float; 0 for the
+// reference slot and beyond K) from the match lists bmnd_match wrote.
+hipError_t launch_member_scores(const StageCfg& c, const float* src, const int* match,
+                                const int* count, int n_refs, float* score,
+                                const MomentTables* mom, hipStream_t s);
 // out_mode: 0 write patches/weights, 1 aggregate (FP64 sums), 2 mc sweep 1, 3 mc sweep 2
 hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
                          const float* pilot, int n_refs, const int* match, const int* count,

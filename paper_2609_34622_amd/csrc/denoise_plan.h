@@ -34,9 +34,11 @@ bmnd_status plan_denoise_host(const bmnd_geometry* geom, const bmnd_noise* noise
                               const bmnd_params* params, DenoisePlan* pl);
 
 // The two stages of one denoise on stream s; ws holds pl.total bytes laid
-// out as pl.offs.  With spans, kernel times are recorded for tracing.
+// out as pl.offs.  With spans, kernel times are recorded for tracing.  With
+// from_pilot, d_pilot holds a pilot and only the Wiener stage runs.
 hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out,
-                           float* d_pilot, char* ws, hipStream_t s, bool spans);
+                           float* d_pilot, char* ws, hipStream_t s, bool spans,
+                           bool from_pilot = false);
 
 // Transform, window and Haar tables of one stage configuration in host
 // memory, with their offsets (t.f32 / t.f64 left null).

@@ -668,13 +668,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                         toff += (qq % J) * blk.S[kAx - D + d];
                         qq /= J;
                     }
-                    const float ww = wj * axis_prod<D, J>(tab, a.t.win, i);
+                    // w omega exactly (FP64 product of the two floats), as in
+                    // eta = W * omega and in zeta: the sums then conserve mass
+                    // to FP64 round-off
+                    const double ww = double(wj) * double(axis_prod<D, J>(tab, a.t.win, i));
                     if constexpr (OM == 3) {
-                        const double val = double(ww) * (double(x[i]) + alpha);
+                        const double val = ww * (double(x[i]) + alpha);
                         if (inbox) atomicAdd(&box[tb + toff], val);
                         else unsafeAtomicAdd(&numd[vb + org + patch_off<D, J>(i, g)], val);
                     } else {
-                        const double val = double(ww) * double(x[i]);
+                        const double val = ww * double(x[i]);
                         if (inbox) atomicAdd(&box[tb + toff], val);
                         else unsafeAtomicAdd(&numd[vb + org + patch_off<D, J>(i, g)], val);
                     }

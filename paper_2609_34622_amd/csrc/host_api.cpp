@@ -36,8 +36,14 @@ bmnd_status check_geometry(const bmnd_geometry* g)
 {
     if (!g) return fail(BMND_E_ARG, "geometry is NULL");
     if (g->ndim < 1 || g->ndim > BMND_MAX_AXES) return fail(BMND_E_SHAPE, "ndim out of range");
-    if (g->ndim > BMND_GPU_AXES)
-        return fail(BMND_E_UNSUPPORTED, "the GPU kernels accept at most 4 axes");
+    if (g->ndim > BMND_GPU_AXES) {
+        // singleton axes are dropped for the kernels (kernel_axes)
+        int wide = 0;
+        for (int d = 0; d < g->ndim; ++d) wide += g->shape[d] > 1;
+        if (wide > BMND_GPU_AXES)
+            return fail(BMND_E_UNSUPPORTED,
+                        "the GPU kernels accept at most 4 axes of extent > 1");
+    }
     if (g->reserved != 0) return fail(BMND_E_ARG, "geometry.reserved must be 0");
     if (g->batch < 1) return fail(BMND_E_SHAPE, "batch must be >= 1");
     double total = double(g->batch);
@@ -128,12 +134,28 @@ bmnd_status check_noise(const bmnd_noise* n)
     return BMND_OK;
 }
 
+// The axes the kernels see, in order: every axis of an array of at most 4
+// axes; of a larger one, the axes of extent > 1.  A singleton axis has one
+// patch position (j = 1, origin 0) and one candidate, so dropping it changes
+// no patch, window, stride or linear index; the reference origins are still
+// computed on the full geometry, where a singleton axis takes part in the
+// generated schedule's axis hierarchy.
+int kernel_axes(const bmnd_geometry* g, int* ax)
+{
+    int n = 0;
+    for (int d = 0; d < g->ndim; ++d)
+        if (g->ndim <= kAx || g->shape[d] > 1) ax[n++] = d;
+    return n;
+}
+
 Geo make_geo(const bmnd_geometry* g, const bmnd_stage_params* sp)
 {
     Geo o{};
-    const int pad = kAx - g->ndim;
+    int ax[BMND_MAX_AXES];
+    const int na = kernel_axes(g, ax);
+    const int pad = kAx - na;
     for (int k = 0; k < kAx; ++k) {
-        const int d = k - pad;
+        const int d = k - pad >= 0 ? ax[k - pad] : -1;
         o.L[k] = d >= 0 ? int(g->shape[d]) : 1;
         o.j[k] = d >= 0 ? sp->patch[d] : 1;
         o.W[k] = d >= 0 ? sp->search[d] : 1;
@@ -186,7 +208,11 @@ bmnd_status make_stage(const bmnd_geometry* g, const bmnd_noise* n, const bmnd_s
     c.wscope = sp->weight_scope;
     c.mc = sp->mass_conservation ? 1 : 0;
     c.beta = sp->kaiser_beta;
-    c.step_last = sp->step[g->ndim - 1];
+    {
+        int ax[BMND_MAX_AXES];
+        const int na = kernel_axes(g, ax);
+        c.step_last = sp->step[na > 0 ? ax[na - 1] : g->ndim - 1];
+    }
     c.metric = sp->match_metric;
     c.policy = sp->match_policy;
     c.match_t = sp->match_t;
@@ -195,6 +221,8 @@ bmnd_status make_stage(const bmnd_geometry* g, const bmnd_noise* n, const bmnd_s
     c.counts_integral = n && n->kind == BMND_NOISE_POISSON && n->counts_integral;
     c.wdomain = sp->weight_domain;
     if (n && n->kind == BMND_NOISE_CORRELATED) {
+        if (g->ndim > BMND_GPU_AXES)
+            return fail(BMND_E_UNSUPPORTED, "correlated noise: at most 4 axes");
         c.k_exact = 0;  // the full covariance is exact in every plane
         return correlated_bind(n->d_corr, g, sp, stage, c);
     }
@@ -608,6 +636,8 @@ bmnd_status corr_layout(const bmnd_geometry* geom, const bmnd_params* params, Co
                         StageCfg cfg[2])
 {
     if (!geom || !params) return fail(BMND_E_ARG, "NULL argument");
+    if (geom->ndim > BMND_GPU_AXES)
+        return fail(BMND_E_UNSUPPORTED, "correlated noise: at most 4 axes");
     bmnd_geometry g1 = *geom;
     g1.batch = 1;
     bmnd_status st = make_stage(&g1, nullptr, &params->ht, BMND_STAGE_HT, cfg[0]);
@@ -824,6 +854,37 @@ bmnd_status bmnd_reference_origins(const bmnd_geometry* geom, const bmnd_stage_p
     return BMND_OK;
 }
 
+bmnd_status bmnd_reference_coverage(const bmnd_geometry* geom, const bmnd_stage_params* sp,
+                                    uint32_t* out_map, double* stats)
+{
+    int64_t n = 0;
+    bmnd_status st = bmnd_reference_origins(geom, sp, nullptr, 0, &n);
+    if (st != BMND_OK) return st;
+    const std::vector<uint32_t> c = coverage_map(*geom, *sp);
+    if (stats) {
+        // mean and population standard deviation from the histogram of C
+        std::map<uint32_t, int64_t> hist;
+        int64_t sum = 0;
+        for (uint32_t v : c) {
+            ++hist[v];
+            sum += v;
+        }
+        const double V = double(c.size());
+        const double mean = double(sum) / V;
+        double ss = 0.0;
+        for (const auto& kv : hist) {
+            const double dv = double(kv.first) - mean;
+            ss += double(kv.second) * dv * dv;
+        }
+        const double sd = std::sqrt(ss / V);
+        stats[0] = mean;
+        stats[1] = sd;
+        stats[2] = mean > 0.0 ? sd / mean : 0.0;
+    }
+    if (out_map) std::memcpy(out_map, c.data(), c.size() * sizeof(uint32_t));
+    return BMND_OK;
+}
+
 bmnd_status bmnd_transform_matrices(int32_t spatial, int32_t n, double* T, double* U)
 {
     if (n < 1 || n > 1024) return fail(BMND_E_ARG, "n out of range");
@@ -942,10 +1003,47 @@ bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noi
     return denoise_layout(geom, params, n1, n2, offs, bytes);
 }
 
+bmnd_status bmnd_workspace_sums(const bmnd_geometry* geom, const bmnd_noise* noise,
+                                const bmnd_params* params, size_t* num_offset,
+                                size_t* den_offset)
+{
+    if (!num_offset || !den_offset || !params) return fail(BMND_E_ARG, "NULL argument");
+    size_t total = 0;
+    bmnd_status st = bmnd_workspace_size(geom, noise, params, &total);
+    if (st != BMND_OK) return st;
+    bmnd_geometry one = *geom;
+    one.batch = 1;
+    size_t offs[8];
+    st = denoise_layout(geom, params, int64_t(host_origins_cached(one, params->ht).size()),
+                        int64_t(host_origins_cached(one, params->wiener).size()), offs, &total);
+    if (st != BMND_OK) return st;
+    *num_offset = offs[4];
+    *den_offset = offs[5];
+    return BMND_OK;
+}
+
+bmnd_status bmnd_request_bytes(const bmnd_geometry* geom, const bmnd_noise* noise,
+                               const bmnd_params* params, size_t budget, size_t* bytes)
+{
+    if (!bytes) return fail(BMND_E_ARG, "NULL argument");
+    size_t ws = 0;
+    bmnd_status st = bmnd_workspace_size(geom, noise, params, &ws);
+    if (st != BMND_OK) return st;
+    size_t arrays = 2 * sizeof(float) * size_t(geom->batch);
+    for (int d = 0; d < geom->ndim; ++d) arrays *= size_t(geom->shape[d]);
+    *bytes = ws + arrays;
+    if (budget > 0 && *bytes > budget)
+        return fail(BMND_E_BUDGET, "the request needs " + std::to_string(*bytes) +
+                                       " bytes of device memory, more than the budget of " +
+                                       std::to_string(budget));
+    return BMND_OK;
+}
+
 bmnd_status bmnd_match(int32_t stage, const float* d_src, const bmnd_geometry* geom,
                        const bmnd_noise* noise, const bmnd_stage_params* sp,
                        const int64_t* d_refs, int64_t n_refs, int32_t* d_match,
-                       int32_t* d_count, void* d_ws, size_t ws_bytes, void* stream)
+                       int32_t* d_count, float* d_score, void* d_ws, size_t ws_bytes,
+                       void* stream)
 {
     StageCfg c;
     bmnd_status st = make_stage(geom, noise, sp, stage, c);
@@ -973,6 +1071,10 @@ bmnd_status bmnd_match(int32_t stage, const float* d_src, const bmnd_geometry* g
     hipError_t e = launch_match(c, d_src, kappa, psum, d_refs, int(n_refs), d_match, d_count, s,
                                 mom);
     if (e != hipSuccess) return hip_fail(e, "matching kernel");
+    if (d_score) {
+        e = launch_member_scores(c, d_src, d_match, d_count, int(n_refs), d_score, mom, s);
+        if (e != hipSuccess) return hip_fail(e, "member score kernel");
+    }
     return BMND_OK;
 }
 
@@ -1100,7 +1202,7 @@ bmnd_status plan_denoise(const bmnd_geometry* geom, const bmnd_noise* noise,
 
 // The two stages of one denoise on stream s (workspace ws of pl.total bytes).
 hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out,
-                           float* d_pilot, char* ws, hipStream_t s, bool spans)
+                           float* d_pilot, char* ws, hipStream_t s, bool spans, bool from_pilot)
 {
     int* match = reinterpret_cast<int*>(ws + pl.offs[0]);
     int* count = reinterpret_cast<int*>(ws + pl.offs[1]);
@@ -1163,8 +1265,10 @@ hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out
         }
         return e;
     };
-    hipError_t e = run_stage(pl.c1, *pl.t1, pl.r1, pl.n1, d_y, nullptr, pilot);
-    if (e != hipSuccess) return e;
+    if (!from_pilot) {
+        hipError_t e = run_stage(pl.c1, *pl.t1, pl.r1, pl.n1, d_y, nullptr, pilot);
+        if (e != hipSuccess) return e;
+    }
     return run_stage(pl.c2, *pl.t2, pl.r2, pl.n2, pilot, pilot, d_out);
 }
 
@@ -1313,6 +1417,25 @@ bmnd_status bmnd_denoise(const float* d_y, const bmnd_geometry* geom,
     hipError_t e = enqueue_denoise(pl, d_y, d_out, d_pilot, static_cast<char*>(d_ws),
                                    static_cast<hipStream_t>(stream), true);
     if (e != hipSuccess) return hip_fail(e, "denoise");
+    return BMND_OK;
+}
+
+bmnd_status bmnd_denoise_from_pilot(const float* d_y, const float* d_pilot,
+                                    const bmnd_geometry* geom, const bmnd_noise* noise,
+                                    const bmnd_params* params, float* d_out, void* d_ws,
+                                    size_t ws_bytes, void* stream)
+{
+    DenoisePlan pl;
+    bmnd_status st = plan_denoise(geom, noise, params, &pl);
+    if (st != BMND_OK) return st;
+    if (!d_y || !d_pilot || !d_out) return fail(BMND_E_ARG, "NULL device pointer");
+    if (!d_ws || ws_bytes < pl.total)
+        return fail(BMND_E_WORKSPACE, "workspace missing or smaller than bmnd_workspace_size");
+    // the Wiener stage only reads the pilot (matching, gathers, gains)
+    hipError_t e = enqueue_denoise(pl, d_y, d_out, const_cast<float*>(d_pilot),
+                                   static_cast<char*>(d_ws), static_cast<hipStream_t>(stream),
+                                   true, true);
+    if (e != hipSuccess) return hip_fail(e, "denoise from pilot");
     return BMND_OK;
 }
 

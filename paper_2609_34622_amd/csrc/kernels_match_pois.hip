@@ -21,6 +21,7 @@
 
 #include "bmnd_internal.h"
 #include "match_common.h"
+#include "safe_index.h"
 
 namespace bmnd {
 
@@ -321,7 +322,170 @@ hipError_t launch_metric(const MatchArgs& a, int kmax, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---- member scores (the optional score output of matching)
+
+// The distance of every selected member to its reference, in the units the
+// acceptance test compares with tau (section Block Matching: Def. corrected
+// SSD and its bias terms, the Wiener stage's SSD on the pilot, the
+// Poisson-likelihood statistics with their policies), evaluated in FP64
+// from the source array: one thread per (array, reference, slot).  Slot 0
+// (the reference) and slots at or beyond K hold 0.
+enum ScoreKind { kScCount = 0, kScPoissonF = 1, kScGauss = 2, kScCorr = 3, kScPlain = 4,
+                 kScMetric = 5 };
+
+struct ScoreArgs {
+    Geo g;
+    const float* src;
+    const int* match;
+    const int* count;
+    float* score;
+    int n_refs, gmax;
+    int kind, metric, policy, integral;
+    double s_p, gamma, bias;     // bias: white Gaussian gamma 2 P sigma^2
+    const double* bias_td;       // correlated Gaussian: per window offset
+    const double* mu_d;
+    const double* v_d;
+    int nmom;
+};
+
+// offset of patch sample i (C order over the patch axes) from the origin
+__device__ __forceinline__ int patch_sample_offset(const Geo& g, int i)
+{
+    int o = 0;
+    for (int d = kAx - 1; d >= 0; --d) {
+        o += (i % g.j[d]) * g.st[d];
+        i /= g.j[d];
+    }
+    return o;
+}
+
+template <int METRIC>
+__device__ double metric_score(const ScoreArgs& a, const float* y, int r, int q)
+{
+    const int P = a.g.P;
+    double A = 0.0, M = 0.0, S = 0.0;
+    for (int i = 0; i < P; ++i) {
+        const int o = patch_sample_offset(a.g, i);
+        double rk = __ddiv_rn(double(y[r + o]), a.s_p);
+        double ck = __ddiv_rn(double(y[q + o]), a.s_p);
+        if (a.integral) {
+            rk = rint(rk);
+            ck = rint(ck);
+        }
+        rk = fmax(rk, 0.0);
+        ck = fmax(ck, 0.0);
+        A = __dadd_rn(A, phi64<METRIC>(rk, ck));
+        if (a.policy == BMND_POLICY_STANDARDIZED) {
+            const double n = __dadd_rn(rk, ck);
+            if (!(n <= double(a.nmom))) return __longlong_as_double(0x7FF8000000000000LL);
+            M = __dadd_rn(M, a.mu_d[int(n)]);
+            S = __dadd_rn(S, a.v_d[int(n)]);
+        }
+    }
+    if (a.policy == BMND_POLICY_STANDARDIZED) return S > 0.0 ? __ddiv_rn(__dsub_rn(A, M), sqrt(S)) : 0.0;
+    return __ddiv_rn(A, double(P));
+}
+
+__global__ __launch_bounds__(256) void k_member_scores(ScoreArgs a)
+{
+    const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    const long total = long(a.g.batch) * a.n_refs * a.gmax;
+    if (idx >= total) return;
+    const int m = int(idx % a.gmax);
+    const long t = idx / a.gmax;
+    const int b = int(t / a.n_refs);
+    const Geo& g = a.g;
+    const int K = safe_count(a.count[t], a.gmax);
+    double x = 0.0;
+    if (m > 0 && m < K) {
+        const int omax = last_origin(g);
+        const int r = safe_origin(a.match[t * a.gmax], omax);
+        const int q = safe_origin(a.match[t * a.gmax + m], omax);
+        const float* y = a.src + long(b) * g.V;
+        if (a.kind == kScMetric) {
+            if (a.metric == BMND_METRIC_DEVIANCE) x = metric_score<BMND_METRIC_DEVIANCE>(a, y, r, q);
+            else if (a.metric == BMND_METRIC_PEARSON) x = metric_score<BMND_METRIC_PEARSON>(a, y, r, q);
+            else x = metric_score<BMND_METRIC_ANSCOMBE>(a, y, r, q);
+        } else {
+            double ssd = 0.0, bsum = 0.0;
+            for (int i = 0; i < g.P; ++i) {
+                const int o = patch_sample_offset(g, i);
+                double p = double(y[r + o]), c = double(y[q + o]);
+                if (a.kind == kScCount) {
+                    p = rint(__ddiv_rn(p, a.s_p));
+                    c = rint(__ddiv_rn(c, a.s_p));
+                }
+                const double df = __dsub_rn(c, p);
+                ssd = __dadd_rn(ssd, __dmul_rn(df, df));
+                const double pc = __dadd_rn(p, c);
+                if (pc > 0.0) bsum = __dadd_rn(bsum, pc);
+            }
+            if (a.kind == kScCount) {
+                x = __dmul_rn(__dmul_rn(a.s_p, a.s_p), __dsub_rn(ssd, __dmul_rn(a.gamma, bsum)));
+            } else if (a.kind == kScPoissonF) {
+                x = __dsub_rn(ssd, __dmul_rn(__dmul_rn(a.gamma, a.s_p), bsum));
+            } else if (a.kind == kScGauss) {
+                x = __dsub_rn(ssd, a.bias);
+            } else if (a.kind == kScCorr) {
+                // window offset of the displacement, C order over the W_d offsets
+                int wo = 0, wst = 1;
+                for (int d = kAx - 1; d >= 0; --d) {
+                    const int rc = (r / g.st[d]) % g.L[d], qc = (q / g.st[d]) % g.L[d];
+                    wo += (qc - rc + g.W[d] / 2) * wst;
+                    wst *= g.W[d];
+                }
+                x = __dsub_rn(ssd, a.bias_td[wo]);
+            } else {
+                x = ssd;
+            }
+        }
+    }
+    a.score[idx] = float(x);
+}
+
 }  // namespace
+
+hipError_t launch_member_scores(const StageCfg& c, const float* src, const int* match,
+                                const int* count, int n_refs, float* score,
+                                const MomentTables* mom, hipStream_t s)
+{
+    ScoreArgs a{};
+    a.g = c.g;
+    a.src = src;
+    a.match = match;
+    a.count = count;
+    a.score = score;
+    a.n_refs = n_refs;
+    a.gmax = c.gmax;
+    a.s_p = c.s_p;
+    a.gamma = c.gamma;
+    a.metric = c.metric;
+    a.policy = c.policy;
+    a.integral = c.counts_integral ? 1 : 0;
+    if (c.stage == BMND_STAGE_WIENER) {
+        a.kind = kScPlain;
+    } else if (c.metric != BMND_METRIC_SSD) {
+        if (!mom) return hipErrorInvalidValue;
+        a.kind = kScMetric;
+        a.mu_d = mom->mu64;
+        a.v_d = mom->v64;
+        a.nmom = mom->nmax;
+    } else if (c.integral) {
+        a.kind = kScCount;
+    } else if (c.noise == BMND_NOISE_POISSON) {
+        a.kind = kScPoissonF;
+    } else if (c.noise == BMND_NOISE_CORRELATED) {
+        a.kind = kScCorr;
+        a.bias_td = c.corr.bias;
+    } else {
+        a.kind = kScGauss;
+        a.bias = c.gamma * 2.0 * c.g.P * c.sigma * c.sigma;
+    }
+    const long total = long(c.g.batch) * n_refs * c.gmax;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_member_scores, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_match_pois(const MatchArgs& a, int metric, int kmax, hipStream_t s)
 {

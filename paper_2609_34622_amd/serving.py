@@ -22,8 +22,8 @@ from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 
-from . import (BmndError, Params, bmnd_denoise, bmnd_params_default, bmnd_stream_status,
-               bmnd_workspace_size, geometry, poisson, set_axes, PRESET_PLAIN)
+from . import (Params, bmnd_denoise, bmnd_params_default, bmnd_request_bytes,
+               bmnd_stream_status, bmnd_workspace_size, geometry, poisson, set_axes, PRESET_PLAIN)
 from . import synth
 
 
@@ -44,12 +44,13 @@ class Request:
         return int(self.y.size)
 
 
-def request_bytes(req: Request) -> int:
+def request_bytes(req: Request, budget: int = 0) -> int:
     """HBM held while the request runs: input and output arrays and the
-    denoise workspace (match lists, counts, num/den, pilot)."""
-    if req.nbytes == 0:
+    denoise workspace (match lists, counts, num/den, pilot), from the
+    library; BmndError(E_BUDGET) when it exceeds a nonzero budget."""
+    if req.nbytes == 0 or budget:
         geom = geometry(req.y.shape)
-        req.nbytes = 2 * req.y.nbytes + bmnd_workspace_size(geom, poisson(req.s_p), req.params)
+        req.nbytes = bmnd_request_bytes(geom, poisson(req.s_p), req.params, budget)
     return req.nbytes
 
 
@@ -213,8 +214,7 @@ class Server:
         """Replay `trace` (arrival times relative to the call) and return the
         throughput and latency figures; every request gets `out`, `done`."""
         for r in trace:
-            if request_bytes(r) > self.budget:
-                raise BmndError(-6, f"request {r.rid} needs more than the HBM budget")
+            request_bytes(r, self.budget)   # E_BUDGET: never admissible
         pending = deque(sorted(trace, key=lambda r: (r.arrival, r.rid)))
         t0 = self.clock()
         n_done = 0

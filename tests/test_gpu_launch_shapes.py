@@ -1,0 +1,251 @@
+"""GPU parity at the launch shapes the benchmark times, against the FP64
+oracle, and the boundary pieces around bmnd_denoise.
+
+  * Arrays denoised one call each with their own s_P (as the benchmark
+    runs the 2-D microscopy and 3-D phantom batches): every workgroup of
+    the block matcher and the N-D filter busy, many spatial blocks per
+    array.  Stage by stage: the pilot against the oracle's HT stage from
+    y, the output against the oracle's Wiener stage replayed on the GPU's
+    pilot; max |gpu - oracle| <= 1e-4 max |oracle| per array.
+  * A full-size phantom volume (256 x 256 x 128, mass conservation in both
+    stages) compared on sampled boxes: the oracle runs only the reference
+    origins whose groups can reach a box (through the mass-conservation
+    shift of the groups that overlap it), which gives the exact oracle
+    values inside the box.
+  * The FP64 total of the mass-conserving output (the workspace's
+    numerator over eta) against the observed total, to 1e-12.
+  * Arrays with singleton axes beyond four axes, and the Wiener stage from
+    a supplied pilot.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2609_34622_amd as B
+from paper_2609_34622_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL_OUT = 1e-4
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _params(shape, patch, step, search, group=(16, 32), mc=(False, False)):
+    p = B.bmnd_params_default(B.PRESET_PLAIN, len(shape))
+    for sp in (p.ht, p.wiener):
+        B.set_axes(sp, patch=patch, step=step, search=search)
+    p.ht.group_max, p.wiener.group_max = group
+    p.ht.mass_conservation, p.wiener.mass_conservation = int(mc[0]), int(mc[1])
+    return p
+
+
+def _gpu_denoise(y, shape, s_p, p):
+    geom = B.geometry(shape)
+    noise = B.poisson(s_p)
+    yd = torch.from_numpy(np.ascontiguousarray(y, np.float32)).cuda()
+    ws = torch.empty(B.bmnd_workspace_size(geom, noise, p), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(yd)
+    pilot = torch.empty_like(yd)
+    B.bmnd_denoise(yd, geom, noise, p, out, pilot, ws)
+    B.bmnd_stream_status()
+    return out.cpu().numpy().astype(np.float64), pilot.cpu().numpy().astype(np.float64), ws
+
+
+def _rel(a, ref):
+    return float(np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-30))
+
+
+def _stagewise(y, s_p, shape, patch, step, search, group, mc, tag):
+    p = _params(shape, patch, step, search, group, mc)
+    out, pilot, _ = _gpu_denoise(y, shape, s_p, p)
+    ht, wie = O.plain_profile(shape, patch, step, search, s_p=s_p, group=group, mc=mc)
+    pe = _rel(pilot, O.run_stage(ht, O.STAGE_HT, y))
+    we = _rel(out, O.run_stage(wie, O.STAGE_WIENER, y, pilot))
+    _say(f"  {tag}: pilot {pe:.3g}, Wiener replay {we:.3g}")
+    assert pe < REL_OUT, tag
+    assert we < REL_OUT, tag
+
+
+def test_microscopy_images_one_call_each():
+    """Two 256 x 256 microscopy images (8 x 8 patches, step 3, search 39,
+    groups 16/32), each with its own peak rate, one call per image."""
+    shape, patch, step, search = (256, 256), (8, 8), (3, 3), (39, 39)
+    for b in range(2):
+        s = synth.microscopy_2d(seed=3100 + b, size=256)
+        _say(f"microscopy 256^2 image {b}, s_P {s.s_p:.4g}")
+        _stagewise(s.y, s.s_p, shape, patch, step, search, (16, 32), (False, False), f"image {b}")
+
+
+def test_phantom_volumes_one_call_each_mass_conservation():
+    """Two 64^3 phantom volumes (4^3 patches, step 3, search 11^3, groups
+    16/32, mass conservation in both stages), one call per volume."""
+    shape, patch, step, search = (64, 64, 64), (4, 4, 4), (3, 3, 3), (11, 11, 11)
+    for b in range(2):
+        s = synth.phantom_3d(seed=4100 + b, shape=shape)
+        _say(f"phantom 64^3 volume {b}, s_P {s.s_p:.4g}")
+        _stagewise(s.y, s.s_p, shape, patch, step, search, (16, 32), (True, True), f"volume {b}")
+
+
+def _influence(refs, shape, lo, hi, reach):
+    """Origins within `reach` samples (per axis) of the box [lo, hi)."""
+    c = np.stack(np.unravel_index(refs, shape), axis=1)
+    keep = np.ones(len(refs), bool)
+    for d in range(len(shape)):
+        keep &= (c[:, d] >= lo[d] - reach[d]) & (c[:, d] < hi[d] + reach[d])
+    return refs[keep]
+
+
+def _oracle_on_refs(st, stage, y, pilot, refs):
+    src = y if stage == O.STAGE_HT else pilot
+    m, c, _, _ = O.match(st, stage, src, y, refs)
+    pt, wt = O.filter(st, stage, y, pilot, m, c)
+    return O.aggregate(st, stage, y, m, c, pt, wt)
+
+
+def test_full_size_phantom_volume_sampled():
+    """One phantom volume at the full 256 x 256 x 128 size, in the call the
+    benchmark times, compared with the oracle on three boxes of 6^3
+    voxels (a corner, the centre, the far corner).  A group covers voxel x
+    only if its reference lies within j - 1 + W/2 of x; its
+    mass-conservation shift reads eta on its members, within W + 2j - 2
+    of x, where eta sums groups with references within j - 1 + W/2 of
+    those: references within 1.5 W + 3 j of the box give the box's exact
+    oracle values."""
+    shape, patch, step, search = (256, 256, 128), (4, 4, 4), (3, 3, 3), (11, 11, 11)
+    mc, group = (True, True), (16, 32)
+    s = synth.phantom_3d(seed=4000, shape=shape)
+    _say(f"full-size phantom {shape}, s_P {s.s_p:.4g}")
+    p = _params(shape, patch, step, search, group, mc)
+    out, pilot, _ = _gpu_denoise(s.y, shape, s.s_p, p)
+    assert np.isfinite(out).all() and np.isfinite(pilot).all()
+    ht, wie = O.plain_profile(shape, patch, step, search, s_p=s.s_p, group=group, mc=mc)
+    refs = O.schedule(ht)
+    reach = [int(1.5 * search[d] + 3 * patch[d]) + 1 for d in range(3)]
+    box = 6
+    for name, lo in (("corner", (0, 0, 0)), ("centre", (125, 125, 61)),
+                     ("far corner", (250, 250, 122))):
+        hi = tuple(lo[d] + box for d in range(3))
+        sel = _influence(refs, shape, lo, hi, reach)
+        _say(f"  box {name} at {lo}: {len(sel)} reference origins")
+        sl = tuple(slice(lo[d], hi[d]) for d in range(3))
+        pil_o = _oracle_on_refs(ht, O.STAGE_HT, s.y, None, sel)
+        out_o = _oracle_on_refs(wie, O.STAGE_WIENER, s.y, pilot, sel)
+        scale = max(np.abs(pil_o[sl]).max(), 1e-30)
+        pe = float(np.abs(pilot[sl] - pil_o[sl]).max() / scale)
+        we = float(np.abs(out[sl] - out_o[sl]).max() / max(np.abs(out_o[sl]).max(), 1e-30))
+        _say(f"    pilot {pe:.3g}, Wiener replay {we:.3g}")
+        assert pe < REL_OUT, name
+        assert we < REL_OUT, name
+
+
+@pytest.mark.parametrize("shape", [(40, 36, 32), (64, 64, 64)], ids=lambda s: "x".join(map(str, s)))
+def test_mass_conservation_fp64_total(shape):
+    """Thm. mass conservation after normalized overlap-add: the FP64 ratio
+    of the Wiener stage's numerator and eta (read from the workspace after
+    bmnd_denoise) sums to the observed total within 1e-12, and the float
+    output is that ratio rounded."""
+    patch, step, search = (4, 4, 4), (3, 3, 3), (11, 11, 11)
+    s = synth.phantom_3d(seed=4200, shape=shape)
+    _say(f"FP64 total {shape}")
+    p = _params(shape, patch, step, search, (16, 32), (True, True))
+    geom, noise = B.geometry(shape), B.poisson(s.s_p)
+    out, _, ws = _gpu_denoise(s.y, shape, s.s_p, p)
+    no, do = B.bmnd_workspace_sums(geom, noise, p)
+    n = int(np.prod(shape))
+    num = ws[no:no + 8 * n].view(torch.float64).cpu().numpy()
+    den = ws[do:do + 8 * n].view(torch.float64).cpu().numpy()
+    cov = den > 0
+    xh = np.where(cov, num / np.where(cov, den, 1.0), 0.0)
+    # the total is conserved over the voxels some group covers (eta > 0);
+    # the generated schedule leaves a few voxels outside every reference
+    # patch, and those no matched patch reaches stay 0
+    tot = float(np.sum(s.y.astype(np.float64).ravel()[cov]))
+    err = abs(float(np.sum(xh)) - tot) / tot
+    _say(f"  |sum x - sum y| / sum y over covered voxels = {err:.3g} (FP64), "
+         f"uncovered {int((~cov).sum())} of {n}")
+    assert err <= 1e-12
+    assert np.array_equal(out.ravel().astype(np.float32), xh.astype(np.float32))
+
+
+@pytest.mark.parametrize("case", [((1, 24, 1, 20, 16), (1, 4, 1, 4, 4), (1, 3, 1, 3, 3),
+                                   (1, 7, 1, 7, 7)),
+                                  ((30, 1, 1, 28, 1, 1), (8, 1, 1, 8, 1, 1), (3, 1, 1, 3, 1, 1),
+                                   (15, 1, 1, 15, 1, 1)),
+                                  ((1, 1, 1, 1, 1, 1, 1, 600), (1,) * 7 + (32,), (1,) * 7 + (4,),
+                                   (1,) * 7 + (64,))],
+                         ids=["5d", "6d", "8d"])
+def test_singleton_axes_beyond_four(case):
+    """Arrays of 5 to 8 axes with at most three of extent > 1, against the
+    oracle on the full-rank array (its schedule sees every axis)."""
+    shape, patch, step, search = case
+    _say(f"{len(shape)}-axis array {shape}")
+    rng = np.random.default_rng(77)
+    s_p = 0.1
+    wide = [n for n in shape if n > 1]
+    g = np.meshgrid(*[np.linspace(0, 2, n) for n in wide], indexing="ij")
+    lam = (4.0 + 12.0 * np.abs(np.sin(sum(g)))).reshape(shape)
+    y = (rng.poisson(lam) * s_p).astype(np.float32)
+    p = B.bmnd_params_default(B.PRESET_PLAIN, len(shape))
+    for sp in (p.ht, p.wiener):
+        B.set_axes(sp, patch=patch, step=step, search=search)
+    out, pilot, _ = _gpu_denoise(y, shape, s_p, p)
+    ht, wie = O.plain_profile(shape, patch, step, search, s_p=s_p, group=(16, 32))
+    pe = _rel(pilot, O.run_stage(ht, O.STAGE_HT, y))
+    we = _rel(out, O.run_stage(wie, O.STAGE_WIENER, y, pilot))
+    _say(f"  pilot {pe:.3g}, Wiener replay {we:.3g}")
+    assert pe < REL_OUT and we < REL_OUT
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_denoise_from_supplied_pilot(dim):
+    """bmnd_denoise_from_pilot with bmnd_denoise's own pilot gives its
+    output bit for bit; with another pilot it gives the oracle's Wiener
+    stage on that pilot."""
+    if dim == 2:
+        s = synth.image_2d_small(1020, size=96)
+        shape, patch, step, search, mc = (96, 96), (8, 8), (3, 3), (21, 21), (False, False)
+    else:
+        s = synth.phantom_3d(seed=4300, shape=(36, 32, 28))
+        shape, patch, step, search, mc = (36, 32, 28), (4, 4, 4), (3, 3, 3), (9, 9, 9), (True, True)
+    _say(f"Wiener stage from a supplied pilot, {shape}")
+    p = _params(shape, patch, step, search, (16, 32), mc)
+    geom, noise = B.geometry(shape), B.poisson(s.s_p)
+    yd = torch.from_numpy(np.ascontiguousarray(s.y, np.float32)).cuda()
+    ws = torch.empty(B.bmnd_workspace_size(geom, noise, p), dtype=torch.uint8, device="cuda")
+    out, pilot = torch.empty_like(yd), torch.empty_like(yd)
+    B.bmnd_denoise(yd, geom, noise, p, out, pilot, ws)
+    out2 = torch.empty_like(yd)
+    B.bmnd_denoise_from_pilot(yd, pilot, geom, noise, p, out2, ws)
+    B.bmnd_stream_status()
+    assert torch.equal(out, out2)
+    # another pilot: a smoothed observation
+    other = torch.nn.functional.avg_pool1d(yd.reshape(1, 1, -1), 3, 1, 1).reshape(shape).contiguous()
+    out3 = torch.empty_like(yd)
+    B.bmnd_denoise_from_pilot(yd, other, geom, noise, p, out3, ws)
+    B.bmnd_stream_status()
+    _, wie = O.plain_profile(shape, patch, step, search, s_p=s.s_p, group=(16, 32), mc=mc)
+    ref = O.run_stage(wie, O.STAGE_WIENER, s.y, other.cpu().numpy().astype(np.float64))
+    e = _rel(out3.cpu().numpy().astype(np.float64), ref)
+    _say(f"  other pilot: Wiener stage {e:.3g}")
+    assert e < REL_OUT
+    with pytest.raises(ValueError):
+        B.bmnd_denoise_from_pilot(yd, other.double(), geom, noise, p, out3, ws)
+    with pytest.raises(B.BmndError) as e:
+        B.bmnd_denoise_from_pilot(yd, None, geom, noise, p, out3, ws)
+    assert e.value.status == B.E_ARG

@@ -225,15 +225,20 @@ def test_denoise_end_to_end_2d(img):
     # Wiener stage replayed on the GPU pilot: the strict check
     out_r = O.run_stage(img["wie"], O.STAGE_WIENER, s.y, pilot.astype(np.float64))
     assert rel_err(out, out_r) < REL_OUT
-    # from y alone: the FP32 pilot may flip near-ties of the Wiener matching;
-    # any excess must lie in the support of a flipped group
+    # from y alone: the FP32 pilot may flip near-ties of the Wiener matching
+    # (the oracle's own matching on the GPU pilot against on its pilot);
+    # the flips are counted and reported every run, at most 1 % of the
+    # groups may flip, and any excess error lies in their support
     err = np.abs(out.astype(np.float64) - out_o) / np.abs(out_o).max()
-    if err.max() >= REL_OUT:
-        mask, flips = flip_mask(img["wie"], img["shape"], img["patch"], img["refs"], s.y,
-                                pil_o, pilot.astype(np.float64))
-        _say(f"end-to-end max rel err {err.max():.2e}, {flips} flipped Wiener groups")
-        assert flips > 0
-        assert err[~mask].max() < REL_OUT
+    mask, flips = flip_mask(img["wie"], img["shape"], img["patch"], img["refs"], s.y,
+                            pil_o, pilot.astype(np.float64))
+    outside = float(err[~mask].max()) if (~mask).any() else 0.0
+    _say(f"end-to-end max rel err {err.max():.2e}; {flips} of {len(img['refs'])} Wiener groups "
+         f"flipped; max rel err outside their support {outside:.2e}")
+    assert flips <= 0.01 * len(img["refs"])
+    assert outside < REL_OUT
+    if flips == 0:
+        assert err.max() < REL_OUT
 
 
 def test_denoise_same_shape_two_search_windows():

@@ -67,8 +67,9 @@ def test_serving_budget_limits_admission():
     assert srv.peak_in_use <= biggest + biggest // 2
     for r in trace:
         assert _rel(r.out, _alone(r)) < 1e-4, r.rid
-    with pytest.raises(B.BmndError):
+    with pytest.raises(B.BmndError) as e:
         serving.Server(budget_bytes=biggest // 2).run(trace[:1] + [max(trace, key=serving.request_bytes)])
+    assert e.value.status == B.E_BUDGET
 
 
 def test_fifo_path_agrees():

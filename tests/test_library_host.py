@@ -220,3 +220,47 @@ def test_serving_work_cap_rule():
     assert not serving.admits(w, w, w, busy=True)         # two large ones: no
     assert serving.admits(w / 4, w / 4, w, busy=True)     # small beside small: yes
     assert serving.admits(w, w, None, busy=True)          # no cap
+
+
+def test_request_bytes_and_budget():
+    """bmnd_request_bytes: arrays plus workspace; E_BUDGET beyond a budget."""
+    shape = (64, 48)
+    p = B.bmnd_params_default(B.PRESET_PLAIN, 2)
+    geom, noise = B.geometry(shape, 3), B.poisson(0.1)
+    need = B.bmnd_request_bytes(geom, noise, p)
+    assert need == B.bmnd_workspace_size(geom, noise, p) + 2 * 4 * 3 * 64 * 48
+    assert B.bmnd_request_bytes(geom, noise, p, need) == need
+    with pytest.raises(B.BmndError) as e:
+        B.bmnd_request_bytes(geom, noise, p, need - 1)
+    assert e.value.status == B.E_BUDGET
+
+
+def test_up_to_eight_axes_with_at_most_four_wide():
+    """ndim up to 8: singleton axes are dropped for the kernels (the sizes
+    equal those of the squeezed array's), more than 4 wide axes are refused,
+    and the schedule is still built on all axes."""
+    p5 = B.bmnd_params_default(B.PRESET_PLAIN, 5)
+    for sp in (p5.ht, p5.wiener):
+        B.set_axes(sp, patch=(1, 4, 1, 4, 4), step=(1, 3, 1, 3, 3), search=(1, 7, 1, 7, 7))
+    p3 = B.bmnd_params_default(B.PRESET_PLAIN, 3)
+    for sp in (p3.ht, p3.wiener):
+        B.set_axes(sp, patch=(4, 4, 4), step=(3, 3, 3), search=(7, 7, 7))
+    n = B.poisson(0.1)
+    g5, g3 = B.geometry((1, 20, 1, 18, 16)), B.geometry((20, 18, 16))
+    assert B.bmnd_workspace_size(g5, n, p5) > 0
+    assert B.bmnd_match_workspace_size(g5, p5.ht) == B.bmnd_match_workspace_size(g3, p3.ht)
+    # the generated schedule sees the singleton axis between axes 1 and 3
+    o5 = B.bmnd_reference_origins(g5, p5.ht)
+    st = O.Stage(shape=(1, 20, 1, 18, 16), patch=(1, 4, 1, 4, 4), step=(1, 3, 1, 3, 3),
+                 search=(1, 7, 1, 7, 7))
+    assert np.array_equal(o5, O.schedule(st))
+    p8 = B.bmnd_params_default(B.PRESET_PLAIN, 8)
+    for sp in (p8.ht, p8.wiener):
+        B.set_axes(sp, patch=(2,) * 5 + (1,) * 3, step=(1,) * 8, search=(3,) * 5 + (1,) * 3)
+    with pytest.raises(B.BmndError) as e:
+        B.bmnd_workspace_size(B.geometry((4, 4, 4, 4, 4, 1, 1, 1)), n, p8)
+    assert e.value.status == B.E_UNSUPPORTED
+    for sp in (p8.ht, p8.wiener):
+        B.set_axes(sp, patch=(1,) + (2,) * 4 + (1,) * 3, step=(1,) * 8,
+                   search=(1,) + (3,) * 4 + (1,) * 3)
+    assert B.bmnd_workspace_size(B.geometry((1, 4, 4, 4, 4, 1, 1, 1)), n, p8) > 0
