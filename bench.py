@@ -317,39 +317,63 @@ def bench_batched(B, torch, reps: int = 3) -> dict:
             "speedup": round(res["plain"]["ms"] / res["batched"]["ms"], 3)}
 
 
-def bench_serving(B, torch, n: int = 60) -> dict:
+def bench_serving(B, torch, n: int = 2000) -> dict:
     """Continuous batching against the plain one-at-a-time path on one seeded
-    trace of mixed requests (host arrays in, host results out); the arrival
-    rate is 0.7 of the plain path's measured capacity."""
+    trace of `n` mixed requests (host arrays in, host results out): 40 %
+    1-D signals of 8k-256k samples, 40 % 2-D images of 256^2-2048^2, 20 %
+    3-D volumes of 64^3-256^3 (mass conservation), peaks log-uniform in
+    [2, 100].  Four passes over the same requests: both paths with every
+    request arriving at 0 (saturating; the plain path's pass also fills the
+    library's per-shape caches and gives its capacity), then both at
+    seeded Poisson arrivals at 0.7 of that capacity."""
     from paper_2609_34622_amd import serving
 
-    kw = dict(len_1d=(8192, 131072), side_2d=(128, 512), side_3d=(32, 64))
-    calib = serving.make_trace(12, 1e6, 7000, **kw)
-    cap = serving.serve_fifo(calib)
-    rate = 0.7 * cap["requests"] / cap["makespan_s"]
-    trace = serving.make_trace(n, rate, 7001, **kw)
-    # one untimed pass of each path: the per-shape library caches (reference
-    # origins, tables), the streams' queues and the pinned host buffers exist
-    # before either path is timed
-    budget = 32 << 30
-    srv = serving.Server(budget_bytes=budget, slots=4)   # in-flight work cap: "auto"
-    serving.serve_fifo(trace)
-    for r in trace:
-        r.out = None
-    srv.run(trace)
-    for r in trace:
-        r.out = None
+    t0 = time.perf_counter()
+    trace = serving.make_trace_crops(n, 7001, torch)
+    gen_s = time.perf_counter() - t0
+    vox = sum(r.voxels for r in trace)
+    kinds = [sum(1 for r in trace if r.y.ndim == d) for d in (1, 2, 3)]
+    print(f"serving trace: {n} requests, {vox / 1e9:.3f} G voxels, generated in {gen_s:.1f} s",
+          file=sys.stderr, flush=True)
+    budget = 64 << 30
+
+    def clear():
+        for r in trace:
+            r.out = None
+
+    def rnd(d):
+        return {k: round(v, 3) for k, v in d.items()}
+
+    serving.set_rate(trace, float("inf"))
+    fifo_sat = serving.serve_fifo(trace)
+    clear()
+    print(f"serving: plain path saturated {fifo_sat['mvox_per_s']:.1f} Mvox/s",
+          file=sys.stderr, flush=True)
+    srv = serving.Server(budget_bytes=budget, slots=4)
+    cont_sat = srv.run(trace)
+    clear()
+    print(f"serving: continuous saturated {cont_sat['mvox_per_s']:.1f} Mvox/s",
+          file=sys.stderr, flush=True)
+    rate = 0.7 * fifo_sat["requests"] / fifo_sat["makespan_s"]
+    serving.set_rate(trace, rate)
     cont = srv.run(trace)
-    for r in trace:
-        r.out = None
+    clear()
     fifo = serving.serve_fifo(trace)
-    return {"requests": n, "arrival_rate_per_s": round(rate, 3), "hbm_budget_gib": budget >> 30,
-            "trace": "seeded Poisson arrivals; 40% 1-D (8k-128k), 40% 2-D (128^2-512^2), "
-                     "20% 3-D (32^3-64^3, mass conservation); peaks log-uniform [2, 100]",
-            "admission": "4 streams, HBM budget, in-flight work at most half the largest "
-                         "request seen so far; one untimed pass of each path first",
-            "continuous": {k: round(v, 3) for k, v in cont.items()},
-            "plain_fifo": {k: round(v, 3) for k, v in fifo.items()}}
+    clear()
+    print(f"serving: at {rate:.2f} req/s continuous p99 {cont['p99_ms']:.1f} ms, plain p99 "
+          f"{fifo['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    return {"requests": n, "voxels": vox, "kinds_1d_2d_3d": kinds,
+            "arrival_rate_per_s": round(rate, 3), "hbm_budget_gib": budget >> 30,
+            "trace": "seeded; 40% 1-D (8k-256k samples), 40% 2-D (256^2-2048^2), 20% 3-D "
+                     "(64^3-256^3, mass conservation); crops of full-size ECG, microscopy, "
+                     "disc/rectangle and phantom means rescaled to peaks log-uniform in [2, 100], "
+                     "Poisson-sampled with a seeded device generator",
+            "admission": "4 streams, HBM budget (bmnd_request_bytes), in-flight work at most "
+                         "half the largest request seen so far",
+            "generation_s": round(gen_s, 1),
+            "saturating": {"continuous": rnd(cont_sat), "plain_fifo": rnd(fifo_sat),
+                           "speedup": round(cont_sat["mvox_per_s"] / fifo_sat["mvox_per_s"], 3)},
+            "fixed_rate": {"continuous": rnd(cont), "plain_fifo": rnd(fifo)}}
 
 
 def bench_standard(B, torch, workload: str = "image-2d-128", reps: int = 10) -> dict:
@@ -657,6 +681,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, copy this many MiB device to device once "
                          "(calibrates HBM byte counters under rocprofv3)")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="requests in the serving trace (0: skip the serving comparison)")
     ap.add_argument("--mixed", type=int, default=1,
                     help="also time the batched path and the serving path on mixed 1-D/2-D/3-D "
                          "workloads (0: skip)")
@@ -713,7 +739,8 @@ def main():
     batched = serving_row = standard = pois = corr = None
     if args.mixed:
         batched = bench_batched(B, torch)
-        serving_row = bench_serving(B, torch)
+        if args.serving_requests > 0:
+            serving_row = bench_serving(B, torch, args.serving_requests)
         standard = bench_standard(B, torch)
         pois = bench_poisson_metrics(B, torch)
         corr = bench_correlated(B, torch)

@@ -186,6 +186,15 @@ bmnd_status bmnd_params_default(int32_t preset, int32_t ndim, bmnd_params* out);
 bmnd_status bmnd_reference_origins(const bmnd_geometry* geom, const bmnd_stage_params* sp,
                                    int64_t* out_lin, int64_t cap, int64_t* n_out);
 
+/* Byte budgets of the library's per-shape caches: host_bytes for the
+ * reference-origin and block lists of each (shape, stage parameters) seen,
+ * device_bytes for their device copies (all devices together); 0 restores
+ * the default of 1 GiB each.  Least recently used entries beyond a budget
+ * are dropped; a device copy is freed only once no call that uses it is
+ * being planned or captured in a cached batch graph, and after the device
+ * has finished its queued work.  Host call, any time. */
+bmnd_status bmnd_cache_limits(size_t host_bytes, size_t device_bytes);
+
 /* Coverage map of a stage's reference schedule (section Experiments, Shift
  * Schedule Analysis): C(x), the number of scheduled reference patches
  * (origin r, patch support B) with x in r + B, for every sample x of one

@@ -92,6 +92,7 @@ EXPORTS = [
     "bmnd_profile_begin", "bmnd_profile_end", "bmnd_batch_workspace_size", "bmnd_denoise_batch",
     "bmnd_correlated_size", "bmnd_correlated_prepare", "bmnd_denoise_noalloc",
     "bmnd_denoise_from_pilot", "bmnd_request_bytes", "bmnd_workspace_sums",
+    "bmnd_cache_limits",
 ]
 KERNEL_IDS = ["counts", "patch_sums", "match_ht", "match_wiener", "filter_ht", "filter_wiener",
               "zero", "normalize"]
@@ -138,6 +139,7 @@ def lib() -> C.CDLL:
         "bmnd_denoise_from_pilot": (i32, [vp, vp, G, N, PP, vp, vp, sz, vp]),
         "bmnd_request_bytes": (i32, [G, N, PP, sz, C.POINTER(sz)]),
         "bmnd_workspace_sums": (i32, [G, N, PP, C.POINTER(sz), C.POINTER(sz)]),
+        "bmnd_cache_limits": (i32, [sz, sz]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -318,6 +320,11 @@ def bmnd_aggregate_workspace_size(geom: Geometry, sp: StageParams) -> int:
     b = C.c_size_t(0)
     _check(lib().bmnd_aggregate_workspace_size(C.byref(geom), C.byref(sp), C.byref(b)))
     return b.value
+
+
+def bmnd_cache_limits(host_bytes: int = 0, device_bytes: int = 0) -> None:
+    """Byte budgets of the per-shape schedule caches (0: the default)."""
+    _check(lib().bmnd_cache_limits(host_bytes, device_bytes))
 
 
 def bmnd_workspace_sums(geom: Geometry, noise: Noise, params: Params):

@@ -104,10 +104,9 @@ struct MomentTables {
 void count_moments_host(int metric, int nmax, std::vector<double>& mu, std::vector<double>& v);
 const MomentTables* device_moments(int metric, std::string& err);
 
-// Cached device copies (library owned, never freed before process exit).
+// Cached device copies of the transform tables (library owned, one per
+// stage configuration, kept until the process ends).
 const DevTables* device_tables(const StageCfg& c, std::string& err);
-const int64_t* device_origins(const bmnd_geometry& geom, const bmnd_stage_params& sp,
-                              int64_t* n_refs, hipStream_t s, std::string& err);
 
 // Kernel launchers (kernels.hip).  Each returns hipSuccess or the launch error.
 hipError_t launch_counts(const StageCfg& c, const float* y, int* kappa, int* psum, hipStream_t s);

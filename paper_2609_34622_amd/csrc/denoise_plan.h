@@ -5,6 +5,7 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <vector>
 
 #include "bmnd_internal.h"
@@ -26,6 +27,8 @@ struct DenoisePlan {
     NdBlocks blk1, blk2;
     size_t offs[8] = {};
     size_t total = 0;
+    // owners of the library's device copies r1 / r2 point into
+    std::shared_ptr<const void> keep[2];
 };
 
 // Host part of a plan: stage configurations, reference counts and the
@@ -50,11 +53,12 @@ struct HostTables {
 void build_tables_host(const StageCfg& c, std::vector<float>& f, std::vector<double>& f64,
                        DevTables& t);
 
-// Process-lifetime host caches (entries are never removed, so references
-// stay valid for asynchronous copies).
+// Host caches.  The transform tables are kept for the process (a handful
+// of configurations); origin lists and block lists are kept while recently
+// used, within a byte budget, and shared with their users.
 const HostTables& host_tables_cached(const StageCfg& c);
-const std::vector<int64_t>& host_origins_cached(const bmnd_geometry& geom,
-                                                const bmnd_stage_params& sp);
+std::shared_ptr<const std::vector<int64_t>> host_origins_cached(const bmnd_geometry& geom,
+                                                                const bmnd_stage_params& sp);
 
 // Origins of a stage in the N-D filter's block order, with the block
 // offsets and box geometry (blk.start left null).
@@ -63,8 +67,8 @@ struct HostBlocks {
     std::vector<int> start;
     NdBlocks blk;
 };
-const HostBlocks& host_blocks_cached(const bmnd_geometry& geom, const bmnd_stage_params& sp,
-                                     const Geo& g);
+std::shared_ptr<const HostBlocks> host_blocks_cached(const bmnd_geometry& geom,
+                                                     const bmnd_stage_params& sp, const Geo& g);
 // whether a stage runs the N-D filter with per-origin weights
 bool stage_uses_nd(const StageCfg& c);
 

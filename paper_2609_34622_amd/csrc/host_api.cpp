@@ -3,7 +3,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <list>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -236,9 +238,6 @@ std::mutex g_cache_mu;
 using TabKey = std::tuple<int, int, int, int, int, int, double>;
 std::map<TabKey, DevTables> g_tables;
 
-using OrgKey = std::tuple<int, std::vector<int64_t>, std::vector<int>, std::vector<int>, int, int,
-                          double>;
-std::map<OrgKey, std::pair<int64_t*, int64_t>> g_origins;
 
 }  // namespace
 
@@ -348,7 +347,6 @@ const DevTables* device_tables(const StageCfg& c, std::string& err)
 namespace {
 
 using HostOrgKey = std::tuple<std::vector<int64_t>, std::vector<int>, int, int, double>;
-std::map<HostOrgKey, std::vector<int64_t>> g_host_origins;
 std::map<TabKey, HostTables> g_host_tables;
 
 HostOrgKey host_org_key(const bmnd_geometry& geom, const bmnd_stage_params& sp)
@@ -362,20 +360,130 @@ HostOrgKey host_org_key(const bmnd_geometry& geom, const bmnd_stage_params& sp)
     return HostOrgKey{shape, ps, sp.schedule, sp.passes, sp.shift_density};
 }
 
+// A map of shared entries that keeps the most recently used ones within a
+// byte budget.  Users hold an entry's shared pointer while they need it;
+// evicted entries are handed back to the caller, to be released outside
+// the cache lock.  Callers hold g_cache_mu.
+template <class K, class V>
+class LruCache {
+public:
+    explicit LruCache(size_t cap) : cap_(cap) {}
+    std::shared_ptr<V> find(const K& k)
+    {
+        auto it = map_.find(k);
+        if (it == map_.end()) return nullptr;
+        order_.splice(order_.begin(), order_, it->second.pos);
+        return it->second.v;
+    }
+    std::shared_ptr<V> insert(const K& k, std::shared_ptr<V> v, size_t bytes,
+                              std::vector<std::shared_ptr<V>>& dropped)
+    {
+        if (auto old = find(k)) return old;
+        order_.push_front(k);
+        map_.emplace(k, Entry{v, bytes, order_.begin()});
+        total_ += bytes;
+        trim(1, dropped);
+        return v;
+    }
+    void set_cap(size_t cap, std::vector<std::shared_ptr<V>>& dropped)
+    {
+        cap_ = cap;
+        trim(0, dropped);
+    }
+
+private:
+    // over the budget: evict from the least recently used end down to half
+    // of it (so that device copies are released many at a time, behind one
+    // wait for the device), keeping at least `keep` entries (the one just
+    // inserted)
+    void trim(size_t keep, std::vector<std::shared_ptr<V>>& dropped)
+    {
+        if (total_ <= cap_) return;
+        while (total_ > cap_ / 2 && order_.size() > keep) {
+            auto e = map_.find(order_.back());
+            total_ -= e->second.bytes;
+            dropped.push_back(std::move(e->second.v));
+            map_.erase(e);
+            order_.pop_back();
+        }
+    }
+
+    struct Entry {
+        std::shared_ptr<V> v;
+        size_t bytes;
+        typename std::list<K>::iterator pos;
+    };
+    size_t cap_, total_ = 0;
+    std::list<K> order_;
+    std::map<K, Entry> map_;
+};
+
+constexpr size_t kHostCacheBytes = size_t(1) << 30;    // schedules and block lists
+constexpr size_t kDeviceCacheBytes = size_t(1) << 30;  // their device copies, all devices
+
+// The caches live until the process ends (never destroyed: device entries
+// must not be freed after the HIP runtime has shut down).
+LruCache<HostOrgKey, const std::vector<int64_t>>& host_origin_cache()
+{
+    static auto* c = new LruCache<HostOrgKey, const std::vector<int64_t>>(kHostCacheBytes);
+    return *c;
+}
+
+// blocks depend on the search window too (the box spans it)
+using BlkKey = std::pair<HostOrgKey, std::vector<int>>;
+BlkKey blk_key(const bmnd_geometry& geom, const bmnd_stage_params& sp)
+{
+    return BlkKey{host_org_key(geom, sp), std::vector<int>(sp.search, sp.search + geom.ndim)};
+}
+LruCache<BlkKey, const HostBlocks>& host_block_cache()
+{
+    static auto* c = new LruCache<BlkKey, const HostBlocks>(kHostCacheBytes);
+    return *c;
+}
+
+// A device copy of a stage's origin list (and, for the N-D filter, of its
+// block offsets).  It is freed only after the device has finished all
+// queued work, so no launch that read it can still be running.
+struct DevList {
+    int dev = 0;
+    int64_t* refs = nullptr;
+    int* start = nullptr;
+    int64_t n = 0;
+    NdBlocks blk;
+    ~DevList()
+    {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) return;
+        if (hipSetDevice(dev) == hipSuccess) {
+            (void)hipDeviceSynchronize();
+            if (refs) (void)hipFree(refs);
+            if (start) (void)hipFree(start);
+        }
+        (void)hipSetDevice(cur);
+    }
+};
+// key: device, blocked (0 / 1), origin key, search window (blocked only)
+using DevKey = std::tuple<int, int, BlkKey>;
+LruCache<DevKey, const DevList>& device_list_cache()
+{
+    static auto* c = new LruCache<DevKey, const DevList>(kDeviceCacheBytes);
+    return *c;
+}
+
 }  // namespace
 
-const std::vector<int64_t>& host_origins_cached(const bmnd_geometry& geom,
-                                                const bmnd_stage_params& sp)
+std::shared_ptr<const std::vector<int64_t>> host_origins_cached(const bmnd_geometry& geom,
+                                                                const bmnd_stage_params& sp)
 {
     const HostOrgKey key = host_org_key(geom, sp);
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto it = g_host_origins.find(key);
-        if (it != g_host_origins.end()) return it->second;
+        if (auto v = host_origin_cache().find(key)) return v;
     }
-    std::vector<int64_t> o = reference_origins(geom, sp);
+    auto o = std::make_shared<const std::vector<int64_t>>(reference_origins(geom, sp));
+    std::vector<std::shared_ptr<const std::vector<int64_t>>> dropped;
     std::lock_guard<std::mutex> lk(g_cache_mu);
-    return g_host_origins.emplace(key, std::move(o)).first->second;
+    return host_origin_cache().insert(key, o, o->size() * sizeof(int64_t), dropped);
 }
 
 const HostTables& host_tables_cached(const StageCfg& c)
@@ -389,130 +497,86 @@ const HostTables& host_tables_cached(const StageCfg& c)
     return g_host_tables.emplace(key, std::move(h)).first->second;
 }
 
-namespace {
-// blocks depend on the search window too (the box spans it)
-using BlkKey = std::pair<HostOrgKey, std::vector<int>>;
-BlkKey blk_key(const bmnd_geometry& geom, const bmnd_stage_params& sp)
-{
-    return BlkKey{host_org_key(geom, sp), std::vector<int>(sp.search, sp.search + geom.ndim)};
-}
-std::map<BlkKey, HostBlocks> g_host_blocks;
-struct DevBlocks {
-    const int64_t* refs = nullptr;
-    int64_t n = 0;
-    NdBlocks blk;
-};
-std::map<std::pair<int, BlkKey>, DevBlocks> g_dev_blocks;
-}  // namespace
-
 bool stage_uses_nd(const StageCfg& c)
 {
     return nd_filter_supported(c.g, c.gmax, c.k_exact, c.noise == BMND_NOISE_CORRELATED, c.noise,
                                c.shrink);
 }
 
-const HostBlocks& host_blocks_cached(const bmnd_geometry& geom, const bmnd_stage_params& sp,
-                                     const Geo& g)
+std::shared_ptr<const HostBlocks> host_blocks_cached(const bmnd_geometry& geom,
+                                                     const bmnd_stage_params& sp, const Geo& g)
 {
     const BlkKey key = blk_key(geom, sp);
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto it = g_host_blocks.find(key);
-        if (it != g_host_blocks.end()) return it->second;
+        if (auto v = host_block_cache().find(key)) return v;
     }
-    const std::vector<int64_t>& o = host_origins_cached(geom, sp);
-    HostBlocks h;
+    const auto o = host_origins_cached(geom, sp);
+    auto h = std::make_shared<HostBlocks>();
     Geo g1 = g;
     g1.batch = 1;
-    nd_make_blocks(g1, o, true, h.refs, h.start, h.blk);
+    nd_make_blocks(g1, *o, true, h->refs, h->start, h->blk);
+    const size_t bytes = h->refs.size() * sizeof(int64_t) + h->start.size() * sizeof(int);
+    std::vector<std::shared_ptr<const HostBlocks>> dropped;
     std::lock_guard<std::mutex> lk(g_cache_mu);
-    return g_host_blocks.emplace(key, std::move(h)).first->second;
+    return host_block_cache().insert(key, std::move(h), bytes, dropped);
 }
 
-// device copy of a stage's block-ordered origins and block offsets
-static const int64_t* device_blocks(const bmnd_geometry& geom, const bmnd_stage_params& sp,
-                                    const Geo& g, NdBlocks* blk, int64_t* n_refs,
-                                    std::string& err)
+namespace {
+
+// Device copy of a stage's origins: in block order with the block offsets
+// (blocked), or ascending.  Uploaded once per device and kept while it is
+// among the recently used lists.
+std::shared_ptr<const DevList> device_list(const bmnd_geometry& geom, const bmnd_stage_params& sp,
+                                           const Geo& g, bool blocked, std::string& err)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         err = "hipGetDevice failed";
         return nullptr;
     }
-    const auto key = std::make_pair(dev, blk_key(geom, sp));
+    const DevKey key{dev, blocked ? 1 : 0,
+                     blocked ? blk_key(geom, sp) : BlkKey{host_org_key(geom, sp), {}}};
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto it = g_dev_blocks.find(key);
-        if (it != g_dev_blocks.end()) {
-            *blk = it->second.blk;
-            *n_refs = it->second.n;
-            return it->second.refs;
-        }
+        if (auto v = device_list_cache().find(key)) return v;
     }
-    const HostBlocks& h = host_blocks_cached(geom, sp, g);
-    int64_t* dr = nullptr;
-    int* ds = nullptr;
-    if (hipMalloc(&dr, std::max<size_t>(1, h.refs.size()) * sizeof(int64_t)) != hipSuccess ||
-        hipMalloc(&ds, h.start.size() * sizeof(int)) != hipSuccess ||
-        hipMemcpy(dr, h.refs.data(), h.refs.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        hipMemcpy(ds, h.start.data(), h.start.size() * sizeof(int), hipMemcpyHostToDevice) !=
+    std::shared_ptr<const HostBlocks> hb;
+    std::shared_ptr<const std::vector<int64_t>> ho;
+    if (blocked) hb = host_blocks_cached(geom, sp, g);
+    else ho = host_origins_cached(geom, sp);
+    const std::vector<int64_t>& refs = blocked ? hb->refs : *ho;
+    auto d = std::make_shared<DevList>();
+    d->dev = dev;
+    d->n = int64_t(refs.size());
+    size_t bytes = std::max<size_t>(1, refs.size()) * sizeof(int64_t);
+    if (hipMalloc(&d->refs, bytes) != hipSuccess ||
+        hipMemcpy(d->refs, refs.data(), refs.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
             hipSuccess) {
-        err = "allocation of the block-ordered origin list failed";
-        return nullptr;
-    }
-    DevBlocks d;
-    d.refs = dr;
-    d.n = int64_t(h.refs.size());
-    d.blk = h.blk;
-    d.blk.start = ds;
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    g_dev_blocks[key] = d;
-    *blk = d.blk;
-    *n_refs = int64_t(h.refs.size());
-    return dr;
-}
-
-const int64_t* device_origins(const bmnd_geometry& geom, const bmnd_stage_params& sp,
-                              int64_t* n_refs, hipStream_t, std::string& err)
-{
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) {
-        err = "hipGetDevice failed";
-        return nullptr;
-    }
-    std::vector<int64_t> shape(geom.shape, geom.shape + geom.ndim);
-    std::vector<int> ps(size_t(2 * geom.ndim));
-    for (int d = 0; d < geom.ndim; ++d) {
-        ps[size_t(d)] = sp.patch[d];
-        ps[size_t(geom.ndim + d)] = sp.step[d];
-    }
-    OrgKey key{dev, shape, ps, {}, sp.schedule, sp.passes, sp.shift_density};
-    {
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto it = g_origins.find(key);
-        if (it != g_origins.end()) {
-            *n_refs = it->second.second;
-            return it->second.first;
-        }
-    }
-    const std::vector<int64_t>& o = host_origins_cached(geom, sp);
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    auto it = g_origins.find(key);
-    if (it != g_origins.end()) {
-        *n_refs = it->second.second;
-        return it->second.first;
-    }
-    int64_t* d = nullptr;
-    if (hipMalloc(&d, std::max<size_t>(1, o.size()) * sizeof(int64_t)) != hipSuccess ||
-        hipMemcpy(d, o.data(), o.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
         err = "allocation of the reference-origin list failed";
         return nullptr;
     }
-    g_origins[key] = {d, int64_t(o.size())};
-    *n_refs = int64_t(o.size());
-    return d;
+    if (blocked) {
+        d->blk = hb->blk;
+        bytes += hb->start.size() * sizeof(int);
+        if (hipMalloc(&d->start, hb->start.size() * sizeof(int)) != hipSuccess ||
+            hipMemcpy(d->start, hb->start.data(), hb->start.size() * sizeof(int),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            err = "allocation of the block offsets failed";
+            return nullptr;
+        }
+        d->blk.start = d->start;
+    }
+    std::vector<std::shared_ptr<const DevList>> dropped;
+    std::shared_ptr<const DevList> out;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        out = device_list_cache().insert(key, std::move(d), bytes, dropped);
+    }
+    return out;   // `dropped` (and a duplicate `d`) released here, outside the lock
 }
+
+}  // namespace
 
 // ------------------------------------------------------------- tracing
 
@@ -854,6 +918,20 @@ bmnd_status bmnd_reference_origins(const bmnd_geometry* geom, const bmnd_stage_p
     return BMND_OK;
 }
 
+bmnd_status bmnd_cache_limits(size_t host_bytes, size_t device_bytes)
+{
+    std::vector<std::shared_ptr<const std::vector<int64_t>>> d1;
+    std::vector<std::shared_ptr<const HostBlocks>> d2;
+    std::vector<std::shared_ptr<const DevList>> d3;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        host_origin_cache().set_cap(host_bytes ? host_bytes : kHostCacheBytes, d1);
+        host_block_cache().set_cap(host_bytes ? host_bytes : kHostCacheBytes, d2);
+        device_list_cache().set_cap(device_bytes ? device_bytes : kDeviceCacheBytes, d3);
+    }
+    return BMND_OK;   // evicted entries are released here, outside the lock
+}
+
 bmnd_status bmnd_reference_coverage(const bmnd_geometry* geom, const bmnd_stage_params* sp,
                                     uint32_t* out_map, double* stats)
 {
@@ -997,8 +1075,8 @@ bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noi
     if ((st = make_stage(geom, noise, &params->wiener, BMND_STAGE_WIENER, c2)) != BMND_OK) return st;
     bmnd_geometry one = *geom;
     one.batch = 1;
-    const int64_t n1 = int64_t(host_origins_cached(one, params->ht).size());
-    const int64_t n2 = int64_t(host_origins_cached(one, params->wiener).size());
+    const int64_t n1 = int64_t(host_origins_cached(one, params->ht)->size());
+    const int64_t n2 = int64_t(host_origins_cached(one, params->wiener)->size());
     size_t offs[8];
     return denoise_layout(geom, params, n1, n2, offs, bytes);
 }
@@ -1014,8 +1092,8 @@ bmnd_status bmnd_workspace_sums(const bmnd_geometry* geom, const bmnd_noise* noi
     bmnd_geometry one = *geom;
     one.batch = 1;
     size_t offs[8];
-    st = denoise_layout(geom, params, int64_t(host_origins_cached(one, params->ht).size()),
-                        int64_t(host_origins_cached(one, params->wiener).size()), offs, &total);
+    st = denoise_layout(geom, params, int64_t(host_origins_cached(one, params->ht)->size()),
+                        int64_t(host_origins_cached(one, params->wiener)->size()), offs, &total);
     if (st != BMND_OK) return st;
     *num_offset = offs[4];
     *den_offset = offs[5];
@@ -1163,11 +1241,11 @@ bmnd_status plan_denoise_host(const bmnd_geometry* geom, const bmnd_noise* noise
     if (!noise) return fail(BMND_E_ARG, "noise is NULL");
     bmnd_geometry one = *geom;
     one.batch = 1;
-    pl->n1 = int64_t(host_origins_cached(one, params->ht).size());
-    pl->n2 = int64_t(host_origins_cached(one, params->wiener).size());
-    pl->nd1 = stage_uses_nd(pl->c1) && nd_blocks_fit(host_blocks_cached(one, params->ht, pl->c1.g).blk);
+    pl->n1 = int64_t(host_origins_cached(one, params->ht)->size());
+    pl->n2 = int64_t(host_origins_cached(one, params->wiener)->size());
+    pl->nd1 = stage_uses_nd(pl->c1) && nd_blocks_fit(host_blocks_cached(one, params->ht, pl->c1.g)->blk);
     pl->nd2 = stage_uses_nd(pl->c2) &&
-              nd_blocks_fit(host_blocks_cached(one, params->wiener, pl->c2.g).blk);
+              nd_blocks_fit(host_blocks_cached(one, params->wiener, pl->c2.g)->blk);
     return denoise_layout(geom, params, pl->n1, pl->n2, pl->offs, &pl->total);
 }
 
@@ -1183,15 +1261,20 @@ bmnd_status plan_denoise(const bmnd_geometry* geom, const bmnd_noise* noise,
     std::string err;
     bmnd_geometry one = *geom;
     one.batch = 1;
-    pl->nd1 = stage_uses_nd(pl->c1) && nd_blocks_fit(host_blocks_cached(one, params->ht, pl->c1.g).blk);
+    pl->nd1 = stage_uses_nd(pl->c1) && nd_blocks_fit(host_blocks_cached(one, params->ht, pl->c1.g)->blk);
     pl->nd2 = stage_uses_nd(pl->c2) &&
-              nd_blocks_fit(host_blocks_cached(one, params->wiener, pl->c2.g).blk);
-    pl->r1 = pl->nd1 ? device_blocks(one, params->ht, pl->c1.g, &pl->blk1, &pl->n1, err)
-                     : device_origins(one, params->ht, &pl->n1, nullptr, err);
-    if (pl->r1)
-        pl->r2 = pl->nd2 ? device_blocks(one, params->wiener, pl->c2.g, &pl->blk2, &pl->n2, err)
-                         : device_origins(one, params->wiener, &pl->n2, nullptr, err);
-    if (!pl->r1 || !pl->r2) return fail(BMND_E_NOMEM, err);
+              nd_blocks_fit(host_blocks_cached(one, params->wiener, pl->c2.g)->blk);
+    auto l1 = device_list(one, params->ht, pl->c1.g, pl->nd1, err);
+    auto l2 = l1 ? device_list(one, params->wiener, pl->c2.g, pl->nd2, err) : nullptr;
+    if (!l1 || !l2) return fail(BMND_E_NOMEM, err);
+    pl->r1 = l1->refs;
+    pl->n1 = l1->n;
+    pl->r2 = l2->refs;
+    pl->n2 = l2->n;
+    if (pl->nd1) pl->blk1 = l1->blk;
+    if (pl->nd2) pl->blk2 = l2->blk;
+    pl->keep[0] = l1;
+    pl->keep[1] = l2;
     pl->t1 = device_tables(pl->c1, err);
     pl->t2 = pl->t1 ? device_tables(pl->c2, err) : nullptr;
     if (!pl->t1 || !pl->t2) return fail(BMND_E_NOMEM, err);
@@ -1288,6 +1371,8 @@ struct BatchPool {
     hipEvent_t fork = nullptr, in = nullptr, out = nullptr;
     hipEvent_t join[kBatchStreams] = {};
     std::map<std::string, hipGraphExec_t> graphs;  // launch sequences by job table
+    // the device lists each cached graph reads (kept while it may replay)
+    std::map<std::string, std::vector<std::shared_ptr<const void>>> graph_keep;
     std::vector<std::string> order;                // insertion order (eviction)
 };
 std::mutex g_batch_mu;
@@ -1498,10 +1583,16 @@ bmnd_status bmnd_denoise_batch(int32_t n_jobs, const bmnd_job* jobs, void* d_ws,
                     (void)hipGraphExecDestroy(old->second);
                     P->graphs.erase(old);
                 }
+                P->graph_keep.erase(P->order.front());
                 P->order.erase(P->order.begin());
             }
             P->graphs[key] = exec;
             P->order.push_back(key);
+            auto& keep = P->graph_keep[key];
+            for (const DenoisePlan& pl : L.plans) {
+                keep.push_back(pl.keep[0]);
+                keep.push_back(pl.keep[1]);
+            }
         }
     }
     if (e == hipSuccess) e = hipGraphLaunch(exec, P->capture);

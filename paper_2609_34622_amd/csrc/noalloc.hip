@@ -74,10 +74,14 @@ extern "C" bmnd_status bmnd_denoise_noalloc(const float* d_y, const bmnd_geometr
     bmnd_geometry one = *geom;
     one.batch = 1;
     // N-D filter stages take their origins in block order, with block offsets
-    const HostBlocks* hb1 = pl.nd1 ? &host_blocks_cached(one, params->ht, pl.c1.g) : nullptr;
-    const HostBlocks* hb2 = pl.nd2 ? &host_blocks_cached(one, params->wiener, pl.c2.g) : nullptr;
-    const std::vector<int64_t>& o1 = hb1 ? hb1->refs : host_origins_cached(one, params->ht);
-    const std::vector<int64_t>& o2 = hb2 ? hb2->refs : host_origins_cached(one, params->wiener);
+    // (held until the copies below have read them: a copy from pageable
+    // host memory has taken its data when hipMemcpyAsync returns)
+    const auto hb1 = pl.nd1 ? host_blocks_cached(one, params->ht, pl.c1.g) : nullptr;
+    const auto hb2 = pl.nd2 ? host_blocks_cached(one, params->wiener, pl.c2.g) : nullptr;
+    const auto ho1 = hb1 ? nullptr : host_origins_cached(one, params->ht);
+    const auto ho2 = hb2 ? nullptr : host_origins_cached(one, params->wiener);
+    const std::vector<int64_t>& o1 = hb1 ? hb1->refs : *ho1;
+    const std::vector<int64_t>& o2 = hb2 ? hb2->refs : *ho2;
     const HostTables& h1 = host_tables_cached(pl.c1);
     const HostTables& h2 = host_tables_cached(pl.c2);
 

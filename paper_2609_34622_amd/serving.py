@@ -38,6 +38,7 @@ class Request:
     admitted: float = float("nan")
     done: float = float("nan")
     nbytes: int = 0                # HBM held while running (request_bytes)
+    gap: float = 0.0               # unit-rate arrival gap (set_rate)
 
     @property
     def voxels(self) -> int:
@@ -128,6 +129,63 @@ def make_trace(n: int, rate: float, seed: int, len_1d=(8192, 262144), side_2d=(2
     return out
 
 
+def make_trace_crops(n: int, seed: int, torch, len_1d=(8192, 262144), side_2d=(256, 2048),
+                     side_3d=(64, 256), mix=(0.4, 0.4, 0.2), rate: float = float("inf")) -> List[Request]:
+    """A large seeded trace built fast: the clean means of a few arrays per
+    dimensionality at the largest size (ECG signals; a blob/filament image
+    and a disc/rectangle image; an ellipsoid phantom), and per request a
+    crop of the drawn size at a seeded offset, rescaled to the request's
+    peak (log-uniform in [2, 100] counts) and Poisson-sampled on the device
+    with a seeded generator (y = K / peak, s_P = 1 / peak).  Sizes and kinds
+    are drawn as in make_trace; arrivals are Poisson at `rate` (inf: all at
+    0), with unit-rate gaps kept in `gap` for set_rate."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    b1 = synth.ecg_batch(n_signals=2, length=len_1d[1], seed=seed + 1).x
+    b2 = [synth.microscopy_2d(seed=seed + 2, size=side_2d[1]).x,
+          synth.image_2d_small(seed=seed + 3, size=side_2d[1]).x]
+    b3 = synth.phantom_3d(seed=seed + 4, shape=(side_3d[1],) * 3).x
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    out = []
+    for i in range(n):
+        gap = float(rng.exponential(1.0))
+        kind = rng.choice(3, p=np.asarray(mix) / np.sum(mix))
+        peak = float(np.exp(rng.uniform(np.log(2.0), np.log(100.0))))
+        if kind == 0:
+            L = int(np.exp(rng.uniform(np.log(len_1d[0]), np.log(len_1d[1]))))
+            base = b1[int(rng.integers(0, len(b1)))]
+            o = int(rng.integers(0, base.shape[0] - L + 1))
+            x = base[o:o + L]
+        elif kind == 1:
+            m = int(np.exp(rng.uniform(np.log(side_2d[0]), np.log(side_2d[1]))))
+            base = b2[int(rng.integers(0, 2))]
+            o = rng.integers(0, base.shape[0] - m + 1, size=2)
+            x = base[o[0]:o[0] + m, o[1]:o[1] + m]
+        else:
+            m = int(np.exp(rng.uniform(np.log(side_3d[0]), np.log(side_3d[1]))))
+            o = rng.integers(0, b3.shape[0] - m + 1, size=3)
+            x = b3[o[0]:o[0] + m, o[1]:o[1] + m, o[2]:o[2] + m]
+        xd = torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+        lam = xd * (peak / max(float(xd.max().item()), 1e-12))
+        y = (torch.poisson(lam, generator=gen) / peak).cpu().numpy()
+        r = Request(i, 0.0, np.ascontiguousarray(y, np.float32), 1.0 / peak,
+                    default_params(y.ndim, y.ndim == 3))
+        r.gap = gap
+        out.append(r)
+    set_rate(out, rate)
+    return out
+
+
+def set_rate(trace: Sequence[Request], rate: float):
+    """Arrival times from the trace's unit-rate gaps at `rate` requests/s
+    (inf: every request arrives at 0)."""
+    t = 0.0
+    for r in trace:
+        if np.isfinite(rate):
+            t += r.gap / rate
+        r.arrival = t if np.isfinite(rate) else 0.0
+
+
 class _Slot:
     def __init__(self, torch, staging_bytes: int):
         self.stream = torch.cuda.Stream()          # default priority
@@ -152,7 +210,7 @@ class Server:
 
     def __init__(self, budget_bytes: int, slots: int = 4,
                  clock: Callable[[], float] = time.perf_counter,
-                 work_cap="auto", staging_bytes: int = 4 << 20):
+                 work_cap="auto", staging_bytes: int = 80 << 20):
         import torch
 
         self.torch = torch

@@ -58,19 +58,52 @@ def _rel(a, b):
     return float(np.abs(a.astype(np.float64) - b).max() / max(np.abs(b).max(), 1e-30))
 
 
+def _oracle_stages(spec_i):
+    """The oracle's stages for a job of _jobs_spec (preset 0 plain, 1
+    standard; the parameters set in _params)."""
+    import oracle as O
+
+    y, shape, batch, noise, p = spec_i
+    sp = p.ht
+    nd = len(shape)
+    patch = tuple(sp.patch[d] for d in range(nd))
+    step = tuple(sp.step[d] for d in range(nd))
+    search = tuple(sp.search[d] for d in range(nd))
+    group = (p.ht.group_max, p.wiener.group_max)
+    mc = (bool(p.ht.mass_conservation), bool(p.wiener.mass_conservation))
+    prof = O.standard_profile if p.ht.k_exact > 0 else O.plain_profile
+    return prof(shape, patch, step, search, s_p=noise.s_p, group=group, mc=mc)
+
+
 def test_batch_matches_single_jobs():
+    """Every job of the batch against its own bmnd_denoise and against the
+    oracle stage by stage (its pilot from y, its output replayed on the
+    pilot)."""
+    import oracle as O
+
     print("batch of 4 mixed jobs", flush=True)
     spec = _jobs_spec()
     ref = [_single(*s) for s in spec]
     ys = [torch.from_numpy(np.ascontiguousarray(s[0])).cuda() for s in spec]
     outs = [torch.empty_like(y) for y in ys]
-    jobs = B.make_jobs([(ys[i], outs[i], None, B.geometry(s[1], s[2]), s[3], s[4])
+    pils = [torch.empty_like(y) for y in ys]
+    jobs = B.make_jobs([(ys[i], outs[i], pils[i], B.geometry(s[1], s[2]), s[3], s[4])
                         for i, s in enumerate(spec)])
     ws = torch.empty(B.bmnd_batch_workspace_size(jobs), dtype=torch.uint8, device="cuda")
     B.bmnd_denoise_batch(jobs, ws)
     B.bmnd_stream_status()
-    for i in range(len(spec)):
-        assert _rel(outs[i].cpu().numpy(), ref[i]) < REL_OUT, i
+    for i, s in enumerate(spec):
+        out = outs[i].cpu().numpy()
+        assert _rel(out, ref[i]) < REL_OUT, i
+        ht, wie = _oracle_stages(s)
+        y = np.asarray(s[0], np.float64).reshape((s[2],) + tuple(s[1]))
+        pil = pils[i].cpu().numpy().astype(np.float64).reshape(y.shape)
+        out = out.reshape(y.shape)
+        for b in range(s[2]):
+            pe = _rel(pil[b], O.run_stage(ht, O.STAGE_HT, y[b]))
+            we = _rel(out[b], O.run_stage(wie, O.STAGE_WIENER, y[b], pil[b]))
+            print(f"  job {i} array {b}: pilot {pe:.3g}, Wiener replay {we:.3g}", flush=True)
+            assert pe < REL_OUT and we < REL_OUT, (i, b)
 
 
 def test_batch_graph_replays():
@@ -99,3 +132,42 @@ def test_batch_graph_replays():
         for i, s in enumerate(spec):
             ref = _single(new[i], s[1], s[2], s[3], s[4])
             assert _rel(got[i], ref) < REL_OUT, (rep, i)
+
+
+def test_small_cache_budgets_evict_and_rebuild():
+    """With tiny cache budgets every new shape evicts the previous shapes'
+    origin lists (host and device); denoises that rebuild them, and a
+    cached batch graph whose lists were evicted from the cache, still give
+    the results of the default budgets."""
+    shapes = [(40, 36), (33, 47), (24, 20, 18), (4096,)]
+    ys, ref = [], []
+    for i, sh in enumerate(shapes):
+        rng = np.random.default_rng(900 + i)
+        y = torch.from_numpy((rng.poisson(6.0, sh) * 0.125).astype(np.float32)).cuda()
+        ys.append(y)
+        ref.append(B.denoise(y, B.poisson(0.125)))
+    geoms = [B.geometry(sh) for sh in shapes]
+    params = [B.bmnd_params_default(B.PRESET_PLAIN, len(sh)) for sh in shapes]
+    outs = [torch.empty_like(y) for y in ys]
+    jobs = B.make_jobs([(ys[i], outs[i], None, geoms[i], B.poisson(0.125), params[i])
+                        for i in range(len(shapes))])
+    bws = torch.empty(B.bmnd_batch_workspace_size(jobs), dtype=torch.uint8, device="cuda")
+    B.bmnd_denoise_batch(jobs, bws, flags=B.BATCH_GRAPH)   # capture with default budgets
+    try:
+        B.bmnd_cache_limits(1024, 1024)
+        for rep in range(2):
+            for i, y in enumerate(ys):
+                o = B.denoise(y, B.poisson(0.125))
+                torch.cuda.synchronize()
+                # same kernels; FP64 atomics may add in another order
+                assert _rel(o.cpu().numpy(), ref[i].cpu().numpy().astype(np.float64)) < 1e-6, \
+                    (rep, shapes[i])
+        for o in outs:
+            o.zero_()
+        B.bmnd_denoise_batch(jobs, bws, flags=B.BATCH_GRAPH)   # replay
+        B.bmnd_stream_status()
+        for i in range(len(shapes)):
+            assert _rel(outs[i].cpu().numpy(), ref[i].cpu().numpy().astype(np.float64)) < 1e-6, \
+                shapes[i]
+    finally:
+        B.bmnd_cache_limits(0, 0)
