@@ -11,10 +11,11 @@
 // LDS, in C order over the window.
 //
 // Selection (Def. matched group): the count of accepted scores gives K; the
-// K-1 smallest (score, lin) follow from the (K-1)-th smallest value, found
-// by a radix select over order-preserving 32-bit keys, and the first ties
-// at it in lin order (prefix counts across lanes); the members are ranked
-// by (score, lin).  Float scores within the round-off band of the K-th
+// K-1 smallest (score, lin) follow from the (K-1)-th smallest value of
+// order-preserving 32-bit keys (a histogram of 256 equal bins over the
+// keys' range, then the keys of the rank's bin ranked exactly), and the
+// first ties at it in lin order (prefix counts across lanes); the members
+// are ranked by (score, lin).  Float scores within the round-off band of the K-th
 // value (or of tau, when that changes K) are re-scored in FP64, which then
 // decides membership and order.
 #include <hip/hip_runtime.h>
@@ -436,62 +437,112 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
         return;
     }
 
-    // ---- the need-th smallest key: radix select, 8 bits at a time, from
-    // the highest byte in which the finite keys differ (the bytes above it
-    // are common to all of them)
+    // ---- the need-th smallest finite key.  Level 1: a histogram of 256
+    // equal bins over the keys' range [kmn, kmx] gives the bin that holds
+    // the rank; level 2: the keys of that bin, at most one per lane, are
+    // ranked exactly.  A fuller bin falls back to a radix select, 8 bits at
+    // a time, among its keys.
     kmn = wmin_u(kmn);
     kmx = wmax_u(kmx);
-    const unsigned kdiff = kmn ^ kmx;
-    int shift0 = -8;   // all finite keys equal: that key is the need-th
-    unsigned pmask = 0xFFFFFFFFu;
-    if (kdiff != 0u) {
-        shift0 = ((31 - __clz(kdiff)) >> 3) << 3;
-        pmask = shift0 >= 24 ? 0u : (0xFFFFFFFFu << (shift0 + 8));
-    }
-    unsigned prefix = kmn & pmask;
-    int rank = need;  // 1-based rank of the target within the current prefix
-    for (int shift = shift0; shift >= 0; shift -= 8) {
+    unsigned theta_key = kmn;   // all finite keys equal: that key is the need-th
+    // histogram of f(k) over the finite keys with in(k), then the bin of the
+    // rank-th smallest (1-based) and the rank within it: misc[0], misc[1]
+    auto bin_of_rank = [&](auto f, auto in, int rank_) {
         for (int h = lane; h < 256; h += kWave) hist[h] = 0u;
         wsync();
         for (int ci = lane; ci < ncand; ci += kWave) {
             if (ci == rci) continue;
             const unsigned k = okey(from_int<S>(xs[ci]));
-            if (k != kbig && (k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+            if (k != kbig && in(k)) atomicAdd(&hist[f(k)], 1u);
         }
         wsync();
-        // the bin holding the rank-th key: each lane owns 4 consecutive bins,
-        // a wave prefix sum gives the keys below each lane's bins, and the
-        // one lane whose range holds the rank writes the bin
-        {
-            const uint4 h4 = *reinterpret_cast<const uint4*>(&hist[4 * lane]);
-            const int c0 = int(h4.x), c1 = int(h4.y), c2 = int(h4.z), c3 = int(h4.w);
-            const int tot = c0 + c1 + c2 + c3;
-            const int below = wscan_ex(tot);
-            if (below < rank && below + tot >= rank) {
-                int c = below, bin = 4 * lane;
-                if (c + c0 < rank) {
-                    c += c0;
+        // each lane owns 4 consecutive bins; a wave prefix sum gives the
+        // keys below each lane's bins, and the lane whose range holds the
+        // rank writes the bin
+        const uint4 h4 = *reinterpret_cast<const uint4*>(&hist[4 * lane]);
+        const int c0 = int(h4.x), c1 = int(h4.y), c2 = int(h4.z), c3 = int(h4.w);
+        const int tot = c0 + c1 + c2 + c3;
+        const int below = wscan_ex(tot);
+        if (below < rank_ && below + tot >= rank_) {
+            int c = below, bin = 4 * lane;
+            if (c + c0 < rank_) {
+                c += c0;
+                ++bin;
+                if (c + c1 < rank_) {
+                    c += c1;
                     ++bin;
-                    if (c + c1 < rank) {
-                        c += c1;
+                    if (c + c2 < rank_) {
+                        c += c2;
                         ++bin;
-                        if (c + c2 < rank) {
-                            c += c2;
-                            ++bin;
-                        }
                     }
                 }
-                misc[0] = bin;
-                misc[1] = rank - c;
             }
+            misc[0] = bin;
+            misc[1] = rank_ - c;
         }
         wsync();
-        prefix |= unsigned(misc[0]) << shift;
-        pmask |= 255u << shift;
-        rank = misc[1];
+    };
+    const unsigned span = kmx - kmn;
+    if (span != 0u) {
+        const int sh = span < 256u ? 0 : (32 - __clz(span)) - 8;   // span >> sh < 256
+        auto lvl = [&](unsigned k) { return (k - kmn) >> sh; };
+        bin_of_rank(lvl, [](unsigned) { return true; }, need);
+        const unsigned B = unsigned(misc[0]);
+        const int rank = misc[1];
+        const int cB = int(hist[B]);
+        const unsigned blo = kmn + (B << sh);
         wsync();
+        const unsigned long long top = (unsigned long long)blo + ((1ull << sh) - 1ull);
+        const unsigned bhi = unsigned(top < kmx ? top : kmx);   // the bin's key range
+        if (sh == 0 || bhi == blo) {
+            theta_key = blo;   // a bin of one key value
+        } else if (cB <= kWave) {
+            // the bin's keys into hist[0 .. cB), then each ranked among them
+            int base = 0;
+            for (int c0 = 0; c0 < ncand; c0 += kWave) {
+                const int ci = c0 + lane;
+                unsigned k = kbig;
+                if (ci < ncand && ci != rci) k = okey(from_int<S>(xs[ci]));
+                const bool in = k != kbig && lvl(k) == B;
+                const unsigned long long bal = __ballot(in);
+                if (in) hist[base + __popcll(bal & ((1ull << lane) - 1ull))] = k;
+                base += __popcll(bal);
+            }
+            wsync();
+            if (lane < cB) {
+                const unsigned kj = hist[lane];
+                int less = 0, eq = 0;
+                for (int o = 0; o < cB; ++o) {
+                    const unsigned ko = hist[o];
+                    less += ko < kj;
+                    eq += ko == kj;
+                }
+                if (less < rank && rank <= less + eq) misc[2] = int(kj);
+            }
+            wsync();
+            theta_key = unsigned(misc[2]);
+            wsync();
+        } else {
+            // radix select among the bin's keys, from the highest byte in
+            // which the bin's key range [blo, bhi] varies
+            const unsigned kd = blo ^ bhi;
+            int shift = ((31 - __clz(kd)) >> 3) << 3;
+            unsigned pmask = shift >= 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+            unsigned prefix = blo & pmask;
+            int r2 = rank;
+            for (; shift >= 0; shift -= 8) {
+                const int s_ = shift;
+                const unsigned pm = pmask, pf = prefix;
+                bin_of_rank([s_](unsigned k) { return (k >> s_) & 255u; },
+                            [&](unsigned k) { return lvl(k) == B && (k & pm) == pf; }, r2);
+                prefix |= unsigned(misc[0]) << shift;
+                pmask |= 255u << shift;
+                r2 = misc[1];
+                wsync();
+            }
+            theta_key = prefix;
+        }
     }
-    const unsigned theta_key = prefix;
     // members: keys below theta, then the first ties at theta in lin order
     const int per = (ncand + kWave - 1) / kWave;  // contiguous index range per lane
     const int c_lo = min(ncand, lane * per), c_hi = min(ncand, c_lo + per);
