@@ -614,7 +614,73 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
         }
         const bool amb = nb > wsum(members_in_band) || wsum(close) > 0;
         fp64 = amb;
+        // FP64 score of candidate ci and its lin
+        auto score64 = [&](int ci, int& lin) {
+            int rem = ci, cbo = rbase;
+            lin = 0;
+#pragma unroll
+            for (int d = kAx - 1; d >= 0; --d) {
+                cbo += (rem % n[d]) * sst[d];
+                lin += (lo[d] + rem % n[d]) * g.st[d];
+                rem /= n[d];
+            }
+            double s = 0.0, bb = 0.0;
+            for (int q = 0; q < rows; ++q)
+                for (int i = 0; i < g.j[kAx - 1]; ++i) {
+                    const double pv = __int_as_float(sx[rb + roff[q] + i]);
+                    const double qv = __int_as_float(sx[cbo + roff[q] + i]);
+                    const double df = __dsub_rn(qv, pv);
+                    s = __dadd_rn(s, __dmul_rn(df, df));
+                    if constexpr (MODE == kPoissonF) bb = __dadd_rn(bb, fmax(__dadd_rn(pv, qv), 0.0));
+                }
+            if constexpr (MODE == kGauss) s = __dsub_rn(s, a.bias_td ? a.bias_td[woff(ci)] : a.bias_d);
+            if constexpr (MODE == kPoissonF) s = __dsub_rn(s, __dmul_rn(a.gamma_sp_d, bb));
+            return s;
+        };
+        // the candidates up to theta plus the band, in lin order (C order
+        // over the window), when they fit one per lane
+        int nbc = 0;
         if (fp64) {
+            for (int c0 = 0; c0 < ncand; c0 += kWave) {
+                const int ci = c0 + lane;
+                const bool in = ci < ncand && ci != rci && __int_as_float(xs[ci]) <= thr;
+                const unsigned long long bal = __ballot(in);
+                const int at = nbc + __popcll(bal & ((1ull << lane) - 1ull));
+                if (in && at < kWave) band_l[at] = ci;
+                nbc += __popcll(bal);
+            }
+            wsync();
+        }
+        if (fp64 && nbc <= kWave) {
+            // each re-scored by one lane, then ranked by (FP64 score, lin)
+            double x64 = 0.0;
+            int lin = 0;
+            bool ok = false;
+            if (lane < nbc) {
+                x64 = score64(band_l[lane], lin);
+                ok = x64 == x64;
+            }
+            wsync();
+            if (lane < nbc) {
+                band_x[lane] = ok ? x64 : __longlong_as_double(0x7FF8000000000000LL);
+                band_l[lane] = lin;
+            }
+            wsync();
+            int rk = 0;
+            if (ok) {
+                for (int o = 0; o < nbc; ++o) {
+                    const double xo = band_x[o];
+                    const int lo_ = band_l[o];
+                    rk += xo < x64 || (xo == x64 && lo_ < lin);   // NaN compares false
+                }
+            }
+            if (ok && rk < need) {
+                best_x[rk] = x64;
+                best_l[rk] = lin;
+            }
+            got = min(wsum(ok ? 1 : 0), need);
+            wsync();
+        } else if (fp64) {
             // every candidate up to theta plus the band, re-scored in FP64 in
             // lin order, chunk by chunk; the best `need` by (FP64 score, lin)
             if (lane == 0) misc[2] = 0;  // entries in best_x
@@ -626,24 +692,8 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
                     if (ci == rci) continue;
                     const float x = __int_as_float(xs[ci]);
                     if (!(x <= thr)) continue;
-                    int rem = ci, cbo = rbase, lin = 0;
-#pragma unroll
-                    for (int d = kAx - 1; d >= 0; --d) {
-                        cbo += (rem % n[d]) * sst[d];
-                        lin += (lo[d] + rem % n[d]) * g.st[d];
-                        rem /= n[d];
-                    }
-                    double s = 0.0, bb = 0.0;
-                    for (int q = 0; q < rows; ++q)
-                        for (int i = 0; i < g.j[kAx - 1]; ++i) {
-                            const double pv = __int_as_float(sx[rb + roff[q] + i]);
-                            const double qv = __int_as_float(sx[cbo + roff[q] + i]);
-                            const double df = __dsub_rn(qv, pv);
-                            s = __dadd_rn(s, __dmul_rn(df, df));
-                            if constexpr (MODE == kPoissonF) bb = __dadd_rn(bb, fmax(__dadd_rn(pv, qv), 0.0));
-                        }
-                    if constexpr (MODE == kGauss) s = __dsub_rn(s, a.bias_td ? a.bias_td[woff(ci)] : a.bias_d);
-                    if constexpr (MODE == kPoissonF) s = __dsub_rn(s, __dmul_rn(a.gamma_sp_d, bb));
+                    int lin = 0;
+                    const double s = score64(ci, lin);
                     if (!(s == s)) continue;
                     const int slot = atomicAdd(&misc[3], 1);
                     band_x[slot] = s;
