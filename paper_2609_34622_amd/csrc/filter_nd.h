@@ -27,9 +27,9 @@ bool nd_filter_supported(const Geo& g, int gmax, int kex, bool corr, int noise, 
 bool nd_blocks_fit(const NdBlocks& blk);
 hipError_t launch_filter_nd(const FilterArgs& a, const NdBlocks* blk, hipStream_t s);
 // eta = W convolved with the patch window (the overlap-add denominator from
-// the per-origin weights W)
+// the per-origin weights W), and 1 / eta into reta when it is not null
 hipError_t launch_window_conv(const Geo& g, const DevTables& t, const double* W, double* eta,
-                              hipStream_t s);
+                              double* reta, hipStream_t s);
 
 // Host: block sizes for a geometry and the block order of a sorted origin
 // list (refs_out: the origins in block order, start: block offsets).

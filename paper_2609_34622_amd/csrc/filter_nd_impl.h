@@ -630,16 +630,22 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                 double alpha = 0.0;
                 if constexpr (OM == 3) {
                     // alpha_g = sum zeta (y - p) / sum zeta, zeta = w omega / eta
+                    // (dend holds 1 / eta here: a product per sample, and the
+                    // conservation holds to FP64 round-off all the same)
                     double zs = 0.0, zr = 0.0;
                     if (act) {
-#pragma unroll 8
+                        // four partial sums: independent FP64 chains
+                        double zs4[4] = {0.0, 0.0, 0.0, 0.0}, zr4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
                         for (int i = 0; i < P; ++i) {
                             const int u = org + patch_off<D, J>(i, g);
                             const float w = axis_prod<D, J>(tab, a.t.win, i);
-                            const double zeta = double(wj) * double(w) / dend[vb + u];
-                            zs += zeta;
-                            zr += zeta * (double(yb[u]) - double(x[i]));
+                            const double zeta = double(wj) * double(w) * dend[vb + u];
+                            zs4[i & 3] += zeta;
+                            zr4[i & 3] += zeta * (double(yb[u]) - double(x[i]));
                         }
+                        zs = (zs4[0] + zs4[1]) + (zs4[2] + zs4[3]);
+                        zr = (zr4[0] + zr4[1]) + (zr4[2] + zr4[3]);
                     }
                     zs = seg_sum64<GM>(zs);
                     zr = seg_sum64<GM>(zr);

@@ -1061,6 +1061,9 @@ static bmnd_status denoise_layout(const bmnd_geometry* geom, const bmnd_params* 
     offs[5] = o; o += align256(vox * sizeof(double));                     // den
     offs[6] = o; o += align256(vox * sizeof(float));                      // pilot
     offs[7] = o; o += align256(vox * sizeof(double));                     // per-origin weights
+    // 1 / eta for the second mass-conservation sweep of the N-D filter
+    const bool rd = params->ht.mass_conservation || params->wiener.mass_conservation;
+    offs[8] = o; o += rd ? align256(vox * sizeof(double)) : 0;
     *total = o;
     return BMND_OK;
 }
@@ -1077,7 +1080,7 @@ bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noi
     one.batch = 1;
     const int64_t n1 = int64_t(host_origins_cached(one, params->ht)->size());
     const int64_t n2 = int64_t(host_origins_cached(one, params->wiener)->size());
-    size_t offs[8];
+    size_t offs[9];
     return denoise_layout(geom, params, n1, n2, offs, bytes);
 }
 
@@ -1091,7 +1094,7 @@ bmnd_status bmnd_workspace_sums(const bmnd_geometry* geom, const bmnd_noise* noi
     if (st != BMND_OK) return st;
     bmnd_geometry one = *geom;
     one.batch = 1;
-    size_t offs[8];
+    size_t offs[9];
     st = denoise_layout(geom, params, int64_t(host_origins_cached(one, params->ht)->size()),
                         int64_t(host_origins_cached(one, params->wiener)->size()), offs, &total);
     if (st != BMND_OK) return st;
@@ -1295,6 +1298,7 @@ hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out
     void* den = ws + pl.offs[5];
     float* pilot = d_pilot ? d_pilot : reinterpret_cast<float*>(ws + pl.offs[6]);
     double* wf = reinterpret_cast<double*>(ws + pl.offs[7]);
+    double* rden = reinterpret_cast<double*>(ws + pl.offs[8]);
     const size_t vox = size_t(pl.c1.g.batch) * pl.c1.g.V;
     const int no_span = -1;
 
@@ -1320,16 +1324,19 @@ hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out
             if (nd) {
                 // per-origin weights W, eta = W * window, numerator in boxes
                 if (c.mc) {
+                    // sweep 2 reads 1 / eta (into the reciprocal region)
                     e = launch_filter_blocked(c, t, 2, d_y, pil, int(nr), match, count, num, den,
                                               wf, blk, s);
-                    if (e == hipSuccess) e = launch_window_conv(c.g, t, wf, static_cast<double*>(den), s);
+                    if (e == hipSuccess)
+                        e = launch_window_conv(c.g, t, wf, static_cast<double*>(den), rden, s);
                     if (e == hipSuccess)
                         e = launch_filter_blocked(c, t, 3, d_y, pil, int(nr), match, count, num,
-                                                  den, wf, blk, s);
+                                                  rden, wf, blk, s);
                 } else {
                     e = launch_filter_blocked(c, t, 1, d_y, pil, int(nr), match, count, num, den,
                                               wf, blk, s);
-                    if (e == hipSuccess) e = launch_window_conv(c.g, t, wf, static_cast<double*>(den), s);
+                    if (e == hipSuccess)
+                        e = launch_window_conv(c.g, t, wf, static_cast<double*>(den), nullptr, s);
                 }
             } else if (c.mc) {
                 e = launch_filter(c, t, 2, d_y, pil, int(nr), match, count, nullptr, nullptr, num,

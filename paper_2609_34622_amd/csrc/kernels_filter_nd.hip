@@ -18,10 +18,11 @@ namespace {
 
 // eta(u) = sum over the patch offsets t of W(u - t) omega(t): the weighted
 // overlap-add denominator from the per-origin weights (W is 0 off the
-// origins)
+// origins); reta (nullable) receives 1 / eta (0 where eta = 0)
 template <int D, int J>
 __global__ __launch_bounds__(256) void k_window_conv(Geo g, const double* __restrict__ W,
-                                                    double* __restrict__ eta, const float* win_tab,
+                                                    double* __restrict__ eta,
+                                                    double* __restrict__ reta, const float* win_tab,
                                                     int w1, int w2, int w3, long n)
 {
     for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(256) void k_window_conv(Geo g, const double* __rest
             }
         }
         eta[e] = s;
+        if (reta) reta[e] = s > 0.0 ? 1.0 / s : 0.0;
     }
 }
 
@@ -100,17 +102,17 @@ hipError_t launch_filter_nd(const FilterArgs& a, const NdBlocks* blk, hipStream_
 }
 
 hipError_t launch_window_conv(const Geo& g, const DevTables& t, const double* W, double* eta,
-                              hipStream_t s)
+                              double* reta, hipStream_t s)
 {
     const long n = long(g.batch) * g.V;
     long grid = (n + 255) / 256;
     if (grid > 65536L * 4) grid = 65536L * 4;
     if (g.j[1] == 4)
         hipLaunchKernelGGL((k_window_conv<3, 4>), dim3(unsigned(grid)), dim3(256), 0, s, g, W, eta,
-                           t.f32, t.win[1], t.win[2], t.win[3], n);
+                           reta, t.f32, t.win[1], t.win[2], t.win[3], n);
     else
         hipLaunchKernelGGL((k_window_conv<2, 8>), dim3(unsigned(grid)), dim3(256), 0, s, g, W, eta,
-                           t.f32, t.win[1], t.win[2], t.win[3], n);
+                           reta, t.f32, t.win[1], t.win[2], t.win[3], n);
     return hipGetLastError();
 }
 
