@@ -546,6 +546,15 @@ def time_workload(B, torch, name: str, steps: int, warmup: int, sample=None, sam
         for yy, oo, pp, gg, nn in calls:
             B.bmnd_denoise(yy, gg, nn, p, oo, pp, ws)
 
+    # ---- block rule of the 2-D / 3-D kernels: autotuned on the first array
+    # (every array of the workload has its shape and parameters)
+    tuned = None
+    if len(shape) in (2, 3):
+        yy, oo, pp, gg, nn = calls[0]
+        chosen, ms = B.bmnd_autotune(yy, gg, nn, p, oo, ws)
+        B.bmnd_stream_status()
+        tuned = {"chosen_rule": chosen, "ms_per_rule": [round(m, 3) for m in ms]}
+
     # ---- algorithmic work per step (group sizes from stage-isolated matching)
     one = B.geometry(shape, 1)
     refs = {B.STAGE_HT: B.bmnd_reference_origins(one, p.ht),
@@ -619,11 +628,26 @@ def time_workload(B, torch, name: str, steps: int, warmup: int, sample=None, sam
     checks = {"deterministic": bool(torch.equal(first, out)),
               "finite": bool(torch.isfinite(out).all().item())}
     if w["mc"][1]:
-        # mass conservation: the float32 output total equals the observed total
-        # up to the final float32 rounding of each voxel
-        yo = y.double().reshape(batch, -1).sum(1)
-        oo = out.double().reshape(batch, -1).sum(1)
-        checks["mass_rel_err_max"] = float(((oo - yo).abs() / yo.abs()).max().item())
+        # mass conservation (Thm. mass conservation): over the samples some
+        # group covers (eta > 0), the FP64 numerator over eta sums to the
+        # observed total to FP64 round-off, and the float output to its
+        # float rounding; samples no group covers stay 0
+        fe, oe, unc = [], [], 0
+        for yy, oo, pp, gg, nn in calls:
+            B.bmnd_denoise(yy, gg, nn, p, oo, pp, ws)
+            no, do = B.bmnd_workspace_sums(gg, nn, p)
+            nv = yy.numel()
+            num = ws[no:no + 8 * nv].view(torch.float64)
+            den = ws[do:do + 8 * nv].view(torch.float64)
+            cov = den > 0
+            yt = yy.reshape(-1).double()[cov].sum()
+            fe.append(float(((num[cov] / den[cov]).sum() - yt).abs() / yt))
+            oe.append(float((oo.reshape(-1).double()[cov].sum() - yt).abs() / yt))
+            unc += int((~cov).sum().item())
+        B.bmnd_stream_status()
+        checks["mass_fp64_rel_err_max"] = max(fe)
+        checks["mass_float_rel_err_max"] = max(oe)
+        checks["uncovered_voxels"] = unc
 
     # ---- the GPU on the oracle's sample (same crops, same parameters),
     # stage by stage: the pilot against the oracle's hard-threshold stage, the
@@ -663,7 +687,7 @@ def time_workload(B, torch, name: str, steps: int, warmup: int, sample=None, sam
                        "search": list(w["search"]), "group": list(w["group"]),
                        "profile": "plain", "mass_conservation": list(w["mc"]),
                        "noise": "Poisson, one s_P per array" if not shared else "Poisson, shared s_P",
-                       "parallelism": "single GPU"},
+                       "parallelism": "single GPU", "block_autotune": tuned},
             "roofline": roofline, "kernels": kernels, "output_checks": checks,
             "validation": val}
 
@@ -732,7 +756,7 @@ def main():
                 continue
             r = time_workload(B, torch, name, 3 if name.startswith("micro") else 10, 1)
             extra[name] = {k: r[k] for k in ("value", "ms_per_step", "roofline", "kernels",
-                                             "output_checks")}
+                                             "output_checks", "config")}
             extra[name]["unit"] = "Mvox/s"
             print(f"{name} done: {r['value']} Mvox/s", file=sys.stderr, flush=True)
 

@@ -418,6 +418,24 @@ bmnd_status bmnd_denoise_from_pilot(const float* d_y, const float* d_pilot,
                                     const bmnd_params* params, float* d_out, void* d_ws,
                                     size_t ws_bytes, void* stream);
 
+/* Autotuning of the spatial blocks of references that the 2-D and 3-D
+ * kernels of bmnd_denoise walk (the matcher stages a block's search box
+ * once per workgroup; the filter accumulates a block's numerators in an
+ * LDS box): each of BMND_BLOCK_RULES candidate rules for the block size
+ * (the largest box, the references per block) is timed on this input with
+ * two bmnd_denoise runs on `stream` after one warm-up, and the fastest is
+ * kept in the library's tuning table for this shape, patch, step, schedule
+ * and search window: every later call with them uses it.  The call waits
+ * for the timings (host-synchronous) and leaves the chosen rule's result
+ * in d_out.  ms (host, BMND_BLOCK_RULES doubles, nullable): the best time
+ * of each rule (-1 where a rule was not run); *chosen (nullable): the
+ * chosen rule, -1 when the arrays run no blocked kernels (nothing tuned).
+ * Errors: those of bmnd_denoise. */
+#define BMND_BLOCK_RULES 6
+bmnd_status bmnd_autotune(const float* d_y, const bmnd_geometry* geom, const bmnd_noise* noise,
+                          const bmnd_params* params, float* d_out, void* d_ws, size_t ws_bytes,
+                          void* stream, int32_t* chosen, double* ms);
+
 /* A batch of independent denoises (the serving and batching form of
  * bmnd_denoise, section Method Overview applied per array): any mix of
  * dimensionality, size, noise model and parameters.  Each job is exactly

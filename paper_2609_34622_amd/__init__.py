@@ -92,7 +92,7 @@ EXPORTS = [
     "bmnd_profile_begin", "bmnd_profile_end", "bmnd_batch_workspace_size", "bmnd_denoise_batch",
     "bmnd_correlated_size", "bmnd_correlated_prepare", "bmnd_denoise_noalloc",
     "bmnd_denoise_from_pilot", "bmnd_request_bytes", "bmnd_workspace_sums",
-    "bmnd_cache_limits",
+    "bmnd_cache_limits", "bmnd_autotune",
 ]
 KERNEL_IDS = ["counts", "patch_sums", "match_ht", "match_wiener", "filter_ht", "filter_wiener",
               "zero", "normalize"]
@@ -140,6 +140,7 @@ def lib() -> C.CDLL:
         "bmnd_request_bytes": (i32, [G, N, PP, sz, C.POINTER(sz)]),
         "bmnd_workspace_sums": (i32, [G, N, PP, C.POINTER(sz), C.POINTER(sz)]),
         "bmnd_cache_limits": (i32, [sz, sz]),
+        "bmnd_autotune": (i32, [vp, G, N, PP, vp, vp, sz, vp, C.POINTER(i32), vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -320,6 +321,25 @@ def bmnd_aggregate_workspace_size(geom: Geometry, sp: StageParams) -> int:
     b = C.c_size_t(0)
     _check(lib().bmnd_aggregate_workspace_size(C.byref(geom), C.byref(sp), C.byref(b)))
     return b.value
+
+
+BLOCK_RULES = 6
+
+
+def bmnd_autotune(y, geom, noise, params, out, ws, stream=None):
+    """Time the candidate block rules of the 2-D / 3-D kernels on this input
+    and keep the fastest for its shape and parameters; returns (chosen rule
+    or -1, per-rule milliseconds)."""
+    import torch
+
+    _require(y, torch.float32, name="y")
+    _require(out, torch.float32, name="out")
+    ch = C.c_int32(-1)
+    ms = np.zeros(BLOCK_RULES)
+    _check(lib().bmnd_autotune(_ptr(y), C.byref(geom), C.byref(noise), C.byref(params), _ptr(out),
+                               _ptr(ws), ws.numel() * ws.element_size(), _stream(stream),
+                               C.byref(ch), ms.ctypes.data))
+    return ch.value, ms.tolist()
 
 
 def bmnd_cache_limits(host_bytes: int = 0, device_bytes: int = 0) -> None:

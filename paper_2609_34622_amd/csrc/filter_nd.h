@@ -31,9 +31,26 @@ hipError_t launch_filter_nd(const FilterArgs& a, const NdBlocks* blk, hipStream_
 hipError_t launch_window_conv(const Geo& g, const DevTables& t, const double* W, double* eta,
                               double* reta, hipStream_t s);
 
-// Host: block sizes for a geometry and the block order of a sorted origin
-// list (refs_out: the origins in block order, start: block offsets).
-void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, bool fp64_box,
+// Rules for the size of a spatial block of references: blocks grow by 3
+// lattice positions, innermost axis first, while the box stays within
+// box_cap samples and a block holds at most max(refs_floor, refs *
+// batch / min_blocks) references.  Rule 0 is the default; the others are
+// the autotuner's candidates.
+struct BlockRule {
+    long box_cap;
+    long min_blocks;
+    long refs_floor;
+};
+constexpr BlockRule kBlockRules[] = {
+    {9216, 2048, 16}, {4096, 2048, 16}, {6144, 2048, 16}, {12288, 2048, 16},
+    {9216, 512, 64},  {16384, 1024, 32},
+};
+constexpr int kNumBlockRules = int(sizeof(kBlockRules) / sizeof(kBlockRules[0]));
+
+// Host: block sizes for a geometry under block rule `rule` and the block
+// order of a sorted origin list (refs_out: the origins in block order,
+// start: block offsets).
+void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, int rule,
                     std::vector<int64_t>& refs_out, std::vector<int>& start, NdBlocks& blk);
 
 }  // namespace bmnd

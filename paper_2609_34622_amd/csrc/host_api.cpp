@@ -429,11 +429,27 @@ LruCache<HostOrgKey, const std::vector<int64_t>>& host_origin_cache()
     return *c;
 }
 
-// blocks depend on the search window too (the box spans it)
-using BlkKey = std::pair<HostOrgKey, std::vector<int>>;
+// blocks depend on the search window too (the box spans it), and on the
+// block rule in force for that shape and window (the autotuner's choice,
+// else rule 0)
+using TuneKey = std::pair<HostOrgKey, std::vector<int>>;
+std::map<TuneKey, int> g_block_rule;   // guarded by g_cache_mu
+using BlkKey = std::tuple<HostOrgKey, std::vector<int>, int>;
+TuneKey tune_key(const bmnd_geometry& geom, const bmnd_stage_params& sp)
+{
+    return TuneKey{host_org_key(geom, sp), std::vector<int>(sp.search, sp.search + geom.ndim)};
+}
+int block_rule(const TuneKey& k)
+{
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_block_rule.find(k);
+    return it == g_block_rule.end() ? 0 : it->second;
+}
 BlkKey blk_key(const bmnd_geometry& geom, const bmnd_stage_params& sp)
 {
-    return BlkKey{host_org_key(geom, sp), std::vector<int>(sp.search, sp.search + geom.ndim)};
+    TuneKey t = tune_key(geom, sp);
+    const int rule = block_rule(t);
+    return BlkKey{std::move(t.first), std::move(t.second), rule};
 }
 LruCache<BlkKey, const HostBlocks>& host_block_cache()
 {
@@ -515,7 +531,7 @@ std::shared_ptr<const HostBlocks> host_blocks_cached(const bmnd_geometry& geom,
     auto h = std::make_shared<HostBlocks>();
     Geo g1 = g;
     g1.batch = 1;
-    nd_make_blocks(g1, *o, true, h->refs, h->start, h->blk);
+    nd_make_blocks(g1, *o, std::get<2>(key), h->refs, h->start, h->blk);
     const size_t bytes = h->refs.size() * sizeof(int64_t) + h->start.size() * sizeof(int);
     std::vector<std::shared_ptr<const HostBlocks>> dropped;
     std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -536,7 +552,7 @@ std::shared_ptr<const DevList> device_list(const bmnd_geometry& geom, const bmnd
         return nullptr;
     }
     const DevKey key{dev, blocked ? 1 : 0,
-                     blocked ? blk_key(geom, sp) : BlkKey{host_org_key(geom, sp), {}}};
+                     blocked ? blk_key(geom, sp) : BlkKey{host_org_key(geom, sp), {}, 0}};
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         if (auto v = device_list_cache().find(key)) return v;
@@ -1528,6 +1544,74 @@ bmnd_status bmnd_denoise_from_pilot(const float* d_y, const float* d_pilot,
                                    static_cast<char*>(d_ws), static_cast<hipStream_t>(stream),
                                    true, true);
     if (e != hipSuccess) return hip_fail(e, "denoise from pilot");
+    return BMND_OK;
+}
+
+static_assert(kNumBlockRules == BMND_BLOCK_RULES, "block rules and the C ABI disagree");
+
+bmnd_status bmnd_autotune(const float* d_y, const bmnd_geometry* geom, const bmnd_noise* noise,
+                          const bmnd_params* params, float* d_out, void* d_ws, size_t ws_bytes,
+                          void* stream, int32_t* chosen, double* ms)
+{
+    if (chosen) *chosen = -1;
+    DenoisePlan pl;
+    bmnd_status st = plan_denoise(geom, noise, params, &pl);
+    if (st != BMND_OK) return st;
+    if (!d_y || !d_out) return fail(BMND_E_ARG, "NULL device pointer");
+    if (!d_ws || ws_bytes < pl.total)
+        return fail(BMND_E_WORKSPACE, "workspace missing or smaller than bmnd_workspace_size");
+    if (ms)
+        for (int r = 0; r < kNumBlockRules; ++r) ms[r] = -1.0;
+    if (!pl.nd1 && !pl.nd2) return BMND_OK;   // no spatial blocks: nothing to tune
+    bmnd_geometry one = *geom;
+    one.batch = 1;
+    const TuneKey k1 = tune_key(one, params->ht), k2 = tune_key(one, params->wiener);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(BMND_E_HIP, "event creation failed");
+    auto set_rule = [&](int r) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_block_rule[k1] = r;
+        g_block_rule[k2] = r;
+    };
+    int best = 0;
+    float best_ms = 0.f;
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < kNumBlockRules && e == hipSuccess; ++r) {
+        set_rule(r);
+        DenoisePlan q;
+        if (plan_denoise(geom, noise, params, &q) != BMND_OK) continue;
+        // a candidate whose boxes do not fit keeps the older kernels: skipped
+        if (q.nd1 != pl.nd1 || q.nd2 != pl.nd2) continue;
+        float t = 0.f;
+        e = enqueue_denoise(q, d_y, d_out, nullptr, static_cast<char*>(d_ws), s, false);
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+            if (e == hipSuccess) e = hipEventRecord(a, s);
+            if (e == hipSuccess) e = enqueue_denoise(q, d_y, d_out, nullptr, static_cast<char*>(d_ws), s, false);
+            if (e == hipSuccess) e = hipEventRecord(b, s);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float m = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&m, a, b);
+            t = rep == 0 ? m : std::min(t, m);
+        }
+        if (e != hipSuccess) break;
+        if (ms) ms[r] = double(t);
+        if (r == 0 || t < best_ms) {
+            best = r;
+            best_ms = t;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    set_rule(best);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    // the output of the chosen rule
+    DenoisePlan q;
+    if ((st = plan_denoise(geom, noise, params, &q)) != BMND_OK) return st;
+    e = enqueue_denoise(q, d_y, d_out, nullptr, static_cast<char*>(d_ws), s, false);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    if (chosen) *chosen = best;
     return BMND_OK;
 }
 

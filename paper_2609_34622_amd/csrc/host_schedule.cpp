@@ -110,14 +110,16 @@ std::vector<int64_t> reference_origins(const bmnd_geometry& geom, const bmnd_sta
 // (block + search window + patch per axis) stays within kBoxCap samples and
 // the launch keeps at least kMinBlocks workgroups.  The origins are listed
 // block by block (C-order over the block grid), ascending inside a block.
-void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, bool /*fp64_box*/,
+void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, int rule,
                     std::vector<int64_t>& refs_out, std::vector<int>& start, NdBlocks& blk)
 {
-    constexpr long kBoxCap = 9216;     // 72 KiB of FP64, two workgroups per compute unit
-    constexpr long kMinBlocks = 2048;  // workgroups per launch, summed over the batch
+    // default: boxes of 72 KiB of FP64 (two workgroups per compute unit),
+    // at least 2048 workgroups per launch summed over the batch
+    const BlockRule& R = kBlockRules[rule >= 0 && rule < kNumBlockRules ? rule : 0];
+    const long kBoxCap = R.box_cap;
     blk = NdBlocks{};
     const long nref = long(refs.size());
-    const long max_refs = std::max(16L, nref * std::max(1, g.batch) / kMinBlocks);
+    const long max_refs = std::max(R.refs_floor, nref * std::max(1, g.batch) / R.min_blocks);
     int B[kAx];
     for (int d = 0; d < kAx; ++d) B[d] = std::min(g.L[d], 3);
     auto box = [&](const int* b) {

@@ -249,3 +249,33 @@ def test_denoise_from_supplied_pilot(dim):
     with pytest.raises(B.BmndError) as e:
         B.bmnd_denoise_from_pilot(yd, None, geom, noise, p, out3, ws)
     assert e.value.status == B.E_ARG
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_autotuned_blocks_keep_parity(case):
+    """bmnd_autotune times the block rules on one array and keeps the
+    fastest for its shape; the tuned denoise (every rule is the same
+    arithmetic in another order) still matches the oracle stage by stage."""
+    if case == "2d":
+        s = synth.microscopy_2d(seed=3200, size=160)
+        shape, patch, step, search, mc = (160, 160), (8, 8), (3, 3), (39, 39), (False, False)
+    else:
+        s = synth.phantom_3d(seed=4400, shape=(48, 44, 40))
+        shape, patch, step, search, mc = (48, 44, 40), (4, 4, 4), (3, 3, 3), (11, 11, 11), (True, True)
+    _say(f"autotune {shape}")
+    p = _params(shape, patch, step, search, (16, 32), mc)
+    geom, noise = B.geometry(shape), B.poisson(s.s_p)
+    yd = torch.from_numpy(np.ascontiguousarray(s.y, np.float32)).cuda()
+    ws = torch.empty(B.bmnd_workspace_size(geom, noise, p), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(yd)
+    chosen, ms = B.bmnd_autotune(yd, geom, noise, p, out, ws)
+    B.bmnd_stream_status()
+    _say(f"  chosen rule {chosen}, ms per rule {[round(m, 3) for m in ms]}")
+    assert 0 <= chosen < B.BLOCK_RULES
+    assert ms[chosen] >= 0 and ms[chosen] == min(m for m in ms if m >= 0)
+    assert sum(m >= 0 for m in ms) >= 2
+    o2, pil = _gpu_denoise(s.y, shape, s.s_p, p)[:2]
+    assert _rel(out.cpu().numpy().astype(np.float64), o2) < 1e-6
+    ht, wie = O.plain_profile(shape, patch, step, search, s_p=s.s_p, group=(16, 32), mc=mc)
+    assert _rel(pil, O.run_stage(ht, O.STAGE_HT, s.y)) < REL_OUT
+    assert _rel(o2, O.run_stage(wie, O.STAGE_WIENER, s.y, pil)) < REL_OUT
