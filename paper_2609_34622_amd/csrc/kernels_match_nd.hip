@@ -132,9 +132,13 @@ __device__ __forceinline__ void wsync()
 template <int GM>
 struct WaveSel {
     static constexpr int M = GM > 1 ? GM - 1 : 1;
-    unsigned hist[256];
+    // 16-byte aligned in every element of an array of these: the bin scan
+    // reads it four bins at a time
+    alignas(16) unsigned hist[256];
     int sel_lin[M];
     int sel_key[M];
+    int srt_lin[M];   // the members ranked by (key, lin)
+    int srt_key[M];
     double band_x[kBandCap];
     int band_l[kBandCap];
     double best_x[M];
@@ -165,6 +169,8 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     unsigned* hist = ws.hist;
     int* sel_lin = ws.sel_lin;
     int* sel_key = ws.sel_key;
+    int* srt_lin = ws.srt_lin;
+    int* srt_key = ws.srt_key;
     double* band_x = ws.band_x;
     int* band_l = ws.band_l;
     double* best_x = ws.best_x;
@@ -445,6 +451,7 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     kmn = wmin_u(kmn);
     kmx = wmax_u(kmx);
     unsigned theta_key = kmn;   // all finite keys equal: that key is the need-th
+    int less_total = 0;         // finite keys below theta (-1: not known yet)
     // histogram of f(k) over the finite keys with in(k), then the bin of the
     // rank-th smallest (1-based) and the rank within it: misc[0], misc[1]
     auto bin_of_rank = [&](auto f, auto in, int rank_) {
@@ -496,6 +503,7 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
         const unsigned bhi = unsigned(top < kmx ? top : kmx);   // the bin's key range
         if (sh == 0 || bhi == blo) {
             theta_key = blo;   // a bin of one key value
+            less_total = need - rank;
         } else if (cB <= kWave) {
             // the bin's keys into hist[0 .. cB), then each ranked among them
             int base = 0;
@@ -505,8 +513,8 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
                 if (ci < ncand && ci != rci) k = okey(from_int<S>(xs[ci]));
                 const bool in = k != kbig && lvl(k) == B;
                 const unsigned long long bal = __ballot(in);
-                if (in) hist[base + __popcll(bal & ((1ull << lane) - 1ull))] = k;
-                base += __popcll(bal);
+                if (in) hist[base + int(__popcll(bal & ((1ull << lane) - 1ull)))] = k;
+                base += int(__popcll(bal));
             }
             wsync();
             if (lane < cB) {
@@ -517,10 +525,14 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
                     less += ko < kj;
                     eq += ko == kj;
                 }
-                if (less < rank && rank <= less + eq) misc[2] = int(kj);
+                if (less < rank && rank <= less + eq) {
+                    misc[2] = int(kj);
+                    misc[3] = need - rank + less;   // finite keys below theta
+                }
             }
             wsync();
             theta_key = unsigned(misc[2]);
+            less_total = misc[3];
             wsync();
         } else {
             // radix select among the bin's keys, from the highest byte in
@@ -541,34 +553,35 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
                 wsync();
             }
             theta_key = prefix;
+            less_total = -1;
         }
     }
     // members: keys below theta, then the first ties at theta in lin order
-    const int per = (ncand + kWave - 1) / kWave;  // contiguous index range per lane
-    const int c_lo = min(ncand, lane * per), c_hi = min(ncand, c_lo + per);
-    int n_less = 0, n_eq = 0;
-    for (int ci = c_lo; ci < c_hi; ++ci) {
-        if (ci == rci) continue;
-        const unsigned k = okey(from_int<S>(xs[ci]));
-        if (k == kbig) continue;
-        n_less += k < theta_key;
-        n_eq += k == theta_key;
-    }
-    const int less_total = wsum(n_less);
-    const int eq_before = wscan_ex(n_eq);
-    int ties_left = need - less_total - eq_before;  // ties this lane may still take
-    const int slot0 = wscan_ex(n_less + max(0, min(n_eq, ties_left)));
-    {
-        int slot = slot0;
-        for (int ci = c_lo; ci < c_hi; ++ci) {
+    // (candidate order is lin order), in one pass of rounds over the
+    // candidates with slots from ballots
+    if (less_total < 0) {
+        int nl = 0;
+        for (int ci = lane; ci < ncand; ci += kWave) {
             if (ci == rci) continue;
-            const unsigned k = okey(from_int<S>(xs[ci]));
-            if (k == kbig) continue;
-            bool take = k < theta_key;
-            if (!take && k == theta_key && ties_left > 0) {
-                take = true;
-                --ties_left;
-            }
+            nl += okey(from_int<S>(xs[ci])) < theta_key;   // kbig is never below theta
+        }
+        less_total = wsum(nl);
+    }
+    {
+        const unsigned long long below = (1ull << lane) - 1ull;
+        int ties_left = need - less_total;
+        int base = 0;
+        for (int c0 = 0; c0 < ncand; c0 += kWave) {
+            const int ci = c0 + lane;
+            unsigned k = kbig;
+            if (ci < ncand && ci != rci) k = okey(from_int<S>(xs[ci]));
+            const bool eq = k == theta_key;
+            const unsigned long long beq = __ballot(eq);
+            // (the population counts are unsigned: kept out of signed arithmetic)
+            const int eq_rank = int(__popcll(beq & below)), n_eq = int(__popcll(beq));
+            const bool take = k < theta_key || (eq && eq_rank < ties_left);
+            ties_left = ties_left > n_eq ? ties_left - n_eq : 0;
+            const unsigned long long bt = __ballot(take);
             if (take) {
                 // lin of candidate ci (C order over the window)
                 int rem = ci, lin = 0;
@@ -577,11 +590,24 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
                     lin += (lo[d] + rem % n[d]) * g.st[d];
                     rem /= n[d];
                 }
+                const int slot = base + int(__popcll(bt & below));
                 sel_lin[slot] = lin;
                 sel_key[slot] = int(k ^ 0x80000000u);  // signed order = key order
-                ++slot;
             }
+            base += int(__popcll(bt));
         }
+    }
+    wsync();
+    // ranked by (key, lin)
+    for (int m = lane; m < need; m += kWave) {
+        const int km = sel_key[m], lm = sel_lin[m];
+        int rk = 0;
+        for (int o = 0; o < need; ++o) {
+            const int ko = sel_key[o], lo_ = sel_lin[o];
+            rk += ko < km || (ko == km && lo_ < lm);
+        }
+        srt_key[rk] = km;
+        srt_lin[rk] = lm;
     }
     wsync();
     int got = need;
@@ -600,16 +626,17 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
             nb += x <= thr && !(x == 0.f && th == 0.f);
         }
         nb = wsum(nb);
+        // members within the band above theta; two members within the band
+        // of each other (the band of the larger): if any pair is, so is a
+        // pair adjacent in the ranking with the same larger member
         int members_in_band = 0, close = 0;
         for (int m = lane; m < need; m += kWave) {
-            const float xm = key_float(unsigned(sel_key[m]) ^ 0x80000000u);
+            const float xm = key_float(unsigned(srt_key[m]) ^ 0x80000000u);
             members_in_band += xm <= thr && !(xm == 0.f && th == 0.f);
-            for (int o = 0; o < need; ++o) {
-                if (o == m) continue;
-                const float xo = key_float(unsigned(sel_key[o]) ^ 0x80000000u);
-                const float hi_ = fmaxf(xm, xo), lo_ = fminf(xm, xo);
-                close += hi_ - lo_ <= float(kTieBand) * (fabsf(hi_) + bmag) &&
-                         !(hi_ == 0.f && lo_ == 0.f);
+            if (m + 1 < need) {
+                const float hi_ = key_float(unsigned(srt_key[m + 1]) ^ 0x80000000u);
+                close += hi_ - xm <= float(kTieBand) * (fabsf(hi_) + bmag) &&
+                         !(hi_ == 0.f && xm == 0.f);
             }
         }
         const bool amb = nb > wsum(members_in_band) || wsum(close) > 0;
@@ -645,9 +672,9 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
                 const int ci = c0 + lane;
                 const bool in = ci < ncand && ci != rci && __int_as_float(xs[ci]) <= thr;
                 const unsigned long long bal = __ballot(in);
-                const int at = nbc + __popcll(bal & ((1ull << lane) - 1ull));
+                const int at = nbc + int(__popcll(bal & ((1ull << lane) - 1ull)));
                 if (in && at < kWave) band_l[at] = ci;
-                nbc += __popcll(bal);
+                nbc += int(__popcll(bal));
             }
             wsync();
         }
@@ -747,15 +774,7 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     if (fp64) {
         for (int m = lane; m < K - 1; m += kWave) out[1 + m] = best_l[m];
     } else {
-        for (int m = lane; m < need; m += kWave) {
-            const int km = sel_key[m], lm = sel_lin[m];
-            int rk = 0;
-            for (int o = 0; o < need; ++o) {
-                const int ko = sel_key[o], lo_ = sel_lin[o];
-                rk += ko < km || (ko == km && lo_ < lm);
-            }
-            if (rk < K - 1) out[1 + rk] = lm;
-        }
+        for (int m = lane; m < K - 1; m += kWave) out[1 + m] = srt_lin[m];
     }
 }
 
