@@ -192,7 +192,9 @@ bmnd_status bmnd_reference_origins(const bmnd_geometry* geom, const bmnd_stage_p
  * the default of 1 GiB each.  Least recently used entries beyond a budget
  * are dropped; a device copy is freed only once no call that uses it is
  * being planned or captured in a cached batch graph, and after the device
- * has finished its queued work.  Host call, any time. */
+ * has finished its queued work.  A new copy is uploaded asynchronously on
+ * the stream of the call that first needs it; calls on other streams wait
+ * for that upload on the device.  Host call, any time. */
 bmnd_status bmnd_cache_limits(size_t host_bytes, size_t device_bytes);
 
 /* Coverage map of a stage's reference schedule (section Experiments, Shift
@@ -282,7 +284,9 @@ bmnd_status bmnd_workspace_sums(const bmnd_geometry* geom, const bmnd_noise* noi
 
 /* Device memory one bmnd_denoise request holds while it runs (admission
  * against an HBM budget when serving): the input and output arrays
- * (2 batch V floats) plus bmnd_workspace_size().  Host call.  *bytes is
+ * (2 batch V floats) plus bmnd_workspace_size(); the library's own device
+ * copies of origin lists are shared between requests of one shape and
+ * bounded by bmnd_cache_limits, and are not counted.  Host call.  *bytes is
  * always written on success of the size computation; BMND_E_BUDGET when
  * budget > 0 and the request needs more than budget bytes (it can never be
  * admitted within it); other errors as bmnd_workspace_size. */

@@ -27,8 +27,10 @@ struct DenoisePlan {
     NdBlocks blk1, blk2;
     size_t offs[9] = {};
     size_t total = 0;
-    // owners of the library's device copies r1 / r2 point into
+    // owners of the library's device copies r1 / r2 point into, and the
+    // events that mark the end of their uploads
     std::shared_ptr<const void> keep[2];
+    hipEvent_t ready[2] = {nullptr, nullptr};
 };
 
 // Host part of a plan: stage configurations, reference counts and the

@@ -460,12 +460,16 @@ LruCache<BlkKey, const HostBlocks>& host_block_cache()
 // A device copy of a stage's origin list (and, for the N-D filter, of its
 // block offsets).  It is freed only after the device has finished all
 // queued work, so no launch that read it can still be running.
+// The upload runs on the stream of the call that first needs the list, from
+// host lists this entry keeps alive; `ready` marks its end for other streams.
 struct DevList {
     int dev = 0;
     int64_t* refs = nullptr;
     int* start = nullptr;
     int64_t n = 0;
     NdBlocks blk;
+    hipEvent_t ready = nullptr;
+    std::shared_ptr<const void> host;   // the host lists the upload reads
     ~DevList()
     {
         int cur = 0;
@@ -474,6 +478,7 @@ struct DevList {
             (void)hipDeviceSynchronize();
             if (refs) (void)hipFree(refs);
             if (start) (void)hipFree(start);
+            if (ready) (void)hipEventDestroy(ready);
         }
         (void)hipSetDevice(cur);
     }
@@ -544,7 +549,8 @@ namespace {
 // (blocked), or ascending.  Uploaded once per device and kept while it is
 // among the recently used lists.
 std::shared_ptr<const DevList> device_list(const bmnd_geometry& geom, const bmnd_stage_params& sp,
-                                           const Geo& g, bool blocked, std::string& err)
+                                           const Geo& g, bool blocked, hipStream_t s,
+                                           std::string& err)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
@@ -565,10 +571,13 @@ std::shared_ptr<const DevList> device_list(const bmnd_geometry& geom, const bmnd
     auto d = std::make_shared<DevList>();
     d->dev = dev;
     d->n = int64_t(refs.size());
+    if (blocked) d->host = hb;
+    else d->host = ho;
     size_t bytes = std::max<size_t>(1, refs.size()) * sizeof(int64_t);
-    if (hipMalloc(&d->refs, bytes) != hipSuccess ||
-        hipMemcpy(d->refs, refs.data(), refs.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
-            hipSuccess) {
+    if (hipEventCreateWithFlags(&d->ready, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&d->refs, bytes) != hipSuccess ||
+        hipMemcpyAsync(d->refs, refs.data(), refs.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                       s) != hipSuccess) {
         err = "allocation of the reference-origin list failed";
         return nullptr;
     }
@@ -576,12 +585,16 @@ std::shared_ptr<const DevList> device_list(const bmnd_geometry& geom, const bmnd
         d->blk = hb->blk;
         bytes += hb->start.size() * sizeof(int);
         if (hipMalloc(&d->start, hb->start.size() * sizeof(int)) != hipSuccess ||
-            hipMemcpy(d->start, hb->start.data(), hb->start.size() * sizeof(int),
-                      hipMemcpyHostToDevice) != hipSuccess) {
+            hipMemcpyAsync(d->start, hb->start.data(), hb->start.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s) != hipSuccess) {
             err = "allocation of the block offsets failed";
             return nullptr;
         }
         d->blk.start = d->start;
+    }
+    if (hipEventRecord(d->ready, s) != hipSuccess) {
+        err = "event record failed";
+        return nullptr;
     }
     std::vector<std::shared_ptr<const DevList>> dropped;
     std::shared_ptr<const DevList> out;
@@ -1269,7 +1282,7 @@ bmnd_status plan_denoise_host(const bmnd_geometry* geom, const bmnd_noise* noise
 }
 
 bmnd_status plan_denoise(const bmnd_geometry* geom, const bmnd_noise* noise,
-                         const bmnd_params* params, DenoisePlan* pl)
+                         const bmnd_params* params, DenoisePlan* pl, hipStream_t s)
 {
     if (!params) return fail(BMND_E_ARG, "params is NULL");
     bmnd_status st = make_stage(geom, noise, &params->ht, BMND_STAGE_HT, pl->c1);
@@ -1283,8 +1296,8 @@ bmnd_status plan_denoise(const bmnd_geometry* geom, const bmnd_noise* noise,
     pl->nd1 = stage_uses_nd(pl->c1) && nd_blocks_fit(host_blocks_cached(one, params->ht, pl->c1.g)->blk);
     pl->nd2 = stage_uses_nd(pl->c2) &&
               nd_blocks_fit(host_blocks_cached(one, params->wiener, pl->c2.g)->blk);
-    auto l1 = device_list(one, params->ht, pl->c1.g, pl->nd1, err);
-    auto l2 = l1 ? device_list(one, params->wiener, pl->c2.g, pl->nd2, err) : nullptr;
+    auto l1 = device_list(one, params->ht, pl->c1.g, pl->nd1, s, err);
+    auto l2 = l1 ? device_list(one, params->wiener, pl->c2.g, pl->nd2, s, err) : nullptr;
     if (!l1 || !l2) return fail(BMND_E_NOMEM, err);
     pl->r1 = l1->refs;
     pl->n1 = l1->n;
@@ -1294,6 +1307,8 @@ bmnd_status plan_denoise(const bmnd_geometry* geom, const bmnd_noise* noise,
     if (pl->nd2) pl->blk2 = l2->blk;
     pl->keep[0] = l1;
     pl->keep[1] = l2;
+    pl->ready[0] = l1->ready;
+    pl->ready[1] = l2->ready;
     pl->t1 = device_tables(pl->c1, err);
     pl->t2 = pl->t1 ? device_tables(pl->c2, err) : nullptr;
     if (!pl->t1 || !pl->t2) return fail(BMND_E_NOMEM, err);
@@ -1316,6 +1331,16 @@ hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out
     double* wf = reinterpret_cast<double*>(ws + pl.offs[7]);
     double* rden = reinterpret_cast<double*>(ws + pl.offs[8]);
     const size_t vox = size_t(pl.c1.g.batch) * pl.c1.g.V;
+    {
+        // the origin lists' uploads, if another stream queued them
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        (void)hipStreamIsCapturing(s, &cs);
+        for (hipEvent_t ev : pl.ready)
+            if (ev && cs == hipStreamCaptureStatusNone) {
+                const hipError_t e = hipStreamWaitEvent(s, ev, 0);
+                if (e != hipSuccess) return e;
+            }
+    }
     const int no_span = -1;
 
     auto run_stage = [&](const StageCfg& c, const DevTables& t, const int64_t* refs, int64_t nr,
@@ -1443,7 +1468,8 @@ struct BatchLayout {
     size_t total = 0;
 };
 
-bmnd_status layout_batch(int32_t n_jobs, const bmnd_job* jobs, BatchLayout* L, bool device)
+bmnd_status layout_batch(int32_t n_jobs, const bmnd_job* jobs, BatchLayout* L, bool device,
+                         hipStream_t s = nullptr)
 {
     if (n_jobs < 0) return fail(BMND_E_ARG, "n_jobs < 0");
     if (n_jobs > 0 && !jobs) return fail(BMND_E_ARG, "jobs is NULL");
@@ -1452,7 +1478,7 @@ bmnd_status layout_batch(int32_t n_jobs, const bmnd_job* jobs, BatchLayout* L, b
     std::vector<double> work(static_cast<size_t>(n_jobs));
     for (int i = 0; i < n_jobs; ++i) {
         DenoisePlan* pl = &L->plans[size_t(i)];
-        const bmnd_status st = device ? plan_denoise(&jobs[i].geom, &jobs[i].noise, &jobs[i].params, pl)
+        const bmnd_status st = device ? plan_denoise(&jobs[i].geom, &jobs[i].noise, &jobs[i].params, pl, s)
                                       : plan_denoise_host(&jobs[i].geom, &jobs[i].noise, &jobs[i].params, pl);
         if (st != BMND_OK) {
             set_error("job " + std::to_string(i) + ": " + bmnd_last_error());
@@ -1517,7 +1543,7 @@ bmnd_status bmnd_denoise(const float* d_y, const bmnd_geometry* geom,
                          float* d_pilot, void* d_ws, size_t ws_bytes, void* stream)
 {
     DenoisePlan pl;
-    bmnd_status st = plan_denoise(geom, noise, params, &pl);
+    bmnd_status st = plan_denoise(geom, noise, params, &pl, static_cast<hipStream_t>(stream));
     if (st != BMND_OK) return st;
     if (!d_y || !d_out) return fail(BMND_E_ARG, "NULL device pointer");
     if (!d_ws || ws_bytes < pl.total)
@@ -1534,7 +1560,7 @@ bmnd_status bmnd_denoise_from_pilot(const float* d_y, const float* d_pilot,
                                     size_t ws_bytes, void* stream)
 {
     DenoisePlan pl;
-    bmnd_status st = plan_denoise(geom, noise, params, &pl);
+    bmnd_status st = plan_denoise(geom, noise, params, &pl, static_cast<hipStream_t>(stream));
     if (st != BMND_OK) return st;
     if (!d_y || !d_pilot || !d_out) return fail(BMND_E_ARG, "NULL device pointer");
     if (!d_ws || ws_bytes < pl.total)
@@ -1555,7 +1581,7 @@ bmnd_status bmnd_autotune(const float* d_y, const bmnd_geometry* geom, const bmn
 {
     if (chosen) *chosen = -1;
     DenoisePlan pl;
-    bmnd_status st = plan_denoise(geom, noise, params, &pl);
+    bmnd_status st = plan_denoise(geom, noise, params, &pl, static_cast<hipStream_t>(stream));
     if (st != BMND_OK) return st;
     if (!d_y || !d_out) return fail(BMND_E_ARG, "NULL device pointer");
     if (!d_ws || ws_bytes < pl.total)
@@ -1581,7 +1607,7 @@ bmnd_status bmnd_autotune(const float* d_y, const bmnd_geometry* geom, const bmn
     for (int r = 0; r < kNumBlockRules && e == hipSuccess; ++r) {
         set_rule(r);
         DenoisePlan q;
-        if (plan_denoise(geom, noise, params, &q) != BMND_OK) continue;
+        if (plan_denoise(geom, noise, params, &q, s) != BMND_OK) continue;
         // a candidate whose boxes do not fit keeps the older kernels: skipped
         if (q.nd1 != pl.nd1 || q.nd2 != pl.nd2) continue;
         float t = 0.f;
@@ -1608,7 +1634,7 @@ bmnd_status bmnd_autotune(const float* d_y, const bmnd_geometry* geom, const bmn
     if (e != hipSuccess) return hip_fail(e, "autotune");
     // the output of the chosen rule
     DenoisePlan q;
-    if ((st = plan_denoise(geom, noise, params, &q)) != BMND_OK) return st;
+    if ((st = plan_denoise(geom, noise, params, &q, s)) != BMND_OK) return st;
     e = enqueue_denoise(q, d_y, d_out, nullptr, static_cast<char*>(d_ws), s, false);
     if (e != hipSuccess) return hip_fail(e, "autotune");
     if (chosen) *chosen = best;
@@ -1629,7 +1655,7 @@ bmnd_status bmnd_denoise_batch(int32_t n_jobs, const bmnd_job* jobs, void* d_ws,
                                int32_t flags, void* stream)
 {
     BatchLayout L;
-    bmnd_status st = layout_batch(n_jobs, jobs, &L, true);
+    bmnd_status st = layout_batch(n_jobs, jobs, &L, true, static_cast<hipStream_t>(stream));
     if (st != BMND_OK) return st;
     if (n_jobs == 0) return BMND_OK;
     for (int i = 0; i < n_jobs; ++i)
