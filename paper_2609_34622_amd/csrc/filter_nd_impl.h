@@ -224,6 +224,32 @@ __device__ __forceinline__ int patch_off(int i, const Geo& g)
     else return (i / (J * J)) * g.st[kAx - 3] + ((i / J) % J) * g.st[kAx - 2] + (i % J);
 }
 
+// Rows of a patch (runs of J samples along the last axis) read four samples
+// per load: one address per row and four samples instead of a load per
+// sample (a wavefront's lanes read different patches, so each load costs
+// one address per lane).  Global memory takes these 4-byte aligned.
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef double d4u __attribute__((ext_vector_type(4), aligned(8)));
+
+template <int D, int J, int P>
+__device__ __forceinline__ void load_patch(const float* __restrict__ p, const Geo& g,
+                                           float (&out)[P])
+{
+    static_assert(J % 4 == 0, "rows of a multiple of 4 samples");
+#pragma unroll
+    for (int r = 0; r < P / J; ++r) {
+        const float* row = p + patch_off<D, J>(r * J, g);
+#pragma unroll
+        for (int c = 0; c < J; c += 4) {
+            const f4u v = *reinterpret_cast<const f4u*>(row + c);
+            out[r * J + c] = v.x;
+            out[r * J + c + 1] = v.y;
+            out[r * J + c + 2] = v.z;
+            out[r * J + c + 3] = v.w;
+        }
+    }
+}
+
 // product over the patch axes of a per-axis table entry tab[axis][c_axis]
 // for sample (or coefficient) index i, C-order over the D patch axes
 template <int D, int J>
@@ -420,10 +446,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
         if constexpr (WIE) {
             // ---- pilot: Gamma and sigma^2, then the gains
             float gm[P];
+            load_patch<D, J>(pb + org, g, gm);
 #pragma unroll
             for (int i = 0; i < P; ++i) {
-                const float ld = pb[org + patch_off<D, J>(i, g)];
-                const float pv = act ? ld : 0.f;
+                const float pv = act ? gm[i] : 0.f;
                 gm[i] = pv;
                 v[i] = fmaxf(pv, 0.f);
             }
@@ -459,11 +485,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
             }
             if constexpr (OM != 2) {
                 // ---- observation: C = G Y
+                load_patch<D, J>(yo, g, x);
 #pragma unroll
-                for (int i = 0; i < P; ++i) {
-                    const float ld = yo[patch_off<D, J>(i, g)];
-                    x[i] = act ? ld : 0.f;
-                }
+                for (int i = 0; i < P; ++i) x[i] = act ? x[i] : 0.f;
                 spatial_reg<D, J>(x, Tm);
                 haar_fwd<GM, P>(x, jl, lk);
 #pragma unroll
@@ -471,10 +495,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
             }
         } else {
             // ---- observation and its variance map
+            load_patch<D, J>(yo, g, x);
 #pragma unroll
             for (int i = 0; i < P; ++i) {
-                const float ld = yo[patch_off<D, J>(i, g)];
-                const float yv = act ? ld : 0.f;
+                const float yv = act ? x[i] : 0.f;
                 x[i] = yv;
                 gn2 = __builtin_fmaf(yv, yv, gn2);
                 v[i] = fmaxf(yv, 0.f);
@@ -637,12 +661,21 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                         // four partial sums: independent FP64 chains
                         double zs4[4] = {0.0, 0.0, 0.0, 0.0}, zr4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                        for (int i = 0; i < P; ++i) {
-                            const int u = org + patch_off<D, J>(i, g);
-                            const float w = axis_prod<D, J>(tab, a.t.win, i);
-                            const double zeta = double(wj) * double(w) * dend[vb + u];
-                            zs4[i & 3] += zeta;
-                            zr4[i & 3] += zeta * (double(yb[u]) - double(x[i]));
+                        for (int i0 = 0; i0 < P; i0 += 4) {
+                            // four samples of a row: 1 / eta and y by vector loads
+                            const int u = org + patch_off<D, J>(i0, g);
+                            const d4u re = *reinterpret_cast<const d4u*>(dend + vb + u);
+                            const f4u yr = *reinterpret_cast<const f4u*>(yb + u);
+                            const double rev[4] = {re.x, re.y, re.z, re.w};
+                            const float yv[4] = {yr.x, yr.y, yr.z, yr.w};
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                const int i = i0 + c;
+                                const float w = axis_prod<D, J>(tab, a.t.win, i);
+                                const double zeta = double(wj) * double(w) * rev[c];
+                                zs4[c] += zeta;
+                                zr4[c] += zeta * (double(yv[c]) - double(x[i]));
+                            }
                         }
                         zs = (zs4[0] + zs4[1]) + (zs4[2] + zs4[3]);
                         zr = (zr4[0] + zr4[1]) + (zr4[2] + zr4[3]);
