@@ -247,7 +247,8 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
         return o;
     };
 
-    // ---- scores of every candidate
+    // ---- scores of every candidate, and the range of the finite keys
+    unsigned kmn = 0xFFFFFFFFu, kmx = 0u;
     const float bmag = MODE == kGauss ? (a.bias_t ? float(*a.bias_bound) : fabsf(a.bias)) : 0.f;
     const int n3 = n[kAx - 1];
     const int rpr = (n3 + kRB - 1) / kRB;  // runs per line
@@ -304,6 +305,10 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
                         int x = int(sp2 + q2 - 2u * pq) - a.gamma_i * int(sp1 + q1);
                         if (ci == rci) x = INT_MAX;
                         xs[ci] = x;
+                        if (ci != rci) {
+                            kmn = min(kmn, okey(x));
+                            kmx = max(kmx, okey(x));
+                        }
                     }
                 }
             }
@@ -361,6 +366,10 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
                 if constexpr (kF) x = x == x ? x : bigv<S>();
                 if (ci == rci) x = bigv<S>();
                 xs[ci] = as_int(x);
+                if (okey(x) != okey(bigv<S>())) {
+                    kmn = min(kmn, okey(x));
+                    kmx = max(kmx, okey(x));
+                }
             }
         }
     }
@@ -370,15 +379,21 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     float tau_band = 0.f;
     if constexpr (kF) tau_band = float(kTieBand) * (fabsf(a.tau_f) + bmag);
     const unsigned kbig = okey(bigv<S>());  // excluded: the reference, non-finite scores
+    // the histogram of 256 equal bins over the keys' range is built in the
+    // same pass (level 1 of the selection below)
+    kmn = wmin_u(kmn);
+    kmx = wmax_u(kmx);
+    const unsigned span = kmx > kmn ? kmx - kmn : 0u;
+    const int sh = span < 256u ? 0 : (32 - __clz(span)) - 8;   // span >> sh < 256
+    for (int h = lane; h < 256; h += kWave) hist[h] = 0u;
+    wsync();
     int acc = 0, namb = 0, nfin = 0;
-    unsigned kmn = 0xFFFFFFFFu, kmx = 0u;   // range of the finite keys
     for (int ci = lane; ci < ncand; ci += kWave) {
         const S x = from_int<S>(xs[ci]);
         const unsigned kx = okey(x);
         if (ci == rci || kx == kbig) continue;
         ++nfin;
-        kmn = min(kmn, kx);
-        kmx = max(kmx, kx);
+        if (span != 0u) atomicAdd(&hist[(kx - kmn) >> sh], 1u);
         if constexpr (MODE == kCount) {
             acc += x < a.tau_i;
         } else {
@@ -448,19 +463,19 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     // the rank; level 2: the keys of that bin, at most one per lane, are
     // ranked exactly.  A fuller bin falls back to a radix select, 8 bits at
     // a time, among its keys.
-    kmn = wmin_u(kmn);
-    kmx = wmax_u(kmx);
     unsigned theta_key = kmn;   // all finite keys equal: that key is the need-th
     int less_total = 0;         // finite keys below theta (-1: not known yet)
     // histogram of f(k) over the finite keys with in(k), then the bin of the
     // rank-th smallest (1-based) and the rank within it: misc[0], misc[1]
-    auto bin_of_rank = [&](auto f, auto in, int rank_) {
-        for (int h = lane; h < 256; h += kWave) hist[h] = 0u;
-        wsync();
-        for (int ci = lane; ci < ncand; ci += kWave) {
-            if (ci == rci) continue;
-            const unsigned k = okey(from_int<S>(xs[ci]));
-            if (k != kbig && in(k)) atomicAdd(&hist[f(k)], 1u);
+    auto bin_of_rank = [&](auto f, auto in, int rank_, bool built) {
+        if (!built) {
+            for (int h = lane; h < 256; h += kWave) hist[h] = 0u;
+            wsync();
+            for (int ci = lane; ci < ncand; ci += kWave) {
+                if (ci == rci) continue;
+                const unsigned k = okey(from_int<S>(xs[ci]));
+                if (k != kbig && in(k)) atomicAdd(&hist[f(k)], 1u);
+            }
         }
         wsync();
         // each lane owns 4 consecutive bins; a wave prefix sum gives the
@@ -489,11 +504,9 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
         }
         wsync();
     };
-    const unsigned span = kmx - kmn;
     if (span != 0u) {
-        const int sh = span < 256u ? 0 : (32 - __clz(span)) - 8;   // span >> sh < 256
         auto lvl = [&](unsigned k) { return (k - kmn) >> sh; };
-        bin_of_rank(lvl, [](unsigned) { return true; }, need);
+        bin_of_rank(lvl, [](unsigned) { return true; }, need, true);
         const unsigned B = unsigned(misc[0]);
         const int rank = misc[1];
         const int cB = int(hist[B]);
@@ -546,7 +559,8 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
                 const int s_ = shift;
                 const unsigned pm = pmask, pf = prefix;
                 bin_of_rank([s_](unsigned k) { return (k >> s_) & 255u; },
-                            [&](unsigned k) { return lvl(k) == B && (k & pm) == pf; }, r2);
+                            [&](unsigned k) { return lvl(k) == B && (k & pm) == pf; }, r2,
+                            false);
                 prefix |= unsigned(misc[0]) << shift;
                 pmask |= 255u << shift;
                 r2 = misc[1];
