@@ -38,6 +38,7 @@ PEAK_HBM_GBS = 8000.0
 COPY_KERNEL_HINT = "MulFunctor"   # the calibration kernel: dst = src * 1
 METRIC = "denoised Mvox/s (both stages) at \u22641e-4 rel err; serving p50/p99 latency"
 REL_ERR_BAR = 1e-4
+AUTOTUNE = True
 
 WORKLOADS = {
     "ecg-1d-batch": dict(shape=(65536,), batch=256, patch=(32,), step=(4,), search=(256,),
@@ -549,7 +550,7 @@ def time_workload(B, torch, name: str, steps: int, warmup: int, sample=None, sam
     # ---- block rule of the 2-D / 3-D kernels: autotuned on the first array
     # (every array of the workload has its shape and parameters)
     tuned = None
-    if len(shape) in (2, 3):
+    if AUTOTUNE and len(shape) in (2, 3):
         yy, oo, pp, gg, nn = calls[0]
         chosen, ms = B.bmnd_autotune(yy, gg, nn, p, oo, ws)
         B.bmnd_stream_status()
@@ -705,6 +706,9 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, copy this many MiB device to device once "
                          "(calibrates HBM byte counters under rocprofv3)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="tune the 2-D/3-D block rule on the first array before timing (0: the "
+                         "default rule, as the profiling commands run)")
     ap.add_argument("--serving-requests", type=int, default=2000,
                     help="requests in the serving trace (0: skip the serving comparison)")
     ap.add_argument("--mixed", type=int, default=1,
@@ -714,6 +718,8 @@ def main():
                     help="summarize rocprofv3 databases (FETCH_SIZE / WRITE_SIZE runs of a "
                          "--copy-probe-mib bench) into per-launch HBM bytes, print JSON, exit")
     args = ap.parse_args()
+    global AUTOTUNE
+    AUTOTUNE = bool(args.autotune)
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(args.summarize_pmc, args.copy_probe_mib), indent=1))
         return

@@ -427,8 +427,10 @@ bmnd_status bmnd_denoise_from_pilot(const float* d_y, const float* d_pilot,
  * once per workgroup; the filter accumulates a block's numerators in an
  * LDS box): each of BMND_BLOCK_RULES candidate rules for the block size
  * (the largest box, the references per block) is timed on this input with
- * two bmnd_denoise runs on `stream` after one warm-up, and the fastest is
- * kept in the library's tuning table for this shape, patch, step, schedule
+ * two bmnd_denoise runs on `stream` after one warm-up, and the fastest (a
+ * rule replaces rule 0, the default, or an earlier rule only when at least
+ * 3 % faster) is kept in the library's tuning table for this shape, patch,
+ * step, schedule
  * and search window: every later call with them uses it.  The call waits
  * for the timings (host-synchronous) and leaves the chosen rule's result
  * in d_out.  ms (host, BMND_BLOCK_RULES doubles, nullable): the best time

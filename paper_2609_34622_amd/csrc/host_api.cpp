@@ -1623,7 +1623,9 @@ bmnd_status bmnd_autotune(const float* d_y, const bmnd_geometry* geom, const bmn
         }
         if (e != hipSuccess) break;
         if (ms) ms[r] = double(t);
-        if (r == 0 || t < best_ms) {
+        // another rule replaces rule 0 (and a later rule an earlier one) only
+        // when at least 3 % faster, so timing noise does not flip the choice
+        if (r == 0 || t < 0.97f * best_ms) {
             best = r;
             best_ms = t;
         }

@@ -272,7 +272,7 @@ def test_autotuned_blocks_keep_parity(case):
     B.bmnd_stream_status()
     _say(f"  chosen rule {chosen}, ms per rule {[round(m, 3) for m in ms]}")
     assert 0 <= chosen < B.BLOCK_RULES
-    assert ms[chosen] >= 0 and ms[chosen] == min(m for m in ms if m >= 0)
+    assert ms[chosen] >= 0 and ms[chosen] <= min(m for m in ms if m >= 0) / 0.97 + 1e-9
     assert sum(m >= 0 for m in ms) >= 2
     o2, pil = _gpu_denoise(s.y, shape, s.s_p, p)[:2]
     assert _rel(out.cpu().numpy().astype(np.float64), o2) < 1e-6
