@@ -19,6 +19,16 @@ struct NdBlocks {
     int E[kAx] = {1, 1, 1, 1};
     int S[kAx] = {1, 1, 1, 1};
     int box_size = 0;
+    // The matcher's LDS copies of the same box: 32-bit samples at strides
+    // MS (mbox words in all), and four byte copies of counts at strides MSb
+    // (mbox_b bytes each, copy c at byte c * mcst).  Rows and planes are
+    // padded so that the wavefront's lanes, one run of candidates each,
+    // read distinct LDS banks (see nd_match_layout).
+    int MS[kAx] = {1, 1, 1, 1};
+    int MSb[kAx] = {1, 1, 1, 1};
+    int mbox = 0;
+    int mbox_b = 0;
+    int mcst = 0;
 };
 
 struct FilterArgs;
@@ -52,5 +62,9 @@ constexpr int kNumBlockRules = int(sizeof(kBlockRules) / sizeof(kBlockRules[0]))
 // start: block offsets).
 void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, int rule,
                     std::vector<int64_t>& refs_out, std::vector<int>& start, NdBlocks& blk);
+
+// Host: the matcher's padded LDS layouts of a block's box (MS, MSb, mbox,
+// mbox_b, mcst) for the geometry's window and patch; nd_make_blocks calls it.
+void nd_match_layout(const Geo& g, NdBlocks& blk);
 
 }  // namespace bmnd

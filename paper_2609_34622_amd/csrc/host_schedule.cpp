@@ -162,6 +162,7 @@ void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, int rule,
     }
     blk.box_size = s;
     blk.nblocks = int(nblocks);
+    nd_match_layout(g, blk);
     // counting sort by block
     std::vector<int> bid(refs.size());
     start.assign(size_t(nblocks) + 1, 0);

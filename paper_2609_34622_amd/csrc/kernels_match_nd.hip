@@ -797,10 +797,12 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
 // scoring, float bit patterns otherwise; positions outside the array are 0
 // (no candidate reads them).  Coordinates advance by the thread stride with
 // carries, without a division per sample.
+// The samples of the box of extents ext from org (zeros outside the array)
+// into sx, sample (c_0, ..., c_3) of the box at sum_d c_d sst[d].
 template <int MODE>
 __device__ __forceinline__ void stage_box(const MatchArgs& a, int kmax, const float* src,
-                                          const int* org, const int* ext, int total, int* sx,
-                                          int tid, int nthreads)
+                                          const int* org, const int* ext, int total,
+                                          const int* sst, int* sx, int tid, int nthreads)
 {
     const Geo& g = a.g;
     int c[kAx], dc[kAx];
@@ -823,7 +825,9 @@ __device__ __forceinline__ void stage_box(const MatchArgs& a, int kmax, const fl
             in = in && x >= 0 && x < g.L[d];
             u += x * g.st[d];
         }
-        int v = 0;
+        int v = 0, p = 0;
+#pragma unroll
+        for (int d = 0; d < kAx; ++d) p += c[d] * sst[d];
         if (in) {
             const float x = src[u];
             if constexpr (MODE == kCount) {
@@ -836,7 +840,7 @@ __device__ __forceinline__ void stage_box(const MatchArgs& a, int kmax, const fl
                 v = __float_as_int(x);
             }
         }
-        sx[e] = v;
+        sx[p] = v;
         // advance by nthreads: add the per-axis digits with carries
         int carry = 0;
 #pragma unroll
@@ -883,12 +887,25 @@ __global__ __launch_bounds__(kWave) void k_match_nd(MatchArgs a, int kmax)
     }
     int* sx = smem;                   // [nreg + kPad] staged samples
     int* xs = smem + nreg + kPad;     // [ncand] scores (bit patterns)
-    stage_box<MODE>(a, kmax, a.src + long(b) * g.V, lo, R, nreg, sx, lane, kWave);
+    stage_box<MODE>(a, kmax, a.src + long(b) * g.V, lo, R, nreg, sst, sx, lane, kWave);
     for (int e = nreg + lane; e < nreg + kPad; e += kWave) sx[e] = 0;
     wsync();
     int roff[64 / J3];
     row_offsets(g, sst, roff);
     match_one<MODE, GM, J3, kRB>(a, b, gi, sx, lo, sst, roff, xs, ws, nullptr, 0);
+}
+
+// Candidates per run along the last axis in the block kernel: runs fill
+// the 11-candidate lines of 4-sample patches and the 39-candidate lines of
+// 8-sample patches.
+constexpr int blk_rb(int j3) { return j3 == 4 ? 11 : 13; }
+
+// LDS words of a block's staged box: the 32-bit copy with its pad; in
+// count mode also the four byte copies (the same memory), whichever is
+// larger.
+__host__ __device__ inline int blk_box_words(const NdBlocks& blk, bool count)
+{
+    return !count || blk.mbox + kPad > blk.mcst ? blk.mbox + kPad : blk.mcst;
 }
 
 // One workgroup per spatial block of references (the list in block order,
@@ -919,9 +936,9 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
             blo[d] = bc * blk.B[d] - g.W[d] / 2;
         }
     }
-    constexpr int RB = J3 == 4 ? 11 : 13;   // runs fill 11- and 39-candidate lines
-    int* sx = smem;                                            // [box + kPad]
-    int* xs = smem + blk.box_size + kPad + wave * ncand_max;   // [ncand] per wavefront
+    constexpr int RB = blk_rb(J3);
+    int* sx = smem;                                        // [box words]
+    int* xs = smem + blk_box_words(blk, MODE == kCount) + wave * ncand_max;   // [ncand] per wavefront
     const float* src = a.src + long(b) * g.V;
     const unsigned char* sb = nullptr;
     int cst = 0;
@@ -931,10 +948,10 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
         // byte; otherwise staged again as integers below
         __shared__ int big;
         if (threadIdx.x == 0) big = 0;
-        cst = (blk.box_size + kPad + 3) & ~3;
+        cst = blk.mcst;
         unsigned char* cb = reinterpret_cast<unsigned char*>(smem);
         __syncthreads();
-        for (int e = blk.box_size + int(threadIdx.x); e < cst + 3; e += kMWaves * kWave)
+        for (int e = blk.mbox_b + int(threadIdx.x); e < cst + 3; e += kMWaves * kWave)
 #pragma unroll
             for (int c = 0; c < 4; ++c)
                 if (e - c >= 0 && e - c < cst) cb[c * cst + e - c] = 0;
@@ -958,7 +975,9 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
                     in = in && x >= 0 && x < g.L[d];
                     u += x * g.st[d];
                 }
-                int v = 0;
+                int v = 0, p = 0;
+#pragma unroll
+                for (int d = 0; d < kAx; ++d) p += c[d] * blk.MSb[d];
                 if (in) {
                     const float rk = rintf(src[u] * a.inv_sp);
                     const bool ok = rk >= 0.f && rk <= float(kmax);
@@ -968,7 +987,7 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
                 over = over || v > 255;
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (e - k >= 0) cb[k * cst + e - k] = (unsigned char)(v & 255);
+                    if (p - k >= 0) cb[k * cst + p - k] = (unsigned char)(v & 255);
                 int carry = 0;
 #pragma unroll
                 for (int d = kAx - 1; d >= 0; --d) {
@@ -987,16 +1006,19 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
     }
     if (sb == nullptr) {
         if constexpr (MODE == kCount) __syncthreads();   // the byte copies are done with
-        stage_box<MODE>(a, kmax, src, blo, blk.E, blk.box_size, sx, threadIdx.x, kMWaves * kWave);
-        for (int e = blk.box_size + int(threadIdx.x); e < blk.box_size + kPad;
-             e += kMWaves * kWave)
+        stage_box<MODE>(a, kmax, src, blo, blk.E, blk.box_size, blk.MS, sx, threadIdx.x,
+                        kMWaves * kWave);
+        for (int e = blk.mbox + int(threadIdx.x); e < blk.mbox + kPad; e += kMWaves * kWave)
             sx[e] = 0;
     }
     __syncthreads();
+    int sst[kAx];
+#pragma unroll
+    for (int d = 0; d < kAx; ++d) sst[d] = sb != nullptr ? blk.MSb[d] : blk.MS[d];
     int roff[64 / J3];
-    row_offsets(g, blk.S, roff);
+    row_offsets(g, sst, roff);
     for (int gi = r0 + wave; gi < r1; gi += kMWaves)
-        match_one<MODE, GM, J3, RB>(a, b, gi, sx, blo, blk.S, roff, xs, ws[wave], sb, cst);
+        match_one<MODE, GM, J3, RB>(a, b, gi, sx, blo, sst, roff, xs, ws[wave], sb, cst);
 }
 
 }  // namespace
@@ -1070,6 +1092,136 @@ static void nd_sizes(const Geo& g, int* region, int* cand)
     *cand = cd;
 }
 
+namespace {
+
+// Bank collisions of a wavefront's reads in a staged box: lanes take runs of
+// rb candidates in order, run = r + rpr * line with the line in C order over
+// the window's other axes (positions n[0..2]), and read at the same offset
+// from their run's first sample.  32-bit samples sit at strides S (words);
+// byte copies (bytes true) at strides S in bytes, copy c at word offset
+// c * x, a lane reading the word of its run's first sample in the copy of
+// its byte phase.  Summed over the first run groups (and the four byte
+// phases): the largest number of lanes on one bank, with 32 banks for each
+// half of a wavefront plus with 64 banks for the whole of it.
+int bank_cost(const int* n, const int* S, int rb, int rpr, bool bytes, int x)
+{
+    const int nruns = n[0] * n[1] * n[2] * rpr;
+    int cost = 0;
+    for (int g0 = 0; g0 < std::min(nruns, 4 * kWave); g0 += kWave)
+        for (int v = 0; v < (bytes ? 4 : 1); ++v) {
+            int c32[2][32] = {}, c64[64] = {};
+            int w32 = 0, w64 = 0;
+            for (int run = g0; run < std::min(nruns, g0 + kWave); ++run) {
+                const int line = run / rpr, r = run - line * rpr;
+                long p = long(rb) * r + v;
+                int rem = line;
+                for (int d = kAx - 2; d >= 0; --d) {
+                    p += long(rem % n[d]) * S[d];
+                    rem /= n[d];
+                }
+                const long w = bytes ? (p >> 2) + (p & 3) * long(x) : p;
+                const int half = (run - g0) >> 5;
+                w32 = std::max(w32, ++c32[half][w & 31]);
+                w64 = std::max(w64, ++c64[w & 63]);
+            }
+            cost += w32 + w64;
+        }
+    return cost;
+}
+
+}  // namespace
+
+// The matcher's LDS layouts of a block's box: row and plane strides padded
+// so that the lanes of a wavefront, one run of candidates each, read from
+// distinct banks where the padding allows it.  Candidates: row strides up
+// to 32 samples past the row (multiples of 4 bytes for the byte copies),
+// plane strides up to 32 words past the plane, and for byte copies whose
+// lanes differ in byte phase (several runs a line) the copies' word offset
+// mod 64.  The fewest collisions win, then the smallest box; a layout only
+// counts while the workgroup's LDS stays within what the unpadded box
+// needs or half a compute unit's LDS, whichever is larger, so that as many
+// workgroups stay resident.  Outer strides of 4-D boxes are left unpadded.
+void nd_match_layout(const Geo& g, NdBlocks& blk)
+{
+    const int rb = blk_rb(g.j[kAx - 1]);
+    int n[kAx];
+    for (int d = 0; d < kAx; ++d) n[d] = std::min(g.W[d], g.ell[d] + 1);
+    const int rpr = (n[kAx - 1] + rb - 1) / rb;
+    int region = 0, cand = 0;
+    nd_sizes(g, &region, &cand);
+    const long fixed = long(sizeof(int)) * kMWaves * cand + kMWaves * long(sizeof(WaveSel<32>));
+    const long plain_words = blk.box_size + kPad;
+    const long budget_words =
+        std::max(plain_words, (80L * 1024L - fixed) / long(sizeof(int)));
+    const bool plane = n[kAx - 3] > 1;   // lines span a second axis
+
+    auto outer = [&](int* S) {
+        for (int d = kAx - 4; d >= 0; --d) S[d] = blk.E[d + 1] * S[d + 1];
+    };
+    // 32-bit copy
+    {
+        int best = INT_MAX;
+        long best_size = 0;
+        int S[kAx];
+        S[kAx - 1] = 1;
+        for (int s2 = blk.E[kAx - 1]; s2 < blk.E[kAx - 1] + 32; ++s2)
+            for (int s1 = blk.E[kAx - 2] * s2; s1 < blk.E[kAx - 2] * s2 + (plane ? 32 : 1); ++s1) {
+                S[kAx - 2] = s2;
+                S[kAx - 3] = s1;
+                outer(S);
+                const long size = long(blk.E[0]) * S[0];
+                if (size + kPad > budget_words) continue;
+                const int k = bank_cost(n, S, rb, rpr, false, 0);
+                if (k < best || (k == best && size < best_size)) {
+                    best = k;
+                    best_size = size;
+                    std::copy(S, S + kAx, blk.MS);
+                }
+            }
+        if (best == INT_MAX) std::copy(blk.S, blk.S + kAx, blk.MS);
+        blk.mbox = blk.E[0] * blk.MS[0];
+    }
+    // byte copies
+    {
+        int best = INT_MAX;
+        long best_size = 0;
+        int bx = 0;
+        int S[kAx];
+        S[kAx - 1] = 1;
+        const int e3 = (blk.E[kAx - 1] + 3) & ~3;
+        const int nx = rpr > 1 ? 64 : 1, xstep = plane ? 4 : 1;
+        for (int s2 = e3; s2 < e3 + 32; s2 += 4)
+            for (int s1 = blk.E[kAx - 2] * s2; s1 < blk.E[kAx - 2] * s2 + (plane ? 128 : 1);
+                 s1 += 4)
+                for (int x = 0; x < nx; x += xstep) {
+                    S[kAx - 2] = s2;
+                    S[kAx - 3] = s1;
+                    outer(S);
+                    const long bytes = long(blk.E[0]) * S[0];
+                    long cst = (bytes + kPad + 3) & ~3L;
+                    if (rpr > 1) cst += ((4L * x - cst) % 256 + 256) % 256;
+                    if (cst > budget_words) continue;   // four copies: cst words
+                    const int k = bank_cost(n, S, rb, rpr, true, x);
+                    if (k < best || (k == best && cst < best_size)) {
+                        best = k;
+                        best_size = cst;
+                        bx = x;
+                        std::copy(S, S + kAx, blk.MSb);
+                    }
+                }
+        if (best == INT_MAX) {
+            std::copy(blk.S, blk.S + kAx, blk.MSb);
+            blk.mbox_b = blk.box_size;
+            blk.mcst = (blk.box_size + kPad + 3) & ~3;
+        } else {
+            blk.mbox_b = blk.E[0] * blk.MSb[0];
+            long cst = (long(blk.mbox_b) + kPad + 3) & ~3L;
+            if (rpr > 1) cst += ((4L * bx - cst) % 256 + 256) % 256;
+            blk.mcst = int(cst);
+        }
+    }
+}
+
 bool match_nd_supported(const Geo& g)
 {
     const int j3 = g.j[kAx - 1];
@@ -1089,7 +1241,8 @@ hipError_t launch_match_nd(const MatchArgs& a, int mode, int kmax, const NdBlock
         (a.g.j[kAx - 1] == 4 || a.g.j[kAx - 1] == 8)) {
         // the block's box staged once per workgroup, beside one score array
         // per wavefront; within a compute unit's LDS with the static scratch
-        const size_t lds = sizeof(int) * size_t(blk->box_size + kPad + kMWaves * cand);
+        const size_t lds =
+            sizeof(int) * size_t(blk_box_words(*blk, mode == kCount) + kMWaves * cand);
         if (lds + kMWaves * sizeof(WaveSel<32>) <= 160u * 1024u) {
             switch (mode) {
             case kCount: return launch_blk<kCount>(a, kmax, *blk, cand, lds, s);
