@@ -273,6 +273,8 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
                         sp1 = __builtin_amdgcn_udot4(rw[q][w], kOnes, sp1, false);
                     }
             }
+            // words spanning a run's row segment (kRB + J3 - 1 samples)
+            constexpr int NWR = (kRB + J3 - 1 + 3) / 4;
             for (int run = lane; run < nruns; run += kWave) {
                 const int line = run / rpr;
                 const int c3 = (run - line * rpr) * kRB;
@@ -282,27 +284,41 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
                     cb += (rem % n[d]) * sst[d];
                     rem /= n[d];
                 }
+                // the copy in which sample cb starts a word: word k of a
+                // row holds the row's samples 4k .. 4k + 3 from the run's
+                // start, and the 4 samples from any offset o are a byte
+                // alignment of words o / 4 and o / 4 + 1
+                const unsigned* cw =
+                    reinterpret_cast<const unsigned*>(sb + (cb & 3) * cst) + (cb >> 2);
+                unsigned pq[kRB], q2[kRB], q1[kRB];
 #pragma unroll
-                for (int u = 0; u < kRB; ++u) {
-                    const int bb = cb + u;
-                    const unsigned* cp =
-                        reinterpret_cast<const unsigned*>(sb + (bb & 3) * cst) + (bb >> 2);
-                    unsigned pq = 0, q2 = 0, q1 = 0;
+                for (int u = 0; u < kRB; ++u) pq[u] = q2[u] = q1[u] = 0u;
 #pragma unroll
-                    for (int q = 0; q < MR; ++q) {
-                        if (q < rows) {
+                for (int q = 0; q < MR; ++q) {
+                    if (q < rows) {
+                        unsigned wv[NWR];
+#pragma unroll
+                        for (int k = 0; k < NWR; ++k) wv[k] = cw[(roff[q] >> 2) + k];
+#pragma unroll
+                        for (int u = 0; u < kRB; ++u)
 #pragma unroll
                             for (int w = 0; w < NW; ++w) {
-                                const unsigned qw = cp[(roff[q] >> 2) + w];
-                                pq = __builtin_amdgcn_udot4(rw[q][w], qw, pq, false);
-                                q2 = __builtin_amdgcn_udot4(qw, qw, q2, false);
-                                q1 = __builtin_amdgcn_udot4(qw, kOnes, q1, false);
+                                const int o = u + 4 * w;
+                                const unsigned qw =
+                                    (o & 3) == 0 ? wv[o >> 2]
+                                                 : __builtin_amdgcn_alignbyte(wv[(o >> 2) + 1],
+                                                                              wv[o >> 2], o & 3);
+                                pq[u] = __builtin_amdgcn_udot4(rw[q][w], qw, pq[u], false);
+                                q2[u] = __builtin_amdgcn_udot4(qw, qw, q2[u], false);
+                                q1[u] = __builtin_amdgcn_udot4(qw, kOnes, q1[u], false);
                             }
-                        }
                     }
+                }
+#pragma unroll
+                for (int u = 0; u < kRB; ++u) {
                     const int ci = line * n3 + c3 + u;
                     if (c3 + u < n3) {
-                        int x = int(sp2 + q2 - 2u * pq) - a.gamma_i * int(sp1 + q1);
+                        int x = int(sp2 + q2[u] - 2u * pq[u]) - a.gamma_i * int(sp1 + q1[u]);
                         if (ci == rci) x = INT_MAX;
                         xs[ci] = x;
                         if (ci != rci) {
