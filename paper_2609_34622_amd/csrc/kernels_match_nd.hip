@@ -135,14 +135,16 @@ struct WaveSel {
     // 16-byte aligned in every element of an array of these: the bin scan
     // reads it four bins at a time
     alignas(16) unsigned hist[256];
-    int sel_lin[M];
+    // candidates are named by window index (C order over the clipped
+    // window, which is their lin order; lin is formed only for the output)
+    int sel_ci[M];    // members in window order
     int sel_key[M];
-    int srt_lin[M];   // the members ranked by (key, lin)
+    int srt_ci[M];    // ranked by (key, window index)
     int srt_key[M];
     double band_x[kBandCap];
-    int band_l[kBandCap];
+    int band_l[kBandCap];   // window indices
     double best_x[M];
-    int best_l[M];
+    int best_l[M];          // window indices
     int misc[4];
 };
 
@@ -167,9 +169,9 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     constexpr int SEG = J3 + kRB - 1;
     constexpr int M = WaveSel<GM>::M;
     unsigned* hist = ws.hist;
-    int* sel_lin = ws.sel_lin;
+    int* sel_ci = ws.sel_ci;
     int* sel_key = ws.sel_key;
-    int* srt_lin = ws.srt_lin;
+    int* srt_ci = ws.srt_ci;
     int* srt_key = ws.srt_key;
     double* band_x = ws.band_x;
     int* band_l = ws.band_l;
@@ -546,14 +548,16 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
                 base += int(__popcll(bal));
             }
             wsync();
+            // each lane's key against every other, read across lanes
+            const unsigned kj = lane < cB ? hist[lane] : 0u;
+            int less = 0, eq = 0;
+            const int cBu = __builtin_amdgcn_readfirstlane(cB);   // uniform
+            for (int o = 0; o < cBu; ++o) {
+                const unsigned ko = unsigned(__builtin_amdgcn_readlane(int(kj), o));
+                less += ko < kj;
+                eq += ko == kj;
+            }
             if (lane < cB) {
-                const unsigned kj = hist[lane];
-                int less = 0, eq = 0;
-                for (int o = 0; o < cB; ++o) {
-                    const unsigned ko = hist[o];
-                    less += ko < kj;
-                    eq += ko == kj;
-                }
                 if (less < rank && rank <= less + eq) {
                     misc[2] = int(kj);
                     misc[3] = need - rank + less;   // finite keys below theta
@@ -613,31 +617,29 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
             ties_left = ties_left > n_eq ? ties_left - n_eq : 0;
             const unsigned long long bt = __ballot(take);
             if (take) {
-                // lin of candidate ci (C order over the window)
-                int rem = ci, lin = 0;
-#pragma unroll
-                for (int d = kAx - 1; d >= 0; --d) {
-                    lin += (lo[d] + rem % n[d]) * g.st[d];
-                    rem /= n[d];
-                }
                 const int slot = base + int(__popcll(bt & below));
-                sel_lin[slot] = lin;
+                sel_ci[slot] = ci;
                 sel_key[slot] = int(k ^ 0x80000000u);  // signed order = key order
             }
             base += int(__popcll(bt));
         }
     }
     wsync();
-    // ranked by (key, lin)
-    for (int m = lane; m < need; m += kWave) {
-        const int km = sel_key[m], lm = sel_lin[m];
+    // ranked by (key, window index), the members read across lanes (need
+    // <= 31 < kWave)
+    {
+        const int km = lane < need ? sel_key[lane] : 0, lm = lane < need ? sel_ci[lane] : 0;
         int rk = 0;
-        for (int o = 0; o < need; ++o) {
-            const int ko = sel_key[o], lo_ = sel_lin[o];
+        const int nu = __builtin_amdgcn_readfirstlane(need);   // uniform
+        for (int o = 0; o < nu; ++o) {
+            const int ko = __builtin_amdgcn_readlane(km, o);
+            const int lo_ = __builtin_amdgcn_readlane(lm, o);
             rk += ko < km || (ko == km && lo_ < lm);
         }
-        srt_key[rk] = km;
-        srt_lin[rk] = lm;
+        if (lane < need) {
+            srt_key[rk] = km;
+            srt_ci[rk] = lm;
+        }
     }
     wsync();
     int got = need;
@@ -671,14 +673,13 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
         }
         const bool amb = nb > wsum(members_in_band) || wsum(close) > 0;
         fp64 = amb;
-        // FP64 score of candidate ci and its lin
+        // FP64 score of candidate ci (its window index ci is the order key)
         auto score64 = [&](int ci, int& lin) {
             int rem = ci, cbo = rbase;
-            lin = 0;
+            lin = ci;
 #pragma unroll
             for (int d = kAx - 1; d >= 0; --d) {
                 cbo += (rem % n[d]) * sst[d];
-                lin += (lo[d] + rem % n[d]) * g.st[d];
                 rem /= n[d];
             }
             double s = 0.0, bb = 0.0;
@@ -801,20 +802,24 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
         out[0] = r;
     }
     for (int m = K + lane; m < a.gmax; m += kWave) out[m] = -1;
-    if (fp64) {
-        for (int m = lane; m < K - 1; m += kWave) out[1 + m] = best_l[m];
-    } else {
-        for (int m = lane; m < K - 1; m += kWave) out[1 + m] = srt_lin[m];
+    for (int m = lane; m < K - 1; m += kWave) {
+        // lin of the member's window index (C order over the window)
+        int rem = fp64 ? best_l[m] : srt_ci[m], lin = 0;
+#pragma unroll
+        for (int d = kAx - 1; d >= 0; --d) {
+            lin += (lo[d] + rem % n[d]) * g.st[d];
+            rem /= n[d];
+        }
+        out[1 + m] = lin;
     }
 }
 
 // Stages the box of `ext` samples per axis from array coordinates `org`
-// (C order, thread tid of nthreads) into sx: raw counts for count-domain
-// scoring, float bit patterns otherwise; positions outside the array are 0
-// (no candidate reads them).  Coordinates advance by the thread stride with
-// carries, without a division per sample.
-// The samples of the box of extents ext from org (zeros outside the array)
-// into sx, sample (c_0, ..., c_3) of the box at sum_d c_d sst[d].
+// (thread tid of nthreads) into sx, sample (c_0, ..., c_3) of the box at
+// sum_d c_d sst[d]: raw counts for count-domain scoring, float bit patterns
+// otherwise; positions outside the array are 0 (no candidate reads them).
+// Coordinates advance by the thread stride with carries, without a
+// division per sample.
 template <int MODE>
 __device__ __forceinline__ void stage_box(const MatchArgs& a, int kmax, const float* src,
                                           const int* org, const int* ext, int total,
