@@ -57,6 +57,11 @@ __device__ __forceinline__ float key_float(unsigned k)
     return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
 }
 
+// the score of a key (inverse of okey)
+template <typename S> __device__ __forceinline__ S key_value(unsigned k);
+template <> __device__ __forceinline__ int key_value<int>(unsigned k) { return int(k ^ 0x80000000u); }
+template <> __device__ __forceinline__ float key_value<float>(unsigned k) { return key_float(k); }
+
 template <typename S> __device__ __forceinline__ S bigv();
 template <> __device__ __forceinline__ int bigv<int>() { return INT_MAX; }
 template <> __device__ __forceinline__ float bigv<float>() { return FLT_MAX; }
@@ -405,20 +410,34 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     const int sh = span < 256u ? 0 : (32 - __clz(span)) - 8;   // span >> sh < 256
     for (int h = lane; h < 256; h += kWave) hist[h] = 0u;
     wsync();
+    // The passes over the scores read four per lane before using them (four
+    // LDS reads in flight); the reference's own score is the excluded key.
+    auto load4 = [&](int c0, unsigned (&kk)[4]) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int ci = c0 + h * kWave + lane;
+            kk[h] = ci < ncand ? okey(from_int<S>(xs[ci])) : kbig;
+        }
+    };
     int acc = 0, namb = 0, nfin = 0;
-    for (int ci = lane; ci < ncand; ci += kWave) {
-        const S x = from_int<S>(xs[ci]);
-        const unsigned kx = okey(x);
-        if (ci == rci || kx == kbig) continue;
-        ++nfin;
-        if (span != 0u) atomicAdd(&hist[(kx - kmn) >> sh], 1u);
-        if constexpr (MODE == kCount) {
-            acc += x < a.tau_i;
-        } else {
-            // acc: certain acceptances; namb: the band around tau
-            const bool amb = fabsf(x - a.tau_f) <= tau_band;
-            acc += x < a.tau_f && !amb;
-            namb += amb;
+    for (int c0 = 0; c0 < ncand; c0 += 4 * kWave) {
+        unsigned kk[4];
+        load4(c0, kk);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const unsigned kx = kk[h];
+            if (kx == kbig) continue;
+            const S x = key_value<S>(kx);
+            ++nfin;
+            if (span != 0u) atomicAdd(&hist[(kx - kmn) >> sh], 1u);
+            if constexpr (MODE == kCount) {
+                acc += x < a.tau_i;
+            } else {
+                // acc: certain acceptances; namb: the band around tau
+                const bool amb = fabsf(x - a.tau_f) <= tau_band;
+                acc += x < a.tau_f && !amb;
+                namb += amb;
+            }
         }
     }
     acc = wsum(acc);
@@ -538,14 +557,17 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
         } else if (cB <= kWave) {
             // the bin's keys into hist[0 .. cB), then each ranked among them
             int base = 0;
-            for (int c0 = 0; c0 < ncand; c0 += kWave) {
-                const int ci = c0 + lane;
-                unsigned k = kbig;
-                if (ci < ncand && ci != rci) k = okey(from_int<S>(xs[ci]));
-                const bool in = k != kbig && lvl(k) == B;
-                const unsigned long long bal = __ballot(in);
-                if (in) hist[base + int(__popcll(bal & ((1ull << lane) - 1ull)))] = k;
-                base += int(__popcll(bal));
+            for (int c0 = 0; c0 < ncand; c0 += 4 * kWave) {
+                unsigned kk[4];
+                load4(c0, kk);
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const unsigned k = kk[h];
+                    const bool in = k != kbig && lvl(k) == B;
+                    const unsigned long long bal = __ballot(in);
+                    if (in) hist[base + int(__popcll(bal & ((1ull << lane) - 1ull)))] = k;
+                    base += int(__popcll(bal));
+                }
             }
             wsync();
             // each lane's key against every other, read across lanes
@@ -601,27 +623,40 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
         }
         less_total = wsum(nl);
     }
+    // float modes: the same pass counts the candidates up to theta plus the
+    // FP32 band above it (nb, for the near-tie check below)
+    const float th = kF ? key_float(theta_key) : 0.f;
+    const float thr = kF ? th + float(kTieBand) * (fabsf(th) + bmag) : 0.f;
+    int nb = 0;
     {
         const unsigned long long below = (1ull << lane) - 1ull;
         int ties_left = need - less_total;
         int base = 0;
-        for (int c0 = 0; c0 < ncand; c0 += kWave) {
-            const int ci = c0 + lane;
-            unsigned k = kbig;
-            if (ci < ncand && ci != rci) k = okey(from_int<S>(xs[ci]));
-            const bool eq = k == theta_key;
-            const unsigned long long beq = __ballot(eq);
-            // (the population counts are unsigned: kept out of signed arithmetic)
-            const int eq_rank = int(__popcll(beq & below)), n_eq = int(__popcll(beq));
-            const bool take = k < theta_key || (eq && eq_rank < ties_left);
-            ties_left = ties_left > n_eq ? ties_left - n_eq : 0;
-            const unsigned long long bt = __ballot(take);
-            if (take) {
-                const int slot = base + int(__popcll(bt & below));
-                sel_ci[slot] = ci;
-                sel_key[slot] = int(k ^ 0x80000000u);  // signed order = key order
+        for (int c0 = 0; c0 < ncand; c0 += 4 * kWave) {
+            unsigned kk[4];
+            load4(c0, kk);
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int ci = c0 + h * kWave + lane;
+                const unsigned k = kk[h];
+                if constexpr (kF) {
+                    const float x = key_float(k);
+                    nb += ci < ncand && ci != rci && x <= thr && !(x == 0.f && th == 0.f);
+                }
+                const bool eq = k == theta_key && k != kbig;
+                const unsigned long long beq = __ballot(eq);
+                // (the population counts are unsigned: kept out of signed arithmetic)
+                const int eq_rank = int(__popcll(beq & below)), n_eq = int(__popcll(beq));
+                const bool take = k < theta_key || (eq && eq_rank < ties_left);
+                ties_left = ties_left > n_eq ? ties_left - n_eq : 0;
+                const unsigned long long bt = __ballot(take);
+                if (take) {
+                    const int slot = base + int(__popcll(bt & below));
+                    sel_ci[slot] = ci;
+                    sel_key[slot] = int(k ^ 0x80000000u);  // signed order = key order
+                }
+                base += int(__popcll(bt));
             }
-            base += int(__popcll(bt));
         }
     }
     wsync();
@@ -649,14 +684,6 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
         // FP32 ranking = FP64 ranking unless a non-member lies within the
         // band above theta, or two members lie within the band of each other
         // (equal zeros are exact)
-        const float th = key_float(theta_key);
-        const float thr = th + float(kTieBand) * (fabsf(th) + bmag);
-        int nb = 0;
-        for (int ci = lane; ci < ncand; ci += kWave) {
-            if (ci == rci) continue;
-            const float x = __int_as_float(xs[ci]);
-            nb += x <= thr && !(x == 0.f && th == 0.f);
-        }
         nb = wsum(nb);
         // members within the band above theta; two members within the band
         // of each other (the band of the larger): if any pair is, so is a
@@ -965,62 +992,59 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
     int cst = 0;
     if constexpr (MODE == kCount) {
         // counts of the box as four byte-shifted copies in the same LDS (each
-        // copy box + kPad bytes, zero past the box) when every count fits a
-        // byte; otherwise staged again as integers below
+        // copy box + kPad bytes, zero past the box and in the row and plane
+        // padding) when every count fits a byte; otherwise staged again as
+        // integers below.  Copy 0 is written a word (4 samples of a row) per
+        // thread and item; word w of copy c is then bytes 4 w + c .. 4 w + c
+        // + 3 of copy 0, a byte alignment of its words w and w + 1.
         __shared__ int big;
         if (threadIdx.x == 0) big = 0;
         cst = blk.mcst;
         unsigned char* cb = reinterpret_cast<unsigned char*>(smem);
+        unsigned* w0 = reinterpret_cast<unsigned*>(smem);
+        const int nw0 = cst >> 2;   // words of a copy
         __syncthreads();
-        for (int e = blk.mbox_b + int(threadIdx.x); e < cst + 3; e += kMWaves * kWave)
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (e - c >= 0 && e - c < cst) cb[c * cst + e - c] = 0;
         {
-            int c[kAx], dc[kAx];
-            int rem = threadIdx.x, st = kMWaves * kWave;
-#pragma unroll
-            for (int d = kAx - 1; d >= 0; --d) {
-                c[d] = rem % blk.E[d];
-                rem /= blk.E[d];
-                dc[d] = st % blk.E[d];
-                st /= blk.E[d];
-            }
             bool over = false;
-            for (int e = threadIdx.x; e < blk.box_size; e += kMWaves * kWave) {
-                bool in = true;
-                int u = 0;
+            for (int w = threadIdx.x; w < nw0; w += kMWaves * kWave) {
+                unsigned word = 0u;
+                int rem = 4 * w;
+                if (rem < blk.mbox_b) {
+                    // box coordinates of the word's first sample (the rows
+                    // start on word boundaries)
+                    bool in = true;
+                    int base = 0;
 #pragma unroll
-                for (int d = 0; d < kAx; ++d) {
-                    const int x = blo[d] + c[d];
-                    in = in && x >= 0 && x < g.L[d];
-                    u += x * g.st[d];
-                }
-                int v = 0, p = 0;
+                    for (int d = 0; d < kAx - 1; ++d) {
+                        const int c = rem / blk.MSb[d];
+                        rem -= c * blk.MSb[d];
+                        const int x = blo[d] + c;
+                        in = in && c < blk.E[d] && x >= 0 && x < g.L[d];
+                        base += x * g.st[d];
+                    }
 #pragma unroll
-                for (int d = 0; d < kAx; ++d) p += c[d] * blk.MSb[d];
-                if (in) {
-                    const float rk = rintf(src[u] * a.inv_sp);
-                    const bool ok = rk >= 0.f && rk <= float(kmax);
-                    if (!ok) atomicOr(a.range_flag, 1);
-                    v = ok ? int(rk) : 0;
-                }
-                over = over || v > 255;
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (p - k >= 0) cb[k * cst + p - k] = (unsigned char)(v & 255);
-                int carry = 0;
-#pragma unroll
-                for (int d = kAx - 1; d >= 0; --d) {
-                    c[d] += dc[d] + carry;
-                    carry = 0;
-                    while (c[d] >= blk.E[d]) {
-                        c[d] -= blk.E[d];
-                        ++carry;
+                    for (int k = 0; k < 4; ++k) {
+                        const int c3 = rem + k, x3 = blo[kAx - 1] + c3;
+                        int v = 0;
+                        if (in && c3 < blk.E[kAx - 1] && x3 >= 0 && x3 < g.L[kAx - 1]) {
+                            const float rk = rintf(src[base + x3 * g.st[kAx - 1]] * a.inv_sp);
+                            const bool ok = rk >= 0.f && rk <= float(kmax);
+                            if (!ok) atomicOr(a.range_flag, 1);
+                            v = ok ? int(rk) : 0;
+                        }
+                        over = over || v > 255;
+                        word |= unsigned(v & 255) << (8 * k);
                     }
                 }
+                w0[w] = word;
             }
             if (over) atomicOr(&big, 1);
+        }
+        __syncthreads();
+        for (int w = threadIdx.x; w < nw0; w += kMWaves * kWave) {
+            const unsigned lw = w0[w], hw = w + 1 < nw0 ? w0[w + 1] : 0u;
+#pragma unroll
+            for (int c = 1; c < 4; ++c) w0[c * nw0 + w] = __builtin_amdgcn_alignbyte(hw, lw, c);
         }
         __syncthreads();
         if (big == 0) sb = cb;
