@@ -394,8 +394,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
     int b = 0, r0 = 0, r1 = 0;
     int blo[kAx] = {0, 0, 0, 0};
     if constexpr (BLK) {
-        const int blkid = blockIdx.x % blk.nblocks;
-        b = blockIdx.x / blk.nblocks;
+        // workgroups are dealt to the 8 XCDs in turn: each XCD takes a
+        // contiguous run of blocks, so neighbours (whose boxes overlap)
+        // share an L2 (a bijection; the last gridDim.x % 8 keep their index)
+        int bid = int(blockIdx.x);
+        {
+            const int q = int(gridDim.x) / 8;
+            if (bid < 8 * q) bid = (bid % 8) * q + bid / 8;
+        }
+        const int blkid = bid % blk.nblocks;
+        b = bid / blk.nblocks;
         r0 = bstart[blkid];
         r1 = bstart[blkid + 1];
         if (r0 >= r1) return;   // an empty block (uniform over the workgroup)

@@ -970,6 +970,8 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
     __shared__ WaveSel<GM> ws[kMWaves];
     const Geo& g = a.g;
     const int wave = threadIdx.x / kWave;
+    // (workgroups in block order: a contiguous run of blocks per XCD was
+    // slower here, unlike in the filter)
     const int blkid = blockIdx.x % blk.nblocks;
     const int b = blockIdx.x / blk.nblocks;
     const int r0 = blk.start[blkid], r1 = blk.start[blkid + 1];
