@@ -146,63 +146,90 @@ __device__ __forceinline__ void spatial_reg(float* x, const float* __restrict__ 
     }
 }
 
-// one butterfly level at pair distance d: lanes aligned to d take part
+// One butterfly level at pair distance d: lanes aligned to d take part
 // (while d < K), the low lane of a pair gets the sum, the high lane the
-// difference (low - high)
-template <int d, int N>
+// difference (low - high).  The lane exchanges run with every lane active;
+// MASK: the arithmetic of a chunk of kHc values runs under the
+// participating lanes' mask instead of a select per value (fewer
+// instructions, more registers: taken where the kernel spills anyway).
+// At most kHc exchanges in flight (register pressure).
+constexpr int kHc = 8;
+template <int d, int N, bool MASK>
 __device__ __forceinline__ void bfly(float* x, int jl, int lk)
 {
     constexpr int t = d == 1 ? 0 : (d == 2 ? 1 : (d == 4 ? 2 : (d == 8 ? 3 : 4)));
     const bool part = t < lk && (jl & (d - 1)) == 0;
     const float sg = (jl & d) ? -1.f : 1.f;
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const float p = xlane<d>(x[k]);
-        const float r = __builtin_fmaf(sg, x[k], p);   // low: x + p; high: p - x
-        x[k] = part ? r : x[k];
-        // at most 16 lane exchanges in flight (register pressure)
-        if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+    for (int k0 = 0; k0 < N; k0 += kHc) {
+        float p[kHc];
+#pragma unroll
+        for (int k = 0; k < kHc; ++k) p[k] = xlane<d>(x[k0 + k]);
+        if constexpr (MASK) {
+            if (part) {
+#pragma unroll
+                for (int k = 0; k < kHc; ++k)
+                    x[k0 + k] = __builtin_fmaf(sg, x[k0 + k], p[k]);   // low: x + p; high: p - x
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kHc; ++k) {
+                const float r = __builtin_fmaf(sg, x[k0 + k], p[k]);
+                x[k0 + k] = part ? r : x[k0 + k];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 // block sums: both lanes of a pair get the sum
-template <int d, int N>
+template <int d, int N, bool MASK>
 __device__ __forceinline__ void bsum(float* x, int jl, int lk)
 {
     constexpr int t = d == 1 ? 0 : (d == 2 ? 1 : (d == 4 ? 2 : (d == 8 ? 3 : 4)));
     const bool part = t < lk && (jl & (d - 1)) == 0;
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const float p = xlane<d>(x[k]);
-        x[k] = part ? x[k] + p : x[k];
-        if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+    for (int k0 = 0; k0 < N; k0 += kHc) {
+        float p[kHc];
+#pragma unroll
+        for (int k = 0; k < kHc; ++k) p[k] = xlane<d>(x[k0 + k]);
+        if constexpr (MASK) {
+            if (part) {
+#pragma unroll
+                for (int k = 0; k < kHc; ++k) x[k0 + k] += p[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kHc; ++k) x[k0 + k] = part ? x[k0 + k] + p[k] : x[k0 + k];
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
-template <int GM, int N>
+template <int GM, int N, bool MASK>
 __device__ __forceinline__ void haar_fwd(float* x, int jl, int lk)
 {
-    if constexpr (GM > 1) bfly<1, N>(x, jl, lk);
-    if constexpr (GM > 2) bfly<2, N>(x, jl, lk);
-    if constexpr (GM > 4) bfly<4, N>(x, jl, lk);
-    if constexpr (GM > 8) bfly<8, N>(x, jl, lk);
-    if constexpr (GM > 16) bfly<16, N>(x, jl, lk);
+    if constexpr (GM > 1) bfly<1, N, MASK>(x, jl, lk);
+    if constexpr (GM > 2) bfly<2, N, MASK>(x, jl, lk);
+    if constexpr (GM > 4) bfly<4, N, MASK>(x, jl, lk);
+    if constexpr (GM > 8) bfly<8, N, MASK>(x, jl, lk);
+    if constexpr (GM > 16) bfly<16, N, MASK>(x, jl, lk);
 }
-template <int GM, int N>
+template <int GM, int N, bool MASK>
 __device__ __forceinline__ void haar_inv(float* x, int jl, int lk)
 {
-    if constexpr (GM > 16) bfly<16, N>(x, jl, lk);
-    if constexpr (GM > 8) bfly<8, N>(x, jl, lk);
-    if constexpr (GM > 4) bfly<4, N>(x, jl, lk);
-    if constexpr (GM > 2) bfly<2, N>(x, jl, lk);
-    if constexpr (GM > 1) bfly<1, N>(x, jl, lk);
+    if constexpr (GM > 16) bfly<16, N, MASK>(x, jl, lk);
+    if constexpr (GM > 8) bfly<8, N, MASK>(x, jl, lk);
+    if constexpr (GM > 4) bfly<4, N, MASK>(x, jl, lk);
+    if constexpr (GM > 2) bfly<2, N, MASK>(x, jl, lk);
+    if constexpr (GM > 1) bfly<1, N, MASK>(x, jl, lk);
 }
-template <int GM, int N>
+template <int GM, int N, bool MASK>
 __device__ __forceinline__ void haar_sq(float* x, int jl, int lk)
 {
-    if constexpr (GM > 1) bsum<1, N>(x, jl, lk);
-    if constexpr (GM > 2) bsum<2, N>(x, jl, lk);
-    if constexpr (GM > 4) bsum<4, N>(x, jl, lk);
-    if constexpr (GM > 8) bsum<8, N>(x, jl, lk);
-    if constexpr (GM > 16) bsum<16, N>(x, jl, lk);
+    if constexpr (GM > 1) bsum<1, N, MASK>(x, jl, lk);
+    if constexpr (GM > 2) bsum<2, N, MASK>(x, jl, lk);
+    if constexpr (GM > 4) bsum<4, N, MASK>(x, jl, lk);
+    if constexpr (GM > 8) bsum<8, N, MASK>(x, jl, lk);
+    if constexpr (GM > 16) bsum<16, N, MASK>(x, jl, lk);
 }
 
 // FP64 Haar entry H[row of lane p][member j] for a group of K
@@ -376,6 +403,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
     static_assert(P == 64, "64-sample patches");
     constexpr int NG = kWave / GM;                 // groups per wavefront
     constexpr bool WIE = SH == BMND_SHRINK_WIENER;
+    // masked Haar arithmetic for the thresholding stages (which spill either
+    // way); selects for the Wiener stage (which then keeps its registers)
+    constexpr bool kMask = !WIE;
     // FP64 box: sums that do not depend on the order of the LDS atomics
     // beyond FP64 round-off, so an array's result is the same in every run
     // and in every batch or serving mix
@@ -463,7 +493,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
             }
             if (poisson) {
                 spatial_reg<D, J>(v, T2m);
-                haar_sq<GM, P>(v, jl, lk);
+                haar_sq<GM, P, kMask>(v, jl, lk);
                 const float sc = a.s_p * f2;
 #pragma unroll
                 for (int i = 0; i < P; ++i) v[i] *= sc;
@@ -475,7 +505,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                 }
             }
             spatial_reg<D, J>(gm, Tm);
-            haar_fwd<GM, P>(gm, jl, lk);
+            haar_fwd<GM, P, kMask>(gm, jl, lk);
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 const float vv = fmaxf(v[i], 0.f);
@@ -497,7 +527,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
 #pragma unroll
                 for (int i = 0; i < P; ++i) x[i] = act ? x[i] : 0.f;
                 spatial_reg<D, J>(x, Tm);
-                haar_fwd<GM, P>(x, jl, lk);
+                haar_fwd<GM, P, kMask>(x, jl, lk);
 #pragma unroll
                 for (int i = 0; i < P; ++i) x[i] *= v[i];
             }
@@ -512,10 +542,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                 v[i] = fmaxf(yv, 0.f);
             }
             spatial_reg<D, J>(x, Tm);
-            haar_fwd<GM, P>(x, jl, lk);
+            haar_fwd<GM, P, kMask>(x, jl, lk);
             if (poisson) {
                 spatial_reg<D, J>(v, T2m);
-                haar_sq<GM, P>(v, jl, lk);
+                haar_sq<GM, P, kMask>(v, jl, lk);
                 const float sc = a.s_p * f2;
 #pragma unroll
                 for (int i = 0; i < P; ++i) v[i] *= sc;
@@ -647,7 +677,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
             continue;
         } else {
             // ---- synthesis: B^T (scales applied above), then U on every axis
-            haar_inv<GM, P>(x, jl, lk);
+            haar_inv<GM, P, kMask>(x, jl, lk);
             spatial_reg<D, J>(x, Um);
             if constexpr (OM == 0) {
                 // patches (no window) and weights of every slot up to group_max
