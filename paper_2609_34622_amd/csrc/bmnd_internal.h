@@ -130,12 +130,19 @@ hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, co
 // N-D filter with per-origin weights W (FP64, one value per origin) and the
 // numerator accumulated in LDS boxes of the spatial blocks `blk` (the
 // origin list must be in blk's order); out_mode 1 (W and numerator), 2 (W
-// only), 3 (numerator with the mass-conservation shift, eta in den)
+// only), 3 (numerator with the mass-conservation shift, eta in den).
+// sweep_state: hard-threshold stages with out modes 2 and 3 pass each
+// member's decisions and weight from sweep 1 to sweep 2 through it
+// (nd_sweep_state_bytes); null otherwise
 struct NdBlocks;
+inline size_t nd_sweep_state_bytes(long groups, int gmax)
+{
+    return size_t(groups) * size_t(gmax) * (16 + sizeof(float));
+}
 hipError_t launch_filter_blocked(const StageCfg& c, const DevTables& t, int out_mode,
                                  const float* y, const float* pilot, int n_refs, const int* match,
                                  const int* count, void* num, void* den, double* wfield,
-                                 const NdBlocks* blk, hipStream_t s);
+                                 const NdBlocks* blk, void* sweep_state, hipStream_t s);
 hipError_t launch_aggregate(const StageCfg& c, const DevTables& t, int out_mode, const float* y,
                             int n_refs, const int* match, const int* count, const float* patches,
                             const float* weights, void* num, void* den, hipStream_t s);

@@ -25,7 +25,7 @@ struct DenoisePlan {
     // are listed block by block (r1 / r2 then point to that order)
     bool nd1 = false, nd2 = false;
     NdBlocks blk1, blk2;
-    size_t offs[9] = {};
+    size_t offs[10] = {};
     size_t total = 0;
     // owners of the library's device copies r1 / r2 point into, and the
     // events that mark the end of their uploads

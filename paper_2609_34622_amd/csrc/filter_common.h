@@ -28,6 +28,12 @@ struct FilterArgs {
     double* numd;
     double* dend;
     double* wfield;   // per-origin weight sums (N-D filter: eta = W * window)
+    // N-D filter, thresholding with mass conservation: per member (group *
+    // gmax + slot) its final keep mask and the coefficients the FP64
+    // re-decision kept (4 words), and its weight, written by sweep 1 and
+    // read by sweep 2
+    unsigned* hmask;
+    float* hwt;
     // correlated Gaussian noise: variance table D(Delta, q) over the member
     // box of extents cbw (null otherwise)
     const double* cdtab;

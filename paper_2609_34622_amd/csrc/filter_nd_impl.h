@@ -406,6 +406,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
     // masked Haar arithmetic for the thresholding stages (which spill either
     // way); selects for the Wiener stage (which then keeps its registers)
     constexpr bool kMask = !WIE;
+    // second sweep of a thresholding stage: the first sweep recorded every
+    // member's final decisions and weight (a.hmask, a.hwt), so this sweep
+    // neither propagates the variances nor decides again
+    constexpr bool kRecHT = !WIE && SH == BMND_SHRINK_HARD && OM == 3;
     // FP64 box: sums that do not depend on the order of the LDS atomics
     // beyond FP64 round-off, so an array's result is the same in every run
     // and in every batch or serving mix
@@ -479,6 +483,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
         float x[P];      // observation -> Y -> C -> p
         float v[P];      // variance source -> sigma^2 (HT); Wiener: gains
         float rl = 0.f;  // weight surrogate of the lane's Haar row
+        // thresholding, sweep 1: the final decisions, and those the FP64
+        // re-decision kept (recorded for sweep 2)
+        unsigned long long keep_out = 0, fixed = 0;
         float gn2 = 0.f;
 
         if constexpr (WIE) {
@@ -531,6 +538,44 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
 #pragma unroll
                 for (int i = 0; i < P; ++i) x[i] *= v[i];
             }
+        } else if constexpr (kRecHT) {
+            load_patch<D, J>(yo, g, x);
+#pragma unroll
+            for (int i = 0; i < P; ++i) x[i] = act ? x[i] : 0.f;
+            spatial_reg<D, J>(x, Tm);
+            haar_fwd<GM, P, kMask>(x, jl, lk);
+            // the decisions of the first sweep: kept (FP32 values), and among
+            // them those kept by the FP64 re-decision (their FP64 values)
+            const long slot = grp * a.gmax + jl;
+            uint4 m = make_uint4(0u, 0u, 0u, 0u);
+            if (act) m = reinterpret_cast<const uint4*>(a.hmask)[slot];
+            const unsigned long long keep = (unsigned long long)m.y << 32 | m.x;
+            unsigned long long fx = (unsigned long long)m.w << 32 | m.z;
+#pragma unroll
+            for (int i = 0; i < P; ++i) x[i] = ((keep >> i) & 1ull) ? x[i] * f : 0.f;
+            const unsigned long long segbits =
+                (GM >= 64 ? ~0ull : ((1ull << GM) - 1ull)) << (seg * GM);
+            for (;;) {
+                const unsigned long long mk = __ballot(fx != 0);
+                if (mk == 0) break;
+                const unsigned long long sk = mk & segbits;
+                const bool segact = sk != 0;
+                const int src = segact ? __ffsll((long long)sk) - 1 : lane;
+                const unsigned nlo = unsigned(__shfl(int(unsigned(fx & 0xffffffffull)), src));
+                const unsigned nhi = unsigned(__shfl(int(unsigned(fx >> 32)), src));
+                const int q = nlo != 0 ? __ffs(int(nlo)) - 1 : (nhi != 0 ? 32 + __ffs(int(nhi)) - 1 : 0);
+                double cy = 0.0, cv = 0.0;
+                (void)ht_decide64<D, J, GM>(a, tab64, yo, segact && act, src % GM, jl, K, q, &cy,
+                                            &cv);
+                if (segact && lane == src) {
+                    fx &= ~(1ull << q);
+                    const float cq = float(cy);
+#pragma unroll
+                    for (int i = 0; i < P; ++i) x[i] = i == q ? cq : x[i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i) x[i] *= f;   // B^T F: the synthesis scale
         } else {
             // ---- observation and its variance map
             load_patch<D, J>(yo, g, x);
@@ -616,6 +661,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                         const bool was = (keep >> q) & 1ull;
                         if (kp != was) {
                             keep ^= 1ull << q;
+                            if (kp) fixed |= 1ull << q;
                             float t = 1.f;
                             if (a.wmodel == BMND_WEIGHT_VARIANCE) t *= float(fmax(cv, 0.0));
                             if (a.wdomain == BMND_WDOMAIN_WINDOWED)
@@ -627,6 +673,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                         }
                     }
                 }
+                keep_out = keep;
             } else {
                 // soft threshold (eq. soft-threshold), attenuation |C| / |Y|
 #pragma unroll
@@ -654,7 +701,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
         // ---- weights (Def. aggregation-weight scope): group R = sum_l r_l;
         // patch R_j = sum over the rows whose support holds j of r_l / support
         float wj;
-        if (a.wscope == BMND_SCOPE_GROUP) {
+        if constexpr (kRecHT) {
+            wj = act ? a.hwt[grp * a.gmax + jl] : 0.f;
+        } else if (a.wscope == BMND_SCOPE_GROUP) {
             const float R = seg_sum<GM>(rl);
             wj = R > 0.f ? 1.f / R : 1.f;
         } else {
@@ -672,8 +721,18 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
         wj = act ? wj : 0.f;
 
         if constexpr (OM == 2) {
-            // mass conservation, sweep 1: the weights only
+            // mass conservation, sweep 1: the weights only (and, thresholding,
+            // the decisions and weight of every member for sweep 2)
             if (act) unsafeAtomicAdd(&wfield[vb + org], double(wj));
+            if constexpr (!WIE && SH == BMND_SHRINK_HARD) {
+                if (act) {
+                    const long slot = grp * a.gmax + jl;
+                    reinterpret_cast<uint4*>(a.hmask)[slot] =
+                        make_uint4(unsigned(keep_out), unsigned(keep_out >> 32), unsigned(fixed),
+                                   unsigned(fixed >> 32));
+                    a.hwt[slot] = wj;
+                }
+            }
             continue;
         } else {
             // ---- synthesis: B^T (scales applied above), then U on every axis

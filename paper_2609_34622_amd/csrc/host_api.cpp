@@ -1093,6 +1093,11 @@ static bmnd_status denoise_layout(const bmnd_geometry* geom, const bmnd_params* 
     // 1 / eta for the second mass-conservation sweep of the N-D filter
     const bool rd = params->ht.mass_conservation || params->wiener.mass_conservation;
     offs[8] = o; o += rd ? align256(vox * sizeof(double)) : 0;
+    // hard-threshold stage with mass conservation: each member's decisions
+    // and weight from the filter's first sweep to its second
+    const bool hs = params->ht.mass_conservation != 0;
+    offs[9] = o;
+    o += hs ? align256(nd_sweep_state_bytes(long(g.batch) * n_ht, params->ht.group_max)) : 0;
     *total = o;
     return BMND_OK;
 }
@@ -1109,7 +1114,7 @@ bmnd_status bmnd_workspace_size(const bmnd_geometry* geom, const bmnd_noise* noi
     one.batch = 1;
     const int64_t n1 = int64_t(host_origins_cached(one, params->ht)->size());
     const int64_t n2 = int64_t(host_origins_cached(one, params->wiener)->size());
-    size_t offs[9];
+    size_t offs[10];
     return denoise_layout(geom, params, n1, n2, offs, bytes);
 }
 
@@ -1123,7 +1128,7 @@ bmnd_status bmnd_workspace_sums(const bmnd_geometry* geom, const bmnd_noise* noi
     if (st != BMND_OK) return st;
     bmnd_geometry one = *geom;
     one.batch = 1;
-    size_t offs[9];
+    size_t offs[10];
     st = denoise_layout(geom, params, int64_t(host_origins_cached(one, params->ht)->size()),
                         int64_t(host_origins_cached(one, params->wiener)->size()), offs, &total);
     if (st != BMND_OK) return st;
@@ -1330,6 +1335,7 @@ hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out
     float* pilot = d_pilot ? d_pilot : reinterpret_cast<float*>(ws + pl.offs[6]);
     double* wf = reinterpret_cast<double*>(ws + pl.offs[7]);
     double* rden = reinterpret_cast<double*>(ws + pl.offs[8]);
+    void* hstate = ws + pl.offs[9];
     const size_t vox = size_t(pl.c1.g.batch) * pl.c1.g.V;
     {
         // the origin lists' uploads, if another stream queued them
@@ -1366,16 +1372,17 @@ hipError_t enqueue_denoise(const DenoisePlan& pl, const float* d_y, float* d_out
                 // per-origin weights W, eta = W * window, numerator in boxes
                 if (c.mc) {
                     // sweep 2 reads 1 / eta (into the reciprocal region)
+                    void* st = ht ? hstate : nullptr;
                     e = launch_filter_blocked(c, t, 2, d_y, pil, int(nr), match, count, num, den,
-                                              wf, blk, s);
+                                              wf, blk, st, s);
                     if (e == hipSuccess)
                         e = launch_window_conv(c.g, t, wf, static_cast<double*>(den), rden, s);
                     if (e == hipSuccess)
                         e = launch_filter_blocked(c, t, 3, d_y, pil, int(nr), match, count, num,
-                                                  rden, wf, blk, s);
+                                                  rden, wf, blk, st, s);
                 } else {
                     e = launch_filter_blocked(c, t, 1, d_y, pil, int(nr), match, count, num, den,
-                                              wf, blk, s);
+                                              wf, blk, nullptr, s);
                     if (e == hipSuccess)
                         e = launch_window_conv(c.g, t, wf, static_cast<double*>(den), nullptr, s);
                 }

@@ -1117,9 +1117,17 @@ hipError_t launch_filter(const StageCfg& c, const DevTables& t, int out_mode, co
 hipError_t launch_filter_blocked(const StageCfg& c, const DevTables& t, int out_mode,
                                  const float* y, const float* pilot, int n_refs, const int* match,
                                  const int* count, void* num, void* den, double* wfield,
-                                 const NdBlocks* blk, hipStream_t s)
+                                 const NdBlocks* blk, void* sweep_state, hipStream_t s)
 {
     FilterArgs a = filter_args(c, t, out_mode);
+    if (c.stage == BMND_STAGE_HT && c.shrink == BMND_SHRINK_HARD &&
+        (out_mode == 2 || out_mode == 3)) {
+        // the decisions and weights passed from sweep 1 to sweep 2
+        if (!sweep_state) return hipErrorInvalidValue;
+        const size_t members = size_t(c.g.batch) * size_t(n_refs) * size_t(c.gmax);
+        a.hmask = static_cast<unsigned*>(sweep_state);
+        a.hwt = reinterpret_cast<float*>(static_cast<char*>(sweep_state) + members * 16);
+    }
     a.n_refs = n_refs;
     a.y = y;
     a.pilot = pilot;
