@@ -1053,8 +1053,44 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
     }
     if (sb == nullptr) {
         if constexpr (MODE == kCount) __syncthreads();   // the byte copies are done with
-        stage_box<MODE>(a, kmax, src, blo, blk.E, blk.box_size, blk.MS, sx, threadIdx.x,
-                        kMWaves * kWave);
+        // four consecutive samples of a box row per thread and item (the
+        // row's coordinates from one division chain per item)
+        const int cpr = (blk.E[kAx - 1] + 3) >> 2;   // items a row
+        const int nitems = (blk.box_size / blk.E[kAx - 1]) * cpr;
+        for (int it = threadIdx.x; it < nitems; it += kMWaves * kWave) {
+            int row = it / cpr;
+            const int c3 = 4 * (it - row * cpr);
+            bool in = true;
+            int base = 0, p = c3;
+#pragma unroll
+            for (int d = kAx - 2; d >= 0; --d) {
+                const int c = row % blk.E[d];
+                row /= blk.E[d];
+                const int x = blo[d] + c;
+                in = in && x >= 0 && x < g.L[d];
+                base += x * g.st[d];
+                p += c * blk.MS[d];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int cc = c3 + k, x3 = blo[kAx - 1] + cc;
+                if (cc >= blk.E[kAx - 1]) break;
+                int v = 0;
+                if (in && x3 >= 0 && x3 < g.L[kAx - 1]) {
+                    const float xv = src[base + x3 * g.st[kAx - 1]];
+                    if constexpr (MODE == kCount) {
+                        // non-finite or out-of-range counts are flagged (scored as 0)
+                        const float rk = rintf(xv * a.inv_sp);
+                        const bool ok = rk >= 0.f && rk <= float(kmax);
+                        if (!ok) atomicOr(a.range_flag, 1);
+                        v = ok ? int(rk) : 0;
+                    } else {
+                        v = __float_as_int(xv);
+                    }
+                }
+                sx[p + k] = v;
+            }
+        }
         for (int e = blk.mbox + int(threadIdx.x); e < blk.mbox + kPad; e += kMWaves * kWave)
             sx[e] = 0;
     }
