@@ -318,6 +318,40 @@ def test_denoise_3d_mass_conservation():
     assert abs(pilot.astype(np.float64).sum() - tot) <= 1e-6 * tot
 
 
+# -------------------------------- blocked matcher with counts above 255
+
+HIGH_COUNTS = [
+    # shape, patch, step, search, mass conservation
+    ((96, 40), (8, 8), (3, 3), (15, 15), (False, False)),
+    ((60, 20, 16), (4, 4, 4), (3, 3, 3), (7, 7, 7), (True, True)),
+]
+
+
+@pytest.mark.parametrize("case", HIGH_COUNTS, ids=lambda c: "x".join(map(str, c[0])))
+def test_denoise_blocked_counts_above_255(case):
+    """Inside bmnd_denoise the 2-D and 3-D block matcher stages a block's
+    raw counts as bytes, and a block whose box holds a count above 255 as
+    32-bit integers at the strides of that copy.  Mean counts rising from
+    30 to 450 along the first axis send the first blocks one way and the
+    last the other; both stages
+    against the oracle (the pilot from y, the output replayed on the GPU's
+    pilot)."""
+    shape, patch, step, search, mc = case
+    _say(f"denoise {'x'.join(map(str, shape))}, counts up to ~450")
+    rng = np.random.default_rng(2550)
+    ramp = np.linspace(30.0, 450.0, shape[0]).reshape((shape[0],) + (1,) * (len(shape) - 1))
+    lam = np.broadcast_to(ramp, shape) * (0.9 + 0.2 * rng.uniform(size=shape))
+    s_p = 0.5
+    y = (rng.poisson(lam) * s_p).astype(np.float32)
+    assert (y / s_p).max() > 255 and (y[: shape[0] // 4] / s_p).max() < 255
+    p = params_for(shape, patch, step, search, mc=mc)
+    out, pilot = gpu_denoise(dev(y), B.geometry(shape), B.poisson(s_p), p)
+    ht, wie = oracle_stages(shape, patch, step, search, s_p, mc=mc)
+    yd = y.astype(np.float64)
+    assert rel_err(pilot, O.run_stage(ht, O.STAGE_HT, yd)) < REL_OUT
+    assert rel_err(out, O.run_stage(wie, O.STAGE_WIENER, yd, pilot.astype(np.float64))) < REL_OUT
+
+
 # ------------------------------------------------------------- edge cases
 
 EDGE = [
