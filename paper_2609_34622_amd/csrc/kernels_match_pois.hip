@@ -29,6 +29,41 @@ namespace {
 
 constexpr int kPoisThreads = 64;
 
+// 1-D arrays: a block's 64 references (one array, grid.y) stage the counts
+// of the union of their windows once in LDS, with a per-count term of the
+// metric, when that region holds at most kStageCap samples
+constexpr int kStageCap = 1024;
+
+// per-count term staged beside the counts: n ln n for the deviance, the
+// Anscombe transform 2 sqrt(n + 3/8) (its FP32 value, as phi32 forms it)
+template <int METRIC>
+__device__ __forceinline__ float pois_term(float n)
+{
+    if constexpr (METRIC == BMND_METRIC_DEVIANCE) return n > 0.f ? n * logf(n) : 0.f;
+    else if constexpr (METRIC == BMND_METRIC_ANSCOMBE) return 2.f * sqrtf(n + 0.375f);
+    else return 0.f;
+}
+
+// phi32 from staged counts r, c and their terms tr, tc: the deviance as
+// 2 (s ln 2 + r ln r + c ln c - s ln s), s = r + c (the same value up to
+// FP32 round-off, within the score's band); Anscombe and Pearson as phi32
+template <int METRIC>
+__device__ __forceinline__ float phi32s(float r, float c, float tr, float tc)
+{
+    if constexpr (METRIC == BMND_METRIC_DEVIANCE) {
+        const float s = r + c;
+        const float ts = s > 0.f ? s * logf(s) : 0.f;
+        return 2.f * (__builtin_fmaf(s, 0.69314718f, tr + tc) - ts);
+    } else if constexpr (METRIC == BMND_METRIC_ANSCOMBE) {
+        const float d = tc - tr;
+        return 0.5f * d * d;
+    } else {
+        const float s = r + c;
+        const float d = c - r;
+        return s > 0.f ? d * d * __builtin_amdgcn_rcpf(s) : 0.f;
+    }
+}
+
 // per-entry contribution phi(r, c) (eq. varphi) in FP32: the deviance's
 // 2 (r ln(2r/s) + c ln(2c/s)), Pearson's (c - r)^2 / s (both 0 for s = 0),
 // and (A(c) - A(r))^2 / 2 with A(n) = 2 sqrt(n + 3/8)
@@ -75,20 +110,34 @@ __device__ __forceinline__ double phi64(double r, double c)
 
 __device__ __forceinline__ int p2floor_p(int x) { return x <= 1 ? 1 : (1 << (31 - __clz(x))); }
 
-template <int METRIC, int GM>
+// STAGED (1-D arrays): blocks of 64 references of one array (grid.y the
+// array), the counts of their windows' union and their terms in LDS when
+// the union holds at most kStageCap samples (else read from the array)
+template <int METRIC, int GM, bool STAGED>
 __global__ __launch_bounds__(kPoisThreads) void k_match_pois(MatchArgs a, int kmax)
 {
     constexpr int M = GM > 1 ? GM - 1 : 1;
     constexpr int NS = M + 1;
     __shared__ double sel_s[M][kPoisThreads];
     __shared__ int sel_l[M][kPoisThreads];
+    __shared__ float st_c[STAGED ? kStageCap : 1], st_t[STAGED ? kStageCap : 1];
+    __shared__ int st_lo, st_hi;
 
     const Geo& g = a.g;
-    const long t = long(blockIdx.x) * kPoisThreads + threadIdx.x;
-    if (t >= long(g.batch) * a.n_refs) return;
-    const int b = int(t / a.n_refs);
-    const int gi = int(t - long(b) * a.n_refs);
-    const int r = safe_origin(int(a.refs[gi]), last_origin(g));
+    long t;
+    int b, gi;
+    if constexpr (STAGED) {
+        b = int(blockIdx.y);
+        gi = int(blockIdx.x) * kPoisThreads + int(threadIdx.x);
+        t = long(b) * a.n_refs + gi;
+    } else {
+        t = long(blockIdx.x) * kPoisThreads + threadIdx.x;
+        if (t >= long(g.batch) * a.n_refs) return;
+        b = int(t / a.n_refs);
+        gi = int(t - long(b) * a.n_refs);
+    }
+    const bool valid = !STAGED || gi < a.n_refs;
+    const int r = safe_origin(int(a.refs[valid ? gi : 0]), last_origin(g));
     const float* src = a.src + long(b) * g.V;
     const int P = g.P;
 
@@ -121,6 +170,37 @@ __global__ __launch_bounds__(kPoisThreads) void k_match_pois(MatchArgs a, int km
         }
         return k;
     };
+
+    // STAGED: the union of the block's windows (window origins plus a patch
+    // along the one array axis)
+    bool staged = false;
+    int slo = 0;
+    if constexpr (STAGED) {
+        if (threadIdx.x == 0) {
+            st_lo = INT_MAX;
+            st_hi = INT_MIN;
+        }
+        __syncthreads();
+        if (valid) {
+            const int L3 = g.L[kAx - 1], W3 = g.W[kAx - 1];
+            const int rc = r % L3;
+            atomicMin(&st_lo, max(rc - W3 / 2, 0));
+            atomicMax(&st_hi, min(rc + W3 - 1 - W3 / 2, g.ell[kAx - 1]) + g.j[kAx - 1] - 1);
+        }
+        __syncthreads();
+        slo = st_lo;
+        const int n_st = st_hi - st_lo + 1;
+        staged = n_st <= kStageCap;   // uniform over the block
+        if (staged) {
+            for (int e = threadIdx.x; e < n_st; e += kPoisThreads) {
+                const float k = cnt32(src[slo + e]);
+                st_c[e] = k;
+                st_t[e] = pois_term<METRIC>(k);
+            }
+        }
+        __syncthreads();
+        if (!valid) return;
+    }
 
     int lo[kAx], hi[kAx];
     int ncand = 1;
@@ -160,6 +240,20 @@ __global__ __launch_bounds__(kPoisThreads) void k_match_pois(MatchArgs a, int km
     // FP32 score and its round-off bound
     auto score = [&](int c, float* band) -> float {
         float A = 0.f, Mu = 0.f, S = 0.f, ssum = 0.f;
+        if (STAGED && staged) {
+            // 1-D: the patch is one run along the last axis
+            const int pr = r - slo, pc = c - slo;
+            for (int i3 = 0; i3 < g.j[kAx - 1]; ++i3) {
+                const float rr = st_c[pr + i3], cc = st_c[pc + i3];
+                A += phi32s<METRIC>(rr, cc, st_t[pr + i3], st_t[pc + i3]);
+                ssum += rr + cc;
+                if (a.policy == BMND_POLICY_STANDARDIZED) {
+                    const int n = tab(rr + cc);
+                    Mu += a.mu_f[n];
+                    S += a.v_f[n];
+                }
+            }
+        } else
         for (int i0 = 0; i0 < g.j[0]; ++i0)
             for (int i1 = 0; i1 < g.j[1]; ++i1)
                 for (int i2 = 0; i2 < g.j[2]; ++i2) {
@@ -306,20 +400,32 @@ __global__ __launch_bounds__(kPoisThreads) void k_match_pois(MatchArgs a, int km
     for (int m = 0; m < K - 1; ++m) out[1 + m] = sel_l[m][threadIdx.x];
 }
 
+template <int METRIC, bool STAGED>
+hipError_t launch_metric_st(const MatchArgs& a, int kmax, dim3 grid, hipStream_t s)
+{
+    switch (a.gmax) {
+    case 1: hipLaunchKernelGGL((k_match_pois<METRIC, 1, STAGED>), grid, dim3(kPoisThreads), 0, s, a, kmax); break;
+    case 2: hipLaunchKernelGGL((k_match_pois<METRIC, 2, STAGED>), grid, dim3(kPoisThreads), 0, s, a, kmax); break;
+    case 4: hipLaunchKernelGGL((k_match_pois<METRIC, 4, STAGED>), grid, dim3(kPoisThreads), 0, s, a, kmax); break;
+    case 8: hipLaunchKernelGGL((k_match_pois<METRIC, 8, STAGED>), grid, dim3(kPoisThreads), 0, s, a, kmax); break;
+    case 16: hipLaunchKernelGGL((k_match_pois<METRIC, 16, STAGED>), grid, dim3(kPoisThreads), 0, s, a, kmax); break;
+    default: hipLaunchKernelGGL((k_match_pois<METRIC, 32, STAGED>), grid, dim3(kPoisThreads), 0, s, a, kmax); break;
+    }
+    return hipGetLastError();
+}
+
 template <int METRIC>
 hipError_t launch_metric(const MatchArgs& a, int kmax, hipStream_t s)
 {
-    const long n = long(a.g.batch) * a.n_refs;
-    const dim3 grid(unsigned((n + kPoisThreads - 1) / kPoisThreads));
-    switch (a.gmax) {
-    case 1: hipLaunchKernelGGL((k_match_pois<METRIC, 1>), grid, dim3(kPoisThreads), 0, s, a, kmax); break;
-    case 2: hipLaunchKernelGGL((k_match_pois<METRIC, 2>), grid, dim3(kPoisThreads), 0, s, a, kmax); break;
-    case 4: hipLaunchKernelGGL((k_match_pois<METRIC, 4>), grid, dim3(kPoisThreads), 0, s, a, kmax); break;
-    case 8: hipLaunchKernelGGL((k_match_pois<METRIC, 8>), grid, dim3(kPoisThreads), 0, s, a, kmax); break;
-    case 16: hipLaunchKernelGGL((k_match_pois<METRIC, 16>), grid, dim3(kPoisThreads), 0, s, a, kmax); break;
-    default: hipLaunchKernelGGL((k_match_pois<METRIC, 32>), grid, dim3(kPoisThreads), 0, s, a, kmax); break;
+    bool one_axis = true;   // the patch and the window run along the last axis only
+    for (int d = 0; d < kAx - 1; ++d) one_axis = one_axis && a.g.L[d] == 1;
+    if (one_axis) {
+        const dim3 grid(unsigned((a.n_refs + kPoisThreads - 1) / kPoisThreads),
+                        unsigned(a.g.batch));
+        return launch_metric_st<METRIC, true>(a, kmax, grid, s);
     }
-    return hipGetLastError();
+    const long n = long(a.g.batch) * a.n_refs;
+    return launch_metric_st<METRIC, false>(a, kmax, dim3(unsigned((n + kPoisThreads - 1) / kPoisThreads)), s);
 }
 
 // ---- member scores (the optional score output of matching)
