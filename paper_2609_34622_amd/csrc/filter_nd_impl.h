@@ -519,7 +519,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                 const float gam = gm[i] * f;
                 const float shat = fmaxf(gam * gam - a.power_a * vv, 0.f);
                 const float den = shat + a.s_v * vv;
-                const float G = den > 0.f ? shat / den : 0.f;
+                // the gain from a hardware reciprocal (1 ulp) instead of a
+                // correctly rounded division: the same gain to FP32 accuracy
+                const float G = den > 0.f ? shat * __builtin_amdgcn_rcpf(den) : 0.f;
                 float t;
                 if (a.wmodel == BMND_WEIGHT_CLASSIC) t = G * G;
                 else if (a.wmodel == BMND_WEIGHT_VARIANCE) t = G * G * vv;
