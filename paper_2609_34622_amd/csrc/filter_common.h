@@ -9,6 +9,7 @@ namespace bmnd {
 struct FilterArgs {
     Geo g;
     int stage, shrink, noise;
+    int spatial;   // the stage's spatial transform (BMND_SPATIAL_*)
     float s_p, sigma2, lambda, s_v, power_a;
     double s_p64, sigma2_64, lambda64;
     int wmodel, wscope;

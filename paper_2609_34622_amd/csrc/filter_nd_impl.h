@@ -120,29 +120,77 @@ __device__ __forceinline__ void fibre(float* x, int base, const float* __restric
     for (int a = 0; a < J; ++a) x[base + a * stride] = t[a];
 }
 
+// 4-point fibres with the symmetries of the orthonormal DCT-II (the Wiener
+// stage's spatial transform): KIND 1 the analysis T (even and odd halves,
+// C_0,2 = T_00 (a0 +- a1), C_1 = T_10 b0 + T_11 b1, C_3 = T_11 b0 - T_10 b1
+// with a = x_n + x_3-n, b = x_n - x_3-n), 2 the synthesis U = T^T (the same
+// butterflies reversed), 3 the squared entries T o T of the variance
+// propagation (rows 0 and 2 both 1/4, rows 1 and 3 the even sums weighted
+// (T_10^2, T_11^2) and (T_11^2, T_10^2)).  The coefficients come from the
+// same tables as the matrix products; the results agree with them to FP32
+// round-off.
+template <int KIND, int stride>
+__device__ __forceinline__ void fibre_dct4(float* x, int base, const float* __restrict__ M)
+{
+    const float x0 = x[base], x1 = x[base + stride], x2 = x[base + 2 * stride],
+                x3 = x[base + 3 * stride];
+    if constexpr (KIND == 1) {
+        const float h = M[0], c1 = M[4], c3 = M[5];
+        const float a0 = x0 + x3, a1 = x1 + x2, b0 = x0 - x3, b1 = x1 - x2;
+        x[base] = h * (a0 + a1);
+        x[base + stride] = __builtin_fmaf(c1, b0, c3 * b1);
+        x[base + 2 * stride] = h * (a0 - a1);
+        x[base + 3 * stride] = __builtin_fmaf(c3, b0, -(c1 * b1));
+    } else if constexpr (KIND == 2) {
+        const float h = M[0], u1 = M[1], u3 = M[3];
+        const float e0 = h * (x0 + x2), e1 = h * (x0 - x2);
+        const float o0 = __builtin_fmaf(u1, x1, u3 * x3), o1 = __builtin_fmaf(u3, x1, -(u1 * x3));
+        x[base] = e0 + o0;
+        x[base + stride] = e1 + o1;
+        x[base + 2 * stride] = e1 - o1;
+        x[base + 3 * stride] = e0 - o0;
+    } else {
+        const float q = M[0], s1 = M[4], s3 = M[5];
+        const float e = x0 + x3, f = x1 + x2;
+        const float v02 = q * (e + f);
+        x[base] = v02;
+        x[base + stride] = __builtin_fmaf(s1, e, s3 * f);
+        x[base + 2 * stride] = v02;
+        x[base + 3 * stride] = __builtin_fmaf(s3, e, s1 * f);
+    }
+}
+
+template <int J, int stride, int KIND>
+__device__ __forceinline__ void fibre_k(float* x, int base, const float* __restrict__ M)
+{
+    if constexpr (KIND != 0 && J == 4) fibre_dct4<KIND, stride>(x, base, M);
+    else fibre<J, stride>(x, base, M);
+}
+
 // separable spatial transform inside a lane: the same J x J matrix along
-// every patch axis (samples in C order)
-template <int D, int J>
+// every patch axis (samples in C order); KIND (4-point DCT stages only)
+// selects the butterfly form of fibre_dct4
+template <int D, int J, int KIND = 0>
 __device__ __forceinline__ void spatial_reg(float* x, const float* __restrict__ M)
 {
     if constexpr (D == 2) {
 #pragma unroll
-        for (int r = 0; r < J; ++r) fibre<J, 1>(x, r * J, M);
+        for (int r = 0; r < J; ++r) fibre_k<J, 1, KIND>(x, r * J, M);
 #pragma unroll
-        for (int c = 0; c < J; ++c) fibre<J, J>(x, c, M);
+        for (int c = 0; c < J; ++c) fibre_k<J, J, KIND>(x, c, M);
     } else {
 #pragma unroll
         for (int i0 = 0; i0 < J; ++i0)
 #pragma unroll
-            for (int i1 = 0; i1 < J; ++i1) fibre<J, 1>(x, (i0 * J + i1) * J, M);
+            for (int i1 = 0; i1 < J; ++i1) fibre_k<J, 1, KIND>(x, (i0 * J + i1) * J, M);
 #pragma unroll
         for (int i0 = 0; i0 < J; ++i0)
 #pragma unroll
-            for (int i2 = 0; i2 < J; ++i2) fibre<J, J>(x, i0 * J * J + i2, M);
+            for (int i2 = 0; i2 < J; ++i2) fibre_k<J, J, KIND>(x, i0 * J * J + i2, M);
 #pragma unroll
         for (int i1 = 0; i1 < J; ++i1)
 #pragma unroll
-            for (int i2 = 0; i2 < J; ++i2) fibre<J, J * J>(x, i1 * J + i2, M);
+            for (int i2 = 0; i2 < J; ++i2) fibre_k<J, J * J, KIND>(x, i1 * J + i2, M);
     }
 }
 
@@ -392,7 +440,8 @@ __device__ __forceinline__ bool ht_decide64(const FilterArgs& a,
 // loads from them are then known not to be clobbered by the kernel's stores,
 // so uniform table entries are read with scalar loads and samples with global
 // (not generic) loads.
-template <int D, int J, int GM, int SH, int OM, bool BLK>
+// FAST: the stage's spatial transform is the 4-point DCT (butterfly fibres)
+template <int D, int J, int GM, int SH, int OM, bool BLK, bool FAST>
 __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
     FilterArgs a, NdBlocks blk, const float* __restrict__ y_, const float* __restrict__ pilot_,
     const int* __restrict__ match_, const int* __restrict__ count_, const float* __restrict__ tab,
@@ -403,6 +452,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
     static_assert(P == 64, "64-sample patches");
     constexpr int NG = kWave / GM;                 // groups per wavefront
     constexpr bool WIE = SH == BMND_SHRINK_WIENER;
+    static_assert(!FAST || (J == 4 && WIE), "butterfly fibres: 4-point DCT, Wiener stage");
+    constexpr int kT = FAST ? 1 : 0, kU = FAST ? 2 : 0, kT2 = FAST ? 3 : 0;
     // masked Haar arithmetic for the thresholding stages (which spill either
     // way); selects for the Wiener stage (which then keeps its registers)
     constexpr bool kMask = !WIE;
@@ -499,7 +550,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                 v[i] = fmaxf(pv, 0.f);
             }
             if (poisson) {
-                spatial_reg<D, J>(v, T2m);
+                spatial_reg<D, J, kT2>(v, T2m);
                 haar_sq<GM, P, kMask>(v, jl, lk);
                 const float sc = a.s_p * f2;
 #pragma unroll
@@ -511,7 +562,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                     v[i] = a.sigma2 * rn * rn;
                 }
             }
-            spatial_reg<D, J>(gm, Tm);
+            spatial_reg<D, J, kT>(gm, Tm);
             haar_fwd<GM, P, kMask>(gm, jl, lk);
 #pragma unroll
             for (int i = 0; i < P; ++i) {
@@ -535,7 +586,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                 load_patch<D, J>(yo, g, x);
 #pragma unroll
                 for (int i = 0; i < P; ++i) x[i] = act ? x[i] : 0.f;
-                spatial_reg<D, J>(x, Tm);
+                spatial_reg<D, J, kT>(x, Tm);
                 haar_fwd<GM, P, kMask>(x, jl, lk);
 #pragma unroll
                 for (int i = 0; i < P; ++i) x[i] *= v[i];
@@ -739,7 +790,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
         } else {
             // ---- synthesis: B^T (scales applied above), then U on every axis
             haar_inv<GM, P, kMask>(x, jl, lk);
-            spatial_reg<D, J>(x, Um);
+            spatial_reg<D, J, kU>(x, Um);
             if constexpr (OM == 0) {
                 // patches (no window) and weights of every slot up to group_max
                 if (gvalid) {
@@ -850,30 +901,40 @@ inline size_t box_bytes(const NdBlocks& blk, int out_mode)
     return size_t(blk.box_size) * sizeof(double);
 }
 
-template <int D, int J, int GM, int SH, int OM>
-hipError_t launch_om(const FilterArgs& a, const NdBlocks* blk, hipStream_t s)
+template <int D, int J, int GM, int SH, int OM, bool FAST>
+hipError_t launch_om_f(const FilterArgs& a, const NdBlocks* blk, hipStream_t s)
 {
     const Geo& g = a.g;
     if constexpr (OM != 0) {
         const size_t lds = box_bytes(*blk, OM);
-        const void* fn = reinterpret_cast<const void*>(&k_filter_nd<D, J, GM, SH, OM, true>);
+        const void* fn = reinterpret_cast<const void*>(&k_filter_nd<D, J, GM, SH, OM, true, FAST>);
         if (lds > 65536) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
             if (e != hipSuccess) return e;
         }
         const dim3 grid(unsigned(long(blk->nblocks) * g.batch));
-        hipLaunchKernelGGL((k_filter_nd<D, J, GM, SH, OM, true>), grid, dim3(kThreads), lds, s, a,
+        hipLaunchKernelGGL((k_filter_nd<D, J, GM, SH, OM, true, FAST>), grid, dim3(kThreads), lds, s, a,
                            *blk, a.y, a.pilot, a.match, a.count, a.t.f32, a.t.f64, blk->start,
                            a.numd, a.dend, a.wfield);
     } else {
         const long per = long(kWaves) * (kWave / GM);
         const long nchunk = (a.n_refs + per - 1) / per;
         NdBlocks none{};
-        hipLaunchKernelGGL((k_filter_nd<D, J, GM, SH, 0, false>), dim3(unsigned(nchunk * g.batch)),
+        hipLaunchKernelGGL((k_filter_nd<D, J, GM, SH, 0, false, FAST>), dim3(unsigned(nchunk * g.batch)),
                            dim3(kThreads), 0, s, a, none, a.y, a.pilot, a.match, a.count, a.t.f32,
                            a.t.f64, nullptr, a.numd, a.dend, a.wfield);
     }
     return hipGetLastError();
+}
+
+template <int D, int J, int GM, int SH, int OM>
+hipError_t launch_om(const FilterArgs& a, const NdBlocks* blk, hipStream_t s)
+{
+    // the Wiener stage's 4-point DCT by butterflies
+    if constexpr (J == 4 && SH == BMND_SHRINK_WIENER) {
+        if (a.spatial == BMND_SPATIAL_DCT) return launch_om_f<D, J, GM, SH, OM, true>(a, blk, s);
+    }
+    return launch_om_f<D, J, GM, SH, OM, false>(a, blk, s);
 }
 
 template <int D, int J, int GM, int SH>

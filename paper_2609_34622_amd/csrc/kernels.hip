@@ -1047,6 +1047,7 @@ static FilterArgs filter_args(const StageCfg& c, const DevTables& t, int out_mod
     a.g = c.g;
     a.stage = c.stage;
     a.shrink = c.shrink;
+    a.spatial = c.spatial;
     a.noise = c.noise;
     a.s_p = float(c.s_p);
     a.sigma2 = float(c.sigma * c.sigma);
