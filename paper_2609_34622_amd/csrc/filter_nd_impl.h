@@ -120,15 +120,16 @@ __device__ __forceinline__ void fibre(float* x, int base, const float* __restric
     for (int a = 0; a < J; ++a) x[base + a * stride] = t[a];
 }
 
-// 4-point fibres with the symmetries of the orthonormal DCT-II (the Wiener
-// stage's spatial transform): KIND 1 the analysis T (even and odd halves,
+// 4-point fibres with the structure of the stage's spatial transform.
+// Orthonormal DCT-II (the Wiener stage's transform): KIND 1 the analysis T (even and odd halves,
 // C_0,2 = T_00 (a0 +- a1), C_1 = T_10 b0 + T_11 b1, C_3 = T_11 b0 - T_10 b1
 // with a = x_n + x_3-n, b = x_n - x_3-n), 2 the synthesis U = T^T (the same
 // butterflies reversed), 3 the squared entries T o T of the variance
 // propagation (rows 0 and 2 both 1/4, rows 1 and 3 the even sums weighted
-// (T_10^2, T_11^2) and (T_11^2, T_10^2)).  The coefficients come from the
-// same tables as the matrix products; the results agree with them to FP32
-// round-off.
+// (T_10^2, T_11^2) and (T_11^2, T_10^2)).  bior1.5 (the hard-threshold
+// stage's), which on 4 points is the two-level Haar transform: KIND 4 T,
+// 5 U, 6 T o T.  The coefficients come from the same tables as the matrix
+// products; the results agree with them to FP32 round-off.
 template <int KIND, int stride>
 __device__ __forceinline__ void fibre_dct4(float* x, int base, const float* __restrict__ M)
 {
@@ -149,7 +150,7 @@ __device__ __forceinline__ void fibre_dct4(float* x, int base, const float* __re
         x[base + stride] = e1 + o1;
         x[base + 2 * stride] = e1 - o1;
         x[base + 3 * stride] = e0 - o0;
-    } else {
+    } else if constexpr (KIND == 3) {
         const float q = M[0], s1 = M[4], s3 = M[5];
         const float e = x0 + x3, f = x1 + x2;
         const float v02 = q * (e + f);
@@ -157,6 +158,30 @@ __device__ __forceinline__ void fibre_dct4(float* x, int base, const float* __re
         x[base + stride] = __builtin_fmaf(s1, e, s3 * f);
         x[base + 2 * stride] = v02;
         x[base + 3 * stride] = __builtin_fmaf(s3, e, s1 * f);
+    } else if constexpr (KIND == 4) {
+        // bior1.5 on 4 points is the two-level orthonormal Haar transform:
+        // rows (1 1 1 1)/2, (1 1 -1 -1)/2, (1 -1 0 0) r, (0 0 1 -1) r
+        const float h = M[0], r = M[8];
+        const float s0 = x0 + x1, s1 = x2 + x3;
+        x[base] = h * (s0 + s1);
+        x[base + stride] = h * (s0 - s1);
+        x[base + 2 * stride] = r * (x0 - x1);
+        x[base + 3 * stride] = r * (x2 - x3);
+    } else if constexpr (KIND == 5) {
+        const float h = M[0], r = M[2];
+        const float e = h * (x0 + x1), f = h * (x0 - x1), g = r * x2, k = r * x3;
+        x[base] = e + g;
+        x[base + stride] = e - g;
+        x[base + 2 * stride] = f + k;
+        x[base + 3 * stride] = f - k;
+    } else {
+        const float q = M[0], w = M[8];
+        const float s0 = x0 + x1, s1 = x2 + x3;
+        const float v01 = q * (s0 + s1);
+        x[base] = v01;
+        x[base + stride] = v01;
+        x[base + 2 * stride] = w * s0;
+        x[base + 3 * stride] = w * s1;
     }
 }
 
@@ -440,8 +465,9 @@ __device__ __forceinline__ bool ht_decide64(const FilterArgs& a,
 // loads from them are then known not to be clobbered by the kernel's stores,
 // so uniform table entries are read with scalar loads and samples with global
 // (not generic) loads.
-// FAST: the stage's spatial transform is the 4-point DCT (butterfly fibres)
-template <int D, int J, int GM, int SH, int OM, bool BLK, bool FAST>
+// SPK: the stage's spatial transform on 4-point fibres by butterflies (1 the
+// DCT, 2 bior1.5), 0 matrix products
+template <int D, int J, int GM, int SH, int OM, bool BLK, int SPK>
 __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
     FilterArgs a, NdBlocks blk, const float* __restrict__ y_, const float* __restrict__ pilot_,
     const int* __restrict__ match_, const int* __restrict__ count_, const float* __restrict__ tab,
@@ -452,8 +478,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
     static_assert(P == 64, "64-sample patches");
     constexpr int NG = kWave / GM;                 // groups per wavefront
     constexpr bool WIE = SH == BMND_SHRINK_WIENER;
-    static_assert(!FAST || (J == 4 && WIE), "butterfly fibres: 4-point DCT, Wiener stage");
-    constexpr int kT = FAST ? 1 : 0, kU = FAST ? 2 : 0, kT2 = FAST ? 3 : 0;
+    static_assert(SPK == 0 || J == 4, "butterfly fibres on 4 points");
+    constexpr int kT = SPK == 1 ? 1 : (SPK == 2 ? 4 : 0);
+    constexpr int kU = SPK == 1 ? 2 : (SPK == 2 ? 5 : 0);
+    constexpr int kT2 = SPK == 1 ? 3 : (SPK == 2 ? 6 : 0);
     // masked Haar arithmetic for the thresholding stages (which spill either
     // way); selects for the Wiener stage (which then keeps its registers)
     constexpr bool kMask = !WIE;
@@ -595,7 +623,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
             load_patch<D, J>(yo, g, x);
 #pragma unroll
             for (int i = 0; i < P; ++i) x[i] = act ? x[i] : 0.f;
-            spatial_reg<D, J>(x, Tm);
+            spatial_reg<D, J, kT>(x, Tm);
             haar_fwd<GM, P, kMask>(x, jl, lk);
             // the decisions of the first sweep: kept (FP32 values), and among
             // them those kept by the FP64 re-decision (their FP64 values)
@@ -639,10 +667,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                 gn2 = __builtin_fmaf(yv, yv, gn2);
                 v[i] = fmaxf(yv, 0.f);
             }
-            spatial_reg<D, J>(x, Tm);
+            spatial_reg<D, J, kT>(x, Tm);
             haar_fwd<GM, P, kMask>(x, jl, lk);
             if (poisson) {
-                spatial_reg<D, J>(v, T2m);
+                spatial_reg<D, J, kT2>(v, T2m);
                 haar_sq<GM, P, kMask>(v, jl, lk);
                 const float sc = a.s_p * f2;
 #pragma unroll
@@ -901,26 +929,26 @@ inline size_t box_bytes(const NdBlocks& blk, int out_mode)
     return size_t(blk.box_size) * sizeof(double);
 }
 
-template <int D, int J, int GM, int SH, int OM, bool FAST>
+template <int D, int J, int GM, int SH, int OM, int SPK>
 hipError_t launch_om_f(const FilterArgs& a, const NdBlocks* blk, hipStream_t s)
 {
     const Geo& g = a.g;
     if constexpr (OM != 0) {
         const size_t lds = box_bytes(*blk, OM);
-        const void* fn = reinterpret_cast<const void*>(&k_filter_nd<D, J, GM, SH, OM, true, FAST>);
+        const void* fn = reinterpret_cast<const void*>(&k_filter_nd<D, J, GM, SH, OM, true, SPK>);
         if (lds > 65536) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
             if (e != hipSuccess) return e;
         }
         const dim3 grid(unsigned(long(blk->nblocks) * g.batch));
-        hipLaunchKernelGGL((k_filter_nd<D, J, GM, SH, OM, true, FAST>), grid, dim3(kThreads), lds, s, a,
+        hipLaunchKernelGGL((k_filter_nd<D, J, GM, SH, OM, true, SPK>), grid, dim3(kThreads), lds, s, a,
                            *blk, a.y, a.pilot, a.match, a.count, a.t.f32, a.t.f64, blk->start,
                            a.numd, a.dend, a.wfield);
     } else {
         const long per = long(kWaves) * (kWave / GM);
         const long nchunk = (a.n_refs + per - 1) / per;
         NdBlocks none{};
-        hipLaunchKernelGGL((k_filter_nd<D, J, GM, SH, 0, false, FAST>), dim3(unsigned(nchunk * g.batch)),
+        hipLaunchKernelGGL((k_filter_nd<D, J, GM, SH, 0, false, SPK>), dim3(unsigned(nchunk * g.batch)),
                            dim3(kThreads), 0, s, a, none, a.y, a.pilot, a.match, a.count, a.t.f32,
                            a.t.f64, nullptr, a.numd, a.dend, a.wfield);
     }
@@ -930,11 +958,15 @@ hipError_t launch_om_f(const FilterArgs& a, const NdBlocks* blk, hipStream_t s)
 template <int D, int J, int GM, int SH, int OM>
 hipError_t launch_om(const FilterArgs& a, const NdBlocks* blk, hipStream_t s)
 {
-    // the Wiener stage's 4-point DCT by butterflies
+    // 4-point transforms by butterflies: the DCT (Wiener stage) and bior1.5
+    // (thresholding stages)
     if constexpr (J == 4 && SH == BMND_SHRINK_WIENER) {
-        if (a.spatial == BMND_SPATIAL_DCT) return launch_om_f<D, J, GM, SH, OM, true>(a, blk, s);
+        if (a.spatial == BMND_SPATIAL_DCT) return launch_om_f<D, J, GM, SH, OM, 1>(a, blk, s);
     }
-    return launch_om_f<D, J, GM, SH, OM, false>(a, blk, s);
+    if constexpr (J == 4 && SH != BMND_SHRINK_WIENER) {
+        if (a.spatial == BMND_SPATIAL_BIOR15) return launch_om_f<D, J, GM, SH, OM, 2>(a, blk, s);
+    }
+    return launch_om_f<D, J, GM, SH, OM, 0>(a, blk, s);
 }
 
 template <int D, int J, int GM, int SH>
