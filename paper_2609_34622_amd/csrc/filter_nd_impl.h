@@ -185,10 +185,68 @@ __device__ __forceinline__ void fibre_dct4(float* x, int base, const float* __re
     }
 }
 
+// 8-point fibres.  DCT-II: rows k even are symmetric and rows k odd
+// antisymmetric about the centre, so T x takes the half sums a_n = x_n +
+// x_7-n and differences b_n = x_n - x_7-n (KIND 7), U C the even and odd
+// partial sums E_n +- O_n (KIND 8), and T o T the half sums (KIND 9).
+// bior1.5 (KIND 10 T, 12 T o T): rows 4-7 are the level-1 Haar details of
+// the sample pairs (two nonzero entries each).  Coefficients from the
+// tables, as above.
+template <int KIND, int stride>
+__device__ __forceinline__ void fibre_fast8(float* x, int base, const float* __restrict__ M)
+{
+    float v[8];
+#pragma unroll
+    for (int n = 0; n < 8; ++n) v[n] = x[base + n * stride];
+    if constexpr (KIND == 7 || KIND == 9) {
+        float a[4], b[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            a[n] = v[n] + v[7 - n];
+            b[n] = v[n] - v[7 - n];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float* h = (KIND == 9 || (k & 1) == 0) ? a : b;
+            float acc = 0.f;
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc = __builtin_fmaf(M[k * 8 + n], h[n], acc);
+            x[base + k * stride] = acc;
+        }
+    } else if constexpr (KIND == 8) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            float e = 0.f, o = 0.f;
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) {
+                e = __builtin_fmaf(M[n * 8 + k], v[k], e);
+                o = __builtin_fmaf(M[n * 8 + k + 1], v[k + 1], o);
+            }
+            x[base + n * stride] = e + o;
+            x[base + (7 - n) * stride] = e - o;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float acc = 0.f;
+#pragma unroll
+            for (int n = 0; n < 8; ++n) acc = __builtin_fmaf(M[k * 8 + n], v[n], acc);
+            x[base + k * stride] = acc;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float w = M[(4 + k) * 8 + 2 * k];
+            x[base + (4 + k) * stride] =
+                w * (KIND == 12 ? v[2 * k] + v[2 * k + 1] : v[2 * k] - v[2 * k + 1]);
+        }
+    }
+}
+
 template <int J, int stride, int KIND>
 __device__ __forceinline__ void fibre_k(float* x, int base, const float* __restrict__ M)
 {
     if constexpr (KIND != 0 && J == 4) fibre_dct4<KIND, stride>(x, base, M);
+    else if constexpr (KIND != 0 && J == 8) fibre_fast8<KIND, stride>(x, base, M);
     else fibre<J, stride>(x, base, M);
 }
 
@@ -478,10 +536,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
     static_assert(P == 64, "64-sample patches");
     constexpr int NG = kWave / GM;                 // groups per wavefront
     constexpr bool WIE = SH == BMND_SHRINK_WIENER;
-    static_assert(SPK == 0 || J == 4, "butterfly fibres on 4 points");
-    constexpr int kT = SPK == 1 ? 1 : (SPK == 2 ? 4 : 0);
-    constexpr int kU = SPK == 1 ? 2 : (SPK == 2 ? 5 : 0);
-    constexpr int kT2 = SPK == 1 ? 3 : (SPK == 2 ? 6 : 0);
+    static_assert(SPK == 0 || J == 4 || J == 8, "structured fibres on 4 or 8 points");
+    // fibre kinds: 4 points 1-3 (DCT) and 4-6 (bior1.5); 8 points 7-9 (DCT),
+    // 10 and 12 (bior1.5; its synthesis by the matrix)
+    constexpr int kT = SPK == 1 ? (J == 4 ? 1 : 7) : (SPK == 2 ? (J == 4 ? 4 : 10) : 0);
+    constexpr int kU = SPK == 1 ? (J == 4 ? 2 : 8) : (SPK == 2 && J == 4 ? 5 : 0);
+    constexpr int kT2 = SPK == 1 ? (J == 4 ? 3 : 9) : (SPK == 2 ? (J == 4 ? 6 : 12) : 0);
     // masked Haar arithmetic for the thresholding stages (which spill either
     // way); selects for the Wiener stage (which then keeps its registers)
     constexpr bool kMask = !WIE;
@@ -958,12 +1018,12 @@ hipError_t launch_om_f(const FilterArgs& a, const NdBlocks* blk, hipStream_t s)
 template <int D, int J, int GM, int SH, int OM>
 hipError_t launch_om(const FilterArgs& a, const NdBlocks* blk, hipStream_t s)
 {
-    // 4-point transforms by butterflies: the DCT (Wiener stage) and bior1.5
-    // (thresholding stages)
-    if constexpr (J == 4 && SH == BMND_SHRINK_WIENER) {
+    // 4- and 8-point transforms by their structure: the DCT (Wiener stage)
+    // and bior1.5 (thresholding stages)
+    if constexpr ((J == 4 || J == 8) && SH == BMND_SHRINK_WIENER) {
         if (a.spatial == BMND_SPATIAL_DCT) return launch_om_f<D, J, GM, SH, OM, 1>(a, blk, s);
     }
-    if constexpr (J == 4 && SH != BMND_SHRINK_WIENER) {
+    if constexpr ((J == 4 || J == 8) && SH != BMND_SHRINK_WIENER) {
         if (a.spatial == BMND_SPATIAL_BIOR15) return launch_om_f<D, J, GM, SH, OM, 2>(a, blk, s);
     }
     return launch_om_f<D, J, GM, SH, OM, 0>(a, blk, s);
