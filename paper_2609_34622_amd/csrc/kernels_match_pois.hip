@@ -52,7 +52,9 @@ __device__ __forceinline__ float phi32s(float r, float c, float tr, float tc)
 {
     if constexpr (METRIC == BMND_METRIC_DEVIANCE) {
         const float s = r + c;
-        const float ts = s > 0.f ? s * logf(s) : 0.f;
+        // s ln s from the hardware base-2 logarithm (about 1 ulp): its error
+        // is far inside the score's round-off band
+        const float ts = s > 0.f ? s * (__builtin_amdgcn_logf(s) * 0.69314718f) : 0.f;
         return 2.f * (__builtin_fmaf(s, 0.69314718f, tr + tc) - ts);
     } else if constexpr (METRIC == BMND_METRIC_ANSCOMBE) {
         const float d = tc - tr;
