@@ -502,6 +502,8 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     // a time, among its keys.
     unsigned theta_key = kmn;   // all finite keys equal: that key is the need-th
     int less_total = 0;         // finite keys below theta (-1: not known yet)
+    bool members_done = false;  // the members already in sel_* (and, float modes, nb)
+    int nb = 0;                 // float modes: candidates up to theta plus the band
     // histogram of f(k) over the finite keys with in(k), then the bin of the
     // rank-th smallest (1-based) and the rank within it: misc[0], misc[1]
     auto bin_of_rank = [&](auto f, auto in, int rank_, bool built) {
@@ -555,39 +557,79 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
             theta_key = blo;   // a bin of one key value
             less_total = need - rank;
         } else if (cB <= kWave) {
-            // the bin's keys into hist[0 .. cB), then each ranked among them
-            int base = 0;
+            // One pass takes the keys of the bins below B as members (slots in
+            // window order) and compacts the keys of bin B with their window
+            // indices into hist[0 .. cB) and hist[64 .. 64 + cB); the rank
+            // smallest of those by (key, window index) complete the members.
+            const unsigned long long below = (1ull << lane) - 1ull;
+            int mbase = 0, cbase = 0, nz_low = 0;
             for (int c0 = 0; c0 < ncand; c0 += 4 * kWave) {
                 unsigned kk[4];
                 load4(c0, kk);
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
+                    const int ci = c0 + h * kWave + lane;
                     const unsigned k = kk[h];
-                    const bool in = k != kbig && lvl(k) == B;
-                    const unsigned long long bal = __ballot(in);
-                    if (in) hist[base + int(__popcll(bal & ((1ull << lane) - 1ull)))] = k;
-                    base += int(__popcll(bal));
+                    const unsigned lv = k != kbig ? lvl(k) : 0xFFFFFFFFu;
+                    const bool low = lv < B, inb = lv == B;
+                    if constexpr (kF) nz_low += low && key_float(k) == 0.f;
+                    const unsigned long long bl = __ballot(low);
+                    if (low) {
+                        const int slot = mbase + int(__popcll(bl & below));
+                        sel_ci[slot] = ci;
+                        sel_key[slot] = int(k ^ 0x80000000u);  // signed order = key order
+                    }
+                    mbase += int(__popcll(bl));
+                    const unsigned long long bb = __ballot(inb);
+                    if (inb) {
+                        const int at = cbase + int(__popcll(bb & below));
+                        hist[at] = k;
+                        hist[64 + at] = unsigned(ci);
+                    }
+                    cbase += int(__popcll(bb));
                 }
             }
             wsync();
-            // each lane's key against every other, read across lanes
+            // each lane's entry against every other, read across lanes
             const unsigned kj = lane < cB ? hist[lane] : 0u;
-            int less = 0, eq = 0;
+            const int cj = lane < cB ? int(hist[64 + lane]) : 0;
+            int rk = 0;
             const int cBu = __builtin_amdgcn_readfirstlane(cB);   // uniform
             for (int o = 0; o < cBu; ++o) {
                 const unsigned ko = unsigned(__builtin_amdgcn_readlane(int(kj), o));
-                less += ko < kj;
-                eq += ko == kj;
+                const int co = __builtin_amdgcn_readlane(cj, o);
+                rk += ko < kj || (ko == kj && co < cj);
             }
-            if (lane < cB) {
-                if (less < rank && rank <= less + eq) {
-                    misc[2] = int(kj);
-                    misc[3] = need - rank + less;   // finite keys below theta
-                }
+            const int low_n = need - rank;   // members below bin B (= mbase)
+            if (lane < cB && rk < rank) {
+                sel_ci[low_n + rk] = cj;
+                sel_key[low_n + rk] = int(kj ^ 0x80000000u);
             }
+            if (lane < cB && rk == rank - 1) misc[2] = int(kj);
             wsync();
             theta_key = unsigned(misc[2]);
-            less_total = misc[3];
+            if constexpr (kF) {
+                // candidates up to theta plus the band: the bins below B
+                // (less the -0 scores when theta is 0), bin B's entries up to
+                // the band, and past bin B only when the band reaches beyond it
+                const float th_ = key_float(theta_key);
+                const float thr_ = th_ + float(kTieBand) * (fabsf(th_) + bmag);
+                const float xj = key_float(kj);
+                const bool inband = lane < cB && xj <= thr_ && !(xj == 0.f && th_ == 0.f);
+                int tot = low_n - (th_ == 0.f ? wsum(nz_low) : 0) + int(__popcll(__ballot(inband)));
+                if (!(okey(thr_) <= bhi)) {
+                    int nx = 0;
+                    for (int ci = lane; ci < ncand; ci += kWave) {
+                        if (ci == rci) continue;
+                        const unsigned k = okey(from_int<S>(xs[ci]));
+                        const float x = key_float(k);
+                        nx += k > bhi && x <= thr_;
+                    }
+                    tot += wsum(nx);
+                }
+                nb = lane == 0 ? tot : 0;   // summed over the wavefront below
+            }
+            members_done = true;
             wsync();
         } else {
             // radix select among the bin's keys, from the highest byte in
@@ -615,7 +657,7 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     // members: keys below theta, then the first ties at theta in lin order
     // (candidate order is lin order), in one pass of rounds over the
     // candidates with slots from ballots
-    if (less_total < 0) {
+    if (!members_done && less_total < 0) {
         int nl = 0;
         for (int ci = lane; ci < ncand; ci += kWave) {
             if (ci == rci) continue;
@@ -627,8 +669,7 @@ __device__ __forceinline__ void match_one(const MatchArgs& a, int b, int gi, con
     // FP32 band above it (nb, for the near-tie check below)
     const float th = kF ? key_float(theta_key) : 0.f;
     const float thr = kF ? th + float(kTieBand) * (fabsf(th) + bmag) : 0.f;
-    int nb = 0;
-    {
+    if (!members_done) {
         const unsigned long long below = (1ull << lane) - 1ull;
         int ties_left = need - less_total;
         int base = 0;
