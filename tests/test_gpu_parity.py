@@ -352,6 +352,34 @@ def test_denoise_blocked_counts_above_255(case):
     assert rel_err(out, O.run_stage(wie, O.STAGE_WIENER, yd, pilot.astype(np.float64))) < REL_OUT
 
 
+# ------------------------- patch axes after axes of patch extent 1
+
+LEADING = [
+    # shape, patch, step, search, mass conservation
+    ((3, 20, 18, 16), (1, 4, 4, 4), (1, 3, 3, 3), (1, 5, 5, 5), (True, True)),
+    ((2, 40, 36), (1, 8, 8), (1, 3, 3), (1, 9, 9), (False, False)),
+]
+
+
+@pytest.mark.parametrize("case", LEADING, ids=lambda c: "x".join(map(str, c[0])))
+def test_denoise_nd_filter_leading_axes(case):
+    """4x4x4 and 8x8 patches on the last axes of a 4-D and a 3-D array
+    whose first axis has patch extent 1 and search 1: the N-D filter and its
+    tiled window convolution walk every sub-volume of the patch axes.  Both
+    stages against the oracle."""
+    shape, patch, step, search, mc = case
+    _say(f"denoise {'x'.join(map(str, shape))}, patch {'x'.join(map(str, patch))}")
+    rng = np.random.default_rng(4242)
+    s_p = 0.25
+    y = (rng.poisson(4.0 + 3.0 * rng.uniform(size=shape)) * s_p).astype(np.float32)
+    p = params_for(shape, patch, step, search, mc=mc)
+    out, pilot = gpu_denoise(dev(y), B.geometry(shape), B.poisson(s_p), p)
+    ht, wie = oracle_stages(shape, patch, step, search, s_p, mc=mc)
+    yd = y.astype(np.float64)
+    assert rel_err(pilot, O.run_stage(ht, O.STAGE_HT, yd)) < REL_OUT
+    assert rel_err(out, O.run_stage(wie, O.STAGE_WIENER, yd, pilot.astype(np.float64))) < REL_OUT
+
+
 # ------------------------------------------------------------- edge cases
 
 EDGE = [
