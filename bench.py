@@ -174,7 +174,7 @@ KERNEL_SYMBOLS = {
     "match_ht": [r"k_match_1d_u8<", r"k_match_1d_rec<", r"k_match_1d_f<2,", r"k_match_nd<0,",
                  r"k_match_blk<0,"],
     "match_wiener": [r"k_match_1d_f<3,", r"k_match_nd<3,", r"k_match_blk<3,"],
-    "window_conv": [r"k_window_conv<"],
+    "window_conv": [r"k_window_conv(_tiled)?<"],
 }
 
 
