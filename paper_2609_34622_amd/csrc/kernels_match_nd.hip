@@ -1141,8 +1141,17 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
     for (int d = 0; d < kAx; ++d) sst[d] = sb != nullptr ? blk.MSb[d] : blk.MS[d];
     int roff[64 / J3];
     row_offsets(g, sst, roff);
-    for (int gi = r0 + wave; gi < r1; gi += kMWaves)
+    // references taken from a shared counter: a wavefront that finishes
+    // early (no FP64 re-ranking, a single-key bin) takes the next one
+    __shared__ int next_ref;
+    if (threadIdx.x == 0) next_ref = r0 + kMWaves;
+    __syncthreads();
+    for (int gi = r0 + wave; gi < r1;) {
         match_one<MODE, GM, J3, RB>(a, b, gi, sx, blo, sst, roff, xs, ws[wave], sb, cst);
+        int nx = 0;
+        if (threadIdx.x % kWave == 0) nx = atomicAdd(&next_ref, 1);
+        gi = __builtin_amdgcn_readfirstlane(nx);
+    }
 }
 
 }  // namespace
