@@ -606,7 +606,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
     const float* __restrict__ Um = tab + a.t.U[kAx - 1];
     const bool poisson = a.noise == BMND_NOISE_POISSON;
 
-    for (int gbase = r0 + wave * NG; gbase < r1; gbase += kWaves * NG) {
+    // groups handed to the wavefronts NG at a time from a shared counter (a
+    // wavefront whose groups need no FP64 re-decision takes the next ones)
+    __shared__ int next_grp;
+    if (threadIdx.x == 0) next_grp = r0 + kWaves * NG;
+    __syncthreads();
+    auto take = [&]() {
+        int nx = 0;
+        if (lane == 0) nx = atomicAdd(&next_grp, NG);
+        return __builtin_amdgcn_readfirstlane(nx);
+    };
+    for (int gbase = r0 + wave * NG; gbase < r1; gbase = take()) {
         const int gi = gbase + seg;
         const bool gvalid = gi < r1;
         const long grp = long(b) * a.n_refs + (gvalid ? gi : r0);
