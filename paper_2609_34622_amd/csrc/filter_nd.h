@@ -29,6 +29,14 @@ struct NdBlocks {
     int mbox = 0;
     int mbox_b = 0;
     int mcst = 0;
+    // The filter's FP64 numerator box: extents FE (E without the last
+    // axis's rounding to 4) at strides FS (fbox doubles in all), rows and
+    // planes padded so that the members of a group, whose patches are added
+    // one sample at a time, fall on distinct LDS banks as often as possible
+    // (see nd_filter_layout)
+    int FE[kAx] = {1, 1, 1, 1};
+    int FS[kAx] = {1, 1, 1, 1};
+    int fbox = 0;
 };
 
 struct FilterArgs;
@@ -62,6 +70,9 @@ constexpr int kNumBlockRules = int(sizeof(kBlockRules) / sizeof(kBlockRules[0]))
 // start: block offsets).
 void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, int rule,
                     std::vector<int64_t>& refs_out, std::vector<int>& start, NdBlocks& blk);
+
+// Host: the filter's padded box strides (FS, fbox); nd_make_blocks calls it.
+void nd_filter_layout(const Geo& g, NdBlocks& blk);
 
 // Host: the matcher's padded LDS layouts of a block's box (MS, MSb, mbox,
 // mbox_b, mcst) for the geometry's window and patch; nd_make_blocks calls it.

@@ -62,14 +62,17 @@ constexpr int kThreads = kWave * kWaves;
 
 __device__ __forceinline__ float fsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 
-// value of the lane `lane ^ d` (d < 32): quad permutations for 1 and 2,
-// bit-mode swizzles (xor within 32 lanes) above
+// value of the lane `lane ^ d` (d < 32): DPP quad permutations for 1 and
+// 2, a DPP rotation of the 16-lane row by 8 for 8 (every source lane valid,
+// so no old value is kept and the move can merge into the instruction that
+// uses it), bit-mode swizzles (xor within 32 lanes) for 4 and 16
 template <int d>
 __device__ __forceinline__ float xlane(float v)
 {
     const int x = __float_as_int(v);
-    if constexpr (d == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xf, 0xf, false));
-    else if constexpr (d == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xf, 0xf, false));
+    if constexpr (d == 1) return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xf, 0xf, true));
+    else if constexpr (d == 2) return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xf, 0xf, true));
+    else if constexpr (d == 8) return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x128, 0xf, 0xf, true));
     else return __int_as_float(__builtin_amdgcn_ds_swizzle(x, 0x1F | (d << 10)));
 }
 template <int d>
@@ -280,10 +283,12 @@ __device__ __forceinline__ void spatial_reg(float* x, const float* __restrict__ 
 // One butterfly level at pair distance d: lanes aligned to d take part
 // (while d < K), the low lane of a pair gets the sum, the high lane the
 // difference (low - high).  The lane exchanges run with every lane active;
-// MASK: the arithmetic of a chunk of kHc values runs under the
-// participating lanes' mask instead of a select per value (fewer
-// instructions, more registers: taken where the kernel spills anyway).
-// At most kHc exchanges in flight (register pressure).
+// the arithmetic is one product and one FMA per value, s x + p m with
+// m = 1, s = +-1 on the participating lanes and m = 0, s = 1 on the others
+// (which keep x; p is always finite here).  MASK: the arithmetic of a
+// chunk of kHc values runs under the participating lanes' mask instead
+// (fewer registers: taken where the kernel spills anyway).  At most kHc
+// exchanges in flight (register pressure).
 constexpr int kHc = 8;
 template <int d, int N, bool MASK>
 __device__ __forceinline__ void bfly(float* x, int jl, int lk)
@@ -291,6 +296,8 @@ __device__ __forceinline__ void bfly(float* x, int jl, int lk)
     constexpr int t = d == 1 ? 0 : (d == 2 ? 1 : (d == 4 ? 2 : (d == 8 ? 3 : 4)));
     const bool part = t < lk && (jl & (d - 1)) == 0;
     const float sg = (jl & d) ? -1.f : 1.f;
+    const float sm = part ? sg : 1.f;
+    const float pm = part ? 1.f : 0.f;
 #pragma unroll
     for (int k0 = 0; k0 < N; k0 += kHc) {
         float p[kHc];
@@ -304,10 +311,7 @@ __device__ __forceinline__ void bfly(float* x, int jl, int lk)
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < kHc; ++k) {
-                const float r = __builtin_fmaf(sg, x[k0 + k], p[k]);
-                x[k0 + k] = part ? r : x[k0 + k];
-            }
+            for (int k = 0; k < kHc; ++k) x[k0 + k] = __builtin_fmaf(sm, x[k0 + k], p[k] * pm);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -318,6 +322,7 @@ __device__ __forceinline__ void bsum(float* x, int jl, int lk)
 {
     constexpr int t = d == 1 ? 0 : (d == 2 ? 1 : (d == 4 ? 2 : (d == 8 ? 3 : 4)));
     const bool part = t < lk && (jl & (d - 1)) == 0;
+    const float pm = part ? 1.f : 0.f;
 #pragma unroll
     for (int k0 = 0; k0 < N; k0 += kHc) {
         float p[kHc];
@@ -330,7 +335,7 @@ __device__ __forceinline__ void bsum(float* x, int jl, int lk)
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < kHc; ++k) x[k0 + k] = part ? x[k0 + k] + p[k] : x[k0 + k];
+            for (int k = 0; k < kHc; ++k) x[k0 + k] = __builtin_fmaf(p[k], pm, x[k0 + k]);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -542,13 +547,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
     constexpr int kT = SPK == 1 ? (J == 4 ? 1 : 7) : (SPK == 2 ? (J == 4 ? 4 : 10) : 0);
     constexpr int kU = SPK == 1 ? (J == 4 ? 2 : 8) : (SPK == 2 && J == 4 ? 5 : 0);
     constexpr int kT2 = SPK == 1 ? (J == 4 ? 3 : 9) : (SPK == 2 ? (J == 4 ? 6 : 12) : 0);
-    // masked Haar arithmetic for the thresholding stages (which spill either
-    // way); selects for the Wiener stage (which then keeps its registers)
-    constexpr bool kMask = !WIE;
     // second sweep of a thresholding stage: the first sweep recorded every
     // member's final decisions and weight (a.hmask, a.hwt), so this sweep
     // neither propagates the variances nor decides again
     constexpr bool kRecHT = !WIE && SH == BMND_SHRINK_HARD && OM == 3;
+    // masked Haar arithmetic for the thresholding stages that spill either
+    // way; per-lane factors for the Wiener stage and the recorded sweep
+    // (which then keep their registers)
+    constexpr bool kMask = !WIE && !kRecHT;
     // FP64 box: sums that do not depend on the order of the LDS atomics
     // beyond FP64 round-off, so an array's result is the same in every run
     // and in every batch or serving mix
@@ -588,7 +594,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
             blo[d] = bc * blk.B[d] - g.W[d] / 2;
         }
         if constexpr (OM == 1 || OM == 3) {
-            for (int e = threadIdx.x; e < blk.box_size; e += kThreads) box[e] = Acc(0);
+            for (int e = threadIdx.x; e < blk.fbox; e += kThreads) box[e] = Acc(0);
             __syncthreads();
         }
     } else {
@@ -943,8 +949,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                     for (int d = kAx - 1; d >= 0; --d) {
                         const int c = rem % g.L[d] - blo[d];
                         rem /= g.L[d];
-                        inbox = inbox && c >= 0 && c + g.j[d] <= blk.E[d];
-                        tb += c * blk.S[d];
+                        inbox = inbox && c >= 0 && c + g.j[d] <= blk.FE[d];
+                        tb += c * blk.FS[d];
                     }
                 }
 #pragma unroll
@@ -952,7 +958,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                     int qq = i, toff = 0;
 #pragma unroll
                     for (int d = D - 1; d >= 0; --d) {
-                        toff += (qq % J) * blk.S[kAx - D + d];
+                        toff += (qq % J) * blk.FS[kAx - D + d];
                         qq /= J;
                     }
                     // w omega exactly (FP64 product of the two floats), as in
@@ -974,18 +980,20 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
     }
 
     // ---- flush the box: one FP64 atomic per touched voxel, rows contiguous
+    // (the padding between rows and planes is never written and stays 0)
     if constexpr (BLK && (OM == 1 || OM == 3)) {
         __syncthreads();
-        for (int e = threadIdx.x; e < blk.box_size; e += kThreads) {
+        for (int e = threadIdx.x; e < blk.fbox; e += kThreads) {
             const Acc val = box[e];
             if (val == Acc(0)) continue;
             int rem = e, u = 0;
             bool in = true;
 #pragma unroll
-            for (int d = kAx - 1; d >= 0; --d) {
-                const int c = rem % blk.E[d] + blo[d];
-                rem /= blk.E[d];
-                in = in && c >= 0 && c < g.L[d];
+            for (int d = 0; d < kAx; ++d) {
+                const int cb = rem / blk.FS[d];
+                rem -= cb * blk.FS[d];
+                const int c = cb + blo[d];
+                in = in && cb < blk.FE[d] && c >= 0 && c < g.L[d];
                 u += c * g.st[d];
             }
             if (in) unsafeAtomicAdd(&numd[vb + u], double(val));
@@ -996,7 +1004,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
 inline size_t box_bytes(const NdBlocks& blk, int out_mode)
 {
     if (out_mode != 1 && out_mode != 3) return 0;
-    return size_t(blk.box_size) * sizeof(double);
+    return size_t(blk.fbox) * sizeof(double);
 }
 
 template <int D, int J, int GM, int SH, int OM, int SPK>

@@ -163,6 +163,7 @@ void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, int rule,
     blk.box_size = s;
     blk.nblocks = int(nblocks);
     nd_match_layout(g, blk);
+    nd_filter_layout(g, blk);
     // counting sort by block
     std::vector<int> bid(refs.size());
     start.assign(size_t(nblocks) + 1, 0);
@@ -179,6 +180,144 @@ void nd_make_blocks(const Geo& g, const std::vector<int64_t>& refs, int rule,
     refs_out.assign(refs.size(), 0);
     std::vector<int> pos(start.begin(), start.end() - 1);
     for (size_t k = 0; k < refs.size(); ++k) refs_out[size_t(pos[size_t(bid[k])]++)] = refs[k];
+}
+
+// The filter adds a group's patches to its block's FP64 box one sample
+// offset at a time: in one LDS instruction the lanes (members) write at
+// addresses that differ by their origins.  The LDS serves a 64-bit access
+// 16 lanes at a time, one double per bank pair (16 pairs); lanes of a pass
+// that share a pair wait for each other.  Members lie anywhere in the search
+// window, often along an edge or a plane of the volume, so the strides are
+// chosen by their cost on fixed pseudo-random member sets of the window:
+// uniform, within one axis-aligned plane or a slab three samples thick, and
+// clustered about the reference.  Rows and planes may grow by up to 15
+// doubles within max(the C-order box, 10112 doubles): two workgroups still
+// share a compute unit's LDS.
+void nd_filter_layout(const Geo& g, NdBlocks& blk)
+{
+    std::copy(blk.E, blk.E + kAx, blk.FE);
+    std::copy(blk.S, blk.S + kAx, blk.FS);
+    blk.fbox = blk.box_size;
+    int act[kAx], na = 0;   // active axes, outermost first
+    for (int d = 0; d < kAx; ++d)
+        if (blk.E[d] > 1) act[na++] = d;
+    if (na < 2) return;
+    int FE[kAx];
+    std::copy(blk.E, blk.E + kAx, FE);
+    // the last axis without its rounding to 4 (no patch reaches past it)
+    FE[kAx - 1] = std::min(blk.E[kAx - 1], blk.B[kAx - 1] + g.W[kAx - 1] + g.j[kAx - 1] - 2);
+    int n[kAx];   // window positions per axis
+    for (int d = 0; d < kAx; ++d) n[d] = std::max(1, std::min(g.W[d], g.ell[d] + 1));
+
+    // member sets: 32 window positions each, as coordinates
+    constexpr int kM = 32, kPer = 8;
+    const int npos = n[0] * n[1] * n[2] * n[3];
+    std::vector<int> xyz(size_t(npos) * kAx);   // coordinates, innermost axis first
+    std::vector<double> r2(size_t(npos), 0.0);  // squared distance from the centre
+    for (int q = 0; q < npos; ++q) {
+        int rem = q;
+        for (int d = kAx - 1; d >= 0; --d) {
+            const int x = rem % n[d];
+            rem /= n[d];
+            xyz[size_t(q) * kAx + size_t(kAx - 1 - d)] = x;
+            const double c = x - 0.5 * (n[d] - 1);
+            r2[size_t(q)] += c * c;
+        }
+    }
+    std::vector<int> sets;   // [set][member]: a position, or -1
+    uint64_t st = 0x9e3779b97f4a7c15ull;
+    auto rnd = [&](int m) {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        return int((st >> 33) % uint64_t(m));
+    };
+    std::vector<int> pool;
+    auto add_set = [&]() {
+        // 32 distinct positions of the pool (all of it when smaller)
+        const int take = std::min<int>(kM, int(pool.size()));
+        for (int k = 0; k < take; ++k)
+            std::swap(pool[size_t(k)], pool[size_t(k + rnd(int(pool.size()) - k))]);
+        for (int k = 0; k < kM; ++k) sets.push_back(k < take ? pool[size_t(k)] : -1);
+    };
+    for (int k = 0; k < kPer; ++k) {
+        pool.resize(size_t(npos));
+        for (int q = 0; q < npos; ++q) pool[size_t(q)] = q;
+        add_set();
+    }
+    for (int a = 0; a < na; ++a) {
+        const int d = act[a], xi = kAx - 1 - d;
+        for (int k = 0; k < kPer; ++k) {
+            const int c = rnd(n[d]), c3 = rnd(std::max(1, n[d] - 2));
+            pool.clear();
+            for (int q = 0; q < npos; ++q)
+                if (xyz[size_t(q) * kAx + size_t(xi)] == c) pool.push_back(q);
+            add_set();
+            pool.clear();
+            for (int q = 0; q < npos; ++q) {
+                const int x = xyz[size_t(q) * kAx + size_t(xi)];
+                if (x >= c3 && x < c3 + 3) pool.push_back(q);
+            }
+            add_set();
+        }
+    }
+    {
+        // the positions nearest the centre, distances jittered
+        std::vector<std::pair<double, int>> dist;
+        for (int q = 0; q < npos; ++q)
+            if (r2[size_t(q)] <= 16.0 + 1e-9) dist.push_back({r2[size_t(q)], q});
+        for (int k = 0; k < kPer; ++k) {
+            for (auto& e : dist) e.first = r2[size_t(e.second)] + 6.0 * rnd(1000) / 1000.0;
+            std::sort(dist.begin(), dist.end());
+            pool.clear();
+            for (int m = 0; m < kM && m < int(dist.size()); ++m) pool.push_back(dist[size_t(m)].second);
+            add_set();
+        }
+    }
+    const int nsets = int(sets.size()) / kM;
+    std::vector<long> addr(static_cast<size_t>(npos));
+    auto cost = [&](const int* S) {
+        for (int q = 0; q < npos; ++q) {
+            long v = 0;
+            for (int d = 0; d < kAx; ++d) v += long(xyz[size_t(q) * kAx + size_t(d)]) * S[kAx - 1 - d];
+            addr[size_t(q)] = v;
+        }
+        long c = 0;
+        for (int t = 0; t < nsets; ++t)
+            for (int pass = 0; pass < kM; pass += 16) {
+                int cnt[16] = {0};
+                int mx = 0;
+                for (int m = pass; m < pass + 16; ++m) {
+                    const int q = sets[size_t(t * kM + m)];
+                    if (q < 0) continue;
+                    mx = std::max(mx, ++cnt[addr[size_t(q)] & 15]);
+                }
+                c += mx;
+            }
+        return c;
+    };
+    const long cap = std::max<long>(blk.box_size, 10112);
+    const int mid = act[na - 2], out3 = na >= 3 ? act[na - 3] : -1;
+    long best = -1, best_size = 0;
+    int S[kAx];
+    for (int p1 = 0; p1 < 16; ++p1)
+        for (int p0 = 0; p0 < (out3 >= 0 ? 16 : 1); ++p0) {
+            // C-order strides over FE, the rows (stride of axis mid) longer
+            // by p1 and the planes (stride of axis out3) by p0
+            S[kAx - 1] = 1;
+            for (int d = kAx - 2; d >= 0; --d)
+                S[d] = FE[d + 1] * S[d + 1] + (d == mid ? p1 : (d == out3 ? p0 : 0));
+            const long size = long(FE[0]) * S[0];
+            if (size > cap) continue;
+            const long k = cost(S);
+            if (best < 0 || k < best || (k == best && size < best_size)) {
+                best = k;
+                best_size = size;
+                std::copy(S, S + kAx, blk.FS);
+            }
+        }
+    if (best >= 0) {
+        std::copy(FE, FE + kAx, blk.FE);
+        blk.fbox = int(best_size);
+    }
 }
 
 // Coverage map of a schedule (section Experiments, Shift Schedule

@@ -156,7 +156,7 @@ bool nd_filter_supported(const Geo& g, int gmax, int kex, bool corr, int noise, 
 bool nd_blocks_fit(const NdBlocks& blk)
 {
     // the FP64 box of mass conservation within a compute unit's LDS
-    return size_t(blk.box_size) * sizeof(double) <= 160u * 1024u;
+    return size_t(blk.fbox) * sizeof(double) <= 160u * 1024u;
 }
 
 hipError_t launch_filter_nd(const FilterArgs& a, const NdBlocks* blk, hipStream_t s)
