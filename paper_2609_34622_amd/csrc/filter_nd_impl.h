@@ -285,7 +285,9 @@ __device__ __forceinline__ void spatial_reg(float* x, const float* __restrict__ 
 // difference (low - high).  The lane exchanges run with every lane active;
 // the arithmetic is one product and one FMA per value, s x + p m with
 // m = 1, s = +-1 on the participating lanes and m = 0, s = 1 on the others
-// (which keep x; p is always finite here).  MASK: the arithmetic of a
+// (which keep x while p is finite: lanes past K hold zeros, and a
+// non-finite sample makes its whole group non-finite through the inverse
+// transform either way).  MASK: the arithmetic of a
 // chunk of kHc values runs under the participating lanes' mask instead
 // (fewer registers: taken where the kernel spills anyway).  At most kHc
 // exchanges in flight (register pressure).
