@@ -955,27 +955,41 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                         tb += c * blk.FS[d];
                     }
                 }
+                // w omega exactly (FP64 product of the two floats), as in
+                // eta = W * omega and in zeta: the sums then conserve mass to
+                // FP64 round-off.  In chunks of kOc samples: the window
+                // values (scalar loads) of a chunk are read before its LDS
+                // atomics, so waiting for them does not wait for the atomics
+                // sample by sample.
+                const double wjd = double(wj);
+                auto value = [&](int i) {
+                    const double ww = wjd * double(axis_prod<D, J>(tab, a.t.win, i));
+                    if constexpr (OM == 3) return ww * (double(x[i]) + alpha);
+                    else return ww * double(x[i]);
+                };
+                if (inbox) {
+                    constexpr int kOc = 16;
 #pragma unroll
-                for (int i = 0; i < P; ++i) {
-                    int qq = i, toff = 0;
+                    for (int i0 = 0; i0 < P; i0 += kOc) {
+                        double val[kOc];
 #pragma unroll
-                    for (int d = D - 1; d >= 0; --d) {
-                        toff += (qq % J) * blk.FS[kAx - D + d];
-                        qq /= J;
+                        for (int k = 0; k < kOc; ++k) val[k] = value(i0 + k);
+#pragma unroll
+                        for (int k = 0; k < kOc; ++k) {
+                            int qq = i0 + k, toff = 0;
+#pragma unroll
+                            for (int d = D - 1; d >= 0; --d) {
+                                toff += (qq % J) * blk.FS[kAx - D + d];
+                                qq /= J;
+                            }
+                            atomicAdd(&box[tb + toff], val[k]);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                    // w omega exactly (FP64 product of the two floats), as in
-                    // eta = W * omega and in zeta: the sums then conserve mass
-                    // to FP64 round-off
-                    const double ww = double(wj) * double(axis_prod<D, J>(tab, a.t.win, i));
-                    if constexpr (OM == 3) {
-                        const double val = ww * (double(x[i]) + alpha);
-                        if (inbox) atomicAdd(&box[tb + toff], val);
-                        else unsafeAtomicAdd(&numd[vb + org + patch_off<D, J>(i, g)], val);
-                    } else {
-                        const double val = ww * double(x[i]);
-                        if (inbox) atomicAdd(&box[tb + toff], val);
-                        else unsafeAtomicAdd(&numd[vb + org + patch_off<D, J>(i, g)], val);
-                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < P; ++i)
+                        unsafeAtomicAdd(&numd[vb + org + patch_off<D, J>(i, g)], value(i));
                 }
             }
         }
