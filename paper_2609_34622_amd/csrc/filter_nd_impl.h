@@ -916,21 +916,32 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
                     if (act) {
                         // four partial sums: independent FP64 chains
                         double zs4[4] = {0.0, 0.0, 0.0, 0.0}, zr4[4] = {0.0, 0.0, 0.0, 0.0};
+                        // kZr rows of four samples at a time: their loads of
+                        // 1 / eta and y are all issued before the first use,
+                        // so one memory round trip serves kZr rows
+                        constexpr int kZr = 4;
 #pragma unroll
-                        for (int i0 = 0; i0 < P; i0 += 4) {
-                            // four samples of a row: 1 / eta and y by vector loads
-                            const int u = org + patch_off<D, J>(i0, g);
-                            const d4u re = *reinterpret_cast<const d4u*>(dend + vb + u);
-                            const f4u yr = *reinterpret_cast<const f4u*>(yb + u);
-                            const double rev[4] = {re.x, re.y, re.z, re.w};
-                            const float yv[4] = {yr.x, yr.y, yr.z, yr.w};
+                        for (int r0 = 0; r0 < P; r0 += 4 * kZr) {
+                            d4u re[kZr];
+                            f4u yr[kZr];
 #pragma unroll
-                            for (int c = 0; c < 4; ++c) {
-                                const int i = i0 + c;
-                                const float w = axis_prod<D, J>(tab, a.t.win, i);
-                                const double zeta = double(wj) * double(w) * rev[c];
-                                zs4[c] += zeta;
-                                zr4[c] += zeta * (double(yv[c]) - double(x[i]));
+                            for (int k = 0; k < kZr; ++k) {
+                                const int u = org + patch_off<D, J>(r0 + 4 * k, g);
+                                re[k] = *reinterpret_cast<const d4u*>(dend + vb + u);
+                                yr[k] = *reinterpret_cast<const f4u*>(yb + u);
+                            }
+#pragma unroll
+                            for (int k = 0; k < kZr; ++k) {
+                                const double rev[4] = {re[k].x, re[k].y, re[k].z, re[k].w};
+                                const float yv[4] = {yr[k].x, yr[k].y, yr[k].z, yr[k].w};
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) {
+                                    const int i = r0 + 4 * k + c;
+                                    const float w = axis_prod<D, J>(tab, a.t.win, i);
+                                    const double zeta = double(wj) * double(w) * rev[c];
+                                    zs4[c] += zeta;
+                                    zr4[c] += zeta * (double(yv[c]) - double(x[i]));
+                                }
                             }
                         }
                         zs = (zs4[0] + zs4[1]) + (zs4[2] + zs4[3]);
