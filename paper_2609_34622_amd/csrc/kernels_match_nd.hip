@@ -1048,14 +1048,20 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
         const int nw0 = cst >> 2;   // words of a copy
         __syncthreads();
         {
+            // kSw words per thread at a time: the samples of all of them are
+            // loaded before the first is used (one memory round trip)
+            constexpr int kSw = 4;
+            constexpr int kTh = kMWaves * kWave;
             bool over = false;
-            for (int w = threadIdx.x; w < nw0; w += kMWaves * kWave) {
-                unsigned word = 0u;
-                int rem = 4 * w;
-                if (rem < blk.mbox_b) {
+            for (int wb = threadIdx.x; wb < nw0; wb += kSw * kTh) {
+                float xv[kSw][4];
+                bool ld[kSw][4];
+#pragma unroll
+                for (int q = 0; q < kSw; ++q) {
+                    int rem = 4 * (wb + q * kTh);
                     // box coordinates of the word's first sample (the rows
                     // start on word boundaries)
-                    bool in = true;
+                    bool in = wb + q * kTh < nw0 && rem < blk.mbox_b;
                     int base = 0;
 #pragma unroll
                     for (int d = 0; d < kAx - 1; ++d) {
@@ -1068,9 +1074,20 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const int c3 = rem + k, x3 = blo[kAx - 1] + c3;
+                        ld[q][k] = in && c3 < blk.E[kAx - 1] && x3 >= 0 && x3 < g.L[kAx - 1];
+                        xv[q][k] = ld[q][k] ? src[base + x3 * g.st[kAx - 1]] : 0.f;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kSw; ++q) {
+                    const int w = wb + q * kTh;
+                    if (w >= nw0) break;
+                    unsigned word = 0u;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
                         int v = 0;
-                        if (in && c3 < blk.E[kAx - 1] && x3 >= 0 && x3 < g.L[kAx - 1]) {
-                            const float rk = rintf(src[base + x3 * g.st[kAx - 1]] * a.inv_sp);
+                        if (ld[q][k]) {
+                            const float rk = rintf(xv[q][k] * a.inv_sp);
                             const bool ok = rk >= 0.f && rk <= float(kmax);
                             if (!ok) atomicOr(a.range_flag, 1);
                             v = ok ? int(rk) : 0;
@@ -1078,8 +1095,8 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
                         over = over || v > 255;
                         word |= unsigned(v & 255) << (8 * k);
                     }
+                    w0[w] = word;
                 }
-                w0[w] = word;
             }
             if (over) atomicOr(&big, 1);
         }
@@ -1098,38 +1115,59 @@ __global__ __launch_bounds__(kMWaves * kWave) void k_match_blk(MatchArgs a, int 
         // row's coordinates from one division chain per item)
         const int cpr = (blk.E[kAx - 1] + 3) >> 2;   // items a row
         const int nitems = (blk.box_size / blk.E[kAx - 1]) * cpr;
-        for (int it = threadIdx.x; it < nitems; it += kMWaves * kWave) {
-            int row = it / cpr;
-            const int c3 = 4 * (it - row * cpr);
-            bool in = true;
-            int base = 0, p = c3;
+        // kSi items per thread at a time, all loaded before the first is used
+        constexpr int kSi = 4;
+        constexpr int kTh = kMWaves * kWave;
+        for (int ib = threadIdx.x; ib < nitems; ib += kSi * kTh) {
+            float xv[kSi][4];
+            bool ld[kSi][4];
+            int pp[kSi];
 #pragma unroll
-            for (int d = kAx - 2; d >= 0; --d) {
-                const int c = row % blk.E[d];
-                row /= blk.E[d];
-                const int x = blo[d] + c;
-                in = in && x >= 0 && x < g.L[d];
-                base += x * g.st[d];
-                p += c * blk.MS[d];
+            for (int q = 0; q < kSi; ++q) {
+                const int it = ib + q * kTh;
+                int row = it / cpr;
+                const int c3 = 4 * (it - row * cpr);
+                bool in = it < nitems;
+                int base = 0, p = c3;
+#pragma unroll
+                for (int d = kAx - 2; d >= 0; --d) {
+                    const int c = row % blk.E[d];
+                    row /= blk.E[d];
+                    const int x = blo[d] + c;
+                    in = in && x >= 0 && x < g.L[d];
+                    base += x * g.st[d];
+                    p += c * blk.MS[d];
+                }
+                pp[q] = p;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int x3 = blo[kAx - 1] + c3 + k;
+                    ld[q][k] = in && c3 + k < blk.E[kAx - 1] && x3 >= 0 && x3 < g.L[kAx - 1];
+                    xv[q][k] = ld[q][k] ? src[base + x3 * g.st[kAx - 1]] : 0.f;
+                }
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int cc = c3 + k, x3 = blo[kAx - 1] + cc;
-                if (cc >= blk.E[kAx - 1]) break;
-                int v = 0;
-                if (in && x3 >= 0 && x3 < g.L[kAx - 1]) {
-                    const float xv = src[base + x3 * g.st[kAx - 1]];
-                    if constexpr (MODE == kCount) {
-                        // non-finite or out-of-range counts are flagged (scored as 0)
-                        const float rk = rintf(xv * a.inv_sp);
-                        const bool ok = rk >= 0.f && rk <= float(kmax);
-                        if (!ok) atomicOr(a.range_flag, 1);
-                        v = ok ? int(rk) : 0;
-                    } else {
-                        v = __float_as_int(xv);
+            for (int q = 0; q < kSi; ++q) {
+                const int it = ib + q * kTh;
+                if (it >= nitems) break;
+                const int c3 = 4 * (it % cpr);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (c3 + k >= blk.E[kAx - 1]) break;
+                    int v = 0;
+                    if (ld[q][k]) {
+                        if constexpr (MODE == kCount) {
+                            // non-finite or out-of-range counts are flagged (scored as 0)
+                            const float rk = rintf(xv[q][k] * a.inv_sp);
+                            const bool ok = rk >= 0.f && rk <= float(kmax);
+                            if (!ok) atomicOr(a.range_flag, 1);
+                            v = ok ? int(rk) : 0;
+                        } else {
+                            v = __float_as_int(xv[q][k]);
+                        }
                     }
+                    sx[pp[q] + k] = v;
                 }
-                sx[p + k] = v;
             }
         }
         for (int e = blk.mbox + int(threadIdx.x); e < blk.mbox + kPad; e += kMWaves * kWave)
