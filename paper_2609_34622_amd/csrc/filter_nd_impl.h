@@ -624,14 +624,37 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
         if (lane == 0) nx = atomicAdd(&next_grp, NG);
         return __builtin_amdgcn_readfirstlane(nx);
     };
-    for (int gbase = r0 + wave * NG; gbase < r1; gbase = take()) {
+    // Wiener stage: a group's count and list entry are loaded one iteration
+    // ahead (the next group base is taken from the counter at the start of
+    // an iteration), so its patch loads do not wait behind them.  The
+    // thresholding stages load them in their own iteration (the prefetch
+    // made them slower).
+    constexpr bool kPf = WIE;
+    auto fetch = [&](int gb, int& c, int& m) {
+        const int gi = gb + seg;
+        const long grp = long(b) * a.n_refs + (gi < r1 ? gi : r0);
+        c = count_[grp];
+        m = jl < a.gmax ? match_[grp * a.gmax + jl] : 0;
+    };
+    int cnt_n = 0, mt_n = 0, nb = 0;
+    if (kPf && r0 + wave * NG < r1) fetch(r0 + wave * NG, cnt_n, mt_n);
+    for (int gbase = r0 + wave * NG; gbase < r1; gbase = kPf ? nb : take()) {
+        int cnt = 0, mt = 0;
+        if constexpr (kPf) {
+            nb = take();
+            cnt = cnt_n;
+            mt = mt_n;
+            if (nb < r1) fetch(nb, cnt_n, mt_n);
+        }
         const int gi = gbase + seg;
         const bool gvalid = gi < r1;
         const long grp = long(b) * a.n_refs + (gvalid ? gi : r0);
-        const int K = gvalid ? safe_count(count_[grp], a.gmax) : 0;
+        if constexpr (!kPf) cnt = gvalid ? count_[grp] : 0;
+        const int K = gvalid ? safe_count(cnt, a.gmax) : 0;
         const int lk = 31 - __clz(max(K, 1));
         const bool act = jl < K;
-        const int org = safe_origin(act ? match_[grp * a.gmax + jl] : 0, omax);
+        if constexpr (!kPf) mt = act ? match_[grp * a.gmax + jl] : 0;
+        const int org = safe_origin(act ? mt : 0, omax);
         const float* __restrict__ yo = yb + org;   // the member's first sample
         const int sup = jl == 0 ? max(K, 1) : 2 * (jl & -jl);   // support of the lane's Haar row
         const float f = 1.f / fsqrt(float(sup));
