@@ -1030,23 +1030,49 @@ __global__ __launch_bounds__(kThreads, 2) void k_filter_nd(
     }
 
     // ---- flush the box: one FP64 atomic per touched voxel, rows contiguous
-    // (the padding between rows and planes is never written and stays 0)
+    // (the padding between rows and planes is never written and stays 0).
+    // kFb cells per thread at a time, their LDS reads issued together; box
+    // coordinates by a float-reciprocal quotient with one correction step
+    // (exact: the index is below 2^24 and the quotient's error below 1)
     if constexpr (BLK && (OM == 1 || OM == 3)) {
         __syncthreads();
-        for (int e = threadIdx.x; e < blk.fbox; e += kThreads) {
-            const Acc val = box[e];
-            if (val == Acc(0)) continue;
-            int rem = e, u = 0;
-            bool in = true;
+        float inv[kAx - 1];
 #pragma unroll
-            for (int d = 0; d < kAx; ++d) {
-                const int cb = rem / blk.FS[d];
-                rem -= cb * blk.FS[d];
-                const int c = cb + blo[d];
-                in = in && cb < blk.FE[d] && c >= 0 && c < g.L[d];
-                u += c * g.st[d];
+        for (int d = 0; d < kAx - 1; ++d) inv[d] = 1.f / float(blk.FS[d]);
+        constexpr int kFb = 4;
+        for (int e0 = threadIdx.x; e0 < blk.fbox; e0 += kFb * kThreads) {
+            Acc val[kFb];
+#pragma unroll
+            for (int k = 0; k < kFb; ++k) {
+                const int e = e0 + k * kThreads;
+                val[k] = e < blk.fbox ? box[e] : Acc(0);
             }
-            if (in) unsafeAtomicAdd(&numd[vb + u], double(val));
+#pragma unroll
+            for (int k = 0; k < kFb; ++k) {
+                if (val[k] == Acc(0)) continue;
+                int rem = e0 + k * kThreads;
+                long u = vb;
+                bool in = true;
+#pragma unroll
+                for (int d = 0; d < kAx - 1; ++d) {
+                    int cb = int(float(rem) * inv[d]);
+                    int r = rem - cb * blk.FS[d];
+                    if (r < 0) {
+                        --cb;
+                        r += blk.FS[d];
+                    } else if (r >= blk.FS[d]) {
+                        ++cb;
+                        r -= blk.FS[d];
+                    }
+                    rem = r;
+                    const int c = cb + blo[d];
+                    in = in && cb < blk.FE[d] && c >= 0 && c < g.L[d];
+                    u += long(c) * g.st[d];
+                }
+                const int c3 = rem + blo[kAx - 1];
+                in = in && rem < blk.FE[kAx - 1] && c3 >= 0 && c3 < g.L[kAx - 1];
+                if (in) unsafeAtomicAdd(&numd[u + c3], double(val[k]));
+            }
         }
     }
 }
